@@ -1,0 +1,20 @@
+"""Plain FP64 CPU oracle for the source-extended elastic FWI hot path.
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import anything under ``oracle/``. The product
+path (the HIP library and its Python binding) never imports, calls or links it, and the
+oracle imports nothing from the product package: the two share no code.
+
+Modules
+-------
+``elastic2d``   eq.(1)-(4), (6), (8) data term: 2D isotropic elastic velocity-stress
+                propagation (forward, exact discrete transpose, per-shot gradient).
+``elastic3d``   the same for 3D (9 fields).
+``regularizer`` eq.(8) regularization term with the operators W (eq.(11)), S_w (eq.(12))
+                and S^T, written as dense per-point matrices.
+``checkpoint``  the 16-bit checkpoint encodings (per-snapshot max-abs scaling).
+
+Every function is FP64 and unblocked; arrays are NumPy. Where the paper is silent
+(discretization, absorbing boundary, source injection, DAS sampling details) the reading
+taken is stated in the docstring of the function that implements it.
+"""

@@ -1,0 +1,194 @@
+"""Seeded synthetic workloads shared by the tests, the benchmark and the smoke check.
+
+This module holds no arithmetic of the method (no propagation, staging, absorbing
+boundary, misfit, gradient or regularizer): it only draws models, source and channel
+geometry, moment tensors and source time functions from fixed seeds, in the shapes and
+value distributions of the paper's guided-wave settings (a low-velocity reservoir layer
+crossed by a horizontal DAS well with in-layer moment-tensor sources; the paper's field
+data and its synthetic model's exact geometry are not available, so these stand in).
+
+All arrays are NumPy float64 (the caller casts); models are [3][nz][nx] = (Vp, Vs, rho).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.ndimage import gaussian_filter
+
+
+@dataclass
+class Shot2D:
+    src_iz: int
+    src_ix: int
+    M: np.ndarray              # (Mxx, Mzz, Mxz)
+    ch_iz: np.ndarray          # [nch] int32
+    ch_ix: np.ndarray          # [nch] int32
+    # subdomain window into the full model (batched form); whole model when w* == 0
+    z0: int = 0
+    x0: int = 0
+    wz: int = 0
+    wx: int = 0
+
+
+@dataclass
+class Workload2D:
+    name: str
+    nz: int
+    nx: int
+    dz: float
+    dx: float
+    dt: float
+    nt: int
+    npml: int
+    f0: float                  # Ricker central frequency
+    vp_max: float
+    stf: np.ndarray            # [nt] moment-rate s(t_{n+1/2})
+    m_start: np.ndarray        # [3][nz][nx]
+    m_true: np.ndarray         # [3][nz][nx]
+    shots: list = field(default_factory=list)
+    pml_R: float = 1e-3
+
+
+def ricker(nt, dt, f0, amp=1.0):
+    """Ricker wavelet with delay 1.5/f0 and unit peak, sampled at t_{n+1/2} = (n + 1/2) dt."""
+    t = (np.arange(nt) + 0.5) * dt
+    tau = t - 1.5 / f0
+    a = (math.pi * f0 * tau) ** 2
+    return amp * (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def smooth_random_field(shape, corr_cells, seed, max_abs):
+    """White N(0,1) noise smoothed by a Gaussian of sigma = corr_cells / 2 (correlation
+    ~exp(-r^2/corr^2)), rescaled so that max|field| = max_abs."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(shape)
+    s = gaussian_filter(w, sigma=corr_cells / 2.0, mode="reflect")
+    return s * (max_abs / np.max(np.abs(s)))
+
+
+def gaussian_blob(shape, cz, cx, sigma, amp):
+    z = np.arange(shape[0])[:, None]
+    x = np.arange(shape[1])[None, :]
+    return amp * np.exp(-((z - cz) ** 2 + (x - cx) ** 2) / (2.0 * sigma ** 2))
+
+
+# ---------------------------------------------------------------------------------------
+# Parity workload: 100 x 200, dx = 5 m, three layers with a 20 m low-velocity layer.
+# ---------------------------------------------------------------------------------------
+def parity_2d(nt=1000, M0=1.0e16):
+    nz, nx, h = 100, 200, 5.0
+    vp = np.full((nz, nx), 3600.0)
+    rho = np.full((nz, nx), 2450.0)
+    vp[48:52] = 3000.0          # 4 cells = 20 m low-velocity layer (waveguide)
+    rho[48:52] = 2300.0
+    vp[52:] = 4500.0
+    rho[52:] = 2600.0
+    vs = vp / 1.7
+    m_start = np.stack([vp, vs, rho])
+    blob = gaussian_blob((nz, nx), 50, 110, 4.0, 0.03)
+    m_true = m_start.copy()
+    m_true[0] *= 1.0 + blob
+    m_true[1] *= 1.0 + blob
+    ch_ix = (60 + 3 * np.arange(40)).astype(np.int32)
+    ch_iz = np.full(40, 50, np.int32)
+    shot = Shot2D(src_iz=50, src_ix=40, M=np.array([M0, M0, 0.0]), ch_iz=ch_iz, ch_ix=ch_ix)
+    return Workload2D(name="parity-2d-100x200", nz=nz, nx=nx, dz=h, dx=h, dt=0.5e-3, nt=nt,
+                      npml=20, f0=30.0, vp_max=4500.0, stf=ricker(nt, 0.5e-3, 30.0),
+                      m_start=m_start, m_true=m_true, shots=[shot])
+
+
+# ---------------------------------------------------------------------------------------
+# Plain per-shot workload: 1000 x 3000, dx = 2.5 m, shale with a 15 m reservoir layer.
+# ---------------------------------------------------------------------------------------
+def _shale_model(nz, nx, h, res_top, res_bot, seed=14130, corr_m=50.0, anomalies=True):
+    vp = np.full((nz, nx), 3800.0)
+    ratio = np.full((nz, nx), 0.6)
+    rho = np.full((nz, nx), 2550.0)
+    vp[res_top:res_bot] = 3400.0
+    ratio[res_top:res_bot] = 0.55
+    rho[res_top:res_bot] = 2450.0
+    vs = vp * ratio
+    m = np.stack([vp, vs, rho])
+    if anomalies:
+        for k in range(3):
+            m[k] = m[k] * (1.0 + smooth_random_field((nz, nx), corr_m / h, seed + k, 0.05))
+    return m
+
+
+def _mt_components(rng, M0):
+    M = rng.uniform(-1.0, 1.0, 3)
+    frob = math.sqrt(M[0] ** 2 + M[1] ** 2 + 2.0 * M[2] ** 2)
+    return M * (M0 / frob)
+
+
+def plain_2d(nz=1000, nx=3000, nt=4000, nshots=20, nch=1500, M0=1.0e16, anomalies=True):
+    """Grid 1000 x 3000 at 2.5 m, nt = 4000 at 0.25 ms, 40-cell CPML, Ricker 60 Hz, 20
+    moment-tensor sources in the layer, 1500 DAS e_xx channels along the well (iz = 500)."""
+    h = 2.5
+    res_top, res_bot = nz // 2 - 3, nz // 2 + 3
+    m_true = _shale_model(nz, nx, h, res_top, res_bot, anomalies=anomalies)
+    m_start = _shale_model(nz, nx, h, res_top, res_bot, anomalies=False)
+    rng = np.random.default_rng(2305)
+    iz = nz // 2
+    ch_ix = (nx // 4 + np.arange(nch)).astype(np.int32)
+    ch_iz = np.full(nch, iz, np.int32)
+    shots = []
+    span = max(1, (nx // 2) // max(1, nshots))
+    for k in range(nshots):
+        shots.append(Shot2D(src_iz=iz, src_ix=int(nx * 4 // 15 + span * k),
+                            M=_mt_components(rng, M0), ch_iz=ch_iz, ch_ix=ch_ix))
+    return Workload2D(name=f"plain-2d-{nz}x{nx}", nz=nz, nx=nx, dz=h, dx=h, dt=0.25e-3, nt=nt,
+                      npml=40, f0=60.0, vp_max=3800.0 * 1.05, stf=ricker(nt, 0.25e-3, 60.0),
+                      m_start=m_start, m_true=m_true, shots=shots)
+
+
+def batched_2d(nshots=64, nt=4000, nz=1000, nx=3000, seed=64, M0=1.0e16, zrange=(400, 1000),
+               xrange_=(800, 3000), npml=40):
+    """64 shots on uneven subdomains (nz_s ~ U[400,1000], nx_s ~ U[800,3000]) cut around
+    each source from the plain workload's model; channels are the well's channels inside
+    each window's interior."""
+    base = plain_2d(nz=nz, nx=nx, nt=nt, nshots=1, M0=M0)
+    rng = np.random.default_rng(seed)
+    mt_rng = np.random.default_rng(seed + 1)
+    iz = nz // 2
+    xs = np.linspace(nx / 6.0, nx * 5.0 / 6.0, nshots).round().astype(int)
+    well_ix = base.shots[0].ch_ix
+    shots = []
+    for k in range(nshots):
+        wz = int(rng.integers(zrange[0], zrange[1] + 1))
+        wx = int(rng.integers(xrange_[0], xrange_[1] + 1))
+        wz, wx = min(wz, nz), min(wx, nx)
+        z0 = int(np.clip(iz - wz // 2, 0, nz - wz))
+        x0 = int(np.clip(xs[k] - wx // 2, 0, nx - wx))
+        lo, hi = x0 + npml + 2, x0 + wx - npml - 3
+        sel = well_ix[(well_ix >= lo) & (well_ix <= hi)]
+        shots.append(Shot2D(src_iz=iz, src_ix=int(xs[k]), M=_mt_components(mt_rng, M0),
+                            ch_iz=np.full(len(sel), iz, np.int32), ch_ix=sel.astype(np.int32),
+                            z0=z0, x0=x0, wz=wz, wx=wx))
+    base.name = f"batched-2d-{nshots}shots"
+    base.shots = shots
+    return base
+
+
+def hard_sinkholes(nshots, nz, nx, src_iz, src_ix, a_z=8, a_x=40):
+    """Hard source masks (uint8 [Ns][nz][nx]): 1 inside the ellipse |dz/a_z|^2 + |dx/a_x|^2 < 1
+    around each source, and the matching ZOI weights b (0 inside, 1 elsewhere)."""
+    z = np.arange(nz)[:, None]
+    x = np.arange(nx)[None, :]
+    sink = np.zeros((nshots, nz, nx), np.uint8)
+    for s in range(nshots):
+        sink[s] = (((z - src_iz[s]) / a_z) ** 2 + ((x - src_ix[s]) / a_x) ** 2) < 1.0
+    b = np.where(sink > 0, 0.0, 1.0)
+    return b, sink
+
+
+def perturbed_extension(m, nshots, seed=77, rel=0.01, corr_cells=10.0):
+    """Extended model m~ = S^T m plus per-shot smooth relative noise (so the consistency
+    term is nonzero): [Ns][3][nz][nx]."""
+    out = np.empty((nshots,) + m.shape)
+    for s in range(nshots):
+        for k in range(3):
+            out[s, k] = m[k] * (1.0 + smooth_random_field(m.shape[1:], corr_cells, seed + 3 * s + k, rel))
+    return out
