@@ -1,0 +1,186 @@
+"""Throughput of the source-extended elastic FWI hot path on one MI355X.
+
+One step = one pass of the whole hot path over the plain per-shot workload: for each of the
+20 shots of the 1000 x 3000 (dx = 2.5 m), nt = 4000 shale model, a full shot gradient
+(forward sweep with DAS recording and sqrt(nt) FP32 checkpoints, FP64 misfit, reverse sweep
+with segment recomputation, transposed stress/velocity steps, imaging condition, chain rule
+into the shot's own component m_s of the extended model), then the consistency-regularizer
+value and gradient over the 20-component extended model.
+
+Metric: Gcell-updates/s = shots * nz * nx * nt / wall time (fwd + adj + grad), inputs
+resident in HBM before the timed region. The JSON line also carries:
+* roofline: the dominant kernel's algorithmic bytes per launch over its mean launch time
+  (HIP events around sampled launches on the library's stream), against 8 TB/s;
+* cpu_baseline: the FP64 NumPy oracle on a bounded sample (one shot, full grid, 8 time
+  steps), in the same unit;
+* path: the whole step's algorithmic bytes (204 B per cell-step for fwd + adj + grad with
+  sqrt(nt) recomputation) over the step time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Compulsory bytes per cell of each kernel launch (FP32; each array read or written once):
+#   fwd_vel      read sxx szz sxz vx vz bx bz, write vx vz                     36 B
+#                + store qx qz of the step for the imaging condition           +8 B
+#   fwd_str      read vx vz sxx szz sxz l2m lam muxz, write sxx szz sxz         44 B
+#                + store pxx pzz (pzx+pxz)                                      +12 B
+#   adj_vel      read sxxb szzb sxzb vxb vzb l2m lam muxz, write vxb vzb,
+#                read pxx pzz ps, read+write 3 imaging sums                    76 B
+#   adj_str      read vxb vzb sxxb szzb sxzb bx bz, write sxxb szzb sxzb,
+#                read qx qz, read+write 2 imaging sums                         64 B
+KERNEL_BYTES = {"fwd_vel": (36, 44), "fwd_str": (44, 56), "adj_vel": (76, 76), "adj_str": (64, 64)}
+# Whole-path algorithmic bytes per cell-step (fwd + adj + grad, sqrt(nt) recomputation):
+# forward 52 + stored velocities 8 + adjoint 52 + imaging reads 16 + accumulators 24 + recompute 52.
+PATH_BYTES_PER_CELL_STEP = 204
+
+
+def kernel_bytes_per_launch(name, cells, nt, L):
+    """Mean compulsory bytes per launch: every step is stored once for the imaging condition
+    (the last segment during the first sweep, the others during recomputation), and the
+    first sweep's other steps run without storing."""
+    plain, store = KERNEL_BYTES[name]
+    if name.startswith("adj"):
+        return plain * cells
+    nseg = (nt + L - 1) // L
+    nostore = (nseg - 1) * L
+    return (nostore * plain + nt * store) / (nostore + nt) * cells
+
+
+def cpu_baseline(w, steps=8):
+    """FP64 oracle on one shot of the same grid for `steps` time steps (fwd + adj + grad)."""
+    from oracle import elastic2d as E
+    sh = w.shots[0]
+    g = E.Grid2D(nz=w.nz, nx=w.nx, dz=w.dz, dx=w.dx, dt=w.dt, nt=steps, npml=w.npml, pml_R=w.pml_R,
+                 pml_f0=w.f0, vp_max=w.vp_max)
+    src = np.outer(sh.M, w.stf[:steps])
+    d_obs = np.zeros((len(sh.ch_iz), steps))
+    t0 = time.perf_counter()
+    E.shot_gradient(g, w.m_start, sh.src_iz, sh.src_ix, src, sh.ch_iz, sh.ch_ix, d_obs)
+    dt = time.perf_counter() - t0
+    return {"value": w.nz * w.nx * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 shot, full {w.nz}x{w.nx} grid, {steps} of {w.nt} time steps, fwd+adj+grad, "
+                      f"FP64 NumPy (single-threaded elementwise), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=20, help="shots per step (profiling runs use fewer)")
+    ap.add_argument("--nt", type=int, default=4000, help="time steps (profiling runs use fewer)")
+    ap.add_argument("--sample-every", type=int, default=16, help="time every k-th launch of each kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(shots shard across GPUs by design, see DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2305_14130_amd import efwi, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = inputs.plain_2d(nshots=args.shots, nt=args.nt)
+    ns, nz, nx, nt = len(w.shots), w.nz, w.nx, w.nt
+    grid = efwi.make_grid(nz, nx, w.dz, w.dx, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)
+    shots = [efwi.Shot(s.src_iz, s.src_ix, s.ch_iz, s.ch_ix, ckpt_interval=0) for s in w.shots]
+    T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+
+    # ---- untimed set-up: inputs resident in HBM ----
+    m_start, m_true = T(w.m_start), T(w.m_true)
+    src = T(np.stack([np.outer(s.M, w.stf) for s in w.shots]))
+    fwd_ws = efwi.workspace(efwi.workspace_size(efwi.WS_FORWARD, grid, shots[:1]), dev)
+    d_obs = torch.cat([efwi.model_forward(grid, shots[k], m_true, src[k], ws=fwd_ws) for k in range(ns)])
+    del fwd_ws
+    noise = T(np.stack([inputs.smooth_random_field((nz, nx), 20.0, 77 + k, 0.01) for k in range(3)]))
+    m_ext = torch.stack([m_start * (1.0 + torch.roll(noise, shifts=(0, 37 * k), dims=(1, 2))) for k in range(ns)])
+    b_np, sink_np = inputs.hard_sinkholes(ns, nz, nx, [s.src_iz for s in w.shots], [s.src_ix for s in w.shots])
+    b, sink = T(b_np), torch.tensor(sink_np, device=dev)
+    del b_np, sink_np
+    g_ext = torch.empty_like(m_ext)
+    phi = torch.empty((ns,), dtype=torch.float64, device=dev)
+    phi_reg = torch.empty((), dtype=torch.float64, device=dev)
+    ws = efwi.workspace(efwi.workspace_size(efwi.WS_BATCH, grid, shots), dev)
+    rws = efwi.workspace(efwi.workspace_size(efwi.WS_REGULARIZER, grid, []), dev)
+    torch.cuda.synchronize()
+
+    def step():
+        efwi.batch_gradient(grid, shots, m_ext, src, d_obs, g_ext=g_ext, phi=phi, ws=ws)
+        efwi.extension_regularizer(grid, m_ext, b, sink, 1.0, g_ext, phi=phi_reg, ws=rws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    efwi.timing_reset()
+    efwi.timing_enable(args.sample_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timing = efwi.timing_query()
+    efwi.timing_enable(0)
+    assert bool(torch.isfinite(phi).all()) and bool(torch.isfinite(phi_reg))
+
+    cell_steps = ns * nz * nx * nt * args.steps
+    value = cell_steps / elapsed / 1e9
+    L = int(np.ceil(np.sqrt(nt)))
+    kern = {}
+    for name, (launches, timed, ms) in timing.items():
+        if launches:
+            kern[name] = {"launches": launches, "timed": timed, "mean_us": round(ms * 1e3, 2),
+                          "share": None}
+    total_ms = sum(k["launches"] * k["mean_us"] / 1e3 for k in kern.values())
+    for k in kern.values():
+        k["share"] = round(k["launches"] * k["mean_us"] / 1e3 / total_ms, 4)
+    dominant = max((n for n in kern if n in KERNEL_BYTES), key=lambda n: kern[n]["share"])
+    bytes_launch = kernel_bytes_per_launch(dominant, nz * nx, nt, L)
+    achieved = bytes_launch / (kern[dominant]["mean_us"] * 1e-6) / 1e9
+    out = {
+        "metric": "Gcell-updates/s fwd+adj+grad (and % HBM roofline); shots/s batched vs plain",
+        "value": round(value, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"plain per-shot 2D elastic, {nz}x{nx} dx=2.5m, nt={nt}, {ns} MT shots, "
+                               f"{len(w.shots[0].ch_ix)} DAS channels, CPML {w.npml}, sqrt(nt) FP32 checkpoints, "
+                               f"+ extension regularizer (hard sinkholes)",
+                   "nz": nz, "nx": nx, "nt": nt, "shots": ns, "ckpt_interval": L, "form": "plain per-shot"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": int(bytes_launch), "mean_launch_us": kern[dominant]["mean_us"]},
+        "path": {"bytes_per_cell_step": PATH_BYTES_PER_CELL_STEP,
+                 "achieved_GBs": round(PATH_BYTES_PER_CELL_STEP * cell_steps / elapsed / 1e9, 1),
+                 "frac": round(PATH_BYTES_PER_CELL_STEP * cell_steps / elapsed / 1e9 / HBM_PEAK_GBS, 4)},
+        "shots_per_s": {"plain": round(ns * args.steps / elapsed, 4)},
+        "kernels": kern,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

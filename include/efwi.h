@@ -1,0 +1,171 @@
+/*
+ * efwi.h - C ABI of the MI355X (gfx950) library for the hot path of source-extended
+ * elastic full-waveform inversion (Bader, Clapp, Nihei, Biondi: "Source footprint
+ * elimination in full-waveform inversion by model extension").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments marked DEVICE are device pointers owned by the caller, contiguous,
+ *   FP32 unless stated. Arrays marked HOST are read during the call only.
+ * - Grid arrays are [nz][nx] with x fastest. A model m is [3][nz][nx] = (Vp, Vs, rho)
+ *   in m/s, m/s, kg/m^3. An extended model is [ns][3][nz][nx].
+ * - DAS data are [nch][nt]: d[c][n] is the horizontal strain e_xx at channel c at time
+ *   t_{n+1} = (n+1) dt.
+ * - Source components are [3][nt] = (f_xx, f_zz, f_xz): the moment-tensor components times
+ *   the moment-rate wavelet, sampled at t_{n+1/2} (Forward problem, eq.(2), MT case).
+ * - The library allocates no device memory. Scratch comes from a caller-provided
+ *   workspace of at least efwi_workspace_size() bytes (256-byte aligned). Workspaces
+ *   must not be shared by calls that may overlap in time.
+ * - Every call is asynchronous on the given HIP stream (hipStream_t passed as void*);
+ *   scalar results (misfits) are written to DEVICE doubles.
+ * - All arguments are validated on the host before anything is enqueued; on error the
+ *   call returns a negative efwi_status, enqueues nothing, and efwi_last_error() holds a
+ *   message (thread-local). No exception crosses the ABI.
+ * - Results are deterministic: no floating-point atomics on any result path.
+ *
+ * Discretization (the paper gives none; this is the reading implemented): first-order
+ * velocity-stress system, staggered grid (sxx, szz at (i,j); vx at (i,j+1/2); vz at
+ * (i+1/2,j); sxz at (i+1/2,j+1/2)), 4th-order differences (9/8, -1/24), leapfrog in time,
+ * values outside the grid zero, unsplit CPML (kappa = 1) in strips of npml cells.
+ */
+#ifndef EFWI_H
+#define EFWI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EFWI_OK = 0,
+  EFWI_E_INVAL = -1,        /* null pointer, bad size, duplicate channel, nt < 1 ...   */
+  EFWI_E_RANGE = -2,        /* source or channel outside the window interior / in CPML */
+  EFWI_E_CFL = -3,          /* dt * vp_max * (9/8 + 1/24) * sqrt(sum 1/h^2) >= 1       */
+  EFWI_E_WORKSPACE = -4,    /* workspace smaller than efwi_workspace_size()            */
+  EFWI_E_HIP = -5,          /* a HIP runtime call failed (message in efwi_last_error)  */
+  EFWI_E_NONFINITE = -6,    /* reserved: non-finite value detected                      */
+  EFWI_E_UNSUPPORTED = -7   /* option not supported by this build                       */
+} efwi_status;
+
+/* Simulation grid. In the batched call nz, nx are the extended model's full size and each
+ * shot runs on its own window. */
+typedef struct {
+  int ndim;        /* 2                                                              */
+  int nz, ny, nx;  /* grid points; ny = 1 in 2D                                      */
+  float dz, dy, dx;/* spacing in m                                                   */
+  float dt;        /* time step in s                                                 */
+  int nt;          /* number of time steps                                           */
+  int npml;        /* CPML thickness in cells, inside each window (0: rigid walls)   */
+  float pml_R;     /* CPML target reflection coefficient (e.g. 1e-3)                 */
+  float pml_f0;    /* CPML frequency-shift parameter alpha_max = pi * pml_f0         */
+  float vp_max;    /* caller's bound on Vp: CFL check and CPML damping d0            */
+} efwi_grid;
+
+/* Checkpoint storage modes for the reverse sweep (wavefield recomputation). */
+enum { EFWI_CKPT_FP32 = 0, EFWI_CKPT_BF16 = 1, EFWI_CKPT_FP16 = 2 };
+
+/* One shot: a moment-tensor source, its DAS channels and its subdomain window. */
+typedef struct {
+  int src_iz, src_iy, src_ix; /* normal node of the source, full-model coordinates       */
+  int nch;                    /* number of DAS channels (>= 0)                           */
+  const int* ch_iz;           /* HOST [nch] channel normal nodes (full-model coords)     */
+  const int* ch_iy;           /* HOST [nch], may be NULL in 2D                           */
+  const int* ch_ix;           /* HOST [nch]                                              */
+  int z0, y0, x0;             /* window origin in the full model                         */
+  int wz, wy, wx;             /* window size; 0 means "to the end of the model"          */
+  int ckpt_interval;          /* time steps per checkpoint segment; 0 = ceil(sqrt(nt));
+                                 >= nt = keep the whole forward history (no recompute)   */
+  int ckpt_mode;              /* EFWI_CKPT_*                                             */
+} efwi_shot;
+
+/* Which entry point a workspace is sized for. */
+typedef enum {
+  EFWI_WS_FORWARD = 0,
+  EFWI_WS_ADJOINT = 1,
+  EFWI_WS_GRADIENT = 2,
+  EFWI_WS_BATCH = 3,
+  EFWI_WS_REGULARIZER = 4
+} efwi_ws_kind;
+
+/* Workspace bytes needed by one call of the given kind (0 on invalid arguments; see
+ * efwi_last_error). For EFWI_WS_BATCH, shots points to ns HOST descriptors. */
+size_t efwi_workspace_size(efwi_ws_kind kind, const efwi_grid* grid, int ns, const efwi_shot* shots);
+
+/* Host-side validation only (no HIP call): the checks every entry point runs first. */
+efwi_status efwi_validate(const efwi_grid* grid, int ns, const efwi_shot* shots);
+
+/* model_forward: d = K_r u_s(m) for one shot (Forward problem, eqs.(1)-(3)).
+ *   m   DEVICE [3][nz][nx] model (Vp, Vs, rho); only the shot's window is read.
+ *   src DEVICE [3][nt] source components.
+ *   d   DEVICE [nch][nt] output, overwritten. */
+efwi_status efwi_model_forward(const efwi_grid* grid, const efwi_shot* shot, const float* m,
+                               const float* src, float* d, void* ws, size_t ws_bytes, void* stream);
+
+/* model_adjoint: src_bar = L^T r, the exact transpose of model_forward with respect to the
+ * source components (used for the dot-product test <L f, r> = <f, L^T r>).
+ *   r       DEVICE [nch][nt] data-space input.
+ *   src_bar DEVICE [3][nt] output, overwritten. */
+efwi_status efwi_model_adjoint(const efwi_grid* grid, const efwi_shot* shot, const float* m,
+                               const float* r, float* src_bar, void* ws, size_t ws_bytes, void* stream);
+
+/* shot_gradient: data misfit phi_s = 1/2 ||d_s(m_s) - d_obs||^2 (eq.(4), data term of
+ * eq.(8)) and its gradient g_s = J_s^T (d_s - d_obs) (eq.(6)) with respect to m_s =
+ * (Vp, Vs, rho): the exact transpose of the discrete forward map, computed by the
+ * adjoint-state method with checkpointed recomputation of the forward wavefield.
+ *   d_obs DEVICE [nch][nt].
+ *   g     DEVICE [3][nz][nx] output, overwritten (zero outside the shot's window).
+ *   phi   DEVICE double, overwritten.
+ *   d_out DEVICE [nch][nt] predicted data, or NULL. */
+efwi_status efwi_shot_gradient(const efwi_grid* grid, const efwi_shot* shot, const float* m,
+                               const float* src, const float* d_obs, float* g, double* phi,
+                               float* d_out, void* ws, size_t ws_bytes, void* stream);
+
+/* batch_gradient: the data term of eq.(8) for ns shots at once, each shot s on its own
+ * component m_s of the extended model and its own window, advanced together (one launch
+ * per half step covers every shot's tiles).
+ *   m_ext DEVICE [ns][3][nz][nx]; src DEVICE [ns][3][nt];
+ *   d_obs DEVICE concatenation of the shots' [nch_s][nt] blocks in shot order;
+ *   g_ext DEVICE [ns][3][nz][nx] output, overwritten (slot s holds g_s);
+ *   phi   DEVICE double [ns] output. */
+efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* shots,
+                                const float* m_ext, const float* src, const float* d_obs,
+                                float* g_ext, double* phi, void* ws, size_t ws_bytes, void* stream);
+
+/* extension_regularizer: value and gradient of 1/2 eta^2 ||(I - S^T S_w) W m~||^2 (eq.(8)
+ * second term), with W from eq.(11) (sinkhole samples of m_s replaced by the b-weighted mix
+ * of the other components; a row whose other weights sum to 0 is the identity), S_w from
+ * eq.(12) (b'_s = 1 inside s's sinkhole, b_s elsewhere; points where sum b' = 0 contribute
+ * nothing) and S^T the copy along shots. Pointwise in space, same weights for Vp, Vs, rho.
+ *   m_ext DEVICE [ns][3][nz][nx]; b DEVICE [ns][nz][nx] weights in [0,1];
+ *   sink  DEVICE unsigned char [ns][nz][nx], nonzero inside s's sinkhole;
+ *   g_ext DEVICE [ns][3][nz][nx], ACCUMULATED (+=) so data and penalty gradients sum;
+ *   phi   DEVICE double, overwritten with the penalty value. */
+efwi_status efwi_extension_regularizer(const efwi_grid* grid, int ns, const float* m_ext,
+                                       const float* b, const unsigned char* sink, float eta,
+                                       float* g_ext, double* phi, void* ws, size_t ws_bytes,
+                                       void* stream);
+
+/* Kernel timing sampler (profiling aid, off by default). With sample_every = k > 0, every
+ * k-th launch of each kernel kind is bracketed by two HIP events recorded on the launch's
+ * stream; 0 turns sampling off. efwi_timing_query() waits for the pending events of one kind
+ * and returns the number of launches, of timed launches and their summed duration in ms.
+ * Kinds are 0 .. efwi_kernel_count() - 1, named by efwi_kernel_name(). */
+efwi_status efwi_timing_enable(int sample_every);
+efwi_status efwi_timing_reset(void);
+efwi_status efwi_timing_query(int kind, long* launches, long* timed, double* total_ms);
+int efwi_kernel_count(void);
+const char* efwi_kernel_name(int kind);
+
+/* Human-readable name of a status code (static storage). */
+const char* efwi_status_string(efwi_status s);
+/* Message of the last failing call on this thread (static thread-local storage). */
+const char* efwi_last_error(void);
+/* Library version string. */
+const char* efwi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EFWI_H */

@@ -1,0 +1,93 @@
+// Internal declarations shared by the HIP kernels and the host-side C ABI.
+// Not installed; the public interface is include/efwi.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace efwi {
+
+// Padded field layout: every wavefield and staged-parameter array has HALO zero cells on
+// each side in z and x so that the 4th-order stencils never branch on the grid edge.
+constexpr int HALO = 2;
+// Thread-block shape of the 2D stencil kernels: 64 lanes along x (one wavefront per row)
+// by 4 rows along z.
+constexpr int BX = 64;
+constexpr int BZ = 4;
+// Number of per-step forward quantities kept for the imaging condition:
+// pxx, pzz (normal node), pzx + pxz (shear node), qx (vx node), qz (vz node).
+constexpr int NSEG_FIELDS = 5;
+// Number of imaging accumulators: lambda, mu (normal), mu_xz (shear), b_x, b_z.
+constexpr int NACC = 5;
+// Time steps summed in FP32 before the imaging sums are chained into the FP64 gradient.
+constexpr int FLUSH_STEPS = 32;
+
+// Everything a 2D kernel needs about one shot. Pointers to padded arrays point at the
+// interior origin (i = 0, j = 0); element (i, j) is at p[i * ld + j].
+struct Shot2D {
+  int nz, nx, ld, P;            // window size, padded pitch, CPML strip half-width (0: none)
+  int nt, nch;
+  int si, sj;                   // source normal node, window coordinates
+  float dt, rdx, rdz, w;        // w = dt / (dx dz)
+  long cells;                   // nz * nx
+  // forward state
+  float *vx, *vz, *sxx, *szz, *sxz;
+  float* psx[4];                // x-strip memory variables [nz][2P]: VXX, VZX, XX, XZ
+  float* psz[4];                // z-strip memory variables [2P][nx]: VXZ, VZZ, ZZ, XZ
+  // adjoint state
+  float *vxb, *vzb, *sxxb, *szzb, *sxzb;
+  float* pbx[2][4];             // double-buffered x-strip adjoint memory variables
+  float* pbz[2][4];             // double-buffered z-strip adjoint memory variables
+  // staged parameters (padded, zero halo)
+  float *l2m, *lam, *muxz, *bx, *bz;
+  // CPML profiles: axi bxi axh bxh [nx] then azi bzi azh bzh [nz]
+  const float* prof;
+  // source
+  const float* src;             // [3][nt]
+  float* src_bar;               // [3][nt] (adjoint only)
+  // DAS
+  const int* row_slot;          // [nz]: slot of the row in rowch, or -1
+  const int* rowch;             // [nslots][nx]: channel id at normal node, or -1
+  float* e;                     // [nch] running strain
+  float* d;                     // [nch][nt]
+  const float* ebar;            // [nt][nch] reverse cumulative residual
+  // model window (unpadded, full-model pitch) for the chain rule
+  const float *mvp, *mvs, *mrho;
+  long mld;
+  // imaging
+  float* seg;                   // [L][5][cells]
+  float* acc;                   // [5][cells]
+  double* G;                    // [3][cells]
+};
+
+// Strip index helpers (x: column j of width nx; z: row i of height nz).
+__host__ __device__ inline int strip_index(int k, int n, int P) {
+  if (P <= 0) return -1;
+  if (k < P) return k;
+  if (k >= n - P) return k - (n - 2 * P);
+  return -1;
+}
+
+// Kernel launchers (kernels2d.hip). All enqueue on `st` and return hipGetLastError().
+hipError_t launch_stage2d(const Shot2D& s, hipStream_t st);
+hipError_t launch_fwd_vel(const Shot2D& s, int n, float* seg_step, hipStream_t st);
+hipError_t launch_fwd_str(const Shot2D& s, int n, float* seg_step, bool record, hipStream_t st);
+hipError_t launch_adj_vel(const Shot2D& s, int n, const float* seg_step, bool grad, bool first,
+                          bool srcadj, hipStream_t st);
+hipError_t launch_adj_str(const Shot2D& s, int n, const float* seg_step, bool grad, bool first,
+                          hipStream_t st);
+hipError_t launch_chain_flush(const Shot2D& s, hipStream_t st);
+hipError_t launch_write_gradient(const Shot2D& s, float* g, long mplane, int z0, int x0,
+                                 hipStream_t st);
+hipError_t launch_misfit(const Shot2D& s, const float* d, const float* dobs, double* partial,
+                         double* phi, float* ebar, hipStream_t st);
+hipError_t launch_residual_cumsum(const Shot2D& s, const float* r, float* ebar, hipStream_t st);
+
+// Regularizer (regularizer.hip).
+hipError_t launch_regularizer(int ns, long npts, long plane, const float* m_ext, const float* b,
+                              const unsigned char* sink, float eta, float* g_ext, double* partial,
+                              int nblocks, double* phi, hipStream_t st);
+int regularizer_blocks(long npts);
+
+}  // namespace efwi

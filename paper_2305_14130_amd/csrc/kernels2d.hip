@@ -1,0 +1,622 @@
+// 2D isotropic elastic velocity-stress kernels for gfx950 (forward, exact transpose,
+// imaging condition, chain rule, misfit).
+//
+// Method passages: Forward problem eq.(1) (wave equation), eq.(2) (moment-tensor point
+// source), eq.(3) (sampling operator, here DAS e_xx); Solving the inverse problem eq.(4)
+// (L2 misfit) and eq.(6) (per-shot gradient J_s^T r by the adjoint-state method); Model
+// extension eq.(8) (shot s differentiates only its own component m_s).
+//
+// Staggering: sxx, szz at (i, j); vx at (i, j+1/2); vz at (i+1/2, j); sxz at (i+1/2, j+1/2).
+// Differences are 4th order with coefficients 9/8 and -1/24, values outside the grid are
+// zero (zero halo of the padded arrays), time stepping is leapfrog, the absorbing
+// boundary is an unsplit CPML with kappa = 1 whose memory variables live only in strips.
+//
+// The stencils are bandwidth bound (well under 1 flop/byte), so there is no MFMA: each
+// thread owns one cell (one node of every type), a wavefront covers 64 consecutive x, and
+// neighbour reads are served by L1/L2. The adjoint kernels are the exact transposes of the
+// forward sub-steps: material parameters sit inside the transposed differences, so they
+// are separate kernels rather than the forward run backwards.
+#include "efwi_internal.h"
+
+namespace efwi {
+namespace {
+
+constexpr float K1 = 1.125f;              // 9/8
+constexpr float K2 = -0.041666666666666664f;  // -1/24
+
+// Strip slots (see Shot2D): x-strips
+constexpr int X_VXX = 0, X_VZX = 1, X_XX = 2, X_XZ = 3;
+// z-strips
+constexpr int Z_VXZ = 0, Z_VZZ = 1, Z_ZZ = 2, Z_XZ = 3;
+
+__device__ __forceinline__ const float* axi(const Shot2D& s) { return s.prof; }
+__device__ __forceinline__ const float* bxi(const Shot2D& s) { return s.prof + s.nx; }
+__device__ __forceinline__ const float* axh(const Shot2D& s) { return s.prof + 2 * s.nx; }
+__device__ __forceinline__ const float* bxh(const Shot2D& s) { return s.prof + 3 * s.nx; }
+__device__ __forceinline__ const float* azi(const Shot2D& s) { return s.prof + 4 * s.nx; }
+__device__ __forceinline__ const float* bzi(const Shot2D& s) { return s.prof + 4 * s.nx + s.nz; }
+__device__ __forceinline__ const float* azh(const Shot2D& s) { return s.prof + 4 * s.nx + 2 * s.nz; }
+__device__ __forceinline__ const float* bzh(const Shot2D& s) { return s.prof + 4 * s.nx + 3 * s.nz; }
+
+// Forward D+ at the half node after index k, and D- at integer node k (array index k holds
+// the half node k+1/2); `st` is the element stride along the axis.
+__device__ __forceinline__ float dplus(const float* f, long o, long st, float r) {
+  return (K1 * (f[o + st] - f[o]) + K2 * (f[o + 2 * st] - f[o - st])) * r;
+}
+__device__ __forceinline__ float dminus(const float* f, long o, long st, float r) {
+  return (K1 * (f[o] - f[o - st]) + K2 * (f[o + st] - f[o - 2 * st])) * r;
+}
+
+// Does the block touch a CPML strip (with `pad` extra cells of neighbourhood)?
+__device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, int pad) {
+  if (s.P <= 0) return false;
+  const int j1 = j0 + BX - 1 + pad, i1 = i0 + BZ - 1 + pad;
+  return (j0 - pad < s.P) || (j1 >= s.nx - s.P) || (i0 - pad < s.P) || (i1 >= s.nz - s.P);
+}
+
+// ------------------------------------------------------------------------------------
+// Forward velocity half step: v^{n+1/2} = v^{n-1/2} + dt b (div sigma^n), CPML in strips.
+// ------------------------------------------------------------------------------------
+template <bool STORE>
+__device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, bool pml, float* seg) {
+  const long ld = s.ld;
+  const long o = (long)i * ld + j;
+  float d1 = dplus(s.sxx, o, 1, s.rdx);    // D+x sxx at (i, j+1/2)
+  float d2 = dminus(s.sxz, o, ld, s.rdz);  // D-z sxz at (i, j+1/2)
+  float d3 = dminus(s.sxz, o, 1, s.rdx);   // D-x sxz at (i+1/2, j)
+  float d4 = dplus(s.szz, o, ld, s.rdz);   // D+z szz at (i+1/2, j)
+  if (pml) {
+    const int sx = strip_index(j, s.nx, s.P);
+    const int sz = strip_index(i, s.nz, s.P);
+    if (sx >= 0) {
+      const long q = (long)i * 2 * s.P + sx;
+      float p = bxh(s)[j] * s.psx[X_VXX][q] + axh(s)[j] * d1;
+      s.psx[X_VXX][q] = p;
+      d1 += p;
+      p = bxi(s)[j] * s.psx[X_VZX][q] + axi(s)[j] * d3;
+      s.psx[X_VZX][q] = p;
+      d3 += p;
+    }
+    if (sz >= 0) {
+      const long q = (long)sz * s.nx + j;
+      float p = bzi(s)[i] * s.psz[Z_VXZ][q] + azi(s)[i] * d2;
+      s.psz[Z_VXZ][q] = p;
+      d2 += p;
+      p = bzh(s)[i] * s.psz[Z_VZZ][q] + azh(s)[i] * d4;
+      s.psz[Z_VZZ][q] = p;
+      d4 += p;
+    }
+  }
+  const float qx = d1 + d2, qz = d3 + d4;
+  s.vx[o] += s.dt * s.bx[o] * qx;
+  s.vz[o] += s.dt * s.bz[o] * qz;
+  if (STORE) {
+    const long c = (long)i * s.nx + j;
+    seg[3 * s.cells + c] = qx;
+    seg[4 * s.cells + c] = qz;
+  }
+}
+
+template <bool STORE>
+__global__ __launch_bounds__(BX * BZ) void k_fwd_vel(const Shot2D s, float* seg) {
+  const int j0 = blockIdx.x * BX, i0 = blockIdx.y * BZ;
+  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  const bool pml = block_in_pml(s, j0, i0, 0);
+  if (i < s.nz && j < s.nx) fwd_vel_cell<STORE>(s, i, j, pml, seg);
+}
+
+// ------------------------------------------------------------------------------------
+// Forward stress half step: sigma^{n+1} = sigma^n + dt C (strain rate of v^{n+1/2}),
+// moment-tensor injection at t_{n+1/2}, DAS strain record.
+// ------------------------------------------------------------------------------------
+template <bool STORE, bool RECORD>
+__device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int n, bool pml, float* seg) {
+  const long ld = s.ld;
+  const long o = (long)i * ld + j;
+  float pxx = dminus(s.vx, o, 1, s.rdx);   // D-x vx at (i, j)
+  float pzz = dminus(s.vz, o, ld, s.rdz);  // D-z vz at (i, j)
+  float pzx = dplus(s.vx, o, ld, s.rdz);   // D+z vx at (i+1/2, j+1/2)
+  float pxz = dplus(s.vz, o, 1, s.rdx);    // D+x vz at (i+1/2, j+1/2)
+  const float raw_pxx = pxx;
+  if (pml) {
+    const int sx = strip_index(j, s.nx, s.P);
+    const int sz = strip_index(i, s.nz, s.P);
+    if (sx >= 0) {
+      const long q = (long)i * 2 * s.P + sx;
+      float p = bxi(s)[j] * s.psx[X_XX][q] + axi(s)[j] * pxx;
+      s.psx[X_XX][q] = p;
+      pxx += p;
+      p = bxh(s)[j] * s.psx[X_XZ][q] + axh(s)[j] * pxz;
+      s.psx[X_XZ][q] = p;
+      pxz += p;
+    }
+    if (sz >= 0) {
+      const long q = (long)sz * s.nx + j;
+      float p = bzi(s)[i] * s.psz[Z_ZZ][q] + azi(s)[i] * pzz;
+      s.psz[Z_ZZ][q] = p;
+      pzz += p;
+      p = bzh(s)[i] * s.psz[Z_XZ][q] + azh(s)[i] * pzx;
+      s.psz[Z_XZ][q] = p;
+      pzx += p;
+    }
+  }
+  const float l2m = s.l2m[o], lam = s.lam[o];
+  const float ps = pzx + pxz;
+  float sxx = s.sxx[o] + s.dt * (l2m * pxx + lam * pzz);
+  float szz = s.szz[o] + s.dt * (lam * pxx + l2m * pzz);
+  float sxz = s.sxz[o] + s.dt * s.muxz[o] * ps;
+  if (i == s.si && j == s.sj) {
+    sxx -= s.w * s.src[n];
+    szz -= s.w * s.src[s.nt + n];
+  }
+  if ((i == s.si || i == s.si - 1) && (j == s.sj || j == s.sj - 1)) sxz -= 0.25f * s.w * s.src[2 * s.nt + n];
+  s.sxx[o] = sxx;
+  s.szz[o] = szz;
+  s.sxz[o] = sxz;
+  if (RECORD) {
+    const int slot = s.row_slot[i];
+    if (slot >= 0) {
+      const int c = s.rowch[(long)slot * s.nx + j];
+      if (c >= 0) {
+        const float e = s.e[c] + s.dt * raw_pxx;
+        s.e[c] = e;
+        s.d[(long)c * s.nt + n] = e;
+      }
+    }
+  }
+  if (STORE) {
+    const long c = (long)i * s.nx + j;
+    seg[c] = pxx;
+    seg[s.cells + c] = pzz;
+    seg[2 * s.cells + c] = ps;
+  }
+}
+
+template <bool STORE, bool RECORD>
+__global__ __launch_bounds__(BX * BZ) void k_fwd_str(const Shot2D s, int n, float* seg) {
+  const int j0 = blockIdx.x * BX, i0 = blockIdx.y * BZ;
+  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  const bool pml = block_in_pml(s, j0, i0, 0);
+  if (i < s.nz && j < s.nx) fwd_str_cell<STORE, RECORD>(s, i, j, n, pml, seg);
+}
+
+// ------------------------------------------------------------------------------------
+// Transposed stress sub-step (run first at reverse step n): with sigma_bar the adjoint of
+// sigma^{n+1}, p_bar = dt C sigma_bar (+ CPML transpose), v_bar += D^T p_bar; DAS transpose
+// injects dt * e_bar through (D-x)^T at the vx nodes around each channel; imaging terms for
+// lambda, mu, mu_xz; optional transpose of the source injection.
+// ------------------------------------------------------------------------------------
+struct PbarCtx {
+  const Shot2D& s;
+  bool pml;
+  const float* const* px;   // x-strip adjoint memory variables, current
+  const float* const* pz;   // z-strip, current
+};
+
+// Corrected p_bar for pxx at normal node (ii, jj): dt((l+2m) sxx_b + l szz_b) + CPML(XX, x int)
+__device__ __forceinline__ float pbar_xx(const PbarCtx& c, int ii, int jj) {
+  const Shot2D& s = c.s;
+  const long oo = (long)ii * s.ld + jj;
+  float v = s.dt * (s.l2m[oo] * s.sxxb[oo] + s.lam[oo] * s.szzb[oo]);
+  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+    const int sx = strip_index(jj, s.nx, s.P);
+    if (sx >= 0) v += axi(s)[jj] * (c.px[X_XX][(long)ii * 2 * s.P + sx] + v);
+  }
+  return v;
+}
+__device__ __forceinline__ float pbar_zz(const PbarCtx& c, int ii, int jj) {
+  const Shot2D& s = c.s;
+  const long oo = (long)ii * s.ld + jj;
+  float v = s.dt * (s.lam[oo] * s.sxxb[oo] + s.l2m[oo] * s.szzb[oo]);
+  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+    const int sz = strip_index(ii, s.nz, s.P);
+    if (sz >= 0) v += azi(s)[ii] * (c.pz[Z_ZZ][(long)sz * s.nx + jj] + v);
+  }
+  return v;
+}
+// shear node: pzx uses the z-half profile (Z_XZ), pxz the x-half profile (X_XZ)
+__device__ __forceinline__ float pbar_zx(const PbarCtx& c, int ii, int jj) {
+  const Shot2D& s = c.s;
+  const long oo = (long)ii * s.ld + jj;
+  float v = s.dt * s.muxz[oo] * s.sxzb[oo];
+  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+    const int sz = strip_index(ii, s.nz, s.P);
+    if (sz >= 0) v += azh(s)[ii] * (c.pz[Z_XZ][(long)sz * s.nx + jj] + v);
+  }
+  return v;
+}
+__device__ __forceinline__ float pbar_xz(const PbarCtx& c, int ii, int jj) {
+  const Shot2D& s = c.s;
+  const long oo = (long)ii * s.ld + jj;
+  float v = s.dt * s.muxz[oo] * s.sxzb[oo];
+  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+    const int sx = strip_index(jj, s.nx, s.P);
+    if (sx >= 0) v += axh(s)[jj] * (c.px[X_XZ][(long)ii * 2 * s.P + sx] + v);
+  }
+  return v;
+}
+
+__device__ __forceinline__ float ebar_at(const Shot2D& s, int slot, int jc, int n) {
+  if (jc < 0 || jc >= s.nx) return 0.0f;
+  const int c = s.rowch[(long)slot * s.nx + jc];
+  return c >= 0 ? s.ebar[(long)n * s.nch + c] : 0.0f;
+}
+
+template <bool GRAD, bool SRCADJ>
+__device__ __forceinline__ void adj_vel_cell(const Shot2D& s, int i, int j, int n, bool pml,
+                                             const float* seg, bool first) {
+  const long ld = s.ld;
+  const long o = (long)i * ld + j;
+  const int rd = (n + 1) & 1, wr = n & 1;
+  const PbarCtx c{s, pml, s.pbx[rd], s.pbz[rd]};
+  // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx)
+  float ux = K1 * (pbar_xx(c, i, j + 1) - pbar_xx(c, i, j)) + K2 * (pbar_xx(c, i, j + 2) - pbar_xx(c, i, j - 1));
+  float uz = K1 * (pbar_zx(c, i, j) - pbar_zx(c, i - 1, j)) + K2 * (pbar_zx(c, i + 1, j) - pbar_zx(c, i - 2, j));
+  float gx = -(ux * s.rdx + uz * s.rdz);
+  // v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
+  float wz = K1 * (pbar_zz(c, i + 1, j) - pbar_zz(c, i, j)) + K2 * (pbar_zz(c, i + 2, j) - pbar_zz(c, i - 1, j));
+  float wx = K1 * (pbar_xz(c, i, j) - pbar_xz(c, i, j - 1)) + K2 * (pbar_xz(c, i, j + 1) - pbar_xz(c, i, j - 2));
+  const float gz = -(wz * s.rdz + wx * s.rdx);
+  // DAS transpose: channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1), jc+1 (c2), jc-2 (-c2)
+  const int slot = s.row_slot[i];
+  if (slot >= 0) {
+    const float inj = K1 * (ebar_at(s, slot, j, n) - ebar_at(s, slot, j + 1, n)) +
+                      K2 * (ebar_at(s, slot, j - 1, n) - ebar_at(s, slot, j + 2, n));
+    gx += s.dt * s.rdx * inj;
+  }
+  const float sxxb = s.sxxb[o], szzb = s.szzb[o], sxzb = s.sxzb[o];
+  // owned adjoint memory variables: psi_bar_next = b (psi_bar + p_bar~)
+  if (pml) {
+    const int sx = strip_index(j, s.nx, s.P);
+    const int sz = strip_index(i, s.nz, s.P);
+    const float pxx_t = s.dt * (s.l2m[o] * sxxb + s.lam[o] * szzb);
+    const float pzz_t = s.dt * (s.lam[o] * sxxb + s.l2m[o] * szzb);
+    const float ps_t = s.dt * s.muxz[o] * sxzb;
+    if (sx >= 0) {
+      const long q = (long)i * 2 * s.P + sx;
+      s.pbx[wr][X_XX][q] = bxi(s)[j] * (s.pbx[rd][X_XX][q] + pxx_t);
+      s.pbx[wr][X_XZ][q] = bxh(s)[j] * (s.pbx[rd][X_XZ][q] + ps_t);
+    }
+    if (sz >= 0) {
+      const long q = (long)sz * s.nx + j;
+      s.pbz[wr][Z_ZZ][q] = bzi(s)[i] * (s.pbz[rd][Z_ZZ][q] + pzz_t);
+      s.pbz[wr][Z_XZ][q] = bzh(s)[i] * (s.pbz[rd][Z_XZ][q] + ps_t);
+    }
+  }
+  s.vxb[o] += gx;
+  s.vzb[o] += gz;
+  if (GRAD) {
+    const long cc = (long)i * s.nx + j;
+    const float pxx = seg[cc], pzz = seg[s.cells + cc], ps = seg[2 * s.cells + cc];
+    const float a0 = s.dt * (sxxb + szzb) * (pxx + pzz);
+    const float a1 = 2.0f * s.dt * (sxxb * pxx + szzb * pzz);
+    const float a2 = s.dt * sxzb * ps;
+    float* acc = s.acc;
+    if (first) {
+      acc[cc] = a0;
+      acc[s.cells + cc] = a1;
+      acc[2 * s.cells + cc] = a2;
+    } else {
+      acc[cc] += a0;
+      acc[s.cells + cc] += a1;
+      acc[2 * s.cells + cc] += a2;
+    }
+  }
+  if (SRCADJ && i == s.si && j == s.sj) {
+    s.src_bar[n] = -s.w * sxxb;
+    s.src_bar[s.nt + n] = -s.w * szzb;
+    const float t = s.sxzb[o] + s.sxzb[o - 1] + s.sxzb[o - ld] + s.sxzb[o - ld - 1];
+    s.src_bar[2 * s.nt + n] = -0.25f * s.w * t;
+  }
+}
+
+template <bool GRAD, bool SRCADJ>
+__global__ __launch_bounds__(BX * BZ) void k_adj_vel(const Shot2D s, int n, const float* seg, int first) {
+  const int j0 = blockIdx.x * BX, i0 = blockIdx.y * BZ;
+  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  const bool pml = block_in_pml(s, j0, i0, 2);
+  if (i < s.nz && j < s.nx) adj_vel_cell<GRAD, SRCADJ>(s, i, j, n, pml, seg, first != 0);
+}
+
+// ------------------------------------------------------------------------------------
+// Transposed velocity sub-step (second at reverse step n): q_bar = dt b v_bar (+ CPML
+// transpose), sigma_bar += D^T q_bar; imaging terms for b_x, b_z.
+// ------------------------------------------------------------------------------------
+struct QbarCtx {
+  const Shot2D& s;
+  bool pml;
+  const float* const* px;
+  const float* const* pz;
+};
+// qx_bar at vx node corrected for D+x sxx (x-half, X_VXX)
+__device__ __forceinline__ float qbar_xa(const QbarCtx& c, int ii, int jj) {
+  const Shot2D& s = c.s;
+  const long oo = (long)ii * s.ld + jj;
+  float v = s.dt * s.bx[oo] * s.vxb[oo];
+  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+    const int sx = strip_index(jj, s.nx, s.P);
+    if (sx >= 0) v += axh(s)[jj] * (c.px[X_VXX][(long)ii * 2 * s.P + sx] + v);
+  }
+  return v;
+}
+// qx_bar corrected for D-z sxz (z-int, Z_VXZ)
+__device__ __forceinline__ float qbar_xb(const QbarCtx& c, int ii, int jj) {
+  const Shot2D& s = c.s;
+  const long oo = (long)ii * s.ld + jj;
+  float v = s.dt * s.bx[oo] * s.vxb[oo];
+  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+    const int sz = strip_index(ii, s.nz, s.P);
+    if (sz >= 0) v += azi(s)[ii] * (c.pz[Z_VXZ][(long)sz * s.nx + jj] + v);
+  }
+  return v;
+}
+// qz_bar corrected for D-x sxz (x-int, X_VZX)
+__device__ __forceinline__ float qbar_za(const QbarCtx& c, int ii, int jj) {
+  const Shot2D& s = c.s;
+  const long oo = (long)ii * s.ld + jj;
+  float v = s.dt * s.bz[oo] * s.vzb[oo];
+  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+    const int sx = strip_index(jj, s.nx, s.P);
+    if (sx >= 0) v += axi(s)[jj] * (c.px[X_VZX][(long)ii * 2 * s.P + sx] + v);
+  }
+  return v;
+}
+// qz_bar corrected for D+z szz (z-half, Z_VZZ)
+__device__ __forceinline__ float qbar_zb(const QbarCtx& c, int ii, int jj) {
+  const Shot2D& s = c.s;
+  const long oo = (long)ii * s.ld + jj;
+  float v = s.dt * s.bz[oo] * s.vzb[oo];
+  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+    const int sz = strip_index(ii, s.nz, s.P);
+    if (sz >= 0) v += azh(s)[ii] * (c.pz[Z_VZZ][(long)sz * s.nx + jj] + v);
+  }
+  return v;
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void adj_str_cell(const Shot2D& s, int i, int j, int n, bool pml,
+                                             const float* seg, bool first) {
+  const long ld = s.ld;
+  const long o = (long)i * ld + j;
+  const int rd = (n + 1) & 1, wr = n & 1;
+  const QbarCtx c{s, pml, s.pbx[rd], s.pbz[rd]};
+  // sxx_bar += -D-x qa ; szz_bar += -D-z qzb ; sxz_bar += -(D+z qxb + D+x qza)
+  const float txx = K1 * (qbar_xa(c, i, j) - qbar_xa(c, i, j - 1)) + K2 * (qbar_xa(c, i, j + 1) - qbar_xa(c, i, j - 2));
+  const float tzz = K1 * (qbar_zb(c, i, j) - qbar_zb(c, i - 1, j)) + K2 * (qbar_zb(c, i + 1, j) - qbar_zb(c, i - 2, j));
+  const float t1 = K1 * (qbar_xb(c, i + 1, j) - qbar_xb(c, i, j)) + K2 * (qbar_xb(c, i + 2, j) - qbar_xb(c, i - 1, j));
+  const float t2 = K1 * (qbar_za(c, i, j + 1) - qbar_za(c, i, j)) + K2 * (qbar_za(c, i, j + 2) - qbar_za(c, i, j - 1));
+  const float vxb = s.vxb[o], vzb = s.vzb[o];
+  if (pml) {
+    const int sx = strip_index(j, s.nx, s.P);
+    const int sz = strip_index(i, s.nz, s.P);
+    const float qx_t = s.dt * s.bx[o] * vxb;
+    const float qz_t = s.dt * s.bz[o] * vzb;
+    if (sx >= 0) {
+      const long q = (long)i * 2 * s.P + sx;
+      s.pbx[wr][X_VXX][q] = bxh(s)[j] * (s.pbx[rd][X_VXX][q] + qx_t);
+      s.pbx[wr][X_VZX][q] = bxi(s)[j] * (s.pbx[rd][X_VZX][q] + qz_t);
+    }
+    if (sz >= 0) {
+      const long q = (long)sz * s.nx + j;
+      s.pbz[wr][Z_VXZ][q] = bzi(s)[i] * (s.pbz[rd][Z_VXZ][q] + qx_t);
+      s.pbz[wr][Z_VZZ][q] = bzh(s)[i] * (s.pbz[rd][Z_VZZ][q] + qz_t);
+    }
+  }
+  s.sxxb[o] -= txx * s.rdx;
+  s.szzb[o] -= tzz * s.rdz;
+  s.sxzb[o] -= t1 * s.rdz + t2 * s.rdx;
+  if (GRAD) {
+    const long cc = (long)i * s.nx + j;
+    const float a3 = s.dt * vxb * seg[3 * s.cells + cc];
+    const float a4 = s.dt * vzb * seg[4 * s.cells + cc];
+    float* acc = s.acc;
+    if (first) {
+      acc[3 * s.cells + cc] = a3;
+      acc[4 * s.cells + cc] = a4;
+    } else {
+      acc[3 * s.cells + cc] += a3;
+      acc[4 * s.cells + cc] += a4;
+    }
+  }
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(BX * BZ) void k_adj_str(const Shot2D s, int n, const float* seg, int first) {
+  const int j0 = blockIdx.x * BX, i0 = blockIdx.y * BZ;
+  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  const bool pml = block_in_pml(s, j0, i0, 2);
+  if (i < s.nz && j < s.nx) adj_str_cell<GRAD>(s, i, j, n, pml, seg, first != 0);
+}
+
+// ------------------------------------------------------------------------------------
+// Staging: (Vp, Vs, rho) of the window -> lambda + 2 mu, lambda, harmonic mu_xz, b_x, b_z.
+// ------------------------------------------------------------------------------------
+__global__ void k_stage(const Shot2D s) {
+  const int j = blockIdx.x * BX + threadIdx.x, i = blockIdx.y * BZ + threadIdx.y;
+  if (i >= s.nz || j >= s.nx) return;
+  const int ip = min(i + 1, s.nz - 1), jp = min(j + 1, s.nx - 1);
+  auto at = [&](const float* f, int a, int b) { return f[(long)a * s.mld + b]; };
+  const float vp = at(s.mvp, i, j), vs = at(s.mvs, i, j), rho = at(s.mrho, i, j);
+  auto mu_at = [&](int a, int b) {
+    const float v = at(s.mvs, a, b);
+    return at(s.mrho, a, b) * v * v;
+  };
+  const float mu = rho * vs * vs;
+  const float l2m = rho * vp * vp;
+  const long o = (long)i * s.ld + j;
+  s.l2m[o] = l2m;
+  s.lam[o] = l2m - 2.0f * mu;
+  const float m00 = mu, m10 = mu_at(ip, j), m01 = mu_at(i, jp), m11 = mu_at(ip, jp);
+  float mxz = 0.0f;
+  if (m00 > 0.0f && m10 > 0.0f && m01 > 0.0f && m11 > 0.0f)
+    mxz = 4.0f / (1.0f / m00 + 1.0f / m10 + 1.0f / m01 + 1.0f / m11);
+  s.muxz[o] = mxz;
+  s.bx[o] = 2.0f / (rho + at(s.mrho, i, jp));
+  s.bz[o] = 2.0f / (rho + at(s.mrho, ip, j));
+}
+
+// ------------------------------------------------------------------------------------
+// Chain rule of one segment's FP32 imaging sums into the FP64 (Vp, Vs, rho) gradient.
+// d mu_xz / d mu_k = mu_xz^2 / (4 mu_k^2) over its four clamped corners; d b / d rho = -b^2/2
+// on both (clamped) nodes of the average; lambda = rho(Vp^2 - 2Vs^2), mu = rho Vs^2.
+// ------------------------------------------------------------------------------------
+__global__ void k_chain_flush(const Shot2D s) {
+  const int j = blockIdx.x * BX + threadIdx.x, i = blockIdx.y * BZ + threadIdx.y;
+  if (i >= s.nz || j >= s.nx) return;
+  const long cc = (long)i * s.nx + j;
+  const long mo = (long)i * s.mld + j;
+  const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
+  const float mu = rho * vs * vs;
+  const float* glam = s.acc;
+  const float* gmu = s.acc + s.cells;
+  const float* gmuxz = s.acc + 2 * s.cells;
+  const float* gbx = s.acc + 3 * s.cells;
+  const float* gbz = s.acc + 4 * s.cells;
+  double gmu_tot = gmu[cc];
+  for (int di = -1; di <= 0; ++di) {
+    for (int dj = -1; dj <= 0; ++dj) {
+      const int a = i + di, b = j + dj;
+      if (a < 0 || b < 0) continue;
+      const int ap = min(a + 1, s.nz - 1), bp = min(b + 1, s.nx - 1);
+      const int mult = (a == i && b == j) + (ap == i && b == j) + (a == i && bp == j) + (ap == i && bp == j);
+      if (mult == 0) continue;
+      const float mxz = s.muxz[(long)a * s.ld + b];
+      if (mxz > 0.0f)
+        gmu_tot += (double)mult * gmuxz[(long)a * s.nx + b] * ((double)mxz * mxz / (4.0 * (double)mu * mu));
+    }
+  }
+  double grho_b = 0.0;
+  for (int db = -1; db <= 0; ++db) {      // vx nodes (i, b) average rho(i, b), rho(i, b+1)
+    const int b = j + db;
+    if (b < 0) continue;
+    const int bp = min(b + 1, s.nx - 1);
+    const int mult = (b == j) + (bp == j);
+    if (mult == 0) continue;
+    const double bxv = s.bx[(long)i * s.ld + b];
+    grho_b -= 0.5 * mult * gbx[(long)i * s.nx + b] * bxv * bxv;
+  }
+  for (int da = -1; da <= 0; ++da) {      // vz nodes (a, j) average rho(a, j), rho(a+1, j)
+    const int a = i + da;
+    if (a < 0) continue;
+    const int ap = min(a + 1, s.nz - 1);
+    const int mult = (a == i) + (ap == i);
+    if (mult == 0) continue;
+    const double bzv = s.bz[(long)a * s.ld + j];
+    grho_b -= 0.5 * mult * gbz[(long)a * s.nx + j] * bzv * bzv;
+  }
+  const double gl = glam[cc];
+  const double dvp = vp, dvs = vs, drho = rho;
+  s.G[cc] += 2.0 * drho * dvp * gl;
+  s.G[s.cells + cc] += 2.0 * drho * dvs * (gmu_tot - 2.0 * gl);
+  s.G[2 * s.cells + cc] += (dvp * dvp - 2.0 * dvs * dvs) * gl + dvs * dvs * gmu_tot + grho_b;
+}
+
+__global__ void k_write_gradient(const Shot2D s, float* g, long mplane, int z0, int x0) {
+  const int j = blockIdx.x * BX + threadIdx.x, i = blockIdx.y * BZ + threadIdx.y;
+  if (i >= s.nz || j >= s.nx) return;
+  const long cc = (long)i * s.nx + j;
+  const long go = (long)(z0 + i) * s.mld + (x0 + j);
+  for (int k = 0; k < 3; ++k) g[k * mplane + go] = (float)s.G[k * s.cells + cc];
+}
+
+// ------------------------------------------------------------------------------------
+// Misfit (FP64) and the reverse cumulative residual that drives the DAS transpose:
+// e_bar[n][c] = sum_{k >= n} r[c][k], r = d - d_obs. One thread per channel; the per-channel
+// FP64 partial sums are reduced in a fixed order by a single block.
+// ------------------------------------------------------------------------------------
+__global__ void k_residual(const float* d, const float* dobs, int nch, int nt, double* partial, float* ebar) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nch) return;
+  double acc = 0.0, sq = 0.0;
+  for (int n = nt - 1; n >= 0; --n) {
+    const long k = (long)c * nt + n;
+    const double r = dobs ? (double)d[k] - (double)dobs[k] : (double)d[k];
+    sq += r * r;
+    acc += r;
+    ebar[(long)n * nch + c] = (float)acc;
+  }
+  if (partial) partial[c] = sq;
+}
+
+__global__ void k_reduce_phi(const double* partial, int n, double* phi) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) a += partial[k];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *phi = 0.5 * sh[0];
+}
+
+inline dim3 grid2d(const Shot2D& s) { return dim3((s.nx + BX - 1) / BX, (s.nz + BZ - 1) / BZ); }
+inline dim3 block2d() { return dim3(BX, BZ); }
+
+}  // namespace
+
+hipError_t launch_stage2d(const Shot2D& s, hipStream_t st) {
+  k_stage<<<grid2d(s), block2d(), 0, st>>>(s);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_vel(const Shot2D& s, int n, float* seg, hipStream_t st) {
+  (void)n;
+  if (seg) k_fwd_vel<true><<<grid2d(s), block2d(), 0, st>>>(s, seg);
+  else k_fwd_vel<false><<<grid2d(s), block2d(), 0, st>>>(s, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_str(const Shot2D& s, int n, float* seg, bool record, hipStream_t st) {
+  if (seg) {
+    if (record) k_fwd_str<true, true><<<grid2d(s), block2d(), 0, st>>>(s, n, seg);
+    else k_fwd_str<true, false><<<grid2d(s), block2d(), 0, st>>>(s, n, seg);
+  } else {
+    if (record) k_fwd_str<false, true><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr);
+    else k_fwd_str<false, false><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_vel(const Shot2D& s, int n, const float* seg, bool grad, bool first, bool srcadj,
+                          hipStream_t st) {
+  if (grad) k_adj_vel<true, false><<<grid2d(s), block2d(), 0, st>>>(s, n, seg, first);
+  else if (srcadj) k_adj_vel<false, true><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr, 0);
+  else k_adj_vel<false, false><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_str(const Shot2D& s, int n, const float* seg, bool grad, bool first, hipStream_t st) {
+  if (grad) k_adj_str<true><<<grid2d(s), block2d(), 0, st>>>(s, n, seg, first);
+  else k_adj_str<false><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_flush(const Shot2D& s, hipStream_t st) {
+  k_chain_flush<<<grid2d(s), block2d(), 0, st>>>(s);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_gradient(const Shot2D& s, float* g, long mplane, int z0, int x0, hipStream_t st) {
+  k_write_gradient<<<grid2d(s), block2d(), 0, st>>>(s, g, mplane, z0, x0);
+  return hipGetLastError();
+}
+
+hipError_t launch_misfit(const Shot2D& s, const float* d, const float* dobs, double* partial, double* phi,
+                         float* ebar, hipStream_t st) {
+  if (s.nch > 0) {
+    k_residual<<<(s.nch + 127) / 128, 128, 0, st>>>(d, dobs, s.nch, s.nt, partial, ebar);
+    k_reduce_phi<<<1, 256, 0, st>>>(partial, s.nch, phi);
+  } else {
+    k_reduce_phi<<<1, 256, 0, st>>>(partial, 0, phi);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_cumsum(const Shot2D& s, const float* r, float* ebar, hipStream_t st) {
+  if (s.nch > 0) k_residual<<<(s.nch + 127) / 128, 128, 0, st>>>(r, nullptr, s.nch, s.nt, nullptr, ebar);
+  return hipGetLastError();
+}
+
+}  // namespace efwi

@@ -1,0 +1,272 @@
+"""Python binding of the gfx950 HIP library ``libefwi.so`` (C ABI in ``include/efwi.h``).
+
+Argument marshalling only: every step of the hot path runs in the library's HIP kernels.
+Tensors are PyTorch device tensors (torch supplies device memory and the current HIP
+stream); channel coordinates are host arrays. Importing this module fails loudly when the
+library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libefwi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2305_14130_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes (efwi_status)
+OK, E_INVAL, E_RANGE, E_CFL, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+CKPT_FP32, CKPT_BF16, CKPT_FP16 = 0, 1, 2
+WS_FORWARD, WS_ADJOINT, WS_GRADIENT, WS_BATCH, WS_REGULARIZER = 0, 1, 2, 3, 4
+
+EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_model_adjoint",
+            "efwi_shot_gradient", "efwi_batch_gradient", "efwi_extension_regularizer",
+            "efwi_status_string", "efwi_last_error", "efwi_version", "efwi_timing_enable",
+            "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name"]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("nz", ctypes.c_int), ("ny", ctypes.c_int), ("nx", ctypes.c_int),
+                ("dz", ctypes.c_float), ("dy", ctypes.c_float), ("dx", ctypes.c_float), ("dt", ctypes.c_float),
+                ("nt", ctypes.c_int), ("npml", ctypes.c_int), ("pml_R", ctypes.c_float),
+                ("pml_f0", ctypes.c_float), ("vp_max", ctypes.c_float)]
+
+
+class _ShotC(ctypes.Structure):
+    _fields_ = [("src_iz", ctypes.c_int), ("src_iy", ctypes.c_int), ("src_ix", ctypes.c_int),
+                ("nch", ctypes.c_int), ("ch_iz", ctypes.POINTER(ctypes.c_int)),
+                ("ch_iy", ctypes.POINTER(ctypes.c_int)), ("ch_ix", ctypes.POINTER(ctypes.c_int)),
+                ("z0", ctypes.c_int), ("y0", ctypes.c_int), ("x0", ctypes.c_int),
+                ("wz", ctypes.c_int), ("wy", ctypes.c_int), ("wx", ctypes.c_int),
+                ("ckpt_interval", ctypes.c_int), ("ckpt_mode", ctypes.c_int)]
+
+
+@dataclass
+class Shot:
+    """One shot: source node, DAS channel nodes (full-model coordinates), window, checkpointing."""
+    src_iz: int
+    src_ix: int
+    ch_iz: np.ndarray
+    ch_ix: np.ndarray
+    z0: int = 0
+    x0: int = 0
+    wz: int = 0
+    wx: int = 0
+    ckpt_interval: int = 0
+    ckpt_mode: int = CKPT_FP32
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def nch(self) -> int:
+        return int(len(self.ch_iz))
+
+    def c_struct(self) -> _ShotC:
+        iz = np.ascontiguousarray(self.ch_iz, dtype=np.int32)
+        ix = np.ascontiguousarray(self.ch_ix, dtype=np.int32)
+        self._keep[:] = [iz, ix]
+        ip = ctypes.POINTER(ctypes.c_int)
+        return _ShotC(self.src_iz, 0, self.src_ix, len(iz), iz.ctypes.data_as(ip), None, ix.ctypes.data_as(ip),
+                      self.z0, 0, self.x0, self.wz, 0, self.wx, self.ckpt_interval, self.ckpt_mode)
+
+
+def make_grid(nz, nx, dz, dx, dt, nt, npml=0, pml_R=1e-3, pml_f0=10.0, vp_max=0.0) -> Grid:
+    return Grid(2, int(nz), 1, int(nx), float(dz), 1.0, float(dx), float(dt), int(nt), int(npml),
+                float(pml_R), float(pml_f0), float(vp_max))
+
+
+_vp = ctypes.c_void_p
+_lib.efwi_workspace_size.restype = ctypes.c_size_t
+_lib.efwi_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC)]
+_lib.efwi_validate.restype = ctypes.c_int
+_lib.efwi_validate.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC)]
+_lib.efwi_model_forward.restype = ctypes.c_int
+_lib.efwi_model_forward.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp]
+_lib.efwi_model_adjoint.restype = ctypes.c_int
+_lib.efwi_model_adjoint.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp]
+_lib.efwi_shot_gradient.restype = ctypes.c_int
+_lib.efwi_shot_gradient.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _vp, ctypes.c_size_t, _vp]
+_lib.efwi_batch_gradient.restype = ctypes.c_int
+_lib.efwi_batch_gradient.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), _vp, _vp, _vp,
+                                     _vp, _vp, _vp, ctypes.c_size_t, _vp]
+_lib.efwi_extension_regularizer.restype = ctypes.c_int
+_lib.efwi_extension_regularizer.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, _vp, _vp, _vp, ctypes.c_float, _vp,
+                                            _vp, _vp, ctypes.c_size_t, _vp]
+_lib.efwi_status_string.restype = ctypes.c_char_p
+_lib.efwi_status_string.argtypes = [ctypes.c_int]
+_lib.efwi_last_error.restype = ctypes.c_char_p
+_lib.efwi_last_error.argtypes = []
+_lib.efwi_version.restype = ctypes.c_char_p
+_lib.efwi_version.argtypes = []
+_lib.efwi_timing_enable.restype = ctypes.c_int
+_lib.efwi_timing_enable.argtypes = [ctypes.c_int]
+_lib.efwi_timing_reset.restype = ctypes.c_int
+_lib.efwi_timing_reset.argtypes = []
+_lib.efwi_timing_query.restype = ctypes.c_int
+_lib.efwi_timing_query.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long),
+                                   ctypes.POINTER(ctypes.c_double)]
+_lib.efwi_kernel_count.restype = ctypes.c_int
+_lib.efwi_kernel_count.argtypes = []
+_lib.efwi_kernel_name.restype = ctypes.c_char_p
+_lib.efwi_kernel_name.argtypes = [ctypes.c_int]
+
+
+class EfwiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_lib.efwi_status_string(status).decode()}: {message}")
+        self.status = status
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise EfwiError(rc, _lib.efwi_last_error().decode())
+
+
+def version() -> str:
+    return _lib.efwi_version().decode()
+
+
+def timing_enable(sample_every: int) -> None:
+    """Bracket every k-th launch of each kernel kind with HIP events (0 = off)."""
+    _check(_lib.efwi_timing_enable(int(sample_every)))
+
+
+def timing_reset() -> None:
+    _check(_lib.efwi_timing_reset())
+
+
+def timing_query() -> dict:
+    """{kernel name: (launches, timed launches, mean ms per timed launch)}."""
+    out = {}
+    for k in range(_lib.efwi_kernel_count()):
+        la, ti, ms = ctypes.c_long(), ctypes.c_long(), ctypes.c_double()
+        _check(_lib.efwi_timing_query(k, ctypes.byref(la), ctypes.byref(ti), ctypes.byref(ms)))
+        name = _lib.efwi_kernel_name(k).decode()
+        out[name] = (la.value, ti.value, ms.value / ti.value if ti.value else 0.0)
+    return out
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _f32(t, name):
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 device tensor")
+    return t
+
+
+def validate(grid: Grid, shots) -> None:
+    arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
+    _check(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr))
+
+
+def workspace_size(kind: int, grid: Grid, shots) -> int:
+    shots = list(shots)
+    arr = (_ShotC * max(1, len(shots)))(*[s.c_struct() for s in shots])
+    n = _lib.efwi_workspace_size(kind, ctypes.byref(grid), len(shots), arr)
+    if n == 0 and kind != WS_REGULARIZER:
+        raise EfwiError(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr), _lib.efwi_last_error().decode())
+    return int(n)
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    return torch.empty(max(256, nbytes), dtype=torch.uint8, device=device or "cuda")
+
+
+def model_forward(grid: Grid, shot: Shot, m, src, d=None, ws=None, stream=None):
+    """d = K u(m): DAS e_xx data [nch][nt] of one shot."""
+    _f32(m, "m"), _f32(src, "src")
+    if d is None:
+        d = torch.empty((shot.nch, grid.nt), dtype=torch.float32, device=m.device)
+    sc = shot.c_struct()
+    need = _lib.efwi_workspace_size(WS_FORWARD, ctypes.byref(grid), 1, ctypes.byref(sc))
+    ws = ws if ws is not None else workspace(need, m.device)
+    _check(_lib.efwi_model_forward(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(d), _ptr(ws),
+                                   ws.numel(), _stream(stream)))
+    return d
+
+
+def model_adjoint(grid: Grid, shot: Shot, m, r, src_bar=None, ws=None, stream=None):
+    """L^T r with respect to the [3][nt] source components."""
+    _f32(m, "m"), _f32(r, "r")
+    if src_bar is None:
+        src_bar = torch.empty((3, grid.nt), dtype=torch.float32, device=m.device)
+    sc = shot.c_struct()
+    need = _lib.efwi_workspace_size(WS_ADJOINT, ctypes.byref(grid), 1, ctypes.byref(sc))
+    ws = ws if ws is not None else workspace(need, m.device)
+    _check(_lib.efwi_model_adjoint(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(r), _ptr(src_bar),
+                                   _ptr(ws), ws.numel(), _stream(stream)))
+    return src_bar
+
+
+def shot_gradient(grid: Grid, shot: Shot, m, src, d_obs, g=None, phi=None, d_out=None, ws=None, stream=None):
+    """Misfit phi_s (device double) and gradient g_s [3][nz][nx] w.r.t. (Vp, Vs, rho)."""
+    _f32(m, "m"), _f32(src, "src"), _f32(d_obs, "d_obs")
+    if g is None:
+        g = torch.empty_like(m)
+    if phi is None:
+        phi = torch.empty((), dtype=torch.float64, device=m.device)
+    sc = shot.c_struct()
+    need = _lib.efwi_workspace_size(WS_GRADIENT, ctypes.byref(grid), 1, ctypes.byref(sc))
+    ws = ws if ws is not None else workspace(need, m.device)
+    _check(_lib.efwi_shot_gradient(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(d_obs), _ptr(g),
+                                   _ptr(phi), _ptr(d_out), _ptr(ws), ws.numel(), _stream(stream)))
+    return g, phi
+
+
+def batch_gradient(grid: Grid, shots, m_ext, src, d_obs, g_ext=None, phi=None, ws=None, stream=None):
+    """Data term of the extended misfit for all shots: g_ext[s] = J_s^T r_s on m_ext[s]."""
+    shots = list(shots)
+    _f32(m_ext, "m_ext"), _f32(src, "src"), _f32(d_obs, "d_obs")
+    if g_ext is None:
+        g_ext = torch.empty_like(m_ext)
+    if phi is None:
+        phi = torch.empty((len(shots),), dtype=torch.float64, device=m_ext.device)
+    arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
+    need = _lib.efwi_workspace_size(WS_BATCH, ctypes.byref(grid), len(shots), arr)
+    if need == 0:
+        _check(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr))
+    ws = ws if ws is not None else workspace(need, m_ext.device)
+    _check(_lib.efwi_batch_gradient(ctypes.byref(grid), len(shots), arr, _ptr(m_ext), _ptr(src), _ptr(d_obs),
+                                    _ptr(g_ext), _ptr(phi), _ptr(ws), ws.numel(), _stream(stream)))
+    return g_ext, phi
+
+
+def extension_regularizer(grid: Grid, m_ext, b, sink, eta, g_ext, phi=None, ws=None, stream=None):
+    """phi_reg (device double) and g_ext += gradient of 1/2 eta^2 ||(I - S^T S_w) W m~||^2."""
+    _f32(m_ext, "m_ext"), _f32(b, "b"), _f32(g_ext, "g_ext")
+    if sink.dtype != torch.uint8:
+        raise TypeError("sink must be uint8")
+    ns = m_ext.shape[0]
+    if phi is None:
+        phi = torch.empty((), dtype=torch.float64, device=m_ext.device)
+    need = _lib.efwi_workspace_size(WS_REGULARIZER, ctypes.byref(grid), 0, None)
+    ws = ws if ws is not None else workspace(need, m_ext.device)
+    _check(_lib.efwi_extension_regularizer(ctypes.byref(grid), ns, _ptr(m_ext), _ptr(b), _ptr(sink),
+                                           float(eta), _ptr(g_ext), _ptr(phi), _ptr(ws), ws.numel(),
+                                           _stream(stream)))
+    return phi
+
+
+def source_components(M, stf) -> np.ndarray:
+    """[3][nt] source components (M_xx, M_zz, M_xz) x moment-rate samples."""
+    return np.outer(np.asarray(M, np.float64)[:3], np.asarray(stf, np.float64)).astype(np.float32)

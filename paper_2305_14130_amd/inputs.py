@@ -77,7 +77,7 @@ def gaussian_blob(shape, cz, cx, sigma, amp):
 # ---------------------------------------------------------------------------------------
 # Parity workload: 100 x 200, dx = 5 m, three layers with a 20 m low-velocity layer.
 # ---------------------------------------------------------------------------------------
-def parity_2d(nt=1000, M0=1.0e16):
+def parity_2d(nt=1000, M0=1.0e16, blob_amp=0.03):
     nz, nx, h = 100, 200, 5.0
     vp = np.full((nz, nx), 3600.0)
     rho = np.full((nz, nx), 2450.0)
@@ -87,7 +87,7 @@ def parity_2d(nt=1000, M0=1.0e16):
     rho[52:] = 2600.0
     vs = vp / 1.7
     m_start = np.stack([vp, vs, rho])
-    blob = gaussian_blob((nz, nx), 50, 110, 4.0, 0.03)
+    blob = gaussian_blob((nz, nx), 50, 110, 4.0, blob_amp)
     m_true = m_start.copy()
     m_true[0] *= 1.0 + blob
     m_true[1] *= 1.0 + blob

@@ -1,0 +1,79 @@
+"""C ABI checks that need no GPU: the library loads, exports every function that
+include/efwi.h declares, and validates arguments on the host before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "efwi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(efwi_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def efwi():
+    from paper_2305_14130_amd import efwi as mod
+    return mod
+
+
+def test_every_declared_symbol_is_exported(efwi):
+    names = _declared()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(efwi.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(efwi.EXPORTED)
+
+
+def test_version_and_status_strings(efwi):
+    assert efwi.version().startswith("efwi-gfx950")
+    assert efwi._lib.efwi_status_string(efwi.E_CFL) == b"EFWI_E_CFL"
+
+
+def _ok_case(efwi):
+    grid = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+    shot = efwi.Shot(50, 40, np.full(3, 50, np.int32), np.array([60, 63, 66], np.int32))
+    return grid, shot
+
+
+def test_validation_accepts_good_arguments(efwi):
+    grid, shot = _ok_case(efwi)
+    efwi.validate(grid, [shot])
+    assert efwi.workspace_size(efwi.WS_GRADIENT, grid, [shot]) > 0
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda g, s: setattr(g, "dt", 1.0e-3), "E_CFL"),
+    (lambda g, s: setattr(g, "nt", 0), "E_INVAL"),
+    (lambda g, s: setattr(g, "dx", 0.0), "E_INVAL"),
+    (lambda g, s: setattr(g, "ndim", 3), "E_UNSUPPORTED"),
+    (lambda g, s: setattr(s, "src_ix", 10), "E_RANGE"),            # inside the CPML strip
+    (lambda g, s: setattr(s, "src_iz", 99), "E_RANGE"),
+    (lambda g, s: setattr(s, "ch_ix", np.array([60, 63, 195], np.int32)), "E_RANGE"),
+    (lambda g, s: setattr(s, "ch_ix", np.array([60, 63, 63], np.int32)), "E_INVAL"),   # duplicate node
+    (lambda g, s: setattr(s, "wx", 230), "E_RANGE"),                # window beyond the model
+    (lambda g, s: setattr(s, "ckpt_mode", 7), "E_INVAL"),
+    (lambda g, s: setattr(s, "ckpt_interval", -1), "E_INVAL"),
+])
+def test_validation_errors(efwi, mutate, status):
+    grid, shot = _ok_case(efwi)
+    mutate(grid, shot)
+    with pytest.raises(efwi.EfwiError) as ei:
+        efwi.validate(grid, [shot])
+    assert ei.value.status == getattr(efwi, status)
+    assert efwi._lib.efwi_last_error()
+
+
+def test_workspace_size_grows_with_checkpoint_interval(efwi):
+    grid, shot = _ok_case(efwi)
+    small = efwi.workspace_size(efwi.WS_GRADIENT, grid, [shot])
+    shot.ckpt_interval = 10**6
+    full = efwi.workspace_size(efwi.WS_GRADIENT, grid, [shot])
+    assert full > small
+    assert efwi.workspace_size(efwi.WS_FORWARD, grid, [shot]) < small
