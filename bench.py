@@ -36,11 +36,12 @@ HBM_PEAK_GBS = 8000.0
 #                + store qx qz of the step for the imaging condition           +8 B
 #   fwd_str      read vx vz sxx szz sxz l2m lam muxz, write sxx szz sxz         44 B
 #                + store pxx pzz (pzx+pxz)                                      +12 B
-#   adj_vel      read sxxb szzb sxzb vxb vzb l2m lam muxz, write vxb vzb,
-#                read pxx pzz ps, read+write 3 imaging sums                    76 B
-#   adj_str      read vxb vzb sxxb szzb sxzb bx bz, write sxxb szzb sxzb,
-#                read qx qz, read+write 2 imaging sums                         64 B
-KERNEL_BYTES = {"fwd_vel": (36, 44), "fwd_str": (44, 56), "adj_vel": (76, 76), "adj_str": (64, 64)}
+#   adj_vel      read t_bar (3), u_bar (2), bx bz, write u_bar (2),
+#                read 3 stored quantities, read+write 3 imaging sums            72 B
+#   adj_str      read u_bar (2), t_bar (3), l2m lam muxz, write t_bar (3),
+#                read 2 stored quantities, read+write 2 imaging sums            68 B
+# (u_bar = b v_bar and t_bar = C sigma_bar are the scaled adjoint variables.)
+KERNEL_BYTES = {"fwd_vel": (36, 44), "fwd_str": (44, 56), "adj_vel": (72, 72), "adj_str": (68, 68)}
 # Whole-path algorithmic bytes per cell-step (fwd + adj + grad, sqrt(nt) recomputation):
 # forward 52 + stored velocities 8 + adjoint 52 + imaging reads 16 + accumulators 24 + recompute 52.
 PATH_BYTES_PER_CELL_STEP = 204
@@ -83,6 +84,8 @@ def main():
     ap.add_argument("--nt", type=int, default=4000, help="time steps (profiling runs use fewer)")
     ap.add_argument("--sample-every", type=int, default=16, help="time every k-th launch of each kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -94,6 +97,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy_mb > 0:
+        x = torch.ones(args.calibrate_copy_mb * (1 << 18), dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     w = inputs.plain_2d(nshots=args.shots, nt=args.nt)
     ns, nz, nx, nt = len(w.shots), w.nz, w.nx, w.nt
     grid = efwi.make_grid(nz, nx, w.dz, w.dx, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)

@@ -264,7 +264,7 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
 // ----------------------------------------------------------------------------------------
 struct Plan2D {
   Window w;
-  int nz, nx, ld, rows, P, nslots, nt, nch, L, nseg;
+  int nz, nx, ld, cp, rows, P, nslots, nt, nch, L, nseg;
   long plane, cells;
   size_t state_bytes;  // padded fields + forward CPML strips (one checkpoint)
   size_t off_state, off_e, off_adj, off_par, off_tab, tab_bytes, off_ebar, off_partial, off_dint, off_acc, off_G,
@@ -287,10 +287,11 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.w = window_of(g, s);
   p.nz = p.w.wz;
   p.nx = p.w.wx;
-  p.ld = (p.nx + 2 * HALO + 3) / 4 * 4;
+  p.ld = (XOFF + p.nx + HALO + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
+  p.cp = (p.nx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
   p.rows = p.nz + 2 * HALO;
   p.plane = (long)p.rows * p.ld;
-  p.cells = (long)p.nz * p.nx;
+  p.cells = (long)p.nz * p.cp;
   p.P = strip_width(g);
   p.nt = g.nt;
   p.nch = s.nch;
@@ -396,8 +397,9 @@ Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsign
   d.rdx = (float)(1.0 / g.dx);
   d.rdz = (float)(1.0 / g.dz);
   d.w = (float)((double)g.dt / ((double)g.dx * g.dz));
+  d.cp = p.cp;
   d.cells = p.cells;
-  const long interior = (long)HALO * p.ld + HALO;
+  const long interior = (long)HALO * p.ld + XOFF;
   const size_t strips = strips_floats(p.nz, p.nx, p.P);
   auto fields = [&](size_t off, float** out, int count) {
     float* base = reinterpret_cast<float*>(ws + off);
@@ -422,11 +424,11 @@ Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsign
   {
     float* f[5];
     float* st = fields(p.off_adj, f, 5);
-    d.vxb = f[0];
-    d.vzb = f[1];
-    d.sxxb = f[2];
-    d.szzb = f[3];
-    d.sxzb = f[4];
+    d.uxb = f[0];
+    d.uzb = f[1];
+    d.txxb = f[2];
+    d.tzzb = f[3];
+    d.txzb = f[4];
     strips_at(st, d.pbx[0], d.pbz[0]);
     strips_at(st + strips, d.pbx[1], d.pbz[1]);
   }

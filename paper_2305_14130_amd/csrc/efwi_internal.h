@@ -11,14 +11,23 @@ namespace efwi {
 // Padded field layout: every wavefield and staged-parameter array has HALO zero cells on
 // each side in z and x so that the 4th-order stencils never branch on the grid edge.
 constexpr int HALO = 2;
+// The interior of every padded row starts XOFF floats into the row and the row pitch is a
+// multiple of 32 floats, so each wavefront's 64 consecutive x values fill whole 128-byte
+// lines. Unpadded per-cell arrays (segment buffer, imaging sums, gradient) use a row pitch
+// `cp` rounded up to 32 for the same reason.
+constexpr int XOFF = 32;
+constexpr int ROW_ALIGN = 32;
 // Thread-block shape of the 2D stencil kernels: 64 lanes along x (one wavefront per row)
 // by 4 rows along z.
 constexpr int BX = 64;
 constexpr int BZ = 4;
-// Number of per-step forward quantities kept for the imaging condition:
-// pxx, pzz (normal node), pzx + pxz (shear node), qx (vx node), qz (vz node).
+// Number of per-step forward quantities kept for the imaging condition (see k_fwd_str and
+// k_fwd_vel): (pxx+pzz)/(2(l+m)), (pxx-pzz)/(2m) at the normal node, (pzx+pxz)/mu_xz at the
+// shear node, qx/b_x and qz/b_z at the velocity nodes (p, q: CPML-corrected strain rates
+// and stress divergences of the step).
 constexpr int NSEG_FIELDS = 5;
-// Number of imaging accumulators: lambda, mu (normal), mu_xz (shear), b_x, b_z.
+// Number of imaging accumulators: lambda, mu - lambda (normal node), mu_xz (shear node),
+// b_x, b_z (velocity nodes).
 constexpr int NACC = 5;
 // Time steps summed in FP32 before the imaging sums are chained into the FP64 gradient.
 constexpr int FLUSH_STEPS = 32;
@@ -30,13 +39,16 @@ struct Shot2D {
   int nt, nch;
   int si, sj;                   // source normal node, window coordinates
   float dt, rdx, rdz, w;        // w = dt / (dx dz)
-  long cells;                   // nz * nx
+  int cp;                       // row pitch of the unpadded per-cell arrays
+  long cells;                   // nz * cp
   // forward state
   float *vx, *vz, *sxx, *szz, *sxz;
   float* psx[4];                // x-strip memory variables [nz][2P]: VXX, VZX, XX, XZ
   float* psz[4];                // z-strip memory variables [2P][nx]: VXZ, VZZ, ZZ, XZ
-  // adjoint state
-  float *vxb, *vzb, *sxxb, *szzb, *sxzb;
+  // adjoint state in scaled variables: u_bar = b v_bar at the velocity nodes and
+  // t_bar = C sigma_bar at the stress nodes (t_xx = (l+2m) s_xx + l s_zz, t_zz = l s_xx +
+  // (l+2m) s_zz, t_xz = mu_xz s_xz), an invertible change of variables for Vs > 0
+  float *uxb, *uzb, *txxb, *tzzb, *txzb;
   float* pbx[2][4];             // double-buffered x-strip adjoint memory variables
   float* pbz[2][4];             // double-buffered z-strip adjoint memory variables
   // staged parameters (padded, zero halo)

@@ -47,6 +47,23 @@ __device__ __forceinline__ float dminus(const float* f, long o, long st, float r
   return (K1 * (f[o] - f[o - st]) + K2 * (f[o + st] - f[o - 2 * st])) * r;
 }
 
+// XCD-aware tile order. The hardware deals workgroup w to XCD (w mod 8), so workgroup w
+// takes tile (w mod 8) * chunk + w / 8: each XCD walks one contiguous run of tiles (whole
+// row bands, x fastest) and the z-halo rows its stencils re-read are still in its own L2.
+// Returns false for the padding workgroups of the last chunk.
+constexpr int NXCD = 8;
+__device__ __forceinline__ bool tile_of(int nz, int nx, int& i0, int& j0) {
+  const int ntx = (nx + BX - 1) / BX, ntz = (nz + BZ - 1) / BZ;
+  const int ntiles = ntx * ntz;
+  const int chunk = (ntiles + NXCD - 1) / NXCD;
+  const int w = blockIdx.x;
+  const int t = (w % NXCD) * chunk + w / NXCD;
+  if (t >= ntiles) return false;
+  i0 = (t / ntx) * BZ;
+  j0 = (t % ntx) * BX;
+  return true;
+}
+
 // Does the block touch a CPML strip (with `pad` extra cells of neighbourhood)?
 __device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, int pad) {
   if (s.P <= 0) return false;
@@ -57,15 +74,15 @@ __device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, in
 // ------------------------------------------------------------------------------------
 // Forward velocity half step: v^{n+1/2} = v^{n-1/2} + dt b (div sigma^n), CPML in strips.
 // ------------------------------------------------------------------------------------
-template <bool STORE>
-__device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, bool pml, float* seg) {
+template <bool STORE, bool PML>
+__device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, float* seg) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   float d1 = dplus(s.sxx, o, 1, s.rdx);    // D+x sxx at (i, j+1/2)
   float d2 = dminus(s.sxz, o, ld, s.rdz);  // D-z sxz at (i, j+1/2)
   float d3 = dminus(s.sxz, o, 1, s.rdx);   // D-x sxz at (i+1/2, j)
   float d4 = dplus(s.szz, o, ld, s.rdz);   // D+z szz at (i+1/2, j)
-  if (pml) {
+  if (PML) {
     const int sx = strip_index(j, s.nx, s.P);
     const int sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
@@ -90,27 +107,29 @@ __device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, bool
   const float qx = d1 + d2, qz = d3 + d4;
   s.vx[o] += s.dt * s.bx[o] * qx;
   s.vz[o] += s.dt * s.bz[o] * qz;
-  if (STORE) {
-    const long c = (long)i * s.nx + j;
-    seg[3 * s.cells + c] = qx;
-    seg[4 * s.cells + c] = qz;
+  if (STORE) {  // divergences pre-divided by the buoyancy for the b_x, b_z imaging terms
+    const long c = (long)i * s.cp + j;
+    seg[3 * s.cells + c] = qx / s.bx[o];
+    seg[4 * s.cells + c] = qz / s.bz[o];
   }
 }
 
 template <bool STORE>
 __global__ __launch_bounds__(BX * BZ) void k_fwd_vel(const Shot2D s, float* seg) {
-  const int j0 = blockIdx.x * BX, i0 = blockIdx.y * BZ;
+  int i0, j0;
+  if (!tile_of(s.nz, s.nx, i0, j0)) return;
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
-  const bool pml = block_in_pml(s, j0, i0, 0);
-  if (i < s.nz && j < s.nx) fwd_vel_cell<STORE>(s, i, j, pml, seg);
+  if (i >= s.nz || j >= s.nx) return;
+  if (block_in_pml(s, j0, i0, 0)) fwd_vel_cell<STORE, true>(s, i, j, seg);
+  else fwd_vel_cell<STORE, false>(s, i, j, seg);
 }
 
 // ------------------------------------------------------------------------------------
 // Forward stress half step: sigma^{n+1} = sigma^n + dt C (strain rate of v^{n+1/2}),
 // moment-tensor injection at t_{n+1/2}, DAS strain record.
 // ------------------------------------------------------------------------------------
-template <bool STORE, bool RECORD>
-__device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int n, bool pml, float* seg) {
+template <bool STORE, bool RECORD, bool PML>
+__device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int n, float* seg) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   float pxx = dminus(s.vx, o, 1, s.rdx);   // D-x vx at (i, j)
@@ -118,7 +137,7 @@ __device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int 
   float pzx = dplus(s.vx, o, ld, s.rdz);   // D+z vx at (i+1/2, j+1/2)
   float pxz = dplus(s.vz, o, 1, s.rdx);    // D+x vz at (i+1/2, j+1/2)
   const float raw_pxx = pxx;
-  if (pml) {
+  if (PML) {
     const int sx = strip_index(j, s.nx, s.P);
     const int sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
@@ -164,76 +183,109 @@ __device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int 
       }
     }
   }
-  if (STORE) {
-    const long c = (long)i * s.nx + j;
-    seg[c] = pxx;
-    seg[s.cells + c] = pzz;
-    seg[2 * s.cells + c] = ps;
+  if (STORE) {  // strain rates pre-divided by the moduli for the lambda, mu, mu_xz imaging terms
+    const long c = (long)i * s.cp + j;
+    const float mxz = s.muxz[o];
+    seg[c] = (pxx + pzz) / (l2m + lam);
+    seg[s.cells + c] = (pxx - pzz) / (l2m - lam);
+    seg[2 * s.cells + c] = mxz > 0.0f ? ps / mxz : 0.0f;
   }
 }
 
 template <bool STORE, bool RECORD>
 __global__ __launch_bounds__(BX * BZ) void k_fwd_str(const Shot2D s, int n, float* seg) {
-  const int j0 = blockIdx.x * BX, i0 = blockIdx.y * BZ;
+  int i0, j0;
+  if (!tile_of(s.nz, s.nx, i0, j0)) return;
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
-  const bool pml = block_in_pml(s, j0, i0, 0);
-  if (i < s.nz && j < s.nx) fwd_str_cell<STORE, RECORD>(s, i, j, n, pml, seg);
+  if (i >= s.nz || j >= s.nx) return;
+  if (block_in_pml(s, j0, i0, 0)) fwd_str_cell<STORE, RECORD, true>(s, i, j, n, seg);
+  else fwd_str_cell<STORE, RECORD, false>(s, i, j, n, seg);
 }
 
 // ------------------------------------------------------------------------------------
-// Transposed stress sub-step (run first at reverse step n): with sigma_bar the adjoint of
-// sigma^{n+1}, p_bar = dt C sigma_bar (+ CPML transpose), v_bar += D^T p_bar; DAS transpose
-// injects dt * e_bar through (D-x)^T at the vx nodes around each channel; imaging terms for
-// lambda, mu, mu_xz; optional transpose of the source injection.
+// Adjoint (exact transpose) in scaled variables.
+//
+// With sigma_bar the adjoint of sigma^{n+1} and v_bar the adjoint of v^{n+1/2}, the
+// transposed sub-steps of step n are (reverse order of the forward):
+//   DAS:      v_bar_x += dt (D-x)^T e_bar at the channels, e_bar = sum_{k>=n} r[:, k]
+//   stress:   p_bar = dt C sigma_bar (+ CPML transpose), v_bar += D^T p_bar
+//   velocity: q_bar = dt b v_bar (+ CPML transpose),     sigma_bar += D^T q_bar
+// Carrying u_bar = b v_bar and t_bar = C sigma_bar instead, p_bar~ = dt t_bar and
+// q_bar~ = dt u_bar are read straight from the neighbours (no material parameters there),
+// and the parameters act only on the owned node: u_bar += b D^T p_bar,
+// t_bar += C D^T q_bar. D^T uses D-^T = -D+ and D+^T = -D- (zero outside the grid).
+// CPML transpose of psi <- b psi + a D, D~ = D + psi: psi_bar += y_bar; x_bar = y_bar +
+// a psi_bar; psi_bar <- b psi_bar (double-buffered: neighbours read the old value).
+// Imaging (gradients of <d, r> w.r.t. the staged parameters) with the forward quantities
+// stored pre-divided by the parameters:
+//   g_lambda += dt (t_xx + t_zz) (pxx + pzz)/(2(l+m))          = dt sum(sigma_bar) (pxx+pzz)
+//   g_mu - g_lambda += dt (t_xx - t_zz) (pxx - pzz)/(2m)
+//   g_mu_xz += dt t_xz (pzx + pxz)/mu_xz                        = dt sigma_bar_xz (pzx+pxz)
+//   g_b_x += dt u_x qx / b_x                                    = dt v_bar_x qx   (same z)
 // ------------------------------------------------------------------------------------
-struct PbarCtx {
+template <bool PML>
+struct AdjCtx {
   const Shot2D& s;
-  bool pml;
-  const float* const* px;   // x-strip adjoint memory variables, current
-  const float* const* pz;   // z-strip, current
+  const float* const* px;   // x-strip adjoint memory variables, previous (read) buffer
+  const float* const* pz;   // z-strip, previous buffer
 };
 
-// Corrected p_bar for pxx at normal node (ii, jj): dt((l+2m) sxx_b + l szz_b) + CPML(XX, x int)
-__device__ __forceinline__ float pbar_xx(const PbarCtx& c, int ii, int jj) {
+// Corrected transposed operands at node (ii, jj); `a` is the profile coefficient for the
+// node's coordinate along the derivative's axis and `psi` the matching adjoint memory
+// variable, used only inside the CPML strips.
+template <bool PML>
+__device__ __forceinline__ float corr_x(const AdjCtx<PML>& c, float v, int ii, int jj, const float* aprof, int slot) {
   const Shot2D& s = c.s;
-  const long oo = (long)ii * s.ld + jj;
-  float v = s.dt * (s.l2m[oo] * s.sxxb[oo] + s.lam[oo] * s.szzb[oo]);
-  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+  if (PML && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
     const int sx = strip_index(jj, s.nx, s.P);
-    if (sx >= 0) v += axi(s)[jj] * (c.px[X_XX][(long)ii * 2 * s.P + sx] + v);
+    if (sx >= 0) v += aprof[jj] * (c.px[slot][(long)ii * 2 * s.P + sx] + v);
   }
   return v;
 }
-__device__ __forceinline__ float pbar_zz(const PbarCtx& c, int ii, int jj) {
+template <bool PML>
+__device__ __forceinline__ float corr_z(const AdjCtx<PML>& c, float v, int ii, int jj, const float* aprof, int slot) {
   const Shot2D& s = c.s;
-  const long oo = (long)ii * s.ld + jj;
-  float v = s.dt * (s.lam[oo] * s.sxxb[oo] + s.l2m[oo] * s.szzb[oo]);
-  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+  if (PML && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
     const int sz = strip_index(ii, s.nz, s.P);
-    if (sz >= 0) v += azi(s)[ii] * (c.pz[Z_ZZ][(long)sz * s.nx + jj] + v);
+    if (sz >= 0) v += aprof[ii] * (c.pz[slot][(long)sz * s.nx + jj] + v);
   }
   return v;
 }
-// shear node: pzx uses the z-half profile (Z_XZ), pxz the x-half profile (X_XZ)
-__device__ __forceinline__ float pbar_zx(const PbarCtx& c, int ii, int jj) {
-  const Shot2D& s = c.s;
-  const long oo = (long)ii * s.ld + jj;
-  float v = s.dt * s.muxz[oo] * s.sxzb[oo];
-  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-    const int sz = strip_index(ii, s.nz, s.P);
-    if (sz >= 0) v += azh(s)[ii] * (c.pz[Z_XZ][(long)sz * s.nx + jj] + v);
-  }
-  return v;
+
+// p_bar for pxx (x int, X_XX), pzz (z int, Z_ZZ), pzx (z half, Z_XZ), pxz (x half, X_XZ)
+template <bool PML>
+__device__ __forceinline__ float pb_xx(const AdjCtx<PML>& c, int ii, int jj) {
+  return corr_x(c, c.s.dt * c.s.txxb[(long)ii * c.s.ld + jj], ii, jj, axi(c.s), X_XX);
 }
-__device__ __forceinline__ float pbar_xz(const PbarCtx& c, int ii, int jj) {
-  const Shot2D& s = c.s;
-  const long oo = (long)ii * s.ld + jj;
-  float v = s.dt * s.muxz[oo] * s.sxzb[oo];
-  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-    const int sx = strip_index(jj, s.nx, s.P);
-    if (sx >= 0) v += axh(s)[jj] * (c.px[X_XZ][(long)ii * 2 * s.P + sx] + v);
-  }
-  return v;
+template <bool PML>
+__device__ __forceinline__ float pb_zz(const AdjCtx<PML>& c, int ii, int jj) {
+  return corr_z(c, c.s.dt * c.s.tzzb[(long)ii * c.s.ld + jj], ii, jj, azi(c.s), Z_ZZ);
+}
+template <bool PML>
+__device__ __forceinline__ float pb_zx(const AdjCtx<PML>& c, int ii, int jj) {
+  return corr_z(c, c.s.dt * c.s.txzb[(long)ii * c.s.ld + jj], ii, jj, azh(c.s), Z_XZ);
+}
+template <bool PML>
+__device__ __forceinline__ float pb_xz(const AdjCtx<PML>& c, int ii, int jj) {
+  return corr_x(c, c.s.dt * c.s.txzb[(long)ii * c.s.ld + jj], ii, jj, axh(c.s), X_XZ);
+}
+// q_bar for qx with D+x sxx (x half, X_VXX), with D-z sxz (z int, Z_VXZ);
+// for qz with D-x sxz (x int, X_VZX), with D+z szz (z half, Z_VZZ)
+template <bool PML>
+__device__ __forceinline__ float qb_xa(const AdjCtx<PML>& c, int ii, int jj) {
+  return corr_x(c, c.s.dt * c.s.uxb[(long)ii * c.s.ld + jj], ii, jj, axh(c.s), X_VXX);
+}
+template <bool PML>
+__device__ __forceinline__ float qb_xb(const AdjCtx<PML>& c, int ii, int jj) {
+  return corr_z(c, c.s.dt * c.s.uxb[(long)ii * c.s.ld + jj], ii, jj, azi(c.s), Z_VXZ);
+}
+template <bool PML>
+__device__ __forceinline__ float qb_za(const AdjCtx<PML>& c, int ii, int jj) {
+  return corr_x(c, c.s.dt * c.s.uzb[(long)ii * c.s.ld + jj], ii, jj, axi(c.s), X_VZX);
+}
+template <bool PML>
+__device__ __forceinline__ float qb_zb(const AdjCtx<PML>& c, int ii, int jj) {
+  return corr_z(c, c.s.dt * c.s.uzb[(long)ii * c.s.ld + jj], ii, jj, azh(c.s), Z_VZZ);
 }
 
 __device__ __forceinline__ float ebar_at(const Shot2D& s, int slot, int jc, int n) {
@@ -242,197 +294,136 @@ __device__ __forceinline__ float ebar_at(const Shot2D& s, int slot, int jc, int 
   return c >= 0 ? s.ebar[(long)n * s.nch + c] : 0.0f;
 }
 
-template <bool GRAD, bool SRCADJ>
-__device__ __forceinline__ void adj_vel_cell(const Shot2D& s, int i, int j, int n, bool pml,
-                                             const float* seg, bool first) {
+__device__ __forceinline__ void accumulate(float* acc, long idx, float v, bool first) {
+  if (first) acc[idx] = v;
+  else acc[idx] += v;
+}
+
+// Transposed stress sub-step (first at reverse step n): t_bar -> u_bar.
+template <bool GRAD, bool SRCADJ, bool PML>
+__device__ __forceinline__ void adj_vel_cell(const Shot2D& s, int i, int j, int n, const float* seg, bool first) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  const PbarCtx c{s, pml, s.pbx[rd], s.pbz[rd]};
-  // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx)
-  float ux = K1 * (pbar_xx(c, i, j + 1) - pbar_xx(c, i, j)) + K2 * (pbar_xx(c, i, j + 2) - pbar_xx(c, i, j - 1));
-  float uz = K1 * (pbar_zx(c, i, j) - pbar_zx(c, i - 1, j)) + K2 * (pbar_zx(c, i + 1, j) - pbar_zx(c, i - 2, j));
+  const AdjCtx<PML> c{s, s.pbx[rd], s.pbz[rd]};
+  // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx); v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
+  const float ux = K1 * (pb_xx(c, i, j + 1) - pb_xx(c, i, j)) + K2 * (pb_xx(c, i, j + 2) - pb_xx(c, i, j - 1));
+  const float uz = K1 * (pb_zx(c, i, j) - pb_zx(c, i - 1, j)) + K2 * (pb_zx(c, i + 1, j) - pb_zx(c, i - 2, j));
+  const float wz = K1 * (pb_zz(c, i + 1, j) - pb_zz(c, i, j)) + K2 * (pb_zz(c, i + 2, j) - pb_zz(c, i - 1, j));
+  const float wx = K1 * (pb_xz(c, i, j) - pb_xz(c, i, j - 1)) + K2 * (pb_xz(c, i, j + 1) - pb_xz(c, i, j - 2));
   float gx = -(ux * s.rdx + uz * s.rdz);
-  // v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
-  float wz = K1 * (pbar_zz(c, i + 1, j) - pbar_zz(c, i, j)) + K2 * (pbar_zz(c, i + 2, j) - pbar_zz(c, i - 1, j));
-  float wx = K1 * (pbar_xz(c, i, j) - pbar_xz(c, i, j - 1)) + K2 * (pbar_xz(c, i, j + 1) - pbar_xz(c, i, j - 2));
   const float gz = -(wz * s.rdz + wx * s.rdx);
-  // DAS transpose: channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1), jc+1 (c2), jc-2 (-c2)
+  // DAS transpose: the channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1),
+  // jc+1 (c2) and jc-2 (-c2) of its row
   const int slot = s.row_slot[i];
   if (slot >= 0) {
     const float inj = K1 * (ebar_at(s, slot, j, n) - ebar_at(s, slot, j + 1, n)) +
                       K2 * (ebar_at(s, slot, j - 1, n) - ebar_at(s, slot, j + 2, n));
     gx += s.dt * s.rdx * inj;
   }
-  const float sxxb = s.sxxb[o], szzb = s.szzb[o], sxzb = s.sxzb[o];
-  // owned adjoint memory variables: psi_bar_next = b (psi_bar + p_bar~)
-  if (pml) {
+  const float txx = s.txxb[o], tzz = s.tzzb[o], txz = s.txzb[o];
+  if (PML) {  // owned adjoint memory variables of the stress-side derivatives
     const int sx = strip_index(j, s.nx, s.P);
     const int sz = strip_index(i, s.nz, s.P);
-    const float pxx_t = s.dt * (s.l2m[o] * sxxb + s.lam[o] * szzb);
-    const float pzz_t = s.dt * (s.lam[o] * sxxb + s.l2m[o] * szzb);
-    const float ps_t = s.dt * s.muxz[o] * sxzb;
     if (sx >= 0) {
       const long q = (long)i * 2 * s.P + sx;
-      s.pbx[wr][X_XX][q] = bxi(s)[j] * (s.pbx[rd][X_XX][q] + pxx_t);
-      s.pbx[wr][X_XZ][q] = bxh(s)[j] * (s.pbx[rd][X_XZ][q] + ps_t);
+      s.pbx[wr][X_XX][q] = bxi(s)[j] * (s.pbx[rd][X_XX][q] + s.dt * txx);
+      s.pbx[wr][X_XZ][q] = bxh(s)[j] * (s.pbx[rd][X_XZ][q] + s.dt * txz);
     }
     if (sz >= 0) {
       const long q = (long)sz * s.nx + j;
-      s.pbz[wr][Z_ZZ][q] = bzi(s)[i] * (s.pbz[rd][Z_ZZ][q] + pzz_t);
-      s.pbz[wr][Z_XZ][q] = bzh(s)[i] * (s.pbz[rd][Z_XZ][q] + ps_t);
+      s.pbz[wr][Z_ZZ][q] = bzi(s)[i] * (s.pbz[rd][Z_ZZ][q] + s.dt * tzz);
+      s.pbz[wr][Z_XZ][q] = bzh(s)[i] * (s.pbz[rd][Z_XZ][q] + s.dt * txz);
     }
   }
-  s.vxb[o] += gx;
-  s.vzb[o] += gz;
+  s.uxb[o] += s.bx[o] * gx;
+  s.uzb[o] += s.bz[o] * gz;
   if (GRAD) {
-    const long cc = (long)i * s.nx + j;
-    const float pxx = seg[cc], pzz = seg[s.cells + cc], ps = seg[2 * s.cells + cc];
-    const float a0 = s.dt * (sxxb + szzb) * (pxx + pzz);
-    const float a1 = 2.0f * s.dt * (sxxb * pxx + szzb * pzz);
-    const float a2 = s.dt * sxzb * ps;
-    float* acc = s.acc;
-    if (first) {
-      acc[cc] = a0;
-      acc[s.cells + cc] = a1;
-      acc[2 * s.cells + cc] = a2;
-    } else {
-      acc[cc] += a0;
-      acc[s.cells + cc] += a1;
-      acc[2 * s.cells + cc] += a2;
-    }
+    const long cc = (long)i * s.cp + j;
+    accumulate(s.acc, cc, s.dt * (txx + tzz) * seg[cc], first);
+    accumulate(s.acc, s.cells + cc, s.dt * (txx - tzz) * seg[s.cells + cc], first);
+    accumulate(s.acc, 2 * s.cells + cc, s.dt * txz * seg[2 * s.cells + cc], first);
   }
   if (SRCADJ && i == s.si && j == s.sj) {
-    s.src_bar[n] = -s.w * sxxb;
-    s.src_bar[s.nt + n] = -s.w * szzb;
-    const float t = s.sxzb[o] + s.sxzb[o - 1] + s.sxzb[o - ld] + s.sxzb[o - ld - 1];
+    // sigma_bar at the source from t_bar: invert the 2x2 normal block and the shear moduli
+    const float l2m = s.l2m[o], lam = s.lam[o];
+    const float det = (l2m - lam) * (l2m + lam);
+    const float sxx = (l2m * txx - lam * tzz) / det, szz = (l2m * tzz - lam * txx) / det;
+    auto sxz_at = [&](long oo) { return s.muxz[oo] > 0.0f ? s.txzb[oo] / s.muxz[oo] : 0.0f; };
+    const float t = sxz_at(o) + sxz_at(o - 1) + sxz_at(o - ld) + sxz_at(o - ld - 1);
+    s.src_bar[n] = -s.w * sxx;
+    s.src_bar[s.nt + n] = -s.w * szz;
     s.src_bar[2 * s.nt + n] = -0.25f * s.w * t;
   }
 }
 
 template <bool GRAD, bool SRCADJ>
 __global__ __launch_bounds__(BX * BZ) void k_adj_vel(const Shot2D s, int n, const float* seg, int first) {
-  const int j0 = blockIdx.x * BX, i0 = blockIdx.y * BZ;
+  int i0, j0;
+  if (!tile_of(s.nz, s.nx, i0, j0)) return;
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
-  const bool pml = block_in_pml(s, j0, i0, 2);
-  if (i < s.nz && j < s.nx) adj_vel_cell<GRAD, SRCADJ>(s, i, j, n, pml, seg, first != 0);
+  if (i >= s.nz || j >= s.nx) return;
+  if (block_in_pml(s, j0, i0, 2)) adj_vel_cell<GRAD, SRCADJ, true>(s, i, j, n, seg, first != 0);
+  else adj_vel_cell<GRAD, SRCADJ, false>(s, i, j, n, seg, first != 0);
 }
 
-// ------------------------------------------------------------------------------------
-// Transposed velocity sub-step (second at reverse step n): q_bar = dt b v_bar (+ CPML
-// transpose), sigma_bar += D^T q_bar; imaging terms for b_x, b_z.
-// ------------------------------------------------------------------------------------
-struct QbarCtx {
-  const Shot2D& s;
-  bool pml;
-  const float* const* px;
-  const float* const* pz;
-};
-// qx_bar at vx node corrected for D+x sxx (x-half, X_VXX)
-__device__ __forceinline__ float qbar_xa(const QbarCtx& c, int ii, int jj) {
-  const Shot2D& s = c.s;
-  const long oo = (long)ii * s.ld + jj;
-  float v = s.dt * s.bx[oo] * s.vxb[oo];
-  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-    const int sx = strip_index(jj, s.nx, s.P);
-    if (sx >= 0) v += axh(s)[jj] * (c.px[X_VXX][(long)ii * 2 * s.P + sx] + v);
-  }
-  return v;
-}
-// qx_bar corrected for D-z sxz (z-int, Z_VXZ)
-__device__ __forceinline__ float qbar_xb(const QbarCtx& c, int ii, int jj) {
-  const Shot2D& s = c.s;
-  const long oo = (long)ii * s.ld + jj;
-  float v = s.dt * s.bx[oo] * s.vxb[oo];
-  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-    const int sz = strip_index(ii, s.nz, s.P);
-    if (sz >= 0) v += azi(s)[ii] * (c.pz[Z_VXZ][(long)sz * s.nx + jj] + v);
-  }
-  return v;
-}
-// qz_bar corrected for D-x sxz (x-int, X_VZX)
-__device__ __forceinline__ float qbar_za(const QbarCtx& c, int ii, int jj) {
-  const Shot2D& s = c.s;
-  const long oo = (long)ii * s.ld + jj;
-  float v = s.dt * s.bz[oo] * s.vzb[oo];
-  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-    const int sx = strip_index(jj, s.nx, s.P);
-    if (sx >= 0) v += axi(s)[jj] * (c.px[X_VZX][(long)ii * 2 * s.P + sx] + v);
-  }
-  return v;
-}
-// qz_bar corrected for D+z szz (z-half, Z_VZZ)
-__device__ __forceinline__ float qbar_zb(const QbarCtx& c, int ii, int jj) {
-  const Shot2D& s = c.s;
-  const long oo = (long)ii * s.ld + jj;
-  float v = s.dt * s.bz[oo] * s.vzb[oo];
-  if (c.pml && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-    const int sz = strip_index(ii, s.nz, s.P);
-    if (sz >= 0) v += azh(s)[ii] * (c.pz[Z_VZZ][(long)sz * s.nx + jj] + v);
-  }
-  return v;
-}
-
-template <bool GRAD>
-__device__ __forceinline__ void adj_str_cell(const Shot2D& s, int i, int j, int n, bool pml,
-                                             const float* seg, bool first) {
+// Transposed velocity sub-step (second at reverse step n): u_bar -> t_bar.
+template <bool GRAD, bool PML>
+__device__ __forceinline__ void adj_str_cell(const Shot2D& s, int i, int j, int n, const float* seg, bool first) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  const QbarCtx c{s, pml, s.pbx[rd], s.pbz[rd]};
-  // sxx_bar += -D-x qa ; szz_bar += -D-z qzb ; sxz_bar += -(D+z qxb + D+x qza)
-  const float txx = K1 * (qbar_xa(c, i, j) - qbar_xa(c, i, j - 1)) + K2 * (qbar_xa(c, i, j + 1) - qbar_xa(c, i, j - 2));
-  const float tzz = K1 * (qbar_zb(c, i, j) - qbar_zb(c, i - 1, j)) + K2 * (qbar_zb(c, i + 1, j) - qbar_zb(c, i - 2, j));
-  const float t1 = K1 * (qbar_xb(c, i + 1, j) - qbar_xb(c, i, j)) + K2 * (qbar_xb(c, i + 2, j) - qbar_xb(c, i - 1, j));
-  const float t2 = K1 * (qbar_za(c, i, j + 1) - qbar_za(c, i, j)) + K2 * (qbar_za(c, i, j + 2) - qbar_za(c, i, j - 1));
-  const float vxb = s.vxb[o], vzb = s.vzb[o];
-  if (pml) {
+  const AdjCtx<PML> c{s, s.pbx[rd], s.pbz[rd]};
+  // sigma_bar_xx += -D-x q_bar_xa ; sigma_bar_zz += -D-z q_bar_zb ;
+  // sigma_bar_xz += -(D+z q_bar_xb + D+x q_bar_za)
+  const float txx = K1 * (qb_xa(c, i, j) - qb_xa(c, i, j - 1)) + K2 * (qb_xa(c, i, j + 1) - qb_xa(c, i, j - 2));
+  const float tzz = K1 * (qb_zb(c, i, j) - qb_zb(c, i - 1, j)) + K2 * (qb_zb(c, i + 1, j) - qb_zb(c, i - 2, j));
+  const float t1 = K1 * (qb_xb(c, i + 1, j) - qb_xb(c, i, j)) + K2 * (qb_xb(c, i + 2, j) - qb_xb(c, i - 1, j));
+  const float t2 = K1 * (qb_za(c, i, j + 1) - qb_za(c, i, j)) + K2 * (qb_za(c, i, j + 2) - qb_za(c, i, j - 1));
+  const float dsxx = -txx * s.rdx, dszz = -tzz * s.rdz, dsxz = -(t1 * s.rdz + t2 * s.rdx);
+  const float ux = s.uxb[o], uz = s.uzb[o];
+  if (PML) {  // owned adjoint memory variables of the velocity-side derivatives
     const int sx = strip_index(j, s.nx, s.P);
     const int sz = strip_index(i, s.nz, s.P);
-    const float qx_t = s.dt * s.bx[o] * vxb;
-    const float qz_t = s.dt * s.bz[o] * vzb;
     if (sx >= 0) {
       const long q = (long)i * 2 * s.P + sx;
-      s.pbx[wr][X_VXX][q] = bxh(s)[j] * (s.pbx[rd][X_VXX][q] + qx_t);
-      s.pbx[wr][X_VZX][q] = bxi(s)[j] * (s.pbx[rd][X_VZX][q] + qz_t);
+      s.pbx[wr][X_VXX][q] = bxh(s)[j] * (s.pbx[rd][X_VXX][q] + s.dt * ux);
+      s.pbx[wr][X_VZX][q] = bxi(s)[j] * (s.pbx[rd][X_VZX][q] + s.dt * uz);
     }
     if (sz >= 0) {
       const long q = (long)sz * s.nx + j;
-      s.pbz[wr][Z_VXZ][q] = bzi(s)[i] * (s.pbz[rd][Z_VXZ][q] + qx_t);
-      s.pbz[wr][Z_VZZ][q] = bzh(s)[i] * (s.pbz[rd][Z_VZZ][q] + qz_t);
+      s.pbz[wr][Z_VXZ][q] = bzi(s)[i] * (s.pbz[rd][Z_VXZ][q] + s.dt * ux);
+      s.pbz[wr][Z_VZZ][q] = bzh(s)[i] * (s.pbz[rd][Z_VZZ][q] + s.dt * uz);
     }
   }
-  s.sxxb[o] -= txx * s.rdx;
-  s.szzb[o] -= tzz * s.rdz;
-  s.sxzb[o] -= t1 * s.rdz + t2 * s.rdx;
+  const float l2m = s.l2m[o], lam = s.lam[o];
+  s.txxb[o] += l2m * dsxx + lam * dszz;
+  s.tzzb[o] += lam * dsxx + l2m * dszz;
+  s.txzb[o] += s.muxz[o] * dsxz;
   if (GRAD) {
-    const long cc = (long)i * s.nx + j;
-    const float a3 = s.dt * vxb * seg[3 * s.cells + cc];
-    const float a4 = s.dt * vzb * seg[4 * s.cells + cc];
-    float* acc = s.acc;
-    if (first) {
-      acc[3 * s.cells + cc] = a3;
-      acc[4 * s.cells + cc] = a4;
-    } else {
-      acc[3 * s.cells + cc] += a3;
-      acc[4 * s.cells + cc] += a4;
-    }
+    const long cc = (long)i * s.cp + j;
+    accumulate(s.acc, 3 * s.cells + cc, s.dt * ux * seg[3 * s.cells + cc], first);
+    accumulate(s.acc, 4 * s.cells + cc, s.dt * uz * seg[4 * s.cells + cc], first);
   }
 }
 
 template <bool GRAD>
 __global__ __launch_bounds__(BX * BZ) void k_adj_str(const Shot2D s, int n, const float* seg, int first) {
-  const int j0 = blockIdx.x * BX, i0 = blockIdx.y * BZ;
+  int i0, j0;
+  if (!tile_of(s.nz, s.nx, i0, j0)) return;
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
-  const bool pml = block_in_pml(s, j0, i0, 2);
-  if (i < s.nz && j < s.nx) adj_str_cell<GRAD>(s, i, j, n, pml, seg, first != 0);
+  if (i >= s.nz || j >= s.nx) return;
+  if (block_in_pml(s, j0, i0, 2)) adj_str_cell<GRAD, true>(s, i, j, n, seg, first != 0);
+  else adj_str_cell<GRAD, false>(s, i, j, n, seg, first != 0);
 }
 
 // ------------------------------------------------------------------------------------
 // Staging: (Vp, Vs, rho) of the window -> lambda + 2 mu, lambda, harmonic mu_xz, b_x, b_z.
 // ------------------------------------------------------------------------------------
 __global__ void k_stage(const Shot2D s) {
-  const int j = blockIdx.x * BX + threadIdx.x, i = blockIdx.y * BZ + threadIdx.y;
+  int i0, j0;
+  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   if (i >= s.nz || j >= s.nx) return;
   const int ip = min(i + 1, s.nz - 1), jp = min(j + 1, s.nx - 1);
   auto at = [&](const float* f, int a, int b) { return f[(long)a * s.mld + b]; };
@@ -461,18 +452,20 @@ __global__ void k_stage(const Shot2D s) {
 // on both (clamped) nodes of the average; lambda = rho(Vp^2 - 2Vs^2), mu = rho Vs^2.
 // ------------------------------------------------------------------------------------
 __global__ void k_chain_flush(const Shot2D s) {
-  const int j = blockIdx.x * BX + threadIdx.x, i = blockIdx.y * BZ + threadIdx.y;
+  int i0, j0;
+  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   if (i >= s.nz || j >= s.nx) return;
-  const long cc = (long)i * s.nx + j;
+  const long cc = (long)i * s.cp + j;
   const long mo = (long)i * s.mld + j;
   const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
   const float mu = rho * vs * vs;
   const float* glam = s.acc;
-  const float* gmu = s.acc + s.cells;
+  const float* gdmu = s.acc + s.cells;        // g_mu - g_lambda
   const float* gmuxz = s.acc + 2 * s.cells;
   const float* gbx = s.acc + 3 * s.cells;
   const float* gbz = s.acc + 4 * s.cells;
-  double gmu_tot = gmu[cc];
+  double gmu_tot = (double)glam[cc] + (double)gdmu[cc];
   for (int di = -1; di <= 0; ++di) {
     for (int dj = -1; dj <= 0; ++dj) {
       const int a = i + di, b = j + dj;
@@ -482,7 +475,7 @@ __global__ void k_chain_flush(const Shot2D s) {
       if (mult == 0) continue;
       const float mxz = s.muxz[(long)a * s.ld + b];
       if (mxz > 0.0f)
-        gmu_tot += (double)mult * gmuxz[(long)a * s.nx + b] * ((double)mxz * mxz / (4.0 * (double)mu * mu));
+        gmu_tot += (double)mult * gmuxz[(long)a * s.cp + b] * ((double)mxz * mxz / (4.0 * (double)mu * mu));
     }
   }
   double grho_b = 0.0;
@@ -493,7 +486,7 @@ __global__ void k_chain_flush(const Shot2D s) {
     const int mult = (b == j) + (bp == j);
     if (mult == 0) continue;
     const double bxv = s.bx[(long)i * s.ld + b];
-    grho_b -= 0.5 * mult * gbx[(long)i * s.nx + b] * bxv * bxv;
+    grho_b -= 0.5 * mult * gbx[(long)i * s.cp + b] * bxv * bxv;
   }
   for (int da = -1; da <= 0; ++da) {      // vz nodes (a, j) average rho(a, j), rho(a+1, j)
     const int a = i + da;
@@ -502,7 +495,7 @@ __global__ void k_chain_flush(const Shot2D s) {
     const int mult = (a == i) + (ap == i);
     if (mult == 0) continue;
     const double bzv = s.bz[(long)a * s.ld + j];
-    grho_b -= 0.5 * mult * gbz[(long)a * s.nx + j] * bzv * bzv;
+    grho_b -= 0.5 * mult * gbz[(long)a * s.cp + j] * bzv * bzv;
   }
   const double gl = glam[cc];
   const double dvp = vp, dvs = vs, drho = rho;
@@ -512,9 +505,11 @@ __global__ void k_chain_flush(const Shot2D s) {
 }
 
 __global__ void k_write_gradient(const Shot2D s, float* g, long mplane, int z0, int x0) {
-  const int j = blockIdx.x * BX + threadIdx.x, i = blockIdx.y * BZ + threadIdx.y;
+  int i0, j0;
+  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   if (i >= s.nz || j >= s.nx) return;
-  const long cc = (long)i * s.nx + j;
+  const long cc = (long)i * s.cp + j;
   const long go = (long)(z0 + i) * s.mld + (x0 + j);
   for (int k = 0; k < 3; ++k) g[k * mplane + go] = (float)s.G[k * s.cells + cc];
 }
@@ -551,7 +546,10 @@ __global__ void k_reduce_phi(const double* partial, int n, double* phi) {
   if (threadIdx.x == 0) *phi = 0.5 * sh[0];
 }
 
-inline dim3 grid2d(const Shot2D& s) { return dim3((s.nx + BX - 1) / BX, (s.nz + BZ - 1) / BZ); }
+inline dim3 grid2d(const Shot2D& s) {
+  const int ntiles = ((s.nx + BX - 1) / BX) * ((s.nz + BZ - 1) / BZ);
+  return dim3(NXCD * ((ntiles + NXCD - 1) / NXCD));
+}
 inline dim3 block2d() { return dim3(BX, BZ); }
 
 }  // namespace
