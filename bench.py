@@ -75,7 +75,7 @@ def cpu_baseline(w, steps=8):
                       f"FP64 NumPy (single-threaded elementwise), {dt:.1f} s"}
 
 
-def main():
+def main():  # noqa: C901
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--nt", type=int, default=4000, help="time steps (profiling runs use fewer)")
     ap.add_argument("--sample-every", type=int, default=16, help="time every k-th launch of each kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -124,28 +125,53 @@ def main():
     g_ext = torch.empty_like(m_ext)
     phi = torch.empty((ns,), dtype=torch.float64, device=dev)
     phi_reg = torch.empty((), dtype=torch.float64, device=dev)
-    ws = efwi.workspace(efwi.workspace_size(efwi.WS_BATCH, grid, shots), dev)
     rws = efwi.workspace(efwi.workspace_size(efwi.WS_REGULARIZER, grid, []), dev)
+    nch = [s.nch for s in shots]
+    obs = list(torch.split(d_obs, nch))
+    ws = efwi.workspace(efwi.workspace_size(efwi.WS_GRADIENT, grid, shots[:1]), dev)
     torch.cuda.synchronize()
 
-    def step():
-        efwi.batch_gradient(grid, shots, m_ext, src, d_obs, g_ext=g_ext, phi=phi, ws=ws)
+    def plain_step():
+        """Plain per-shot form: one shot gradient after the other, one shot's workspace."""
+        for k in range(ns):
+            efwi.shot_gradient(grid, shots[k], m_ext[k], src[k], obs[k], g=g_ext[k], phi=phi[k], ws=ws)
         efwi.extension_regularizer(grid, m_ext, b, sink, 1.0, g_ext, phi=phi_reg, ws=rws)
 
     for _ in range(args.warmup):
-        step()
+        plain_step()
     torch.cuda.synchronize()
     efwi.timing_reset()
     efwi.timing_enable(args.sample_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        plain_step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timing = efwi.timing_query()
     efwi.timing_enable(0)
     assert bool(torch.isfinite(phi).all()) and bool(torch.isfinite(phi_reg))
+    g_plain = g_ext.clone() if not args.no_batched else None
+    del ws
+
+    batched = None
+    if not args.no_batched:
+        # Batched form: every shot advanced together (one launch per half step covers all
+        # shots' tiles), in as few waves as the free device memory allows.
+        need = efwi.workspace_size(efwi.WS_BATCH, grid, shots)
+        free = torch.cuda.mem_get_info(dev)[0]
+        bws = efwi.workspace(min(need, int(free * 0.9)), dev)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        efwi.batch_gradient(grid, shots, m_ext, src, d_obs, g_ext=g_ext, phi=phi, ws=bws)
+        efwi.extension_regularizer(grid, m_ext, b, sink, 1.0, g_ext, phi=phi_reg, ws=rws)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - tb
+        same = bool(torch.equal(g_plain, g_ext))
+        batched = {"shots_per_s": round(ns / tb, 4), "gcell_per_s": round(ns * nz * nx * nt / tb / 1e9, 4),
+                   "ms_per_step": round(tb * 1e3, 2), "waves": -(-need // bws.numel()),
+                   "identical_to_plain": same}
+        del bws
 
     cell_steps = ns * nz * nx * nt * args.steps
     value = cell_steps / elapsed / 1e9
@@ -184,7 +210,9 @@ def main():
         "path": {"bytes_per_cell_step": PATH_BYTES_PER_CELL_STEP,
                  "achieved_GBs": round(PATH_BYTES_PER_CELL_STEP * cell_steps / elapsed / 1e9, 1),
                  "frac": round(PATH_BYTES_PER_CELL_STEP * cell_steps / elapsed / 1e9 / HBM_PEAK_GBS, 4)},
-        "shots_per_s": {"plain": round(ns * args.steps / elapsed, 4)},
+        "shots_per_s": {"plain": round(ns * args.steps / elapsed, 4),
+                        "batched": batched["shots_per_s"] if batched else None},
+        "batched": batched,
         "kernels": kern,
     }
     if not args.no_cpu_baseline:

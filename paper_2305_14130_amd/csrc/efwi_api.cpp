@@ -260,15 +260,16 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
 }
 
 // ----------------------------------------------------------------------------------------
-// Workspace plan of one 2D shot.
+// Workspace plan of one 2D shot (its private region of the workspace).
 // ----------------------------------------------------------------------------------------
 struct Plan2D {
   Window w;
-  int nz, nx, ld, cp, rows, P, nslots, nt, nch, L, nseg;
+  int nz, nx, ld, cp, rows, P, nslots, nt, nch, L, nseg, ntiles;
   long plane, cells;
   size_t state_bytes;  // padded fields + forward CPML strips (one checkpoint)
-  size_t off_state, off_e, off_adj, off_par, off_tab, tab_bytes, off_ebar, off_partial, off_dint, off_acc, off_G,
-      off_seg, off_ckpt, total;
+  size_t tab_bytes;    // CPML profiles + channel maps (kept in the batch header)
+  size_t off_state, off_e, off_adj, off_par, off_ebar, off_partial, off_dint, off_acc, off_G, off_seg, off_ckpt,
+      total;
   size_t adj_bytes, par_bytes;
 };
 
@@ -280,6 +281,11 @@ int count_slots(const efwi_shot& s, const Window& w) {
   std::sort(rows.begin(), rows.end());
   rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
   return (int)rows.size();
+}
+
+int interval_of(const efwi_grid& g, const efwi_shot& s) {
+  int L = s.ckpt_interval > 0 ? s.ckpt_interval : (int)std::ceil(std::sqrt((double)g.nt));
+  return std::max(1, std::min(L, g.nt));
 }
 
 Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
@@ -296,10 +302,9 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.nt = g.nt;
   p.nch = s.nch;
   p.nslots = count_slots(s, p.w);
-  int L = s.ckpt_interval > 0 ? s.ckpt_interval : (int)std::ceil(std::sqrt((double)g.nt));
-  L = std::max(1, std::min(L, g.nt));
-  p.L = L;
-  p.nseg = (g.nt + L - 1) / L;
+  p.ntiles = ((p.nx + BX - 1) / BX) * ((p.nz + BZ - 1) / BZ);
+  p.L = interval_of(g, s);
+  p.nseg = (g.nt + p.L - 1) / p.L;
   const size_t strips = strips_floats(p.nz, p.nx, p.P);
   p.state_bytes = align_up(((size_t)5 * p.plane + strips) * sizeof(float));
   p.adj_bytes = align_up(((size_t)5 * p.plane + 2 * strips) * sizeof(float));
@@ -316,7 +321,6 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
     return at;
   };
   p.off_par = take(p.par_bytes);
-  p.off_tab = take(p.tab_bytes);
   p.off_state = fwd ? take(p.state_bytes) : 0;
   p.off_e = fwd ? take((size_t)std::max(1, p.nch) * sizeof(float)) : 0;
   p.off_adj = adj ? take(p.adj_bytes) : 0;
@@ -331,11 +335,12 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   return p;
 }
 
-// Host tables: CPML profiles (computed in double, stored FP32), row -> slot map, and the
-// [slot][x] channel map.
-void cpml_profile(std::vector<float>& a, std::vector<float>& b, int n, double h, const efwi_grid& g, bool half) {
-  a.assign(n, 0.f);
-  b.assign(n, 1.f);
+// CPML profile of one axis, computed in double and stored FP32.
+void cpml_profile(float* a, float* b, int n, double h, const efwi_grid& g, bool half) {
+  for (int k = 0; k < n; ++k) {
+    a[k] = 0.f;
+    b[k] = 1.f;
+  }
   if (g.npml <= 0) return;
   const double L = g.npml;
   const double d0 = -3.0 * g.vp_max * std::log((double)g.pml_R) / (2.0 * L * h);
@@ -352,23 +357,15 @@ void cpml_profile(std::vector<float>& a, std::vector<float>& b, int n, double h,
   }
 }
 
-std::vector<unsigned char> build_tables(const efwi_grid& g, const efwi_shot& s, const Plan2D& p) {
-  std::vector<unsigned char> blob(p.tab_bytes, 0);
-  float* prof = reinterpret_cast<float*>(blob.data());
-  std::vector<float> a, b;
+// Per-shot tables: CPML profiles, row -> slot map and the [slot][x] channel map.
+void build_tables(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsigned char* out) {
+  std::memset(out, 0, p.tab_bytes);
+  float* prof = reinterpret_cast<float*>(out);
   const int nx = p.nx, nz = p.nz;
-  cpml_profile(a, b, nx, g.dx, g, false);
-  std::copy(a.begin(), a.end(), prof);
-  std::copy(b.begin(), b.end(), prof + nx);
-  cpml_profile(a, b, nx, g.dx, g, true);
-  std::copy(a.begin(), a.end(), prof + 2 * nx);
-  std::copy(b.begin(), b.end(), prof + 3 * nx);
-  cpml_profile(a, b, nz, g.dz, g, false);
-  std::copy(a.begin(), a.end(), prof + 4 * nx);
-  std::copy(b.begin(), b.end(), prof + 4 * nx + nz);
-  cpml_profile(a, b, nz, g.dz, g, true);
-  std::copy(a.begin(), a.end(), prof + 4 * nx + 2 * nz);
-  std::copy(b.begin(), b.end(), prof + 4 * nx + 3 * nz);
+  cpml_profile(prof, prof + nx, nx, g.dx, g, false);
+  cpml_profile(prof + 2 * nx, prof + 3 * nx, nx, g.dx, g, true);
+  cpml_profile(prof + 4 * nx, prof + 4 * nx + nz, nz, g.dz, g, false);
+  cpml_profile(prof + 4 * nx + 2 * nz, prof + 4 * nx + 3 * nz, nz, g.dz, g, true);
   int* row_slot = reinterpret_cast<int*>(prof + 4 * nx + 4 * nz);
   int* rowch = row_slot + nz;
   std::fill(row_slot, row_slot + nz, -1);
@@ -379,11 +376,23 @@ std::vector<unsigned char> build_tables(const efwi_grid& g, const efwi_shot& s, 
     if (row_slot[ci] < 0) row_slot[ci] = nslots++;
     rowch[(size_t)row_slot[ci] * nx + cj] = c;
   }
-  return blob;
 }
 
-Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsigned char* ws, const float* m,
-                 long mplane) {
+// What one shot reads and writes (device pointers; unused ones are NULL).
+struct ShotIO {
+  const float* m = nullptr;   // window of the full-model [3][nz][nx] array
+  long mplane = 0;
+  const float* src = nullptr;
+  const float* dobs = nullptr;
+  const float* r = nullptr;
+  float* d = nullptr;          // forward data output
+  float* gout = nullptr;
+  double* phi = nullptr;
+  float* src_bar = nullptr;
+};
+
+Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsigned char* region,
+                 const float* tab, const ShotIO& io) {
   Shot2D d{};
   d.nz = p.nz;
   d.nx = p.nx;
@@ -401,61 +410,49 @@ Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsign
   d.cells = p.cells;
   const long interior = (long)HALO * p.ld + XOFF;
   const size_t strips = strips_floats(p.nz, p.nx, p.P);
-  auto fields = [&](size_t off, float** out, int count) {
-    float* base = reinterpret_cast<float*>(ws + off);
-    for (int k = 0; k < count; ++k) out[k] = base + k * p.plane + interior;
+  auto fields = [&](size_t off, gfloat** out) {
+    gfloat* base = (gfloat*)(region + off);
+    for (int k = 0; k < 5; ++k) out[k] = base + k * p.plane + interior;
     return base + (size_t)5 * p.plane;  // strips follow the five planes
   };
-  auto strips_at = [&](float* base, float** px, float** pz) {
+  auto strips_at = [&](gfloat* base, gfloat** px, gfloat** pz) {
     const size_t xs = (size_t)p.nz * 2 * p.P, zs = (size_t)2 * p.P * p.nx;
     for (int k = 0; k < 4; ++k) px[k] = base + k * xs;
     for (int k = 0; k < 4; ++k) pz[k] = base + 4 * xs + k * zs;
   };
-  {
-    float* f[5];
-    float* st = fields(p.off_state, f, 5);
-    d.vx = f[0];
-    d.vz = f[1];
-    d.sxx = f[2];
-    d.szz = f[3];
-    d.sxz = f[4];
-    strips_at(st, d.psx, d.psz);
-  }
-  {
-    float* f[5];
-    float* st = fields(p.off_adj, f, 5);
-    d.uxb = f[0];
-    d.uzb = f[1];
-    d.txxb = f[2];
-    d.tzzb = f[3];
-    d.txzb = f[4];
-    strips_at(st, d.pbx[0], d.pbz[0]);
-    strips_at(st + strips, d.pbx[1], d.pbz[1]);
-  }
-  {
-    float* f[5];
-    fields(p.off_par, f, 5);
-    d.l2m = f[0];
-    d.lam = f[1];
-    d.muxz = f[2];
-    d.bx = f[3];
-    d.bz = f[4];
-  }
-  float* prof = reinterpret_cast<float*>(ws + p.off_tab);
-  d.prof = prof;
-  d.row_slot = reinterpret_cast<const int*>(prof + 4 * p.nx + 4 * p.nz);
+  gfloat* f[5];
+  gfloat* st = fields(p.off_state, f);
+  d.vx = f[0], d.vz = f[1], d.sxx = f[2], d.szz = f[3], d.sxz = f[4];
+  strips_at(st, d.psx, d.psz);
+  st = fields(p.off_adj, f);
+  d.uxb = f[0], d.uzb = f[1], d.txxb = f[2], d.tzzb = f[3], d.txzb = f[4];
+  strips_at(st, d.pbx[0], d.pbz[0]);
+  strips_at(st + strips, d.pbx[1], d.pbz[1]);
+  fields(p.off_par, f);
+  d.l2m = f[0], d.lam = f[1], d.muxz = f[2], d.bx = f[3], d.bz = f[4];
+  d.prof = (const gfloat*)(tab);
+  d.row_slot = (const gint*)(tab + 4 * p.nx + 4 * p.nz);
   d.rowch = d.row_slot + p.nz;
-  d.e = reinterpret_cast<float*>(ws + p.off_e);
-  d.ebar = reinterpret_cast<const float*>(ws + p.off_ebar);
-  d.acc = reinterpret_cast<float*>(ws + p.off_acc);
-  d.G = reinterpret_cast<double*>(ws + p.off_G);
-  d.seg = reinterpret_cast<float*>(ws + p.off_seg);
+  d.e = (gfloat*)(region + p.off_e);
+  d.ebar = (const gfloat*)(region + p.off_ebar);
+  d.acc = (gfloat*)(region + p.off_acc);
+  d.G = (gdouble*)(region + p.off_G);
+  d.seg = (gfloat*)(region + p.off_seg);
   const long mld = g.nx;
-  const float* mw = m + (long)p.w.z0 * mld + p.w.x0;
-  d.mvp = mw;
-  d.mvs = mw + mplane;
-  d.mrho = mw + 2 * mplane;
+  if (io.m) {
+    const gfloat* mw = (const gfloat*)(io.m + (long)p.w.z0 * mld + p.w.x0);
+    d.mvp = mw;
+    d.mvs = mw + io.mplane;
+    d.mrho = mw + 2 * io.mplane;
+  }
   d.mld = mld;
+  d.src = (const gfloat*)(io.src);
+  d.src_bar = (gfloat*)(io.src_bar);
+  d.d = (gfloat*)(io.d ? io.d : reinterpret_cast<float*>(region + p.off_dint));
+  d.gout = (gfloat*)(io.gout);
+  d.mplane = io.mplane;
+  d.z0 = p.w.z0;
+  d.x0 = p.w.x0;
   return d;
 }
 
@@ -466,87 +463,205 @@ efwi_status check_ws(const void* ws, size_t have, size_t need) {
   return EFWI_OK;
 }
 
-// Common set-up: zero what must start at zero, upload the tables, stage the parameters.
-efwi_status setup_shot(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsigned char* ws, Shot2D& d,
-                       bool fwd, bool adj, bool grad, hipStream_t st) {
-  HIP_TRY(hipMemsetAsync(ws + p.off_par, 0, p.par_bytes, st));
-  if (fwd) {
-    HIP_TRY(hipMemsetAsync(ws + p.off_state, 0, p.state_bytes, st));
-    HIP_TRY(hipMemsetAsync(ws + p.off_e, 0, (size_t)std::max(1, p.nch) * sizeof(float), st));
+// ----------------------------------------------------------------------------------------
+// A wave: shots [first, first + count) of a call, advanced together. The workspace holds a
+// header (descriptors, tile list, per-shot tables: uploaded once) followed by each shot's
+// private region.
+// ----------------------------------------------------------------------------------------
+size_t header_bytes(const std::vector<Plan2D>& plans, int first, int count) {
+  size_t tiles = 0, tabs = 0;
+  for (int k = first; k < first + count; ++k) {
+    tiles += plans[k].ntiles;
+    tabs += plans[k].tab_bytes;
   }
-  if (adj) HIP_TRY(hipMemsetAsync(ws + p.off_adj, 0, p.adj_bytes, st));
-  if (grad) HIP_TRY(hipMemsetAsync(ws + p.off_G, 0, (size_t)3 * p.cells * sizeof(double), st));
-  std::vector<unsigned char> tab = build_tables(g, s, p);
-  HIP_TRY(staging().upload(ws + p.off_tab, tab.data(), tab.size(), st));
-  HIP_TRY(launch_stage2d(d, st));
-  return EFWI_OK;
+  return align_up((size_t)count * sizeof(Shot2D)) + align_up((size_t)count * sizeof(int)) +
+         align_up(tiles * sizeof(int)) + tabs;
 }
 
-efwi_status run_forward(Shot2D& d, const Plan2D& p, unsigned char* ws, bool checkpoints, hipStream_t st) {
-  const int last0 = (p.nseg - 1) * p.L;
-  for (int n = 0; n < p.nt; ++n) {
-    if (checkpoints && n % p.L == 0 && n > 0 && n < last0) {
-      const int k = n / p.L;
-      HIP_TRY(hipMemcpyAsync(ws + p.off_ckpt + (size_t)(k - 1) * p.state_bytes, ws + p.off_state, p.state_bytes,
-                             hipMemcpyDeviceToDevice, st));
+size_t wave_bytes(const std::vector<Plan2D>& plans, int first, int count) {
+  size_t t = header_bytes(plans, first, count);
+  for (int k = first; k < first + count; ++k) t += plans[k].total;
+  return t;
+}
+
+struct Wave {
+  std::vector<Plan2D> plans;   // of the wave's shots
+  std::vector<Shot2D> descs;   // host copies
+  std::vector<size_t> regions; // byte offset of each shot's region
+  Batch2D batch{};
+  int L = 1, nseg = 1, nt = 0;
+};
+
+efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::vector<Plan2D>& plans, int first,
+                       int count, const std::vector<ShotIO>& io, efwi_ws_kind kind, unsigned char* ws, Wave& wv,
+                       hipStream_t st) {
+  wv.plans.assign(plans.begin() + first, plans.begin() + first + count);
+  wv.nt = g.nt;
+  wv.L = wv.plans[0].L;
+  wv.nseg = wv.plans[0].nseg;
+  int ntiles = 0;
+  for (const Plan2D& p : wv.plans) ntiles += p.ntiles;
+  // header layout
+  const size_t off_desc = 0;
+  const size_t off_first = off_desc + align_up((size_t)count * sizeof(Shot2D));
+  const size_t off_tshot = off_first + align_up((size_t)count * sizeof(int));
+  size_t off_tab = off_tshot + align_up((size_t)ntiles * sizeof(int));
+  const size_t hdr = header_bytes(plans, first, count);
+  std::vector<unsigned char> blob(hdr, 0);
+  int* tfirst = reinterpret_cast<int*>(blob.data() + off_first);
+  int* tshot = reinterpret_cast<int*>(blob.data() + off_tshot);
+  size_t region = hdr;
+  int t = 0;
+  wv.descs.clear();
+  wv.regions.clear();
+  for (int k = 0; k < count; ++k) {
+    const Plan2D& p = wv.plans[k];
+    const efwi_shot& s = shots[first + k];
+    tfirst[k] = t;
+    for (int q = 0; q < p.ntiles; ++q) tshot[t++] = k;
+    build_tables(g, s, p, blob.data() + off_tab);
+    const float* tab_dev = reinterpret_cast<const float*>(ws + off_tab);
+    wv.descs.push_back(make_desc(g, s, p, ws + region, tab_dev, io[first + k]));
+    wv.regions.push_back(region);
+    off_tab += p.tab_bytes;
+    region += p.total;
+  }
+  std::memcpy(blob.data() + off_desc, wv.descs.data(), (size_t)count * sizeof(Shot2D));
+  wv.batch.shots = reinterpret_cast<const Shot2D*>(ws + off_desc);
+  wv.batch.tile_first = reinterpret_cast<const int*>(ws + off_first);
+  wv.batch.tile_shot = reinterpret_cast<const int*>(ws + off_tshot);
+  wv.batch.ns = count;
+  wv.batch.ntiles = ntiles;
+  // zero what must start at zero
+  const bool fwd = kind != EFWI_WS_ADJOINT;
+  const bool adj = kind != EFWI_WS_FORWARD;
+  const bool grad = kind == EFWI_WS_GRADIENT || kind == EFWI_WS_BATCH;
+  for (int k = 0; k < count; ++k) {
+    const Plan2D& p = wv.plans[k];
+    unsigned char* r = ws + wv.regions[k];
+    HIP_TRY(hipMemsetAsync(r + p.off_par, 0, p.par_bytes, st));
+    if (fwd) {
+      HIP_TRY(hipMemsetAsync(r + p.off_state, 0, p.state_bytes, st));
+      HIP_TRY(hipMemsetAsync(r + p.off_e, 0, (size_t)std::max(1, p.nch) * sizeof(float), st));
     }
-    float* seg = nullptr;
-    if (checkpoints && n >= last0) seg = d.seg + (size_t)(n - last0) * NSEG_FIELDS * p.cells;
-    HIP_TRY(TIMED(KK_FWD_VEL, st, launch_fwd_vel(d, n, seg, st)));
-    HIP_TRY(TIMED(KK_FWD_STR, st, launch_fwd_str(d, n, seg, true, st)));
+    if (adj) HIP_TRY(hipMemsetAsync(r + p.off_adj, 0, p.adj_bytes, st));
+    if (grad) HIP_TRY(hipMemsetAsync(r + p.off_G, 0, (size_t)3 * p.cells * sizeof(double), st));
+  }
+  HIP_TRY(staging().upload(ws, blob.data(), blob.size(), st));
+  HIP_TRY(launch_stage2d(wv.batch, st));
+  return EFWI_OK;
+}
+
+// Forward sweep of a wave. With `checkpoints`, the state block of every shot is copied at
+// the start of segments 1 .. nseg-2 (segment 0 starts from zero) and the last segment's
+// imaging quantities are kept from this sweep, so the reverse sweep need not recompute it.
+efwi_status run_forward(Wave& wv, unsigned char* ws, bool checkpoints, hipStream_t st) {
+  const int last0 = (wv.nseg - 1) * wv.L;
+  for (int n = 0; n < wv.nt; ++n) {
+    if (checkpoints && n % wv.L == 0 && n > 0 && n < last0) {
+      const int k = n / wv.L;
+      for (size_t q = 0; q < wv.plans.size(); ++q) {
+        const Plan2D& p = wv.plans[q];
+        unsigned char* r = ws + wv.regions[q];
+        HIP_TRY(hipMemcpyAsync(r + p.off_ckpt + (size_t)(k - 1) * p.state_bytes, r + p.off_state, p.state_bytes,
+                               hipMemcpyDeviceToDevice, st));
+      }
+    }
+    const int kstore = (checkpoints && n >= last0) ? n - last0 : -1;
+    HIP_TRY(TIMED(KK_FWD_VEL, st, launch_fwd_vel(wv.batch, kstore, st)));
+    HIP_TRY(TIMED(KK_FWD_STR, st, launch_fwd_str(wv.batch, n, kstore, true, st)));
   }
   return EFWI_OK;
 }
 
-efwi_status run_reverse(Shot2D& d, const Plan2D& p, unsigned char* ws, hipStream_t st) {
-  for (int k = p.nseg - 1; k >= 0; --k) {
-    const int n0 = k * p.L, n1 = std::min(p.nt, n0 + p.L);
-    if (k < p.nseg - 1) {
-      if (k == 0) HIP_TRY(hipMemsetAsync(ws + p.off_state, 0, p.state_bytes, st));
-      else
-        HIP_TRY(hipMemcpyAsync(ws + p.off_state, ws + p.off_ckpt + (size_t)(k - 1) * p.state_bytes, p.state_bytes,
-                               hipMemcpyDeviceToDevice, st));
+// Reverse sweep of a wave: segments last to first; each segment (but the last) is
+// recomputed from its checkpoint while storing the imaging quantities, then stepped back.
+efwi_status run_reverse(Wave& wv, unsigned char* ws, hipStream_t st) {
+  for (int k = wv.nseg - 1; k >= 0; --k) {
+    const int n0 = k * wv.L, n1 = std::min(wv.nt, n0 + wv.L);
+    if (k < wv.nseg - 1) {
+      for (size_t q = 0; q < wv.plans.size(); ++q) {
+        const Plan2D& p = wv.plans[q];
+        unsigned char* r = ws + wv.regions[q];
+        if (k == 0) HIP_TRY(hipMemsetAsync(r + p.off_state, 0, p.state_bytes, st));
+        else
+          HIP_TRY(hipMemcpyAsync(r + p.off_state, r + p.off_ckpt + (size_t)(k - 1) * p.state_bytes, p.state_bytes,
+                                 hipMemcpyDeviceToDevice, st));
+      }
       for (int n = n0; n < n1; ++n) {
-        float* seg = d.seg + (size_t)(n - n0) * NSEG_FIELDS * p.cells;
-        HIP_TRY(TIMED(KK_FWD_VEL, st, launch_fwd_vel(d, n, seg, st)));
-        HIP_TRY(TIMED(KK_FWD_STR, st, launch_fwd_str(d, n, seg, false, st)));
+        HIP_TRY(TIMED(KK_FWD_VEL, st, launch_fwd_vel(wv.batch, n - n0, st)));
+        HIP_TRY(TIMED(KK_FWD_STR, st, launch_fwd_str(wv.batch, n, n - n0, false, st)));
       }
     }
     // Imaging sums run in FP32 over blocks of FLUSH_STEPS steps aligned on absolute step
     // numbers and are then added into the FP64 gradient, so the result does not depend on
     // the checkpoint interval.
     for (int n = n1 - 1; n >= n0; --n) {
-      const float* seg = d.seg + (size_t)(n - n0) * NSEG_FIELDS * p.cells;
-      const bool first = (n == p.nt - 1) || ((n + 1) % FLUSH_STEPS == 0);
-      HIP_TRY(TIMED(KK_ADJ_VEL, st, launch_adj_vel(d, n, seg, true, first, false, st)));
-      HIP_TRY(TIMED(KK_ADJ_STR, st, launch_adj_str(d, n, seg, true, first, st)));
-      if (n % FLUSH_STEPS == 0) HIP_TRY(TIMED(KK_CHAIN, st, launch_chain_flush(d, st)));
+      const bool first = (n == wv.nt - 1) || ((n + 1) % FLUSH_STEPS == 0);
+      HIP_TRY(TIMED(KK_ADJ_VEL, st, launch_adj_vel(wv.batch, n, n - n0, true, first, false, st)));
+      HIP_TRY(TIMED(KK_ADJ_STR, st, launch_adj_str(wv.batch, n, n - n0, true, first, st)));
+      if (n % FLUSH_STEPS == 0) HIP_TRY(TIMED(KK_CHAIN, st, launch_chain_flush(wv.batch, st)));
     }
   }
   return EFWI_OK;
 }
 
-efwi_status shot_gradient_impl(const efwi_grid& g, const efwi_shot& s, const float* m, long mplane, const float* src,
-                               const float* d_obs, float* gout, double* phi, float* d_out, unsigned char* ws,
-                               size_t ws_bytes, hipStream_t st, bool zero_outside) {
-  const Plan2D p = plan2d(g, s, EFWI_WS_GRADIENT);
-  efwi_status rc = check_ws(ws, ws_bytes, p.total);
+// Split shots [0, ns) into waves that fit ws_bytes (all at once when possible).
+efwi_status plan_waves(const std::vector<Plan2D>& plans, size_t ws_bytes, std::vector<std::pair<int, int>>& waves) {
+  const int ns = (int)plans.size();
+  int first = 0;
+  while (first < ns) {
+    int count = 0;
+    while (first + count < ns && wave_bytes(plans, first, count + 1) <= ws_bytes) ++count;
+    if (count == 0)
+      return fail(EFWI_E_WORKSPACE, "workspace has %zu bytes; shot %d alone needs %zu", ws_bytes, first,
+                  wave_bytes(plans, first, 1));
+    waves.push_back({first, count});
+    first += count;
+  }
+  return EFWI_OK;
+}
+
+efwi_status gradient_waves(const efwi_grid& g, const efwi_shot* shots, int ns, const std::vector<ShotIO>& io,
+                           unsigned char* ws, size_t ws_bytes, hipStream_t st) {
+  std::vector<Plan2D> plans;
+  for (int k = 0; k < ns; ++k) plans.push_back(plan2d(g, shots[k], EFWI_WS_GRADIENT));
+  efwi_status rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
   if (rc != EFWI_OK) return rc;
-  Shot2D d = make_desc(g, s, p, ws, m, mplane);
-  d.src = src;
-  d.d = d_out ? d_out : reinterpret_cast<float*>(ws + p.off_dint);
-  rc = setup_shot(g, s, p, ws, d, true, true, true, st);
+  std::vector<std::pair<int, int>> waves;
+  rc = plan_waves(plans, ws_bytes, waves);
   if (rc != EFWI_OK) return rc;
-  rc = run_forward(d, p, ws, true, st);
-  if (rc != EFWI_OK) return rc;
-  HIP_TRY(TIMED(KK_MISFIT, st,
-                launch_misfit(d, d.d, d_obs, reinterpret_cast<double*>(ws + p.off_partial), phi,
-                              reinterpret_cast<float*>(ws + p.off_ebar), st)));
-  rc = run_reverse(d, p, ws, st);
-  if (rc != EFWI_OK) return rc;
-  const bool full = p.w.z0 == 0 && p.w.x0 == 0 && p.nz == g.nz && p.nx == g.nx;
-  if (zero_outside && !full) HIP_TRY(hipMemsetAsync(gout, 0, (size_t)3 * mplane * sizeof(float), st));
-  HIP_TRY(launch_write_gradient(d, gout, mplane, p.w.z0, p.w.x0, st));
+  for (auto [first, count] : waves) {
+    Wave wv;
+    rc = setup_wave(g, shots, plans, first, count, io, EFWI_WS_GRADIENT, ws, wv, st);
+    if (rc != EFWI_OK) return rc;
+    rc = run_forward(wv, ws, true, st);
+    if (rc != EFWI_OK) return rc;
+    for (int k = 0; k < count; ++k) {
+      const Shot2D& d = wv.descs[k];
+      unsigned char* r = ws + wv.regions[k];
+      const Plan2D& p = wv.plans[k];
+      HIP_TRY(TIMED(KK_MISFIT, st,
+                    launch_misfit(d, (const float*)(d.d), io[first + k].dobs, reinterpret_cast<double*>(r + p.off_partial),
+                                  io[first + k].phi, reinterpret_cast<float*>(r + p.off_ebar), st)));
+    }
+    rc = run_reverse(wv, ws, st);
+    if (rc != EFWI_OK) return rc;
+    for (int k = 0; k < count; ++k) {
+      const Plan2D& p = wv.plans[k];
+      const bool full = p.w.z0 == 0 && p.w.x0 == 0 && p.nz == g.nz && p.nx == g.nx;
+      if (!full) HIP_TRY(hipMemsetAsync(io[first + k].gout, 0, (size_t)3 * io[first + k].mplane * sizeof(float), st));
+    }
+    HIP_TRY(launch_write_gradient(wv.batch, st));
+  }
+  return EFWI_OK;
+}
+
+efwi_status check_same_schedule(const efwi_grid& g, int ns, const efwi_shot* shots) {
+  for (int k = 1; k < ns; ++k) {
+    if (interval_of(g, shots[k]) != interval_of(g, shots[0]) || shots[k].ckpt_mode != shots[0].ckpt_mode)
+      return fail(EFWI_E_INVAL, "shots of one batch must share ckpt_interval and ckpt_mode");
+  }
   return EFWI_OK;
 }
 
@@ -616,13 +731,11 @@ size_t efwi_workspace_size(efwi_ws_kind kind, const efwi_grid* grid, int ns, con
     const long npts = (long)grid->nz * grid->nx;
     return align_up((size_t)regularizer_blocks(npts) * sizeof(double));
   }
-  if (efwi_validate(grid, kind == EFWI_WS_BATCH ? ns : 1, shots) != EFWI_OK) return 0;
-  if (kind == EFWI_WS_BATCH) {
-    size_t mx = 0;
-    for (int k = 0; k < ns; ++k) mx = std::max(mx, plan2d(*grid, shots[k], kind).total);
-    return mx;
-  }
-  return plan2d(*grid, *shots, kind).total;
+  const int n = kind == EFWI_WS_BATCH ? ns : 1;
+  if (efwi_validate(grid, n, shots) != EFWI_OK) return 0;
+  std::vector<Plan2D> plans;
+  for (int k = 0; k < n; ++k) plans.push_back(plan2d(*grid, shots[k], kind));
+  return wave_bytes(plans, 0, n);
 }
 
 efwi_status efwi_model_forward(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* src,
@@ -631,16 +744,19 @@ efwi_status efwi_model_forward(const efwi_grid* grid, const efwi_shot* shot, con
   if (rc != EFWI_OK) return rc;
   if (!m || !src || (shot->nch > 0 && !d)) return fail(EFWI_E_INVAL, "NULL array argument");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const Plan2D p = plan2d(*grid, *shot, EFWI_WS_FORWARD);
-  rc = check_ws(ws, ws_bytes, p.total);
+  std::vector<Plan2D> plans{plan2d(*grid, *shot, EFWI_WS_FORWARD)};
+  rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
   if (rc != EFWI_OK) return rc;
   unsigned char* w = static_cast<unsigned char*>(ws);
-  Shot2D dd = make_desc(*grid, *shot, p, w, m, (long)grid->nz * grid->nx);
-  dd.src = src;
-  dd.d = d;
-  rc = setup_shot(*grid, *shot, p, w, dd, true, false, false, st);
+  ShotIO io;
+  io.m = m;
+  io.mplane = (long)grid->nz * grid->nx;
+  io.src = src;
+  io.d = d;
+  Wave wv;
+  rc = setup_wave(*grid, shot, plans, 0, 1, {io}, EFWI_WS_FORWARD, w, wv, st);
   if (rc != EFWI_OK) return rc;
-  return run_forward(dd, p, w, false, st);
+  return run_forward(wv, w, false, st);
 }
 
 efwi_status efwi_model_adjoint(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* r,
@@ -649,18 +765,22 @@ efwi_status efwi_model_adjoint(const efwi_grid* grid, const efwi_shot* shot, con
   if (rc != EFWI_OK) return rc;
   if (!m || !src_bar || (shot->nch > 0 && !r)) return fail(EFWI_E_INVAL, "NULL array argument");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const Plan2D p = plan2d(*grid, *shot, EFWI_WS_ADJOINT);
-  rc = check_ws(ws, ws_bytes, p.total);
+  std::vector<Plan2D> plans{plan2d(*grid, *shot, EFWI_WS_ADJOINT)};
+  rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
   if (rc != EFWI_OK) return rc;
   unsigned char* w = static_cast<unsigned char*>(ws);
-  Shot2D dd = make_desc(*grid, *shot, p, w, m, (long)grid->nz * grid->nx);
-  dd.src_bar = src_bar;
-  rc = setup_shot(*grid, *shot, p, w, dd, false, true, false, st);
+  ShotIO io;
+  io.m = m;
+  io.mplane = (long)grid->nz * grid->nx;
+  io.src_bar = src_bar;
+  Wave wv;
+  rc = setup_wave(*grid, shot, plans, 0, 1, {io}, EFWI_WS_ADJOINT, w, wv, st);
   if (rc != EFWI_OK) return rc;
-  HIP_TRY(launch_residual_cumsum(dd, r, reinterpret_cast<float*>(w + p.off_ebar), st));
+  const Plan2D& p = wv.plans[0];
+  HIP_TRY(launch_residual_cumsum(wv.descs[0], r, reinterpret_cast<float*>(w + wv.regions[0] + p.off_ebar), st));
   for (int n = p.nt - 1; n >= 0; --n) {
-    HIP_TRY(launch_adj_vel(dd, n, nullptr, false, false, true, st));
-    HIP_TRY(launch_adj_str(dd, n, nullptr, false, false, st));
+    HIP_TRY(TIMED(KK_ADJ_VEL, st, launch_adj_vel(wv.batch, n, 0, false, false, true, st)));
+    HIP_TRY(TIMED(KK_ADJ_STR, st, launch_adj_str(wv.batch, n, 0, false, false, st)));
   }
   return EFWI_OK;
 }
@@ -672,8 +792,16 @@ efwi_status efwi_shot_gradient(const efwi_grid* grid, const efwi_shot* shot, con
   if (rc != EFWI_OK) return rc;
   if (shot->ckpt_mode != EFWI_CKPT_FP32) return fail(EFWI_E_UNSUPPORTED, "16-bit checkpoints not built yet");
   if (!m || !src || !g || !phi || (shot->nch > 0 && !d_obs)) return fail(EFWI_E_INVAL, "NULL array argument");
-  return shot_gradient_impl(*grid, *shot, m, (long)grid->nz * grid->nx, src, d_obs, g, phi, d_out,
-                            static_cast<unsigned char*>(ws), ws_bytes, reinterpret_cast<hipStream_t>(stream), true);
+  ShotIO io;
+  io.m = m;
+  io.mplane = (long)grid->nz * grid->nx;
+  io.src = src;
+  io.dobs = d_obs;
+  io.d = d_out;
+  io.gout = g;
+  io.phi = phi;
+  return gradient_waves(*grid, shot, 1, {io}, static_cast<unsigned char*>(ws), ws_bytes,
+                        reinterpret_cast<hipStream_t>(stream));
 }
 
 efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* shots, const float* m_ext,
@@ -683,18 +811,24 @@ efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* 
   if (rc != EFWI_OK) return rc;
   if (ns < 1) return fail(EFWI_E_INVAL, "ns must be >= 1");
   if (!m_ext || !src || !g_ext || !phi) return fail(EFWI_E_INVAL, "NULL array argument");
+  rc = check_same_schedule(*grid, ns, shots);
+  if (rc != EFWI_OK) return rc;
   const long plane = (long)grid->nz * grid->nx;
+  std::vector<ShotIO> io(ns);
   size_t off_obs = 0;
   for (int s = 0; s < ns; ++s) {
     if (shots[s].ckpt_mode != EFWI_CKPT_FP32) return fail(EFWI_E_UNSUPPORTED, "16-bit checkpoints not built yet");
     if (shots[s].nch > 0 && !d_obs) return fail(EFWI_E_INVAL, "d_obs is NULL");
-    rc = shot_gradient_impl(*grid, shots[s], m_ext + (size_t)s * 3 * plane, plane, src + (size_t)s * 3 * grid->nt,
-                            d_obs ? d_obs + off_obs : nullptr, g_ext + (size_t)s * 3 * plane, phi + s, nullptr,
-                            static_cast<unsigned char*>(ws), ws_bytes, reinterpret_cast<hipStream_t>(stream), true);
-    if (rc != EFWI_OK) return rc;
+    io[s].m = m_ext + (size_t)s * 3 * plane;
+    io[s].mplane = plane;
+    io[s].src = src + (size_t)s * 3 * grid->nt;
+    io[s].dobs = d_obs ? d_obs + off_obs : nullptr;
+    io[s].gout = g_ext + (size_t)s * 3 * plane;
+    io[s].phi = phi + s;
     off_obs += (size_t)shots[s].nch * grid->nt;
   }
-  return EFWI_OK;
+  return gradient_waves(*grid, shots, ns, io, static_cast<unsigned char*>(ws), ws_bytes,
+                        reinterpret_cast<hipStream_t>(stream));
 }
 
 efwi_status efwi_extension_regularizer(const efwi_grid* grid, int ns, const float* m_ext, const float* b,

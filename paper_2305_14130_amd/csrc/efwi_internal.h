@@ -32,6 +32,13 @@ constexpr int NACC = 5;
 // Time steps summed in FP32 before the imaging sums are chained into the FP64 gradient.
 constexpr int FLUSH_STEPS = 32;
 
+// Device pointers in the global address space. Kernels read each shot's descriptor from a
+// device array; typing its pointer members as global keeps every access a global_load /
+// global_store instead of a generic flat access.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) int gint;
+typedef __attribute__((address_space(1))) double gdouble;
+
 // Everything a 2D kernel needs about one shot. Pointers to padded arrays point at the
 // interior origin (i = 0, j = 0); element (i, j) is at p[i * ld + j].
 struct Shot2D {
@@ -42,35 +49,48 @@ struct Shot2D {
   int cp;                       // row pitch of the unpadded per-cell arrays
   long cells;                   // nz * cp
   // forward state
-  float *vx, *vz, *sxx, *szz, *sxz;
-  float* psx[4];                // x-strip memory variables [nz][2P]: VXX, VZX, XX, XZ
-  float* psz[4];                // z-strip memory variables [2P][nx]: VXZ, VZZ, ZZ, XZ
+  gfloat *vx, *vz, *sxx, *szz, *sxz;
+  gfloat* psx[4];                // x-strip memory variables [nz][2P]: VXX, VZX, XX, XZ
+  gfloat* psz[4];                // z-strip memory variables [2P][nx]: VXZ, VZZ, ZZ, XZ
   // adjoint state in scaled variables: u_bar = b v_bar at the velocity nodes and
   // t_bar = C sigma_bar at the stress nodes (t_xx = (l+2m) s_xx + l s_zz, t_zz = l s_xx +
   // (l+2m) s_zz, t_xz = mu_xz s_xz), an invertible change of variables for Vs > 0
-  float *uxb, *uzb, *txxb, *tzzb, *txzb;
-  float* pbx[2][4];             // double-buffered x-strip adjoint memory variables
-  float* pbz[2][4];             // double-buffered z-strip adjoint memory variables
+  gfloat *uxb, *uzb, *txxb, *tzzb, *txzb;
+  gfloat* pbx[2][4];             // double-buffered x-strip adjoint memory variables
+  gfloat* pbz[2][4];             // double-buffered z-strip adjoint memory variables
   // staged parameters (padded, zero halo)
-  float *l2m, *lam, *muxz, *bx, *bz;
+  gfloat *l2m, *lam, *muxz, *bx, *bz;
   // CPML profiles: axi bxi axh bxh [nx] then azi bzi azh bzh [nz]
-  const float* prof;
+  const gfloat* prof;
   // source
-  const float* src;             // [3][nt]
-  float* src_bar;               // [3][nt] (adjoint only)
+  const gfloat* src;             // [3][nt]
+  gfloat* src_bar;               // [3][nt] (adjoint only)
   // DAS
-  const int* row_slot;          // [nz]: slot of the row in rowch, or -1
-  const int* rowch;             // [nslots][nx]: channel id at normal node, or -1
-  float* e;                     // [nch] running strain
-  float* d;                     // [nch][nt]
-  const float* ebar;            // [nt][nch] reverse cumulative residual
+  const gint* row_slot;          // [nz]: slot of the row in rowch, or -1
+  const gint* rowch;             // [nslots][nx]: channel id at normal node, or -1
+  gfloat* e;                     // [nch] running strain
+  gfloat* d;                     // [nch][nt]
+  const gfloat* ebar;            // [nt][nch] reverse cumulative residual
   // model window (unpadded, full-model pitch) for the chain rule
-  const float *mvp, *mvs, *mrho;
+  const gfloat *mvp, *mvs, *mrho;
   long mld;
   // imaging
-  float* seg;                   // [L][5][cells]
-  float* acc;                   // [5][cells]
-  double* G;                    // [3][cells]
+  gfloat* seg;                   // [L][5][cells]
+  gfloat* acc;                   // [5][cells]
+  gdouble* G;                    // [3][cells]
+  // gradient output: slot of the extended gradient, full-model plane size, window origin
+  gfloat* gout;
+  long mplane;
+  int z0, x0;
+};
+
+// A batch of shots advanced together: device descriptors and the flat tile list (tiles of
+// shot s are tile_first[s] .. tile_first[s] + tiles(s) - 1; tile_shot maps tile -> shot).
+struct Batch2D {
+  const Shot2D* shots;
+  const int* tile_shot;
+  const int* tile_first;
+  int ns, ntiles;
 };
 
 // Strip index helpers (x: column j of width nx; z: row i of height nz).
@@ -82,16 +102,15 @@ __host__ __device__ inline int strip_index(int k, int n, int P) {
 }
 
 // Kernel launchers (kernels2d.hip). All enqueue on `st` and return hipGetLastError().
-hipError_t launch_stage2d(const Shot2D& s, hipStream_t st);
-hipError_t launch_fwd_vel(const Shot2D& s, int n, float* seg_step, hipStream_t st);
-hipError_t launch_fwd_str(const Shot2D& s, int n, float* seg_step, bool record, hipStream_t st);
-hipError_t launch_adj_vel(const Shot2D& s, int n, const float* seg_step, bool grad, bool first,
-                          bool srcadj, hipStream_t st);
-hipError_t launch_adj_str(const Shot2D& s, int n, const float* seg_step, bool grad, bool first,
-                          hipStream_t st);
-hipError_t launch_chain_flush(const Shot2D& s, hipStream_t st);
-hipError_t launch_write_gradient(const Shot2D& s, float* g, long mplane, int z0, int x0,
-                                 hipStream_t st);
+// `kstore` / `k` index the step inside the checkpoint segment buffer (-1: do not store).
+hipError_t launch_stage2d(const Batch2D& b, hipStream_t st);
+hipError_t launch_fwd_vel(const Batch2D& b, int kstore, hipStream_t st);
+hipError_t launch_fwd_str(const Batch2D& b, int n, int kstore, bool record, hipStream_t st);
+hipError_t launch_adj_vel(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st);
+hipError_t launch_adj_str(const Batch2D& b, int n, int k, bool grad, bool first, hipStream_t st);
+hipError_t launch_chain_flush(const Batch2D& b, hipStream_t st);
+hipError_t launch_write_gradient(const Batch2D& b, hipStream_t st);
+// Per-shot (host copy of the shot's descriptor).
 hipError_t launch_misfit(const Shot2D& s, const float* d, const float* dobs, double* partial,
                          double* phi, float* ebar, hipStream_t st);
 hipError_t launch_residual_cumsum(const Shot2D& s, const float* r, float* ebar, hipStream_t st);

@@ -29,40 +29,55 @@ constexpr int X_VXX = 0, X_VZX = 1, X_XX = 2, X_XZ = 3;
 // z-strips
 constexpr int Z_VXZ = 0, Z_VZZ = 1, Z_ZZ = 2, Z_XZ = 3;
 
-__device__ __forceinline__ const float* axi(const Shot2D& s) { return s.prof; }
-__device__ __forceinline__ const float* bxi(const Shot2D& s) { return s.prof + s.nx; }
-__device__ __forceinline__ const float* axh(const Shot2D& s) { return s.prof + 2 * s.nx; }
-__device__ __forceinline__ const float* bxh(const Shot2D& s) { return s.prof + 3 * s.nx; }
-__device__ __forceinline__ const float* azi(const Shot2D& s) { return s.prof + 4 * s.nx; }
-__device__ __forceinline__ const float* bzi(const Shot2D& s) { return s.prof + 4 * s.nx + s.nz; }
-__device__ __forceinline__ const float* azh(const Shot2D& s) { return s.prof + 4 * s.nx + 2 * s.nz; }
-__device__ __forceinline__ const float* bzh(const Shot2D& s) { return s.prof + 4 * s.nx + 3 * s.nz; }
+__device__ __forceinline__ const gfloat* axi(const Shot2D& s) { return s.prof; }
+__device__ __forceinline__ const gfloat* bxi(const Shot2D& s) { return s.prof + s.nx; }
+__device__ __forceinline__ const gfloat* axh(const Shot2D& s) { return s.prof + 2 * s.nx; }
+__device__ __forceinline__ const gfloat* bxh(const Shot2D& s) { return s.prof + 3 * s.nx; }
+__device__ __forceinline__ const gfloat* azi(const Shot2D& s) { return s.prof + 4 * s.nx; }
+__device__ __forceinline__ const gfloat* bzi(const Shot2D& s) { return s.prof + 4 * s.nx + s.nz; }
+__device__ __forceinline__ const gfloat* azh(const Shot2D& s) { return s.prof + 4 * s.nx + 2 * s.nz; }
+__device__ __forceinline__ const gfloat* bzh(const Shot2D& s) { return s.prof + 4 * s.nx + 3 * s.nz; }
 
 // Forward D+ at the half node after index k, and D- at integer node k (array index k holds
 // the half node k+1/2); `st` is the element stride along the axis.
-__device__ __forceinline__ float dplus(const float* f, long o, long st, float r) {
+template <class P>
+__device__ __forceinline__ float dplus(P f, long o, long st, float r) {
   return (K1 * (f[o + st] - f[o]) + K2 * (f[o + 2 * st] - f[o - st])) * r;
 }
-__device__ __forceinline__ float dminus(const float* f, long o, long st, float r) {
+template <class P>
+__device__ __forceinline__ float dminus(P f, long o, long st, float r) {
   return (K1 * (f[o] - f[o - st]) + K2 * (f[o + st] - f[o - 2 * st])) * r;
 }
 
-// XCD-aware tile order. The hardware deals workgroup w to XCD (w mod 8), so workgroup w
-// takes tile (w mod 8) * chunk + w / 8: each XCD walks one contiguous run of tiles (whole
-// row bands, x fastest) and the z-halo rows its stencils re-read are still in its own L2.
-// Returns false for the padding workgroups of the last chunk.
+// Work decomposition. A launch covers the tiles of every shot of a batch: tiles are listed
+// shot by shot, row band by row band (x fastest), and `tile_first[s]` is shot s's first
+// tile. The hardware deals workgroup w to XCD (w mod 8), so workgroup w takes tile
+// (w mod 8) * chunk + w / 8: each XCD walks one contiguous run of the list, and the
+// z-halo rows its stencils re-read are still in its own L2. The padding workgroups of the
+// last chunk return at once.
 constexpr int NXCD = 8;
-__device__ __forceinline__ bool tile_of(int nz, int nx, int& i0, int& j0) {
-  const int ntx = (nx + BX - 1) / BX, ntz = (nz + BZ - 1) / BZ;
-  const int ntiles = ntx * ntz;
+__device__ __forceinline__ bool batch_tile(const int* __restrict__ tile_shot, const int* __restrict__ tile_first,
+                                           const Shot2D* __restrict__ shots, int ntiles, int& sh, int& i0,
+                                           int& j0) {
   const int chunk = (ntiles + NXCD - 1) / NXCD;
   const int w = blockIdx.x;
   const int t = (w % NXCD) * chunk + w / NXCD;
   if (t >= ntiles) return false;
-  i0 = (t / ntx) * BZ;
-  j0 = (t % ntx) * BX;
+  sh = tile_shot[t];
+  const int local = t - tile_first[sh];
+  const int ntx = (shots[sh].nx + BX - 1) / BX;
+  i0 = (local / ntx) * BZ;
+  j0 = (local % ntx) * BX;
   return true;
 }
+
+#define BATCH_PARAMS                                                                           \
+  const Shot2D* __restrict__ shots, const int* __restrict__ tile_shot, const int* __restrict__ tile_first, \
+      int ntiles
+#define BATCH_TILE()                                                                           \
+  int sh_, i0, j0;                                                                              \
+  if (!batch_tile(tile_shot, tile_first, shots, ntiles, sh_, i0, j0)) return;                  \
+  const Shot2D& s = shots[sh_]
 
 // Does the block touch a CPML strip (with `pad` extra cells of neighbourhood)?
 __device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, int pad) {
@@ -75,7 +90,7 @@ __device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, in
 // Forward velocity half step: v^{n+1/2} = v^{n-1/2} + dt b (div sigma^n), CPML in strips.
 // ------------------------------------------------------------------------------------
 template <bool STORE, bool PML>
-__device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, float* seg) {
+__device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, gfloat* seg) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   float d1 = dplus(s.sxx, o, 1, s.rdx);    // D+x sxx at (i, j+1/2)
@@ -115,10 +130,10 @@ __device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, floa
 }
 
 template <bool STORE>
-__global__ __launch_bounds__(BX * BZ) void k_fwd_vel(const Shot2D s, float* seg) {
-  int i0, j0;
-  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+__global__ __launch_bounds__(BX * BZ) void k_fwd_vel(BATCH_PARAMS, int kstore) {
+  BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG_FIELDS * s.cells : nullptr;
   if (i >= s.nz || j >= s.nx) return;
   if (block_in_pml(s, j0, i0, 0)) fwd_vel_cell<STORE, true>(s, i, j, seg);
   else fwd_vel_cell<STORE, false>(s, i, j, seg);
@@ -129,7 +144,7 @@ __global__ __launch_bounds__(BX * BZ) void k_fwd_vel(const Shot2D s, float* seg)
 // moment-tensor injection at t_{n+1/2}, DAS strain record.
 // ------------------------------------------------------------------------------------
 template <bool STORE, bool RECORD, bool PML>
-__device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int n, float* seg) {
+__device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int n, gfloat* seg) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   float pxx = dminus(s.vx, o, 1, s.rdx);   // D-x vx at (i, j)
@@ -193,10 +208,10 @@ __device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int 
 }
 
 template <bool STORE, bool RECORD>
-__global__ __launch_bounds__(BX * BZ) void k_fwd_str(const Shot2D s, int n, float* seg) {
-  int i0, j0;
-  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+__global__ __launch_bounds__(BX * BZ) void k_fwd_str(BATCH_PARAMS, int n, int kstore) {
+  BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG_FIELDS * s.cells : nullptr;
   if (i >= s.nz || j >= s.nx) return;
   if (block_in_pml(s, j0, i0, 0)) fwd_str_cell<STORE, RECORD, true>(s, i, j, n, seg);
   else fwd_str_cell<STORE, RECORD, false>(s, i, j, n, seg);
@@ -226,28 +241,27 @@ __global__ __launch_bounds__(BX * BZ) void k_fwd_str(const Shot2D s, int n, floa
 template <bool PML>
 struct AdjCtx {
   const Shot2D& s;
-  const float* const* px;   // x-strip adjoint memory variables, previous (read) buffer
-  const float* const* pz;   // z-strip, previous buffer
+  int rd;                   // which buffer of the adjoint memory variables holds step n+1
 };
 
 // Corrected transposed operands at node (ii, jj); `a` is the profile coefficient for the
 // node's coordinate along the derivative's axis and `psi` the matching adjoint memory
 // variable, used only inside the CPML strips.
 template <bool PML>
-__device__ __forceinline__ float corr_x(const AdjCtx<PML>& c, float v, int ii, int jj, const float* aprof, int slot) {
+__device__ __forceinline__ float corr_x(const AdjCtx<PML>& c, float v, int ii, int jj, const gfloat* aprof, int slot) {
   const Shot2D& s = c.s;
   if (PML && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
     const int sx = strip_index(jj, s.nx, s.P);
-    if (sx >= 0) v += aprof[jj] * (c.px[slot][(long)ii * 2 * s.P + sx] + v);
+    if (sx >= 0) v += aprof[jj] * (s.pbx[c.rd][slot][(long)ii * 2 * s.P + sx] + v);
   }
   return v;
 }
 template <bool PML>
-__device__ __forceinline__ float corr_z(const AdjCtx<PML>& c, float v, int ii, int jj, const float* aprof, int slot) {
+__device__ __forceinline__ float corr_z(const AdjCtx<PML>& c, float v, int ii, int jj, const gfloat* aprof, int slot) {
   const Shot2D& s = c.s;
   if (PML && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
     const int sz = strip_index(ii, s.nz, s.P);
-    if (sz >= 0) v += aprof[ii] * (c.pz[slot][(long)sz * s.nx + jj] + v);
+    if (sz >= 0) v += aprof[ii] * (s.pbz[c.rd][slot][(long)sz * s.nx + jj] + v);
   }
   return v;
 }
@@ -294,18 +308,18 @@ __device__ __forceinline__ float ebar_at(const Shot2D& s, int slot, int jc, int 
   return c >= 0 ? s.ebar[(long)n * s.nch + c] : 0.0f;
 }
 
-__device__ __forceinline__ void accumulate(float* acc, long idx, float v, bool first) {
+__device__ __forceinline__ void accumulate(gfloat* acc, long idx, float v, bool first) {
   if (first) acc[idx] = v;
   else acc[idx] += v;
 }
 
 // Transposed stress sub-step (first at reverse step n): t_bar -> u_bar.
 template <bool GRAD, bool SRCADJ, bool PML>
-__device__ __forceinline__ void adj_vel_cell(const Shot2D& s, int i, int j, int n, const float* seg, bool first) {
+__device__ __forceinline__ void adj_vel_cell(const Shot2D& s, int i, int j, int n, const gfloat* seg, bool first) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  const AdjCtx<PML> c{s, s.pbx[rd], s.pbz[rd]};
+  const AdjCtx<PML> c{s, rd};
   // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx); v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
   const float ux = K1 * (pb_xx(c, i, j + 1) - pb_xx(c, i, j)) + K2 * (pb_xx(c, i, j + 2) - pb_xx(c, i, j - 1));
   const float uz = K1 * (pb_zx(c, i, j) - pb_zx(c, i - 1, j)) + K2 * (pb_zx(c, i + 1, j) - pb_zx(c, i - 2, j));
@@ -358,10 +372,10 @@ __device__ __forceinline__ void adj_vel_cell(const Shot2D& s, int i, int j, int 
 }
 
 template <bool GRAD, bool SRCADJ>
-__global__ __launch_bounds__(BX * BZ) void k_adj_vel(const Shot2D s, int n, const float* seg, int first) {
-  int i0, j0;
-  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+__global__ __launch_bounds__(BX * BZ) void k_adj_vel(BATCH_PARAMS, int n, int k, int first) {
+  BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
   if (i >= s.nz || j >= s.nx) return;
   if (block_in_pml(s, j0, i0, 2)) adj_vel_cell<GRAD, SRCADJ, true>(s, i, j, n, seg, first != 0);
   else adj_vel_cell<GRAD, SRCADJ, false>(s, i, j, n, seg, first != 0);
@@ -369,11 +383,11 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_vel(const Shot2D s, int n, cons
 
 // Transposed velocity sub-step (second at reverse step n): u_bar -> t_bar.
 template <bool GRAD, bool PML>
-__device__ __forceinline__ void adj_str_cell(const Shot2D& s, int i, int j, int n, const float* seg, bool first) {
+__device__ __forceinline__ void adj_str_cell(const Shot2D& s, int i, int j, int n, const gfloat* seg, bool first) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  const AdjCtx<PML> c{s, s.pbx[rd], s.pbz[rd]};
+  const AdjCtx<PML> c{s, rd};
   // sigma_bar_xx += -D-x q_bar_xa ; sigma_bar_zz += -D-z q_bar_zb ;
   // sigma_bar_xz += -(D+z q_bar_xb + D+x q_bar_za)
   const float txx = K1 * (qb_xa(c, i, j) - qb_xa(c, i, j - 1)) + K2 * (qb_xa(c, i, j + 1) - qb_xa(c, i, j - 2));
@@ -408,10 +422,10 @@ __device__ __forceinline__ void adj_str_cell(const Shot2D& s, int i, int j, int 
 }
 
 template <bool GRAD>
-__global__ __launch_bounds__(BX * BZ) void k_adj_str(const Shot2D s, int n, const float* seg, int first) {
-  int i0, j0;
-  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+__global__ __launch_bounds__(BX * BZ) void k_adj_str(BATCH_PARAMS, int n, int k, int first) {
+  BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
   if (i >= s.nz || j >= s.nx) return;
   if (block_in_pml(s, j0, i0, 2)) adj_str_cell<GRAD, true>(s, i, j, n, seg, first != 0);
   else adj_str_cell<GRAD, false>(s, i, j, n, seg, first != 0);
@@ -420,13 +434,12 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_str(const Shot2D s, int n, cons
 // ------------------------------------------------------------------------------------
 // Staging: (Vp, Vs, rho) of the window -> lambda + 2 mu, lambda, harmonic mu_xz, b_x, b_z.
 // ------------------------------------------------------------------------------------
-__global__ void k_stage(const Shot2D s) {
-  int i0, j0;
-  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+__global__ __launch_bounds__(BX * BZ) void k_stage(BATCH_PARAMS) {
+  BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   if (i >= s.nz || j >= s.nx) return;
   const int ip = min(i + 1, s.nz - 1), jp = min(j + 1, s.nx - 1);
-  auto at = [&](const float* f, int a, int b) { return f[(long)a * s.mld + b]; };
+  auto at = [&](const gfloat* f, int a, int b) { return f[(long)a * s.mld + b]; };
   const float vp = at(s.mvp, i, j), vs = at(s.mvs, i, j), rho = at(s.mrho, i, j);
   auto mu_at = [&](int a, int b) {
     const float v = at(s.mvs, a, b);
@@ -451,20 +464,19 @@ __global__ void k_stage(const Shot2D s) {
 // d mu_xz / d mu_k = mu_xz^2 / (4 mu_k^2) over its four clamped corners; d b / d rho = -b^2/2
 // on both (clamped) nodes of the average; lambda = rho(Vp^2 - 2Vs^2), mu = rho Vs^2.
 // ------------------------------------------------------------------------------------
-__global__ void k_chain_flush(const Shot2D s) {
-  int i0, j0;
-  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+__global__ __launch_bounds__(BX * BZ) void k_chain_flush(BATCH_PARAMS) {
+  BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   if (i >= s.nz || j >= s.nx) return;
   const long cc = (long)i * s.cp + j;
   const long mo = (long)i * s.mld + j;
   const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
   const float mu = rho * vs * vs;
-  const float* glam = s.acc;
-  const float* gdmu = s.acc + s.cells;        // g_mu - g_lambda
-  const float* gmuxz = s.acc + 2 * s.cells;
-  const float* gbx = s.acc + 3 * s.cells;
-  const float* gbz = s.acc + 4 * s.cells;
+  const gfloat* glam = s.acc;
+  const gfloat* gdmu = s.acc + s.cells;        // g_mu - g_lambda
+  const gfloat* gmuxz = s.acc + 2 * s.cells;
+  const gfloat* gbx = s.acc + 3 * s.cells;
+  const gfloat* gbz = s.acc + 4 * s.cells;
   double gmu_tot = (double)glam[cc] + (double)gdmu[cc];
   for (int di = -1; di <= 0; ++di) {
     for (int dj = -1; dj <= 0; ++dj) {
@@ -504,9 +516,11 @@ __global__ void k_chain_flush(const Shot2D s) {
   s.G[2 * s.cells + cc] += (dvp * dvp - 2.0 * dvs * dvs) * gl + dvs * dvs * gmu_tot + grho_b;
 }
 
-__global__ void k_write_gradient(const Shot2D s, float* g, long mplane, int z0, int x0) {
-  int i0, j0;
-  if (!tile_of(s.nz, s.nx, i0, j0)) return;
+__global__ __launch_bounds__(BX * BZ) void k_write_gradient(BATCH_PARAMS) {
+  BATCH_TILE();
+  gfloat* g = s.gout;
+  const long mplane = s.mplane;
+  const int z0 = s.z0, x0 = s.x0;
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   if (i >= s.nz || j >= s.nx) return;
   const long cc = (long)i * s.cp + j;
@@ -546,58 +560,54 @@ __global__ void k_reduce_phi(const double* partial, int n, double* phi) {
   if (threadIdx.x == 0) *phi = 0.5 * sh[0];
 }
 
-inline dim3 grid2d(const Shot2D& s) {
-  const int ntiles = ((s.nx + BX - 1) / BX) * ((s.nz + BZ - 1) / BZ);
-  return dim3(NXCD * ((ntiles + NXCD - 1) / NXCD));
-}
+inline dim3 grid_of(const Batch2D& b) { return dim3(NXCD * ((b.ntiles + NXCD - 1) / NXCD)); }
 inline dim3 block2d() { return dim3(BX, BZ); }
+#define BATCH_ARGS b.shots, b.tile_shot, b.tile_first, b.ntiles
 
 }  // namespace
 
-hipError_t launch_stage2d(const Shot2D& s, hipStream_t st) {
-  k_stage<<<grid2d(s), block2d(), 0, st>>>(s);
+hipError_t launch_stage2d(const Batch2D& b, hipStream_t st) {
+  k_stage<<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS);
   return hipGetLastError();
 }
 
-hipError_t launch_fwd_vel(const Shot2D& s, int n, float* seg, hipStream_t st) {
-  (void)n;
-  if (seg) k_fwd_vel<true><<<grid2d(s), block2d(), 0, st>>>(s, seg);
-  else k_fwd_vel<false><<<grid2d(s), block2d(), 0, st>>>(s, nullptr);
+hipError_t launch_fwd_vel(const Batch2D& b, int kstore, hipStream_t st) {
+  if (kstore >= 0) k_fwd_vel<true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, kstore);
+  else k_fwd_vel<false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_fwd_str(const Shot2D& s, int n, float* seg, bool record, hipStream_t st) {
-  if (seg) {
-    if (record) k_fwd_str<true, true><<<grid2d(s), block2d(), 0, st>>>(s, n, seg);
-    else k_fwd_str<true, false><<<grid2d(s), block2d(), 0, st>>>(s, n, seg);
+hipError_t launch_fwd_str(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
+  if (kstore >= 0) {
+    if (record) k_fwd_str<true, true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, kstore);
+    else k_fwd_str<true, false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, kstore);
   } else {
-    if (record) k_fwd_str<false, true><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr);
-    else k_fwd_str<false, false><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr);
+    if (record) k_fwd_str<false, true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0);
+    else k_fwd_str<false, false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_adj_vel(const Shot2D& s, int n, const float* seg, bool grad, bool first, bool srcadj,
-                          hipStream_t st) {
-  if (grad) k_adj_vel<true, false><<<grid2d(s), block2d(), 0, st>>>(s, n, seg, first);
-  else if (srcadj) k_adj_vel<false, true><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr, 0);
-  else k_adj_vel<false, false><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr, 0);
+hipError_t launch_adj_vel(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
+  if (grad) k_adj_vel<true, false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, k, first);
+  else if (srcadj) k_adj_vel<false, true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0, 0);
+  else k_adj_vel<false, false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_adj_str(const Shot2D& s, int n, const float* seg, bool grad, bool first, hipStream_t st) {
-  if (grad) k_adj_str<true><<<grid2d(s), block2d(), 0, st>>>(s, n, seg, first);
-  else k_adj_str<false><<<grid2d(s), block2d(), 0, st>>>(s, n, nullptr, 0);
+hipError_t launch_adj_str(const Batch2D& b, int n, int k, bool grad, bool first, hipStream_t st) {
+  if (grad) k_adj_str<true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, k, first);
+  else k_adj_str<false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_chain_flush(const Shot2D& s, hipStream_t st) {
-  k_chain_flush<<<grid2d(s), block2d(), 0, st>>>(s);
+hipError_t launch_chain_flush(const Batch2D& b, hipStream_t st) {
+  k_chain_flush<<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS);
   return hipGetLastError();
 }
 
-hipError_t launch_write_gradient(const Shot2D& s, float* g, long mplane, int z0, int x0, hipStream_t st) {
-  k_write_gradient<<<grid2d(s), block2d(), 0, st>>>(s, g, mplane, z0, x0);
+hipError_t launch_write_gradient(const Batch2D& b, hipStream_t st) {
+  k_write_gradient<<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS);
   return hipGetLastError();
 }
 

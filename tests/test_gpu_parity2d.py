@@ -241,3 +241,43 @@ def test_regularizer_parity(gpu_lib, hard):
     g = g.cpu().numpy().astype(np.float64) - g0
     assert abs(phi.item() - phi_o) / phi_o <= 1e-6
     assert rel(g, g_o) <= TOL
+
+
+def test_batch_uneven_windows_and_waves(gpu_lib):
+    """Shots on different windows of one model advance together (one launch per half step
+    over all shots' tiles); a workspace that holds only some shots runs them in waves. Both
+    must equal per-shot calls bit for bit (each cell's arithmetic is the same)."""
+    efwi = gpu_lib
+    rng = np.random.default_rng(12)
+    nz, nx, nt = 96, 180, 160
+    base = _f32(inputs.parity_2d().m_start[:, :nz, :nx])
+    grid = efwi.make_grid(nz, nx, 5.0, 5.0, 0.5e-3, nt, 10, 1e-3, 30.0, 4600.0)
+    wins = [(0, 0, 96, 180), (10, 20, 70, 120), (5, 50, 80, 130), (20, 8, 60, 100)]
+    shots, src = [], []
+    for k, (z0, x0, wz, wx) in enumerate(wins):
+        siz, six = z0 + wz // 2, x0 + wx // 2
+        chx = np.arange(x0 + 14, x0 + wx - 14, 3).astype(np.int32)
+        shots.append(efwi.Shot(siz, six, np.full(len(chx), siz + 1, np.int32), chx, z0=z0, x0=x0, wz=wz, wx=wx,
+                               ckpt_interval=11))
+        src.append(np.outer(rng.uniform(-1, 1, 3) * 1e16, inputs.ricker(nt, 0.5e-3, 30.0)))
+    src = T(np.stack(src))
+    m_ext = T(np.stack([base * (1 + 0.01 * rng.standard_normal(base.shape)) for _ in wins]))
+    d_obs = [efwi.model_forward(grid, shots[k], T(base * 1.05), src[k]) for k in range(len(wins))]
+    g1 = torch.empty_like(m_ext)
+    p1 = torch.empty(len(wins), dtype=torch.float64, device="cuda")
+    for k in range(len(wins)):
+        efwi.shot_gradient(grid, shots[k], m_ext[k], src[k], d_obs[k], g=g1[k], phi=p1[k])
+    full = efwi.workspace_size(efwi.WS_BATCH, grid, shots)
+    one = efwi.workspace_size(efwi.WS_GRADIENT, grid, shots[:1])
+    for nbytes in (full, max(one, full // 2)):
+        ws = efwi.workspace(nbytes)
+        g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, torch.cat(d_obs), ws=ws)
+        assert torch.equal(g1, g2) and torch.equal(p1, p2), nbytes
+    # outside each window the shot's gradient slot is zero
+    for k, (z0, x0, wz, wx) in enumerate(wins):
+        gk = g1[k].clone()
+        gk[:, z0:z0 + wz, x0:x0 + wx] = 0
+        assert float(gk.abs().max()) == 0.0
+    with pytest.raises(efwi.EfwiError) as ei:
+        efwi.batch_gradient(grid, shots, m_ext, src, torch.cat(d_obs), ws=efwi.workspace(one // 4))
+    assert ei.value.status == efwi.E_WORKSPACE
