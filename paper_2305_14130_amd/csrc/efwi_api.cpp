@@ -468,6 +468,12 @@ efwi_status check_ws(const void* ws, size_t have, size_t need) {
 // header (descriptors, tile list, per-shot tables: uploaded once) followed by each shot's
 // private region.
 // ----------------------------------------------------------------------------------------
+// Schedule entries needed for `tiles` tiles: a run holds at most its weight in tiles
+// (weights >= 1) and its weight is below wtot / NUM_XCD + PML_TILE_WEIGHT.
+size_t sched_capacity(size_t tiles) {
+  return (size_t)NUM_XCD * (tiles * PML_TILE_WEIGHT / NUM_XCD + PML_TILE_WEIGHT + 1);
+}
+
 size_t header_bytes(const std::vector<Plan2D>& plans, int first, int count) {
   size_t tiles = 0, tabs = 0;
   for (int k = first; k < first + count; ++k) {
@@ -475,7 +481,7 @@ size_t header_bytes(const std::vector<Plan2D>& plans, int first, int count) {
     tabs += plans[k].tab_bytes;
   }
   return align_up((size_t)count * sizeof(Shot2D)) + align_up((size_t)count * sizeof(int)) +
-         align_up(tiles * sizeof(int)) + tabs;
+         align_up(tiles * sizeof(int)) + 2 * align_up(sched_capacity(tiles) * sizeof(int)) + tabs;
 }
 
 size_t wave_bytes(const std::vector<Plan2D>& plans, int first, int count) {
@@ -505,7 +511,9 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   const size_t off_desc = 0;
   const size_t off_first = off_desc + align_up((size_t)count * sizeof(Shot2D));
   const size_t off_tshot = off_first + align_up((size_t)count * sizeof(int));
-  size_t off_tab = off_tshot + align_up((size_t)ntiles * sizeof(int));
+  const size_t off_sched = off_tshot + align_up((size_t)ntiles * sizeof(int));
+  const size_t off_sched2 = off_sched + align_up(sched_capacity(ntiles) * sizeof(int));
+  size_t off_tab = off_sched2 + align_up(sched_capacity(ntiles) * sizeof(int));
   const size_t hdr = header_bytes(plans, first, count);
   std::vector<unsigned char> blob(hdr, 0);
   int* tfirst = reinterpret_cast<int*>(blob.data() + off_first);
@@ -527,9 +535,44 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     region += p.total;
   }
   std::memcpy(blob.data() + off_desc, wv.descs.data(), (size_t)count * sizeof(Shot2D));
+  // XCD schedules: cut the tile list into NUM_XCD contiguous runs of equal (weighted) cost
+  std::vector<int> weight(ntiles);
+  for (int k = 0, q = 0; k < count; ++k) {
+    const Plan2D& p = wv.plans[k];
+    const int ntx = (p.nx + BX - 1) / BX;
+    for (int l = 0; l < p.ntiles; ++l, ++q) {
+      const int i0 = (l / ntx) * BZ, j0 = (l % ntx) * BX, pad = 2;
+      const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
+                                   (i0 + BZ - 1 + pad >= p.nz - p.P));
+      weight[q] = pml ? PML_TILE_WEIGHT : 1;
+    }
+  }
+  int nsched[2];
+  for (int variant = 0; variant < 2; ++variant) {
+    std::vector<int> wq(ntiles, 1);
+    if (variant == 1) wq = weight;
+    long wtot = 0;
+    for (int x : wq) wtot += x;
+    std::vector<int> cut(NUM_XCD + 1, ntiles);
+    cut[0] = 0;
+    long acc = 0;
+    for (int q = 0, k = 1; q < ntiles && k < NUM_XCD; ++q) {
+      acc += wq[q];
+      while (k < NUM_XCD && acc * NUM_XCD >= wtot * k) cut[k++] = q + 1;
+    }
+    int maxrun = 0;
+    for (int k = 0; k < NUM_XCD; ++k) maxrun = std::max(maxrun, cut[k + 1] - cut[k]);
+    if ((size_t)maxrun * NUM_XCD > sched_capacity(ntiles)) return fail(EFWI_E_INVAL, "tile schedule overflow");
+    int* sched = reinterpret_cast<int*>(blob.data() + (variant == 0 ? off_sched : off_sched2));
+    for (int m = 0; m < maxrun; ++m)
+      for (int k = 0; k < NUM_XCD; ++k) sched[m * NUM_XCD + k] = (cut[k] + m < cut[k + 1]) ? cut[k] + m : -1;
+    nsched[variant] = maxrun * NUM_XCD;
+  }
   wv.batch.shots = reinterpret_cast<const Shot2D*>(ws + off_desc);
   wv.batch.tile_first = reinterpret_cast<const int*>(ws + off_first);
   wv.batch.tile_shot = reinterpret_cast<const int*>(ws + off_tshot);
+  wv.batch.even = Sched{reinterpret_cast<const int*>(ws + off_sched), nsched[0]};
+  wv.batch.weighted = Sched{reinterpret_cast<const int*>(ws + off_sched2), nsched[1]};
   wv.batch.ns = count;
   wv.batch.ntiles = ntiles;
   // zero what must start at zero

@@ -85,13 +85,27 @@ struct Shot2D {
 };
 
 // A batch of shots advanced together: device descriptors and the flat tile list (tiles of
-// shot s are tile_first[s] .. tile_first[s] + tiles(s) - 1; tile_shot maps tile -> shot).
+// shot s are tile_first[s] .. tile_first[s] + tiles(s) - 1; tile_shot maps tile -> shot),
+// and two launch schedules: workgroup w processes tile sched[w] (-1: none). `even` splits
+// the tiles evenly over the XCDs (forward and pointwise kernels); `weighted` balances the
+// adjoint kernels, whose CPML tiles cost several interior tiles.
+struct Sched {
+  const int* sched;
+  int n;
+};
 struct Batch2D {
   const Shot2D* shots;
   const int* tile_shot;
   const int* tile_first;
+  Sched even, weighted;
   int ns, ntiles;
 };
+
+// Number of XCDs the hardware deals workgroups to, round robin.
+constexpr int NUM_XCD = 8;
+// Relative cost of a tile that touches a CPML strip in the adjoint kernels (measured on
+// MI355X: ~3x an interior tile; ~1.3x in the forward kernels, which use the even split).
+constexpr int PML_TILE_WEIGHT = 3;
 
 // Strip index helpers (x: column j of width nx; z: row i of height nz).
 __host__ __device__ inline int strip_index(int k, int n, int P) {

@@ -51,18 +51,17 @@ __device__ __forceinline__ float dminus(P f, long o, long st, float r) {
 
 // Work decomposition. A launch covers the tiles of every shot of a batch: tiles are listed
 // shot by shot, row band by row band (x fastest), and `tile_first[s]` is shot s's first
-// tile. The hardware deals workgroup w to XCD (w mod 8), so workgroup w takes tile
-// (w mod 8) * chunk + w / 8: each XCD walks one contiguous run of the list, and the
-// z-halo rows its stencils re-read are still in its own L2. The padding workgroups of the
-// last chunk return at once.
+// tile. The hardware deals workgroup w to XCD (w mod 8); the host-built schedule gives
+// XCD k one contiguous run of the tile list, cut so that every XCD gets the same weighted
+// cost (tiles touching the CPML strips cost more), and workgroup w = k + 8 m takes the
+// m-th tile of run k. Contiguous runs keep each stencil's z-halo rows in the XCD's own L2.
+// Schedule entries of -1 pad the shorter runs.
 constexpr int NXCD = 8;
-__device__ __forceinline__ bool batch_tile(const int* __restrict__ tile_shot, const int* __restrict__ tile_first,
-                                           const Shot2D* __restrict__ shots, int ntiles, int& sh, int& i0,
-                                           int& j0) {
-  const int chunk = (ntiles + NXCD - 1) / NXCD;
-  const int w = blockIdx.x;
-  const int t = (w % NXCD) * chunk + w / NXCD;
-  if (t >= ntiles) return false;
+__device__ __forceinline__ bool batch_tile(const int* __restrict__ sched, const int* __restrict__ tile_shot,
+                                           const int* __restrict__ tile_first, const Shot2D* __restrict__ shots,
+                                           int& sh, int& i0, int& j0) {
+  const int t = sched[blockIdx.x];
+  if (t < 0) return false;
   sh = tile_shot[t];
   const int local = t - tile_first[sh];
   const int ntx = (shots[sh].nx + BX - 1) / BX;
@@ -73,10 +72,10 @@ __device__ __forceinline__ bool batch_tile(const int* __restrict__ tile_shot, co
 
 #define BATCH_PARAMS                                                                           \
   const Shot2D* __restrict__ shots, const int* __restrict__ tile_shot, const int* __restrict__ tile_first, \
-      int ntiles
+      const int* __restrict__ sched
 #define BATCH_TILE()                                                                           \
   int sh_, i0, j0;                                                                              \
-  if (!batch_tile(tile_shot, tile_first, shots, ntiles, sh_, i0, j0)) return;                  \
+  if (!batch_tile(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;                   \
   const Shot2D& s = shots[sh_]
 
 // Does the block touch a CPML strip (with `pad` extra cells of neighbourhood)?
@@ -313,18 +312,58 @@ __device__ __forceinline__ void accumulate(gfloat* acc, long idx, float v, bool 
   else acc[idx] += v;
 }
 
+// CPML tiles stage the corrected transposed operands of the tile and its halo in LDS, so
+// each node's correction (strip test, profile, adjoint memory variable) is computed once
+// instead of once per neighbour that reads it. Four operands, each over the tile rows or
+// columns it is differentiated along: x-operands cover columns [j0 + lo, j0 + 64 + hi] of
+// the 4 tile rows, z-operands rows [i0 + lo, i0 + 4 + hi] of the 64 tile columns.
+constexpr int LX = BX + 3;      // 67 columns (x-operands)
+constexpr int LZ = BZ + 3;      // 7 rows (z-operands)
+constexpr int LDS_OPS = 2 * BZ * LX + 2 * LZ * BX;
+
+struct StageArea {
+  float* x0;  // [BZ][LX]
+  float* x1;  // [BZ][LX]
+  float* z0;  // [LZ][BX]
+  float* z1;  // [LZ][BX]
+};
+
+// Fill the four staged operands: fx0/fx1 at (i0 + r, j0 + c + lox0/lox1), fz0/fz1 at
+// (i0 + r + loz0/loz1, j0 + c). Nodes outside the grid hold zero.
+template <class F0, class F1, class F2, class F3>
+__device__ __forceinline__ void stage_operands(const Shot2D& s, int i0, int j0, StageArea a, int lox0, int lox1,
+                                               int loz0, int loz1, F0 fx0, F1 fx1, F2 fz0, F3 fz1) {
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  for (int e = tid; e < LDS_OPS; e += BX * BZ) {
+    int q = e;
+    int which, r, c;
+    if (q < BZ * LX) { which = 0; r = q / LX; c = q % LX; }
+    else if ((q -= BZ * LX) < BZ * LX) { which = 1; r = q / LX; c = q % LX; }
+    else if ((q -= BZ * LX) < LZ * BX) { which = 2; r = q / BX; c = q % BX; }
+    else { q -= LZ * BX; which = 3; r = q / BX; c = q % BX; }
+    const int ii = i0 + r + (which == 2 ? loz0 : which == 3 ? loz1 : 0);
+    const int jj = j0 + c + (which == 0 ? lox0 : which == 1 ? lox1 : 0);
+    float v = 0.0f;
+    if (ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
+      if (which == 0) v = fx0(ii, jj);
+      else if (which == 1) v = fx1(ii, jj);
+      else if (which == 2) v = fz0(ii, jj);
+      else v = fz1(ii, jj);
+    }
+    (which == 0 ? a.x0 : which == 1 ? a.x1 : which == 2 ? a.z0 : a.z1)[which < 2 ? r * LX + c : r * BX + c] = v;
+  }
+}
+
 // Transposed stress sub-step (first at reverse step n): t_bar -> u_bar.
+// ux, uz, wz, wx are the four transposed differences: D+x p_bar_xx, D-z p_bar_zx,
+// D+z p_bar_zz and D-x p_bar_xz at the cell's velocity nodes (without 1/h).
 template <bool GRAD, bool SRCADJ, bool PML>
-__device__ __forceinline__ void adj_vel_cell(const Shot2D& s, int i, int j, int n, const gfloat* seg, bool first) {
+__device__ __forceinline__ void adj_vel_finish(const Shot2D& s, int i, int j, int n, const gfloat* seg, bool first,
+                                               float ux, float uz, float wz, float wx) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  const AdjCtx<PML> c{s, rd};
   // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx); v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
-  const float ux = K1 * (pb_xx(c, i, j + 1) - pb_xx(c, i, j)) + K2 * (pb_xx(c, i, j + 2) - pb_xx(c, i, j - 1));
-  const float uz = K1 * (pb_zx(c, i, j) - pb_zx(c, i - 1, j)) + K2 * (pb_zx(c, i + 1, j) - pb_zx(c, i - 2, j));
-  const float wz = K1 * (pb_zz(c, i + 1, j) - pb_zz(c, i, j)) + K2 * (pb_zz(c, i + 2, j) - pb_zz(c, i - 1, j));
-  const float wx = K1 * (pb_xz(c, i, j) - pb_xz(c, i, j - 1)) + K2 * (pb_xz(c, i, j + 1) - pb_xz(c, i, j - 2));
   float gx = -(ux * s.rdx + uz * s.rdz);
   const float gz = -(wz * s.rdz + wx * s.rdx);
   // DAS transpose: the channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1),
@@ -376,24 +415,49 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_vel(BATCH_PARAMS, int n, int k,
   BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
-  if (i >= s.nz || j >= s.nx) return;
-  if (block_in_pml(s, j0, i0, 2)) adj_vel_cell<GRAD, SRCADJ, true>(s, i, j, n, seg, first != 0);
-  else adj_vel_cell<GRAD, SRCADJ, false>(s, i, j, n, seg, first != 0);
+  const bool active = i < s.nz && j < s.nx;
+  if (block_in_pml(s, j0, i0, 2)) {  // block-uniform: every thread reaches the barrier
+    __shared__ float lds[LDS_OPS];
+    const StageArea a{lds, lds + BZ * LX, lds + 2 * BZ * LX, lds + 2 * BZ * LX + LZ * BX};
+    const AdjCtx<true> c{s, (n + 1) & 1};
+    // x0: p_bar_xx at columns j-1 .. j+2; x1: p_bar_xz at j-2 .. j+1;
+    // z0: p_bar_zx at rows i-2 .. i+1;     z1: p_bar_zz at i-1 .. i+2
+    stage_operands(s, i0, j0, a, -1, -2, -2, -1, [&](int ii, int jj) { return pb_xx(c, ii, jj); },
+                   [&](int ii, int jj) { return pb_xz(c, ii, jj); }, [&](int ii, int jj) { return pb_zx(c, ii, jj); },
+                   [&](int ii, int jj) { return pb_zz(c, ii, jj); });
+    __syncthreads();
+    if (!active) return;
+    const int r = threadIdx.y, q = threadIdx.x;
+    const float* X0 = a.x0 + r * LX + q;   // X0[m] = p_bar_xx(i, j - 1 + m)
+    const float* X1 = a.x1 + r * LX + q;   // X1[m] = p_bar_xz(i, j - 2 + m)
+    const float* Z0 = a.z0 + r * BX + q;   // Z0[m BX] = p_bar_zx(i - 2 + m, j)
+    const float* Z1 = a.z1 + r * BX + q;   // Z1[m BX] = p_bar_zz(i - 1 + m, j)
+    const float ux = K1 * (X0[2] - X0[1]) + K2 * (X0[3] - X0[0]);
+    const float uz = K1 * (Z0[2 * BX] - Z0[BX]) + K2 * (Z0[3 * BX] - Z0[0]);
+    const float wz = K1 * (Z1[2 * BX] - Z1[BX]) + K2 * (Z1[3 * BX] - Z1[0]);
+    const float wx = K1 * (X1[2] - X1[1]) + K2 * (X1[3] - X1[0]);
+    adj_vel_finish<GRAD, SRCADJ, true>(s, i, j, n, seg, first != 0, ux, uz, wz, wx);
+  } else if (active) {
+    const AdjCtx<false> c{s, 0};
+    const float ux = K1 * (pb_xx(c, i, j + 1) - pb_xx(c, i, j)) + K2 * (pb_xx(c, i, j + 2) - pb_xx(c, i, j - 1));
+    const float uz = K1 * (pb_zx(c, i, j) - pb_zx(c, i - 1, j)) + K2 * (pb_zx(c, i + 1, j) - pb_zx(c, i - 2, j));
+    const float wz = K1 * (pb_zz(c, i + 1, j) - pb_zz(c, i, j)) + K2 * (pb_zz(c, i + 2, j) - pb_zz(c, i - 1, j));
+    const float wx = K1 * (pb_xz(c, i, j) - pb_xz(c, i, j - 1)) + K2 * (pb_xz(c, i, j + 1) - pb_xz(c, i, j - 2));
+    adj_vel_finish<GRAD, SRCADJ, false>(s, i, j, n, seg, first != 0, ux, uz, wz, wx);
+  }
 }
 
 // Transposed velocity sub-step (second at reverse step n): u_bar -> t_bar.
+// txx, tzz, t1, t2: D-x q_bar_xa, D-z q_bar_zb, D+z q_bar_xb, D+x q_bar_za at the cell's
+// stress nodes (without 1/h).
 template <bool GRAD, bool PML>
-__device__ __forceinline__ void adj_str_cell(const Shot2D& s, int i, int j, int n, const gfloat* seg, bool first) {
+__device__ __forceinline__ void adj_str_finish(const Shot2D& s, int i, int j, int n, const gfloat* seg, bool first,
+                                               float txx, float tzz, float t1, float t2) {
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  const AdjCtx<PML> c{s, rd};
   // sigma_bar_xx += -D-x q_bar_xa ; sigma_bar_zz += -D-z q_bar_zb ;
   // sigma_bar_xz += -(D+z q_bar_xb + D+x q_bar_za)
-  const float txx = K1 * (qb_xa(c, i, j) - qb_xa(c, i, j - 1)) + K2 * (qb_xa(c, i, j + 1) - qb_xa(c, i, j - 2));
-  const float tzz = K1 * (qb_zb(c, i, j) - qb_zb(c, i - 1, j)) + K2 * (qb_zb(c, i + 1, j) - qb_zb(c, i - 2, j));
-  const float t1 = K1 * (qb_xb(c, i + 1, j) - qb_xb(c, i, j)) + K2 * (qb_xb(c, i + 2, j) - qb_xb(c, i - 1, j));
-  const float t2 = K1 * (qb_za(c, i, j + 1) - qb_za(c, i, j)) + K2 * (qb_za(c, i, j + 2) - qb_za(c, i, j - 1));
   const float dsxx = -txx * s.rdx, dszz = -tzz * s.rdz, dsxz = -(t1 * s.rdz + t2 * s.rdx);
   const float ux = s.uxb[o], uz = s.uzb[o];
   if (PML) {  // owned adjoint memory variables of the velocity-side derivatives
@@ -426,9 +490,36 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_str(BATCH_PARAMS, int n, int k,
   BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
-  if (i >= s.nz || j >= s.nx) return;
-  if (block_in_pml(s, j0, i0, 2)) adj_str_cell<GRAD, true>(s, i, j, n, seg, first != 0);
-  else adj_str_cell<GRAD, false>(s, i, j, n, seg, first != 0);
+  const bool active = i < s.nz && j < s.nx;
+  if (block_in_pml(s, j0, i0, 2)) {  // block-uniform: every thread reaches the barrier
+    __shared__ float lds[LDS_OPS];
+    const StageArea a{lds, lds + BZ * LX, lds + 2 * BZ * LX, lds + 2 * BZ * LX + LZ * BX};
+    const AdjCtx<true> c{s, (n + 1) & 1};
+    // x0: q_bar_xa at columns j-2 .. j+1; x1: q_bar_za at j-1 .. j+2;
+    // z0: q_bar_zb at rows i-2 .. i+1;     z1: q_bar_xb at i-1 .. i+2
+    stage_operands(s, i0, j0, a, -2, -1, -2, -1, [&](int ii, int jj) { return qb_xa(c, ii, jj); },
+                   [&](int ii, int jj) { return qb_za(c, ii, jj); }, [&](int ii, int jj) { return qb_zb(c, ii, jj); },
+                   [&](int ii, int jj) { return qb_xb(c, ii, jj); });
+    __syncthreads();
+    if (!active) return;
+    const int r = threadIdx.y, q = threadIdx.x;
+    const float* X0 = a.x0 + r * LX + q;   // X0[m] = q_bar_xa(i, j - 2 + m)
+    const float* X1 = a.x1 + r * LX + q;   // X1[m] = q_bar_za(i, j - 1 + m)
+    const float* Z0 = a.z0 + r * BX + q;   // Z0[m BX] = q_bar_zb(i - 2 + m, j)
+    const float* Z1 = a.z1 + r * BX + q;   // Z1[m BX] = q_bar_xb(i - 1 + m, j)
+    const float txx = K1 * (X0[2] - X0[1]) + K2 * (X0[3] - X0[0]);
+    const float tzz = K1 * (Z0[2 * BX] - Z0[BX]) + K2 * (Z0[3 * BX] - Z0[0]);
+    const float t1 = K1 * (Z1[2 * BX] - Z1[BX]) + K2 * (Z1[3 * BX] - Z1[0]);
+    const float t2 = K1 * (X1[2] - X1[1]) + K2 * (X1[3] - X1[0]);
+    adj_str_finish<GRAD, true>(s, i, j, n, seg, first != 0, txx, tzz, t1, t2);
+  } else if (active) {
+    const AdjCtx<false> c{s, 0};
+    const float txx = K1 * (qb_xa(c, i, j) - qb_xa(c, i, j - 1)) + K2 * (qb_xa(c, i, j + 1) - qb_xa(c, i, j - 2));
+    const float tzz = K1 * (qb_zb(c, i, j) - qb_zb(c, i - 1, j)) + K2 * (qb_zb(c, i + 1, j) - qb_zb(c, i - 2, j));
+    const float t1 = K1 * (qb_xb(c, i + 1, j) - qb_xb(c, i, j)) + K2 * (qb_xb(c, i + 2, j) - qb_xb(c, i - 1, j));
+    const float t2 = K1 * (qb_za(c, i, j + 1) - qb_za(c, i, j)) + K2 * (qb_za(c, i, j + 2) - qb_za(c, i, j - 1));
+    adj_str_finish<GRAD, false>(s, i, j, n, seg, first != 0, txx, tzz, t1, t2);
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -560,54 +651,55 @@ __global__ void k_reduce_phi(const double* partial, int n, double* phi) {
   if (threadIdx.x == 0) *phi = 0.5 * sh[0];
 }
 
-inline dim3 grid_of(const Batch2D& b) { return dim3(NXCD * ((b.ntiles + NXCD - 1) / NXCD)); }
+inline dim3 grid_of(const Sched& q) { return dim3(q.n); }
 inline dim3 block2d() { return dim3(BX, BZ); }
-#define BATCH_ARGS b.shots, b.tile_shot, b.tile_first, b.ntiles
+#define EVEN_ARGS b.shots, b.tile_shot, b.tile_first, b.even.sched
+#define WEIGHTED_ARGS b.shots, b.tile_shot, b.tile_first, b.weighted.sched
 
 }  // namespace
 
 hipError_t launch_stage2d(const Batch2D& b, hipStream_t st) {
-  k_stage<<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS);
+  k_stage<<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS);
   return hipGetLastError();
 }
 
 hipError_t launch_fwd_vel(const Batch2D& b, int kstore, hipStream_t st) {
-  if (kstore >= 0) k_fwd_vel<true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, kstore);
-  else k_fwd_vel<false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, 0);
+  if (kstore >= 0) k_fwd_vel<true><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, kstore);
+  else k_fwd_vel<false><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_fwd_str(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
   if (kstore >= 0) {
-    if (record) k_fwd_str<true, true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, kstore);
-    else k_fwd_str<true, false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, kstore);
+    if (record) k_fwd_str<true, true><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, n, kstore);
+    else k_fwd_str<true, false><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, n, kstore);
   } else {
-    if (record) k_fwd_str<false, true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0);
-    else k_fwd_str<false, false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0);
+    if (record) k_fwd_str<false, true><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, n, 0);
+    else k_fwd_str<false, false><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, n, 0);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_adj_vel(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
-  if (grad) k_adj_vel<true, false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, k, first);
-  else if (srcadj) k_adj_vel<false, true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0, 0);
-  else k_adj_vel<false, false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0, 0);
+  if (grad) k_adj_vel<true, false><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, k, first);
+  else if (srcadj) k_adj_vel<false, true><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, 0, 0);
+  else k_adj_vel<false, false><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_str(const Batch2D& b, int n, int k, bool grad, bool first, hipStream_t st) {
-  if (grad) k_adj_str<true><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, k, first);
-  else k_adj_str<false><<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS, n, 0, 0);
+  if (grad) k_adj_str<true><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, k, first);
+  else k_adj_str<false><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_chain_flush(const Batch2D& b, hipStream_t st) {
-  k_chain_flush<<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS);
+  k_chain_flush<<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS);
   return hipGetLastError();
 }
 
 hipError_t launch_write_gradient(const Batch2D& b, hipStream_t st) {
-  k_write_gradient<<<grid_of(b), block2d(), 0, st>>>(BATCH_ARGS);
+  k_write_gradient<<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS);
   return hipGetLastError();
 }
 
