@@ -121,6 +121,15 @@ efwi_status efwi_shot_gradient(const efwi_grid* grid, const efwi_shot* shot, con
                                const float* src, const float* d_obs, float* g, double* phi,
                                float* d_out, void* ws, size_t ws_bytes, void* stream);
 
+/* shot_jt: g = J_s^T v for a data-space vector v [nch][nt] (eq.(6) with the residual
+ * replaced by v): the backward of the differentiable map m_s -> d_s, for any data-space
+ * loss. The forward wavefield is recomputed from checkpoints as in efwi_shot_gradient
+ * (same workspace size).
+ *   v     DEVICE [nch][nt]; g DEVICE [3][nz][nx] output (zero outside the window);
+ *   d_out DEVICE [nch][nt] predicted data, or NULL. */
+efwi_status efwi_shot_jt(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* src,
+                         const float* v, float* g, float* d_out, void* ws, size_t ws_bytes, void* stream);
+
 /* batch_gradient: the data term of eq.(8) for ns shots at once, each shot s on its own
  * component m_s of the extended model and its own window, advanced together (one launch
  * per half step covers every shot's tiles).

@@ -684,9 +684,13 @@ efwi_status gradient_waves(const efwi_grid& g, const efwi_shot* shots, int ns, c
       const Shot2D& d = wv.descs[k];
       unsigned char* r = ws + wv.regions[k];
       const Plan2D& p = wv.plans[k];
-      HIP_TRY(TIMED(KK_MISFIT, st,
-                    launch_misfit(d, (const float*)(d.d), io[first + k].dobs, reinterpret_cast<double*>(r + p.off_partial),
-                                  io[first + k].phi, reinterpret_cast<float*>(r + p.off_ebar), st)));
+      float* ebar = reinterpret_cast<float*>(r + p.off_ebar);
+      if (io[first + k].r)  // J^T v: the data-space vector drives the adjoint directly
+        HIP_TRY(TIMED(KK_MISFIT, st, launch_residual_cumsum(d, io[first + k].r, ebar, st)));
+      else
+        HIP_TRY(TIMED(KK_MISFIT, st,
+                      launch_misfit(d, (const float*)(d.d), io[first + k].dobs,
+                                    reinterpret_cast<double*>(r + p.off_partial), io[first + k].phi, ebar, st)));
     }
     rc = run_reverse(wv, ws, st);
     if (rc != EFWI_OK) return rc;
@@ -843,6 +847,23 @@ efwi_status efwi_shot_gradient(const efwi_grid* grid, const efwi_shot* shot, con
   io.d = d_out;
   io.gout = g;
   io.phi = phi;
+  return gradient_waves(*grid, shot, 1, {io}, static_cast<unsigned char*>(ws), ws_bytes,
+                        reinterpret_cast<hipStream_t>(stream));
+}
+
+efwi_status efwi_shot_jt(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* src,
+                         const float* v, float* g, float* d_out, void* ws, size_t ws_bytes, void* stream) {
+  efwi_status rc = efwi_validate(grid, 1, shot);
+  if (rc != EFWI_OK) return rc;
+  if (shot->ckpt_mode != EFWI_CKPT_FP32) return fail(EFWI_E_UNSUPPORTED, "16-bit checkpoints not built yet");
+  if (!m || !src || !g || (shot->nch > 0 && !v)) return fail(EFWI_E_INVAL, "NULL array argument");
+  ShotIO io;
+  io.m = m;
+  io.mplane = (long)grid->nz * grid->nx;
+  io.src = src;
+  io.r = v;
+  io.d = d_out;
+  io.gout = g;
   return gradient_waves(*grid, shot, 1, {io}, static_cast<unsigned char*>(ws), ws_bytes,
                         reinterpret_cast<hipStream_t>(stream));
 }

@@ -27,7 +27,7 @@ CKPT_FP32, CKPT_BF16, CKPT_FP16 = 0, 1, 2
 WS_FORWARD, WS_ADJOINT, WS_GRADIENT, WS_BATCH, WS_REGULARIZER = 0, 1, 2, 3, 4
 
 EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_model_adjoint",
-            "efwi_shot_gradient", "efwi_batch_gradient", "efwi_extension_regularizer",
+            "efwi_shot_gradient", "efwi_shot_jt", "efwi_batch_gradient", "efwi_extension_regularizer",
             "efwi_status_string", "efwi_last_error", "efwi_version", "efwi_timing_enable",
             "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name"]
 
@@ -95,6 +95,9 @@ _lib.efwi_model_adjoint.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC)
 _lib.efwi_shot_gradient.restype = ctypes.c_int
 _lib.efwi_shot_gradient.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp, _vp, _vp, _vp,
                                     _vp, ctypes.c_size_t, _vp]
+_lib.efwi_shot_jt.restype = ctypes.c_int
+_lib.efwi_shot_jt.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp, _vp, _vp, _vp,
+                              ctypes.c_size_t, _vp]
 _lib.efwi_batch_gradient.restype = ctypes.c_int
 _lib.efwi_batch_gradient.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), _vp, _vp, _vp,
                                      _vp, _vp, _vp, ctypes.c_size_t, _vp]
@@ -231,6 +234,19 @@ def shot_gradient(grid: Grid, shot: Shot, m, src, d_obs, g=None, phi=None, d_out
     _check(_lib.efwi_shot_gradient(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(d_obs), _ptr(g),
                                    _ptr(phi), _ptr(d_out), _ptr(ws), ws.numel(), _stream(stream)))
     return g, phi
+
+
+def shot_jt(grid: Grid, shot: Shot, m, src, v, g=None, d_out=None, ws=None, stream=None):
+    """g = J_s^T v for a data-space vector v [nch][nt] (backward of m -> d)."""
+    _f32(m, "m"), _f32(src, "src"), _f32(v, "v")
+    if g is None:
+        g = torch.empty_like(m)
+    sc = shot.c_struct()
+    need = _lib.efwi_workspace_size(WS_GRADIENT, ctypes.byref(grid), 1, ctypes.byref(sc))
+    ws = ws if ws is not None else workspace(need, m.device)
+    _check(_lib.efwi_shot_jt(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(v), _ptr(g),
+                             _ptr(d_out), _ptr(ws), ws.numel(), _stream(stream)))
+    return g
 
 
 def batch_gradient(grid: Grid, shots, m_ext, src, d_obs, g_ext=None, phi=None, ws=None, stream=None):
