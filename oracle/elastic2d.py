@@ -268,6 +268,78 @@ def forward(grid: Grid2D, vp, vs, rho, src_iz, src_ix, src, ch_iz, ch_ix, store=
 # ---------------------------------------------------------------------------------------
 # Exact discrete transpose.
 # ---------------------------------------------------------------------------------------
+class Adjoint2D:
+    """State of the exact discrete transpose of ``forward`` (adjoints of v, sigma, the CPML
+    memory variables and the DAS accumulators), stepped backward one time step at a time."""
+
+    def __init__(self, grid: Grid2D, vp, vs, rho, src_iz, src_ix, ch_iz, ch_ix, want_grad):
+        g = grid
+        self.g = g
+        self.med = stage(vp, vs, rho)
+        self.pml = cpml_2d(g)
+        shape = (g.nz, g.nx)
+        self.vxb, self.vzb = np.zeros(shape), np.zeros(shape)
+        self.sxxb, self.szzb, self.sxzb = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+        self.psib = {k: np.zeros(shape) for k in PSI_PROFILE}
+        self.ch_iz = np.asarray(ch_iz)
+        self.ch_ix = np.asarray(ch_ix)
+        self.src = (src_iz, src_ix)
+        self.ebar = np.zeros(len(self.ch_iz))
+        self.want_grad = want_grad
+        if want_grad:
+            self.glam, self.gmu, self.gmuxz = np.zeros(shape), np.zeros(shape), np.zeros(shape)
+            self.gbx, self.gbz = np.zeros(shape), np.zeros(shape)
+
+    def _cpml_T(self, key, ybar):
+        a, b = (self.pml[k] for k in PSI_PROFILE[key])
+        self.psib[key] = self.psib[key] + ybar
+        xbar = ybar + a * self.psib[key]
+        self.psib[key] = b * self.psib[key]
+        return xbar
+
+    def step(self, r_n, hist_n=None):
+        """Transpose of time step n: r_n is r[:, n]; hist_n the forward quantities of step n
+        (needed for the gradient). Returns the source-component adjoints (3,) of step n."""
+        g, med = self.g, self.med
+        iz, ix = self.src
+        w = g.dt / (g.dx * g.dz)
+        # DAS record: d[:, n] = e ; e += dt * D-x vx at channels
+        self.ebar = self.ebar + r_n
+        pch = np.zeros((g.nz, g.nx))
+        np.add.at(pch, (self.ch_iz, self.ch_ix), g.dt * self.ebar)
+        self.vxb = self.vxb + d_minus_T(pch, g.dx, 1)
+        # source injection
+        fbar = np.array([-w * self.sxxb[iz, ix], -w * self.szzb[iz, ix],
+                         -0.25 * w * self.sxzb[iz - 1:iz + 1, ix - 1:ix + 1].sum()])
+        # stress update
+        sxxb, szzb, sxzb = self.sxxb, self.szzb, self.sxzb
+        if self.want_grad:
+            pxx, pzz, ps, qx, qz = hist_n
+            self.glam += g.dt * (sxxb + szzb) * (pxx + pzz)
+            self.gmu += 2.0 * g.dt * (sxxb * pxx + szzb * pzz)
+            self.gmuxz += g.dt * sxzb * ps
+        pxx_b = g.dt * (med["lam2mu"] * sxxb + med["lam"] * szzb)
+        pzz_b = g.dt * (med["lam"] * sxxb + med["lam2mu"] * szzb)
+        ps_b = g.dt * med["muxz"] * sxzb
+        cT = self._cpml_T
+        self.vxb = self.vxb + d_minus_T(cT("xx_x", pxx_b), g.dx, 1) + d_plus_T(cT("xz_z", ps_b), g.dz, 0)
+        self.vzb = self.vzb + d_minus_T(cT("zz_z", pzz_b), g.dz, 0) + d_plus_T(cT("xz_x", ps_b), g.dx, 1)
+        # velocity update
+        if self.want_grad:
+            self.gbx += g.dt * self.vxb * qx
+            self.gbz += g.dt * self.vzb * qz
+        qx_b = g.dt * med["bx"] * self.vxb
+        qz_b = g.dt * med["bz"] * self.vzb
+        self.sxxb = self.sxxb + d_plus_T(cT("vx_x", qx_b), g.dx, 1)
+        self.sxzb = (self.sxzb + d_minus_T(cT("vx_z", qx_b), g.dz, 0)
+                     + d_minus_T(cT("vz_x", qz_b), g.dx, 1))
+        self.szzb = self.szzb + d_plus_T(cT("vz_z", qz_b), g.dz, 0)
+        return fbar
+
+    def gradients(self):
+        return self.glam, self.gmu, self.gmuxz, self.gbx, self.gbz
+
+
 def adjoint(grid: Grid2D, vp, vs, rho, src_iz, src_ix, ch_iz, ch_ix, r, hist=None):
     """Transpose of ``forward`` applied to r[nch][nt].
 
@@ -278,62 +350,12 @@ def adjoint(grid: Grid2D, vp, vs, rho, src_iz, src_ix, ch_iz, ch_ix, r, hist=Non
     Each forward sub-step y += T x becomes x_bar += T^T y_bar, taken in reverse order:
     DAS record, source injection, stress update (with its CPML variables), velocity update
     (with its CPML variables)."""
-    g = grid
-    med = stage(vp, vs, rho)
-    pml = cpml_2d(g)
-    shape = (g.nz, g.nx)
-    vxb, vzb = np.zeros(shape), np.zeros(shape)
-    sxxb, szzb, sxzb = np.zeros(shape), np.zeros(shape), np.zeros(shape)
-    psib = {k: np.zeros(shape) for k in PSI_PROFILE}
-    ch_iz = np.asarray(ch_iz)
-    ch_ix = np.asarray(ch_ix)
-    ebar = np.zeros(len(ch_iz))
-    fbar = np.zeros((3, g.nt))
-    want_grad = hist is not None
-    if want_grad:
-        glam, gmu, gmuxz = np.zeros(shape), np.zeros(shape), np.zeros(shape)
-        gbx, gbz = np.zeros(shape), np.zeros(shape)
-    w = g.dt / (g.dx * g.dz)
-
-    def cpml_T(key, ybar):
-        a, b = (pml[k] for k in PSI_PROFILE[key])
-        psib[key] = psib[key] + ybar
-        xbar = ybar + a * psib[key]
-        psib[key] = b * psib[key]
-        return xbar
-
-    for n in range(g.nt - 1, -1, -1):
-        # DAS record: d[:, n] = e ; e += dt * D-x vx at channels
-        ebar = ebar + r[:, n]
-        pch = np.zeros(shape)
-        np.add.at(pch, (ch_iz, ch_ix), g.dt * ebar)
-        vxb = vxb + d_minus_T(pch, g.dx, 1)
-        # source injection
-        fbar[0, n] = -w * sxxb[src_iz, src_ix]
-        fbar[1, n] = -w * szzb[src_iz, src_ix]
-        fbar[2, n] = -0.25 * w * sxzb[src_iz - 1:src_iz + 1, src_ix - 1:src_ix + 1].sum()
-        # stress update
-        if want_grad:
-            pxx, pzz, ps, qx, qz = hist[n]
-            glam += g.dt * (sxxb + szzb) * (pxx + pzz)
-            gmu += 2.0 * g.dt * (sxxb * pxx + szzb * pzz)
-            gmuxz += g.dt * sxzb * ps
-        pxx_b = g.dt * (med["lam2mu"] * sxxb + med["lam"] * szzb)
-        pzz_b = g.dt * (med["lam"] * sxxb + med["lam2mu"] * szzb)
-        ps_b = g.dt * med["muxz"] * sxzb
-        vxb = vxb + d_minus_T(cpml_T("xx_x", pxx_b), g.dx, 1) + d_plus_T(cpml_T("xz_z", ps_b), g.dz, 0)
-        vzb = vzb + d_minus_T(cpml_T("zz_z", pzz_b), g.dz, 0) + d_plus_T(cpml_T("xz_x", ps_b), g.dx, 1)
-        # velocity update
-        if want_grad:
-            gbx += g.dt * vxb * qx
-            gbz += g.dt * vzb * qz
-        qx_b = g.dt * med["bx"] * vxb
-        qz_b = g.dt * med["bz"] * vzb
-        sxxb = sxxb + d_plus_T(cpml_T("vx_x", qx_b), g.dx, 1)
-        sxzb = sxzb + d_minus_T(cpml_T("vx_z", qx_b), g.dz, 0) + d_minus_T(cpml_T("vz_x", qz_b), g.dx, 1)
-        szzb = szzb + d_plus_T(cpml_T("vz_z", qz_b), g.dz, 0)
-    if want_grad:
-        return fbar, (glam, gmu, gmuxz, gbx, gbz)
+    A = Adjoint2D(grid, vp, vs, rho, src_iz, src_ix, ch_iz, ch_ix, want_grad=hist is not None)
+    fbar = np.zeros((3, grid.nt))
+    for n in range(grid.nt - 1, -1, -1):
+        fbar[:, n] = A.step(r[:, n], hist[n] if hist is not None else None)
+    if hist is not None:
+        return fbar, A.gradients()
     return fbar
 
 
@@ -390,3 +412,74 @@ def shot_gradient(grid, m, src_iz, src_ix, src, ch_iz, ch_ix, d_obs):
     phi, r = misfit(d, d_obs)
     _, gpar = adjoint(grid, m[0], m[1], m[2], src_iz, src_ix, ch_iz, ch_ix, r, hist=hist)
     return chain_rule(m[0], m[1], m[2], *gpar), phi, d
+
+
+# ---------------------------------------------------------------------------------------
+# Checkpointed gradient (the wavefield-recomputation schedule), optionally with 16-bit
+# snapshots. Mirrors what the product path computes, so its compressed-checkpoint mode can
+# be compared with this function at FP32 parity (and with ``shot_gradient`` for the error
+# the compression itself causes).
+# ---------------------------------------------------------------------------------------
+STATE_FIELDS = ("vx", "vz", "sxx", "szz", "sxz")
+
+
+def _snapshot(P, codec):
+    from .checkpoint import roundtrip
+    snap = {k: roundtrip(getattr(P, k), codec) for k in STATE_FIELDS}
+    snap["psi"] = {k: roundtrip(v, codec) for k, v in P.psi.items()}
+    return snap
+
+
+def _restore(P, snap):
+    for k in STATE_FIELDS:
+        setattr(P, k, snap[k].copy())
+    P.psi = {k: v.copy() for k, v in snap["psi"].items()}
+
+
+def shot_gradient_checkpointed(grid, m, src_iz, src_ix, src, ch_iz, ch_ix, d_obs, interval, codec=None):
+    """Per-shot gradient with the forward state snapshotted at the start of every segment of
+    `interval` steps (each field encoded by ``checkpoint.roundtrip(., codec)``), the last
+    segment's forward quantities kept from the first sweep, and every other segment
+    recomputed from its (decoded) snapshot before its transposed steps. Segment 0 starts
+    from the exact zero state. With codec None this equals ``shot_gradient`` to round-off.
+
+    Returns (g[3][nz][nx], phi, d)."""
+    g = grid
+    L = max(1, min(int(interval), g.nt))
+    nseg = (g.nt + L - 1) // L
+    last0 = (nseg - 1) * L
+    P = Propagator2D(g, m[0], m[1], m[2])
+    ch_iz, ch_ix = np.asarray(ch_iz), np.asarray(ch_ix)
+    d = np.zeros((len(ch_iz), g.nt))
+    e = np.zeros(len(ch_iz))
+    snaps = {}
+    last_hist = []
+    for n in range(g.nt):
+        if n % L == 0 and 0 < n < last0:
+            snaps[n // L] = _snapshot(P, codec)
+        qx, qz = P.velocity_half_step()
+        pxx, pzz, ps = P.stress_half_step()
+        P.inject(src_iz, src_ix, src[0][n], src[1][n], src[2][n])
+        e = e + g.dt * P.strain_rate_xx(ch_iz, ch_ix)
+        d[:, n] = e
+        if n >= last0:
+            last_hist.append((pxx, pzz, ps, qx, qz))
+    phi, r = misfit(d, d_obs)
+    A = Adjoint2D(g, m[0], m[1], m[2], src_iz, src_ix, ch_iz, ch_ix, want_grad=True)
+    for k in range(nseg - 1, -1, -1):
+        n0, n1 = k * L, min(g.nt, (k + 1) * L)
+        if k == nseg - 1:
+            hist = last_hist
+        else:
+            Q = Propagator2D(g, m[0], m[1], m[2])
+            if k > 0:
+                _restore(Q, snaps[k])
+            hist = []
+            for n in range(n0, n1):
+                qx, qz = Q.velocity_half_step()
+                pxx, pzz, ps = Q.stress_half_step()
+                Q.inject(src_iz, src_ix, src[0][n], src[1][n], src[2][n])
+                hist.append((pxx, pzz, ps, qx, qz))
+        for n in range(n1 - 1, n0 - 1, -1):
+            A.step(r[:, n], hist[n - n0])
+    return chain_rule(m[0], m[1], m[2], *A.gradients()), phi, d

@@ -266,10 +266,14 @@ struct Plan2D {
   Window w;
   int nz, nx, ld, cp, rows, P, nslots, nt, nch, L, nseg, ntiles;
   long plane, cells;
-  size_t state_bytes;  // padded fields + forward CPML strips (one checkpoint)
+  size_t state_bytes;  // padded fields + forward CPML strips
+  size_t state_elems;
+  int ckpt_mode;
+  size_t slot_bytes;   // one checkpoint (FP32 copy of the state block, or 16-bit codes)
+  CkptFields fields;
   size_t tab_bytes;    // CPML profiles + channel maps (kept in the batch header)
   size_t off_state, off_e, off_adj, off_par, off_ebar, off_partial, off_dint, off_acc, off_G, off_seg, off_ckpt,
-      total;
+      off_maxbits, total;
   size_t adj_bytes, par_bytes;
 };
 
@@ -306,7 +310,24 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.L = interval_of(g, s);
   p.nseg = (g.nt + p.L - 1) / p.L;
   const size_t strips = strips_floats(p.nz, p.nx, p.P);
-  p.state_bytes = align_up(((size_t)5 * p.plane + strips) * sizeof(float));
+  p.state_elems = (size_t)5 * p.plane + strips;
+  p.state_bytes = align_up(p.state_elems * sizeof(float));
+  p.ckpt_mode = s.ckpt_mode;
+  p.slot_bytes = s.ckpt_mode == EFWI_CKPT_FP32 ? p.state_bytes
+                                               : align_up(CKPT_HEADER + p.state_elems * sizeof(unsigned short));
+  {
+    const long xs = (long)p.nz * 2 * p.P, zs = (long)2 * p.P * p.nx;
+    for (int k = 0; k < 5; ++k) {
+      p.fields.off[k] = k * p.plane;
+      p.fields.len[k] = p.plane;
+    }
+    for (int k = 0; k < 4; ++k) {
+      p.fields.off[5 + k] = 5 * p.plane + k * xs;
+      p.fields.len[5 + k] = xs;
+      p.fields.off[9 + k] = 5 * p.plane + 4 * xs + k * zs;
+      p.fields.len[9 + k] = zs;
+    }
+  }
   p.adj_bytes = align_up(((size_t)5 * p.plane + 2 * strips) * sizeof(float));
   p.par_bytes = align_up((size_t)5 * p.plane * sizeof(float));
   p.tab_bytes = align_up((size_t)(4 * p.nx + 4 * p.nz) * sizeof(float) + (size_t)p.nz * sizeof(int) +
@@ -330,7 +351,8 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.off_acc = grad ? take((size_t)NACC * p.cells * sizeof(float)) : 0;
   p.off_G = grad ? take((size_t)3 * p.cells * sizeof(double)) : 0;
   p.off_seg = grad ? take((size_t)p.L * NSEG_FIELDS * p.cells * sizeof(float)) : 0;
-  p.off_ckpt = grad ? take((size_t)std::max(0, p.nseg - 2) * p.state_bytes) : 0;
+  p.off_ckpt = grad ? take((size_t)std::max(0, p.nseg - 2) * p.slot_bytes) : 0;
+  p.off_maxbits = grad ? take(CKPT_NFIELDS * sizeof(unsigned int)) : 0;
   p.total = o;
   return p;
 }
@@ -606,8 +628,12 @@ efwi_status run_forward(Wave& wv, unsigned char* ws, bool checkpoints, hipStream
       for (size_t q = 0; q < wv.plans.size(); ++q) {
         const Plan2D& p = wv.plans[q];
         unsigned char* r = ws + wv.regions[q];
-        HIP_TRY(hipMemcpyAsync(r + p.off_ckpt + (size_t)(k - 1) * p.state_bytes, r + p.off_state, p.state_bytes,
-                               hipMemcpyDeviceToDevice, st));
+        unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
+        if (p.ckpt_mode == EFWI_CKPT_FP32)
+          HIP_TRY(hipMemcpyAsync(slot, r + p.off_state, p.state_bytes, hipMemcpyDeviceToDevice, st));
+        else
+          HIP_TRY(launch_ckpt_encode(reinterpret_cast<const float*>(r + p.off_state), p.fields,
+                                     reinterpret_cast<unsigned int*>(r + p.off_maxbits), slot, p.ckpt_mode, st));
       }
     }
     const int kstore = (checkpoints && n >= last0) ? n - last0 : -1;
@@ -626,10 +652,12 @@ efwi_status run_reverse(Wave& wv, unsigned char* ws, hipStream_t st) {
       for (size_t q = 0; q < wv.plans.size(); ++q) {
         const Plan2D& p = wv.plans[q];
         unsigned char* r = ws + wv.regions[q];
+        const unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
         if (k == 0) HIP_TRY(hipMemsetAsync(r + p.off_state, 0, p.state_bytes, st));
+        else if (p.ckpt_mode == EFWI_CKPT_FP32)
+          HIP_TRY(hipMemcpyAsync(r + p.off_state, slot, p.state_bytes, hipMemcpyDeviceToDevice, st));
         else
-          HIP_TRY(hipMemcpyAsync(r + p.off_state, r + p.off_ckpt + (size_t)(k - 1) * p.state_bytes, p.state_bytes,
-                                 hipMemcpyDeviceToDevice, st));
+          HIP_TRY(launch_ckpt_decode(reinterpret_cast<float*>(r + p.off_state), p.fields, slot, p.ckpt_mode, st));
       }
       for (int n = n0; n < n1; ++n) {
         HIP_TRY(TIMED(KK_FWD_VEL, st, launch_fwd_vel(wv.batch, n - n0, st)));
@@ -837,7 +865,6 @@ efwi_status efwi_shot_gradient(const efwi_grid* grid, const efwi_shot* shot, con
                                void* stream) {
   efwi_status rc = efwi_validate(grid, 1, shot);
   if (rc != EFWI_OK) return rc;
-  if (shot->ckpt_mode != EFWI_CKPT_FP32) return fail(EFWI_E_UNSUPPORTED, "16-bit checkpoints not built yet");
   if (!m || !src || !g || !phi || (shot->nch > 0 && !d_obs)) return fail(EFWI_E_INVAL, "NULL array argument");
   ShotIO io;
   io.m = m;
@@ -855,7 +882,6 @@ efwi_status efwi_shot_jt(const efwi_grid* grid, const efwi_shot* shot, const flo
                          const float* v, float* g, float* d_out, void* ws, size_t ws_bytes, void* stream) {
   efwi_status rc = efwi_validate(grid, 1, shot);
   if (rc != EFWI_OK) return rc;
-  if (shot->ckpt_mode != EFWI_CKPT_FP32) return fail(EFWI_E_UNSUPPORTED, "16-bit checkpoints not built yet");
   if (!m || !src || !g || (shot->nch > 0 && !v)) return fail(EFWI_E_INVAL, "NULL array argument");
   ShotIO io;
   io.m = m;
@@ -881,7 +907,6 @@ efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* 
   std::vector<ShotIO> io(ns);
   size_t off_obs = 0;
   for (int s = 0; s < ns; ++s) {
-    if (shots[s].ckpt_mode != EFWI_CKPT_FP32) return fail(EFWI_E_UNSUPPORTED, "16-bit checkpoints not built yet");
     if (shots[s].nch > 0 && !d_obs) return fail(EFWI_E_INVAL, "d_obs is NULL");
     io[s].m = m_ext + (size_t)s * 3 * plane;
     io[s].mplane = plane;

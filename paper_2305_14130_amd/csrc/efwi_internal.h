@@ -129,6 +129,20 @@ hipError_t launch_misfit(const Shot2D& s, const float* d, const float* dobs, dou
                          double* phi, float* ebar, hipStream_t st);
 hipError_t launch_residual_cumsum(const Shot2D& s, const float* r, float* ebar, hipStream_t st);
 
+// 16-bit checkpoints (checkpoint.hip): the 13 fields of a state block (five padded
+// wavefields, eight CPML strip arrays), as element offsets and lengths.
+constexpr int CKPT_NFIELDS = 13;
+constexpr int CKPT_HEADER = 256;          // bytes of per-field scales at the head of a slot
+constexpr int CKPT_CODEC_BF16 = 1;        // values of efwi_shot.ckpt_mode
+constexpr int CKPT_CODEC_FP16 = 2;
+struct CkptFields {
+  long off[CKPT_NFIELDS];
+  long len[CKPT_NFIELDS];
+};
+hipError_t launch_ckpt_encode(const float* state, const CkptFields& f, unsigned int* maxbits, void* slot, int codec,
+                              hipStream_t st);
+hipError_t launch_ckpt_decode(float* state, const CkptFields& f, const void* slot, int codec, hipStream_t st);
+
 // Regularizer (regularizer.hip).
 hipError_t launch_regularizer(int ns, long npts, long plane, const float* m_ext, const float* b,
                               const unsigned char* sink, float eta, float* g_ext, double* partial,
