@@ -59,17 +59,25 @@ def kernel_bytes_per_launch(name, cells, nt, L):
     return (nostore * plain + nt * store) / (nostore + nt) * cells
 
 
-def cpu_baseline(w, steps=8):
-    """FP64 oracle on one shot of the same grid for `steps` time steps (fwd + adj + grad)."""
+def cpu_baseline(w, target_s=12.0):
+    """FP64 oracle on one shot of the same grid, truncated in time (fwd + adj + grad): 8 steps
+    first, then a run sized to take about `target_s` seconds (at most 64 steps)."""
     from oracle import elastic2d as E
     sh = w.shots[0]
-    g = E.Grid2D(nz=w.nz, nx=w.nx, dz=w.dz, dx=w.dx, dt=w.dt, nt=steps, npml=w.npml, pml_R=w.pml_R,
-                 pml_f0=w.f0, vp_max=w.vp_max)
-    src = np.outer(sh.M, w.stf[:steps])
-    d_obs = np.zeros((len(sh.ch_iz), steps))
-    t0 = time.perf_counter()
-    E.shot_gradient(g, w.m_start, sh.src_iz, sh.src_ix, src, sh.ch_iz, sh.ch_ix, d_obs)
-    dt = time.perf_counter() - t0
+
+    def run(steps):
+        g = E.Grid2D(nz=w.nz, nx=w.nx, dz=w.dz, dx=w.dx, dt=w.dt, nt=steps, npml=w.npml, pml_R=w.pml_R,
+                     pml_f0=w.f0, vp_max=w.vp_max)
+        src = np.outer(sh.M, w.stf[:steps])
+        t0 = time.perf_counter()
+        E.shot_gradient(g, w.m_start, sh.src_iz, sh.src_ix, src, sh.ch_iz, sh.ch_ix, np.zeros((len(sh.ch_iz), steps)))
+        return time.perf_counter() - t0
+
+    steps = 8
+    dt = run(steps)
+    if dt < 0.5 * target_s:
+        steps = int(min(64, max(8, round(steps * target_s / dt))))
+        dt = run(steps)
     return {"value": w.nz * w.nx * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"1 shot, full {w.nz}x{w.nx} grid, {steps} of {w.nt} time steps, fwd+adj+grad, "
                       f"FP64 NumPy (single-threaded elementwise), {dt:.1f} s"}

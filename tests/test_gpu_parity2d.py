@@ -281,3 +281,44 @@ def test_batch_uneven_windows_and_waves(gpu_lib):
     with pytest.raises(efwi.EfwiError) as ei:
         efwi.batch_gradient(grid, shots, m_ext, src, torch.cat(d_obs), ws=efwi.workspace(one // 4))
     assert ei.value.status == efwi.E_WORKSPACE
+
+
+def test_full_size_sampled(gpu_lib):
+    """The bench's workload geometry at full size (1000 x 3000 at 2.5 m, CPML 40, 1500 DAS
+    channels, one moment-tensor shot, sqrt(nt) checkpoints), in the bench's launch
+    configuration, for nt = 120 steps: the wavefield travels < 50 cells, so the oracle on a
+    300 x 300 crop around the source reproduces the data at the channels inside the crop and
+    the gradient inside the crop's interior (its own absorbing strips lie beyond the waves).
+    Channels outside the crop carry zero data on both sides."""
+    efwi = gpu_lib
+    nt = 120
+    w = inputs.plain_2d(nshots=1, nt=nt)
+    sh = w.shots[0]
+    z0, x0, cz, cx = sh.src_iz - 150, sh.src_ix - 150, 300, 300
+    grid_o = E.Grid2D(nz=cz, nx=cx, dz=r32(w.dz), dx=r32(w.dx), dt=r32(w.dt), nt=nt, npml=w.npml,
+                      pml_R=r32(w.pml_R), pml_f0=r32(w.f0), vp_max=r32(w.vp_max))
+    m = _f32(w.m_start)
+    mt = _f32(w.m_true)
+    src = _f32(np.outer(sh.M, w.stf))
+    inside = (sh.ch_ix >= x0 + w.npml + 2) & (sh.ch_ix < x0 + cx - w.npml - 2)
+    cz_ch, cx_ch = sh.ch_iz[inside] - z0, sh.ch_ix[inside] - x0
+    crop = (slice(None), slice(z0, z0 + cz), slice(x0, x0 + cx))
+    d_obs_c = _f32(E.model_forward(grid_o, mt[crop], sh.src_iz - z0, sh.src_ix - x0, src, cz_ch, cx_ch))
+    g_o, phi_o, d_o = E.shot_gradient(grid_o, m[crop], sh.src_iz - z0, sh.src_ix - x0, src, cz_ch, cx_ch, d_obs_c)
+    d_obs = np.zeros((len(sh.ch_ix), nt))
+    d_obs[inside] = d_obs_c
+    grid = efwi.make_grid(w.nz, w.nx, w.dz, w.dx, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)
+    shot = efwi.Shot(sh.src_iz, sh.src_ix, sh.ch_iz, sh.ch_ix, ckpt_interval=0)
+    d_out = torch.empty((len(sh.ch_ix), nt), dtype=torch.float32, device="cuda")
+    g, phi = efwi.shot_gradient(grid, shot, T(m), T(src), T(d_obs), d_out=d_out)
+    torch.cuda.synchronize()
+    d = d_out.cpu().numpy()
+    assert rel(d[inside], d_o) <= TOL
+    assert np.max(np.abs(d[~inside])) <= 1e-6 * np.max(np.abs(d_o))
+    k = kappa(d_o, d_o - d_obs_c)
+    core = (slice(None), slice(z0 + 45, z0 + cz - 45), slice(x0 + 45, x0 + cx - 45))
+    ccore = (slice(None), slice(45, cz - 45), slice(45, cx - 45))
+    g = g.cpu().numpy()
+    for q in range(3):
+        assert rel(g[core][q], g_o[ccore][q]) <= TOL * k, q
+    assert abs(phi.item() - phi_o) / phi_o <= 2 * TOL * k
