@@ -1,13 +1,14 @@
 // 16-bit wavefield checkpoints with per-field max-abs scaling.
 //
-// A checkpoint holds one shot's forward state block (the five padded wavefields and the
-// eight CPML strip arrays: 13 fields). Each field gets one FP32 scale per snapshot:
+// A checkpoint holds one shot's forward state block (2D: the five padded wavefields and the
+// eight CPML strip arrays; 3D: nine and eighteen). Each field gets one FP32 scale per
+// snapshot:
 //   FP16: codes x / s, s = max|x| / 2^14 (largest code 16384 < 65504; values down to
 //         max|x| 2^-28 stay normal),
 //   BF16: codes x / s, s = max|x| (BF16 keeps FP32's exponent range).
 // Both round to nearest even; a zero field keeps s = 0 and decodes to zeros.
-// Slot layout: CKPT_HEADER bytes of scales (13 floats, padded), then one 16-bit code per
-// element of the state block, in the block's element order.
+// Slot layout: CKPT_HEADER bytes of scales (one float per field, padded), then one 16-bit
+// code per element of the state block, in the block's element order.
 #include <hip/hip_fp16.h>
 
 #include "efwi_internal.h"
@@ -80,17 +81,17 @@ __global__ __launch_bounds__(CB) void k_decode(float* __restrict__ state, CkptFi
 
 dim3 grid_for(const CkptFields& f) {
   long mx = 1;
-  for (int k = 0; k < CKPT_NFIELDS; ++k) mx = f.len[k] > mx ? f.len[k] : mx;
+  for (int k = 0; k < f.n; ++k) mx = f.len[k] > mx ? f.len[k] : mx;
   long nb = (mx + 4L * CB - 1) / (4L * CB);
   if (nb > 2048) nb = 2048;
-  return dim3((unsigned)nb, CKPT_NFIELDS);
+  return dim3((unsigned)nb, (unsigned)f.n);
 }
 
 }  // namespace
 
 hipError_t launch_ckpt_encode(const float* state, const CkptFields& f, unsigned int* maxbits, void* slot, int codec,
                               hipStream_t st) {
-  hipError_t e = hipMemsetAsync(maxbits, 0, CKPT_NFIELDS * sizeof(unsigned int), st);
+  hipError_t e = hipMemsetAsync(maxbits, 0, f.n * sizeof(unsigned int), st);
   if (e != hipSuccess) return e;
   const dim3 g = grid_for(f);
   k_maxabs<<<g, CB, 0, st>>>(state, f, maxbits);

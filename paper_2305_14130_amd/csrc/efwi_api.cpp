@@ -194,7 +194,7 @@ Sampler& sampler() {
 // Validation.
 // ----------------------------------------------------------------------------------------
 struct Window {
-  int z0, x0, wz, wx;
+  int z0, y0, x0, wz, wy, wx;
 };
 
 Window window_of(const efwi_grid& g, const efwi_shot& s) {
@@ -203,6 +203,9 @@ Window window_of(const efwi_grid& g, const efwi_shot& s) {
   w.x0 = s.x0;
   w.wz = s.wz > 0 ? s.wz : g.nz - s.z0;
   w.wx = s.wx > 0 ? s.wx : g.nx - s.x0;
+  const bool three = g.ndim == 3;
+  w.y0 = three ? s.y0 : 0;
+  w.wy = three ? (s.wy > 0 ? s.wy : g.ny - s.y0) : 1;
   return w;
 }
 
@@ -210,45 +213,47 @@ int strip_width(const efwi_grid& g) { return g.npml > 0 ? g.npml + 1 : 0; }
 
 efwi_status validate_grid(const efwi_grid* g) {
   if (!g) return fail(EFWI_E_INVAL, "grid is NULL");
-  if (g->ndim == 3) return fail(EFWI_E_UNSUPPORTED, "3D grids are not supported by this entry point");
-  if (g->ndim != 2) return fail(EFWI_E_INVAL, "ndim must be 2 (got %d)", g->ndim);
-  if (g->nz < 1 || g->nx < 1) return fail(EFWI_E_INVAL, "grid size %d x %d", g->nz, g->nx);
-  if (!(g->dx > 0.f) || !(g->dz > 0.f) || !(g->dt > 0.f))
-    return fail(EFWI_E_INVAL, "dx, dz, dt must be positive");
+  if (g->ndim != 2 && g->ndim != 3) return fail(EFWI_E_INVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
+  const bool three = g->ndim == 3;
+  if (g->nz < 1 || g->nx < 1 || (three && g->ny < 1)) return fail(EFWI_E_INVAL, "bad grid size");
+  if (!(g->dx > 0.f) || !(g->dz > 0.f) || !(g->dt > 0.f) || (three && !(g->dy > 0.f)))
+    return fail(EFWI_E_INVAL, "grid spacings and dt must be positive");
   if (g->nt < 1) return fail(EFWI_E_INVAL, "nt must be >= 1 (got %d)", g->nt);
   if (g->npml < 0) return fail(EFWI_E_INVAL, "npml must be >= 0");
   if (!(g->vp_max > 0.f)) return fail(EFWI_E_INVAL, "vp_max must be positive");
   if (g->npml > 0 && !(g->pml_R > 0.f && g->pml_R < 1.f)) return fail(EFWI_E_INVAL, "pml_R must be in (0, 1)");
   if (g->npml > 0 && !(g->pml_f0 >= 0.f)) return fail(EFWI_E_INVAL, "pml_f0 must be >= 0");
-  const double courant = (double)g->dt * g->vp_max * (9.0 / 8.0 + 1.0 / 24.0) *
-                         std::sqrt(1.0 / ((double)g->dx * g->dx) + 1.0 / ((double)g->dz * g->dz));
+  double inv2 = 1.0 / ((double)g->dx * g->dx) + 1.0 / ((double)g->dz * g->dz);
+  if (three) inv2 += 1.0 / ((double)g->dy * g->dy);
+  const double courant = (double)g->dt * g->vp_max * (9.0 / 8.0 + 1.0 / 24.0) * std::sqrt(inv2);
   if (!(courant < 1.0)) return fail(EFWI_E_CFL, "unstable time step: Courant number %.4f >= 1", courant);
   return EFWI_OK;
 }
 
 efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
   if (!s) return fail(EFWI_E_INVAL, "shot %d descriptor is NULL", index);
+  const bool three = g.ndim == 3;
   const Window w = window_of(g, *s);
   const int P = strip_width(g);
-  if (w.z0 < 0 || w.x0 < 0 || w.wz < 1 || w.wx < 1 || w.z0 + w.wz > g.nz || w.x0 + w.wx > g.nx)
-    return fail(EFWI_E_RANGE, "shot %d: window [%d,+%d) x [%d,+%d) outside the %d x %d model", index, w.z0, w.wz,
-                w.x0, w.wx, g.nz, g.nx);
-  if (w.wz < 2 * P + 4 || w.wx < 2 * P + 4)
-    return fail(EFWI_E_RANGE, "shot %d: window %d x %d too small for %d CPML cells", index, w.wz, w.wx, g.npml);
-  const int si = s->src_iz - w.z0, sj = s->src_ix - w.x0;
-  if (si < P + 1 || si > w.wz - P - 1 || sj < P + 1 || sj > w.wx - P - 1)
-    return fail(EFWI_E_RANGE, "shot %d: source (%d,%d) not in the window interior outside the CPML", index,
-                s->src_iz, s->src_ix);
+  if (w.z0 < 0 || w.x0 < 0 || w.y0 < 0 || w.wz < 1 || w.wx < 1 || w.wy < 1 || w.z0 + w.wz > g.nz ||
+      w.x0 + w.wx > g.nx || (three && w.y0 + w.wy > g.ny))
+    return fail(EFWI_E_RANGE, "shot %d: window outside the model", index);
+  if (w.wz < 2 * P + 4 || w.wx < 2 * P + 4 || (three && w.wy < 2 * P + 4))
+    return fail(EFWI_E_RANGE, "shot %d: window too small for %d CPML cells", index, g.npml);
+  const int si = s->src_iz - w.z0, sj = s->src_ix - w.x0, sk = three ? s->src_iy - w.y0 : 0;
+  if (si < P + 1 || si > w.wz - P - 1 || sj < P + 1 || sj > w.wx - P - 1 ||
+      (three && (sk < P + 1 || sk > w.wy - P - 1)))
+    return fail(EFWI_E_RANGE, "shot %d: source not in the window interior outside the CPML", index);
   if (s->nch < 0) return fail(EFWI_E_INVAL, "shot %d: nch < 0", index);
-  if (s->nch > 0 && (!s->ch_iz || !s->ch_ix)) return fail(EFWI_E_INVAL, "shot %d: channel arrays are NULL", index);
+  if (s->nch > 0 && (!s->ch_iz || !s->ch_ix || (three && !s->ch_iy)))
+    return fail(EFWI_E_INVAL, "shot %d: channel arrays are NULL", index);
   std::vector<long> keys;
   keys.reserve(s->nch);
   for (int c = 0; c < s->nch; ++c) {
-    const int ci = s->ch_iz[c] - w.z0, cj = s->ch_ix[c] - w.x0;
-    if (ci < P || ci > w.wz - P - 1 || cj < P || cj > w.wx - P - 1)
-      return fail(EFWI_E_RANGE, "shot %d: channel %d at (%d,%d) outside the window interior", index, c, s->ch_iz[c],
-                  s->ch_ix[c]);
-    keys.push_back((long)ci * w.wx + cj);
+    const int ci = s->ch_iz[c] - w.z0, cj = s->ch_ix[c] - w.x0, ck = three ? s->ch_iy[c] - w.y0 : 0;
+    if (ci < P || ci > w.wz - P - 1 || cj < P || cj > w.wx - P - 1 || (three && (ck < P || ck > w.wy - P - 1)))
+      return fail(EFWI_E_RANGE, "shot %d: channel %d outside the window interior", index, c);
+    keys.push_back(((long)ci * w.wy + ck) * w.wx + cj);
   }
   std::sort(keys.begin(), keys.end());
   if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
@@ -317,6 +322,7 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
                                                : align_up(CKPT_HEADER + p.state_elems * sizeof(unsigned short));
   {
     const long xs = (long)p.nz * 2 * p.P, zs = (long)2 * p.P * p.nx;
+    p.fields.n = 13;
     for (int k = 0; k < 5; ++k) {
       p.fields.off[k] = k * p.plane;
       p.fields.len[k] = p.plane;
@@ -693,8 +699,12 @@ efwi_status plan_waves(const std::vector<Plan2D>& plans, size_t ws_bytes, std::v
   return EFWI_OK;
 }
 
+efwi_status gradient_waves3(const efwi_grid& g, const efwi_shot* shots, int ns, const std::vector<ShotIO>& io,
+                            unsigned char* ws, size_t ws_bytes, hipStream_t st);
+
 efwi_status gradient_waves(const efwi_grid& g, const efwi_shot* shots, int ns, const std::vector<ShotIO>& io,
                            unsigned char* ws, size_t ws_bytes, hipStream_t st) {
+  if (g.ndim == 3) return gradient_waves3(g, shots, ns, io, ws, ws_bytes, st);
   std::vector<Plan2D> plans;
   for (int k = 0; k < ns; ++k) plans.push_back(plan2d(g, shots[k], EFWI_WS_GRADIENT));
   efwi_status rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
@@ -738,6 +748,400 @@ efwi_status check_same_schedule(const efwi_grid& g, int ns, const efwi_shot* sho
       return fail(EFWI_E_INVAL, "shots of one batch must share ckpt_interval and ckpt_mode");
   }
   return EFWI_OK;
+}
+
+// ========================================================================================
+// 3D: the same schedule on Shot3D descriptors.
+// ========================================================================================
+struct Plan3D {
+  Window w;
+  int nz, ny, nx, ld, cp, P, nslots, nt, nch, L, nseg, ntiles;
+  long pz, plane, cells;
+  size_t strips, state_elems, state_bytes, slot_bytes, tab_bytes, adj_bytes, par_bytes;
+  int ckpt_mode;
+  CkptFields fields;
+  size_t off_par, off_state, off_e, off_adj, off_ebar, off_partial, off_dint, off_acc, off_G, off_seg, off_ckpt,
+      off_maxbits, total;
+};
+
+int count_rows3(const efwi_shot& s, const Window& w) {
+  std::vector<long> rows;
+  for (int c = 0; c < s.nch; ++c) rows.push_back((long)(s.ch_iz[c] - w.z0) * w.wy + (s.ch_iy[c] - w.y0));
+  std::sort(rows.begin(), rows.end());
+  rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+  return (int)rows.size();
+}
+
+Plan3D plan3d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
+  Plan3D p{};
+  p.w = window_of(g, s);
+  p.nz = p.w.wz;
+  p.ny = p.w.wy;
+  p.nx = p.w.wx;
+  p.ld = (XOFF + p.nx + HALO + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
+  p.cp = (p.nx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
+  p.pz = (long)(p.ny + 2 * HALO) * p.ld;
+  p.plane = (long)(p.nz + 2 * HALO) * p.pz;
+  p.cells = (long)p.nz * p.ny * p.cp;
+  p.P = strip_width(g);
+  p.nt = g.nt;
+  p.nch = s.nch;
+  p.nslots = count_rows3(s, p.w);
+  p.ntiles = p.nz * ((p.ny + 3) / 4) * ((p.nx + 63) / 64);
+  p.L = interval_of(g, s);
+  p.nseg = (g.nt + p.L - 1) / p.L;
+  const long xs = (long)p.nz * p.ny * 2 * p.P, ys = (long)p.nz * 2 * p.P * p.nx, zs = (long)2 * p.P * p.ny * p.nx;
+  p.strips = (size_t)6 * (xs + ys + zs);
+  p.state_elems = (size_t)9 * p.plane + p.strips;
+  p.state_bytes = align_up(p.state_elems * sizeof(float));
+  p.adj_bytes = align_up(((size_t)9 * p.plane + 2 * p.strips) * sizeof(float));
+  p.par_bytes = align_up((size_t)8 * p.plane * sizeof(float));
+  p.tab_bytes = align_up((size_t)(4 * p.nx + 4 * p.ny + 4 * p.nz) * sizeof(float) +
+                         (size_t)p.nz * p.ny * sizeof(int) + (size_t)p.nslots * p.nx * sizeof(int));
+  p.ckpt_mode = s.ckpt_mode;
+  p.slot_bytes = s.ckpt_mode == EFWI_CKPT_FP32 ? p.state_bytes
+                                               : align_up(CKPT_HEADER + p.state_elems * sizeof(unsigned short));
+  p.fields.n = 27;
+  for (int k = 0; k < 9; ++k) {
+    p.fields.off[k] = k * p.plane;
+    p.fields.len[k] = p.plane;
+  }
+  long off = 9 * p.plane;
+  for (int k = 0; k < 18; ++k) {
+    const long len = k < 6 ? xs : (k < 12 ? ys : zs);
+    p.fields.off[9 + k] = off;
+    p.fields.len[9 + k] = len;
+    off += len;
+  }
+  const bool fwd = kind != EFWI_WS_ADJOINT;
+  const bool adj = kind != EFWI_WS_FORWARD;
+  const bool grad = kind == EFWI_WS_GRADIENT || kind == EFWI_WS_BATCH;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  p.off_par = take(p.par_bytes);
+  p.off_state = fwd ? take(p.state_bytes) : 0;
+  p.off_e = fwd ? take((size_t)std::max(1, p.nch) * sizeof(float)) : 0;
+  p.off_adj = adj ? take(p.adj_bytes) : 0;
+  p.off_ebar = adj ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
+  p.off_partial = grad ? take((size_t)std::max(1, p.nch) * sizeof(double)) : 0;
+  p.off_dint = grad ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
+  p.off_acc = grad ? take((size_t)NACC3 * p.cells * sizeof(float)) : 0;
+  p.off_G = grad ? take((size_t)3 * p.cells * sizeof(double)) : 0;
+  p.off_seg = grad ? take((size_t)p.L * NSEG3 * p.cells * sizeof(float)) : 0;
+  p.off_ckpt = grad ? take((size_t)std::max(0, p.nseg - 2) * p.slot_bytes) : 0;
+  p.off_maxbits = grad ? take(CKPT_NFIELDS * sizeof(unsigned int)) : 0;
+  p.total = o;
+  return p;
+}
+
+void build_tables3(const efwi_grid& g, const efwi_shot& s, const Plan3D& p, unsigned char* out) {
+  std::memset(out, 0, p.tab_bytes);
+  float* prof = reinterpret_cast<float*>(out);
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  cpml_profile(prof, prof + nx, nx, g.dx, g, false);
+  cpml_profile(prof + 2 * nx, prof + 3 * nx, nx, g.dx, g, true);
+  float* py = prof + 4 * nx;
+  cpml_profile(py, py + ny, ny, g.dy, g, false);
+  cpml_profile(py + 2 * ny, py + 3 * ny, ny, g.dy, g, true);
+  float* pz = py + 4 * ny;
+  cpml_profile(pz, pz + nz, nz, g.dz, g, false);
+  cpml_profile(pz + 2 * nz, pz + 3 * nz, nz, g.dz, g, true);
+  int* row_slot = reinterpret_cast<int*>(pz + 4 * nz);
+  int* rowch = row_slot + (size_t)nz * ny;
+  std::fill(row_slot, row_slot + (size_t)nz * ny, -1);
+  std::fill(rowch, rowch + (size_t)p.nslots * nx, -1);
+  int nslots = 0;
+  for (int c = 0; c < s.nch; ++c) {
+    const long row = (long)(s.ch_iz[c] - p.w.z0) * ny + (s.ch_iy[c] - p.w.y0);
+    if (row_slot[row] < 0) row_slot[row] = nslots++;
+    rowch[(size_t)row_slot[row] * nx + (s.ch_ix[c] - p.w.x0)] = c;
+  }
+}
+
+Shot3D make_desc3(const efwi_grid& g, const efwi_shot& s, const Plan3D& p, unsigned char* region, const float* tab,
+                  const ShotIO& io) {
+  Shot3D d{};
+  d.nz = p.nz, d.ny = p.ny, d.nx = p.nx, d.ld = p.ld, d.P = p.P, d.pz = p.pz;
+  d.nt = p.nt, d.nch = p.nch;
+  d.si = s.src_iz - p.w.z0, d.sk = s.src_iy - p.w.y0, d.sj = s.src_ix - p.w.x0;
+  d.dt = g.dt;
+  d.rdx = (float)(1.0 / g.dx), d.rdy = (float)(1.0 / g.dy), d.rdz = (float)(1.0 / g.dz);
+  d.w = (float)((double)g.dt / ((double)g.dx * g.dy * g.dz));
+  d.cp = p.cp, d.cells = p.cells;
+  const long interior = (long)HALO * p.pz + (long)HALO * p.ld + XOFF;
+  auto fields = [&](size_t off, gfloat** out, int count) {
+    gfloat* base = (gfloat*)(region + off);
+    for (int k = 0; k < count; ++k) out[k] = base + k * p.plane + interior;
+    return base + (size_t)count * p.plane;
+  };
+  const long xs = (long)p.nz * p.ny * 2 * p.P, ys = (long)p.nz * 2 * p.P * p.nx, zs = (long)2 * p.P * p.ny * p.nx;
+  auto strips_at = [&](gfloat* base, gfloat** sx, gfloat** sy, gfloat** sz) {
+    for (int k = 0; k < 6; ++k) sx[k] = base + k * xs;
+    for (int k = 0; k < 6; ++k) sy[k] = base + 6 * xs + k * ys;
+    for (int k = 0; k < 6; ++k) sz[k] = base + 6 * xs + 6 * ys + k * zs;
+  };
+  gfloat* f[9];
+  gfloat* st = fields(p.off_state, f, 9);
+  d.vx = f[0], d.vy = f[1], d.vz = f[2], d.sxx = f[3], d.syy = f[4], d.szz = f[5], d.sxy = f[6], d.sxz = f[7],
+  d.syz = f[8];
+  strips_at(st, d.psx, d.psy, d.psz);
+  st = fields(p.off_adj, f, 9);
+  d.uxb = f[0], d.uyb = f[1], d.uzb = f[2], d.txxb = f[3], d.tyyb = f[4], d.tzzb = f[5], d.txyb = f[6],
+  d.txzb = f[7], d.tyzb = f[8];
+  strips_at(st, d.pbx[0], d.pby[0], d.pbz[0]);
+  strips_at(st + p.strips, d.pbx[1], d.pby[1], d.pbz[1]);
+  fields(p.off_par, f, 8);
+  d.l2m = f[0], d.lam = f[1], d.muxy = f[2], d.muxz = f[3], d.muyz = f[4], d.bx = f[5], d.by = f[6], d.bz = f[7];
+  d.prof = (const gfloat*)(tab);
+  d.row_slot = (const gint*)(tab + 4 * p.nx + 4 * p.ny + 4 * p.nz);
+  d.rowch = d.row_slot + (long)p.nz * p.ny;
+  d.e = (gfloat*)(region + p.off_e);
+  d.ebar = (const gfloat*)(region + p.off_ebar);
+  d.acc = (gfloat*)(region + p.off_acc);
+  d.G = (gdouble*)(region + p.off_G);
+  d.seg = (gfloat*)(region + p.off_seg);
+  d.mld = g.nx;
+  d.mplanestride = (long)g.ny * g.nx;
+  if (io.m) {
+    const float* mw = io.m + (long)p.w.z0 * d.mplanestride + (long)p.w.y0 * d.mld + p.w.x0;
+    d.mvp = (const gfloat*)(mw);
+    d.mvs = (const gfloat*)(mw + io.mplane);
+    d.mrho = (const gfloat*)(mw + 2 * io.mplane);
+  }
+  d.src = (const gfloat*)(io.src);
+  d.src_bar = (gfloat*)(io.src_bar);
+  d.d = (gfloat*)(io.d ? io.d : reinterpret_cast<float*>(region + p.off_dint));
+  d.gout = (gfloat*)(io.gout);
+  d.mplane = io.mplane;
+  d.z0 = p.w.z0, d.y0 = p.w.y0, d.x0 = p.w.x0;
+  return d;
+}
+
+size_t header_bytes3(const std::vector<Plan3D>& plans, int first, int count) {
+  size_t tiles = 0, tabs = 0;
+  for (int k = first; k < first + count; ++k) {
+    tiles += plans[k].ntiles;
+    tabs += plans[k].tab_bytes;
+  }
+  return align_up((size_t)count * sizeof(Shot3D)) + align_up((size_t)count * sizeof(int)) +
+         align_up(tiles * sizeof(int)) + 2 * align_up(sched_capacity(tiles) * sizeof(int)) + tabs;
+}
+
+size_t wave_bytes3(const std::vector<Plan3D>& plans, int first, int count) {
+  size_t t = header_bytes3(plans, first, count);
+  for (int k = first; k < first + count; ++k) t += plans[k].total;
+  return t;
+}
+
+struct Wave3 {
+  std::vector<Plan3D> plans;
+  std::vector<Shot3D> descs;
+  std::vector<size_t> regions;
+  Batch3D batch{};
+  int L = 1, nseg = 1, nt = 0;
+};
+
+// Cut `weight` into NUM_XCD contiguous runs of equal total and write the schedule.
+efwi_status build_sched(const std::vector<int>& weight, int* sched, int& nsched) {
+  const int ntiles = (int)weight.size();
+  long wtot = 0;
+  for (int x : weight) wtot += x;
+  std::vector<int> cut(NUM_XCD + 1, ntiles);
+  cut[0] = 0;
+  long acc = 0;
+  for (int q = 0, k = 1; q < ntiles && k < NUM_XCD; ++q) {
+    acc += weight[q];
+    while (k < NUM_XCD && acc * NUM_XCD >= wtot * k) cut[k++] = q + 1;
+  }
+  int maxrun = 0;
+  for (int k = 0; k < NUM_XCD; ++k) maxrun = std::max(maxrun, cut[k + 1] - cut[k]);
+  if ((size_t)maxrun * NUM_XCD > sched_capacity(ntiles)) return fail(EFWI_E_INVAL, "tile schedule overflow");
+  for (int m = 0; m < maxrun; ++m)
+    for (int k = 0; k < NUM_XCD; ++k) sched[m * NUM_XCD + k] = (cut[k] + m < cut[k + 1]) ? cut[k] + m : -1;
+  nsched = maxrun * NUM_XCD;
+  return EFWI_OK;
+}
+
+efwi_status setup_wave3(const efwi_grid& g, const efwi_shot* shots, const std::vector<Plan3D>& plans, int first,
+                        int count, const std::vector<ShotIO>& io, efwi_ws_kind kind, unsigned char* ws, Wave3& wv,
+                        hipStream_t st) {
+  wv.plans.assign(plans.begin() + first, plans.begin() + first + count);
+  wv.nt = g.nt;
+  wv.L = wv.plans[0].L;
+  wv.nseg = wv.plans[0].nseg;
+  int ntiles = 0;
+  for (const Plan3D& p : wv.plans) ntiles += p.ntiles;
+  const size_t off_first = align_up((size_t)count * sizeof(Shot3D));
+  const size_t off_tshot = off_first + align_up((size_t)count * sizeof(int));
+  const size_t off_sched = off_tshot + align_up((size_t)ntiles * sizeof(int));
+  const size_t off_sched2 = off_sched + align_up(sched_capacity(ntiles) * sizeof(int));
+  size_t off_tab = off_sched2 + align_up(sched_capacity(ntiles) * sizeof(int));
+  const size_t hdr = header_bytes3(plans, first, count);
+  std::vector<unsigned char> blob(hdr, 0);
+  int* tfirst = reinterpret_cast<int*>(blob.data() + off_first);
+  int* tshot = reinterpret_cast<int*>(blob.data() + off_tshot);
+  size_t region = hdr;
+  int t = 0;
+  std::vector<int> weight;
+  wv.descs.clear();
+  wv.regions.clear();
+  for (int k = 0; k < count; ++k) {
+    const Plan3D& p = wv.plans[k];
+    const efwi_shot& s = shots[first + k];
+    tfirst[k] = t;
+    const int ntx = (p.nx + 63) / 64, nty = (p.ny + 3) / 4;
+    for (int q = 0; q < p.ntiles; ++q) {
+      tshot[t++] = k;
+      const int i = q / (ntx * nty), rem = q % (ntx * nty), k0 = (rem / ntx) * 4, j0 = (rem % ntx) * 64, pad = 2;
+      const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + 63 + pad >= p.nx - p.P) || (k0 - pad < p.P) ||
+                                   (k0 + 3 + pad >= p.ny - p.P) || (i - pad < p.P) || (i + pad >= p.nz - p.P));
+      weight.push_back(pml ? PML_TILE_WEIGHT : 1);
+    }
+    build_tables3(g, s, p, blob.data() + off_tab);
+    wv.descs.push_back(make_desc3(g, s, p, ws + region, reinterpret_cast<const float*>(ws + off_tab),
+                                  io[first + k]));
+    wv.regions.push_back(region);
+    off_tab += p.tab_bytes;
+    region += p.total;
+  }
+  std::memcpy(blob.data(), wv.descs.data(), (size_t)count * sizeof(Shot3D));
+  int nsched[2];
+  efwi_status rc = build_sched(std::vector<int>(ntiles, 1), reinterpret_cast<int*>(blob.data() + off_sched), nsched[0]);
+  if (rc != EFWI_OK) return rc;
+  rc = build_sched(weight, reinterpret_cast<int*>(blob.data() + off_sched2), nsched[1]);
+  if (rc != EFWI_OK) return rc;
+  wv.batch.shots = reinterpret_cast<const Shot3D*>(ws);
+  wv.batch.tile_first = reinterpret_cast<const int*>(ws + off_first);
+  wv.batch.tile_shot = reinterpret_cast<const int*>(ws + off_tshot);
+  wv.batch.even = Sched{reinterpret_cast<const int*>(ws + off_sched), nsched[0]};
+  wv.batch.weighted = Sched{reinterpret_cast<const int*>(ws + off_sched2), nsched[1]};
+  wv.batch.ns = count;
+  wv.batch.ntiles = ntiles;
+  const bool fwd = kind != EFWI_WS_ADJOINT;
+  const bool adj = kind != EFWI_WS_FORWARD;
+  const bool grad = kind == EFWI_WS_GRADIENT || kind == EFWI_WS_BATCH;
+  for (int k = 0; k < count; ++k) {
+    const Plan3D& p = wv.plans[k];
+    unsigned char* r = ws + wv.regions[k];
+    HIP_TRY(hipMemsetAsync(r + p.off_par, 0, p.par_bytes, st));
+    if (fwd) {
+      HIP_TRY(hipMemsetAsync(r + p.off_state, 0, p.state_bytes, st));
+      HIP_TRY(hipMemsetAsync(r + p.off_e, 0, (size_t)std::max(1, p.nch) * sizeof(float), st));
+    }
+    if (adj) HIP_TRY(hipMemsetAsync(r + p.off_adj, 0, p.adj_bytes, st));
+    if (grad) HIP_TRY(hipMemsetAsync(r + p.off_G, 0, (size_t)3 * p.cells * sizeof(double), st));
+  }
+  HIP_TRY(staging().upload(ws, blob.data(), blob.size(), st));
+  HIP_TRY(launch3_stage(wv.batch, st));
+  return EFWI_OK;
+}
+
+efwi_status save_or_restore3(Wave3& wv, unsigned char* ws, int k, bool save, hipStream_t st) {
+  for (size_t q = 0; q < wv.plans.size(); ++q) {
+    const Plan3D& p = wv.plans[q];
+    unsigned char* r = ws + wv.regions[q];
+    unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
+    float* state = reinterpret_cast<float*>(r + p.off_state);
+    if (save) {
+      if (p.ckpt_mode == EFWI_CKPT_FP32)
+        HIP_TRY(hipMemcpyAsync(slot, state, p.state_bytes, hipMemcpyDeviceToDevice, st));
+      else
+        HIP_TRY(launch_ckpt_encode(state, p.fields, reinterpret_cast<unsigned int*>(r + p.off_maxbits), slot,
+                                   p.ckpt_mode, st));
+    } else if (k == 0) {
+      HIP_TRY(hipMemsetAsync(state, 0, p.state_bytes, st));
+    } else if (p.ckpt_mode == EFWI_CKPT_FP32) {
+      HIP_TRY(hipMemcpyAsync(state, slot, p.state_bytes, hipMemcpyDeviceToDevice, st));
+    } else {
+      HIP_TRY(launch_ckpt_decode(state, p.fields, slot, p.ckpt_mode, st));
+    }
+  }
+  return EFWI_OK;
+}
+
+efwi_status run_forward3(Wave3& wv, unsigned char* ws, bool checkpoints, hipStream_t st) {
+  const int last0 = (wv.nseg - 1) * wv.L;
+  for (int n = 0; n < wv.nt; ++n) {
+    if (checkpoints && n % wv.L == 0 && n > 0 && n < last0) {
+      efwi_status rc = save_or_restore3(wv, ws, n / wv.L, true, st);
+      if (rc != EFWI_OK) return rc;
+    }
+    const int kstore = (checkpoints && n >= last0) ? n - last0 : -1;
+    HIP_TRY(TIMED(KK_FWD_VEL, st, launch3_fwd_vel(wv.batch, kstore, st)));
+    HIP_TRY(TIMED(KK_FWD_STR, st, launch3_fwd_str(wv.batch, n, kstore, true, st)));
+  }
+  return EFWI_OK;
+}
+
+efwi_status run_reverse3(Wave3& wv, unsigned char* ws, hipStream_t st) {
+  for (int k = wv.nseg - 1; k >= 0; --k) {
+    const int n0 = k * wv.L, n1 = std::min(wv.nt, n0 + wv.L);
+    if (k < wv.nseg - 1) {
+      efwi_status rc = save_or_restore3(wv, ws, k, false, st);
+      if (rc != EFWI_OK) return rc;
+      for (int n = n0; n < n1; ++n) {
+        HIP_TRY(TIMED(KK_FWD_VEL, st, launch3_fwd_vel(wv.batch, n - n0, st)));
+        HIP_TRY(TIMED(KK_FWD_STR, st, launch3_fwd_str(wv.batch, n, n - n0, false, st)));
+      }
+    }
+    for (int n = n1 - 1; n >= n0; --n) {
+      const bool first = (n == wv.nt - 1) || ((n + 1) % FLUSH_STEPS == 0);
+      HIP_TRY(TIMED(KK_ADJ_VEL, st, launch3_adj_vel(wv.batch, n, n - n0, true, first, false, st)));
+      HIP_TRY(TIMED(KK_ADJ_STR, st, launch3_adj_str(wv.batch, n, n - n0, true, first, st)));
+      if (n % FLUSH_STEPS == 0) HIP_TRY(TIMED(KK_CHAIN, st, launch3_chain_flush(wv.batch, st)));
+    }
+  }
+  return EFWI_OK;
+}
+
+efwi_status gradient_waves3(const efwi_grid& g, const efwi_shot* shots, int ns, const std::vector<ShotIO>& io,
+                            unsigned char* ws, size_t ws_bytes, hipStream_t st) {
+  std::vector<Plan3D> plans;
+  for (int k = 0; k < ns; ++k) plans.push_back(plan3d(g, shots[k], EFWI_WS_GRADIENT));
+  efwi_status rc = check_ws(ws, ws_bytes, wave_bytes3(plans, 0, 1));
+  if (rc != EFWI_OK) return rc;
+  int first = 0;
+  while (first < ns) {
+    int count = 0;
+    while (first + count < ns && wave_bytes3(plans, first, count + 1) <= ws_bytes) ++count;
+    if (count == 0) return fail(EFWI_E_WORKSPACE, "workspace too small for shot %d", first);
+    Wave3 wv;
+    rc = setup_wave3(g, shots, plans, first, count, io, EFWI_WS_GRADIENT, ws, wv, st);
+    if (rc != EFWI_OK) return rc;
+    rc = run_forward3(wv, ws, true, st);
+    if (rc != EFWI_OK) return rc;
+    for (int k = 0; k < count; ++k) {
+      const Plan3D& p = wv.plans[k];
+      unsigned char* r = ws + wv.regions[k];
+      float* ebar = reinterpret_cast<float*>(r + p.off_ebar);
+      if (io[first + k].r)
+        HIP_TRY(TIMED(KK_MISFIT, st, launch_residual_cumsum_raw(p.nch, p.nt, io[first + k].r, ebar, st)));
+      else
+        HIP_TRY(TIMED(KK_MISFIT, st,
+                      launch_misfit_raw(p.nch, p.nt, (const float*)(wv.descs[k].d), io[first + k].dobs,
+                                        reinterpret_cast<double*>(r + p.off_partial), io[first + k].phi, ebar, st)));
+    }
+    rc = run_reverse3(wv, ws, st);
+    if (rc != EFWI_OK) return rc;
+    for (int k = 0; k < count; ++k) {
+      const Plan3D& p = wv.plans[k];
+      const bool full = p.w.z0 == 0 && p.w.y0 == 0 && p.w.x0 == 0 && p.nz == g.nz && p.ny == g.ny && p.nx == g.nx;
+      if (!full) HIP_TRY(hipMemsetAsync(io[first + k].gout, 0, (size_t)3 * io[first + k].mplane * sizeof(float), st));
+    }
+    HIP_TRY(launch3_write_gradient(wv.batch, st));
+    first += count;
+  }
+  return EFWI_OK;
+}
+
+size_t workspace3(efwi_ws_kind kind, const efwi_grid& g, int n, const efwi_shot* shots) {
+  std::vector<Plan3D> plans;
+  for (int k = 0; k < n; ++k) plans.push_back(plan3d(g, shots[k], kind));
+  return wave_bytes3(plans, 0, n);
 }
 
 }  // namespace
@@ -803,11 +1207,12 @@ efwi_status efwi_validate(const efwi_grid* grid, int ns, const efwi_shot* shots)
 size_t efwi_workspace_size(efwi_ws_kind kind, const efwi_grid* grid, int ns, const efwi_shot* shots) {
   if (kind == EFWI_WS_REGULARIZER) {
     if (validate_grid(grid) != EFWI_OK) return 0;
-    const long npts = (long)grid->nz * grid->nx;
+    const long npts = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
     return align_up((size_t)regularizer_blocks(npts) * sizeof(double));
   }
   const int n = kind == EFWI_WS_BATCH ? ns : 1;
   if (efwi_validate(grid, n, shots) != EFWI_OK) return 0;
+  if (grid->ndim == 3) return workspace3(kind, *grid, n, shots);
   std::vector<Plan2D> plans;
   for (int k = 0; k < n; ++k) plans.push_back(plan2d(*grid, shots[k], kind));
   return wave_bytes(plans, 0, n);
@@ -819,15 +1224,24 @@ efwi_status efwi_model_forward(const efwi_grid* grid, const efwi_shot* shot, con
   if (rc != EFWI_OK) return rc;
   if (!m || !src || (shot->nch > 0 && !d)) return fail(EFWI_E_INVAL, "NULL array argument");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  std::vector<Plan2D> plans{plan2d(*grid, *shot, EFWI_WS_FORWARD)};
-  rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
-  if (rc != EFWI_OK) return rc;
   unsigned char* w = static_cast<unsigned char*>(ws);
   ShotIO io;
   io.m = m;
-  io.mplane = (long)grid->nz * grid->nx;
+  io.mplane = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
   io.src = src;
   io.d = d;
+  if (grid->ndim == 3) {
+    std::vector<Plan3D> plans{plan3d(*grid, *shot, EFWI_WS_FORWARD)};
+    rc = check_ws(ws, ws_bytes, wave_bytes3(plans, 0, 1));
+    if (rc != EFWI_OK) return rc;
+    Wave3 wv;
+    rc = setup_wave3(*grid, shot, plans, 0, 1, {io}, EFWI_WS_FORWARD, w, wv, st);
+    if (rc != EFWI_OK) return rc;
+    return run_forward3(wv, w, false, st);
+  }
+  std::vector<Plan2D> plans{plan2d(*grid, *shot, EFWI_WS_FORWARD)};
+  rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
+  if (rc != EFWI_OK) return rc;
   Wave wv;
   rc = setup_wave(*grid, shot, plans, 0, 1, {io}, EFWI_WS_FORWARD, w, wv, st);
   if (rc != EFWI_OK) return rc;
@@ -840,14 +1254,29 @@ efwi_status efwi_model_adjoint(const efwi_grid* grid, const efwi_shot* shot, con
   if (rc != EFWI_OK) return rc;
   if (!m || !src_bar || (shot->nch > 0 && !r)) return fail(EFWI_E_INVAL, "NULL array argument");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  std::vector<Plan2D> plans{plan2d(*grid, *shot, EFWI_WS_ADJOINT)};
-  rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
-  if (rc != EFWI_OK) return rc;
   unsigned char* w = static_cast<unsigned char*>(ws);
   ShotIO io;
   io.m = m;
-  io.mplane = (long)grid->nz * grid->nx;
+  io.mplane = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
   io.src_bar = src_bar;
+  if (grid->ndim == 3) {
+    std::vector<Plan3D> plans{plan3d(*grid, *shot, EFWI_WS_ADJOINT)};
+    rc = check_ws(ws, ws_bytes, wave_bytes3(plans, 0, 1));
+    if (rc != EFWI_OK) return rc;
+    Wave3 wv;
+    rc = setup_wave3(*grid, shot, plans, 0, 1, {io}, EFWI_WS_ADJOINT, w, wv, st);
+    if (rc != EFWI_OK) return rc;
+    const Plan3D& p = wv.plans[0];
+    HIP_TRY(launch_residual_cumsum_raw(p.nch, p.nt, r, reinterpret_cast<float*>(w + wv.regions[0] + p.off_ebar), st));
+    for (int n = p.nt - 1; n >= 0; --n) {
+      HIP_TRY(TIMED(KK_ADJ_VEL, st, launch3_adj_vel(wv.batch, n, 0, false, false, true, st)));
+      HIP_TRY(TIMED(KK_ADJ_STR, st, launch3_adj_str(wv.batch, n, 0, false, false, st)));
+    }
+    return EFWI_OK;
+  }
+  std::vector<Plan2D> plans{plan2d(*grid, *shot, EFWI_WS_ADJOINT)};
+  rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
+  if (rc != EFWI_OK) return rc;
   Wave wv;
   rc = setup_wave(*grid, shot, plans, 0, 1, {io}, EFWI_WS_ADJOINT, w, wv, st);
   if (rc != EFWI_OK) return rc;
@@ -868,7 +1297,7 @@ efwi_status efwi_shot_gradient(const efwi_grid* grid, const efwi_shot* shot, con
   if (!m || !src || !g || !phi || (shot->nch > 0 && !d_obs)) return fail(EFWI_E_INVAL, "NULL array argument");
   ShotIO io;
   io.m = m;
-  io.mplane = (long)grid->nz * grid->nx;
+  io.mplane = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
   io.src = src;
   io.dobs = d_obs;
   io.d = d_out;
@@ -885,7 +1314,7 @@ efwi_status efwi_shot_jt(const efwi_grid* grid, const efwi_shot* shot, const flo
   if (!m || !src || !g || (shot->nch > 0 && !v)) return fail(EFWI_E_INVAL, "NULL array argument");
   ShotIO io;
   io.m = m;
-  io.mplane = (long)grid->nz * grid->nx;
+  io.mplane = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
   io.src = src;
   io.r = v;
   io.d = d_out;
@@ -903,14 +1332,15 @@ efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* 
   if (!m_ext || !src || !g_ext || !phi) return fail(EFWI_E_INVAL, "NULL array argument");
   rc = check_same_schedule(*grid, ns, shots);
   if (rc != EFWI_OK) return rc;
-  const long plane = (long)grid->nz * grid->nx;
+  const long plane = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
+  const int ncomp = grid->ndim == 3 ? 6 : 3;
   std::vector<ShotIO> io(ns);
   size_t off_obs = 0;
   for (int s = 0; s < ns; ++s) {
     if (shots[s].nch > 0 && !d_obs) return fail(EFWI_E_INVAL, "d_obs is NULL");
     io[s].m = m_ext + (size_t)s * 3 * plane;
     io[s].mplane = plane;
-    io[s].src = src + (size_t)s * 3 * grid->nt;
+    io[s].src = src + (size_t)s * ncomp * grid->nt;
     io[s].dobs = d_obs ? d_obs + off_obs : nullptr;
     io[s].gout = g_ext + (size_t)s * 3 * plane;
     io[s].phi = phi + s;
@@ -929,7 +1359,7 @@ efwi_status efwi_extension_regularizer(const efwi_grid* grid, int ns, const floa
   if (ns < 1) return fail(EFWI_E_INVAL, "ns must be >= 1");
   if (!m_ext || !b || !sink || !g_ext || !phi) return fail(EFWI_E_INVAL, "NULL array argument");
   if (!std::isfinite(eta)) return fail(EFWI_E_INVAL, "eta is not finite");
-  const long npts = (long)grid->nz * grid->nx;
+  const long npts = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
   const int nb = regularizer_blocks(npts);
   rc = check_ws(ws, ws_bytes, align_up((size_t)nb * sizeof(double)));
   if (rc != EFWI_OK) return rc;

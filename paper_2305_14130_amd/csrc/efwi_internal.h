@@ -128,16 +128,22 @@ hipError_t launch_write_gradient(const Batch2D& b, hipStream_t st);
 hipError_t launch_misfit(const Shot2D& s, const float* d, const float* dobs, double* partial,
                          double* phi, float* ebar, hipStream_t st);
 hipError_t launch_residual_cumsum(const Shot2D& s, const float* r, float* ebar, hipStream_t st);
+// The same on plain sizes (any dimension): d, d_obs, r [nch][nt]; e_bar [nt][nch].
+hipError_t launch_misfit_raw(int nch, int nt, const float* d, const float* dobs, double* partial, double* phi,
+                             float* ebar, hipStream_t st);
+hipError_t launch_residual_cumsum_raw(int nch, int nt, const float* r, float* ebar, hipStream_t st);
 
-// 16-bit checkpoints (checkpoint.hip): the 13 fields of a state block (five padded
-// wavefields, eight CPML strip arrays), as element offsets and lengths.
-constexpr int CKPT_NFIELDS = 13;
+// 16-bit checkpoints (checkpoint.hip): the fields of a state block (2D: five padded
+// wavefields and eight CPML strip arrays; 3D: nine and eighteen), as element offsets and
+// lengths; `n` is the number of fields used.
+constexpr int CKPT_NFIELDS = 27;
 constexpr int CKPT_HEADER = 256;          // bytes of per-field scales at the head of a slot
 constexpr int CKPT_CODEC_BF16 = 1;        // values of efwi_shot.ckpt_mode
 constexpr int CKPT_CODEC_FP16 = 2;
 struct CkptFields {
   long off[CKPT_NFIELDS];
   long len[CKPT_NFIELDS];
+  int n;
 };
 hipError_t launch_ckpt_encode(const float* state, const CkptFields& f, unsigned int* maxbits, void* slot, int codec,
                               hipStream_t st);
@@ -148,5 +154,64 @@ hipError_t launch_regularizer(int ns, long npts, long plane, const float* m_ext,
                               const unsigned char* sink, float eta, float* g_ext, double* partial,
                               int nblocks, double* phi, hipStream_t st);
 int regularizer_blocks(long npts);
+
+// ---------------------------------------------------------------------------------------
+// 3D. Arrays are [nz][ny][nx]; padded arrays have the same zero halo in z and y as in 2D
+// and the XOFF / ROW_ALIGN layout in x; element (i, k, j) is at p[i * pz + k * ld + j].
+// ---------------------------------------------------------------------------------------
+constexpr int NSEG3 = 9;   // stored per step: tr/(3l+2m), dev_xx/m, dev_yy/m (normal node),
+                           // three shear strain rates / shear moduli, qx/bx, qy/by, qz/bz
+constexpr int NACC3 = 8;   // imaging sums: lambda, deviatoric mu, mu_xy, mu_xz, mu_yz, bx, by, bz
+
+struct Shot3D {
+  int nz, ny, nx, ld, P;
+  long pz;                      // padded plane stride
+  int nt, nch;
+  int si, sk, sj;               // source normal node (window coordinates)
+  float dt, rdx, rdy, rdz, w;   // w = dt / (dx dy dz)
+  int cp;                       // x pitch of the unpadded per-cell arrays
+  long cells;                   // nz * ny * cp
+  gfloat *vx, *vy, *vz, *sxx, *syy, *szz, *sxy, *sxz, *syz;
+  gfloat* psx[6];               // x-strips [nz][ny][2P]
+  gfloat* psy[6];               // y-strips [nz][2P][nx]
+  gfloat* psz[6];               // z-strips [2P][ny][nx]
+  gfloat *uxb, *uyb, *uzb, *txxb, *tyyb, *tzzb, *txyb, *txzb, *tyzb;   // scaled adjoint state
+  gfloat* pbx[2][6];
+  gfloat* pby[2][6];
+  gfloat* pbz[2][6];
+  gfloat *l2m, *lam, *muxy, *muxz, *muyz, *bx, *by, *bz;
+  const gfloat* prof;           // x: a_int b_int a_half b_half [nx] each, then y [ny], then z [nz]
+  const gfloat* src;            // [6][nt]
+  gfloat* src_bar;
+  const gint* row_slot;         // [nz * ny]
+  const gint* rowch;            // [nslots][nx]
+  gfloat* e;
+  gfloat* d;
+  const gfloat* ebar;
+  const gfloat *mvp, *mvs, *mrho;
+  long mld, mplanestride;       // x pitch and z-plane stride of the full model
+  gfloat* seg;                  // [L][9][cells]
+  gfloat* acc;                  // [8][cells]
+  gdouble* G;                   // [3][cells]
+  gfloat* gout;
+  long mplane;                  // elements of one full-model parameter volume
+  int z0, y0, x0;
+};
+
+struct Batch3D {
+  const Shot3D* shots;
+  const int* tile_shot;
+  const int* tile_first;
+  Sched even, weighted;
+  int ns, ntiles;
+};
+
+hipError_t launch3_stage(const Batch3D& b, hipStream_t st);
+hipError_t launch3_fwd_vel(const Batch3D& b, int kstore, hipStream_t st);
+hipError_t launch3_fwd_str(const Batch3D& b, int n, int kstore, bool record, hipStream_t st);
+hipError_t launch3_adj_vel(const Batch3D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st);
+hipError_t launch3_adj_str(const Batch3D& b, int n, int k, bool grad, bool first, hipStream_t st);
+hipError_t launch3_chain_flush(const Batch3D& b, hipStream_t st);
+hipError_t launch3_write_gradient(const Batch3D& b, hipStream_t st);
 
 }  // namespace efwi

@@ -703,20 +703,25 @@ hipError_t launch_write_gradient(const Batch2D& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_misfit(const Shot2D& s, const float* d, const float* dobs, double* partial, double* phi,
-                         float* ebar, hipStream_t st) {
-  if (s.nch > 0) {
-    k_residual<<<(s.nch + 127) / 128, 128, 0, st>>>(d, dobs, s.nch, s.nt, partial, ebar);
-    k_reduce_phi<<<1, 256, 0, st>>>(partial, s.nch, phi);
-  } else {
-    k_reduce_phi<<<1, 256, 0, st>>>(partial, 0, phi);
-  }
+hipError_t launch_misfit_raw(int nch, int nt, const float* d, const float* dobs, double* partial, double* phi,
+                             float* ebar, hipStream_t st) {
+  if (nch > 0) k_residual<<<(nch + 127) / 128, 128, 0, st>>>(d, dobs, nch, nt, partial, ebar);
+  k_reduce_phi<<<1, 256, 0, st>>>(partial, nch > 0 ? nch : 0, phi);
   return hipGetLastError();
 }
 
-hipError_t launch_residual_cumsum(const Shot2D& s, const float* r, float* ebar, hipStream_t st) {
-  if (s.nch > 0) k_residual<<<(s.nch + 127) / 128, 128, 0, st>>>(r, nullptr, s.nch, s.nt, nullptr, ebar);
+hipError_t launch_residual_cumsum_raw(int nch, int nt, const float* r, float* ebar, hipStream_t st) {
+  if (nch > 0) k_residual<<<(nch + 127) / 128, 128, 0, st>>>(r, nullptr, nch, nt, nullptr, ebar);
   return hipGetLastError();
+}
+
+hipError_t launch_misfit(const Shot2D& s, const float* d, const float* dobs, double* partial, double* phi,
+                         float* ebar, hipStream_t st) {
+  return launch_misfit_raw(s.nch, s.nt, d, dobs, partial, phi, ebar, st);
+}
+
+hipError_t launch_residual_cumsum(const Shot2D& s, const float* r, float* ebar, hipStream_t st) {
+  return launch_residual_cumsum_raw(s.nch, s.nt, r, ebar, st);
 }
 
 }  // namespace efwi

@@ -1,0 +1,615 @@
+// 3D isotropic elastic velocity-stress kernels for gfx950: forward, exact transpose (in
+// scaled adjoint variables), imaging condition, chain rule. The 3D counterpart of
+// kernels2d.hip (Forward problem eqs.(1)-(3); Solving the inverse problem eqs.(4),(6);
+// Model extension eq.(8)).
+//
+// Staggering: sxx, syy, szz at (i, k, j); vx (i, k, j+1/2); vy (i, k+1/2, j);
+// vz (i+1/2, k, j); sxy (i, k+1/2, j+1/2); sxz (i+1/2, k, j+1/2); syz (i+1/2, k+1/2, j).
+// i = z, k = y, j = x. 4th-order differences, zero outside the grid (zero halo), leapfrog,
+// unsplit CPML (kappa = 1) with memory variables in strips on every face.
+//
+// Tiles are 64 (x) by 4 (y) cells of one z plane; one thread owns one cell. The adjoint
+// carries u_bar = b v_bar and t_bar = C sigma_bar (C: lambda 1 1^T + 2 mu I on the normal
+// block, the shear moduli on the shear components), so its transposed differences read one
+// array per neighbour, and the imaging condition uses forward quantities stored
+// pre-divided by the moduli:
+//   g_lambda       += dt tr(t) tr(p) / (3l + 2m)          = dt tr(sigma_bar) tr(p)
+//   g_mu (normal)   = 2/3 g_lambda + dt dev(t) : dev(p) / m = 2 dt sum_c sigma_bar_cc p_cc
+//   g_mu_xy        += dt t_xy (D+y vx + D+x vy) / mu_xy    (and xz, yz)
+//   g_b_x          += dt u_x q_x / b_x                     (and y, z)
+#include "efwi_internal.h"
+
+namespace efwi {
+namespace {
+
+constexpr float K1 = 1.125f;
+constexpr float K2 = -0.041666666666666664f;
+constexpr int TX = 64, TY = 4;
+
+// Strip slots. x-strips: vx(D+x sxx) vy(D-x sxy) vz(D-x sxz) pxx(D-x vx) sxy(D+x vy) sxz(D+x vz)
+enum { XS_VX = 0, XS_VY, XS_VZ, XS_PXX, XS_SXY, XS_SXZ };
+// y-strips: vx(D-y sxy) vy(D+y syy) vz(D-y syz) pyy(D-y vy) sxy(D+y vx) syz(D+y vz)
+enum { YS_VX = 0, YS_VY, YS_VZ, YS_PYY, YS_SXY, YS_SYZ };
+// z-strips: vx(D-z sxz) vy(D-z syz) vz(D+z szz) pzz(D-z vz) sxz(D+z vx) syz(D+z vy)
+enum { ZS_VX = 0, ZS_VY, ZS_VZ, ZS_PZZ, ZS_SXZ, ZS_SYZ };
+// profile tables: 0 a_int, 1 b_int, 2 a_half, 3 b_half (D- uses int, D+ uses half)
+__device__ __forceinline__ const gfloat* px_(const Shot3D& s, int w) { return s.prof + w * s.nx; }
+__device__ __forceinline__ const gfloat* py_(const Shot3D& s, int w) { return s.prof + 4 * s.nx + w * s.ny; }
+__device__ __forceinline__ const gfloat* pz_(const Shot3D& s, int w) { return s.prof + 4 * s.nx + 4 * s.ny + w * s.nz; }
+
+template <class P>
+__device__ __forceinline__ float dplus(P f, long o, long st, float r) {
+  return (K1 * (f[o + st] - f[o]) + K2 * (f[o + 2 * st] - f[o - st])) * r;
+}
+template <class P>
+__device__ __forceinline__ float dminus(P f, long o, long st, float r) {
+  return (K1 * (f[o] - f[o - st]) + K2 * (f[o + st] - f[o - 2 * st])) * r;
+}
+
+__device__ __forceinline__ long xq(const Shot3D& s, int i, int k, int sx) { return ((long)i * s.ny + k) * 2 * s.P + sx; }
+__device__ __forceinline__ long yq(const Shot3D& s, int i, int sy, int j) { return ((long)i * 2 * s.P + sy) * s.nx + j; }
+__device__ __forceinline__ long zq(const Shot3D& s, int sz, int k, int j) { return ((long)sz * s.ny + k) * s.nx + j; }
+
+__device__ __forceinline__ bool tile_in_pml(const Shot3D& s, int i, int k0, int j0, int pad) {
+  if (s.P <= 0) return false;
+  return (j0 - pad < s.P) || (j0 + TX - 1 + pad >= s.nx - s.P) || (k0 - pad < s.P) ||
+         (k0 + TY - 1 + pad >= s.ny - s.P) || (i - pad < s.P) || (i + pad >= s.nz - s.P);
+}
+
+// Tile list per shot: z plane, y band, x block (x fastest). Schedule as in 2D.
+__device__ __forceinline__ bool tile3(const int* __restrict__ sched, const int* __restrict__ tile_shot,
+                                      const int* __restrict__ tile_first, const Shot3D* __restrict__ shots, int& sh,
+                                      int& i, int& k0, int& j0) {
+  const int t = sched[blockIdx.x];
+  if (t < 0) return false;
+  sh = tile_shot[t];
+  const int local = t - tile_first[sh];
+  const int ntx = (shots[sh].nx + TX - 1) / TX, nty = (shots[sh].ny + TY - 1) / TY;
+  i = local / (ntx * nty);
+  const int rem = local % (ntx * nty);
+  k0 = (rem / ntx) * TY;
+  j0 = (rem % ntx) * TX;
+  return true;
+}
+
+#define PARAMS3                                                                                      \
+  const Shot3D* __restrict__ shots, const int* __restrict__ tile_shot, const int* __restrict__ tile_first, \
+      const int* __restrict__ sched
+#define TILE3()                                                                                       \
+  int sh_, i, k0, j0;                                                                                  \
+  if (!tile3(sched, tile_shot, tile_first, shots, sh_, i, k0, j0)) return;                            \
+  const Shot3D& s = shots[sh_];                                                                        \
+  const int j = j0 + threadIdx.x, k = k0 + threadIdx.y
+
+// CPML update psi <- b psi + a D at an owned node; returns D + psi.
+__device__ __forceinline__ float cpml(gfloat* psi, long q, const gfloat* a, const gfloat* b, int c, float d) {
+  const float p = b[c] * psi[q] + a[c] * d;
+  psi[q] = p;
+  return d + p;
+}
+
+// ------------------------------------------------------------------------------------
+// Forward velocity half step.
+// ------------------------------------------------------------------------------------
+template <bool STORE, bool PML>
+__device__ __forceinline__ void fwd_vel3(const Shot3D& s, int i, int k, int j, gfloat* seg) {
+  const long ld = s.ld, pz = s.pz;
+  const long o = (long)i * pz + (long)k * ld + j;
+  float a1 = dplus(s.sxx, o, 1, s.rdx), a2 = dminus(s.sxy, o, ld, s.rdy), a3 = dminus(s.sxz, o, pz, s.rdz);
+  float b1 = dminus(s.sxy, o, 1, s.rdx), b2 = dplus(s.syy, o, ld, s.rdy), b3 = dminus(s.syz, o, pz, s.rdz);
+  float c1 = dminus(s.sxz, o, 1, s.rdx), c2 = dminus(s.syz, o, ld, s.rdy), c3 = dplus(s.szz, o, pz, s.rdz);
+  if (PML) {
+    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+    if (sx >= 0) {
+      const long q = xq(s, i, k, sx);
+      a1 = cpml(s.psx[XS_VX], q, px_(s, 2), px_(s, 3), j, a1);
+      b1 = cpml(s.psx[XS_VY], q, px_(s, 0), px_(s, 1), j, b1);
+      c1 = cpml(s.psx[XS_VZ], q, px_(s, 0), px_(s, 1), j, c1);
+    }
+    if (sy >= 0) {
+      const long q = yq(s, i, sy, j);
+      a2 = cpml(s.psy[YS_VX], q, py_(s, 0), py_(s, 1), k, a2);
+      b2 = cpml(s.psy[YS_VY], q, py_(s, 2), py_(s, 3), k, b2);
+      c2 = cpml(s.psy[YS_VZ], q, py_(s, 0), py_(s, 1), k, c2);
+    }
+    if (sz >= 0) {
+      const long q = zq(s, sz, k, j);
+      a3 = cpml(s.psz[ZS_VX], q, pz_(s, 0), pz_(s, 1), i, a3);
+      b3 = cpml(s.psz[ZS_VY], q, pz_(s, 0), pz_(s, 1), i, b3);
+      c3 = cpml(s.psz[ZS_VZ], q, pz_(s, 2), pz_(s, 3), i, c3);
+    }
+  }
+  const float qx = a1 + a2 + a3, qy = b1 + b2 + b3, qz = c1 + c2 + c3;
+  s.vx[o] += s.dt * s.bx[o] * qx;
+  s.vy[o] += s.dt * s.by[o] * qy;
+  s.vz[o] += s.dt * s.bz[o] * qz;
+  if (STORE) {
+    const long c = ((long)i * s.ny + k) * s.cp + j;
+    seg[6 * s.cells + c] = qx / s.bx[o];
+    seg[7 * s.cells + c] = qy / s.by[o];
+    seg[8 * s.cells + c] = qz / s.bz[o];
+  }
+}
+
+template <bool STORE>
+__global__ __launch_bounds__(TX * TY) void k3_fwd_vel(PARAMS3, int kstore) {
+  TILE3();
+  if (k >= s.ny || j >= s.nx) return;
+  gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG3 * s.cells : nullptr;
+  if (tile_in_pml(s, i, k0, j0, 0)) fwd_vel3<STORE, true>(s, i, k, j, seg);
+  else fwd_vel3<STORE, false>(s, i, k, j, seg);
+}
+
+// ------------------------------------------------------------------------------------
+// Forward stress half step + six-component moment-tensor injection + DAS e_xx record.
+// ------------------------------------------------------------------------------------
+template <bool STORE, bool RECORD, bool PML>
+__device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, int n, gfloat* seg) {
+  const long ld = s.ld, pz = s.pz;
+  const long o = (long)i * pz + (long)k * ld + j;
+  float pxx = dminus(s.vx, o, 1, s.rdx), pyy = dminus(s.vy, o, ld, s.rdy), pzz = dminus(s.vz, o, pz, s.rdz);
+  float vx_y = dplus(s.vx, o, ld, s.rdy), vy_x = dplus(s.vy, o, 1, s.rdx);
+  float vx_z = dplus(s.vx, o, pz, s.rdz), vz_x = dplus(s.vz, o, 1, s.rdx);
+  float vy_z = dplus(s.vy, o, pz, s.rdz), vz_y = dplus(s.vz, o, ld, s.rdy);
+  const float raw_pxx = pxx;
+  if (PML) {
+    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+    if (sx >= 0) {
+      const long q = xq(s, i, k, sx);
+      pxx = cpml(s.psx[XS_PXX], q, px_(s, 0), px_(s, 1), j, pxx);
+      vy_x = cpml(s.psx[XS_SXY], q, px_(s, 2), px_(s, 3), j, vy_x);
+      vz_x = cpml(s.psx[XS_SXZ], q, px_(s, 2), px_(s, 3), j, vz_x);
+    }
+    if (sy >= 0) {
+      const long q = yq(s, i, sy, j);
+      pyy = cpml(s.psy[YS_PYY], q, py_(s, 0), py_(s, 1), k, pyy);
+      vx_y = cpml(s.psy[YS_SXY], q, py_(s, 2), py_(s, 3), k, vx_y);
+      vz_y = cpml(s.psy[YS_SYZ], q, py_(s, 2), py_(s, 3), k, vz_y);
+    }
+    if (sz >= 0) {
+      const long q = zq(s, sz, k, j);
+      pzz = cpml(s.psz[ZS_PZZ], q, pz_(s, 0), pz_(s, 1), i, pzz);
+      vx_z = cpml(s.psz[ZS_SXZ], q, pz_(s, 2), pz_(s, 3), i, vx_z);
+      vy_z = cpml(s.psz[ZS_SYZ], q, pz_(s, 2), pz_(s, 3), i, vy_z);
+    }
+  }
+  const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
+  const float tr = pxx + pyy + pzz;
+  const float sxy_r = vx_y + vy_x, sxz_r = vx_z + vz_x, syz_r = vy_z + vz_y;
+  float sxx = s.sxx[o] + s.dt * (lam * tr + two_mu * pxx);
+  float syy = s.syy[o] + s.dt * (lam * tr + two_mu * pyy);
+  float szz = s.szz[o] + s.dt * (lam * tr + two_mu * pzz);
+  float sxy = s.sxy[o] + s.dt * s.muxy[o] * sxy_r;
+  float sxz = s.sxz[o] + s.dt * s.muxz[o] * sxz_r;
+  float syz = s.syz[o] + s.dt * s.muyz[o] * syz_r;
+  const int nt = s.nt;
+  if (i == s.si && k == s.sk && j == s.sj) {
+    sxx -= s.w * s.src[n];
+    syy -= s.w * s.src[nt + n];
+    szz -= s.w * s.src[2 * nt + n];
+  }
+  const bool ii = (i == s.si || i == s.si - 1), kk = (k == s.sk || k == s.sk - 1), jj = (j == s.sj || j == s.sj - 1);
+  if (i == s.si && kk && jj) sxy -= 0.25f * s.w * s.src[3 * nt + n];
+  if (ii && k == s.sk && jj) sxz -= 0.25f * s.w * s.src[4 * nt + n];
+  if (ii && kk && j == s.sj) syz -= 0.25f * s.w * s.src[5 * nt + n];
+  s.sxx[o] = sxx;
+  s.syy[o] = syy;
+  s.szz[o] = szz;
+  s.sxy[o] = sxy;
+  s.sxz[o] = sxz;
+  s.syz[o] = syz;
+  if (RECORD) {
+    const int slot = s.row_slot[(long)i * s.ny + k];
+    if (slot >= 0) {
+      const int c = s.rowch[(long)slot * s.nx + j];
+      if (c >= 0) {
+        const float e = s.e[c] + s.dt * raw_pxx;
+        s.e[c] = e;
+        s.d[(long)c * nt + n] = e;
+      }
+    }
+  }
+  if (STORE) {
+    const long c = ((long)i * s.ny + k) * s.cp + j;
+    const float mu = 0.5f * two_mu, third = tr * (1.0f / 3.0f);
+    const float mxy = s.muxy[o], mxz = s.muxz[o], myz = s.muyz[o];
+    seg[c] = tr / (l2m + 2.0f * lam);
+    seg[s.cells + c] = (pxx - third) / mu;
+    seg[2 * s.cells + c] = (pyy - third) / mu;
+    seg[3 * s.cells + c] = mxy > 0.0f ? sxy_r / mxy : 0.0f;
+    seg[4 * s.cells + c] = mxz > 0.0f ? sxz_r / mxz : 0.0f;
+    seg[5 * s.cells + c] = myz > 0.0f ? syz_r / myz : 0.0f;
+  }
+}
+
+template <bool STORE, bool RECORD>
+__global__ __launch_bounds__(TX * TY) void k3_fwd_str(PARAMS3, int n, int kstore) {
+  TILE3();
+  if (k >= s.ny || j >= s.nx) return;
+  gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG3 * s.cells : nullptr;
+  if (tile_in_pml(s, i, k0, j0, 0)) fwd_str3<STORE, RECORD, true>(s, i, k, j, n, seg);
+  else fwd_str3<STORE, RECORD, false>(s, i, k, j, n, seg);
+}
+
+// ------------------------------------------------------------------------------------
+// Adjoint. Corrected transposed operands at a neighbour node: v + a (psi_bar + v) inside
+// the CPML strip of the derivative's axis (psi_bar from the buffer of step n+1), v outside.
+// ------------------------------------------------------------------------------------
+template <bool PML>
+struct Adj3 {
+  const Shot3D& s;
+  int rd;
+  __device__ __forceinline__ bool in(int i, int k, int j) const {
+    return i >= 0 && i < s.nz && k >= 0 && k < s.ny && j >= 0 && j < s.nx;
+  }
+  __device__ __forceinline__ float cx(float v, int i, int k, int j, int slot, int prof) const {
+    if (PML && in(i, k, j)) {
+      const int sx = strip_index(j, s.nx, s.P);
+      if (sx >= 0) v += px_(s, prof)[j] * (s.pbx[rd][slot][xq(s, i, k, sx)] + v);
+    }
+    return v;
+  }
+  __device__ __forceinline__ float cy(float v, int i, int k, int j, int slot, int prof) const {
+    if (PML && in(i, k, j)) {
+      const int sy = strip_index(k, s.ny, s.P);
+      if (sy >= 0) v += py_(s, prof)[k] * (s.pby[rd][slot][yq(s, i, sy, j)] + v);
+    }
+    return v;
+  }
+  __device__ __forceinline__ float cz(float v, int i, int k, int j, int slot, int prof) const {
+    if (PML && in(i, k, j)) {
+      const int sz = strip_index(i, s.nz, s.P);
+      if (sz >= 0) v += pz_(s, prof)[i] * (s.pbz[rd][slot][zq(s, sz, k, j)] + v);
+    }
+    return v;
+  }
+  __device__ __forceinline__ float at(const gfloat* f, int i, int k, int j) const {
+    return s.dt * f[(long)i * s.pz + (long)k * s.ld + j];
+  }
+};
+
+__device__ __forceinline__ float ebar3(const Shot3D& s, int slot, int jc, int n) {
+  if (jc < 0 || jc >= s.nx) return 0.0f;
+  const int c = s.rowch[(long)slot * s.nx + jc];
+  return c >= 0 ? s.ebar[(long)n * s.nch + c] : 0.0f;
+}
+
+__device__ __forceinline__ void acc3(gfloat* acc, long idx, float v, bool first) {
+  if (first) acc[idx] = v;
+  else acc[idx] += v;
+}
+
+// Transposed stress sub-step: t_bar -> u_bar.
+template <bool GRAD, bool SRCADJ, bool PML>
+__device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, int n, const gfloat* seg, bool first) {
+  const long ld = s.ld, pz = s.pz;
+  const long o = (long)i * pz + (long)k * ld + j;
+  const int rd = (n + 1) & 1, wr = n & 1;
+  const Adj3<PML> A{s, rd};
+  // operands: normal (int profile on their own axis), shear (half profile on the axis of
+  // the velocity derivative they came from)
+  auto Pxx = [&](int a, int b, int c) { return A.cx(A.at(s.txxb, a, b, c), a, b, c, XS_PXX, 0); };
+  auto Pyy = [&](int a, int b, int c) { return A.cy(A.at(s.tyyb, a, b, c), a, b, c, YS_PYY, 0); };
+  auto Pzz = [&](int a, int b, int c) { return A.cz(A.at(s.tzzb, a, b, c), a, b, c, ZS_PZZ, 0); };
+  auto Pxy_vx = [&](int a, int b, int c) { return A.cy(A.at(s.txyb, a, b, c), a, b, c, YS_SXY, 2); };
+  auto Pxy_vy = [&](int a, int b, int c) { return A.cx(A.at(s.txyb, a, b, c), a, b, c, XS_SXY, 2); };
+  auto Pxz_vx = [&](int a, int b, int c) { return A.cz(A.at(s.txzb, a, b, c), a, b, c, ZS_SXZ, 2); };
+  auto Pxz_vz = [&](int a, int b, int c) { return A.cx(A.at(s.txzb, a, b, c), a, b, c, XS_SXZ, 2); };
+  auto Pyz_vy = [&](int a, int b, int c) { return A.cz(A.at(s.tyzb, a, b, c), a, b, c, ZS_SYZ, 2); };
+  auto Pyz_vz = [&](int a, int b, int c) { return A.cy(A.at(s.tyzb, a, b, c), a, b, c, YS_SYZ, 2); };
+  // v_bar_x += -(D+x Pxx + D-y Pxy_vx + D-z Pxz_vx)
+  const float x1 = K1 * (Pxx(i, k, j + 1) - Pxx(i, k, j)) + K2 * (Pxx(i, k, j + 2) - Pxx(i, k, j - 1));
+  const float x2 = K1 * (Pxy_vx(i, k, j) - Pxy_vx(i, k - 1, j)) + K2 * (Pxy_vx(i, k + 1, j) - Pxy_vx(i, k - 2, j));
+  const float x3 = K1 * (Pxz_vx(i, k, j) - Pxz_vx(i - 1, k, j)) + K2 * (Pxz_vx(i + 1, k, j) - Pxz_vx(i - 2, k, j));
+  // v_bar_y += -(D+y Pyy + D-x Pxy_vy + D-z Pyz_vy)
+  const float y1 = K1 * (Pyy(i, k + 1, j) - Pyy(i, k, j)) + K2 * (Pyy(i, k + 2, j) - Pyy(i, k - 1, j));
+  const float y2 = K1 * (Pxy_vy(i, k, j) - Pxy_vy(i, k, j - 1)) + K2 * (Pxy_vy(i, k, j + 1) - Pxy_vy(i, k, j - 2));
+  const float y3 = K1 * (Pyz_vy(i, k, j) - Pyz_vy(i - 1, k, j)) + K2 * (Pyz_vy(i + 1, k, j) - Pyz_vy(i - 2, k, j));
+  // v_bar_z += -(D+z Pzz + D-x Pxz_vz + D-y Pyz_vz)
+  const float z1 = K1 * (Pzz(i + 1, k, j) - Pzz(i, k, j)) + K2 * (Pzz(i + 2, k, j) - Pzz(i - 1, k, j));
+  const float z2 = K1 * (Pxz_vz(i, k, j) - Pxz_vz(i, k, j - 1)) + K2 * (Pxz_vz(i, k, j + 1) - Pxz_vz(i, k, j - 2));
+  const float z3 = K1 * (Pyz_vz(i, k, j) - Pyz_vz(i, k - 1, j)) + K2 * (Pyz_vz(i, k + 1, j) - Pyz_vz(i, k - 2, j));
+  float gx = -(x1 * s.rdx + x2 * s.rdy + x3 * s.rdz);
+  const float gy = -(y1 * s.rdy + y2 * s.rdx + y3 * s.rdz);
+  const float gz = -(z1 * s.rdz + z2 * s.rdx + z3 * s.rdy);
+  const int slot = s.row_slot[(long)i * s.ny + k];
+  if (slot >= 0) {
+    const float inj = K1 * (ebar3(s, slot, j, n) - ebar3(s, slot, j + 1, n)) +
+                      K2 * (ebar3(s, slot, j - 1, n) - ebar3(s, slot, j + 2, n));
+    gx += s.dt * s.rdx * inj;
+  }
+  const float txx = s.txxb[o], tyy = s.tyyb[o], tzz = s.tzzb[o];
+  const float txy = s.txyb[o], txz = s.txzb[o], tyz = s.tyzb[o];
+  if (PML) {
+    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+    const float dt = s.dt;
+    if (sx >= 0) {
+      const long q = xq(s, i, k, sx);
+      s.pbx[wr][XS_PXX][q] = px_(s, 1)[j] * (s.pbx[rd][XS_PXX][q] + dt * txx);
+      s.pbx[wr][XS_SXY][q] = px_(s, 3)[j] * (s.pbx[rd][XS_SXY][q] + dt * txy);
+      s.pbx[wr][XS_SXZ][q] = px_(s, 3)[j] * (s.pbx[rd][XS_SXZ][q] + dt * txz);
+    }
+    if (sy >= 0) {
+      const long q = yq(s, i, sy, j);
+      s.pby[wr][YS_PYY][q] = py_(s, 1)[k] * (s.pby[rd][YS_PYY][q] + dt * tyy);
+      s.pby[wr][YS_SXY][q] = py_(s, 3)[k] * (s.pby[rd][YS_SXY][q] + dt * txy);
+      s.pby[wr][YS_SYZ][q] = py_(s, 3)[k] * (s.pby[rd][YS_SYZ][q] + dt * tyz);
+    }
+    if (sz >= 0) {
+      const long q = zq(s, sz, k, j);
+      s.pbz[wr][ZS_PZZ][q] = pz_(s, 1)[i] * (s.pbz[rd][ZS_PZZ][q] + dt * tzz);
+      s.pbz[wr][ZS_SXZ][q] = pz_(s, 3)[i] * (s.pbz[rd][ZS_SXZ][q] + dt * txz);
+      s.pbz[wr][ZS_SYZ][q] = pz_(s, 3)[i] * (s.pbz[rd][ZS_SYZ][q] + dt * tyz);
+    }
+  }
+  s.uxb[o] += s.bx[o] * gx;
+  s.uyb[o] += s.by[o] * gy;
+  s.uzb[o] += s.bz[o] * gz;
+  if (GRAD) {
+    const long c = ((long)i * s.ny + k) * s.cp + j;
+    const float trt = txx + tyy + tzz;
+    const float da = txx - trt * (1.0f / 3.0f), db = tyy - trt * (1.0f / 3.0f);
+    const float D1 = seg[s.cells + c], D2 = seg[2 * s.cells + c];
+    acc3(s.acc, c, s.dt * trt * seg[c], first);
+    acc3(s.acc, s.cells + c, s.dt * (da * D1 + db * D2 + (da + db) * (D1 + D2)), first);
+    acc3(s.acc, 2 * s.cells + c, s.dt * txy * seg[3 * s.cells + c], first);
+    acc3(s.acc, 3 * s.cells + c, s.dt * txz * seg[4 * s.cells + c], first);
+    acc3(s.acc, 4 * s.cells + c, s.dt * tyz * seg[5 * s.cells + c], first);
+  }
+  if (SRCADJ && i == s.si && k == s.sk && j == s.sj) {
+    // sigma_bar at the source: invert C on the normal block and the shear moduli
+    const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
+    const float trs = (txx + tyy + tzz) / (l2m + 2.0f * lam);
+    const int nt = s.nt;
+    s.src_bar[n] = -s.w * (txx - lam * trs) / two_mu;
+    s.src_bar[nt + n] = -s.w * (tyy - lam * trs) / two_mu;
+    s.src_bar[2 * nt + n] = -s.w * (tzz - lam * trs) / two_mu;
+    auto sh = [&](const gfloat* t, const gfloat* mu, long oo) { return mu[oo] > 0.0f ? t[oo] / mu[oo] : 0.0f; };
+    float a = 0.f, b = 0.f, c = 0.f;
+    for (int q = 0; q < 4; ++q) {
+      const int d1 = q & 1, d2 = q >> 1;
+      a += sh(s.txyb, s.muxy, o - d1 * ld - d2);        // (i, k-d1, j-d2)
+      b += sh(s.txzb, s.muxz, o - d1 * pz - d2);        // (i-d1, k, j-d2)
+      c += sh(s.tyzb, s.muyz, o - d1 * pz - d2 * ld);   // (i-d1, k-d2, j)
+    }
+    s.src_bar[3 * nt + n] = -0.25f * s.w * a;
+    s.src_bar[4 * nt + n] = -0.25f * s.w * b;
+    s.src_bar[5 * nt + n] = -0.25f * s.w * c;
+  }
+}
+
+template <bool GRAD, bool SRCADJ>
+__global__ __launch_bounds__(TX * TY) void k3_adj_vel(PARAMS3, int n, int kseg, int first) {
+  TILE3();
+  if (k >= s.ny || j >= s.nx) return;
+  const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
+  if (tile_in_pml(s, i, k0, j0, 2)) adj_vel3<GRAD, SRCADJ, true>(s, i, k, j, n, seg, first != 0);
+  else adj_vel3<GRAD, SRCADJ, false>(s, i, k, j, n, seg, first != 0);
+}
+
+// Transposed velocity sub-step: u_bar -> t_bar.
+template <bool GRAD, bool PML>
+__device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, int n, const gfloat* seg, bool first) {
+  const long ld = s.ld, pz = s.pz;
+  const long o = (long)i * pz + (long)k * ld + j;
+  const int rd = (n + 1) & 1, wr = n & 1;
+  const Adj3<PML> A{s, rd};
+  auto Qxx = [&](int a, int b, int c) { return A.cx(A.at(s.uxb, a, b, c), a, b, c, XS_VX, 2); };  // vx: D+x sxx
+  auto Qxy = [&](int a, int b, int c) { return A.cy(A.at(s.uxb, a, b, c), a, b, c, YS_VX, 0); };  // vx: D-y sxy
+  auto Qxz = [&](int a, int b, int c) { return A.cz(A.at(s.uxb, a, b, c), a, b, c, ZS_VX, 0); };  // vx: D-z sxz
+  auto Qyx = [&](int a, int b, int c) { return A.cx(A.at(s.uyb, a, b, c), a, b, c, XS_VY, 0); };  // vy: D-x sxy
+  auto Qyy = [&](int a, int b, int c) { return A.cy(A.at(s.uyb, a, b, c), a, b, c, YS_VY, 2); };  // vy: D+y syy
+  auto Qyz = [&](int a, int b, int c) { return A.cz(A.at(s.uyb, a, b, c), a, b, c, ZS_VY, 0); };  // vy: D-z syz
+  auto Qzx = [&](int a, int b, int c) { return A.cx(A.at(s.uzb, a, b, c), a, b, c, XS_VZ, 0); };  // vz: D-x sxz
+  auto Qzy = [&](int a, int b, int c) { return A.cy(A.at(s.uzb, a, b, c), a, b, c, YS_VZ, 0); };  // vz: D-y syz
+  auto Qzz = [&](int a, int b, int c) { return A.cz(A.at(s.uzb, a, b, c), a, b, c, ZS_VZ, 2); };  // vz: D+z szz
+  // sigma_bar_cc += -D-c Q; shear += -(D+ Q + D+ Q)
+  const float dxx = -(K1 * (Qxx(i, k, j) - Qxx(i, k, j - 1)) + K2 * (Qxx(i, k, j + 1) - Qxx(i, k, j - 2))) * s.rdx;
+  const float dyy = -(K1 * (Qyy(i, k, j) - Qyy(i, k - 1, j)) + K2 * (Qyy(i, k + 1, j) - Qyy(i, k - 2, j))) * s.rdy;
+  const float dzz = -(K1 * (Qzz(i, k, j) - Qzz(i - 1, k, j)) + K2 * (Qzz(i + 1, k, j) - Qzz(i - 2, k, j))) * s.rdz;
+  const float dxy = -((K1 * (Qxy(i, k + 1, j) - Qxy(i, k, j)) + K2 * (Qxy(i, k + 2, j) - Qxy(i, k - 1, j))) * s.rdy +
+                      (K1 * (Qyx(i, k, j + 1) - Qyx(i, k, j)) + K2 * (Qyx(i, k, j + 2) - Qyx(i, k, j - 1))) * s.rdx);
+  const float dxz = -((K1 * (Qxz(i + 1, k, j) - Qxz(i, k, j)) + K2 * (Qxz(i + 2, k, j) - Qxz(i - 1, k, j))) * s.rdz +
+                      (K1 * (Qzx(i, k, j + 1) - Qzx(i, k, j)) + K2 * (Qzx(i, k, j + 2) - Qzx(i, k, j - 1))) * s.rdx);
+  const float dyz = -((K1 * (Qyz(i + 1, k, j) - Qyz(i, k, j)) + K2 * (Qyz(i + 2, k, j) - Qyz(i - 1, k, j))) * s.rdz +
+                      (K1 * (Qzy(i, k + 1, j) - Qzy(i, k, j)) + K2 * (Qzy(i, k + 2, j) - Qzy(i, k - 1, j))) * s.rdy);
+  const float ux = s.uxb[o], uy = s.uyb[o], uz = s.uzb[o];
+  if (PML) {
+    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+    const float dt = s.dt;
+    if (sx >= 0) {
+      const long q = xq(s, i, k, sx);
+      s.pbx[wr][XS_VX][q] = px_(s, 3)[j] * (s.pbx[rd][XS_VX][q] + dt * ux);
+      s.pbx[wr][XS_VY][q] = px_(s, 1)[j] * (s.pbx[rd][XS_VY][q] + dt * uy);
+      s.pbx[wr][XS_VZ][q] = px_(s, 1)[j] * (s.pbx[rd][XS_VZ][q] + dt * uz);
+    }
+    if (sy >= 0) {
+      const long q = yq(s, i, sy, j);
+      s.pby[wr][YS_VX][q] = py_(s, 1)[k] * (s.pby[rd][YS_VX][q] + dt * ux);
+      s.pby[wr][YS_VY][q] = py_(s, 3)[k] * (s.pby[rd][YS_VY][q] + dt * uy);
+      s.pby[wr][YS_VZ][q] = py_(s, 1)[k] * (s.pby[rd][YS_VZ][q] + dt * uz);
+    }
+    if (sz >= 0) {
+      const long q = zq(s, sz, k, j);
+      s.pbz[wr][ZS_VX][q] = pz_(s, 1)[i] * (s.pbz[rd][ZS_VX][q] + dt * ux);
+      s.pbz[wr][ZS_VY][q] = pz_(s, 1)[i] * (s.pbz[rd][ZS_VY][q] + dt * uy);
+      s.pbz[wr][ZS_VZ][q] = pz_(s, 3)[i] * (s.pbz[rd][ZS_VZ][q] + dt * uz);
+    }
+  }
+  const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
+  const float tr = dxx + dyy + dzz;
+  s.txxb[o] += lam * tr + two_mu * dxx;
+  s.tyyb[o] += lam * tr + two_mu * dyy;
+  s.tzzb[o] += lam * tr + two_mu * dzz;
+  s.txyb[o] += s.muxy[o] * dxy;
+  s.txzb[o] += s.muxz[o] * dxz;
+  s.tyzb[o] += s.muyz[o] * dyz;
+  if (GRAD) {
+    const long c = ((long)i * s.ny + k) * s.cp + j;
+    acc3(s.acc, 5 * s.cells + c, s.dt * ux * seg[6 * s.cells + c], first);
+    acc3(s.acc, 6 * s.cells + c, s.dt * uy * seg[7 * s.cells + c], first);
+    acc3(s.acc, 7 * s.cells + c, s.dt * uz * seg[8 * s.cells + c], first);
+  }
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(TX * TY) void k3_adj_str(PARAMS3, int n, int kseg, int first) {
+  TILE3();
+  if (k >= s.ny || j >= s.nx) return;
+  const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
+  if (tile_in_pml(s, i, k0, j0, 2)) adj_str3<GRAD, true>(s, i, k, j, n, seg, first != 0);
+  else adj_str3<GRAD, false>(s, i, k, j, n, seg, first != 0);
+}
+
+// ------------------------------------------------------------------------------------
+// Staging: (Vp, Vs, rho) -> lambda + 2 mu, lambda, harmonic shear moduli, buoyancies.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(TX * TY) void k3_stage(PARAMS3) {
+  TILE3();
+  if (k >= s.ny || j >= s.nx) return;
+  const int ip = min(i + 1, s.nz - 1), kp = min(k + 1, s.ny - 1), jp = min(j + 1, s.nx - 1);
+  auto at = [&](const gfloat* f, int a, int b, int c) { return f[(long)a * s.mplanestride + (long)b * s.mld + c]; };
+  auto mu_at = [&](int a, int b, int c) {
+    const float v = at(s.mvs, a, b, c);
+    return at(s.mrho, a, b, c) * v * v;
+  };
+  auto harm = [](float a, float b, float c, float d) {
+    return (a > 0.f && b > 0.f && c > 0.f && d > 0.f) ? 4.0f / (1.0f / a + 1.0f / b + 1.0f / c + 1.0f / d) : 0.0f;
+  };
+  const float vp = at(s.mvp, i, k, j), rho = at(s.mrho, i, k, j);
+  const float mu = mu_at(i, k, j);
+  const long o = (long)i * s.pz + (long)k * s.ld + j;
+  const float l2m = rho * vp * vp;
+  s.l2m[o] = l2m;
+  s.lam[o] = l2m - 2.0f * mu;
+  s.muxy[o] = harm(mu, mu_at(i, kp, j), mu_at(i, k, jp), mu_at(i, kp, jp));
+  s.muxz[o] = harm(mu, mu_at(ip, k, j), mu_at(i, k, jp), mu_at(ip, k, jp));
+  s.muyz[o] = harm(mu, mu_at(ip, k, j), mu_at(i, kp, j), mu_at(ip, kp, j));
+  s.bx[o] = 2.0f / (rho + at(s.mrho, i, k, jp));
+  s.by[o] = 2.0f / (rho + at(s.mrho, i, kp, j));
+  s.bz[o] = 2.0f / (rho + at(s.mrho, ip, k, j));
+}
+
+// ------------------------------------------------------------------------------------
+// Chain rule of one block of FP32 imaging sums into the FP64 (Vp, Vs, rho) gradient.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(TX * TY) void k3_chain_flush(PARAMS3) {
+  TILE3();
+  if (k >= s.ny || j >= s.nx) return;
+  const long cs = s.cells;
+  auto ci = [&](int a, int b, int c) { return ((long)a * s.ny + b) * s.cp + c; };
+  auto pi = [&](int a, int b, int c) { return (long)a * s.pz + (long)b * s.ld + c; };
+  const long cc = ci(i, k, j);
+  const long mo = (long)i * s.mplanestride + (long)k * s.mld + j;
+  const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
+  const double mu = (double)(rho * vs * vs);
+  const double gl = s.acc[cc];
+  double gmu = 2.0 / 3.0 * gl + (double)s.acc[cs + cc];
+  const int NZ = s.nz - 1, NY = s.ny - 1, NX = s.nx - 1;
+  // shear node (a, b, c) of each type and its four clamped corners
+  for (int t = 0; t < 3; ++t) {
+    const gfloat* mod = t == 0 ? s.muxy : (t == 1 ? s.muxz : s.muyz);
+    const gfloat* g = s.acc + (2 + t) * cs;
+    for (int q = 0; q < 4; ++q) {
+      const int d1 = q & 1, d2 = q >> 1;
+      int a = i, b = k, c = j;
+      if (t == 0) { b -= d1; c -= d2; }       // xy: (i, k-1..k, j-1..j)
+      else if (t == 1) { a -= d1; c -= d2; }  // xz: (i-1..i, k, j-1..j)
+      else { a -= d1; b -= d2; }              // yz: (i-1..i, k-1..k, j)
+      if (a < 0 || b < 0 || c < 0) continue;
+      int mult = 0;
+      for (int e = 0; e < 4; ++e) {
+        const int e1 = e & 1, e2 = e >> 1;
+        int aa = a, bb = b, cc2 = c;
+        if (t == 0) { bb = min(b + e1, NY); cc2 = min(c + e2, NX); }
+        else if (t == 1) { aa = min(a + e1, NZ); cc2 = min(c + e2, NX); }
+        else { aa = min(a + e1, NZ); bb = min(b + e2, NY); }
+        mult += (aa == i && bb == k && cc2 == j);
+      }
+      if (mult == 0) continue;
+      const float m = mod[pi(a, b, c)];
+      if (m > 0.0f) gmu += (double)mult * g[ci(a, b, c)] * ((double)m * m / (4.0 * mu * mu));
+    }
+  }
+  double grho = 0.0;
+  for (int t = 0; t < 3; ++t) {
+    const gfloat* bb = t == 0 ? s.bx : (t == 1 ? s.by : s.bz);
+    const gfloat* g = s.acc + (5 + t) * cs;
+    for (int d = -1; d <= 0; ++d) {
+      int a = i, b = k, c = j;
+      int mult;
+      if (t == 0) { c += d; if (c < 0) continue; mult = (c == j) + (min(c + 1, NX) == j); }
+      else if (t == 1) { b += d; if (b < 0) continue; mult = (b == k) + (min(b + 1, NY) == k); }
+      else { a += d; if (a < 0) continue; mult = (a == i) + (min(a + 1, NZ) == i); }
+      if (mult == 0) continue;
+      const double bv = bb[pi(a, b, c)];
+      grho -= 0.5 * mult * g[ci(a, b, c)] * bv * bv;
+    }
+  }
+  const double dvp = vp, dvs = vs, drho = rho;
+  s.G[cc] += 2.0 * drho * dvp * gl;
+  s.G[cs + cc] += 2.0 * drho * dvs * (gmu - 2.0 * gl);
+  s.G[2 * cs + cc] += (dvp * dvp - 2.0 * dvs * dvs) * gl + dvs * dvs * gmu + grho;
+}
+
+__global__ __launch_bounds__(TX * TY) void k3_write_gradient(PARAMS3) {
+  TILE3();
+  if (k >= s.ny || j >= s.nx) return;
+  const long cc = ((long)i * s.ny + k) * s.cp + j;
+  const long go = (long)(s.z0 + i) * s.mplanestride + (long)(s.y0 + k) * s.mld + (s.x0 + j);
+  for (int q = 0; q < 3; ++q) s.gout[q * s.mplane + go] = (float)s.G[q * s.cells + cc];
+}
+
+inline dim3 grid3(const Sched& q) { return dim3(q.n); }
+inline dim3 block3() { return dim3(TX, TY); }
+#define EVEN3 b.shots, b.tile_shot, b.tile_first, b.even.sched
+#define WEIGHTED3 b.shots, b.tile_shot, b.tile_first, b.weighted.sched
+
+}  // namespace
+
+hipError_t launch3_stage(const Batch3D& b, hipStream_t st) {
+  k3_stage<<<grid3(b.even), block3(), 0, st>>>(EVEN3);
+  return hipGetLastError();
+}
+
+hipError_t launch3_fwd_vel(const Batch3D& b, int kstore, hipStream_t st) {
+  if (kstore >= 0) k3_fwd_vel<true><<<grid3(b.even), block3(), 0, st>>>(EVEN3, kstore);
+  else k3_fwd_vel<false><<<grid3(b.even), block3(), 0, st>>>(EVEN3, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch3_fwd_str(const Batch3D& b, int n, int kstore, bool record, hipStream_t st) {
+  if (kstore >= 0) {
+    if (record) k3_fwd_str<true, true><<<grid3(b.even), block3(), 0, st>>>(EVEN3, n, kstore);
+    else k3_fwd_str<true, false><<<grid3(b.even), block3(), 0, st>>>(EVEN3, n, kstore);
+  } else {
+    if (record) k3_fwd_str<false, true><<<grid3(b.even), block3(), 0, st>>>(EVEN3, n, 0);
+    else k3_fwd_str<false, false><<<grid3(b.even), block3(), 0, st>>>(EVEN3, n, 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch3_adj_vel(const Batch3D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
+  if (grad) k3_adj_vel<true, false><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, k, first);
+  else if (srcadj) k3_adj_vel<false, true><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, 0, 0);
+  else k3_adj_vel<false, false><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch3_adj_str(const Batch3D& b, int n, int k, bool grad, bool first, hipStream_t st) {
+  if (grad) k3_adj_str<true><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, k, first);
+  else k3_adj_str<false><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch3_chain_flush(const Batch3D& b, hipStream_t st) {
+  k3_chain_flush<<<grid3(b.even), block3(), 0, st>>>(EVEN3);
+  return hipGetLastError();
+}
+
+hipError_t launch3_write_gradient(const Batch3D& b, hipStream_t st) {
+  k3_write_gradient<<<grid3(b.even), block3(), 0, st>>>(EVEN3);
+  return hipGetLastError();
+}
+
+}  // namespace efwi

@@ -50,7 +50,8 @@ class _ShotC(ctypes.Structure):
 
 @dataclass
 class Shot:
-    """One shot: source node, DAS channel nodes (full-model coordinates), window, checkpointing."""
+    """One shot: source node, DAS channel nodes (full-model coordinates), window, checkpointing.
+    The y fields are used on 3D grids only."""
     src_iz: int
     src_ix: int
     ch_iz: np.ndarray
@@ -61,6 +62,10 @@ class Shot:
     wx: int = 0
     ckpt_interval: int = 0
     ckpt_mode: int = CKPT_FP32
+    src_iy: int = 0
+    ch_iy: np.ndarray = None
+    y0: int = 0
+    wy: int = 0
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -70,15 +75,27 @@ class Shot:
     def c_struct(self) -> _ShotC:
         iz = np.ascontiguousarray(self.ch_iz, dtype=np.int32)
         ix = np.ascontiguousarray(self.ch_ix, dtype=np.int32)
-        self._keep[:] = [iz, ix]
+        iy = None if self.ch_iy is None else np.ascontiguousarray(self.ch_iy, dtype=np.int32)
+        self._keep[:] = [iz, ix, iy]
         ip = ctypes.POINTER(ctypes.c_int)
-        return _ShotC(self.src_iz, 0, self.src_ix, len(iz), iz.ctypes.data_as(ip), None, ix.ctypes.data_as(ip),
-                      self.z0, 0, self.x0, self.wz, 0, self.wx, self.ckpt_interval, self.ckpt_mode)
+        return _ShotC(self.src_iz, self.src_iy, self.src_ix, len(iz), iz.ctypes.data_as(ip),
+                      None if iy is None else iy.ctypes.data_as(ip), ix.ctypes.data_as(ip),
+                      self.z0, self.y0, self.x0, self.wz, self.wy, self.wx, self.ckpt_interval, self.ckpt_mode)
 
 
 def make_grid(nz, nx, dz, dx, dt, nt, npml=0, pml_R=1e-3, pml_f0=10.0, vp_max=0.0) -> Grid:
     return Grid(2, int(nz), 1, int(nx), float(dz), 1.0, float(dx), float(dt), int(nt), int(npml),
                 float(pml_R), float(pml_f0), float(vp_max))
+
+
+def make_grid3d(nz, ny, nx, dz, dy, dx, dt, nt, npml=0, pml_R=1e-3, pml_f0=10.0, vp_max=0.0) -> Grid:
+    return Grid(3, int(nz), int(ny), int(nx), float(dz), float(dy), float(dx), float(dt), int(nt), int(npml),
+                float(pml_R), float(pml_f0), float(vp_max))
+
+
+def n_components(grid: Grid) -> int:
+    """Moment-tensor components of a source series: 3 in 2D (xx, zz, xz), 6 in 3D."""
+    return 6 if grid.ndim == 3 else 3
 
 
 _vp = ctypes.c_void_p
@@ -212,7 +229,7 @@ def model_adjoint(grid: Grid, shot: Shot, m, r, src_bar=None, ws=None, stream=No
     """L^T r with respect to the [3][nt] source components."""
     _f32(m, "m"), _f32(r, "r")
     if src_bar is None:
-        src_bar = torch.empty((3, grid.nt), dtype=torch.float32, device=m.device)
+        src_bar = torch.empty((n_components(grid), grid.nt), dtype=torch.float32, device=m.device)
     sc = shot.c_struct()
     need = _lib.efwi_workspace_size(WS_ADJOINT, ctypes.byref(grid), 1, ctypes.byref(sc))
     ws = ws if ws is not None else workspace(need, m.device)
@@ -284,5 +301,7 @@ def extension_regularizer(grid: Grid, m_ext, b, sink, eta, g_ext, phi=None, ws=N
 
 
 def source_components(M, stf) -> np.ndarray:
-    """[3][nt] source components (M_xx, M_zz, M_xz) x moment-rate samples."""
-    return np.outer(np.asarray(M, np.float64)[:3], np.asarray(stf, np.float64)).astype(np.float32)
+    """Source components x moment-rate samples: [3][nt] for (M_xx, M_zz, M_xz) in 2D,
+    [6][nt] for (M_xx, M_yy, M_zz, M_xy, M_xz, M_yz) in 3D."""
+    M = np.asarray(M, np.float64)
+    return np.outer(M, np.asarray(stf, np.float64)).astype(np.float32)

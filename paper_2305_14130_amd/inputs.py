@@ -192,3 +192,66 @@ def perturbed_extension(m, nshots, seed=77, rel=0.01, corr_cells=10.0):
         for k in range(3):
             out[s, k] = m[k] * (1.0 + smooth_random_field(m.shape[1:], corr_cells, seed + 3 * s + k, rel))
     return out
+
+
+@dataclass
+class Shot3D:
+    src_iz: int
+    src_iy: int
+    src_ix: int
+    M: np.ndarray              # (Mxx, Myy, Mzz, Mxy, Mxz, Myz)
+    ch_iz: np.ndarray
+    ch_iy: np.ndarray
+    ch_ix: np.ndarray
+
+
+@dataclass
+class Workload3D:
+    name: str
+    nz: int
+    ny: int
+    nx: int
+    h: float
+    dt: float
+    nt: int
+    npml: int
+    f0: float
+    vp_max: float
+    stf: np.ndarray
+    m_start: np.ndarray        # [3][nz][ny][nx]
+    m_true: np.ndarray
+    shots: list = field(default_factory=list)
+    pml_R: float = 1e-3
+
+
+def precision_3d(nz=300, ny=400, nx=400, nt=3000, nshots=8, nch_per_well=1000, h=5.0, dt=0.4e-3, npml=20,
+                 f0=30.0, M0=1.0e16, seed=8):
+    """The shale geology at 5 m in 3D: background Vp 3800, Vs/Vp 0.6, rho 2550 with a 15 m
+    (3-cell) reservoir Vp 3400, Vs/Vp 0.55, rho 2450 at mid depth, +-5% Gaussian-correlated
+    anomalies (50 m) in the true model, moment-tensor shots (six components, seed 8) in the
+    layer and two horizontal DAS wells along x at y = 3/8 and 5/8 of the width."""
+    res_top = nz // 2 - 1
+    m = _shale_model(nz, nx, h, res_top, res_top + 3, anomalies=False)[:, :, None, :]
+    m_start = np.repeat(m, ny, axis=2).transpose(0, 1, 2, 3)            # [3][nz][ny][nx]
+    m_true = m_start.copy()
+    for k in range(3):
+        m_true[k] *= 1.0 + smooth_random_field((nz, ny, nx), 50.0 / h, 14130 + k, 0.05)
+    iz = nz // 2
+    wells = [int(ny * 3 // 8), int(ny * 5 // 8)]
+    lo = npml + 2
+    nch = min(nch_per_well, nx - 2 * lo)
+    ch_ix = (lo + np.arange(nch) * max(1, (nx - 2 * lo) // nch)).astype(np.int32)
+    ch_iz = np.full(2 * nch, iz, np.int32)
+    ch_iy = np.concatenate([np.full(nch, wells[0]), np.full(nch, wells[1])]).astype(np.int32)
+    ch_ix2 = np.concatenate([ch_ix, ch_ix]).astype(np.int32)
+    rng = np.random.default_rng(seed)
+    shots = []
+    for s in range(nshots):
+        M = rng.uniform(-1.0, 1.0, 6)
+        M *= M0 / math.sqrt(M[0] ** 2 + M[1] ** 2 + M[2] ** 2 + 2 * (M[3] ** 2 + M[4] ** 2 + M[5] ** 2))
+        sy = wells[s % 2] + (2 if s % 4 < 2 else -2)
+        sx = int(lo + 4 + (nx - 2 * lo - 8) * (s + 0.5) / nshots)
+        shots.append(Shot3D(src_iz=iz, src_iy=sy, src_ix=sx, M=M, ch_iz=ch_iz, ch_iy=ch_iy, ch_ix=ch_ix2))
+    return Workload3D(name=f"precision-3d-{nz}x{ny}x{nx}", nz=nz, ny=ny, nx=nx, h=h, dt=dt, nt=nt, npml=npml,
+                      f0=f0, vp_max=3800.0 * 1.05, stf=ricker(nt, dt, f0), m_start=m_start, m_true=m_true,
+                      shots=shots)

@@ -52,7 +52,8 @@ def test_validation_accepts_good_arguments(efwi):
     (lambda g, s: setattr(g, "dt", 1.0e-3), "E_CFL"),
     (lambda g, s: setattr(g, "nt", 0), "E_INVAL"),
     (lambda g, s: setattr(g, "dx", 0.0), "E_INVAL"),
-    (lambda g, s: setattr(g, "ndim", 3), "E_UNSUPPORTED"),
+    (lambda g, s: setattr(g, "ndim", 4), "E_INVAL"),
+    (lambda g, s: (setattr(g, "ndim", 3), setattr(g, "dy", 5.0)), "E_RANGE"),   # ny = 1: no room for CPML
     (lambda g, s: setattr(s, "src_ix", 10), "E_RANGE"),            # inside the CPML strip
     (lambda g, s: setattr(s, "src_iz", 99), "E_RANGE"),
     (lambda g, s: setattr(s, "ch_ix", np.array([60, 63, 195], np.int32)), "E_RANGE"),
