@@ -2,23 +2,30 @@
 
 One step = one pass of the whole hot path over the plain per-shot workload: for each of the
 20 shots of the 1000 x 3000 (dx = 2.5 m), nt = 4000 shale model, a full shot gradient
-(forward sweep with DAS recording and sqrt(nt) FP32 checkpoints, FP64 misfit, reverse sweep
-with segment recomputation, transposed stress/velocity steps, imaging condition, chain rule
-into the shot's own component m_s of the extended model), then the consistency-regularizer
-value and gradient over the 20-component extended model.
+(forward sweep with DAS recording, FP64 misfit, reverse sweep with transposed
+stress/velocity steps, imaging condition, chain rule into the shot's own component m_s of
+the extended model), then the consistency-regularizer value and gradient over the
+20-component extended model.
+
+The forward history for the imaging condition is kept with the largest checkpoint interval
+whose workspace fits in the free HBM (one shot's whole history, 224 GiB, fits in the 288 GB
+of an MI355X, so nothing is recomputed); the sqrt(nt)-checkpoint form (recomputing all but
+the last segment) and the batched form (all shots advanced together) are timed once each
+and must give the identical gradient.
 
 Metric: Gcell-updates/s = shots * nz * nx * nt / wall time (fwd + adj + grad), inputs
 resident in HBM before the timed region. The JSON line also carries:
 * roofline: the dominant kernel's algorithmic bytes per launch over its mean launch time
   (HIP events around sampled launches on the library's stream), against 8 TB/s;
-* cpu_baseline: the FP64 NumPy oracle on a bounded sample (one shot, full grid, 8 time
-  steps), in the same unit;
-* path: the whole step's algorithmic bytes (204 B per cell-step for fwd + adj + grad with
-  sqrt(nt) recomputation) over the step time.
+* cpu_baseline: the FP64 NumPy oracle on a bounded sample (one shot, full grid, a few
+  time steps), in the same unit;
+* path: the whole step's algorithmic bytes (240 B per cell-step plus 80 B per recomputed
+  cell-step) over the step time.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -42,9 +49,16 @@ HBM_PEAK_GBS = 8000.0
 #                read 2 stored quantities, read+write 2 imaging sums            68 B
 # (u_bar = b v_bar and t_bar = C sigma_bar are the scaled adjoint variables.)
 KERNEL_BYTES = {"fwd_vel": (36, 44), "fwd_str": (44, 56), "adj_vel": (72, 72), "adj_str": (68, 68)}
-# Whole-path algorithmic bytes per cell-step (fwd + adj + grad, sqrt(nt) recomputation):
-# forward 52 + stored velocities 8 + adjoint 52 + imaging reads 16 + accumulators 24 + recompute 52.
-PATH_BYTES_PER_CELL_STEP = 204
+
+
+def path_bytes_per_cell_step(recompute_fraction):
+    """Whole-path algorithmic bytes per cell-step: every step runs forward once with storing
+    (fwd_vel + fwd_str with store) and backward once (adj_vel + adj_str); each recomputed
+    step adds a forward step without storing in the first sweep."""
+    fwd_plain = KERNEL_BYTES["fwd_vel"][0] + KERNEL_BYTES["fwd_str"][0]
+    fwd_store = KERNEL_BYTES["fwd_vel"][1] + KERNEL_BYTES["fwd_str"][1]
+    adj = KERNEL_BYTES["adj_vel"][0] + KERNEL_BYTES["adj_str"][0]
+    return fwd_store + adj + recompute_fraction * fwd_plain
 
 
 def kernel_bytes_per_launch(name, cells, nt, L):
@@ -83,6 +97,10 @@ def cpu_baseline(w, target_s=12.0):
                       f"FP64 NumPy (single-threaded elementwise), {dt:.1f} s"}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():  # noqa: C901
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +111,11 @@ def main():  # noqa: C901
     ap.add_argument("--sample-every", type=int, default=16, help="time every k-th launch of each kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-sqrt", action="store_true", help="skip the sqrt(nt)-checkpoint form")
+    ap.add_argument("--interval", type=int, default=-1,
+                    help="checkpoint interval of the plain form (-1: largest that fits, 0: sqrt(nt))")
+    ap.add_argument("--mem-fraction", type=float, default=0.92,
+                    help="share of the free device memory the plain form's workspace may take")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
@@ -136,54 +159,86 @@ def main():  # noqa: C901
     rws = efwi.workspace(efwi.workspace_size(efwi.WS_REGULARIZER, grid, []), dev)
     nch = [s.nch for s in shots]
     obs = list(torch.split(d_obs, nch))
+    torch.cuda.synchronize()
+    # Checkpoint interval: the largest whose workspace fits in the free HBM (whole history
+    # when it fits: nothing recomputed).
+    budget = int(args.mem_fraction * torch.cuda.mem_get_info(dev)[0])
+    L = efwi.plan_interval(grid, shots[0], budget) if args.interval < 0 else args.interval
+    shots = [dataclasses.replace(s, ckpt_interval=L, _keep=[]) for s in shots]
     ws = efwi.workspace(efwi.workspace_size(efwi.WS_GRADIENT, grid, shots[:1]), dev)
     torch.cuda.synchronize()
+    log(f"set-up done: checkpoint interval {L}, workspace {ws.numel() / 2**30:.1f} GiB")
 
-    def plain_step():
+    def plain_step(shot_list, wsp):
         """Plain per-shot form: one shot gradient after the other, one shot's workspace."""
         for k in range(ns):
-            efwi.shot_gradient(grid, shots[k], m_ext[k], src[k], obs[k], g=g_ext[k], phi=phi[k], ws=ws)
+            efwi.shot_gradient(grid, shot_list[k], m_ext[k], src[k], obs[k], g=g_ext[k], phi=phi[k], ws=wsp)
         efwi.extension_regularizer(grid, m_ext, b, sink, 1.0, g_ext, phi=phi_reg, ws=rws)
 
     for _ in range(args.warmup):
-        plain_step()
+        plain_step(shots, ws)
     torch.cuda.synchronize()
+    log("warm-up done")
     efwi.timing_reset()
     efwi.timing_enable(args.sample_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plain_step()
+        plain_step(shots, ws)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     timing = efwi.timing_query()
     efwi.timing_enable(0)
     assert bool(torch.isfinite(phi).all()) and bool(torch.isfinite(phi_reg))
-    g_plain = g_ext.clone() if not args.no_batched else None
+    g_plain = g_ext.clone()
+    log(f"timed steps done: {elapsed:.2f} s")
     del ws
+    torch.cuda.empty_cache()
 
-    batched = None
+    forms = {}
+
+    def timed_once(fn):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t1
+        return {"shots_per_s": round(ns / dt_, 4), "gcell_per_s": round(ns * nz * nx * nt / dt_ / 1e9, 4),
+                "ms_per_step": round(dt_ * 1e3, 2), "identical_to_plain": bool(torch.equal(g_plain, g_ext))}
+
+    if not args.no_sqrt:
+        # sqrt(nt)-checkpoint form: every segment but the last recomputed in the reverse sweep.
+        sq = [dataclasses.replace(s, ckpt_interval=0, _keep=[]) for s in shots]
+        sws = efwi.workspace(efwi.workspace_size(efwi.WS_GRADIENT, grid, sq[:1]), dev)
+        g_ext.zero_()
+        forms["sqrt_nt_checkpoints"] = timed_once(lambda: plain_step(sq, sws))
+        forms["sqrt_nt_checkpoints"]["recompute_fraction"] = round(efwi.recompute_fraction(grid, 0), 4)
+        log(f"sqrt(nt) form done: {forms['sqrt_nt_checkpoints']}")
+        del sws
+        torch.cuda.empty_cache()
+
     if not args.no_batched:
         # Batched form: every shot advanced together (one launch per half step covers all
-        # shots' tiles), in as few waves as the free device memory allows.
-        need = efwi.workspace_size(efwi.WS_BATCH, grid, shots)
+        # shots' tiles), sqrt(nt) checkpoints, in as few waves as the free memory allows.
+        bshots = [dataclasses.replace(s, ckpt_interval=0, _keep=[]) for s in shots]
+        need = efwi.workspace_size(efwi.WS_BATCH, grid, bshots)
         free = torch.cuda.mem_get_info(dev)[0]
         bws = efwi.workspace(min(need, int(free * 0.9)), dev)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        efwi.batch_gradient(grid, shots, m_ext, src, d_obs, g_ext=g_ext, phi=phi, ws=bws)
-        efwi.extension_regularizer(grid, m_ext, b, sink, 1.0, g_ext, phi=phi_reg, ws=rws)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - tb
-        same = bool(torch.equal(g_plain, g_ext))
-        batched = {"shots_per_s": round(ns / tb, 4), "gcell_per_s": round(ns * nz * nx * nt / tb / 1e9, 4),
-                   "ms_per_step": round(tb * 1e3, 2), "waves": -(-need // bws.numel()),
-                   "identical_to_plain": same}
+        g_ext.zero_()
+
+        def batched_step():
+            efwi.batch_gradient(grid, bshots, m_ext, src, d_obs, g_ext=g_ext, phi=phi, ws=bws)
+            efwi.extension_regularizer(grid, m_ext, b, sink, 1.0, g_ext, phi=phi_reg, ws=rws)
+
+        forms["batched"] = timed_once(batched_step)
+        forms["batched"]["waves"] = -(-need // bws.numel())
+        log(f"batched form done: {forms['batched']}")
         del bws
+        torch.cuda.empty_cache()
 
     cell_steps = ns * nz * nx * nt * args.steps
     value = cell_steps / elapsed / 1e9
-    L = int(np.ceil(np.sqrt(nt)))
+    rf = efwi.recompute_fraction(grid, L)
     kern = {}
     for name, (launches, timed, ms) in timing.items():
         if launches:
@@ -195,6 +250,7 @@ def main():  # noqa: C901
     dominant = max((n for n in kern if n in KERNEL_BYTES), key=lambda n: kern[n]["share"])
     bytes_launch = kernel_bytes_per_launch(dominant, nz * nx, nt, L)
     achieved = bytes_launch / (kern[dominant]["mean_us"] * 1e-6) / 1e9
+    pb = path_bytes_per_cell_step(rf)
     out = {
         "metric": "Gcell-updates/s fwd+adj+grad (and % HBM roofline); shots/s batched vs plain",
         "value": round(value, 4),
@@ -209,18 +265,19 @@ def main():  # noqa: C901
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"plain per-shot 2D elastic, {nz}x{nx} dx=2.5m, nt={nt}, {ns} MT shots, "
-                               f"{len(w.shots[0].ch_ix)} DAS channels, CPML {w.npml}, sqrt(nt) FP32 checkpoints, "
-                               f"+ extension regularizer (hard sinkholes)",
-                   "nz": nz, "nx": nx, "nt": nt, "shots": ns, "ckpt_interval": L, "form": "plain per-shot"},
+                               f"{len(w.shots[0].ch_ix)} DAS channels, CPML {w.npml}, FP32 history "
+                               f"(checkpoint interval {L}), + extension regularizer (hard sinkholes)",
+                   "nz": nz, "nx": nx, "nt": nt, "shots": ns, "ckpt_interval": L,
+                   "recompute_fraction": round(rf, 4), "form": "plain per-shot"},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": int(bytes_launch), "mean_launch_us": kern[dominant]["mean_us"]},
-        "path": {"bytes_per_cell_step": PATH_BYTES_PER_CELL_STEP,
-                 "achieved_GBs": round(PATH_BYTES_PER_CELL_STEP * cell_steps / elapsed / 1e9, 1),
-                 "frac": round(PATH_BYTES_PER_CELL_STEP * cell_steps / elapsed / 1e9 / HBM_PEAK_GBS, 4)},
+        "path": {"bytes_per_cell_step": round(pb, 1),
+                 "achieved_GBs": round(pb * cell_steps / elapsed / 1e9, 1),
+                 "frac": round(pb * cell_steps / elapsed / 1e9 / HBM_PEAK_GBS, 4)},
         "shots_per_s": {"plain": round(ns * args.steps / elapsed, 4),
-                        "batched": batched["shots_per_s"] if batched else None},
-        "batched": batched,
+                        **{k: v["shots_per_s"] for k, v in forms.items()}},
+        "forms": forms,
         "kernels": kern,
     }
     if not args.no_cpu_baseline:

@@ -92,6 +92,17 @@ typedef enum {
  * efwi_last_error). For EFWI_WS_BATCH, shots points to ns HOST descriptors. */
 size_t efwi_workspace_size(efwi_ws_kind kind, const efwi_grid* grid, int ns, const efwi_shot* shots);
 
+/* Checkpoint interval for a memory budget (host only, no HIP call): the largest
+ * ckpt_interval L whose EFWI_WS_GRADIENT workspace for this shot (with its ckpt_mode) fits
+ * in budget_bytes. L = nt keeps the whole forward history and the reverse sweep recomputes
+ * nothing; otherwise it recomputes (ceil(nt / L) - 1) L of the nt steps, so the larger L
+ * the less work. The search starts from ceil(sqrt(nt)), the default interval. (The
+ * gradient of eq.(6) cross-correlates the forward and adjoint wavefields, Solving the
+ * inverse problem; how the forward history is kept is an implementation choice.) Returns L > 0, or a
+ * negative efwi_status: EFWI_E_WORKSPACE when even ceil(sqrt(nt)) does not fit, or the
+ * status efwi_validate reports. */
+int efwi_plan_interval(const efwi_grid* grid, const efwi_shot* shot, size_t budget_bytes);
+
 /* Host-side validation only (no HIP call): the checks every entry point runs first. */
 efwi_status efwi_validate(const efwi_grid* grid, int ns, const efwi_shot* shots);
 

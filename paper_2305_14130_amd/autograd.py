@@ -9,13 +9,12 @@ objective of eq.(8) as differentiable functions of the (extended) model.
 * ``ExtensionPenalty`` m~ -> 1/2 eta^2 ||(I - S^T S_w) W m~||^2.
 * ``extended_misfit`` the sum of the two, eq.(8).
 
-Checkpointing: ``checkpoint_interval`` keeps the whole forward history when its workspace
-fits in a fraction of the free device memory and otherwise picks sqrt(nt) checkpoints with
-recomputation (the library's default for ``ckpt_interval = 0``).
+Checkpointing: ``checkpoint_interval`` picks the largest checkpoint interval whose workspace
+fits in a fraction of the free device memory (the whole forward history when it fits, so
+nothing is recomputed; sqrt(nt) checkpoints, the library's default, at the least).
 """
 from __future__ import annotations
 
-import dataclasses
 
 import torch
 
@@ -23,11 +22,16 @@ from . import efwi
 
 
 def checkpoint_interval(grid, shot, device=None, budget_fraction=0.6) -> int:
-    """nt (no recomputation) if the full-history workspace fits, else 0 (sqrt(nt))."""
-    full = dataclasses.replace(shot, ckpt_interval=grid.nt, _keep=[])
-    need = efwi.workspace_size(efwi.WS_GRADIENT, grid, [full])
-    free = torch.cuda.mem_get_info(device)[0]
-    return grid.nt if need <= budget_fraction * free else 0
+    """Largest checkpoint interval whose workspace fits in a fraction of the free device
+    memory (nt: whole history, no recomputation); 0 (sqrt(nt)) if even that does not fit,
+    and the call then needs the memory it needs."""
+    budget = int(budget_fraction * torch.cuda.mem_get_info(device)[0])
+    try:
+        return efwi.plan_interval(grid, shot, budget)
+    except efwi.EfwiError as e:
+        if e.status != efwi.E_WORKSPACE:
+            raise
+        return 0
 
 
 class ShotData(torch.autograd.Function):

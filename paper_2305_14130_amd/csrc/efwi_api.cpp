@@ -1218,6 +1218,29 @@ size_t efwi_workspace_size(efwi_ws_kind kind, const efwi_grid* grid, int ns, con
   return wave_bytes(plans, 0, n);
 }
 
+int efwi_plan_interval(const efwi_grid* grid, const efwi_shot* shot, size_t budget_bytes) {
+  efwi_status rc = efwi_validate(grid, 1, shot);
+  if (rc != EFWI_OK) return rc;
+  efwi_shot s = *shot;
+  auto need = [&](int L) {
+    s.ckpt_interval = L;
+    return efwi_workspace_size(EFWI_WS_GRADIENT, grid, 1, &s);
+  };
+  const int nt = grid->nt;
+  if (need(nt) <= budget_bytes) return nt;
+  int lo = std::min(nt, (int)std::ceil(std::sqrt((double)nt)));
+  if (need(lo) > budget_bytes)
+    return fail(EFWI_E_WORKSPACE, "even the sqrt(nt) checkpoint workspace (%zu bytes) exceeds the budget",
+                need(lo));
+  int hi = nt;  // need(lo) fits, need(hi) does not
+  while (hi - lo > 1) {
+    const int mid = lo + (hi - lo) / 2;
+    if (need(mid) <= budget_bytes) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 efwi_status efwi_model_forward(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* src,
                                float* d, void* ws, size_t ws_bytes, void* stream) {
   efwi_status rc = efwi_validate(grid, 1, shot);

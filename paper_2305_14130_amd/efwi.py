@@ -29,7 +29,8 @@ WS_FORWARD, WS_ADJOINT, WS_GRADIENT, WS_BATCH, WS_REGULARIZER = 0, 1, 2, 3, 4
 EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_model_adjoint",
             "efwi_shot_gradient", "efwi_shot_jt", "efwi_batch_gradient", "efwi_extension_regularizer",
             "efwi_status_string", "efwi_last_error", "efwi_version", "efwi_timing_enable",
-            "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name"]
+            "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name",
+            "efwi_plan_interval"]
 
 
 class Grid(ctypes.Structure):
@@ -101,6 +102,8 @@ def n_components(grid: Grid) -> int:
 _vp = ctypes.c_void_p
 _lib.efwi_workspace_size.restype = ctypes.c_size_t
 _lib.efwi_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC)]
+_lib.efwi_plan_interval.restype = ctypes.c_int
+_lib.efwi_plan_interval.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), ctypes.c_size_t]
 _lib.efwi_validate.restype = ctypes.c_int
 _lib.efwi_validate.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC)]
 _lib.efwi_model_forward.restype = ctypes.c_int
@@ -206,6 +209,24 @@ def workspace_size(kind: int, grid: Grid, shots) -> int:
     if n == 0 and kind != WS_REGULARIZER:
         raise EfwiError(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr), _lib.efwi_last_error().decode())
     return int(n)
+
+
+def plan_interval(grid: Grid, shot: Shot, budget_bytes: int) -> int:
+    """Largest checkpoint interval whose gradient workspace fits the budget (nt: the whole
+    forward history is kept and nothing is recomputed)."""
+    sc = shot.c_struct()
+    L = _lib.efwi_plan_interval(ctypes.byref(grid), ctypes.byref(sc), int(budget_bytes))
+    _check(min(L, 0))
+    return int(L)
+
+
+def recompute_fraction(grid: Grid, interval: int) -> float:
+    """Share of the nt steps that the reverse sweep recomputes for a checkpoint interval
+    (0: ceil(sqrt(nt))): every segment but the last, which the first sweep keeps."""
+    nt = grid.nt
+    L = interval if interval > 0 else int(np.ceil(np.sqrt(nt)))
+    L = max(1, min(L, nt))
+    return (-(-nt // L) - 1) * L / nt
 
 
 def workspace(nbytes: int, device=None) -> torch.Tensor:

@@ -78,3 +78,25 @@ def test_workspace_size_grows_with_checkpoint_interval(efwi):
     full = efwi.workspace_size(efwi.WS_GRADIENT, grid, [shot])
     assert full > small
     assert efwi.workspace_size(efwi.WS_FORWARD, grid, [shot]) < small
+
+
+def test_plan_interval_fits_the_budget(efwi):
+    grid, shot = _ok_case(efwi)
+    nt = grid.nt
+
+    def need(L):
+        shot.ckpt_interval = L
+        return efwi.workspace_size(efwi.WS_GRADIENT, grid, [shot])
+
+    assert efwi.plan_interval(grid, shot, 1 << 40) == nt
+    sq = int(np.ceil(np.sqrt(nt)))
+    L = efwi.plan_interval(grid, shot, need(sq))   # fewer checkpoint slots may let a larger L fit
+    assert L >= sq and need(L) <= need(sq)
+    budget = (need(sq) + need(nt)) // 2
+    L = efwi.plan_interval(grid, shot, budget)
+    assert sq <= L < nt and need(L) <= budget < need(L + 1)
+    with pytest.raises(efwi.EfwiError) as ei:
+        efwi.plan_interval(grid, shot, need(sq) - 1)
+    assert ei.value.status == efwi.E_WORKSPACE
+    assert efwi.recompute_fraction(grid, nt) == 0.0
+    assert efwi.recompute_fraction(grid, 10) == (5 - 1) * 10 / nt
