@@ -19,7 +19,7 @@ resident in HBM before the timed region. The JSON line also carries:
   (HIP events around sampled launches on the library's stream), against 8 TB/s;
 * cpu_baseline: the FP64 NumPy oracle on a bounded sample (one shot, full grid, a few
   time steps), in the same unit;
-* path: the whole step's algorithmic bytes (240 B per cell-step plus 80 B per recomputed
+* path: the whole step's algorithmic bytes (224 B per cell-step plus 80 B per recomputed
   cell-step) over the step time.
 """
 from __future__ import annotations
@@ -44,11 +44,12 @@ HBM_PEAK_GBS = 8000.0
 #   fwd_str      read vx vz sxx szz sxz l2m lam muxz, write sxx szz sxz         44 B
 #                + store pxx pzz (pzx+pxz)                                      +12 B
 #   adj_vel      read t_bar (3), u_bar (2), bx bz, write u_bar (2),
-#                read 3 stored quantities, read+write 3 imaging sums            72 B
+#                read 3 stored quantities, read+write 2 imaging sums            64 B
 #   adj_str      read u_bar (2), t_bar (3), l2m lam muxz, write t_bar (3),
-#                read 2 stored quantities, read+write 2 imaging sums            68 B
-# (u_bar = b v_bar and t_bar = C sigma_bar are the scaled adjoint variables.)
-KERNEL_BYTES = {"fwd_vel": (36, 44), "fwd_str": (44, 56), "adj_vel": (72, 72), "adj_str": (68, 68)}
+#                read 2 stored quantities, read+write 1 imaging sum             60 B
+# (u_bar = b v_bar and t_bar = C sigma_bar are the scaled adjoint variables; the imaging
+# sums are gathered at the normal node, so neighbours' values come from the caches.)
+KERNEL_BYTES = {"fwd_vel": (36, 44), "fwd_str": (44, 56), "adj_vel": (64, 64), "adj_str": (60, 60)}
 
 
 def path_bytes_per_cell_step(recompute_fraction):

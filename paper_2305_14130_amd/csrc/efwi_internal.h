@@ -22,13 +22,15 @@ constexpr int ROW_ALIGN = 32;
 constexpr int BX = 64;
 constexpr int BZ = 4;
 // Number of per-step forward quantities kept for the imaging condition (see k_fwd_str and
-// k_fwd_vel): (pxx+pzz)/(2(l+m)), (pxx-pzz)/(2m) at the normal node, (pzx+pxz)/mu_xz at the
-// shear node, qx/b_x and qz/b_z at the velocity nodes (p, q: CPML-corrected strain rates
-// and stress divergences of the step).
+// k_fwd_vel), each already multiplied by the factor it meets in the gradient of its
+// parameter: (pxx+pzz)/(2(l+m)) and (pxx-pzz) mu/2 at the normal node, (pzx+pxz) mu_xz/4 at
+// the shear node, qx b_x/2 and qz b_z/2 at the velocity nodes (p, q: CPML-corrected strain
+// rates and stress divergences of the step).
 constexpr int NSEG_FIELDS = 5;
-// Number of imaging accumulators: lambda, mu - lambda (normal node), mu_xz (shear node),
-// b_x, b_z (velocity nodes).
-constexpr int NACC = 5;
+// Number of imaging accumulators, all at the normal node: lambda; mu scaled by mu^2
+// (the normal-node mu term plus the four surrounding mu_xz terms); rho through the
+// buoyancies of the four surrounding velocity nodes.
+constexpr int NACC = 3;
 // Time steps summed in FP32 before the imaging sums are chained into the FP64 gradient.
 constexpr int FLUSH_STEPS = 32;
 

@@ -121,10 +121,10 @@ __device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, gflo
   const float qx = d1 + d2, qz = d3 + d4;
   s.vx[o] += s.dt * s.bx[o] * qx;
   s.vz[o] += s.dt * s.bz[o] * qz;
-  if (STORE) {  // divergences pre-divided by the buoyancy for the b_x, b_z imaging terms
+  if (STORE) {  // divergences times b/2: the rho imaging terms (d b / d rho = -b^2/2)
     const long c = (long)i * s.cp + j;
-    seg[3 * s.cells + c] = qx / s.bx[o];
-    seg[4 * s.cells + c] = qz / s.bz[o];
+    seg[3 * s.cells + c] = 0.5f * qx * s.bx[o];
+    seg[4 * s.cells + c] = 0.5f * qz * s.bz[o];
   }
 }
 
@@ -197,12 +197,11 @@ __device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int 
       }
     }
   }
-  if (STORE) {  // strain rates pre-divided by the moduli for the lambda, mu, mu_xz imaging terms
+  if (STORE) {  // strain rates times the factors of the lambda and mu imaging terms
     const long c = (long)i * s.cp + j;
-    const float mxz = s.muxz[o];
     seg[c] = (pxx + pzz) / (l2m + lam);
-    seg[s.cells + c] = (pxx - pzz) / (l2m - lam);
-    seg[2 * s.cells + c] = mxz > 0.0f ? ps / mxz : 0.0f;
+    seg[s.cells + c] = 0.25f * (pxx - pzz) * (l2m - lam);
+    seg[2 * s.cells + c] = 0.25f * ps * s.muxz[o];
   }
 }
 
@@ -230,12 +229,31 @@ __global__ __launch_bounds__(BX * BZ) void k_fwd_str(BATCH_PARAMS, int n, int ks
 // t_bar += C D^T q_bar. D^T uses D-^T = -D+ and D+^T = -D- (zero outside the grid).
 // CPML transpose of psi <- b psi + a D, D~ = D + psi: psi_bar += y_bar; x_bar = y_bar +
 // a psi_bar; psi_bar <- b psi_bar (double-buffered: neighbours read the old value).
-// Imaging (gradients of <d, r> w.r.t. the staged parameters) with the forward quantities
-// stored pre-divided by the parameters:
-//   g_lambda += dt (t_xx + t_zz) (pxx + pzz)/(2(l+m))          = dt sum(sigma_bar) (pxx+pzz)
-//   g_mu - g_lambda += dt (t_xx - t_zz) (pxx - pzz)/(2m)
-//   g_mu_xz += dt t_xz (pzx + pxz)/mu_xz                        = dt sigma_bar_xz (pzx+pxz)
-//   g_b_x += dt u_x qx / b_x                                    = dt v_bar_x qx   (same z)
+// Imaging (the adjoint-state correlations of eq.(6)), gathered at the normal node (i, j)
+// from the stored forward quantities h0..h4 (see NSEG_FIELDS) into three sums:
+//   A += dt (t_xx + t_zz) h0                                    g_lambda
+//   E += dt [(t_xx - t_zz) h1 + sum_k c_k t_xz(k) h2(k)]        mu^2 g_mu
+//   R -= dt [sum_b c_b u_x(b) h3(b) + sum_a c_a u_z(a) h4(a)]   g_rho through b_x, b_z
+// over the four shear nodes k and the two vx nodes b and two vz nodes a whose staged
+// value uses mu(i, j) or rho(i, j), c counting how often (twice at a clamped edge).
+// With t = C sigma_bar, t_xx + t_zz = 2(l+m)(s_xx + s_zz) and t_xx - t_zz = 2m(s_xx - s_zz);
+// d mu_xz / d mu = mu_xz^2 / (4 mu^2) per corner and d b / d rho = -b^2 / 2, so the chain
+// rule at the end of each block of steps needs only g_mu = A + E / mu^2 and R.
+// ------------------------------------------------------------------------------------
+
+// How often the shear node (a, b) (harmonic mean over the clamped corners (a, b),
+// (a+1, b), (a, b+1), (a+1, b+1)) uses the normal node (i, j).
+__device__ __forceinline__ int corner_count(int a, int b, int i, int j, int nz, int nx) {
+  if (a < 0 || b < 0) return 0;
+  const int ap = min(a + 1, nz - 1), bp = min(b + 1, nx - 1);
+  return (a == i && b == j) + (ap == i && b == j) + (a == i && bp == j) + (ap == i && bp == j);
+}
+// How often the velocity node between k and k+1 (clamped) uses node m along that axis.
+__device__ __forceinline__ int pair_count(int k, int m, int n) {
+  if (k < 0) return 0;
+  return (k == m) + (min(k + 1, n - 1) == m);
+}
+
 // ------------------------------------------------------------------------------------
 template <bool PML>
 struct AdjCtx {
@@ -393,9 +411,16 @@ __device__ __forceinline__ void adj_vel_finish(const Shot2D& s, int i, int j, in
   s.uzb[o] += s.bz[o] * gz;
   if (GRAD) {
     const long cc = (long)i * s.cp + j;
+    const gfloat* h2 = seg + 2 * s.cells;
+    float e = (txx - tzz) * seg[s.cells + cc];
+    for (int a = i - 1; a <= i; ++a) {
+      for (int b = j - 1; b <= j; ++b) {
+        const int c = corner_count(a, b, i, j, s.nz, s.nx);
+        if (c) e += (float)c * s.txzb[(long)a * ld + b] * h2[(long)a * s.cp + b];
+      }
+    }
     accumulate(s.acc, cc, s.dt * (txx + tzz) * seg[cc], first);
-    accumulate(s.acc, s.cells + cc, s.dt * (txx - tzz) * seg[s.cells + cc], first);
-    accumulate(s.acc, 2 * s.cells + cc, s.dt * txz * seg[2 * s.cells + cc], first);
+    accumulate(s.acc, s.cells + cc, s.dt * e, first);
   }
   if (SRCADJ && i == s.si && j == s.sj) {
     // sigma_bar at the source from t_bar: invert the 2x2 normal block and the shear moduli
@@ -480,8 +505,18 @@ __device__ __forceinline__ void adj_str_finish(const Shot2D& s, int i, int j, in
   s.txzb[o] += s.muxz[o] * dsxz;
   if (GRAD) {
     const long cc = (long)i * s.cp + j;
-    accumulate(s.acc, 3 * s.cells + cc, s.dt * ux * seg[3 * s.cells + cc], first);
-    accumulate(s.acc, 4 * s.cells + cc, s.dt * uz * seg[4 * s.cells + cc], first);
+    const gfloat* h3 = seg + 3 * s.cells;
+    const gfloat* h4 = seg + 4 * s.cells;
+    float r = 0.0f;
+    for (int b = j - 1; b <= j; ++b) {  // vx nodes (i, b + 1/2): b_x averages rho(i, b), rho(i, b + 1)
+      const int c = pair_count(b, j, s.nx);
+      if (c) r += (float)c * s.uxb[(long)i * ld + b] * h3[(long)i * s.cp + b];
+    }
+    for (int a = i - 1; a <= i; ++a) {  // vz nodes (a + 1/2, j)
+      const int c = pair_count(a, i, s.nz);
+      if (c) r += (float)c * s.uzb[(long)a * ld + j] * h4[(long)a * s.cp + j];
+    }
+    accumulate(s.acc, 2 * s.cells + cc, -s.dt * r, first);
   }
 }
 
@@ -551,9 +586,9 @@ __global__ __launch_bounds__(BX * BZ) void k_stage(BATCH_PARAMS) {
 }
 
 // ------------------------------------------------------------------------------------
-// Chain rule of one segment's FP32 imaging sums into the FP64 (Vp, Vs, rho) gradient.
-// d mu_xz / d mu_k = mu_xz^2 / (4 mu_k^2) over its four clamped corners; d b / d rho = -b^2/2
-// on both (clamped) nodes of the average; lambda = rho(Vp^2 - 2Vs^2), mu = rho Vs^2.
+// Chain rule of one block's FP32 imaging sums (A, E, R at the normal node, gathered over
+// the staggered nodes by the adjoint kernels) into the FP64 (Vp, Vs, rho) gradient:
+// g_lambda = A, g_mu = A + E / mu^2, g_rho(b) = R; lambda = rho(Vp^2 - 2Vs^2), mu = rho Vs^2.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(BX * BZ) void k_chain_flush(BATCH_PARAMS) {
   BATCH_TILE();
@@ -561,50 +596,13 @@ __global__ __launch_bounds__(BX * BZ) void k_chain_flush(BATCH_PARAMS) {
   if (i >= s.nz || j >= s.nx) return;
   const long cc = (long)i * s.cp + j;
   const long mo = (long)i * s.mld + j;
-  const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
-  const float mu = rho * vs * vs;
-  const gfloat* glam = s.acc;
-  const gfloat* gdmu = s.acc + s.cells;        // g_mu - g_lambda
-  const gfloat* gmuxz = s.acc + 2 * s.cells;
-  const gfloat* gbx = s.acc + 3 * s.cells;
-  const gfloat* gbz = s.acc + 4 * s.cells;
-  double gmu_tot = (double)glam[cc] + (double)gdmu[cc];
-  for (int di = -1; di <= 0; ++di) {
-    for (int dj = -1; dj <= 0; ++dj) {
-      const int a = i + di, b = j + dj;
-      if (a < 0 || b < 0) continue;
-      const int ap = min(a + 1, s.nz - 1), bp = min(b + 1, s.nx - 1);
-      const int mult = (a == i && b == j) + (ap == i && b == j) + (a == i && bp == j) + (ap == i && bp == j);
-      if (mult == 0) continue;
-      const float mxz = s.muxz[(long)a * s.ld + b];
-      if (mxz > 0.0f)
-        gmu_tot += (double)mult * gmuxz[(long)a * s.cp + b] * ((double)mxz * mxz / (4.0 * (double)mu * mu));
-    }
-  }
-  double grho_b = 0.0;
-  for (int db = -1; db <= 0; ++db) {      // vx nodes (i, b) average rho(i, b), rho(i, b+1)
-    const int b = j + db;
-    if (b < 0) continue;
-    const int bp = min(b + 1, s.nx - 1);
-    const int mult = (b == j) + (bp == j);
-    if (mult == 0) continue;
-    const double bxv = s.bx[(long)i * s.ld + b];
-    grho_b -= 0.5 * mult * gbx[(long)i * s.cp + b] * bxv * bxv;
-  }
-  for (int da = -1; da <= 0; ++da) {      // vz nodes (a, j) average rho(a, j), rho(a+1, j)
-    const int a = i + da;
-    if (a < 0) continue;
-    const int ap = min(a + 1, s.nz - 1);
-    const int mult = (a == i) + (ap == i);
-    if (mult == 0) continue;
-    const double bzv = s.bz[(long)a * s.ld + j];
-    grho_b -= 0.5 * mult * gbz[(long)a * s.cp + j] * bzv * bzv;
-  }
-  const double gl = glam[cc];
-  const double dvp = vp, dvs = vs, drho = rho;
-  s.G[cc] += 2.0 * drho * dvp * gl;
-  s.G[s.cells + cc] += 2.0 * drho * dvs * (gmu_tot - 2.0 * gl);
-  s.G[2 * s.cells + cc] += (dvp * dvp - 2.0 * dvs * dvs) * gl + dvs * dvs * gmu_tot + grho_b;
+  const double vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
+  const double mu = rho * vs * vs;
+  const double gl = s.acc[cc];
+  const double gmu = gl + (mu > 0.0 ? (double)s.acc[s.cells + cc] / (mu * mu) : 0.0);
+  s.G[cc] += 2.0 * rho * vp * gl;
+  s.G[s.cells + cc] += 2.0 * rho * vs * (gmu - 2.0 * gl);
+  s.G[2 * s.cells + cc] += (vp * vp - 2.0 * vs * vs) * gl + vs * vs * gmu + (double)s.acc[2 * s.cells + cc];
 }
 
 __global__ __launch_bounds__(BX * BZ) void k_write_gradient(BATCH_PARAMS) {
