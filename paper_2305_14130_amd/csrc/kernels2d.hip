@@ -18,8 +18,15 @@
 // are separate kernels rather than the forward run backwards.
 #include "efwi_internal.h"
 
+// Contract a * b + c into one fused multiply-add only inside a single expression, never
+// across statements: every template instance of a kernel then rounds the same source the
+// same way, so runs that differ only in what they store stay bitwise identical.
+#pragma clang fp contract(on)
+
 namespace efwi {
 namespace {
+
+static_assert(BX == 64, "a wavefront must cover exactly one row of a block");
 
 constexpr float K1 = 1.125f;              // 9/8
 constexpr float K2 = -0.041666666666666664f;  // -1/24
@@ -85,6 +92,10 @@ __device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, in
   return (j0 - pad < s.P) || (j1 >= s.nx - s.P) || (i0 - pad < s.P) || (i1 >= s.nz - s.P);
 }
 
+// Every cell function below issues all of its loads before its first store: the
+// compiler cannot prove that the shot's arrays do not alias, so a store placed before a
+// load would force another memory round trip per wavefront.
+
 // ------------------------------------------------------------------------------------
 // Forward velocity half step: v^{n+1/2} = v^{n-1/2} + dt b (div sigma^n), CPML in strips.
 // ------------------------------------------------------------------------------------
@@ -96,35 +107,45 @@ __device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, gflo
   float d2 = dminus(s.sxz, o, ld, s.rdz);  // D-z sxz at (i, j+1/2)
   float d3 = dminus(s.sxz, o, 1, s.rdx);   // D-x sxz at (i+1/2, j)
   float d4 = dplus(s.szz, o, ld, s.rdz);   // D+z szz at (i+1/2, j)
+  const float vx = s.vx[o], vz = s.vz[o], bx = s.bx[o], bz = s.bz[o];
+  int sx = -1, sz = -1;
+  long qx_ = 0, qz_ = 0;
+  float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f, p4 = 0.0f;
   if (PML) {
-    const int sx = strip_index(j, s.nx, s.P);
-    const int sz = strip_index(i, s.nz, s.P);
+    sx = strip_index(j, s.nx, s.P);
+    sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
-      const long q = (long)i * 2 * s.P + sx;
-      float p = bxh(s)[j] * s.psx[X_VXX][q] + axh(s)[j] * d1;
-      s.psx[X_VXX][q] = p;
-      d1 += p;
-      p = bxi(s)[j] * s.psx[X_VZX][q] + axi(s)[j] * d3;
-      s.psx[X_VZX][q] = p;
-      d3 += p;
+      qx_ = (long)i * 2 * s.P + sx;
+      p1 = bxh(s)[j] * s.psx[X_VXX][qx_] + axh(s)[j] * d1;
+      p3 = bxi(s)[j] * s.psx[X_VZX][qx_] + axi(s)[j] * d3;
+      d1 += p1;
+      d3 += p3;
     }
     if (sz >= 0) {
-      const long q = (long)sz * s.nx + j;
-      float p = bzi(s)[i] * s.psz[Z_VXZ][q] + azi(s)[i] * d2;
-      s.psz[Z_VXZ][q] = p;
-      d2 += p;
-      p = bzh(s)[i] * s.psz[Z_VZZ][q] + azh(s)[i] * d4;
-      s.psz[Z_VZZ][q] = p;
-      d4 += p;
+      qz_ = (long)sz * s.nx + j;
+      p2 = bzi(s)[i] * s.psz[Z_VXZ][qz_] + azi(s)[i] * d2;
+      p4 = bzh(s)[i] * s.psz[Z_VZZ][qz_] + azh(s)[i] * d4;
+      d2 += p2;
+      d4 += p4;
     }
   }
   const float qx = d1 + d2, qz = d3 + d4;
-  s.vx[o] += s.dt * s.bx[o] * qx;
-  s.vz[o] += s.dt * s.bz[o] * qz;
+  if (PML) {
+    if (sx >= 0) {
+      s.psx[X_VXX][qx_] = p1;
+      s.psx[X_VZX][qx_] = p3;
+    }
+    if (sz >= 0) {
+      s.psz[Z_VXZ][qz_] = p2;
+      s.psz[Z_VZZ][qz_] = p4;
+    }
+  }
+  s.vx[o] = vx + s.dt * bx * qx;
+  s.vz[o] = vz + s.dt * bz * qz;
   if (STORE) {  // divergences times b/2: the rho imaging terms (d b / d rho = -b^2/2)
     const long c = (long)i * s.cp + j;
-    seg[3 * s.cells + c] = 0.5f * qx * s.bx[o];
-    seg[4 * s.cells + c] = 0.5f * qz * s.bz[o];
+    seg[3 * s.cells + c] = 0.5f * qx * bx;
+    seg[4 * s.cells + c] = 0.5f * qz * bz;
   }
 }
 
@@ -151,64 +172,82 @@ __device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int 
   float pzx = dplus(s.vx, o, ld, s.rdz);   // D+z vx at (i+1/2, j+1/2)
   float pxz = dplus(s.vz, o, 1, s.rdx);    // D+x vz at (i+1/2, j+1/2)
   const float raw_pxx = pxx;
-  if (PML) {
-    const int sx = strip_index(j, s.nx, s.P);
-    const int sz = strip_index(i, s.nz, s.P);
-    if (sx >= 0) {
-      const long q = (long)i * 2 * s.P + sx;
-      float p = bxi(s)[j] * s.psx[X_XX][q] + axi(s)[j] * pxx;
-      s.psx[X_XX][q] = p;
-      pxx += p;
-      p = bxh(s)[j] * s.psx[X_XZ][q] + axh(s)[j] * pxz;
-      s.psx[X_XZ][q] = p;
-      pxz += p;
-    }
-    if (sz >= 0) {
-      const long q = (long)sz * s.nx + j;
-      float p = bzi(s)[i] * s.psz[Z_ZZ][q] + azi(s)[i] * pzz;
-      s.psz[Z_ZZ][q] = p;
-      pzz += p;
-      p = bzh(s)[i] * s.psz[Z_XZ][q] + azh(s)[i] * pzx;
-      s.psz[Z_XZ][q] = p;
-      pzx += p;
-    }
-  }
-  const float l2m = s.l2m[o], lam = s.lam[o];
-  const float ps = pzx + pxz;
-  float sxx = s.sxx[o] + s.dt * (l2m * pxx + lam * pzz);
-  float szz = s.szz[o] + s.dt * (lam * pxx + l2m * pzz);
-  float sxz = s.sxz[o] + s.dt * s.muxz[o] * ps;
-  if (i == s.si && j == s.sj) {
-    sxx -= s.w * s.src[n];
-    szz -= s.w * s.src[s.nt + n];
-  }
-  if ((i == s.si || i == s.si - 1) && (j == s.sj || j == s.sj - 1)) sxz -= 0.25f * s.w * s.src[2 * s.nt + n];
-  s.sxx[o] = sxx;
-  s.szz[o] = szz;
-  s.sxz[o] = sxz;
+  const float l2m = s.l2m[o], lam = s.lam[o], mxz = s.muxz[o];
+  float sxx = s.sxx[o], szz = s.szz[o], sxz = s.sxz[o];
+  // source components at t_{n+1/2} (uniform scalar loads)
+  const float f_xx = s.src[n], f_zz = s.src[s.nt + n], f_xz = s.src[2 * s.nt + n];
+  // DAS channel of this node, if any (row_slot depends on the wavefront's row only)
+  int ch = -1;
+  float e_old = 0.0f;
   if (RECORD) {
     const int slot = s.row_slot[i];
     if (slot >= 0) {
-      const int c = s.rowch[(long)slot * s.nx + j];
-      if (c >= 0) {
-        const float e = s.e[c] + s.dt * raw_pxx;
-        s.e[c] = e;
-        s.d[(long)c * s.nt + n] = e;
-      }
+      ch = s.rowch[(long)slot * s.nx + j];
+      if (ch >= 0) e_old = s.e[ch];
     }
+  }
+  int sx = -1, sz = -1;
+  long qx_ = 0, qz_ = 0;
+  float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f, p4 = 0.0f;
+  if (PML) {
+    sx = strip_index(j, s.nx, s.P);
+    sz = strip_index(i, s.nz, s.P);
+    if (sx >= 0) {
+      qx_ = (long)i * 2 * s.P + sx;
+      p1 = bxi(s)[j] * s.psx[X_XX][qx_] + axi(s)[j] * pxx;
+      p2 = bxh(s)[j] * s.psx[X_XZ][qx_] + axh(s)[j] * pxz;
+      pxx += p1;
+      pxz += p2;
+    }
+    if (sz >= 0) {
+      qz_ = (long)sz * s.nx + j;
+      p3 = bzi(s)[i] * s.psz[Z_ZZ][qz_] + azi(s)[i] * pzz;
+      p4 = bzh(s)[i] * s.psz[Z_XZ][qz_] + azh(s)[i] * pzx;
+      pzz += p3;
+      pzx += p4;
+    }
+  }
+  const float ps = pzx + pxz;
+  sxx += s.dt * (l2m * pxx + lam * pzz);
+  szz += s.dt * (lam * pxx + l2m * pzz);
+  sxz += s.dt * mxz * ps;
+  if (i == s.si && j == s.sj) {
+    sxx -= s.w * f_xx;
+    szz -= s.w * f_zz;
+  }
+  if ((i == s.si || i == s.si - 1) && (j == s.sj || j == s.sj - 1)) sxz -= 0.25f * s.w * f_xz;
+  if (PML) {
+    if (sx >= 0) {
+      s.psx[X_XX][qx_] = p1;
+      s.psx[X_XZ][qx_] = p2;
+    }
+    if (sz >= 0) {
+      s.psz[Z_ZZ][qz_] = p3;
+      s.psz[Z_XZ][qz_] = p4;
+    }
+  }
+  s.sxx[o] = sxx;
+  s.szz[o] = szz;
+  s.sxz[o] = sxz;
+  if (RECORD && ch >= 0) {
+    const float e = e_old + s.dt * raw_pxx;
+    s.e[ch] = e;
+    s.d[(long)ch * s.nt + n] = e;
   }
   if (STORE) {  // strain rates times the factors of the lambda and mu imaging terms
     const long c = (long)i * s.cp + j;
     seg[c] = (pxx + pzz) / (l2m + lam);
     seg[s.cells + c] = 0.25f * (pxx - pzz) * (l2m - lam);
-    seg[2 * s.cells + c] = 0.25f * ps * s.muxz[o];
+    seg[2 * s.cells + c] = 0.25f * ps * mxz;
   }
 }
 
 template <bool STORE, bool RECORD>
 __global__ __launch_bounds__(BX * BZ) void k_fwd_str(BATCH_PARAMS, int n, int kstore) {
   BATCH_TILE();
-  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  const int j = j0 + threadIdx.x;
+  // all 64 lanes of a wavefront share threadIdx.y: keep the row index scalar
+  const int i = i0 + __builtin_amdgcn_readfirstlane(threadIdx.y);
   gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG_FIELDS * s.cells : nullptr;
   if (i >= s.nz || j >= s.nx) return;
   if (block_in_pml(s, j0, i0, 0)) fwd_str_cell<STORE, RECORD, true>(s, i, j, n, seg);
@@ -325,11 +364,6 @@ __device__ __forceinline__ float ebar_at(const Shot2D& s, int slot, int jc, int 
   return c >= 0 ? s.ebar[(long)n * s.nch + c] : 0.0f;
 }
 
-__device__ __forceinline__ void accumulate(gfloat* acc, long idx, float v, bool first) {
-  if (first) acc[idx] = v;
-  else acc[idx] += v;
-}
-
 // CPML tiles stage the corrected transposed operands of the tile and its halo in LDS, so
 // each node's correction (strip test, profile, adjoint memory variable) is computed once
 // instead of once per neighbour that reads it. Four operands, each over the tile rows or
@@ -381,64 +415,98 @@ __device__ __forceinline__ void adj_vel_finish(const Shot2D& s, int i, int j, in
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx); v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
-  float gx = -(ux * s.rdx + uz * s.rdz);
-  const float gz = -(wz * s.rdz + wx * s.rdx);
-  // DAS transpose: the channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1),
-  // jc+1 (c2) and jc-2 (-c2) of its row
-  const int slot = s.row_slot[i];
-  if (slot >= 0) {
-    const float inj = K1 * (ebar_at(s, slot, j, n) - ebar_at(s, slot, j + 1, n)) +
-                      K2 * (ebar_at(s, slot, j - 1, n) - ebar_at(s, slot, j + 2, n));
-    gx += s.dt * s.rdx * inj;
-  }
+  // ---- loads ----
+  const int slot = s.row_slot[i];  // DAS row slot (depends on the wavefront's row only)
   const float txx = s.txxb[o], tzz = s.tzzb[o], txz = s.txzb[o];
+  const float u0x = s.uxb[o], u0z = s.uzb[o], bx = s.bx[o], bz = s.bz[o];
+  int sx = -1, sz = -1;
+  long qx_ = 0, qz_ = 0;
+  float r1 = 0.0f, r2 = 0.0f, r3 = 0.0f, r4 = 0.0f;
   if (PML) {  // owned adjoint memory variables of the stress-side derivatives
-    const int sx = strip_index(j, s.nx, s.P);
-    const int sz = strip_index(i, s.nz, s.P);
+    sx = strip_index(j, s.nx, s.P);
+    sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
-      const long q = (long)i * 2 * s.P + sx;
-      s.pbx[wr][X_XX][q] = bxi(s)[j] * (s.pbx[rd][X_XX][q] + s.dt * txx);
-      s.pbx[wr][X_XZ][q] = bxh(s)[j] * (s.pbx[rd][X_XZ][q] + s.dt * txz);
+      qx_ = (long)i * 2 * s.P + sx;
+      r1 = bxi(s)[j] * (s.pbx[rd][X_XX][qx_] + s.dt * txx);
+      r2 = bxh(s)[j] * (s.pbx[rd][X_XZ][qx_] + s.dt * txz);
     }
     if (sz >= 0) {
-      const long q = (long)sz * s.nx + j;
-      s.pbz[wr][Z_ZZ][q] = bzi(s)[i] * (s.pbz[rd][Z_ZZ][q] + s.dt * tzz);
-      s.pbz[wr][Z_XZ][q] = bzh(s)[i] * (s.pbz[rd][Z_XZ][q] + s.dt * txz);
+      qz_ = (long)sz * s.nx + j;
+      r3 = bzi(s)[i] * (s.pbz[rd][Z_ZZ][qz_] + s.dt * tzz);
+      r4 = bzh(s)[i] * (s.pbz[rd][Z_XZ][qz_] + s.dt * txz);
     }
   }
-  s.uxb[o] += s.bx[o] * gx;
-  s.uzb[o] += s.bz[o] * gz;
+  long cc = 0;
+  float a0 = 0.0f, a1 = 0.0f, e = 0.0f, h0 = 0.0f;
   if (GRAD) {
-    const long cc = (long)i * s.cp + j;
+    cc = (long)i * s.cp + j;
     const gfloat* h2 = seg + 2 * s.cells;
-    float e = (txx - tzz) * seg[s.cells + cc];
+    h0 = seg[cc];
+    e = (txx - tzz) * seg[s.cells + cc];
+    // shear nodes (a, b), a in {i-1, i}, b in {j-1, j}; indices clamped so every load is
+    // valid and issued up front, with weight 0 where the node does not use mu(i, j)
     for (int a = i - 1; a <= i; ++a) {
       for (int b = j - 1; b <= j; ++b) {
-        const int c = corner_count(a, b, i, j, s.nz, s.nx);
-        if (c) e += (float)c * s.txzb[(long)a * ld + b] * h2[(long)a * s.cp + b];
+        const float c = (float)corner_count(a, b, i, j, s.nz, s.nx);
+        const int aa = max(a, 0), bb = max(b, 0);
+        e += c * s.txzb[(long)aa * ld + bb] * h2[(long)aa * s.cp + bb];
       }
     }
-    accumulate(s.acc, cc, s.dt * (txx + tzz) * seg[cc], first);
-    accumulate(s.acc, s.cells + cc, s.dt * e, first);
+    if (!first) {
+      a0 = s.acc[cc];
+      a1 = s.acc[s.cells + cc];
+    }
   }
-  if (SRCADJ && i == s.si && j == s.sj) {
+  // DAS transpose: the channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1),
+  // jc+1 (c2) and jc-2 (-c2) of its row
+  float inj = 0.0f;
+  if (slot >= 0)
+    inj = K1 * (ebar_at(s, slot, j, n) - ebar_at(s, slot, j + 1, n)) +
+          K2 * (ebar_at(s, slot, j - 1, n) - ebar_at(s, slot, j + 2, n));
+  float sb0 = 0.0f, sb1 = 0.0f, sb2 = 0.0f;
+  const bool at_src = SRCADJ && i == s.si && j == s.sj;
+  if (at_src) {
     // sigma_bar at the source from t_bar: invert the 2x2 normal block and the shear moduli
     const float l2m = s.l2m[o], lam = s.lam[o];
     const float det = (l2m - lam) * (l2m + lam);
-    const float sxx = (l2m * txx - lam * tzz) / det, szz = (l2m * tzz - lam * txx) / det;
+    sb0 = (l2m * txx - lam * tzz) / det;
+    sb1 = (l2m * tzz - lam * txx) / det;
     auto sxz_at = [&](long oo) { return s.muxz[oo] > 0.0f ? s.txzb[oo] / s.muxz[oo] : 0.0f; };
-    const float t = sxz_at(o) + sxz_at(o - 1) + sxz_at(o - ld) + sxz_at(o - ld - 1);
-    s.src_bar[n] = -s.w * sxx;
-    s.src_bar[s.nt + n] = -s.w * szz;
-    s.src_bar[2 * s.nt + n] = -0.25f * s.w * t;
+    sb2 = sxz_at(o) + sxz_at(o - 1) + sxz_at(o - ld) + sxz_at(o - ld - 1);
+  }
+  // ---- arithmetic ----
+  // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx); v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
+  const float gx = -(ux * s.rdx + uz * s.rdz) + s.dt * s.rdx * inj;
+  const float gz = -(wz * s.rdz + wx * s.rdx);
+  // ---- stores ----
+  if (PML) {
+    if (sx >= 0) {
+      s.pbx[wr][X_XX][qx_] = r1;
+      s.pbx[wr][X_XZ][qx_] = r2;
+    }
+    if (sz >= 0) {
+      s.pbz[wr][Z_ZZ][qz_] = r3;
+      s.pbz[wr][Z_XZ][qz_] = r4;
+    }
+  }
+  s.uxb[o] = u0x + bx * gx;
+  s.uzb[o] = u0z + bz * gz;
+  if (GRAD) {
+    s.acc[cc] = a0 + s.dt * (txx + tzz) * h0;
+    s.acc[s.cells + cc] = a1 + s.dt * e;
+  }
+  if (at_src) {
+    s.src_bar[n] = -s.w * sb0;
+    s.src_bar[s.nt + n] = -s.w * sb1;
+    s.src_bar[2 * s.nt + n] = -0.25f * s.w * sb2;
   }
 }
 
 template <bool GRAD, bool SRCADJ>
 __global__ __launch_bounds__(BX * BZ) void k_adj_vel(BATCH_PARAMS, int n, int k, int first) {
   BATCH_TILE();
-  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
+  // all 64 lanes of a wavefront share threadIdx.y: keep the row index scalar
+  const int j = j0 + threadIdx.x, i = i0 + __builtin_amdgcn_readfirstlane(threadIdx.y);
   const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
   const bool active = i < s.nz && j < s.nx;
   if (block_in_pml(s, j0, i0, 2)) {  // block-uniform: every thread reaches the barrier
@@ -481,43 +549,61 @@ __device__ __forceinline__ void adj_str_finish(const Shot2D& s, int i, int j, in
   const long ld = s.ld;
   const long o = (long)i * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
+  // ---- loads ----
+  const float ux = s.uxb[o], uz = s.uzb[o];
+  const float l2m = s.l2m[o], lam = s.lam[o], mxz = s.muxz[o];
+  const float t0xx = s.txxb[o], t0zz = s.tzzb[o], t0xz = s.txzb[o];
+  int sx = -1, sz = -1;
+  long qx_ = 0, qz_ = 0;
+  float r1 = 0.0f, r2 = 0.0f, r3 = 0.0f, r4 = 0.0f;
+  if (PML) {  // owned adjoint memory variables of the velocity-side derivatives
+    sx = strip_index(j, s.nx, s.P);
+    sz = strip_index(i, s.nz, s.P);
+    if (sx >= 0) {
+      qx_ = (long)i * 2 * s.P + sx;
+      r1 = bxh(s)[j] * (s.pbx[rd][X_VXX][qx_] + s.dt * ux);
+      r2 = bxi(s)[j] * (s.pbx[rd][X_VZX][qx_] + s.dt * uz);
+    }
+    if (sz >= 0) {
+      qz_ = (long)sz * s.nx + j;
+      r3 = bzi(s)[i] * (s.pbz[rd][Z_VXZ][qz_] + s.dt * ux);
+      r4 = bzh(s)[i] * (s.pbz[rd][Z_VZZ][qz_] + s.dt * uz);
+    }
+  }
+  long cc = 0;
+  float a2 = 0.0f, r = 0.0f;
+  if (GRAD) {
+    cc = (long)i * s.cp + j;
+    const gfloat* h3 = seg + 3 * s.cells;
+    const gfloat* h4 = seg + 4 * s.cells;
+    // vx nodes (i, b + 1/2), b in {j-1, j}: b_x averages rho(i, b), rho(i, b + 1); vz nodes
+    // (a + 1/2, j), a in {i-1, i}; clamped indices, weight 0 where rho(i, j) is not used
+    const int jm = max(j - 1, 0), im = max(i - 1, 0);
+    r = (float)pair_count(j - 1, j, s.nx) * s.uxb[(long)i * ld + jm] * h3[(long)i * s.cp + jm];
+    r += (float)pair_count(j, j, s.nx) * ux * h3[cc];
+    r += (float)pair_count(i - 1, i, s.nz) * s.uzb[(long)im * ld + j] * h4[(long)im * s.cp + j];
+    r += (float)pair_count(i, i, s.nz) * uz * h4[cc];
+    if (!first) a2 = s.acc[2 * s.cells + cc];
+  }
+  // ---- arithmetic ----
   // sigma_bar_xx += -D-x q_bar_xa ; sigma_bar_zz += -D-z q_bar_zb ;
   // sigma_bar_xz += -(D+z q_bar_xb + D+x q_bar_za)
   const float dsxx = -txx * s.rdx, dszz = -tzz * s.rdz, dsxz = -(t1 * s.rdz + t2 * s.rdx);
-  const float ux = s.uxb[o], uz = s.uzb[o];
-  if (PML) {  // owned adjoint memory variables of the velocity-side derivatives
-    const int sx = strip_index(j, s.nx, s.P);
-    const int sz = strip_index(i, s.nz, s.P);
+  // ---- stores ----
+  if (PML) {
     if (sx >= 0) {
-      const long q = (long)i * 2 * s.P + sx;
-      s.pbx[wr][X_VXX][q] = bxh(s)[j] * (s.pbx[rd][X_VXX][q] + s.dt * ux);
-      s.pbx[wr][X_VZX][q] = bxi(s)[j] * (s.pbx[rd][X_VZX][q] + s.dt * uz);
+      s.pbx[wr][X_VXX][qx_] = r1;
+      s.pbx[wr][X_VZX][qx_] = r2;
     }
     if (sz >= 0) {
-      const long q = (long)sz * s.nx + j;
-      s.pbz[wr][Z_VXZ][q] = bzi(s)[i] * (s.pbz[rd][Z_VXZ][q] + s.dt * ux);
-      s.pbz[wr][Z_VZZ][q] = bzh(s)[i] * (s.pbz[rd][Z_VZZ][q] + s.dt * uz);
+      s.pbz[wr][Z_VXZ][qz_] = r3;
+      s.pbz[wr][Z_VZZ][qz_] = r4;
     }
   }
-  const float l2m = s.l2m[o], lam = s.lam[o];
-  s.txxb[o] += l2m * dsxx + lam * dszz;
-  s.tzzb[o] += lam * dsxx + l2m * dszz;
-  s.txzb[o] += s.muxz[o] * dsxz;
-  if (GRAD) {
-    const long cc = (long)i * s.cp + j;
-    const gfloat* h3 = seg + 3 * s.cells;
-    const gfloat* h4 = seg + 4 * s.cells;
-    float r = 0.0f;
-    for (int b = j - 1; b <= j; ++b) {  // vx nodes (i, b + 1/2): b_x averages rho(i, b), rho(i, b + 1)
-      const int c = pair_count(b, j, s.nx);
-      if (c) r += (float)c * s.uxb[(long)i * ld + b] * h3[(long)i * s.cp + b];
-    }
-    for (int a = i - 1; a <= i; ++a) {  // vz nodes (a + 1/2, j)
-      const int c = pair_count(a, i, s.nz);
-      if (c) r += (float)c * s.uzb[(long)a * ld + j] * h4[(long)a * s.cp + j];
-    }
-    accumulate(s.acc, 2 * s.cells + cc, -s.dt * r, first);
-  }
+  s.txxb[o] = t0xx + (l2m * dsxx + lam * dszz);
+  s.tzzb[o] = t0zz + (lam * dsxx + l2m * dszz);
+  s.txzb[o] = t0xz + mxz * dsxz;
+  if (GRAD) s.acc[2 * s.cells + cc] = a2 - s.dt * r;
 }
 
 template <bool GRAD>

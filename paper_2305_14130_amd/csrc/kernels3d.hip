@@ -19,6 +19,11 @@
 //   g_b_x          += dt u_x q_x / b_x                     (and y, z)
 #include "efwi_internal.h"
 
+// Contract a * b + c into one fused multiply-add only inside a single expression, never
+// across statements: every template instance of a kernel then rounds the same source the
+// same way, so runs that differ only in what they store stay bitwise identical.
+#pragma clang fp contract(on)
+
 namespace efwi {
 namespace {
 
