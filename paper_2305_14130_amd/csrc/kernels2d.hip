@@ -111,20 +111,20 @@ __device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, gflo
   int sx = -1, sz = -1;
   long qx_ = 0, qz_ = 0;
   float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f, p4 = 0.0f;
-  if (PML) {
+  if (PML) {  // clamped strip indices: loads unconditional, stores predicated
     sx = strip_index(j, s.nx, s.P);
     sz = strip_index(i, s.nz, s.P);
+    qx_ = (long)i * 2 * s.P + max(sx, 0);
+    qz_ = (long)max(sz, 0) * s.nx + j;
+    p1 = bxh(s)[j] * s.psx[X_VXX][qx_] + axh(s)[j] * d1;
+    p3 = bxi(s)[j] * s.psx[X_VZX][qx_] + axi(s)[j] * d3;
+    p2 = bzi(s)[i] * s.psz[Z_VXZ][qz_] + azi(s)[i] * d2;
+    p4 = bzh(s)[i] * s.psz[Z_VZZ][qz_] + azh(s)[i] * d4;
     if (sx >= 0) {
-      qx_ = (long)i * 2 * s.P + sx;
-      p1 = bxh(s)[j] * s.psx[X_VXX][qx_] + axh(s)[j] * d1;
-      p3 = bxi(s)[j] * s.psx[X_VZX][qx_] + axi(s)[j] * d3;
       d1 += p1;
       d3 += p3;
     }
     if (sz >= 0) {
-      qz_ = (long)sz * s.nx + j;
-      p2 = bzi(s)[i] * s.psz[Z_VXZ][qz_] + azi(s)[i] * d2;
-      p4 = bzh(s)[i] * s.psz[Z_VZZ][qz_] + azh(s)[i] * d4;
       d2 += p2;
       d4 += p4;
     }
@@ -189,20 +189,20 @@ __device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int 
   int sx = -1, sz = -1;
   long qx_ = 0, qz_ = 0;
   float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f, p4 = 0.0f;
-  if (PML) {
+  if (PML) {  // clamped strip indices: loads unconditional, stores predicated
     sx = strip_index(j, s.nx, s.P);
     sz = strip_index(i, s.nz, s.P);
+    qx_ = (long)i * 2 * s.P + max(sx, 0);
+    qz_ = (long)max(sz, 0) * s.nx + j;
+    p1 = bxi(s)[j] * s.psx[X_XX][qx_] + axi(s)[j] * pxx;
+    p2 = bxh(s)[j] * s.psx[X_XZ][qx_] + axh(s)[j] * pxz;
+    p3 = bzi(s)[i] * s.psz[Z_ZZ][qz_] + azi(s)[i] * pzz;
+    p4 = bzh(s)[i] * s.psz[Z_XZ][qz_] + azh(s)[i] * pzx;
     if (sx >= 0) {
-      qx_ = (long)i * 2 * s.P + sx;
-      p1 = bxi(s)[j] * s.psx[X_XX][qx_] + axi(s)[j] * pxx;
-      p2 = bxh(s)[j] * s.psx[X_XZ][qx_] + axh(s)[j] * pxz;
       pxx += p1;
       pxz += p2;
     }
     if (sz >= 0) {
-      qz_ = (long)sz * s.nx + j;
-      p3 = bzi(s)[i] * s.psz[Z_ZZ][qz_] + azi(s)[i] * pzz;
-      p4 = bzh(s)[i] * s.psz[Z_XZ][qz_] + azh(s)[i] * pzx;
       pzz += p3;
       pzx += p4;
     }
@@ -380,30 +380,66 @@ struct StageArea {
   float* z1;  // [LZ][BX]
 };
 
-// Fill the four staged operands: fx0/fx1 at (i0 + r, j0 + c + lox0/lox1), fz0/fz1 at
-// (i0 + r + loz0/loz1, j0 + c). Nodes outside the grid hold zero.
-template <class F0, class F1, class F2, class F3>
-__device__ __forceinline__ void stage_operands(const Shot2D& s, int i0, int j0, StageArea a, int lox0, int lox1,
-                                               int loz0, int loz1, F0 fx0, F1 fx1, F2 fz0, F3 fz1) {
-  const int tid = threadIdx.y * BX + threadIdx.x;
-  for (int e = tid; e < LDS_OPS; e += BX * BZ) {
-    int q = e;
-    int which, r, c;
-    if (q < BZ * LX) { which = 0; r = q / LX; c = q % LX; }
-    else if ((q -= BZ * LX) < BZ * LX) { which = 1; r = q / LX; c = q % LX; }
-    else if ((q -= BZ * LX) < LZ * BX) { which = 2; r = q / BX; c = q % BX; }
-    else { q -= LZ * BX; which = 3; r = q / BX; c = q % BX; }
-    const int ii = i0 + r + (which == 2 ? loz0 : which == 3 ? loz1 : 0);
-    const int jj = j0 + c + (which == 0 ? lox0 : which == 1 ? lox1 : 0);
-    float v = 0.0f;
-    if (ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-      if (which == 0) v = fx0(ii, jj);
-      else if (which == 1) v = fx1(ii, jj);
-      else if (which == 2) v = fz0(ii, jj);
-      else v = fz1(ii, jj);
-    }
-    (which == 0 ? a.x0 : which == 1 ? a.x1 : which == 2 ? a.z0 : a.z1)[which < 2 ? r * LX + c : r * BX + c] = v;
+// One staged operand: dt * f at the nodes of its patch, plus, inside the CPML strips of its
+// axis, a * (psi + dt * f) with the profile coefficient a of the node's coordinate and the
+// adjoint memory variable psi. x-operands cover (i0 + r, j0 + c + lo), r < BZ, c < LX;
+// z-operands (i0 + r + lo, j0 + c), r < LZ, c < BX. Nodes outside the grid hold zero.
+struct StagedOp {
+  const gfloat* f;
+  const gfloat* a;
+  const gfloat* psi;
+  int lo;
+};
+
+// Every thread takes at most two nodes of each operand: all loads are issued before the
+// first LDS write, so a tile costs one memory round trip.
+template <bool XAXIS>
+__device__ __forceinline__ void stage_load(const Shot2D& s, int i0, int j0, const StagedOp& op, int tid, float* v) {
+  constexpr int N = XAXIS ? BZ * LX : LZ * BX;
+  constexpr int W = XAXIS ? LX : BX;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = tid + k * BX * BZ;
+    const int r = e / W, c = e % W;
+    const int ii = i0 + r + (XAXIS ? 0 : op.lo), jj = j0 + c + (XAXIS ? op.lo : 0);
+    // clamped indices keep every load valid and unconditional (no waits inside branches)
+    const bool in = e < N && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx;
+    const int ic = min(max(ii, 0), s.nz - 1), jc = min(max(jj, 0), s.nx - 1);
+    const int sidx = XAXIS ? strip_index(jc, s.nx, s.P) : strip_index(ic, s.nz, s.P);
+    const int sc = max(sidx, 0);
+    const float f = op.f[(long)ic * s.ld + jc];
+    const float ps = XAXIS ? op.psi[(long)ic * 2 * s.P + sc] : op.psi[(long)sc * s.nx + jc];
+    const float ac = op.a[XAXIS ? jc : ic];
+    // 0/1 masks instead of branches keep the loads unconditional (the compiler would sink
+    // loads used on one side of a select into a branch and wait there)
+    const float m_in = in ? 1.0f : 0.0f, m_strip = sidx >= 0 ? 1.0f : 0.0f;
+    const float val = s.dt * f;
+    v[k] = m_in * (val + (m_strip * ac) * (ps + val));
   }
+}
+template <bool XAXIS>
+__device__ __forceinline__ void stage_store(float* dst, int tid, const float* v) {
+  constexpr int N = XAXIS ? BZ * LX : LZ * BX;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = tid + k * BX * BZ;
+    if (e < N) dst[e] = v[k];
+  }
+}
+// Stage the two x-operands and the two z-operands of a CPML tile.
+__device__ __forceinline__ void stage_operands(const Shot2D& s, int i0, int j0, StageArea a, const StagedOp& x0,
+                                               const StagedOp& x1, const StagedOp& z0, const StagedOp& z1) {
+  static_assert(BZ * LX <= 2 * BX * BZ && LZ * BX <= 2 * BX * BZ, "two nodes per thread and operand");
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  float v0[2], v1[2], v2[2], v3[2];
+  stage_load<true>(s, i0, j0, x0, tid, v0);
+  stage_load<true>(s, i0, j0, x1, tid, v1);
+  stage_load<false>(s, i0, j0, z0, tid, v2);
+  stage_load<false>(s, i0, j0, z1, tid, v3);
+  stage_store<true>(a.x0, tid, v0);
+  stage_store<true>(a.x1, tid, v1);
+  stage_store<false>(a.z0, tid, v2);
+  stage_store<false>(a.z1, tid, v3);
 }
 
 // Transposed stress sub-step (first at reverse step n): t_bar -> u_bar.
@@ -425,16 +461,12 @@ __device__ __forceinline__ void adj_vel_finish(const Shot2D& s, int i, int j, in
   if (PML) {  // owned adjoint memory variables of the stress-side derivatives
     sx = strip_index(j, s.nx, s.P);
     sz = strip_index(i, s.nz, s.P);
-    if (sx >= 0) {
-      qx_ = (long)i * 2 * s.P + sx;
-      r1 = bxi(s)[j] * (s.pbx[rd][X_XX][qx_] + s.dt * txx);
-      r2 = bxh(s)[j] * (s.pbx[rd][X_XZ][qx_] + s.dt * txz);
-    }
-    if (sz >= 0) {
-      qz_ = (long)sz * s.nx + j;
-      r3 = bzi(s)[i] * (s.pbz[rd][Z_ZZ][qz_] + s.dt * tzz);
-      r4 = bzh(s)[i] * (s.pbz[rd][Z_XZ][qz_] + s.dt * txz);
-    }
+    qx_ = (long)i * 2 * s.P + max(sx, 0);
+    qz_ = (long)max(sz, 0) * s.nx + j;
+    r1 = bxi(s)[j] * (s.pbx[rd][X_XX][qx_] + s.dt * txx);
+    r2 = bxh(s)[j] * (s.pbx[rd][X_XZ][qx_] + s.dt * txz);
+    r3 = bzi(s)[i] * (s.pbz[rd][Z_ZZ][qz_] + s.dt * tzz);
+    r4 = bzh(s)[i] * (s.pbz[rd][Z_XZ][qz_] + s.dt * txz);
   }
   long cc = 0;
   float a0 = 0.0f, a1 = 0.0f, e = 0.0f, h0 = 0.0f;
@@ -512,12 +544,12 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_vel(BATCH_PARAMS, int n, int k,
   if (block_in_pml(s, j0, i0, 2)) {  // block-uniform: every thread reaches the barrier
     __shared__ float lds[LDS_OPS];
     const StageArea a{lds, lds + BZ * LX, lds + 2 * BZ * LX, lds + 2 * BZ * LX + LZ * BX};
-    const AdjCtx<true> c{s, (n + 1) & 1};
+    const int rd = (n + 1) & 1;
     // x0: p_bar_xx at columns j-1 .. j+2; x1: p_bar_xz at j-2 .. j+1;
     // z0: p_bar_zx at rows i-2 .. i+1;     z1: p_bar_zz at i-1 .. i+2
-    stage_operands(s, i0, j0, a, -1, -2, -2, -1, [&](int ii, int jj) { return pb_xx(c, ii, jj); },
-                   [&](int ii, int jj) { return pb_xz(c, ii, jj); }, [&](int ii, int jj) { return pb_zx(c, ii, jj); },
-                   [&](int ii, int jj) { return pb_zz(c, ii, jj); });
+    stage_operands(s, i0, j0, a, StagedOp{s.txxb, axi(s), s.pbx[rd][X_XX], -1},
+                   StagedOp{s.txzb, axh(s), s.pbx[rd][X_XZ], -2}, StagedOp{s.txzb, azh(s), s.pbz[rd][Z_XZ], -2},
+                   StagedOp{s.tzzb, azi(s), s.pbz[rd][Z_ZZ], -1});
     __syncthreads();
     if (!active) return;
     const int r = threadIdx.y, q = threadIdx.x;
@@ -559,16 +591,12 @@ __device__ __forceinline__ void adj_str_finish(const Shot2D& s, int i, int j, in
   if (PML) {  // owned adjoint memory variables of the velocity-side derivatives
     sx = strip_index(j, s.nx, s.P);
     sz = strip_index(i, s.nz, s.P);
-    if (sx >= 0) {
-      qx_ = (long)i * 2 * s.P + sx;
-      r1 = bxh(s)[j] * (s.pbx[rd][X_VXX][qx_] + s.dt * ux);
-      r2 = bxi(s)[j] * (s.pbx[rd][X_VZX][qx_] + s.dt * uz);
-    }
-    if (sz >= 0) {
-      qz_ = (long)sz * s.nx + j;
-      r3 = bzi(s)[i] * (s.pbz[rd][Z_VXZ][qz_] + s.dt * ux);
-      r4 = bzh(s)[i] * (s.pbz[rd][Z_VZZ][qz_] + s.dt * uz);
-    }
+    qx_ = (long)i * 2 * s.P + max(sx, 0);
+    qz_ = (long)max(sz, 0) * s.nx + j;
+    r1 = bxh(s)[j] * (s.pbx[rd][X_VXX][qx_] + s.dt * ux);
+    r2 = bxi(s)[j] * (s.pbx[rd][X_VZX][qx_] + s.dt * uz);
+    r3 = bzi(s)[i] * (s.pbz[rd][Z_VXZ][qz_] + s.dt * ux);
+    r4 = bzh(s)[i] * (s.pbz[rd][Z_VZZ][qz_] + s.dt * uz);
   }
   long cc = 0;
   float a2 = 0.0f, r = 0.0f;
@@ -615,12 +643,12 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_str(BATCH_PARAMS, int n, int k,
   if (block_in_pml(s, j0, i0, 2)) {  // block-uniform: every thread reaches the barrier
     __shared__ float lds[LDS_OPS];
     const StageArea a{lds, lds + BZ * LX, lds + 2 * BZ * LX, lds + 2 * BZ * LX + LZ * BX};
-    const AdjCtx<true> c{s, (n + 1) & 1};
+    const int rd = (n + 1) & 1;
     // x0: q_bar_xa at columns j-2 .. j+1; x1: q_bar_za at j-1 .. j+2;
     // z0: q_bar_zb at rows i-2 .. i+1;     z1: q_bar_xb at i-1 .. i+2
-    stage_operands(s, i0, j0, a, -2, -1, -2, -1, [&](int ii, int jj) { return qb_xa(c, ii, jj); },
-                   [&](int ii, int jj) { return qb_za(c, ii, jj); }, [&](int ii, int jj) { return qb_zb(c, ii, jj); },
-                   [&](int ii, int jj) { return qb_xb(c, ii, jj); });
+    stage_operands(s, i0, j0, a, StagedOp{s.uxb, axh(s), s.pbx[rd][X_VXX], -2},
+                   StagedOp{s.uzb, axi(s), s.pbx[rd][X_VZX], -1}, StagedOp{s.uzb, azh(s), s.pbz[rd][Z_VZZ], -2},
+                   StagedOp{s.uxb, azi(s), s.pbz[rd][Z_VXZ], -1});
     __syncthreads();
     if (!active) return;
     const int r = threadIdx.y, q = threadIdx.x;
