@@ -496,10 +496,10 @@ efwi_status check_ws(const void* ws, size_t have, size_t need) {
 // header (descriptors, tile list, per-shot tables: uploaded once) followed by each shot's
 // private region.
 // ----------------------------------------------------------------------------------------
-// Schedule entries needed for `tiles` tiles: a run holds at most its weight in tiles
-// (weights >= 1) and its weight is below wtot / NUM_XCD + PML_TILE_WEIGHT.
+// Schedule entries needed for `tiles` tiles: a run's weight is below wtot / NUM_XCD plus one
+// tile's weight, so it holds at most tiles * SCHED_RATIO / NUM_XCD + SCHED_RATIO + 1 tiles.
 size_t sched_capacity(size_t tiles) {
-  return (size_t)NUM_XCD * (tiles * PML_TILE_WEIGHT / NUM_XCD + PML_TILE_WEIGHT + 1);
+  return (size_t)NUM_XCD * (tiles * SCHED_RATIO / NUM_XCD + SCHED_RATIO + 2);
 }
 
 size_t header_bytes(const std::vector<Plan2D>& plans, int first, int count) {
@@ -516,6 +516,27 @@ size_t wave_bytes(const std::vector<Plan2D>& plans, int first, int count) {
   size_t t = header_bytes(plans, first, count);
   for (int k = first; k < first + count; ++k) t += plans[k].total;
   return t;
+}
+
+// Cut `weight` into NUM_XCD contiguous runs of equal total and write the schedule.
+efwi_status build_sched(const std::vector<int>& weight, int* sched, int& nsched) {
+  const int ntiles = (int)weight.size();
+  long wtot = 0;
+  for (int x : weight) wtot += x;
+  std::vector<int> cut(NUM_XCD + 1, ntiles);
+  cut[0] = 0;
+  long acc = 0;
+  for (int q = 0, k = 1; q < ntiles && k < NUM_XCD; ++q) {
+    acc += weight[q];
+    while (k < NUM_XCD && acc * NUM_XCD >= wtot * k) cut[k++] = q + 1;
+  }
+  int maxrun = 0;
+  for (int k = 0; k < NUM_XCD; ++k) maxrun = std::max(maxrun, cut[k + 1] - cut[k]);
+  if ((size_t)maxrun * NUM_XCD > sched_capacity(ntiles)) return fail(EFWI_E_INVAL, "tile schedule overflow");
+  for (int m = 0; m < maxrun; ++m)
+    for (int k = 0; k < NUM_XCD; ++k) sched[m * NUM_XCD + k] = (cut[k] + m < cut[k + 1]) ? cut[k] + m : -1;
+  nsched = maxrun * NUM_XCD;
+  return EFWI_OK;
 }
 
 struct Wave {
@@ -563,44 +584,33 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     region += p.total;
   }
   std::memcpy(blob.data() + off_desc, wv.descs.data(), (size_t)count * sizeof(Shot2D));
-  // XCD schedules: cut the tile list into NUM_XCD contiguous runs of equal (weighted) cost
-  std::vector<int> weight(ntiles);
+  // XCD schedules: cut the tile list into NUM_XCD contiguous runs of equal weighted cost,
+  // for the forward kernels (tiles with a CPML node) and the adjoint kernels (tiles within
+  // two nodes of a strip, which stage corrected operands)
+  std::vector<int> wfwd(ntiles), wadj(ntiles);
   for (int k = 0, q = 0; k < count; ++k) {
     const Plan2D& p = wv.plans[k];
     const int ntx = (p.nx + BX - 1) / BX;
     for (int l = 0; l < p.ntiles; ++l, ++q) {
-      const int i0 = (l / ntx) * BZ, j0 = (l % ntx) * BX, pad = 2;
-      const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
-                                   (i0 + BZ - 1 + pad >= p.nz - p.P));
-      weight[q] = pml ? PML_TILE_WEIGHT : 1;
+      const int i0 = (l / ntx) * BZ, j0 = (l % ntx) * BX;
+      auto near = [&](int pad) {
+        return p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
+                           (i0 + BZ - 1 + pad >= p.nz - p.P));
+      };
+      wfwd[q] = near(0) ? FWD_W_PML : FWD_W_INT;
+      wadj[q] = near(2) ? ADJ_W_PML : ADJ_W_INT;
     }
   }
   int nsched[2];
-  for (int variant = 0; variant < 2; ++variant) {
-    std::vector<int> wq(ntiles, 1);
-    if (variant == 1) wq = weight;
-    long wtot = 0;
-    for (int x : wq) wtot += x;
-    std::vector<int> cut(NUM_XCD + 1, ntiles);
-    cut[0] = 0;
-    long acc = 0;
-    for (int q = 0, k = 1; q < ntiles && k < NUM_XCD; ++q) {
-      acc += wq[q];
-      while (k < NUM_XCD && acc * NUM_XCD >= wtot * k) cut[k++] = q + 1;
-    }
-    int maxrun = 0;
-    for (int k = 0; k < NUM_XCD; ++k) maxrun = std::max(maxrun, cut[k + 1] - cut[k]);
-    if ((size_t)maxrun * NUM_XCD > sched_capacity(ntiles)) return fail(EFWI_E_INVAL, "tile schedule overflow");
-    int* sched = reinterpret_cast<int*>(blob.data() + (variant == 0 ? off_sched : off_sched2));
-    for (int m = 0; m < maxrun; ++m)
-      for (int k = 0; k < NUM_XCD; ++k) sched[m * NUM_XCD + k] = (cut[k] + m < cut[k + 1]) ? cut[k] + m : -1;
-    nsched[variant] = maxrun * NUM_XCD;
-  }
+  efwi_status rc = build_sched(wfwd, reinterpret_cast<int*>(blob.data() + off_sched), nsched[0]);
+  if (rc != EFWI_OK) return rc;
+  rc = build_sched(wadj, reinterpret_cast<int*>(blob.data() + off_sched2), nsched[1]);
+  if (rc != EFWI_OK) return rc;
   wv.batch.shots = reinterpret_cast<const Shot2D*>(ws + off_desc);
   wv.batch.tile_first = reinterpret_cast<const int*>(ws + off_first);
   wv.batch.tile_shot = reinterpret_cast<const int*>(ws + off_tshot);
-  wv.batch.even = Sched{reinterpret_cast<const int*>(ws + off_sched), nsched[0]};
-  wv.batch.weighted = Sched{reinterpret_cast<const int*>(ws + off_sched2), nsched[1]};
+  wv.batch.fwd = Sched{reinterpret_cast<const int*>(ws + off_sched), nsched[0]};
+  wv.batch.adj = Sched{reinterpret_cast<const int*>(ws + off_sched2), nsched[1]};
   wv.batch.ns = count;
   wv.batch.ntiles = ntiles;
   // zero what must start at zero
@@ -945,27 +955,6 @@ struct Wave3 {
   int L = 1, nseg = 1, nt = 0;
 };
 
-// Cut `weight` into NUM_XCD contiguous runs of equal total and write the schedule.
-efwi_status build_sched(const std::vector<int>& weight, int* sched, int& nsched) {
-  const int ntiles = (int)weight.size();
-  long wtot = 0;
-  for (int x : weight) wtot += x;
-  std::vector<int> cut(NUM_XCD + 1, ntiles);
-  cut[0] = 0;
-  long acc = 0;
-  for (int q = 0, k = 1; q < ntiles && k < NUM_XCD; ++q) {
-    acc += weight[q];
-    while (k < NUM_XCD && acc * NUM_XCD >= wtot * k) cut[k++] = q + 1;
-  }
-  int maxrun = 0;
-  for (int k = 0; k < NUM_XCD; ++k) maxrun = std::max(maxrun, cut[k + 1] - cut[k]);
-  if ((size_t)maxrun * NUM_XCD > sched_capacity(ntiles)) return fail(EFWI_E_INVAL, "tile schedule overflow");
-  for (int m = 0; m < maxrun; ++m)
-    for (int k = 0; k < NUM_XCD; ++k) sched[m * NUM_XCD + k] = (cut[k] + m < cut[k + 1]) ? cut[k] + m : -1;
-  nsched = maxrun * NUM_XCD;
-  return EFWI_OK;
-}
-
 efwi_status setup_wave3(const efwi_grid& g, const efwi_shot* shots, const std::vector<Plan3D>& plans, int first,
                         int count, const std::vector<ShotIO>& io, efwi_ws_kind kind, unsigned char* ws, Wave3& wv,
                         hipStream_t st) {
@@ -999,7 +988,7 @@ efwi_status setup_wave3(const efwi_grid& g, const efwi_shot* shots, const std::v
       const int i = q / (ntx * nty), rem = q % (ntx * nty), k0 = (rem / ntx) * 4, j0 = (rem % ntx) * 64, pad = 2;
       const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + 63 + pad >= p.nx - p.P) || (k0 - pad < p.P) ||
                                    (k0 + 3 + pad >= p.ny - p.P) || (i - pad < p.P) || (i + pad >= p.nz - p.P));
-      weight.push_back(pml ? PML_TILE_WEIGHT : 1);
+      weight.push_back(pml ? ADJ3_W_PML : ADJ3_W_INT);
     }
     build_tables3(g, s, p, blob.data() + off_tab);
     wv.descs.push_back(make_desc3(g, s, p, ws + region, reinterpret_cast<const float*>(ws + off_tab),
@@ -1017,8 +1006,8 @@ efwi_status setup_wave3(const efwi_grid& g, const efwi_shot* shots, const std::v
   wv.batch.shots = reinterpret_cast<const Shot3D*>(ws);
   wv.batch.tile_first = reinterpret_cast<const int*>(ws + off_first);
   wv.batch.tile_shot = reinterpret_cast<const int*>(ws + off_tshot);
-  wv.batch.even = Sched{reinterpret_cast<const int*>(ws + off_sched), nsched[0]};
-  wv.batch.weighted = Sched{reinterpret_cast<const int*>(ws + off_sched2), nsched[1]};
+  wv.batch.fwd = Sched{reinterpret_cast<const int*>(ws + off_sched), nsched[0]};
+  wv.batch.adj = Sched{reinterpret_cast<const int*>(ws + off_sched2), nsched[1]};
   wv.batch.ns = count;
   wv.batch.ntiles = ntiles;
   const bool fwd = kind != EFWI_WS_ADJOINT;

@@ -88,9 +88,9 @@ struct Shot2D {
 
 // A batch of shots advanced together: device descriptors and the flat tile list (tiles of
 // shot s are tile_first[s] .. tile_first[s] + tiles(s) - 1; tile_shot maps tile -> shot),
-// and two launch schedules: workgroup w processes tile sched[w] (-1: none). `even` splits
-// the tiles evenly over the XCDs (forward and pointwise kernels); `weighted` balances the
-// adjoint kernels, whose CPML tiles cost several interior tiles.
+// and two launch schedules: workgroup w processes tile sched[w] (-1: none). Both cut the
+// tile list into one contiguous run per XCD of equal weighted cost, with the weights of
+// the forward (and pointwise) kernels in `fwd` and those of the adjoint kernels in `adj`.
 struct Sched {
   const int* sched;
   int n;
@@ -99,15 +99,24 @@ struct Batch2D {
   const Shot2D* shots;
   const int* tile_shot;
   const int* tile_first;
-  Sched even, weighted;
+  Sched fwd, adj;
   int ns, ntiles;
 };
 
 // Number of XCDs the hardware deals workgroups to, round robin.
 constexpr int NUM_XCD = 8;
-// Relative cost of a tile that touches a CPML strip in the adjoint kernels (measured on
-// MI355X: ~3x an interior tile; ~1.3x in the forward kernels, which use the even split).
-constexpr int PML_TILE_WEIGHT = 3;
+// Relative cost of an interior tile and of a tile that touches a CPML strip, as integer
+// weights (measured on MI355X with the 2D kernels: CPML tiles cost ~1.5x in the forward
+// kernels and ~2x in the adjoint kernels, which also update the adjoint memory variables
+// and stage corrected operands). The 3D adjoint CPML weight is 3.
+constexpr int FWD_W_INT = 2, FWD_W_PML = 3;
+constexpr int ADJ_W_INT = 1, ADJ_W_PML = 2;
+constexpr int ADJ3_W_INT = 1, ADJ3_W_PML = 3;
+// Bound on W_PML / W_INT over all schedules (sizes the schedule arrays).
+constexpr int SCHED_RATIO = 3;
+static_assert(FWD_W_PML <= SCHED_RATIO * FWD_W_INT && ADJ_W_PML <= SCHED_RATIO * ADJ_W_INT &&
+                  ADJ3_W_PML <= SCHED_RATIO * ADJ3_W_INT,
+              "schedule capacity assumes W_PML <= SCHED_RATIO * W_INT");
 
 // Strip index helpers (x: column j of width nx; z: row i of height nz).
 __host__ __device__ inline int strip_index(int k, int n, int P) {
@@ -204,7 +213,7 @@ struct Batch3D {
   const Shot3D* shots;
   const int* tile_shot;
   const int* tile_first;
-  Sched even, weighted;
+  Sched fwd, adj;
   int ns, ntiles;
 };
 

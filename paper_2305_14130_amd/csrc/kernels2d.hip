@@ -765,53 +765,53 @@ __global__ void k_reduce_phi(const double* partial, int n, double* phi) {
 
 inline dim3 grid_of(const Sched& q) { return dim3(q.n); }
 inline dim3 block2d() { return dim3(BX, BZ); }
-#define EVEN_ARGS b.shots, b.tile_shot, b.tile_first, b.even.sched
-#define WEIGHTED_ARGS b.shots, b.tile_shot, b.tile_first, b.weighted.sched
+#define FWD_ARGS b.shots, b.tile_shot, b.tile_first, b.fwd.sched
+#define ADJ_ARGS b.shots, b.tile_shot, b.tile_first, b.adj.sched
 
 }  // namespace
 
 hipError_t launch_stage2d(const Batch2D& b, hipStream_t st) {
-  k_stage<<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS);
+  k_stage<<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS);
   return hipGetLastError();
 }
 
 hipError_t launch_fwd_vel(const Batch2D& b, int kstore, hipStream_t st) {
-  if (kstore >= 0) k_fwd_vel<true><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, kstore);
-  else k_fwd_vel<false><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, 0);
+  if (kstore >= 0) k_fwd_vel<true><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, kstore);
+  else k_fwd_vel<false><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_fwd_str(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
   if (kstore >= 0) {
-    if (record) k_fwd_str<true, true><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, n, kstore);
-    else k_fwd_str<true, false><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, n, kstore);
+    if (record) k_fwd_str<true, true><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, n, kstore);
+    else k_fwd_str<true, false><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, n, kstore);
   } else {
-    if (record) k_fwd_str<false, true><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, n, 0);
-    else k_fwd_str<false, false><<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS, n, 0);
+    if (record) k_fwd_str<false, true><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, n, 0);
+    else k_fwd_str<false, false><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, n, 0);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_adj_vel(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
-  if (grad) k_adj_vel<true, false><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, k, first);
-  else if (srcadj) k_adj_vel<false, true><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, 0, 0);
-  else k_adj_vel<false, false><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, 0, 0);
+  if (grad) k_adj_vel<true, false><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, k, first);
+  else if (srcadj) k_adj_vel<false, true><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, 0, 0);
+  else k_adj_vel<false, false><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_str(const Batch2D& b, int n, int k, bool grad, bool first, hipStream_t st) {
-  if (grad) k_adj_str<true><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, k, first);
-  else k_adj_str<false><<<grid_of(b.weighted), block2d(), 0, st>>>(WEIGHTED_ARGS, n, 0, 0);
+  if (grad) k_adj_str<true><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, k, first);
+  else k_adj_str<false><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_chain_flush(const Batch2D& b, hipStream_t st) {
-  k_chain_flush<<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS);
+  k_chain_flush<<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS);
   return hipGetLastError();
 }
 
 hipError_t launch_write_gradient(const Batch2D& b, hipStream_t st) {
-  k_write_gradient<<<grid_of(b.even), block2d(), 0, st>>>(EVEN_ARGS);
+  k_write_gradient<<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS);
   return hipGetLastError();
 }
 

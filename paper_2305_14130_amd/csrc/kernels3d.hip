@@ -567,53 +567,53 @@ __global__ __launch_bounds__(TX * TY) void k3_write_gradient(PARAMS3) {
 
 inline dim3 grid3(const Sched& q) { return dim3(q.n); }
 inline dim3 block3() { return dim3(TX, TY); }
-#define EVEN3 b.shots, b.tile_shot, b.tile_first, b.even.sched
-#define WEIGHTED3 b.shots, b.tile_shot, b.tile_first, b.weighted.sched
+#define FWD3 b.shots, b.tile_shot, b.tile_first, b.fwd.sched
+#define ADJ3 b.shots, b.tile_shot, b.tile_first, b.adj.sched
 
 }  // namespace
 
 hipError_t launch3_stage(const Batch3D& b, hipStream_t st) {
-  k3_stage<<<grid3(b.even), block3(), 0, st>>>(EVEN3);
+  k3_stage<<<grid3(b.fwd), block3(), 0, st>>>(FWD3);
   return hipGetLastError();
 }
 
 hipError_t launch3_fwd_vel(const Batch3D& b, int kstore, hipStream_t st) {
-  if (kstore >= 0) k3_fwd_vel<true><<<grid3(b.even), block3(), 0, st>>>(EVEN3, kstore);
-  else k3_fwd_vel<false><<<grid3(b.even), block3(), 0, st>>>(EVEN3, 0);
+  if (kstore >= 0) k3_fwd_vel<true><<<grid3(b.fwd), block3(), 0, st>>>(FWD3, kstore);
+  else k3_fwd_vel<false><<<grid3(b.fwd), block3(), 0, st>>>(FWD3, 0);
   return hipGetLastError();
 }
 
 hipError_t launch3_fwd_str(const Batch3D& b, int n, int kstore, bool record, hipStream_t st) {
   if (kstore >= 0) {
-    if (record) k3_fwd_str<true, true><<<grid3(b.even), block3(), 0, st>>>(EVEN3, n, kstore);
-    else k3_fwd_str<true, false><<<grid3(b.even), block3(), 0, st>>>(EVEN3, n, kstore);
+    if (record) k3_fwd_str<true, true><<<grid3(b.fwd), block3(), 0, st>>>(FWD3, n, kstore);
+    else k3_fwd_str<true, false><<<grid3(b.fwd), block3(), 0, st>>>(FWD3, n, kstore);
   } else {
-    if (record) k3_fwd_str<false, true><<<grid3(b.even), block3(), 0, st>>>(EVEN3, n, 0);
-    else k3_fwd_str<false, false><<<grid3(b.even), block3(), 0, st>>>(EVEN3, n, 0);
+    if (record) k3_fwd_str<false, true><<<grid3(b.fwd), block3(), 0, st>>>(FWD3, n, 0);
+    else k3_fwd_str<false, false><<<grid3(b.fwd), block3(), 0, st>>>(FWD3, n, 0);
   }
   return hipGetLastError();
 }
 
 hipError_t launch3_adj_vel(const Batch3D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
-  if (grad) k3_adj_vel<true, false><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, k, first);
-  else if (srcadj) k3_adj_vel<false, true><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, 0, 0);
-  else k3_adj_vel<false, false><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, 0, 0);
+  if (grad) k3_adj_vel<true, false><<<grid3(b.adj), block3(), 0, st>>>(ADJ3, n, k, first);
+  else if (srcadj) k3_adj_vel<false, true><<<grid3(b.adj), block3(), 0, st>>>(ADJ3, n, 0, 0);
+  else k3_adj_vel<false, false><<<grid3(b.adj), block3(), 0, st>>>(ADJ3, n, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch3_adj_str(const Batch3D& b, int n, int k, bool grad, bool first, hipStream_t st) {
-  if (grad) k3_adj_str<true><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, k, first);
-  else k3_adj_str<false><<<grid3(b.weighted), block3(), 0, st>>>(WEIGHTED3, n, 0, 0);
+  if (grad) k3_adj_str<true><<<grid3(b.adj), block3(), 0, st>>>(ADJ3, n, k, first);
+  else k3_adj_str<false><<<grid3(b.adj), block3(), 0, st>>>(ADJ3, n, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch3_chain_flush(const Batch3D& b, hipStream_t st) {
-  k3_chain_flush<<<grid3(b.even), block3(), 0, st>>>(EVEN3);
+  k3_chain_flush<<<grid3(b.fwd), block3(), 0, st>>>(FWD3);
   return hipGetLastError();
 }
 
 hipError_t launch3_write_gradient(const Batch3D& b, hipStream_t st) {
-  k3_write_gradient<<<grid3(b.even), block3(), 0, st>>>(EVEN3);
+  k3_write_gradient<<<grid3(b.fwd), block3(), 0, st>>>(FWD3);
   return hipGetLastError();
 }
 
