@@ -335,7 +335,7 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
     }
   }
   p.adj_bytes = align_up(((size_t)5 * p.plane + 2 * strips) * sizeof(float));
-  p.par_bytes = align_up((size_t)5 * p.plane * sizeof(float));
+  p.par_bytes = align_up((size_t)3 * p.plane * sizeof(float));
   p.tab_bytes = align_up((size_t)(4 * p.nx + 4 * p.nz) * sizeof(float) + (size_t)p.nz * sizeof(int) +
                          (size_t)p.nslots * p.nx * sizeof(int));
   const bool fwd = kind != EFWI_WS_ADJOINT;
@@ -457,7 +457,7 @@ Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsign
   strips_at(st, d.pbx[0], d.pbz[0]);
   strips_at(st + strips, d.pbx[1], d.pbz[1]);
   fields(p.off_par, f);
-  d.l2m = f[0], d.lam = f[1], d.muxz = f[2], d.bx = f[3], d.bz = f[4];
+  d.lam = f[0], d.mu = f[1], d.rho = f[2];
   d.prof = (const gfloat*)(tab);
   d.row_slot = (const gint*)(tab + 4 * p.nx + 4 * p.nz);
   d.rowch = d.row_slot + p.nz;

@@ -60,8 +60,8 @@ struct Shot2D {
   gfloat *uxb, *uzb, *txxb, *tzzb, *txzb;
   gfloat* pbx[2][4];             // double-buffered x-strip adjoint memory variables
   gfloat* pbz[2][4];             // double-buffered z-strip adjoint memory variables
-  // staged parameters (padded, zero halo)
-  gfloat *l2m, *lam, *muxz, *bx, *bz;
+  // staged parameters at the normal nodes (padded; the halo repeats the last row and column)
+  gfloat *lam, *mu, *rho;
   // CPML profiles: axi bxi axh bxh [nx] then azi bzi azh bzh [nz]
   const gfloat* prof;
   // source

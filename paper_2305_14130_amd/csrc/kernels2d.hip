@@ -45,6 +45,21 @@ __device__ __forceinline__ const gfloat* bzi(const Shot2D& s) { return s.prof + 
 __device__ __forceinline__ const gfloat* azh(const Shot2D& s) { return s.prof + 4 * s.nx + 2 * s.nz; }
 __device__ __forceinline__ const gfloat* bzh(const Shot2D& s) { return s.prof + 4 * s.nx + 3 * s.nz; }
 
+// Staged parameters at their own nodes, derived from lambda, mu and rho at the normal
+// nodes (k_stage repeats the last row and column into the halo, so the averages clamp at
+// the far edges): lambda + 2 mu; mu_xz, the harmonic mean of the four surrounding mu (0 if
+// any is 0, since the reciprocal of 0 is infinite); b_x, b_z, the inverse of the arithmetic
+// mean density of the two surrounding normal nodes. v_rcp_f32 (1 ulp); the forward and the
+// transposed kernels evaluate the same expressions, so the transpose stays exact.
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float l2m_of(const Shot2D& s, long o) { return s.lam[o] + 2.0f * s.mu[o]; }
+__device__ __forceinline__ float bx_of(const Shot2D& s, long o) { return 2.0f * rcpf(s.rho[o] + s.rho[o + 1]); }
+__device__ __forceinline__ float bz_of(const Shot2D& s, long o) { return 2.0f * rcpf(s.rho[o] + s.rho[o + s.ld]); }
+__device__ __forceinline__ float muxz_of(const Shot2D& s, long o) {
+  const long ld = s.ld;
+  return 4.0f * rcpf(rcpf(s.mu[o]) + rcpf(s.mu[o + 1]) + rcpf(s.mu[o + ld]) + rcpf(s.mu[o + ld + 1]));
+}
+
 // Forward D+ at the half node after index k, and D- at integer node k (array index k holds
 // the half node k+1/2); `st` is the element stride along the axis.
 template <class P>
@@ -107,7 +122,7 @@ __device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, gflo
   float d2 = dminus(s.sxz, o, ld, s.rdz);  // D-z sxz at (i, j+1/2)
   float d3 = dminus(s.sxz, o, 1, s.rdx);   // D-x sxz at (i+1/2, j)
   float d4 = dplus(s.szz, o, ld, s.rdz);   // D+z szz at (i+1/2, j)
-  const float vx = s.vx[o], vz = s.vz[o], bx = s.bx[o], bz = s.bz[o];
+  const float vx = s.vx[o], vz = s.vz[o], bx = bx_of(s, o), bz = bz_of(s, o);
   int sx = -1, sz = -1;
   long qx_ = 0, qz_ = 0;
   float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f, p4 = 0.0f;
@@ -172,7 +187,7 @@ __device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int 
   float pzx = dplus(s.vx, o, ld, s.rdz);   // D+z vx at (i+1/2, j+1/2)
   float pxz = dplus(s.vz, o, 1, s.rdx);    // D+x vz at (i+1/2, j+1/2)
   const float raw_pxx = pxx;
-  const float l2m = s.l2m[o], lam = s.lam[o], mxz = s.muxz[o];
+  const float lam = s.lam[o], l2m = l2m_of(s, o), mxz = muxz_of(s, o);
   float sxx = s.sxx[o], szz = s.szz[o], sxz = s.sxz[o];
   // source components at t_{n+1/2} (uniform scalar loads)
   const float f_xx = s.src[n], f_zz = s.src[s.nt + n], f_xz = s.src[2 * s.nt + n];
@@ -454,7 +469,7 @@ __device__ __forceinline__ void adj_vel_finish(const Shot2D& s, int i, int j, in
   // ---- loads ----
   const int slot = s.row_slot[i];  // DAS row slot (depends on the wavefront's row only)
   const float txx = s.txxb[o], tzz = s.tzzb[o], txz = s.txzb[o];
-  const float u0x = s.uxb[o], u0z = s.uzb[o], bx = s.bx[o], bz = s.bz[o];
+  const float u0x = s.uxb[o], u0z = s.uzb[o], bx = bx_of(s, o), bz = bz_of(s, o);
   int sx = -1, sz = -1;
   long qx_ = 0, qz_ = 0;
   float r1 = 0.0f, r2 = 0.0f, r3 = 0.0f, r4 = 0.0f;
@@ -499,11 +514,14 @@ __device__ __forceinline__ void adj_vel_finish(const Shot2D& s, int i, int j, in
   const bool at_src = SRCADJ && i == s.si && j == s.sj;
   if (at_src) {
     // sigma_bar at the source from t_bar: invert the 2x2 normal block and the shear moduli
-    const float l2m = s.l2m[o], lam = s.lam[o];
+    const float lam = s.lam[o], l2m = l2m_of(s, o);
     const float det = (l2m - lam) * (l2m + lam);
     sb0 = (l2m * txx - lam * tzz) / det;
     sb1 = (l2m * tzz - lam * txx) / det;
-    auto sxz_at = [&](long oo) { return s.muxz[oo] > 0.0f ? s.txzb[oo] / s.muxz[oo] : 0.0f; };
+    auto sxz_at = [&](long oo) {
+      const float m = muxz_of(s, oo);
+      return m > 0.0f ? s.txzb[oo] / m : 0.0f;
+    };
     sb2 = sxz_at(o) + sxz_at(o - 1) + sxz_at(o - ld) + sxz_at(o - ld - 1);
   }
   // ---- arithmetic ----
@@ -583,7 +601,7 @@ __device__ __forceinline__ void adj_str_finish(const Shot2D& s, int i, int j, in
   const int rd = (n + 1) & 1, wr = n & 1;
   // ---- loads ----
   const float ux = s.uxb[o], uz = s.uzb[o];
-  const float l2m = s.l2m[o], lam = s.lam[o], mxz = s.muxz[o];
+  const float lam = s.lam[o], l2m = l2m_of(s, o), mxz = muxz_of(s, o);
   const float t0xx = s.txxb[o], t0zz = s.tzzb[o], t0xz = s.txzb[o];
   int sx = -1, sz = -1;
   long qx_ = 0, qz_ = 0;
@@ -672,31 +690,28 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_str(BATCH_PARAMS, int n, int k,
 }
 
 // ------------------------------------------------------------------------------------
-// Staging: (Vp, Vs, rho) of the window -> lambda + 2 mu, lambda, harmonic mu_xz, b_x, b_z.
+// Staging: (Vp, Vs, rho) of the window -> lambda, mu, rho at the normal nodes; the last row
+// and column are repeated into the halo so that the averages of the staggered parameters
+// clamp at the far edges (see bx_of, muxz_of).
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(BX * BZ) void k_stage(BATCH_PARAMS) {
   BATCH_TILE();
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   if (i >= s.nz || j >= s.nx) return;
-  const int ip = min(i + 1, s.nz - 1), jp = min(j + 1, s.nx - 1);
-  auto at = [&](const gfloat* f, int a, int b) { return f[(long)a * s.mld + b]; };
-  const float vp = at(s.mvp, i, j), vs = at(s.mvs, i, j), rho = at(s.mrho, i, j);
-  auto mu_at = [&](int a, int b) {
-    const float v = at(s.mvs, a, b);
-    return at(s.mrho, a, b) * v * v;
-  };
+  const long mo = (long)i * s.mld + j;
+  const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
   const float mu = rho * vs * vs;
-  const float l2m = rho * vp * vp;
+  const float lam = rho * vp * vp - 2.0f * mu;
   const long o = (long)i * s.ld + j;
-  s.l2m[o] = l2m;
-  s.lam[o] = l2m - 2.0f * mu;
-  const float m00 = mu, m10 = mu_at(ip, j), m01 = mu_at(i, jp), m11 = mu_at(ip, jp);
-  float mxz = 0.0f;
-  if (m00 > 0.0f && m10 > 0.0f && m01 > 0.0f && m11 > 0.0f)
-    mxz = 4.0f / (1.0f / m00 + 1.0f / m10 + 1.0f / m01 + 1.0f / m11);
-  s.muxz[o] = mxz;
-  s.bx[o] = 2.0f / (rho + at(s.mrho, i, jp));
-  s.bz[o] = 2.0f / (rho + at(s.mrho, ip, j));
+  const bool xe = j == s.nx - 1, ze = i == s.nz - 1;
+  for (int c = 0; c < 4; ++c) {
+    const bool dx = c & 1, dz = c >> 1;
+    if ((dx && !xe) || (dz && !ze)) continue;
+    const long oc = o + (dx ? 1 : 0) + (dz ? s.ld : 0);
+    s.lam[oc] = lam;
+    s.mu[oc] = mu;
+    s.rho[oc] = rho;
+  }
 }
 
 // ------------------------------------------------------------------------------------
