@@ -11,7 +11,9 @@ The forward history for the imaging condition is kept with the largest checkpoin
 whose workspace fits in the free HBM (one shot's whole history, 224 GiB, fits in the 288 GB
 of an MI355X, so nothing is recomputed); the sqrt(nt)-checkpoint form (recomputing all but
 the last segment) and the batched form (all shots advanced together) are timed once each
-and must give the identical gradient.
+and must give the identical gradient; the FP16- and BF16-checkpoint forms are timed once
+each with their gradient's relative L2 distance from the FP32 one, and the batched form on
+64 uneven windows (nz_s ~ U[400,1000], nx_s ~ U[800,3000]) is timed once.
 
 Metric: Gcell-updates/s = shots * nz * nx * nt / wall time (fwd + adj + grad), inputs
 resident in HBM before the timed region. The JSON line also carries:
@@ -100,6 +102,50 @@ def cpu_baseline(w, target_s=12.0):
                       f"FP64 NumPy (single-threaded elementwise), {dt:.1f} s"}
 
 
+def uneven_batched_form(efwi, inputs, torch, dev, grid, nt, log):
+    """64 shots on uneven windows (nz_s ~ U[400,1000], nx_s ~ U[800,3000]) cut from the same
+    model, each with its own component of a 64-component extended model, advanced together
+    (sqrt(nt) checkpoints), plus the regularizer over the 64 components; timed once."""
+    w = inputs.batched_2d(nshots=64, nt=nt)
+    T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
+    shots = [efwi.Shot(s.src_iz, s.src_ix, s.ch_iz, s.ch_ix, z0=s.z0, x0=s.x0, wz=s.wz, wx=s.wx) for s in w.shots]
+    ns, nz, nx = len(shots), w.nz, w.nx
+    m_start, m_true = T(w.m_start), T(w.m_true)
+    src = T(np.stack([np.outer(s.M, w.stf) for s in w.shots]))
+    fws = efwi.workspace(max(efwi.workspace_size(efwi.WS_FORWARD, grid, [s]) for s in shots), dev)
+    d_obs = torch.cat([efwi.model_forward(grid, shots[k], m_true, src[k], ws=fws) for k in range(ns)])
+    del fws, m_true
+    noise = T(np.stack([inputs.smooth_random_field((nz, nx), 20.0, 177 + k, 0.01) for k in range(3)]))
+    m_ext = torch.stack([m_start * (1.0 + torch.roll(noise, shifts=(0, 41 * k), dims=(1, 2))) for k in range(ns)])
+    del noise
+    b_np, sink_np = inputs.hard_sinkholes(ns, nz, nx, [s.src_iz for s in w.shots], [s.src_ix for s in w.shots])
+    b, sink = T(b_np), torch.tensor(sink_np, device=dev)
+    del b_np, sink_np
+    g_ext = torch.empty_like(m_ext)
+    phi = torch.empty((ns,), dtype=torch.float64, device=dev)
+    phi_reg = torch.empty((), dtype=torch.float64, device=dev)
+    rws = efwi.workspace(efwi.workspace_size(efwi.WS_REGULARIZER, grid, []), dev)
+    need = efwi.workspace_size(efwi.WS_BATCH, grid, shots)
+    torch.cuda.synchronize()
+    free = torch.cuda.mem_get_info(dev)[0]
+    bws = efwi.workspace(min(need, int(free * 0.9)), dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    efwi.batch_gradient(grid, shots, m_ext, src, d_obs, g_ext=g_ext, phi=phi, ws=bws)
+    efwi.extension_regularizer(grid, m_ext, b, sink, 1.0, g_ext, phi=phi_reg, ws=rws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert bool(torch.isfinite(phi).all()) and bool(torch.isfinite(phi_reg))
+    cells = sum(s.wz * s.wx for s in shots)
+    out = {"shots_per_s": round(ns / dt, 4), "gcell_per_s": round(cells * nt / dt / 1e9, 4),
+           "ms_per_step": round(dt * 1e3, 2), "waves": -(-need // bws.numel()), "shots": ns,
+           "mean_cells_per_shot": int(cells / ns)}
+    log(f"uneven batched form done: {out}")
+    del bws, m_ext, g_ext, b, sink, d_obs, src, m_start
+    torch.cuda.empty_cache()
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -115,6 +161,8 @@ def main():  # noqa: C901
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-sqrt", action="store_true", help="skip the sqrt(nt)-checkpoint form")
+    ap.add_argument("--no-compressed", action="store_true", help="skip the FP16/BF16-checkpoint forms")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 64-shot uneven-window batched form")
     ap.add_argument("--interval", type=int, default=-1,
                     help="checkpoint interval of the plain form (-1: largest that fits, 0: sqrt(nt))")
     ap.add_argument("--mem-fraction", type=float, default=0.92,
@@ -220,6 +268,32 @@ def main():  # noqa: C901
         del sws
         torch.cuda.empty_cache()
 
+    if not args.no_compressed:
+        # Compressed-checkpoint forms: sqrt(nt) checkpoints stored as 16-bit codes with one
+        # FP32 scale per field and snapshot. Accuracy (untimed): the data-term gradient of
+        # the first two shots against the FP32-checkpoint one (bitwise equal to the plain form).
+        acc_shots = range(min(2, ns))
+        sq = [dataclasses.replace(s, ckpt_interval=0, _keep=[]) for s in shots]
+        sws = efwi.workspace(efwi.workspace_size(efwi.WS_GRADIENT, grid, sq[:1]), dev)
+        ref = [efwi.shot_gradient(grid, sq[k], m_ext[k], src[k], obs[k], ws=sws)[0].double() for k in acc_shots]
+        del sws
+        torch.cuda.empty_cache()
+        for name, mode in (("fp16_checkpoints", efwi.CKPT_FP16), ("bf16_checkpoints", efwi.CKPT_BF16)):
+            cs = [dataclasses.replace(s, ckpt_interval=0, ckpt_mode=mode, _keep=[]) for s in shots]
+            cws = efwi.workspace(efwi.workspace_size(efwi.WS_GRADIENT, grid, cs[:1]), dev)
+            f = timed_once(lambda: plain_step(cs, cws))
+            f.pop("identical_to_plain")
+            got = [efwi.shot_gradient(grid, cs[k], m_ext[k], src[k], obs[k], ws=cws)[0].double() for k in acc_shots]
+            f["grad_rel_l2_vs_fp32"] = [
+                max(float(torch.linalg.vector_norm(got[q][c] - ref[q][c]) / torch.linalg.vector_norm(ref[q][c]))
+                    for q in range(len(ref))) for c in range(3)]
+            f["workspace_GiB"] = round(cws.numel() / 2**30, 2)
+            forms[name] = f
+            log(f"{name} form done: {f}")
+            del cws, got
+            torch.cuda.empty_cache()
+        del ref
+
     if not args.no_batched:
         # Batched form: every shot advanced together (one launch per half step covers all
         # shots' tiles), sqrt(nt) checkpoints, in as few waves as the free memory allows.
@@ -238,6 +312,9 @@ def main():  # noqa: C901
         log(f"batched form done: {forms['batched']}")
         del bws
         torch.cuda.empty_cache()
+
+    if not args.no_uneven:
+        forms["batched_uneven_64"] = uneven_batched_form(efwi, inputs, torch, dev, grid, nt, log)
 
     cell_steps = ns * nz * nx * nt * args.steps
     value = cell_steps / elapsed / 1e9
