@@ -99,9 +99,10 @@ Staging& staging() {
 // bracketed by two HIP events recorded on the launch stream; durations are collected when
 // queried. Off by default (no events in the hot loop).
 // ----------------------------------------------------------------------------------------
-enum KernelKind { KK_FWD_VEL = 0, KK_FWD_STR, KK_ADJ_VEL, KK_ADJ_STR, KK_CHAIN, KK_MISFIT, KK_REG, KK_COUNT };
-const char* const kKernelNames[KK_COUNT] = {"fwd_vel", "fwd_str", "adj_vel", "adj_str",
-                                            "chain_flush", "misfit", "regularizer"};
+// fwd_vel and fwd_str are the 3D forward half steps; fwd_step is the fused 2D forward step.
+enum KernelKind { KK_FWD_VEL = 0, KK_FWD_STR, KK_ADJ_VEL, KK_ADJ_STR, KK_CHAIN, KK_MISFIT, KK_REG, KK_FWD_STEP, KK_COUNT };
+const char* const kKernelNames[KK_COUNT] = {"fwd_vel", "fwd_str", "adj_vel", "adj_str", "chain_flush",
+                                            "misfit", "regularizer", "fwd_step"};
 
 class Sampler {
  public:
@@ -269,7 +270,7 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
 // ----------------------------------------------------------------------------------------
 struct Plan2D {
   Window w;
-  int nz, nx, ld, cp, rows, P, nslots, nt, nch, L, nseg, ntiles;
+  int nz, nx, ld, cp, rows, P, nslots, nt, nch, L, nseg, ntiles, nstep_tiles;
   long plane, cells;
   size_t state_bytes;  // padded fields + forward CPML strips
   size_t state_elems;
@@ -312,6 +313,7 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.nch = s.nch;
   p.nslots = count_slots(s, p.w);
   p.ntiles = ((p.nx + BX - 1) / BX) * ((p.nz + BZ - 1) / BZ);
+  p.nstep_tiles = ((p.nx + BX - 1) / BX) * ((p.nz + TSTEP - 1) / TSTEP);
   p.L = interval_of(g, s);
   p.nseg = (g.nt + p.L - 1) / p.L;
   const size_t strips = strips_floats(p.nz, p.nx, p.P);
@@ -348,7 +350,7 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
     return at;
   };
   p.off_par = take(p.par_bytes);
-  p.off_state = fwd ? take(p.state_bytes) : 0;
+  p.off_state = fwd ? take(2 * p.state_bytes) : 0;  // double-buffered by step parity
   p.off_e = fwd ? take((size_t)std::max(1, p.nch) * sizeof(float)) : 0;
   p.off_adj = adj ? take(p.adj_bytes) : 0;
   p.off_ebar = adj ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
@@ -450,6 +452,7 @@ Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsign
   };
   gfloat* f[5];
   gfloat* st = fields(p.off_state, f);
+  d.sbuf = (long)(p.state_bytes / sizeof(float));
   d.vx = f[0], d.vz = f[1], d.sxx = f[2], d.szz = f[3], d.sxz = f[4];
   strips_at(st, d.psx, d.psz);
   st = fields(p.off_adj, f);
@@ -503,13 +506,15 @@ size_t sched_capacity(size_t tiles) {
 }
 
 size_t header_bytes(const std::vector<Plan2D>& plans, int first, int count) {
-  size_t tiles = 0, tabs = 0;
+  size_t tiles = 0, stiles = 0, tabs = 0;
   for (int k = first; k < first + count; ++k) {
     tiles += plans[k].ntiles;
+    stiles += plans[k].nstep_tiles;
     tabs += plans[k].tab_bytes;
   }
-  return align_up((size_t)count * sizeof(Shot2D)) + align_up((size_t)count * sizeof(int)) +
-         align_up(tiles * sizeof(int)) + 2 * align_up(sched_capacity(tiles) * sizeof(int)) + tabs;
+  return align_up((size_t)count * sizeof(Shot2D)) + 2 * align_up((size_t)count * sizeof(int)) +
+         align_up(tiles * sizeof(int)) + 2 * align_up(sched_capacity(tiles) * sizeof(int)) +
+         align_up(stiles * sizeof(int)) + align_up(sched_capacity(stiles) * sizeof(int)) + tabs;
 }
 
 size_t wave_bytes(const std::vector<Plan2D>& plans, int first, int count) {
@@ -554,21 +559,29 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   wv.nt = g.nt;
   wv.L = wv.plans[0].L;
   wv.nseg = wv.plans[0].nseg;
-  int ntiles = 0;
-  for (const Plan2D& p : wv.plans) ntiles += p.ntiles;
+  int ntiles = 0, nstiles = 0;
+  for (const Plan2D& p : wv.plans) {
+    ntiles += p.ntiles;
+    nstiles += p.nstep_tiles;
+  }
   // header layout
   const size_t off_desc = 0;
   const size_t off_first = off_desc + align_up((size_t)count * sizeof(Shot2D));
   const size_t off_tshot = off_first + align_up((size_t)count * sizeof(int));
   const size_t off_sched = off_tshot + align_up((size_t)ntiles * sizeof(int));
   const size_t off_sched2 = off_sched + align_up(sched_capacity(ntiles) * sizeof(int));
-  size_t off_tab = off_sched2 + align_up(sched_capacity(ntiles) * sizeof(int));
+  const size_t off_sfirst = off_sched2 + align_up(sched_capacity(ntiles) * sizeof(int));
+  const size_t off_stshot = off_sfirst + align_up((size_t)count * sizeof(int));
+  const size_t off_ssched = off_stshot + align_up((size_t)nstiles * sizeof(int));
+  size_t off_tab = off_ssched + align_up(sched_capacity(nstiles) * sizeof(int));
   const size_t hdr = header_bytes(plans, first, count);
   std::vector<unsigned char> blob(hdr, 0);
   int* tfirst = reinterpret_cast<int*>(blob.data() + off_first);
   int* tshot = reinterpret_cast<int*>(blob.data() + off_tshot);
+  int* sfirst = reinterpret_cast<int*>(blob.data() + off_sfirst);
+  int* stshot = reinterpret_cast<int*>(blob.data() + off_stshot);
   size_t region = hdr;
-  int t = 0;
+  int t = 0, ts = 0;
   wv.descs.clear();
   wv.regions.clear();
   for (int k = 0; k < count; ++k) {
@@ -576,6 +589,8 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     const efwi_shot& s = shots[first + k];
     tfirst[k] = t;
     for (int q = 0; q < p.ntiles; ++q) tshot[t++] = k;
+    sfirst[k] = ts;
+    for (int q = 0; q < p.nstep_tiles; ++q) stshot[ts++] = k;
     build_tables(g, s, p, blob.data() + off_tab);
     const float* tab_dev = reinterpret_cast<const float*>(ws + off_tab);
     wv.descs.push_back(make_desc(g, s, p, ws + region, tab_dev, io[first + k]));
@@ -601,11 +616,29 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
       wadj[q] = near(2) ? ADJ_W_PML : ADJ_W_INT;
     }
   }
-  int nsched[2];
+  // the fused forward step's tiles (TSTEP rows; CPML path within two nodes of a strip)
+  std::vector<int> wstep(nstiles);
+  for (int k = 0, q = 0; k < count; ++k) {
+    const Plan2D& p = wv.plans[k];
+    const int ntx = (p.nx + BX - 1) / BX;
+    for (int l = 0; l < p.nstep_tiles; ++l, ++q) {
+      const int i0 = (l / ntx) * TSTEP, j0 = (l % ntx) * BX, pad = 2;
+      const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
+                                   (i0 + TSTEP - 1 + pad >= p.nz - p.P));
+      wstep[q] = pml ? FWD_W_PML : FWD_W_INT;
+    }
+  }
+  int nsched[3];
   efwi_status rc = build_sched(wfwd, reinterpret_cast<int*>(blob.data() + off_sched), nsched[0]);
   if (rc != EFWI_OK) return rc;
   rc = build_sched(wadj, reinterpret_cast<int*>(blob.data() + off_sched2), nsched[1]);
   if (rc != EFWI_OK) return rc;
+  rc = build_sched(wstep, reinterpret_cast<int*>(blob.data() + off_ssched), nsched[2]);
+  if (rc != EFWI_OK) return rc;
+  wv.batch.step_tile_first = reinterpret_cast<const int*>(ws + off_sfirst);
+  wv.batch.step_tile_shot = reinterpret_cast<const int*>(ws + off_stshot);
+  wv.batch.step = Sched{reinterpret_cast<const int*>(ws + off_ssched), nsched[2]};
+  wv.batch.nstep_tiles = nstiles;
   wv.batch.shots = reinterpret_cast<const Shot2D*>(ws + off_desc);
   wv.batch.tile_first = reinterpret_cast<const int*>(ws + off_first);
   wv.batch.tile_shot = reinterpret_cast<const int*>(ws + off_tshot);
@@ -622,7 +655,7 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     unsigned char* r = ws + wv.regions[k];
     HIP_TRY(hipMemsetAsync(r + p.off_par, 0, p.par_bytes, st));
     if (fwd) {
-      HIP_TRY(hipMemsetAsync(r + p.off_state, 0, p.state_bytes, st));
+      HIP_TRY(hipMemsetAsync(r + p.off_state, 0, 2 * p.state_bytes, st));
       HIP_TRY(hipMemsetAsync(r + p.off_e, 0, (size_t)std::max(1, p.nch) * sizeof(float), st));
     }
     if (adj) HIP_TRY(hipMemsetAsync(r + p.off_adj, 0, p.adj_bytes, st));
@@ -645,16 +678,16 @@ efwi_status run_forward(Wave& wv, unsigned char* ws, bool checkpoints, hipStream
         const Plan2D& p = wv.plans[q];
         unsigned char* r = ws + wv.regions[q];
         unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
+        unsigned char* state = r + p.off_state + (size_t)(n & 1) * p.state_bytes;  // state of step n
         if (p.ckpt_mode == EFWI_CKPT_FP32)
-          HIP_TRY(hipMemcpyAsync(slot, r + p.off_state, p.state_bytes, hipMemcpyDeviceToDevice, st));
+          HIP_TRY(hipMemcpyAsync(slot, state, p.state_bytes, hipMemcpyDeviceToDevice, st));
         else
-          HIP_TRY(launch_ckpt_encode(reinterpret_cast<const float*>(r + p.off_state), p.fields,
+          HIP_TRY(launch_ckpt_encode(reinterpret_cast<const float*>(state), p.fields,
                                      reinterpret_cast<unsigned int*>(r + p.off_maxbits), slot, p.ckpt_mode, st));
       }
     }
     const int kstore = (checkpoints && n >= last0) ? n - last0 : -1;
-    HIP_TRY(TIMED(KK_FWD_VEL, st, launch_fwd_vel(wv.batch, kstore, st)));
-    HIP_TRY(TIMED(KK_FWD_STR, st, launch_fwd_str(wv.batch, n, kstore, true, st)));
+    HIP_TRY(TIMED(KK_FWD_STEP, st, launch_fwd_step(wv.batch, n, kstore, true, st)));
   }
   return EFWI_OK;
 }
@@ -669,16 +702,14 @@ efwi_status run_reverse(Wave& wv, unsigned char* ws, hipStream_t st) {
         const Plan2D& p = wv.plans[q];
         unsigned char* r = ws + wv.regions[q];
         const unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
-        if (k == 0) HIP_TRY(hipMemsetAsync(r + p.off_state, 0, p.state_bytes, st));
+        unsigned char* state = r + p.off_state + (size_t)(n0 & 1) * p.state_bytes;  // state of step n0
+        if (k == 0) HIP_TRY(hipMemsetAsync(state, 0, p.state_bytes, st));
         else if (p.ckpt_mode == EFWI_CKPT_FP32)
-          HIP_TRY(hipMemcpyAsync(r + p.off_state, slot, p.state_bytes, hipMemcpyDeviceToDevice, st));
+          HIP_TRY(hipMemcpyAsync(state, slot, p.state_bytes, hipMemcpyDeviceToDevice, st));
         else
-          HIP_TRY(launch_ckpt_decode(reinterpret_cast<float*>(r + p.off_state), p.fields, slot, p.ckpt_mode, st));
+          HIP_TRY(launch_ckpt_decode(reinterpret_cast<float*>(state), p.fields, slot, p.ckpt_mode, st));
       }
-      for (int n = n0; n < n1; ++n) {
-        HIP_TRY(TIMED(KK_FWD_VEL, st, launch_fwd_vel(wv.batch, n - n0, st)));
-        HIP_TRY(TIMED(KK_FWD_STR, st, launch_fwd_str(wv.batch, n, n - n0, false, st)));
-      }
+      for (int n = n0; n < n1; ++n) HIP_TRY(TIMED(KK_FWD_STEP, st, launch_fwd_step(wv.batch, n, n - n0, false, st)));
     }
     // Imaging sums run in FP32 over blocks of FLUSH_STEPS steps aligned on absolute step
     // numbers and are then added into the FP64 gradient, so the result does not depend on

@@ -50,7 +50,9 @@ struct Shot2D {
   float dt, rdx, rdz, w;        // w = dt / (dx dz)
   int cp;                       // row pitch of the unpadded per-cell arrays
   long cells;                   // nz * cp
-  // forward state
+  // forward state, double-buffered by step parity: these pointers address buffer 0 and
+  // element p + sbuf is the same element of buffer 1
+  long sbuf;
   gfloat *vx, *vz, *sxx, *szz, *sxz;
   gfloat* psx[4];                // x-strip memory variables [nz][2P]: VXX, VZX, XX, XZ
   gfloat* psz[4];                // z-strip memory variables [2P][nx]: VXZ, VZZ, ZZ, XZ
@@ -101,7 +103,15 @@ struct Batch2D {
   const int* tile_first;
   Sched fwd, adj;
   int ns, ntiles;
+  // the same for the fused forward step's tiles of TSTEP rows
+  const int* step_tile_shot;
+  const int* step_tile_first;
+  Sched step;
+  int nstep_tiles;
 };
+
+// Rows of a fused forward-step tile (64 columns wide).
+constexpr int TSTEP = 8;
 
 // Number of XCDs the hardware deals workgroups to, round robin.
 constexpr int NUM_XCD = 8;
@@ -129,8 +139,8 @@ __host__ __device__ inline int strip_index(int k, int n, int P) {
 // Kernel launchers (kernels2d.hip). All enqueue on `st` and return hipGetLastError().
 // `kstore` / `k` index the step inside the checkpoint segment buffer (-1: do not store).
 hipError_t launch_stage2d(const Batch2D& b, hipStream_t st);
-hipError_t launch_fwd_vel(const Batch2D& b, int kstore, hipStream_t st);
-hipError_t launch_fwd_str(const Batch2D& b, int n, int kstore, bool record, hipStream_t st);
+// Fused forward step n: reads state buffer n & 1, writes buffer (n + 1) & 1.
+hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hipStream_t st);
 hipError_t launch_adj_vel(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st);
 hipError_t launch_adj_str(const Batch2D& b, int n, int k, bool grad, bool first, hipStream_t st);
 hipError_t launch_chain_flush(const Batch2D& b, hipStream_t st);

@@ -79,6 +79,7 @@ __device__ __forceinline__ float dminus(P f, long o, long st, float r) {
 // m-th tile of run k. Contiguous runs keep each stencil's z-halo rows in the XCD's own L2.
 // Schedule entries of -1 pad the shorter runs.
 constexpr int NXCD = 8;
+template <int ROWS>
 __device__ __forceinline__ bool batch_tile(const int* __restrict__ sched, const int* __restrict__ tile_shot,
                                            const int* __restrict__ tile_first, const Shot2D* __restrict__ shots,
                                            int& sh, int& i0, int& j0) {
@@ -87,7 +88,7 @@ __device__ __forceinline__ bool batch_tile(const int* __restrict__ sched, const 
   sh = tile_shot[t];
   const int local = t - tile_first[sh];
   const int ntx = (shots[sh].nx + BX - 1) / BX;
-  i0 = (local / ntx) * BZ;
+  i0 = (local / ntx) * ROWS;
   j0 = (local % ntx) * BX;
   return true;
 }
@@ -95,15 +96,16 @@ __device__ __forceinline__ bool batch_tile(const int* __restrict__ sched, const 
 #define BATCH_PARAMS                                                                           \
   const Shot2D* __restrict__ shots, const int* __restrict__ tile_shot, const int* __restrict__ tile_first, \
       const int* __restrict__ sched
+#define STEP_PARAMS BATCH_PARAMS
 #define BATCH_TILE()                                                                           \
   int sh_, i0, j0;                                                                              \
-  if (!batch_tile(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;                   \
+  if (!batch_tile<BZ>(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;               \
   const Shot2D& s = shots[sh_]
 
-// Does the block touch a CPML strip (with `pad` extra cells of neighbourhood)?
-__device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, int pad) {
+// Does the tile of `rows` rows touch a CPML strip (with `pad` extra cells of neighbourhood)?
+__device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, int rows, int pad) {
   if (s.P <= 0) return false;
-  const int j1 = j0 + BX - 1 + pad, i1 = i0 + BZ - 1 + pad;
+  const int j1 = j0 + BX - 1 + pad, i1 = i0 + rows - 1 + pad;
   return (j0 - pad < s.P) || (j1 >= s.nx - s.P) || (i0 - pad < s.P) || (i1 >= s.nz - s.P);
 }
 
@@ -112,29 +114,137 @@ __device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, in
 // load would force another memory round trip per wavefront.
 
 // ------------------------------------------------------------------------------------
-// Forward velocity half step: v^{n+1/2} = v^{n-1/2} + dt b (div sigma^n), CPML in strips.
+// Fused forward time step n, eq.(1)-(3), on tiles of TZ rows x 64 columns. The forward
+// state is double-buffered by step parity: buffer n & 1 holds sigma^n, v^{n-1/2} and the
+// CPML memory variables, and the step writes buffer (n + 1) & 1, so no tile reads what
+// another tile of the same launch writes. Per tile:
+//   1. sigma^n of the tile and a 4-node halo is staged in LDS by one coalesced sweep;
+//   2. velocity half step v^{n+1/2} = v^{n-1/2} + dt b div(sigma^n) on the tile and a
+//      2-node halo, from LDS (halo nodes are recomputed rather than exchanged); owned
+//      nodes go to HBM, all of them to LDS;
+//   3. stress half step sigma^{n+1} = sigma^n + dt C (strain rate of v^{n+1/2}) on the
+//      tile from the LDS velocities, with the moment-tensor injection at t_{n+1/2}
+//      (eq.(2)) and the DAS strain record (eq.(3)).
+// Each step reads sigma, v and the parameters once and writes sigma and v once, instead of
+// re-reading sigma and v between two half-step kernels.
 // ------------------------------------------------------------------------------------
+template <int TZ>
+struct StepTile {
+  static_assert(TZ % BZ == 0, "tile rows must be a multiple of the block's rows");
+  static constexpr int SR = TZ + 8, SC = BX + 8;  // sigma: rows i0-4 .. i0+TZ+3, columns j0-4 .. j0+67
+  static constexpr int VR = TZ + 4, VC = BX + 4;  // velocity: rows i0-2 .. i0+TZ+1, columns j0-2 .. j0+65
+  static constexpr int NS = 3 * SR * SC;
+  static constexpr int LDS_FLOATS = NS + 2 * VR * VC;
+};
+
+// Uniform (scalar) base pointers of one fused step. Every per-lane index below is a
+// non-negative 32-bit element offset from one of them, so an access is a scalar base plus
+// a 32-bit lane offset rather than per-lane 64-bit address arithmetic.
+struct StepPtrs {
+  const gfloat *sxx, *szz, *sxz, *vx, *vz;   // buffer n & 1, padded plane origins
+  gfloat *wsxx, *wszz, *wsxz, *wvx, *wvz;    // buffer (n + 1) & 1
+  const gfloat *lam, *mu, *rho;              // staged parameters, padded plane origins
+  const gfloat *rpx[4], *rpz[4];             // memory variables of buffer n & 1
+  gfloat *wpx[4], *wpz[4];                   // and of buffer (n + 1) & 1
+  const gfloat *axi, *bxi, *axh, *bxh, *azi, *bzi, *azh, *bzh;
+  gfloat* seg;                               // this step's slot of the history (STORE)
+  int ld, nx, nz, P2;                        // row pitch, window, strip width 2P
+};
+
+__device__ __forceinline__ StepPtrs step_ptrs(const Shot2D& s, int n, gfloat* seg) {
+  StepPtrs p;
+  const long org = (long)HALO * s.ld + XOFF;   // interior origin inside a padded plane
+  const long rd = (long)(n & 1) * s.sbuf, wr = (long)((n + 1) & 1) * s.sbuf;
+  p.sxx = s.sxx - org + rd;
+  p.szz = s.szz - org + rd;
+  p.sxz = s.sxz - org + rd;
+  p.vx = s.vx - org + rd;
+  p.vz = s.vz - org + rd;
+  p.wsxx = s.sxx - org + wr;
+  p.wszz = s.szz - org + wr;
+  p.wsxz = s.sxz - org + wr;
+  p.wvx = s.vx - org + wr;
+  p.wvz = s.vz - org + wr;
+  p.lam = s.lam - org;
+  p.mu = s.mu - org;
+  p.rho = s.rho - org;
+  for (int k = 0; k < 4; ++k) {
+    p.rpx[k] = s.psx[k] + rd;
+    p.rpz[k] = s.psz[k] + rd;
+    p.wpx[k] = s.psx[k] + wr;
+    p.wpz[k] = s.psz[k] + wr;
+  }
+  p.axi = axi(s), p.bxi = bxi(s), p.axh = axh(s), p.bxh = bxh(s);
+  p.azi = azi(s), p.bzi = bzi(s), p.azh = azh(s), p.bzh = bzh(s);
+  p.seg = seg;
+  p.ld = s.ld, p.nx = s.nx, p.nz = s.nz, p.P2 = 2 * s.P;
+  return p;
+}
+
+// Offset of padded node (i, j), i >= -HALO, j >= -XOFF, from its plane origin.
+__device__ __forceinline__ unsigned pofs(const StepPtrs& p, int i, int j) {
+  return (unsigned)((i + HALO) * p.ld + XOFF + j);
+}
+
+// Element `e` of a global array as a 32-bit byte offset from a uniform base (the form the
+// hardware's scalar-base global loads and stores take).
+template <class P>
+__device__ __forceinline__ auto& G(P* base, unsigned e) {
+  typedef __attribute__((address_space(1))) char gchar;
+  return *(P*)((gchar*)base + e * 4u);
+}
+template <class P>
+__device__ __forceinline__ const auto& G(const P* base, unsigned e) {
+  typedef const __attribute__((address_space(1))) char gchar;
+  return *(const P*)((gchar*)base + e * 4u);
+}
+
+// Inputs of one velocity node (loads only).
+struct VelLoads {
+  float vx, vz, r0, rx, rz;
+  float p1, p2, p3, p4;        // velocity-side memory variables (CPML tiles)
+};
+
+template <bool PML>
+__device__ __forceinline__ VelLoads vel_loads(const StepPtrs& p, const Shot2D& s, int gi, int gj) {
+  VelLoads L;
+  const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
+  const unsigned o = pofs(p, ic, jc);
+  L.vx = G(p.vx, o);
+  L.vz = G(p.vz, o);
+  L.r0 = G(p.rho, o);
+  L.rx = G(p.rho, o + 1);
+  L.rz = G(p.rho, o + p.ld);
+  L.p1 = L.p2 = L.p3 = L.p4 = 0.0f;
+  if (PML) {
+    const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
+    const unsigned qx = (unsigned)(ic * p.P2 + sx), qz = (unsigned)(sz * p.nx + jc);
+    L.p1 = G(p.rpx[X_VXX], qx);
+    L.p3 = G(p.rpx[X_VZX], qx);
+    L.p2 = G(p.rpz[Z_VXZ], qz);
+    L.p4 = G(p.rpz[Z_VZZ], qz);
+  }
+  return L;
+}
+
+// Velocity node (gi, gj): the four stress differences d1 = D+x sxx, d2 = D-z sxz (vx) and
+// d3 = D-x sxz, d4 = D+z szz (vz) come from LDS. Returns v^{n+1/2} (0 outside the grid);
+// with `owned`, writes v, the memory variables and the stored divergences.
 template <bool STORE, bool PML>
-__device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, gfloat* seg) {
-  const long ld = s.ld;
-  const long o = (long)i * ld + j;
-  float d1 = dplus(s.sxx, o, 1, s.rdx);    // D+x sxx at (i, j+1/2)
-  float d2 = dminus(s.sxz, o, ld, s.rdz);  // D-z sxz at (i, j+1/2)
-  float d3 = dminus(s.sxz, o, 1, s.rdx);   // D-x sxz at (i+1/2, j)
-  float d4 = dplus(s.szz, o, ld, s.rdz);   // D+z szz at (i+1/2, j)
-  const float vx = s.vx[o], vz = s.vz[o], bx = bx_of(s, o), bz = bz_of(s, o);
+__device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int gi, int gj, bool owned,
+                                         const VelLoads& L, float d1, float d2, float d3, float d4, float& vxn,
+                                         float& vzn) {
+  const bool in = gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx;
   int sx = -1, sz = -1;
-  long qx_ = 0, qz_ = 0;
   float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f, p4 = 0.0f;
-  if (PML) {  // clamped strip indices: loads unconditional, stores predicated
-    sx = strip_index(j, s.nx, s.P);
-    sz = strip_index(i, s.nz, s.P);
-    qx_ = (long)i * 2 * s.P + max(sx, 0);
-    qz_ = (long)max(sz, 0) * s.nx + j;
-    p1 = bxh(s)[j] * s.psx[X_VXX][qx_] + axh(s)[j] * d1;
-    p3 = bxi(s)[j] * s.psx[X_VZX][qx_] + axi(s)[j] * d3;
-    p2 = bzi(s)[i] * s.psz[Z_VXZ][qz_] + azi(s)[i] * d2;
-    p4 = bzh(s)[i] * s.psz[Z_VZZ][qz_] + azh(s)[i] * d4;
+  if (PML) {
+    const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
+    sx = strip_index(jc, p.nx, s.P);
+    sz = strip_index(ic, p.nz, s.P);
+    p1 = G(p.bxh, jc) * L.p1 + G(p.axh, jc) * d1;
+    p3 = G(p.bxi, jc) * L.p3 + G(p.axi, jc) * d3;
+    p2 = G(p.bzi, ic) * L.p2 + G(p.azi, ic) * d2;
+    p4 = G(p.bzh, ic) * L.p4 + G(p.azh, ic) * d4;
     if (sx >= 0) {
       d1 += p1;
       d3 += p3;
@@ -145,74 +255,81 @@ __device__ __forceinline__ void fwd_vel_cell(const Shot2D& s, int i, int j, gflo
     }
   }
   const float qx = d1 + d2, qz = d3 + d4;
+  const float bx = 2.0f * rcpf(L.r0 + L.rx), bz = 2.0f * rcpf(L.r0 + L.rz);
+  const float m = in ? 1.0f : 0.0f;
+  vxn = m * (L.vx + s.dt * bx * qx);
+  vzn = m * (L.vz + s.dt * bz * qz);
+  if (owned) {
+    const unsigned o = pofs(p, gi, gj);
+    G(p.wvx, o) = vxn;
+    G(p.wvz, o) = vzn;
+    if (PML) {
+      if (sx >= 0) {
+        const unsigned q = (unsigned)(gi * p.P2 + sx);
+        G(p.wpx[X_VXX], q) = p1;
+        G(p.wpx[X_VZX], q) = p3;
+      }
+      if (sz >= 0) {
+        const unsigned q = (unsigned)(sz * p.nx + gj);
+        G(p.wpz[Z_VXZ], q) = p2;
+        G(p.wpz[Z_VZZ], q) = p4;
+      }
+    }
+    if (STORE) {  // divergences times b/2: the rho imaging terms (d b / d rho = -b^2/2)
+      const unsigned c = (unsigned)(gi * s.cp + gj);
+      G(p.seg, 3 * s.cells + c) = 0.5f * qx * bx;
+      G(p.seg, 4 * s.cells + c) = 0.5f * qz * bz;
+    }
+  }
+}
+
+// Inputs of one stress node (loads only; the DAS channel, in the rare channel rows, is
+// looked up in str_node).
+struct StrLoads {
+  float lam, mu, mu_x, mu_z, mu_xz;
+  float p1, p2, p3, p4;        // stress-side memory variables (CPML tiles)
+};
+
+template <bool PML>
+__device__ __forceinline__ StrLoads str_loads(const StepPtrs& p, const Shot2D& s, int gi, int gj) {
+  StrLoads L;
+  const int ic = min(gi, p.nz - 1), jc = min(gj, p.nx - 1);
+  const unsigned o = pofs(p, ic, jc);
+  L.lam = G(p.lam, o);
+  L.mu = G(p.mu, o);
+  L.mu_x = G(p.mu, o + 1);
+  L.mu_z = G(p.mu, o + p.ld);
+  L.mu_xz = G(p.mu, o + p.ld + 1);
+  L.p1 = L.p2 = L.p3 = L.p4 = 0.0f;
   if (PML) {
-    if (sx >= 0) {
-      s.psx[X_VXX][qx_] = p1;
-      s.psx[X_VZX][qx_] = p3;
-    }
-    if (sz >= 0) {
-      s.psz[Z_VXZ][qz_] = p2;
-      s.psz[Z_VZZ][qz_] = p4;
-    }
+    const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
+    const unsigned qx = (unsigned)(ic * p.P2 + sx), qz = (unsigned)(sz * p.nx + jc);
+    L.p1 = G(p.rpx[X_XX], qx);
+    L.p2 = G(p.rpx[X_XZ], qx);
+    L.p3 = G(p.rpz[Z_ZZ], qz);
+    L.p4 = G(p.rpz[Z_XZ], qz);
   }
-  s.vx[o] = vx + s.dt * bx * qx;
-  s.vz[o] = vz + s.dt * bz * qz;
-  if (STORE) {  // divergences times b/2: the rho imaging terms (d b / d rho = -b^2/2)
-    const long c = (long)i * s.cp + j;
-    seg[3 * s.cells + c] = 0.5f * qx * bx;
-    seg[4 * s.cells + c] = 0.5f * qz * bz;
-  }
+  return L;
 }
 
-template <bool STORE>
-__global__ __launch_bounds__(BX * BZ) void k_fwd_vel(BATCH_PARAMS, int kstore) {
-  BATCH_TILE();
-  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
-  gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG_FIELDS * s.cells : nullptr;
-  if (i >= s.nz || j >= s.nx) return;
-  if (block_in_pml(s, j0, i0, 0)) fwd_vel_cell<STORE, true>(s, i, j, seg);
-  else fwd_vel_cell<STORE, false>(s, i, j, seg);
-}
-
-// ------------------------------------------------------------------------------------
-// Forward stress half step: sigma^{n+1} = sigma^n + dt C (strain rate of v^{n+1/2}),
-// moment-tensor injection at t_{n+1/2}, DAS strain record.
-// ------------------------------------------------------------------------------------
+// Stress node (i, j) from the LDS strain rates pxx = D-x vx, pzz = D-z vz, pzx = D+z vx,
+// pxz = D+x vz and the LDS sigma^n.
 template <bool STORE, bool RECORD, bool PML>
-__device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int n, gfloat* seg) {
-  const long ld = s.ld;
-  const long o = (long)i * ld + j;
-  float pxx = dminus(s.vx, o, 1, s.rdx);   // D-x vx at (i, j)
-  float pzz = dminus(s.vz, o, ld, s.rdz);  // D-z vz at (i, j)
-  float pzx = dplus(s.vx, o, ld, s.rdz);   // D+z vx at (i+1/2, j+1/2)
-  float pxz = dplus(s.vz, o, 1, s.rdx);    // D+x vz at (i+1/2, j+1/2)
+__device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int i, int j, int n, const StrLoads& L,
+                                         int slot, float pxx, float pzz, float pzx, float pxz, float sxx, float szz,
+                                         float sxz, float f_xx, float f_zz, float f_xz) {
   const float raw_pxx = pxx;
-  const float lam = s.lam[o], l2m = l2m_of(s, o), mxz = muxz_of(s, o);
-  float sxx = s.sxx[o], szz = s.szz[o], sxz = s.sxz[o];
-  // source components at t_{n+1/2} (uniform scalar loads)
-  const float f_xx = s.src[n], f_zz = s.src[s.nt + n], f_xz = s.src[2 * s.nt + n];
-  // DAS channel of this node, if any (row_slot depends on the wavefront's row only)
-  int ch = -1;
-  float e_old = 0.0f;
-  if (RECORD) {
-    const int slot = s.row_slot[i];
-    if (slot >= 0) {
-      ch = s.rowch[(long)slot * s.nx + j];
-      if (ch >= 0) e_old = s.e[ch];
-    }
-  }
+  const float mu = L.mu, lam = L.lam, l2m = lam + 2.0f * mu;
+  const float mxz = 4.0f * rcpf(rcpf(mu) + rcpf(L.mu_x) + rcpf(L.mu_z) + rcpf(L.mu_xz));
   int sx = -1, sz = -1;
-  long qx_ = 0, qz_ = 0;
   float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f, p4 = 0.0f;
-  if (PML) {  // clamped strip indices: loads unconditional, stores predicated
-    sx = strip_index(j, s.nx, s.P);
-    sz = strip_index(i, s.nz, s.P);
-    qx_ = (long)i * 2 * s.P + max(sx, 0);
-    qz_ = (long)max(sz, 0) * s.nx + j;
-    p1 = bxi(s)[j] * s.psx[X_XX][qx_] + axi(s)[j] * pxx;
-    p2 = bxh(s)[j] * s.psx[X_XZ][qx_] + axh(s)[j] * pxz;
-    p3 = bzi(s)[i] * s.psz[Z_ZZ][qz_] + azi(s)[i] * pzz;
-    p4 = bzh(s)[i] * s.psz[Z_XZ][qz_] + azh(s)[i] * pzx;
+  if (PML) {
+    sx = strip_index(j, p.nx, s.P);
+    sz = strip_index(i, p.nz, s.P);
+    p1 = G(p.bxi, j) * L.p1 + G(p.axi, j) * pxx;
+    p2 = G(p.bxh, j) * L.p2 + G(p.axh, j) * pxz;
+    p3 = G(p.bzi, i) * L.p3 + G(p.azi, i) * pzz;
+    p4 = G(p.bzh, i) * L.p4 + G(p.azh, i) * pzx;
     if (sx >= 0) {
       pxx += p1;
       pxz += p2;
@@ -233,40 +350,172 @@ __device__ __forceinline__ void fwd_str_cell(const Shot2D& s, int i, int j, int 
   if ((i == s.si || i == s.si - 1) && (j == s.sj || j == s.sj - 1)) sxz -= 0.25f * s.w * f_xz;
   if (PML) {
     if (sx >= 0) {
-      s.psx[X_XX][qx_] = p1;
-      s.psx[X_XZ][qx_] = p2;
+      const unsigned q = (unsigned)(i * p.P2 + sx);
+      G(p.wpx[X_XX], q) = p1;
+      G(p.wpx[X_XZ], q) = p2;
     }
     if (sz >= 0) {
-      s.psz[Z_ZZ][qz_] = p3;
-      s.psz[Z_XZ][qz_] = p4;
+      const unsigned q = (unsigned)(sz * p.nx + j);
+      G(p.wpz[Z_ZZ], q) = p3;
+      G(p.wpz[Z_XZ], q) = p4;
     }
   }
-  s.sxx[o] = sxx;
-  s.szz[o] = szz;
-  s.sxz[o] = sxz;
-  if (RECORD && ch >= 0) {
-    const float e = e_old + s.dt * raw_pxx;
-    s.e[ch] = e;
-    s.d[(long)ch * s.nt + n] = e;
+  const unsigned o = pofs(p, i, j);
+  G(p.wsxx, o) = sxx;
+  G(p.wszz, o) = szz;
+  G(p.wsxz, o) = sxz;
+  if (RECORD && slot >= 0) {  // slot: the row's DAS slot, uniform over the wavefront
+    const int ch = s.rowch[(long)slot * s.nx + j];
+    if (ch >= 0) {
+      const float e = s.e[ch] + s.dt * raw_pxx;
+      s.e[ch] = e;
+      s.d[(long)ch * s.nt + n] = e;
+    }
   }
   if (STORE) {  // strain rates times the factors of the lambda and mu imaging terms
-    const long c = (long)i * s.cp + j;
-    seg[c] = (pxx + pzz) / (l2m + lam);
-    seg[s.cells + c] = 0.25f * (pxx - pzz) * (l2m - lam);
-    seg[2 * s.cells + c] = 0.25f * ps * mxz;
+    const unsigned c = (unsigned)(i * s.cp + j);
+    G(p.seg, c) = (pxx + pzz) / (l2m + lam);
+    G(p.seg, s.cells + c) = 0.5f * (pxx - pzz) * mu;
+    G(p.seg, 2 * s.cells + c) = 0.25f * ps * mxz;
   }
 }
 
-template <bool STORE, bool RECORD>
-__global__ __launch_bounds__(BX * BZ) void k_fwd_str(BATCH_PARAMS, int n, int kstore) {
-  BATCH_TILE();
-  const int j = j0 + threadIdx.x;
-  // all 64 lanes of a wavefront share threadIdx.y: keep the row index scalar
-  const int i = i0 + __builtin_amdgcn_readfirstlane(threadIdx.y);
+template <int TZ, bool STORE, bool RECORD, bool PML>
+__device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, int n, gfloat* seg, float* lds) {
+  using T = StepTile<TZ>;
+  constexpr int SR = T::SR, SC = T::SC, VR = T::VR, VC = T::VC, NS = T::NS;
+  constexpr int NT = BX * BZ;
+  constexpr int NV = VR / BZ, NSR = TZ / BZ;
+  constexpr int Q = SC / 4;                         // float4 per staged row
+  constexpr int NQ = 3 * SR * Q;
+  constexpr int PER = (NQ + NT - 1) / NT;           // float4 loads per thread
+  static_assert(SC % 4 == 0, "staged rows are whole float4s");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const StepPtrs p = step_ptrs(s, n, seg);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+  const int tyu = __builtin_amdgcn_readfirstlane(ty);   // a wavefront's row is uniform
+  float* SXX = lds;
+  float* SZZ = lds + SR * SC;
+  float* SXZ = lds + 2 * SR * SC;
+  float* VXL = lds + NS;
+  float* VZL = VXL + VR * VC;
+  const int hv = min(tid >> 2, VR - 1), hc = tid & 3;
+  const int hcol = hc < 2 ? hc : VC - 4 + hc;      // LDS velocity column 0, 1, 66, 67
+
+  // ---- every global load of the tile, issued before the first LDS write ----
+  int slot[NSR];                                    // DAS slots of the thread's stress rows
+#pragma unroll
+  for (int k = 0; k < NSR; ++k) slot[k] = RECORD ? s.row_slot[min(i0 + tyu + k * BZ, p.nz - 1)] : -1;
+  // sigma^n of the tile and a 4-node halo, zero outside the grid: rows are clamped into the
+  // grid (the masked values of a clamped row are discarded) and a float4 that crosses the
+  // right edge reads the row's zero padding or the halo rows below it
+  // thread tid takes float4 e = tid + k NT, i.e. (field f, row r, float4 c4) of the
+  // [3][SR][Q] staging area, advanced by NT = 256 float4s per k without divisions
+  constexpr int DC = NT % Q, DR = (NT / Q) % SR, DF = NT / (SR * Q);
+  static_assert(DF == 0, "one step of NT float4s stays inside a field's staging area");
+  int sf[PER], sr_[PER], sc4[PER];
+  {
+    int f = tid / (SR * Q), rem = tid - f * (SR * Q);
+    int r = rem / Q, c4 = rem - r * Q;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      sf[k] = f, sr_[k] = r, sc4[k] = c4;
+      c4 += DC;
+      r += DR;
+      if (c4 >= Q) c4 -= Q, ++r;
+      if (r >= SR) r -= SR, ++f;
+    }
+  }
+  f4 sv[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int f = min(sf[k], 2);   // past the last field only when e >= NQ: load a valid float4
+    const int ic = min(max(i0 - 4 + sr_[k], 0), p.nz - 1);
+    const gfloat* src = f == 0 ? p.sxx : f == 1 ? p.szz : p.sxz;
+    typedef const __attribute__((address_space(1))) char gchar;
+    sv[k] = *(const __attribute__((address_space(1))) f4*)((gchar*)src + pofs(p, ic, j0 - 4 + 4 * sc4[k]) * 4u);
+  }
+  VelLoads L[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) L[k] = vel_loads<PML>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
+  const VelLoads H = vel_loads<PML>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
+  StrLoads SL[NSR];
+#pragma unroll
+  for (int k = 0; k < NSR; ++k) SL[k] = str_loads<PML>(p, s, i0 + tyu + k * BZ, j0 + tx);
+  const float f_xx = s.src[n], f_zz = s.src[s.nt + n], f_xz = s.src[2 * s.nt + n];
+
+  // ---- 1. staged sigma to LDS ----
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (sf[k] < 3) {
+      const int f = sf[k], r = sr_[k], c4 = sc4[k];
+      const int gi = i0 - 4 + r, gj = j0 - 4 + 4 * c4;
+      const bool row_in = gi >= 0 && gi < p.nz;
+      f4 v;
+      v.x = (row_in && gj + 0 >= 0 && gj + 0 < p.nx) ? sv[k].x : 0.0f;
+      v.y = (row_in && gj + 1 >= 0 && gj + 1 < p.nx) ? sv[k].y : 0.0f;
+      v.z = (row_in && gj + 2 >= 0 && gj + 2 < p.nx) ? sv[k].z : 0.0f;
+      v.w = (row_in && gj + 3 >= 0 && gj + 3 < p.nx) ? sv[k].w : 0.0f;
+      *(f4*)(lds + f * SR * SC + r * SC + 4 * c4) = v;
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. velocities: the 64 tile columns over VR rows (thread row ty, ty + 4, ...), then
+  //         the four halo columns j0-2, j0-1, j0+64, j0+65 (threads 0 .. 4 VR - 1) ----
+  auto vel = [&](int vr, int lcol, const VelLoads& LL, bool owned) {
+    const int gi = i0 - 2 + vr, gj = j0 - 2 + lcol;
+    const int sr = vr + 2, sc = lcol + 2;   // LDS sigma coordinates of the node
+    const float d1 = (K1 * (SXX[sr * SC + sc + 1] - SXX[sr * SC + sc]) +
+                      K2 * (SXX[sr * SC + sc + 2] - SXX[sr * SC + sc - 1])) * s.rdx;
+    const float d2 = (K1 * (SXZ[sr * SC + sc] - SXZ[(sr - 1) * SC + sc]) +
+                      K2 * (SXZ[(sr + 1) * SC + sc] - SXZ[(sr - 2) * SC + sc])) * s.rdz;
+    const float d3 = (K1 * (SXZ[sr * SC + sc] - SXZ[sr * SC + sc - 1]) +
+                      K2 * (SXZ[sr * SC + sc + 1] - SXZ[sr * SC + sc - 2])) * s.rdx;
+    const float d4 = (K1 * (SZZ[(sr + 1) * SC + sc] - SZZ[sr * SC + sc]) +
+                      K2 * (SZZ[(sr + 2) * SC + sc] - SZZ[(sr - 1) * SC + sc])) * s.rdz;
+    float vxn, vzn;
+    vel_node<STORE, PML>(p, s, gi, gj, owned, LL, d1, d2, d3, d4, vxn, vzn);
+    VXL[vr * VC + lcol] = vxn;
+    VZL[vr * VC + lcol] = vzn;
+  };
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int vr = ty + k * BZ, gi = i0 - 2 + vr;
+    vel(vr, tx + 2, L[k], gi >= i0 && gi < i0 + TZ && gi < p.nz && j0 + tx < p.nx);
+  }
+  if ((tid >> 2) < VR) vel(hv, hcol, H, false);
+  __syncthreads();
+
+  // ---- 3. stresses of the tile ----
+#pragma unroll
+  for (int k = 0; k < NSR; ++k) {
+    const int i = i0 + tyu + k * BZ, j = j0 + tx;
+    if (i >= p.nz || j >= p.nx) continue;
+    const int vr = tyu + k * BZ + 2, vc = tx + 2;   // LDS velocity coordinates of the node
+    const float* X = VXL + vr * VC + vc;
+    const float* Z = VZL + vr * VC + vc;
+    const float pxx = (K1 * (X[0] - X[-1]) + K2 * (X[1] - X[-2])) * s.rdx;
+    const float pzz = (K1 * (Z[0] - Z[-VC]) + K2 * (Z[VC] - Z[-2 * VC])) * s.rdz;
+    const float pzx = (K1 * (X[VC] - X[0]) + K2 * (X[2 * VC] - X[-VC])) * s.rdz;
+    const float pxz = (K1 * (Z[1] - Z[0]) + K2 * (Z[2] - Z[-1])) * s.rdx;
+    const int so = (vr + 2) * SC + tx + 4;           // LDS sigma of the node
+    str_node<STORE, RECORD, PML>(p, s, i, j, n, SL[k], slot[k], pxx, pzz, pzx, pxz, SXX[so], SZZ[so], SXZ[so],
+                                 f_xx, f_zz, f_xz);
+  }
+}
+
+// Tile shape of the fused forward step: TSTEP rows x 64 columns.
+template <int TZ, bool STORE, bool RECORD>
+__global__ __launch_bounds__(BX * BZ) void k_fwd_step(STEP_PARAMS, int n, int kstore) {
+  __shared__ float lds[StepTile<TZ>::LDS_FLOATS];
+  int sh_, i0, j0;
+  if (!batch_tile<TZ>(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;
+  const Shot2D& s = shots[sh_];
   gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG_FIELDS * s.cells : nullptr;
-  if (i >= s.nz || j >= s.nx) return;
-  if (block_in_pml(s, j0, i0, 0)) fwd_str_cell<STORE, RECORD, true>(s, i, j, n, seg);
-  else fwd_str_cell<STORE, RECORD, false>(s, i, j, n, seg);
+  // block-uniform branch: every thread reaches the barriers
+  if (block_in_pml(s, j0, i0, TZ, 2)) fwd_step_tile<TZ, STORE, RECORD, true>(s, i0, j0, n, seg, lds);
+  else fwd_step_tile<TZ, STORE, RECORD, false>(s, i0, j0, n, seg, lds);
 }
 
 // ------------------------------------------------------------------------------------
@@ -559,7 +808,7 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_vel(BATCH_PARAMS, int n, int k,
   const int j = j0 + threadIdx.x, i = i0 + __builtin_amdgcn_readfirstlane(threadIdx.y);
   const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
   const bool active = i < s.nz && j < s.nx;
-  if (block_in_pml(s, j0, i0, 2)) {  // block-uniform: every thread reaches the barrier
+  if (block_in_pml(s, j0, i0, BZ, 2)) {  // block-uniform: every thread reaches the barrier
     __shared__ float lds[LDS_OPS];
     const StageArea a{lds, lds + BZ * LX, lds + 2 * BZ * LX, lds + 2 * BZ * LX + LZ * BX};
     const int rd = (n + 1) & 1;
@@ -658,7 +907,7 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_str(BATCH_PARAMS, int n, int k,
   const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
   const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
   const bool active = i < s.nz && j < s.nx;
-  if (block_in_pml(s, j0, i0, 2)) {  // block-uniform: every thread reaches the barrier
+  if (block_in_pml(s, j0, i0, BZ, 2)) {  // block-uniform: every thread reaches the barrier
     __shared__ float lds[LDS_OPS];
     const StageArea a{lds, lds + BZ * LX, lds + 2 * BZ * LX, lds + 2 * BZ * LX + LZ * BX};
     const int rd = (n + 1) & 1;
@@ -790,19 +1039,16 @@ hipError_t launch_stage2d(const Batch2D& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_fwd_vel(const Batch2D& b, int kstore, hipStream_t st) {
-  if (kstore >= 0) k_fwd_vel<true><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, kstore);
-  else k_fwd_vel<false><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, 0);
-  return hipGetLastError();
-}
+#define STEP_ARGS b.shots, b.step_tile_shot, b.step_tile_first, b.step.sched
 
-hipError_t launch_fwd_str(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
+hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
+  const dim3 g = grid_of(b.step);
   if (kstore >= 0) {
-    if (record) k_fwd_str<true, true><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, n, kstore);
-    else k_fwd_str<true, false><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, n, kstore);
+    if (record) k_fwd_step<TSTEP, true, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
+    else k_fwd_step<TSTEP, true, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
   } else {
-    if (record) k_fwd_str<false, true><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, n, 0);
-    else k_fwd_str<false, false><<<grid_of(b.fwd), block2d(), 0, st>>>(FWD_ARGS, n, 0);
+    if (record) k_fwd_step<TSTEP, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
+    else k_fwd_step<TSTEP, false, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
   }
   return hipGetLastError();
 }
