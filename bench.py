@@ -21,7 +21,7 @@ resident in HBM before the timed region. The JSON line also carries:
   (HIP events around sampled launches on the library's stream), against 8 TB/s;
 * cpu_baseline: the FP64 NumPy oracle on a bounded sample (one shot, full grid, a few
   time steps), in the same unit;
-* path: the whole step's algorithmic bytes (188 B per cell-step plus 52 B per recomputed
+* path: the whole step's algorithmic bytes (168 B per cell-step plus 52 B per recomputed
   cell-step) over the step time.
 """
 from __future__ import annotations
@@ -46,20 +46,19 @@ HBM_PEAK_GBS = 8000.0
 #   fwd_step     fused forward step: read sxx szz sxz vx vz lambda mu rho,
 #                write sxx szz sxz vx vz (state double-buffered)                52 B
 #                + store the 5 imaging quantities of the step                  +20 B
-#   adj_vel      read t_bar (3), u_bar (2), rho, write u_bar (2),
-#                read 3 stored quantities, read+write 2 imaging sums            60 B
-#   adj_str      read u_bar (2), t_bar (3), lambda mu, write t_bar (3),
-#                read 2 stored quantities, read+write 1 imaging sum             56 B
+#   adj_step     fused transposed step: read t_bar (3), u_bar (2), lambda mu rho,
+#                the 5 stored quantities, 3 imaging sums; write t_bar, u_bar (5)
+#                and the 3 sums (adjoint fields double-buffered)                 96 B
 # (u_bar = b v_bar and t_bar = C sigma_bar are the scaled adjoint variables; the imaging
 # sums are gathered at the normal node.)
-KERNEL_BYTES = {"fwd_step": (52, 72), "adj_vel": (60, 60), "adj_str": (56, 56)}
+KERNEL_BYTES = {"fwd_step": (52, 72), "adj_step": (96, 96)}
 
 def path_bytes_per_cell_step(recompute_fraction):
     """Whole-path algorithmic bytes per cell-step: every step runs forward once with storing
-    (fwd_vel + fwd_str with store) and backward once (adj_vel + adj_str); each recomputed
+    (fwd_step with store) and backward once (adj_step); each recomputed
     step adds a forward step without storing in the first sweep."""
     fwd_plain, fwd_store = KERNEL_BYTES["fwd_step"]
-    adj = KERNEL_BYTES["adj_vel"][0] + KERNEL_BYTES["adj_str"][0]
+    adj = KERNEL_BYTES["adj_step"][0]
     return fwd_store + adj + recompute_fraction * fwd_plain
 
 

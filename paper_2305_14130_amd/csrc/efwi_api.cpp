@@ -99,10 +99,13 @@ Staging& staging() {
 // bracketed by two HIP events recorded on the launch stream; durations are collected when
 // queried. Off by default (no events in the hot loop).
 // ----------------------------------------------------------------------------------------
-// fwd_vel and fwd_str are the 3D forward half steps; fwd_step is the fused 2D forward step.
-enum KernelKind { KK_FWD_VEL = 0, KK_FWD_STR, KK_ADJ_VEL, KK_ADJ_STR, KK_CHAIN, KK_MISFIT, KK_REG, KK_FWD_STEP, KK_COUNT };
-const char* const kKernelNames[KK_COUNT] = {"fwd_vel", "fwd_str", "adj_vel", "adj_str", "chain_flush",
-                                            "misfit", "regularizer", "fwd_step"};
+// fwd_vel, fwd_str, adj_vel and adj_str are the 3D half steps; fwd_step and adj_step are the
+// fused 2D forward and transposed steps.
+enum KernelKind {
+  KK_FWD_VEL = 0, KK_FWD_STR, KK_ADJ_VEL, KK_ADJ_STR, KK_CHAIN, KK_MISFIT, KK_REG, KK_FWD_STEP, KK_ADJ_STEP, KK_COUNT
+};
+const char* const kKernelNames[KK_COUNT] = {"fwd_vel", "fwd_str",     "adj_vel",  "adj_str", "chain_flush",
+                                            "misfit",  "regularizer", "fwd_step", "adj_step"};
 
 class Sampler {
  public:
@@ -336,7 +339,9 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
       p.fields.len[9 + k] = zs;
     }
   }
-  p.adj_bytes = align_up(((size_t)5 * p.plane + 2 * strips) * sizeof(float));
+  // adjoint fields double-buffered by step parity (10 planes), then the two buffers of the
+  // adjoint memory variables
+  p.adj_bytes = align_up(((size_t)10 * p.plane + 2 * strips) * sizeof(float));
   p.par_bytes = align_up((size_t)3 * p.plane * sizeof(float));
   p.tab_bytes = align_up((size_t)(4 * p.nx + 4 * p.nz) * sizeof(float) + (size_t)p.nz * sizeof(int) +
                          (size_t)p.nslots * p.nx * sizeof(int));
@@ -455,7 +460,8 @@ Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsign
   d.sbuf = (long)(p.state_bytes / sizeof(float));
   d.vx = f[0], d.vz = f[1], d.sxx = f[2], d.szz = f[3], d.sxz = f[4];
   strips_at(st, d.psx, d.psz);
-  st = fields(p.off_adj, f);
+  st = fields(p.off_adj, f) + (size_t)5 * p.plane;  // buffer 1's planes, then the strips
+  d.abuf = (long)5 * p.plane;
   d.uxb = f[0], d.uzb = f[1], d.txxb = f[2], d.tzzb = f[3], d.txzb = f[4];
   strips_at(st, d.pbx[0], d.pbz[0]);
   strips_at(st + strips, d.pbx[1], d.pbz[1]);
@@ -513,8 +519,8 @@ size_t header_bytes(const std::vector<Plan2D>& plans, int first, int count) {
     tabs += plans[k].tab_bytes;
   }
   return align_up((size_t)count * sizeof(Shot2D)) + 2 * align_up((size_t)count * sizeof(int)) +
-         align_up(tiles * sizeof(int)) + 2 * align_up(sched_capacity(tiles) * sizeof(int)) +
-         align_up(stiles * sizeof(int)) + align_up(sched_capacity(stiles) * sizeof(int)) + tabs;
+         align_up(tiles * sizeof(int)) + align_up(sched_capacity(tiles) * sizeof(int)) +
+         align_up(stiles * sizeof(int)) + 2 * align_up(sched_capacity(stiles) * sizeof(int)) + tabs;
 }
 
 size_t wave_bytes(const std::vector<Plan2D>& plans, int first, int count) {
@@ -569,11 +575,11 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   const size_t off_first = off_desc + align_up((size_t)count * sizeof(Shot2D));
   const size_t off_tshot = off_first + align_up((size_t)count * sizeof(int));
   const size_t off_sched = off_tshot + align_up((size_t)ntiles * sizeof(int));
-  const size_t off_sched2 = off_sched + align_up(sched_capacity(ntiles) * sizeof(int));
-  const size_t off_sfirst = off_sched2 + align_up(sched_capacity(ntiles) * sizeof(int));
+  const size_t off_sfirst = off_sched + align_up(sched_capacity(ntiles) * sizeof(int));
   const size_t off_stshot = off_sfirst + align_up((size_t)count * sizeof(int));
   const size_t off_ssched = off_stshot + align_up((size_t)nstiles * sizeof(int));
-  size_t off_tab = off_ssched + align_up(sched_capacity(nstiles) * sizeof(int));
+  const size_t off_asched = off_ssched + align_up(sched_capacity(nstiles) * sizeof(int));
+  size_t off_tab = off_asched + align_up(sched_capacity(nstiles) * sizeof(int));
   const size_t hdr = header_bytes(plans, first, count);
   std::vector<unsigned char> blob(hdr, 0);
   int* tfirst = reinterpret_cast<int*>(blob.data() + off_first);
@@ -599,42 +605,43 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     region += p.total;
   }
   std::memcpy(blob.data() + off_desc, wv.descs.data(), (size_t)count * sizeof(Shot2D));
-  // XCD schedules: cut the tile list into NUM_XCD contiguous runs of equal weighted cost,
-  // for the forward kernels (tiles with a CPML node) and the adjoint kernels (tiles within
-  // two nodes of a strip, which stage corrected operands)
-  std::vector<int> wfwd(ntiles), wadj(ntiles);
+  // XCD schedules: cut each tile list into NUM_XCD contiguous runs of equal weighted cost.
+  // The 4-row tiles serve the pointwise kernels (staging, chain rule, gradient output).
+  std::vector<int> wfwd(ntiles);
   for (int k = 0, q = 0; k < count; ++k) {
     const Plan2D& p = wv.plans[k];
     const int ntx = (p.nx + BX - 1) / BX;
     for (int l = 0; l < p.ntiles; ++l, ++q) {
       const int i0 = (l / ntx) * BZ, j0 = (l % ntx) * BX;
-      auto near = [&](int pad) {
-        return p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
-                           (i0 + BZ - 1 + pad >= p.nz - p.P));
-      };
-      wfwd[q] = near(0) ? FWD_W_PML : FWD_W_INT;
-      wadj[q] = near(2) ? ADJ_W_PML : ADJ_W_INT;
+      const bool pml = p.P > 0 && ((j0 < p.P) || (j0 + BX - 1 >= p.nx - p.P) || (i0 < p.P) ||
+                                   (i0 + BZ - 1 >= p.nz - p.P));
+      wfwd[q] = pml ? FWD_W_PML : FWD_W_INT;
     }
   }
-  // the fused forward step's tiles (TSTEP rows; CPML path within two nodes of a strip)
-  std::vector<int> wstep(nstiles);
+  // the fused steps' tiles (TSTEP rows): CPML path of the forward step within two nodes of
+  // a strip, of the transposed step within four
+  std::vector<int> wstep(nstiles), wastep(nstiles);
   for (int k = 0, q = 0; k < count; ++k) {
     const Plan2D& p = wv.plans[k];
     const int ntx = (p.nx + BX - 1) / BX;
     for (int l = 0; l < p.nstep_tiles; ++l, ++q) {
-      const int i0 = (l / ntx) * TSTEP, j0 = (l % ntx) * BX, pad = 2;
-      const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
-                                   (i0 + TSTEP - 1 + pad >= p.nz - p.P));
-      wstep[q] = pml ? FWD_W_PML : FWD_W_INT;
+      const int i0 = (l / ntx) * TSTEP, j0 = (l % ntx) * BX;
+      auto near = [&](int pad) {
+        return p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
+                           (i0 + TSTEP - 1 + pad >= p.nz - p.P));
+      };
+      wstep[q] = near(2) ? FWD_W_PML : FWD_W_INT;
+      wastep[q] = near(4) ? ADJ_W_PML : ADJ_W_INT;
     }
   }
-  int nsched[3];
+  int nsched[4];
   efwi_status rc = build_sched(wfwd, reinterpret_cast<int*>(blob.data() + off_sched), nsched[0]);
-  if (rc != EFWI_OK) return rc;
-  rc = build_sched(wadj, reinterpret_cast<int*>(blob.data() + off_sched2), nsched[1]);
   if (rc != EFWI_OK) return rc;
   rc = build_sched(wstep, reinterpret_cast<int*>(blob.data() + off_ssched), nsched[2]);
   if (rc != EFWI_OK) return rc;
+  rc = build_sched(wastep, reinterpret_cast<int*>(blob.data() + off_asched), nsched[3]);
+  if (rc != EFWI_OK) return rc;
+  wv.batch.adj_step = Sched{reinterpret_cast<const int*>(ws + off_asched), nsched[3]};
   wv.batch.step_tile_first = reinterpret_cast<const int*>(ws + off_sfirst);
   wv.batch.step_tile_shot = reinterpret_cast<const int*>(ws + off_stshot);
   wv.batch.step = Sched{reinterpret_cast<const int*>(ws + off_ssched), nsched[2]};
@@ -643,7 +650,6 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   wv.batch.tile_first = reinterpret_cast<const int*>(ws + off_first);
   wv.batch.tile_shot = reinterpret_cast<const int*>(ws + off_tshot);
   wv.batch.fwd = Sched{reinterpret_cast<const int*>(ws + off_sched), nsched[0]};
-  wv.batch.adj = Sched{reinterpret_cast<const int*>(ws + off_sched2), nsched[1]};
   wv.batch.ns = count;
   wv.batch.ntiles = ntiles;
   // zero what must start at zero
@@ -716,8 +722,7 @@ efwi_status run_reverse(Wave& wv, unsigned char* ws, hipStream_t st) {
     // the checkpoint interval.
     for (int n = n1 - 1; n >= n0; --n) {
       const bool first = (n == wv.nt - 1) || ((n + 1) % FLUSH_STEPS == 0);
-      HIP_TRY(TIMED(KK_ADJ_VEL, st, launch_adj_vel(wv.batch, n, n - n0, true, first, false, st)));
-      HIP_TRY(TIMED(KK_ADJ_STR, st, launch_adj_str(wv.batch, n, n - n0, true, first, st)));
+      HIP_TRY(TIMED(KK_ADJ_STEP, st, launch_adj_step(wv.batch, n, n - n0, true, first, false, st)));
       if (n % FLUSH_STEPS == 0) HIP_TRY(TIMED(KK_CHAIN, st, launch_chain_flush(wv.batch, st)));
     }
   }
@@ -1326,8 +1331,7 @@ efwi_status efwi_model_adjoint(const efwi_grid* grid, const efwi_shot* shot, con
   const Plan2D& p = wv.plans[0];
   HIP_TRY(launch_residual_cumsum(wv.descs[0], r, reinterpret_cast<float*>(w + wv.regions[0] + p.off_ebar), st));
   for (int n = p.nt - 1; n >= 0; --n) {
-    HIP_TRY(TIMED(KK_ADJ_VEL, st, launch_adj_vel(wv.batch, n, 0, false, false, true, st)));
-    HIP_TRY(TIMED(KK_ADJ_STR, st, launch_adj_str(wv.batch, n, 0, false, false, st)));
+    HIP_TRY(TIMED(KK_ADJ_STEP, st, launch_adj_step(wv.batch, n, 0, false, false, true, st)));
   }
   return EFWI_OK;
 }

@@ -59,6 +59,9 @@ struct Shot2D {
   // adjoint state in scaled variables: u_bar = b v_bar at the velocity nodes and
   // t_bar = C sigma_bar at the stress nodes (t_xx = (l+2m) s_xx + l s_zz, t_zz = l s_xx +
   // (l+2m) s_zz, t_xz = mu_xz s_xz), an invertible change of variables for Vs > 0
+  // (double-buffered by step parity like the forward state: element p + abuf is the same
+  // element of buffer 1)
+  long abuf;
   gfloat *uxb, *uzb, *txxb, *tzzb, *txzb;
   gfloat* pbx[2][4];             // double-buffered x-strip adjoint memory variables
   gfloat* pbz[2][4];             // double-buffered z-strip adjoint memory variables
@@ -99,14 +102,13 @@ struct Sched {
 };
 struct Batch2D {
   const Shot2D* shots;
-  const int* tile_shot;
+  const int* tile_shot;      // 4-row tiles (pointwise kernels)
   const int* tile_first;
-  Sched fwd, adj;
+  Sched fwd;
   int ns, ntiles;
-  // the same for the fused forward step's tiles of TSTEP rows
-  const int* step_tile_shot;
+  const int* step_tile_shot; // TSTEP-row tiles of the fused forward and transposed steps
   const int* step_tile_first;
-  Sched step;
+  Sched step, adj_step;
   int nstep_tiles;
 };
 
@@ -141,8 +143,8 @@ __host__ __device__ inline int strip_index(int k, int n, int P) {
 hipError_t launch_stage2d(const Batch2D& b, hipStream_t st);
 // Fused forward step n: reads state buffer n & 1, writes buffer (n + 1) & 1.
 hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hipStream_t st);
-hipError_t launch_adj_vel(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st);
-hipError_t launch_adj_str(const Batch2D& b, int n, int k, bool grad, bool first, hipStream_t st);
+// Fused transposed step n: reads adjoint buffer (n + 1) & 1, writes buffer n & 1.
+hipError_t launch_adj_step(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st);
 hipError_t launch_chain_flush(const Batch2D& b, hipStream_t st);
 hipError_t launch_write_gradient(const Batch2D& b, hipStream_t st);
 // Per-shot (host copy of the shot's descriptor).

@@ -557,385 +557,440 @@ __device__ __forceinline__ int pair_count(int k, int m, int n) {
   return (k == m) + (min(k + 1, n - 1) == m);
 }
 
-// ------------------------------------------------------------------------------------
-template <bool PML>
-struct AdjCtx {
-  const Shot2D& s;
-  int rd;                   // which buffer of the adjoint memory variables holds step n+1
-};
-
-// Corrected transposed operands at node (ii, jj); `a` is the profile coefficient for the
-// node's coordinate along the derivative's axis and `psi` the matching adjoint memory
-// variable, used only inside the CPML strips.
-template <bool PML>
-__device__ __forceinline__ float corr_x(const AdjCtx<PML>& c, float v, int ii, int jj, const gfloat* aprof, int slot) {
-  const Shot2D& s = c.s;
-  if (PML && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-    const int sx = strip_index(jj, s.nx, s.P);
-    if (sx >= 0) v += aprof[jj] * (s.pbx[c.rd][slot][(long)ii * 2 * s.P + sx] + v);
-  }
-  return v;
-}
-template <bool PML>
-__device__ __forceinline__ float corr_z(const AdjCtx<PML>& c, float v, int ii, int jj, const gfloat* aprof, int slot) {
-  const Shot2D& s = c.s;
-  if (PML && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx) {
-    const int sz = strip_index(ii, s.nz, s.P);
-    if (sz >= 0) v += aprof[ii] * (s.pbz[c.rd][slot][(long)sz * s.nx + jj] + v);
-  }
-  return v;
-}
-
-// p_bar for pxx (x int, X_XX), pzz (z int, Z_ZZ), pzx (z half, Z_XZ), pxz (x half, X_XZ)
-template <bool PML>
-__device__ __forceinline__ float pb_xx(const AdjCtx<PML>& c, int ii, int jj) {
-  return corr_x(c, c.s.dt * c.s.txxb[(long)ii * c.s.ld + jj], ii, jj, axi(c.s), X_XX);
-}
-template <bool PML>
-__device__ __forceinline__ float pb_zz(const AdjCtx<PML>& c, int ii, int jj) {
-  return corr_z(c, c.s.dt * c.s.tzzb[(long)ii * c.s.ld + jj], ii, jj, azi(c.s), Z_ZZ);
-}
-template <bool PML>
-__device__ __forceinline__ float pb_zx(const AdjCtx<PML>& c, int ii, int jj) {
-  return corr_z(c, c.s.dt * c.s.txzb[(long)ii * c.s.ld + jj], ii, jj, azh(c.s), Z_XZ);
-}
-template <bool PML>
-__device__ __forceinline__ float pb_xz(const AdjCtx<PML>& c, int ii, int jj) {
-  return corr_x(c, c.s.dt * c.s.txzb[(long)ii * c.s.ld + jj], ii, jj, axh(c.s), X_XZ);
-}
-// q_bar for qx with D+x sxx (x half, X_VXX), with D-z sxz (z int, Z_VXZ);
-// for qz with D-x sxz (x int, X_VZX), with D+z szz (z half, Z_VZZ)
-template <bool PML>
-__device__ __forceinline__ float qb_xa(const AdjCtx<PML>& c, int ii, int jj) {
-  return corr_x(c, c.s.dt * c.s.uxb[(long)ii * c.s.ld + jj], ii, jj, axh(c.s), X_VXX);
-}
-template <bool PML>
-__device__ __forceinline__ float qb_xb(const AdjCtx<PML>& c, int ii, int jj) {
-  return corr_z(c, c.s.dt * c.s.uxb[(long)ii * c.s.ld + jj], ii, jj, azi(c.s), Z_VXZ);
-}
-template <bool PML>
-__device__ __forceinline__ float qb_za(const AdjCtx<PML>& c, int ii, int jj) {
-  return corr_x(c, c.s.dt * c.s.uzb[(long)ii * c.s.ld + jj], ii, jj, axi(c.s), X_VZX);
-}
-template <bool PML>
-__device__ __forceinline__ float qb_zb(const AdjCtx<PML>& c, int ii, int jj) {
-  return corr_z(c, c.s.dt * c.s.uzb[(long)ii * c.s.ld + jj], ii, jj, azh(c.s), Z_VZZ);
-}
-
 __device__ __forceinline__ float ebar_at(const Shot2D& s, int slot, int jc, int n) {
   if (jc < 0 || jc >= s.nx) return 0.0f;
   const int c = s.rowch[(long)slot * s.nx + jc];
   return c >= 0 ? s.ebar[(long)n * s.nch + c] : 0.0f;
 }
 
-// CPML tiles stage the corrected transposed operands of the tile and its halo in LDS, so
-// each node's correction (strip test, profile, adjoint memory variable) is computed once
-// instead of once per neighbour that reads it. Four operands, each over the tile rows or
-// columns it is differentiated along: x-operands cover columns [j0 + lo, j0 + 64 + hi] of
-// the 4 tile rows, z-operands rows [i0 + lo, i0 + 4 + hi] of the 64 tile columns.
-constexpr int LX = BX + 3;      // 67 columns (x-operands)
-constexpr int LZ = BZ + 3;      // 7 rows (z-operands)
-constexpr int LDS_OPS = 2 * BZ * LX + 2 * LZ * BX;
-
-struct StageArea {
-  float* x0;  // [BZ][LX]
-  float* x1;  // [BZ][LX]
-  float* z0;  // [LZ][BX]
-  float* z1;  // [LZ][BX]
+// ------------------------------------------------------------------------------------
+// Fused transposed step n (reverse time) on the forward step's tiles of TZ rows x 64
+// columns: the transpose of the stress half step and then of the velocity half step, in
+// the scaled variables above. The adjoint fields are double-buffered by step parity like
+// the forward state: buffer (n + 1) & 1 holds t_bar, u_bar of step n + 1, the step writes
+// buffer n & 1. Per tile:
+//   1. the corrected transposed stress operands p_bar (dt t_bar, plus the CPML transpose
+//      inside the strips) of the tile and a 4-node halo are staged in LDS;
+//   2. u_bar += b (-D^T p_bar) (+ the DAS transpose) on the tile and a 2-node halo, kept in
+//      LDS with the corrected transposed velocity operands q_bar;
+//   3. t_bar += C (-D^T q_bar) on the tile, the memory variables, and the imaging sums.
+// ------------------------------------------------------------------------------------
+template <int TZ>
+struct AdjTile {
+  static constexpr int SR = TZ + 8, SC = BX + 8;  // p_bar: rows i0-4 .. i0+TZ+3, columns j0-4 .. j0+67
+  static constexpr int VR = TZ + 4, VC = BX + 4;  // u_bar, q_bar: rows i0-2 .. i0+TZ+1, columns j0-2 .. j0+65
+  static constexpr int NP = SR * SC, NU = VR * VC;
+  static constexpr int LDS_FLOATS = 4 * NP + 6 * NU;
 };
 
-// One staged operand: dt * f at the nodes of its patch, plus, inside the CPML strips of its
-// axis, a * (psi + dt * f) with the profile coefficient a of the node's coordinate and the
-// adjoint memory variable psi. x-operands cover (i0 + r, j0 + c + lo), r < BZ, c < LX;
-// z-operands (i0 + r + lo, j0 + c), r < LZ, c < BX. Nodes outside the grid hold zero.
-struct StagedOp {
-  const gfloat* f;
-  const gfloat* a;
-  const gfloat* psi;
-  int lo;
+struct AdjPtrs {
+  const gfloat *txx, *tzz, *txz, *ux, *uz;   // adjoint buffer (n + 1) & 1, padded plane origins
+  gfloat *wtxx, *wtzz, *wtxz, *wux, *wuz;    // buffer n & 1
+  const gfloat *lam, *mu, *rho;              // staged parameters, padded plane origins
+  const gfloat *rpx[4], *rpz[4];             // adjoint memory variables of step n + 1
+  gfloat *wpx[4], *wpz[4];                   // and of step n
+  const gfloat *axi, *bxi, *axh, *bxh, *azi, *bzi, *azh, *bzh;
+  const gfloat* seg;                         // history slot of step n (imaging)
+  gfloat* acc;
+  int ld, nx, nz, P2;
 };
 
-// Every thread takes at most two nodes of each operand: all loads are issued before the
-// first LDS write, so a tile costs one memory round trip.
-template <bool XAXIS>
-__device__ __forceinline__ void stage_load(const Shot2D& s, int i0, int j0, const StagedOp& op, int tid, float* v) {
-  constexpr int N = XAXIS ? BZ * LX : LZ * BX;
-  constexpr int W = XAXIS ? LX : BX;
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int e = tid + k * BX * BZ;
-    const int r = e / W, c = e % W;
-    const int ii = i0 + r + (XAXIS ? 0 : op.lo), jj = j0 + c + (XAXIS ? op.lo : 0);
-    // clamped indices keep every load valid and unconditional (no waits inside branches)
-    const bool in = e < N && ii >= 0 && ii < s.nz && jj >= 0 && jj < s.nx;
-    const int ic = min(max(ii, 0), s.nz - 1), jc = min(max(jj, 0), s.nx - 1);
-    const int sidx = XAXIS ? strip_index(jc, s.nx, s.P) : strip_index(ic, s.nz, s.P);
-    const int sc = max(sidx, 0);
-    const float f = op.f[(long)ic * s.ld + jc];
-    const float ps = XAXIS ? op.psi[(long)ic * 2 * s.P + sc] : op.psi[(long)sc * s.nx + jc];
-    const float ac = op.a[XAXIS ? jc : ic];
-    // 0/1 masks instead of branches keep the loads unconditional (the compiler would sink
-    // loads used on one side of a select into a branch and wait there)
-    const float m_in = in ? 1.0f : 0.0f, m_strip = sidx >= 0 ? 1.0f : 0.0f;
-    const float val = s.dt * f;
-    v[k] = m_in * (val + (m_strip * ac) * (ps + val));
+__device__ __forceinline__ AdjPtrs adj_ptrs(const Shot2D& s, int n, int kseg) {
+  AdjPtrs p;
+  const long org = (long)HALO * s.ld + XOFF;
+  const int prd = (n + 1) & 1, pwr = n & 1;
+  const long rd = (long)prd * s.abuf, wr = (long)pwr * s.abuf;
+  p.txx = s.txxb - org + rd;
+  p.tzz = s.tzzb - org + rd;
+  p.txz = s.txzb - org + rd;
+  p.ux = s.uxb - org + rd;
+  p.uz = s.uzb - org + rd;
+  p.wtxx = s.txxb - org + wr;
+  p.wtzz = s.tzzb - org + wr;
+  p.wtxz = s.txzb - org + wr;
+  p.wux = s.uxb - org + wr;
+  p.wuz = s.uzb - org + wr;
+  p.lam = s.lam - org;
+  p.mu = s.mu - org;
+  p.rho = s.rho - org;
+  for (int k = 0; k < 4; ++k) {
+    p.rpx[k] = s.pbx[prd][k];
+    p.rpz[k] = s.pbz[prd][k];
+    p.wpx[k] = s.pbx[pwr][k];
+    p.wpz[k] = s.pbz[pwr][k];
   }
-}
-template <bool XAXIS>
-__device__ __forceinline__ void stage_store(float* dst, int tid, const float* v) {
-  constexpr int N = XAXIS ? BZ * LX : LZ * BX;
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int e = tid + k * BX * BZ;
-    if (e < N) dst[e] = v[k];
-  }
-}
-// Stage the two x-operands and the two z-operands of a CPML tile.
-__device__ __forceinline__ void stage_operands(const Shot2D& s, int i0, int j0, StageArea a, const StagedOp& x0,
-                                               const StagedOp& x1, const StagedOp& z0, const StagedOp& z1) {
-  static_assert(BZ * LX <= 2 * BX * BZ && LZ * BX <= 2 * BX * BZ, "two nodes per thread and operand");
-  const int tid = threadIdx.y * BX + threadIdx.x;
-  float v0[2], v1[2], v2[2], v3[2];
-  stage_load<true>(s, i0, j0, x0, tid, v0);
-  stage_load<true>(s, i0, j0, x1, tid, v1);
-  stage_load<false>(s, i0, j0, z0, tid, v2);
-  stage_load<false>(s, i0, j0, z1, tid, v3);
-  stage_store<true>(a.x0, tid, v0);
-  stage_store<true>(a.x1, tid, v1);
-  stage_store<false>(a.z0, tid, v2);
-  stage_store<false>(a.z1, tid, v3);
+  p.axi = axi(s), p.bxi = bxi(s), p.axh = axh(s), p.bxh = bxh(s);
+  p.azi = azi(s), p.bzi = bzi(s), p.azh = azh(s), p.bzh = bzh(s);
+  p.seg = s.seg ? s.seg + (size_t)kseg * NSEG_FIELDS * s.cells : nullptr;
+  p.acc = s.acc;
+  p.ld = s.ld, p.nx = s.nx, p.nz = s.nz, p.P2 = 2 * s.P;
+  return p;
 }
 
-// Transposed stress sub-step (first at reverse step n): t_bar -> u_bar.
-// ux, uz, wz, wx are the four transposed differences: D+x p_bar_xx, D-z p_bar_zx,
-// D+z p_bar_zz and D-x p_bar_xz at the cell's velocity nodes (without 1/h).
-template <bool GRAD, bool SRCADJ, bool PML>
-__device__ __forceinline__ void adj_vel_finish(const Shot2D& s, int i, int j, int n, const gfloat* seg, bool first,
-                                               float ux, float uz, float wz, float wx) {
-  const long ld = s.ld;
-  const long o = (long)i * ld + j;
-  const int rd = (n + 1) & 1, wr = n & 1;
-  // ---- loads ----
-  const int slot = s.row_slot[i];  // DAS row slot (depends on the wavefront's row only)
-  const float txx = s.txxb[o], tzz = s.tzzb[o], txz = s.txzb[o];
-  const float u0x = s.uxb[o], u0z = s.uzb[o], bx = bx_of(s, o), bz = bz_of(s, o);
-  int sx = -1, sz = -1;
-  long qx_ = 0, qz_ = 0;
-  float r1 = 0.0f, r2 = 0.0f, r3 = 0.0f, r4 = 0.0f;
-  if (PML) {  // owned adjoint memory variables of the stress-side derivatives
-    sx = strip_index(j, s.nx, s.P);
-    sz = strip_index(i, s.nz, s.P);
-    qx_ = (long)i * 2 * s.P + max(sx, 0);
-    qz_ = (long)max(sz, 0) * s.nx + j;
-    r1 = bxi(s)[j] * (s.pbx[rd][X_XX][qx_] + s.dt * txx);
-    r2 = bxh(s)[j] * (s.pbx[rd][X_XZ][qx_] + s.dt * txz);
-    r3 = bzi(s)[i] * (s.pbz[rd][Z_ZZ][qz_] + s.dt * tzz);
-    r4 = bzh(s)[i] * (s.pbz[rd][Z_XZ][qz_] + s.dt * txz);
+__device__ __forceinline__ unsigned pofs(const AdjPtrs& p, int i, int j) {
+  return (unsigned)((i + HALO) * p.ld + XOFF + j);
+}
+
+// Inputs of one u_bar node (loads only).
+struct UbLoads {
+  int slot;                  // DAS slot of the node's row (-1: none or outside the grid)
+  float ux, uz, r0, rx, rz;
+  float q1, q2, q3, q4;      // velocity-side adjoint memory variables of step n + 1 (CPML)
+};
+
+template <bool PML>
+__device__ __forceinline__ UbLoads ub_loads(const AdjPtrs& p, const Shot2D& s, int gi, int gj) {
+  UbLoads L;
+  const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
+  const unsigned o = pofs(p, ic, jc);
+  const bool in = gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx;
+  const int slot = s.row_slot[ic];
+  L.slot = in ? slot : -1;
+  L.ux = G(p.ux, o);
+  L.uz = G(p.uz, o);
+  L.r0 = G(p.rho, o);
+  L.rx = G(p.rho, o + 1);
+  L.rz = G(p.rho, o + p.ld);
+  L.q1 = L.q2 = L.q3 = L.q4 = 0.0f;
+  if (PML) {
+    const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
+    const unsigned qx = (unsigned)(ic * p.P2 + sx), qz = (unsigned)(sz * p.nx + jc);
+    L.q1 = G(p.rpx[X_VXX], qx);
+    L.q2 = G(p.rpx[X_VZX], qx);
+    L.q3 = G(p.rpz[Z_VXZ], qz);
+    L.q4 = G(p.rpz[Z_VZZ], qz);
   }
-  long cc = 0;
-  float a0 = 0.0f, a1 = 0.0f, e = 0.0f, h0 = 0.0f;
+  return L;
+}
+
+// Inputs of one t_bar node (loads only).
+struct TbLoads {
+  float txx, tzz, txz, lam, mu, mu_x, mu_z, mu_xz;
+  float r1, r2, r3, r4;      // stress-side adjoint memory variables of step n + 1 (CPML)
+  float h0, h1, e_nb, h3m, h3, h4m, h4, a0, a1, a2;   // imaging inputs
+};
+
+// `edges`: the node may sit on the grid's first or clamped last row or column (tiles that
+// touch a CPML strip, or any tile without CPML); elsewhere every count below is 1.
+template <bool GRAD, bool PML>
+__device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, int gi, int gj, bool first,
+                                            bool edges) {
+  TbLoads L;
+  const int ic = min(gi, p.nz - 1), jc = min(gj, p.nx - 1);
+  const unsigned o = pofs(p, ic, jc);
+  L.txx = G(p.txx, o);
+  L.tzz = G(p.tzz, o);
+  L.txz = G(p.txz, o);
+  L.lam = G(p.lam, o);
+  L.mu = G(p.mu, o);
+  L.mu_x = G(p.mu, o + 1);
+  L.mu_z = G(p.mu, o + p.ld);
+  L.mu_xz = G(p.mu, o + p.ld + 1);
+  L.r1 = L.r2 = L.r3 = L.r4 = 0.0f;
+  if (PML) {
+    const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
+    const unsigned qx = (unsigned)(ic * p.P2 + sx), qz = (unsigned)(sz * p.nx + jc);
+    L.r1 = G(p.rpx[X_XX], qx);
+    L.r2 = G(p.rpx[X_XZ], qx);
+    L.r3 = G(p.rpz[Z_ZZ], qz);
+    L.r4 = G(p.rpz[Z_XZ], qz);
+  }
+  L.h0 = L.h1 = L.e_nb = L.h3m = L.h3 = L.h4m = L.h4 = L.a0 = L.a1 = L.a2 = 0.0f;
   if (GRAD) {
-    cc = (long)i * s.cp + j;
-    const gfloat* h2 = seg + 2 * s.cells;
-    h0 = seg[cc];
-    e = (txx - tzz) * seg[s.cells + cc];
-    // shear nodes (a, b), a in {i-1, i}, b in {j-1, j}; indices clamped so every load is
-    // valid and issued up front, with weight 0 where the node does not use mu(i, j)
-    for (int a = i - 1; a <= i; ++a) {
-      for (int b = j - 1; b <= j; ++b) {
-        const float c = (float)corner_count(a, b, i, j, s.nz, s.nx);
-        const int aa = max(a, 0), bb = max(b, 0);
-        e += c * s.txzb[(long)aa * ld + bb] * h2[(long)aa * s.cp + bb];
+    const unsigned cc = (unsigned)(ic * s.cp + jc), cells = (unsigned)s.cells;
+    L.h0 = G(p.seg, cc);
+    L.h1 = G(p.seg, cells + cc);
+    // shear nodes (a, b), a in {i-1, i}, b in {j-1, j}: t_bar_xz (step n + 1) times the
+    // stored (pzx + pxz) mu_xz / 4, weighted by how often mu_xz(a, b) uses mu(i, j)
+    float e = 0.0f;
+    for (int a = ic - 1; a <= ic; ++a) {
+      for (int b = jc - 1; b <= jc; ++b) {
+        const float c = edges ? (float)corner_count(a, b, ic, jc, p.nz, p.nx) : 1.0f;
+        const int aa = edges ? max(a, 0) : a, bb = edges ? max(b, 0) : b;
+        e += c * G(p.txz, pofs(p, aa, bb)) * G(p.seg, 2 * cells + (unsigned)(aa * s.cp + bb));
       }
     }
+    L.e_nb = e;
+    const int jm = max(jc - 1, 0), im = max(ic - 1, 0);
+    L.h3m = G(p.seg, 3 * cells + (unsigned)(ic * s.cp + jm));
+    L.h3 = G(p.seg, 3 * cells + cc);
+    L.h4m = G(p.seg, 4 * cells + (unsigned)(im * s.cp + jc));
+    L.h4 = G(p.seg, 4 * cells + cc);
     if (!first) {
-      a0 = s.acc[cc];
-      a1 = s.acc[s.cells + cc];
+      L.a0 = G(p.acc, cc);
+      L.a1 = G(p.acc, cells + cc);
+      L.a2 = G(p.acc, 2 * cells + cc);
     }
   }
-  // DAS transpose: the channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1),
-  // jc+1 (c2) and jc-2 (-c2) of its row
-  float inj = 0.0f;
-  if (slot >= 0)
-    inj = K1 * (ebar_at(s, slot, j, n) - ebar_at(s, slot, j + 1, n)) +
-          K2 * (ebar_at(s, slot, j - 1, n) - ebar_at(s, slot, j + 2, n));
-  float sb0 = 0.0f, sb1 = 0.0f, sb2 = 0.0f;
-  const bool at_src = SRCADJ && i == s.si && j == s.sj;
-  if (at_src) {
-    // sigma_bar at the source from t_bar: invert the 2x2 normal block and the shear moduli
-    const float lam = s.lam[o], l2m = l2m_of(s, o);
-    const float det = (l2m - lam) * (l2m + lam);
-    sb0 = (l2m * txx - lam * tzz) / det;
-    sb1 = (l2m * tzz - lam * txx) / det;
-    auto sxz_at = [&](long oo) {
-      const float m = muxz_of(s, oo);
-      return m > 0.0f ? s.txzb[oo] / m : 0.0f;
-    };
-    sb2 = sxz_at(o) + sxz_at(o - 1) + sxz_at(o - ld) + sxz_at(o - ld - 1);
-  }
-  // ---- arithmetic ----
-  // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx); v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
-  const float gx = -(ux * s.rdx + uz * s.rdz) + s.dt * s.rdx * inj;
-  const float gz = -(wz * s.rdz + wx * s.rdx);
-  // ---- stores ----
-  if (PML) {
-    if (sx >= 0) {
-      s.pbx[wr][X_XX][qx_] = r1;
-      s.pbx[wr][X_XZ][qx_] = r2;
+  return L;
+}
+
+template <int TZ, bool GRAD, bool SRCADJ, bool PML>
+__device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, int n, int kseg, bool first,
+                                              float* lds) {
+  using T = AdjTile<TZ>;
+  constexpr int SR = T::SR, SC = T::SC, VR = T::VR, VC = T::VC, NP = T::NP, NU = T::NU;
+  constexpr int NT = BX * BZ;
+  constexpr int NV = VR / BZ, NSR = TZ / BZ;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(1))) char gchar;
+  const AdjPtrs p = adj_ptrs(s, n, kseg);
+  const float dt = s.dt;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+  const int tyu = __builtin_amdgcn_readfirstlane(ty);
+  // LDS: p_bar operands OX0 = p_xx, OX1 = p_xz (x-differentiated), OZ0 = p_zx, OZ1 = p_zz
+  // (z-differentiated); in interior tiles OX1 and OZ0 are the same array (no correction)
+  float* OX0 = lds;
+  float* OZ1 = lds + NP;
+  float* OX1 = lds + 2 * NP;
+  float* OZ0 = PML ? lds + 3 * NP : OX1;
+  float* UX = lds + 4 * NP;
+  float* UZ = UX + NU;
+  float* QXA = UZ + NU;      // q_bar operands (CPML tiles): x-differentiated from u_x, u_z,
+  float* QZA = QXA + NU;     // z-differentiated from u_x, u_z
+  float* QXB = QZA + NU;
+  float* QZB = QXB + NU;
+  const int hv = min(tid >> 2, VR - 1), hc = tid & 3;
+  const int hcol = hc < 2 ? hc : VC - 4 + hc;     // LDS u column 0, 1, 66, 67
+
+  // ---- loads of the velocity and stress nodes, issued first ----
+  UbLoads UL[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) UL[k] = ub_loads<PML>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
+  const UbLoads UH = ub_loads<PML>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
+
+  // ---- 1. stage p_bar ----
+  if (!PML) {
+    constexpr int Q = SC / 4, NQ = 3 * SR * Q, PER = (NQ + NT - 1) / NT;
+    constexpr int DC = NT % Q, DR = (NT / Q) % SR;
+    static_assert(NT / (SR * Q) == 0, "one step of NT float4s stays inside a field's staging area");
+    int sf[PER], sr_[PER], sc4[PER];
+    {
+      int f = tid / (SR * Q), rem = tid - f * (SR * Q);
+      int r = rem / Q, c4 = rem - r * Q;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        sf[k] = f, sr_[k] = r, sc4[k] = c4;
+        c4 += DC;
+        r += DR;
+        if (c4 >= Q) c4 -= Q, ++r;
+        if (r >= SR) r -= SR, ++f;
+      }
     }
-    if (sz >= 0) {
-      s.pbz[wr][Z_ZZ][qz_] = r3;
-      s.pbz[wr][Z_XZ][qz_] = r4;
+    f4 sv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int f = min(sf[k], 2);
+      const int ic = min(max(i0 - 4 + sr_[k], 0), p.nz - 1);
+      const gfloat* src = f == 0 ? p.txx : f == 1 ? p.tzz : p.txz;
+      sv[k] = *(const __attribute__((address_space(1))) f4*)((gchar*)src + pofs(p, ic, j0 - 4 + 4 * sc4[k]) * 4u);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (sf[k] < 3) {
+        const int f = sf[k], r = sr_[k], c4 = sc4[k];
+        const int gi = i0 - 4 + r, gj = j0 - 4 + 4 * c4;
+        const bool row_in = gi >= 0 && gi < p.nz;
+        f4 v;
+        v.x = (row_in && gj + 0 >= 0 && gj + 0 < p.nx) ? dt * sv[k].x : 0.0f;
+        v.y = (row_in && gj + 1 >= 0 && gj + 1 < p.nx) ? dt * sv[k].y : 0.0f;
+        v.z = (row_in && gj + 2 >= 0 && gj + 2 < p.nx) ? dt * sv[k].z : 0.0f;
+        v.w = (row_in && gj + 3 >= 0 && gj + 3 < p.nx) ? dt * sv[k].w : 0.0f;
+        *(f4*)(lds + f * NP + r * SC + 4 * c4) = v;
+      }
+    }
+  } else {
+    // CPML tiles: four corrected operands, one after the other (a node's correction uses
+    // the memory variable and profile of the operand's own axis)
+    constexpr int PER = (NP + NT - 1) / NT;
+#pragma unroll
+    for (int op = 0; op < 4; ++op) {
+      const gfloat* f = op == 0 ? p.txx : op == 3 ? p.tzz : p.txz;
+      const bool xaxis = op < 2;
+      const gfloat* prof = op == 0 ? p.axi : op == 1 ? p.axh : op == 2 ? p.azh : p.azi;
+      const gfloat* psi = op == 0 ? p.rpx[X_XX] : op == 1 ? p.rpx[X_XZ] : op == 2 ? p.rpz[Z_XZ] : p.rpz[Z_ZZ];
+      float* dst = op == 0 ? OX0 : op == 1 ? OX1 : op == 2 ? OZ0 : OZ1;
+      float v[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = min(tid + k * NT, NP - 1);
+        const int r = e / SC, c = e - r * SC;
+        const int gi = i0 - 4 + r, gj = j0 - 4 + c;
+        const bool in = gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx;
+        const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
+        const int sidx = xaxis ? strip_index(jc, p.nx, s.P) : strip_index(ic, p.nz, s.P);
+        const int sc = max(sidx, 0);
+        const float val = dt * G(f, pofs(p, ic, jc));
+        const float ps = G(psi, xaxis ? (unsigned)(ic * p.P2 + sc) : (unsigned)(sc * p.nx + jc));
+        const float ac = G(prof, (unsigned)(xaxis ? jc : ic));
+        const float m_in = in ? 1.0f : 0.0f, m_strip = sidx >= 0 ? 1.0f : 0.0f;
+        v[k] = m_in * (val + (m_strip * ac) * (ps + val));
+      }
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * NT;
+        if (e < NP) dst[e] = v[k];
+      }
     }
   }
-  s.uxb[o] = u0x + bx * gx;
-  s.uzb[o] = u0z + bz * gz;
-  if (GRAD) {
-    s.acc[cc] = a0 + s.dt * (txx + tzz) * h0;
-    s.acc[s.cells + cc] = a1 + s.dt * e;
+  __syncthreads();
+
+  // ---- 2. u_bar on the tile and a 2-node halo ----
+  auto ubar = [&](int vr, int lcol, const UbLoads& L, bool owned) {
+    const int gi = i0 - 2 + vr, gj = j0 - 2 + lcol;
+    const int sr = vr + 2, sc = lcol + 2;   // LDS p_bar coordinates of the node
+    const float ux_d = K1 * (OX0[sr * SC + sc + 1] - OX0[sr * SC + sc]) +
+                       K2 * (OX0[sr * SC + sc + 2] - OX0[sr * SC + sc - 1]);
+    const float uz_d = K1 * (OZ0[sr * SC + sc] - OZ0[(sr - 1) * SC + sc]) +
+                       K2 * (OZ0[(sr + 1) * SC + sc] - OZ0[(sr - 2) * SC + sc]);
+    const float wz_d = K1 * (OZ1[(sr + 1) * SC + sc] - OZ1[sr * SC + sc]) +
+                       K2 * (OZ1[(sr + 2) * SC + sc] - OZ1[(sr - 1) * SC + sc]);
+    const float wx_d = K1 * (OX1[sr * SC + sc] - OX1[sr * SC + sc - 1]) +
+                       K2 * (OX1[sr * SC + sc + 1] - OX1[sr * SC + sc - 2]);
+    const bool in = gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx;
+    // DAS transpose: the channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1),
+    // jc+1 (c2) and jc-2 (-c2) of its row
+    float inj = 0.0f;
+    if (L.slot >= 0)
+      inj = K1 * (ebar_at(s, L.slot, gj, n) - ebar_at(s, L.slot, gj + 1, n)) +
+            K2 * (ebar_at(s, L.slot, gj - 1, n) - ebar_at(s, L.slot, gj + 2, n));
+    // v_bar_x += -(D+x p_bar_xx + D-z p_bar_zx); v_bar_z += -(D+z p_bar_zz + D-x p_bar_xz)
+    const float gx = -(ux_d * s.rdx + uz_d * s.rdz) + dt * s.rdx * inj;
+    const float gz = -(wz_d * s.rdz + wx_d * s.rdx);
+    const float bx = 2.0f * rcpf(L.r0 + L.rx), bz = 2.0f * rcpf(L.r0 + L.rz);
+    const float m = in ? 1.0f : 0.0f;
+    const float uxn = m * (L.ux + bx * gx), uzn = m * (L.uz + bz * gz);
+    UX[vr * VC + lcol] = uxn;
+    UZ[vr * VC + lcol] = uzn;
+    int sx = -1, sz = -1;
+    if (PML) {  // corrected q_bar operands: dt u (+ a (psi_bar + dt u) inside the strips)
+      const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
+      sx = strip_index(jc, p.nx, s.P);
+      sz = strip_index(ic, p.nz, s.P);
+      const float mx = sx >= 0 ? 1.0f : 0.0f, mz = sz >= 0 ? 1.0f : 0.0f;
+      const float dux = dt * uxn, duz = dt * uzn;
+      QXA[vr * VC + lcol] = m * (dux + (mx * G(p.axh, (unsigned)jc)) * (L.q1 + dux));
+      QZA[vr * VC + lcol] = m * (duz + (mx * G(p.axi, (unsigned)jc)) * (L.q2 + duz));
+      QXB[vr * VC + lcol] = m * (dux + (mz * G(p.azi, (unsigned)ic)) * (L.q3 + dux));
+      QZB[vr * VC + lcol] = m * (duz + (mz * G(p.azh, (unsigned)ic)) * (L.q4 + duz));
+    }
+    if (owned) {
+      const unsigned o = pofs(p, gi, gj);
+      G(p.wux, o) = uxn;
+      G(p.wuz, o) = uzn;
+      if (PML) {  // owned velocity-side adjoint memory variables
+        if (sx >= 0) {
+          const unsigned q = (unsigned)(gi * p.P2 + sx);
+          G(p.wpx[X_VXX], q) = G(p.bxh, (unsigned)gj) * (L.q1 + dt * uxn);
+          G(p.wpx[X_VZX], q) = G(p.bxi, (unsigned)gj) * (L.q2 + dt * uzn);
+        }
+        if (sz >= 0) {
+          const unsigned q = (unsigned)(sz * p.nx + gj);
+          G(p.wpz[Z_VXZ], q) = G(p.bzi, (unsigned)gi) * (L.q3 + dt * uxn);
+          G(p.wpz[Z_VZZ], q) = G(p.bzh, (unsigned)gi) * (L.q4 + dt * uzn);
+        }
+      }
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int vr = ty + k * BZ, gi = i0 - 2 + vr;
+    ubar(vr, tx + 2, UL[k], gi >= i0 && gi < i0 + TZ && gi < p.nz && j0 + tx < p.nx);
   }
-  if (at_src) {
-    s.src_bar[n] = -s.w * sb0;
-    s.src_bar[s.nt + n] = -s.w * sb1;
-    s.src_bar[2 * s.nt + n] = -0.25f * s.w * sb2;
+  if ((tid >> 2) < VR) ubar(hv, hcol, UH, false);
+  __syncthreads();
+
+  // ---- 3. t_bar, memory variables and imaging at the tile's normal nodes (their loads
+  //         issued here, after the velocity phase, to bound the live registers) ----
+  TbLoads TL[NSR];
+  const bool edges = PML || s.P == 0;
+#pragma unroll
+  for (int k = 0; k < NSR; ++k) TL[k] = tb_loads<GRAD, PML>(p, s, i0 + tyu + k * BZ, j0 + tx, first, edges);
+#pragma unroll
+  for (int k = 0; k < NSR; ++k) {
+    const int i = i0 + tyu + k * BZ, j = j0 + tx;
+    if (i >= p.nz || j >= p.nx) continue;
+    const TbLoads& L = TL[k];
+    const int vr = tyu + k * BZ + 2, vc = tx + 2;   // LDS u coordinates of the node
+    const int u0 = vr * VC + vc;
+    // q operands: interior tiles read dt u_bar directly
+    auto qxa = [&](int d) { return PML ? QXA[u0 + d] : dt * UX[u0 + d]; };
+    auto qxb = [&](int d) { return PML ? QXB[u0 + d] : dt * UX[u0 + d]; };
+    auto qza = [&](int d) { return PML ? QZA[u0 + d] : dt * UZ[u0 + d]; };
+    auto qzb = [&](int d) { return PML ? QZB[u0 + d] : dt * UZ[u0 + d]; };
+    const float txx_d = K1 * (qxa(0) - qxa(-1)) + K2 * (qxa(1) - qxa(-2));
+    const float tzz_d = K1 * (qzb(0) - qzb(-VC)) + K2 * (qzb(VC) - qzb(-2 * VC));
+    const float t1 = K1 * (qxb(VC) - qxb(0)) + K2 * (qxb(2 * VC) - qxb(-VC));
+    const float t2 = K1 * (qza(1) - qza(0)) + K2 * (qza(2) - qza(-1));
+    // sigma_bar_xx += -D-x q_bar_xa ; sigma_bar_zz += -D-z q_bar_zb ;
+    // sigma_bar_xz += -(D+z q_bar_xb + D+x q_bar_za)
+    const float dsxx = -txx_d * s.rdx, dszz = -tzz_d * s.rdz, dsxz = -(t1 * s.rdz + t2 * s.rdx);
+    const float mu = L.mu, lam = L.lam, l2m = lam + 2.0f * mu;
+    const float mxz = 4.0f * rcpf(rcpf(mu) + rcpf(L.mu_x) + rcpf(L.mu_z) + rcpf(L.mu_xz));
+    const unsigned o = pofs(p, i, j);
+    if (PML) {  // owned stress-side adjoint memory variables, from t_bar of step n + 1
+      const int sx = strip_index(j, p.nx, s.P), sz = strip_index(i, p.nz, s.P);
+      if (sx >= 0) {
+        const unsigned q = (unsigned)(i * p.P2 + sx);
+        G(p.wpx[X_XX], q) = G(p.bxi, (unsigned)j) * (L.r1 + dt * L.txx);
+        G(p.wpx[X_XZ], q) = G(p.bxh, (unsigned)j) * (L.r2 + dt * L.txz);
+      }
+      if (sz >= 0) {
+        const unsigned q = (unsigned)(sz * p.nx + j);
+        G(p.wpz[Z_ZZ], q) = G(p.bzi, (unsigned)i) * (L.r3 + dt * L.tzz);
+        G(p.wpz[Z_XZ], q) = G(p.bzh, (unsigned)i) * (L.r4 + dt * L.txz);
+      }
+    }
+    G(p.wtxx, o) = L.txx + (l2m * dsxx + lam * dszz);
+    G(p.wtzz, o) = L.tzz + (lam * dsxx + l2m * dszz);
+    G(p.wtxz, o) = L.txz + mxz * dsxz;
+    if (GRAD) {
+      const unsigned cc = (unsigned)(i * s.cp + j), cells = (unsigned)s.cells;
+      const float e = (L.txx - L.tzz) * L.h1 + L.e_nb;
+      // vx nodes (i, j-1/2), (i, j+1/2) and vz nodes (i-1/2, j), (i+1/2, j) around rho(i, j)
+      const float c0 = edges ? (float)pair_count(j - 1, j, p.nx) : 1.0f;
+      const float c1 = edges ? (float)pair_count(j, j, p.nx) : 1.0f;
+      const float c2 = edges ? (float)pair_count(i - 1, i, p.nz) : 1.0f;
+      const float c3 = edges ? (float)pair_count(i, i, p.nz) : 1.0f;
+      float r = c0 * UX[u0 - 1] * L.h3m;
+      r += c1 * UX[u0] * L.h3;
+      r += c2 * UZ[u0 - VC] * L.h4m;
+      r += c3 * UZ[u0] * L.h4;
+      G(p.acc, cc) = L.a0 + dt * (L.txx + L.tzz) * L.h0;
+      G(p.acc, cells + cc) = L.a1 + dt * e;
+      G(p.acc, 2 * cells + cc) = L.a2 - dt * r;
+    }
+    if (SRCADJ && i == s.si && j == s.sj) {
+      // sigma_bar at the source from t_bar of step n + 1: invert the 2x2 normal block and
+      // the shear moduli of the four shear nodes around the source
+      const float det = (l2m - lam) * (l2m + lam);
+      const float sb0 = (l2m * L.txx - lam * L.tzz) / det, sb1 = (l2m * L.tzz - lam * L.txx) / det;
+      float sb2 = 0.0f;
+      for (int a = i - 1; a <= i; ++a) {
+        for (int b = j - 1; b <= j; ++b) {
+          const unsigned oo = pofs(p, a, b);
+          const float m4 = 4.0f * rcpf(rcpf(G(p.mu, oo)) + rcpf(G(p.mu, oo + 1)) + rcpf(G(p.mu, oo + p.ld)) +
+                                       rcpf(G(p.mu, oo + p.ld + 1)));
+          sb2 += m4 > 0.0f ? G(p.txz, oo) / m4 : 0.0f;
+        }
+      }
+      s.src_bar[n] = -s.w * sb0;
+      s.src_bar[s.nt + n] = -s.w * sb1;
+      s.src_bar[2 * s.nt + n] = -0.25f * s.w * sb2;
+    }
   }
 }
 
-template <bool GRAD, bool SRCADJ>
-__global__ __launch_bounds__(BX * BZ) void k_adj_vel(BATCH_PARAMS, int n, int k, int first) {
-  BATCH_TILE();
-  // all 64 lanes of a wavefront share threadIdx.y: keep the row index scalar
-  const int j = j0 + threadIdx.x, i = i0 + __builtin_amdgcn_readfirstlane(threadIdx.y);
-  const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
-  const bool active = i < s.nz && j < s.nx;
-  if (block_in_pml(s, j0, i0, BZ, 2)) {  // block-uniform: every thread reaches the barrier
-    __shared__ float lds[LDS_OPS];
-    const StageArea a{lds, lds + BZ * LX, lds + 2 * BZ * LX, lds + 2 * BZ * LX + LZ * BX};
-    const int rd = (n + 1) & 1;
-    // x0: p_bar_xx at columns j-1 .. j+2; x1: p_bar_xz at j-2 .. j+1;
-    // z0: p_bar_zx at rows i-2 .. i+1;     z1: p_bar_zz at i-1 .. i+2
-    stage_operands(s, i0, j0, a, StagedOp{s.txxb, axi(s), s.pbx[rd][X_XX], -1},
-                   StagedOp{s.txzb, axh(s), s.pbx[rd][X_XZ], -2}, StagedOp{s.txzb, azh(s), s.pbz[rd][Z_XZ], -2},
-                   StagedOp{s.tzzb, azi(s), s.pbz[rd][Z_ZZ], -1});
-    __syncthreads();
-    if (!active) return;
-    const int r = threadIdx.y, q = threadIdx.x;
-    const float* X0 = a.x0 + r * LX + q;   // X0[m] = p_bar_xx(i, j - 1 + m)
-    const float* X1 = a.x1 + r * LX + q;   // X1[m] = p_bar_xz(i, j - 2 + m)
-    const float* Z0 = a.z0 + r * BX + q;   // Z0[m BX] = p_bar_zx(i - 2 + m, j)
-    const float* Z1 = a.z1 + r * BX + q;   // Z1[m BX] = p_bar_zz(i - 1 + m, j)
-    const float ux = K1 * (X0[2] - X0[1]) + K2 * (X0[3] - X0[0]);
-    const float uz = K1 * (Z0[2 * BX] - Z0[BX]) + K2 * (Z0[3 * BX] - Z0[0]);
-    const float wz = K1 * (Z1[2 * BX] - Z1[BX]) + K2 * (Z1[3 * BX] - Z1[0]);
-    const float wx = K1 * (X1[2] - X1[1]) + K2 * (X1[3] - X1[0]);
-    adj_vel_finish<GRAD, SRCADJ, true>(s, i, j, n, seg, first != 0, ux, uz, wz, wx);
-  } else if (active) {
-    const AdjCtx<false> c{s, 0};
-    const float ux = K1 * (pb_xx(c, i, j + 1) - pb_xx(c, i, j)) + K2 * (pb_xx(c, i, j + 2) - pb_xx(c, i, j - 1));
-    const float uz = K1 * (pb_zx(c, i, j) - pb_zx(c, i - 1, j)) + K2 * (pb_zx(c, i + 1, j) - pb_zx(c, i - 2, j));
-    const float wz = K1 * (pb_zz(c, i + 1, j) - pb_zz(c, i, j)) + K2 * (pb_zz(c, i + 2, j) - pb_zz(c, i - 1, j));
-    const float wx = K1 * (pb_xz(c, i, j) - pb_xz(c, i, j - 1)) + K2 * (pb_xz(c, i, j + 1) - pb_xz(c, i, j - 2));
-    adj_vel_finish<GRAD, SRCADJ, false>(s, i, j, n, seg, first != 0, ux, uz, wz, wx);
-  }
-}
-
-// Transposed velocity sub-step (second at reverse step n): u_bar -> t_bar.
-// txx, tzz, t1, t2: D-x q_bar_xa, D-z q_bar_zb, D+z q_bar_xb, D+x q_bar_za at the cell's
-// stress nodes (without 1/h).
-template <bool GRAD, bool PML>
-__device__ __forceinline__ void adj_str_finish(const Shot2D& s, int i, int j, int n, const gfloat* seg, bool first,
-                                               float txx, float tzz, float t1, float t2) {
-  const long ld = s.ld;
-  const long o = (long)i * ld + j;
-  const int rd = (n + 1) & 1, wr = n & 1;
-  // ---- loads ----
-  const float ux = s.uxb[o], uz = s.uzb[o];
-  const float lam = s.lam[o], l2m = l2m_of(s, o), mxz = muxz_of(s, o);
-  const float t0xx = s.txxb[o], t0zz = s.tzzb[o], t0xz = s.txzb[o];
-  int sx = -1, sz = -1;
-  long qx_ = 0, qz_ = 0;
-  float r1 = 0.0f, r2 = 0.0f, r3 = 0.0f, r4 = 0.0f;
-  if (PML) {  // owned adjoint memory variables of the velocity-side derivatives
-    sx = strip_index(j, s.nx, s.P);
-    sz = strip_index(i, s.nz, s.P);
-    qx_ = (long)i * 2 * s.P + max(sx, 0);
-    qz_ = (long)max(sz, 0) * s.nx + j;
-    r1 = bxh(s)[j] * (s.pbx[rd][X_VXX][qx_] + s.dt * ux);
-    r2 = bxi(s)[j] * (s.pbx[rd][X_VZX][qx_] + s.dt * uz);
-    r3 = bzi(s)[i] * (s.pbz[rd][Z_VXZ][qz_] + s.dt * ux);
-    r4 = bzh(s)[i] * (s.pbz[rd][Z_VZZ][qz_] + s.dt * uz);
-  }
-  long cc = 0;
-  float a2 = 0.0f, r = 0.0f;
-  if (GRAD) {
-    cc = (long)i * s.cp + j;
-    const gfloat* h3 = seg + 3 * s.cells;
-    const gfloat* h4 = seg + 4 * s.cells;
-    // vx nodes (i, b + 1/2), b in {j-1, j}: b_x averages rho(i, b), rho(i, b + 1); vz nodes
-    // (a + 1/2, j), a in {i-1, i}; clamped indices, weight 0 where rho(i, j) is not used
-    const int jm = max(j - 1, 0), im = max(i - 1, 0);
-    r = (float)pair_count(j - 1, j, s.nx) * s.uxb[(long)i * ld + jm] * h3[(long)i * s.cp + jm];
-    r += (float)pair_count(j, j, s.nx) * ux * h3[cc];
-    r += (float)pair_count(i - 1, i, s.nz) * s.uzb[(long)im * ld + j] * h4[(long)im * s.cp + j];
-    r += (float)pair_count(i, i, s.nz) * uz * h4[cc];
-    if (!first) a2 = s.acc[2 * s.cells + cc];
-  }
-  // ---- arithmetic ----
-  // sigma_bar_xx += -D-x q_bar_xa ; sigma_bar_zz += -D-z q_bar_zb ;
-  // sigma_bar_xz += -(D+z q_bar_xb + D+x q_bar_za)
-  const float dsxx = -txx * s.rdx, dszz = -tzz * s.rdz, dsxz = -(t1 * s.rdz + t2 * s.rdx);
-  // ---- stores ----
-  if (PML) {
-    if (sx >= 0) {
-      s.pbx[wr][X_VXX][qx_] = r1;
-      s.pbx[wr][X_VZX][qx_] = r2;
-    }
-    if (sz >= 0) {
-      s.pbz[wr][Z_VXZ][qz_] = r3;
-      s.pbz[wr][Z_VZZ][qz_] = r4;
-    }
-  }
-  s.txxb[o] = t0xx + (l2m * dsxx + lam * dszz);
-  s.tzzb[o] = t0zz + (lam * dsxx + l2m * dszz);
-  s.txzb[o] = t0xz + mxz * dsxz;
-  if (GRAD) s.acc[2 * s.cells + cc] = a2 - s.dt * r;
-}
-
-template <bool GRAD>
-__global__ __launch_bounds__(BX * BZ) void k_adj_str(BATCH_PARAMS, int n, int k, int first) {
-  BATCH_TILE();
-  const int j = j0 + threadIdx.x, i = i0 + threadIdx.y;
-  const gfloat* seg = GRAD ? s.seg + (size_t)k * NSEG_FIELDS * s.cells : nullptr;
-  const bool active = i < s.nz && j < s.nx;
-  if (block_in_pml(s, j0, i0, BZ, 2)) {  // block-uniform: every thread reaches the barrier
-    __shared__ float lds[LDS_OPS];
-    const StageArea a{lds, lds + BZ * LX, lds + 2 * BZ * LX, lds + 2 * BZ * LX + LZ * BX};
-    const int rd = (n + 1) & 1;
-    // x0: q_bar_xa at columns j-2 .. j+1; x1: q_bar_za at j-1 .. j+2;
-    // z0: q_bar_zb at rows i-2 .. i+1;     z1: q_bar_xb at i-1 .. i+2
-    stage_operands(s, i0, j0, a, StagedOp{s.uxb, axh(s), s.pbx[rd][X_VXX], -2},
-                   StagedOp{s.uzb, axi(s), s.pbx[rd][X_VZX], -1}, StagedOp{s.uzb, azh(s), s.pbz[rd][Z_VZZ], -2},
-                   StagedOp{s.uxb, azi(s), s.pbz[rd][Z_VXZ], -1});
-    __syncthreads();
-    if (!active) return;
-    const int r = threadIdx.y, q = threadIdx.x;
-    const float* X0 = a.x0 + r * LX + q;   // X0[m] = q_bar_xa(i, j - 2 + m)
-    const float* X1 = a.x1 + r * LX + q;   // X1[m] = q_bar_za(i, j - 1 + m)
-    const float* Z0 = a.z0 + r * BX + q;   // Z0[m BX] = q_bar_zb(i - 2 + m, j)
-    const float* Z1 = a.z1 + r * BX + q;   // Z1[m BX] = q_bar_xb(i - 1 + m, j)
-    const float txx = K1 * (X0[2] - X0[1]) + K2 * (X0[3] - X0[0]);
-    const float tzz = K1 * (Z0[2 * BX] - Z0[BX]) + K2 * (Z0[3 * BX] - Z0[0]);
-    const float t1 = K1 * (Z1[2 * BX] - Z1[BX]) + K2 * (Z1[3 * BX] - Z1[0]);
-    const float t2 = K1 * (X1[2] - X1[1]) + K2 * (X1[3] - X1[0]);
-    adj_str_finish<GRAD, true>(s, i, j, n, seg, first != 0, txx, tzz, t1, t2);
-  } else if (active) {
-    const AdjCtx<false> c{s, 0};
-    const float txx = K1 * (qb_xa(c, i, j) - qb_xa(c, i, j - 1)) + K2 * (qb_xa(c, i, j + 1) - qb_xa(c, i, j - 2));
-    const float tzz = K1 * (qb_zb(c, i, j) - qb_zb(c, i - 1, j)) + K2 * (qb_zb(c, i + 1, j) - qb_zb(c, i - 2, j));
-    const float t1 = K1 * (qb_xb(c, i + 1, j) - qb_xb(c, i, j)) + K2 * (qb_xb(c, i + 2, j) - qb_xb(c, i - 1, j));
-    const float t2 = K1 * (qb_za(c, i, j + 1) - qb_za(c, i, j)) + K2 * (qb_za(c, i, j + 2) - qb_za(c, i, j - 1));
-    adj_str_finish<GRAD, false>(s, i, j, n, seg, first != 0, txx, tzz, t1, t2);
-  }
+template <int TZ, bool GRAD, bool SRCADJ>
+__global__ __launch_bounds__(BX * BZ) void k_adj_step(STEP_PARAMS, int n, int kseg, int first) {
+  __shared__ float lds[AdjTile<TZ>::LDS_FLOATS];
+  int sh_, i0, j0;
+  if (!batch_tile<TZ>(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;
+  const Shot2D& s = shots[sh_];
+  // block-uniform branch: every thread reaches the barriers. The staged p_bar operands
+  // reach 4 nodes beyond the tile, so tiles within 4 nodes of a strip take the CPML path.
+  if (block_in_pml(s, j0, i0, TZ, 4)) adj_step_tile<TZ, GRAD, SRCADJ, true>(s, i0, j0, n, kseg, first != 0, lds);
+  else adj_step_tile<TZ, GRAD, SRCADJ, false>(s, i0, j0, n, kseg, first != 0, lds);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1030,7 +1085,6 @@ __global__ void k_reduce_phi(const double* partial, int n, double* phi) {
 inline dim3 grid_of(const Sched& q) { return dim3(q.n); }
 inline dim3 block2d() { return dim3(BX, BZ); }
 #define FWD_ARGS b.shots, b.tile_shot, b.tile_first, b.fwd.sched
-#define ADJ_ARGS b.shots, b.tile_shot, b.tile_first, b.adj.sched
 
 }  // namespace
 
@@ -1040,6 +1094,7 @@ hipError_t launch_stage2d(const Batch2D& b, hipStream_t st) {
 }
 
 #define STEP_ARGS b.shots, b.step_tile_shot, b.step_tile_first, b.step.sched
+#define ADJSTEP_ARGS b.shots, b.step_tile_shot, b.step_tile_first, b.adj_step.sched
 
 hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
   const dim3 g = grid_of(b.step);
@@ -1053,16 +1108,11 @@ hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hip
   return hipGetLastError();
 }
 
-hipError_t launch_adj_vel(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
-  if (grad) k_adj_vel<true, false><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, k, first);
-  else if (srcadj) k_adj_vel<false, true><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, 0, 0);
-  else k_adj_vel<false, false><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, 0, 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_str(const Batch2D& b, int n, int k, bool grad, bool first, hipStream_t st) {
-  if (grad) k_adj_str<true><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, k, first);
-  else k_adj_str<false><<<grid_of(b.adj), block2d(), 0, st>>>(ADJ_ARGS, n, 0, 0);
+hipError_t launch_adj_step(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
+  const dim3 g = grid_of(b.adj_step);
+  if (grad) k_adj_step<TSTEP, true, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, k, first);
+  else if (srcadj) k_adj_step<TSTEP, false, true><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
+  else k_adj_step<TSTEP, false, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
   return hipGetLastError();
 }
 
