@@ -159,6 +159,7 @@ def main():  # noqa: C901
     ap.add_argument("--no-sqrt", action="store_true", help="skip the sqrt(nt)-checkpoint form")
     ap.add_argument("--no-compressed", action="store_true", help="skip the FP16/BF16-checkpoint forms")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 64-shot uneven-window batched form")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--interval", type=int, default=-1,
                     help="checkpoint interval of the plain form (-1: largest that fits, 0: sqrt(nt))")
     ap.add_argument("--mem-fraction", type=float, default=0.92,
@@ -207,6 +208,12 @@ def main():  # noqa: C901
     nch = [s.nch for s in shots]
     obs = list(torch.split(d_obs, nch))
     torch.cuda.synchronize()
+    # Tile shape of the fused time-step kernels, picked by the library's autotuner from a
+    # short timed run of the first shot (results do not depend on it).
+    tune_ms = {}
+    tiles = efwi.autotune(grid, shots[0], m_ext[0], src[0], steps=64, times=tune_ms) if not args.no_autotune \
+        else efwi.get_tile_rows()
+    log(f"tile rows (forward, transposed): {tiles}; sweep ms by rows: {tune_ms}")
     # Checkpoint interval: the largest whose workspace fits in the free HBM (whole history
     # when it fits: nothing recomputed).
     budget = int(args.mem_fraction * torch.cuda.mem_get_info(dev)[0])
@@ -344,7 +351,9 @@ def main():  # noqa: C901
                                f"{len(w.shots[0].ch_ix)} DAS channels, CPML {w.npml}, FP32 history "
                                f"(checkpoint interval {L}), + extension regularizer (hard sinkholes)",
                    "nz": nz, "nx": nx, "nt": nt, "shots": ns, "ckpt_interval": L,
-                   "recompute_fraction": round(rf, 4), "form": "plain per-shot"},
+                   "recompute_fraction": round(rf, 4), "form": "plain per-shot",
+                   "tile_rows": {"forward": tiles[0], "transposed": tiles[1],
+                                 "autotune_ms": {str(k): [round(x, 3) for x in v] for k, v in tune_ms.items()}}},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": int(bytes_launch), "mean_launch_us": kern[dominant]["mean_us"]},

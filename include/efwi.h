@@ -166,6 +166,29 @@ efwi_status efwi_extension_regularizer(const efwi_grid* grid, int ns, const floa
                                        float* g_ext, double* phi, void* ws, size_t ws_bytes,
                                        void* stream);
 
+/* Tile shape of the fused 2D forward and transposed time-step kernels: tiles of 8, 12 or
+ * 16 rows by 64 columns (the stencil halo is recomputed per tile, so taller tiles recompute
+ * less but hold more LDS and registers). Results do not depend on the choice (every node
+ * is computed by the same arithmetic whichever tile holds it). Process-wide; applies to
+ * calls planned after it. efwi_set_tile_rows: 0 keeps a value; EFWI_E_INVAL for other
+ * values. */
+efwi_status efwi_set_tile_rows(int fwd_rows, int adj_rows);
+efwi_status efwi_get_tile_rows(int* fwd_rows, int* adj_rows);
+
+/* Autotuner of the tile shape: times the shot's forward and transposed sweeps over `steps`
+ * time steps (whole history kept, FP32) for each tile height (a warm-up run, then the best
+ * of two), on the given stream, keeps the fastest for each sweep (efwi_set_tile_rows) and
+ * returns them in *fwd_rows and *adj_rows. Blocks until the timing runs end. 2D grids
+ * only (EFWI_E_UNSUPPORTED for 3D).
+ *   m, src   DEVICE as in efwi_shot_gradient (src is read for the first `steps` samples);
+ *   ws       DEVICE workspace of efwi_autotune_workspace_size() bytes (0 on invalid input);
+ *   times_ms HOST [3][2] (forward, transposed sweep ms for 8, 12, 16 rows), or NULL.
+ * Must not overlap other calls that plan work. */
+size_t efwi_autotune_workspace_size(const efwi_grid* grid, const efwi_shot* shot, int steps);
+efwi_status efwi_autotune(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* src,
+                          int steps, void* ws, size_t ws_bytes, void* stream, int* fwd_rows, int* adj_rows,
+                          float* times_ms);
+
 /* Kernel timing sampler (profiling aid, off by default). With sample_every = k > 0, every
  * k-th launch of each kernel kind is bracketed by two HIP events recorded on the launch's
  * stream; 0 turns sampling off. efwi_timing_query() waits for the pending events of one kind

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -271,9 +272,14 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
 // ----------------------------------------------------------------------------------------
 // Workspace plan of one 2D shot (its private region of the workspace).
 // ----------------------------------------------------------------------------------------
+// Rows of the fused forward-step and transposed-step tiles for the plans made from now on
+// (set by efwi_set_tile_rows or efwi_autotune; process-wide).
+std::atomic<int> g_fwd_rows{DEFAULT_TILE_ROWS}, g_adj_rows{DEFAULT_TILE_ROWS};
+
 struct Plan2D {
   Window w;
-  int nz, nx, ld, cp, rows, P, nslots, nt, nch, L, nseg, ntiles, nstep_tiles;
+  int nz, nx, ld, cp, rows, P, nslots, nt, nch, L, nseg, ntiles;
+  int fwd_rows, adj_rows, nfwd_tiles, nadj_tiles;   // fused-step tiles
   long plane, cells;
   size_t state_bytes;  // padded fields + forward CPML strips
   size_t state_elems;
@@ -301,7 +307,7 @@ int interval_of(const efwi_grid& g, const efwi_shot& s) {
   return std::max(1, std::min(L, g.nt));
 }
 
-Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
+Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind, int fwd_rows = 0, int adj_rows = 0) {
   Plan2D p{};
   p.w = window_of(g, s);
   p.nz = p.w.wz;
@@ -316,7 +322,10 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.nch = s.nch;
   p.nslots = count_slots(s, p.w);
   p.ntiles = ((p.nx + BX - 1) / BX) * ((p.nz + BZ - 1) / BZ);
-  p.nstep_tiles = ((p.nx + BX - 1) / BX) * ((p.nz + TSTEP - 1) / TSTEP);
+  p.fwd_rows = fwd_rows > 0 ? fwd_rows : g_fwd_rows.load();
+  p.adj_rows = adj_rows > 0 ? adj_rows : g_adj_rows.load();
+  p.nfwd_tiles = ((p.nx + BX - 1) / BX) * ((p.nz + p.fwd_rows - 1) / p.fwd_rows);
+  p.nadj_tiles = ((p.nx + BX - 1) / BX) * ((p.nz + p.adj_rows - 1) / p.adj_rows);
   p.L = interval_of(g, s);
   p.nseg = (g.nt + p.L - 1) / p.L;
   const size_t strips = strips_floats(p.nz, p.nx, p.P);
@@ -512,15 +521,18 @@ size_t sched_capacity(size_t tiles) {
 }
 
 size_t header_bytes(const std::vector<Plan2D>& plans, int first, int count) {
-  size_t tiles = 0, stiles = 0, tabs = 0;
+  size_t tiles = 0, ftiles = 0, atiles = 0, tabs = 0;
   for (int k = first; k < first + count; ++k) {
     tiles += plans[k].ntiles;
-    stiles += plans[k].nstep_tiles;
+    ftiles += plans[k].nfwd_tiles;
+    atiles += plans[k].nadj_tiles;
     tabs += plans[k].tab_bytes;
   }
-  return align_up((size_t)count * sizeof(Shot2D)) + 2 * align_up((size_t)count * sizeof(int)) +
-         align_up(tiles * sizeof(int)) + align_up(sched_capacity(tiles) * sizeof(int)) +
-         align_up(stiles * sizeof(int)) + 2 * align_up(sched_capacity(stiles) * sizeof(int)) + tabs;
+  auto list = [&](size_t n) {  // tile_first, tile_shot and schedule of one tile list
+    return align_up((size_t)count * sizeof(int)) + align_up(n * sizeof(int)) +
+           align_up(sched_capacity(n) * sizeof(int));
+  };
+  return align_up((size_t)count * sizeof(Shot2D)) + list(tiles) + list(ftiles) + list(atiles) + tabs;
 }
 
 size_t wave_bytes(const std::vector<Plan2D>& plans, int first, int count) {
@@ -565,38 +577,46 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   wv.nt = g.nt;
   wv.L = wv.plans[0].L;
   wv.nseg = wv.plans[0].nseg;
-  int ntiles = 0, nstiles = 0;
+  int ntiles = 0, nftiles = 0, natiles = 0;
   for (const Plan2D& p : wv.plans) {
     ntiles += p.ntiles;
-    nstiles += p.nstep_tiles;
+    nftiles += p.nfwd_tiles;
+    natiles += p.nadj_tiles;
   }
-  // header layout
+  // header layout: descriptors, then three tile lists (tile_first [count], tile_shot
+  // [tiles], XCD schedule) for the 4-row tiles, the forward-step and the transposed-step
+  // tiles, then the per-shot tables
   const size_t off_desc = 0;
-  const size_t off_first = off_desc + align_up((size_t)count * sizeof(Shot2D));
-  const size_t off_tshot = off_first + align_up((size_t)count * sizeof(int));
-  const size_t off_sched = off_tshot + align_up((size_t)ntiles * sizeof(int));
-  const size_t off_sfirst = off_sched + align_up(sched_capacity(ntiles) * sizeof(int));
-  const size_t off_stshot = off_sfirst + align_up((size_t)count * sizeof(int));
-  const size_t off_ssched = off_stshot + align_up((size_t)nstiles * sizeof(int));
-  const size_t off_asched = off_ssched + align_up(sched_capacity(nstiles) * sizeof(int));
-  size_t off_tab = off_asched + align_up(sched_capacity(nstiles) * sizeof(int));
+  size_t off = off_desc + align_up((size_t)count * sizeof(Shot2D));
+  struct ListAt {
+    size_t first, shot, sched;
+  };
+  auto list_at = [&](size_t n) {
+    ListAt l;
+    l.first = off;
+    l.shot = l.first + align_up((size_t)count * sizeof(int));
+    l.sched = l.shot + align_up(n * sizeof(int));
+    off = l.sched + align_up(sched_capacity(n) * sizeof(int));
+    return l;
+  };
+  const ListAt l4 = list_at(ntiles), lf = list_at(nftiles), la = list_at(natiles);
+  size_t off_tab = off;
   const size_t hdr = header_bytes(plans, first, count);
   std::vector<unsigned char> blob(hdr, 0);
-  int* tfirst = reinterpret_cast<int*>(blob.data() + off_first);
-  int* tshot = reinterpret_cast<int*>(blob.data() + off_tshot);
-  int* sfirst = reinterpret_cast<int*>(blob.data() + off_sfirst);
-  int* stshot = reinterpret_cast<int*>(blob.data() + off_stshot);
+  auto ints = [&](size_t o) { return reinterpret_cast<int*>(blob.data() + o); };
   size_t region = hdr;
-  int t = 0, ts = 0;
+  int t4 = 0, tf = 0, ta = 0;
   wv.descs.clear();
   wv.regions.clear();
   for (int k = 0; k < count; ++k) {
     const Plan2D& p = wv.plans[k];
     const efwi_shot& s = shots[first + k];
-    tfirst[k] = t;
-    for (int q = 0; q < p.ntiles; ++q) tshot[t++] = k;
-    sfirst[k] = ts;
-    for (int q = 0; q < p.nstep_tiles; ++q) stshot[ts++] = k;
+    ints(l4.first)[k] = t4;
+    for (int q = 0; q < p.ntiles; ++q) ints(l4.shot)[t4++] = k;
+    ints(lf.first)[k] = tf;
+    for (int q = 0; q < p.nfwd_tiles; ++q) ints(lf.shot)[tf++] = k;
+    ints(la.first)[k] = ta;
+    for (int q = 0; q < p.nadj_tiles; ++q) ints(la.shot)[ta++] = k;
     build_tables(g, s, p, blob.data() + off_tab);
     const float* tab_dev = reinterpret_cast<const float*>(ws + off_tab);
     wv.descs.push_back(make_desc(g, s, p, ws + region, tab_dev, io[first + k]));
@@ -606,50 +626,44 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   }
   std::memcpy(blob.data() + off_desc, wv.descs.data(), (size_t)count * sizeof(Shot2D));
   // XCD schedules: cut each tile list into NUM_XCD contiguous runs of equal weighted cost.
-  // The 4-row tiles serve the pointwise kernels (staging, chain rule, gradient output).
-  std::vector<int> wfwd(ntiles);
-  for (int k = 0, q = 0; k < count; ++k) {
-    const Plan2D& p = wv.plans[k];
-    const int ntx = (p.nx + BX - 1) / BX;
-    for (int l = 0; l < p.ntiles; ++l, ++q) {
-      const int i0 = (l / ntx) * BZ, j0 = (l % ntx) * BX;
-      const bool pml = p.P > 0 && ((j0 < p.P) || (j0 + BX - 1 >= p.nx - p.P) || (i0 < p.P) ||
-                                   (i0 + BZ - 1 >= p.nz - p.P));
-      wfwd[q] = pml ? FWD_W_PML : FWD_W_INT;
+  // Tiles near a CPML strip cost more: the 4-row tiles (pointwise kernels) that contain
+  // strip nodes, forward-step tiles within two nodes of a strip (velocity halo) and
+  // transposed-step tiles within four (staged operands).
+  auto weights = [&](int rows, int pad, int w_pml, int w_int, size_t n) {
+    std::vector<int> w(n);
+    size_t q = 0;
+    for (const Plan2D& p : wv.plans) {
+      const int ntx = (p.nx + BX - 1) / BX, nty = (p.nz + rows - 1) / rows;
+      for (int l = 0; l < ntx * nty; ++l, ++q) {
+        const int i0 = (l / ntx) * rows, j0 = (l % ntx) * BX;
+        const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
+                                     (i0 + rows - 1 + pad >= p.nz - p.P));
+        w[q] = pml ? w_pml : w_int;
+      }
     }
-  }
-  // the fused steps' tiles (TSTEP rows): CPML path of the forward step within two nodes of
-  // a strip, of the transposed step within four
-  std::vector<int> wstep(nstiles), wastep(nstiles);
-  for (int k = 0, q = 0; k < count; ++k) {
-    const Plan2D& p = wv.plans[k];
-    const int ntx = (p.nx + BX - 1) / BX;
-    for (int l = 0; l < p.nstep_tiles; ++l, ++q) {
-      const int i0 = (l / ntx) * TSTEP, j0 = (l % ntx) * BX;
-      auto near = [&](int pad) {
-        return p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
-                           (i0 + TSTEP - 1 + pad >= p.nz - p.P));
-      };
-      wstep[q] = near(2) ? FWD_W_PML : FWD_W_INT;
-      wastep[q] = near(4) ? ADJ_W_PML : ADJ_W_INT;
-    }
-  }
-  int nsched[4];
-  efwi_status rc = build_sched(wfwd, reinterpret_cast<int*>(blob.data() + off_sched), nsched[0]);
+    return w;
+  };
+  const int frows = wv.plans[0].fwd_rows, arows = wv.plans[0].adj_rows;
+  int nsched[3];
+  efwi_status rc = build_sched(weights(BZ, 0, FWD_W_PML, FWD_W_INT, ntiles), ints(l4.sched), nsched[0]);
   if (rc != EFWI_OK) return rc;
-  rc = build_sched(wstep, reinterpret_cast<int*>(blob.data() + off_ssched), nsched[2]);
+  rc = build_sched(weights(frows, 2, FWD_W_PML, FWD_W_INT, nftiles), ints(lf.sched), nsched[1]);
   if (rc != EFWI_OK) return rc;
-  rc = build_sched(wastep, reinterpret_cast<int*>(blob.data() + off_asched), nsched[3]);
+  rc = build_sched(weights(arows, 4, ADJ_W_PML, ADJ_W_INT, natiles), ints(la.sched), nsched[2]);
   if (rc != EFWI_OK) return rc;
-  wv.batch.adj_step = Sched{reinterpret_cast<const int*>(ws + off_asched), nsched[3]};
-  wv.batch.step_tile_first = reinterpret_cast<const int*>(ws + off_sfirst);
-  wv.batch.step_tile_shot = reinterpret_cast<const int*>(ws + off_stshot);
-  wv.batch.step = Sched{reinterpret_cast<const int*>(ws + off_ssched), nsched[2]};
-  wv.batch.nstep_tiles = nstiles;
+  auto dev = [&](size_t o) { return reinterpret_cast<const int*>(ws + o); };
+  wv.batch.tile_first = dev(l4.first);
+  wv.batch.tile_shot = dev(l4.shot);
+  wv.batch.fwd = Sched{dev(l4.sched), nsched[0]};
+  wv.batch.step_tile_first = dev(lf.first);
+  wv.batch.step_tile_shot = dev(lf.shot);
+  wv.batch.step = Sched{dev(lf.sched), nsched[1]};
+  wv.batch.adj_tile_first = dev(la.first);
+  wv.batch.adj_tile_shot = dev(la.shot);
+  wv.batch.adj_step = Sched{dev(la.sched), nsched[2]};
+  wv.batch.fwd_rows = frows;
+  wv.batch.adj_rows = arows;
   wv.batch.shots = reinterpret_cast<const Shot2D*>(ws + off_desc);
-  wv.batch.tile_first = reinterpret_cast<const int*>(ws + off_first);
-  wv.batch.tile_shot = reinterpret_cast<const int*>(ws + off_tshot);
-  wv.batch.fwd = Sched{reinterpret_cast<const int*>(ws + off_sched), nsched[0]};
   wv.batch.ns = count;
   wv.batch.ntiles = ntiles;
   // zero what must start at zero
@@ -1241,6 +1255,117 @@ size_t efwi_workspace_size(efwi_ws_kind kind, const efwi_grid* grid, int ns, con
   std::vector<Plan2D> plans;
   for (int k = 0; k < n; ++k) plans.push_back(plan2d(*grid, shots[k], kind));
   return wave_bytes(plans, 0, n);
+}
+
+efwi_status efwi_set_tile_rows(int fwd_rows, int adj_rows) {
+  if ((fwd_rows != 0 && !valid_tile_rows(fwd_rows)) || (adj_rows != 0 && !valid_tile_rows(adj_rows)))
+    return fail(EFWI_E_INVAL, "tile rows must be 8, 12 or 16 (0 keeps the current value)");
+  if (fwd_rows) g_fwd_rows.store(fwd_rows);
+  if (adj_rows) g_adj_rows.store(adj_rows);
+  return EFWI_OK;
+}
+
+efwi_status efwi_get_tile_rows(int* fwd_rows, int* adj_rows) {
+  if (!fwd_rows || !adj_rows) return fail(EFWI_E_INVAL, "NULL output pointer");
+  *fwd_rows = g_fwd_rows.load();
+  *adj_rows = g_adj_rows.load();
+  return EFWI_OK;
+}
+
+namespace {
+// The short run the autotuner times: the shot on its window for `steps` time steps, whole
+// history kept, FP32.
+void tune_case(const efwi_grid& g, const efwi_shot& s, int steps, efwi_grid& gt, efwi_shot& st) {
+  gt = g;
+  gt.nt = std::max(1, std::min(steps, g.nt));
+  st = s;
+  st.ckpt_interval = gt.nt;
+  st.ckpt_mode = EFWI_CKPT_FP32;
+}
+size_t tune_bytes(const efwi_grid& gt, const efwi_shot& st) {
+  size_t need = 0;
+  for (int r : TILE_ROWS) {
+    std::vector<Plan2D> plans{plan2d(gt, st, EFWI_WS_GRADIENT, r, r)};
+    need = std::max(need, wave_bytes(plans, 0, 1));
+  }
+  return need + align_up((size_t)std::max(1, st.nch) * gt.nt * sizeof(float));  // DAS data sink
+}
+}  // namespace
+
+size_t efwi_autotune_workspace_size(const efwi_grid* grid, const efwi_shot* shot, int steps) {
+  if (efwi_validate(grid, 1, shot) != EFWI_OK || grid->ndim != 2 || steps < 1) return 0;
+  efwi_grid gt;
+  efwi_shot st;
+  tune_case(*grid, *shot, steps, gt, st);
+  return tune_bytes(gt, st);
+}
+
+efwi_status efwi_autotune(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* src, int steps,
+                          void* ws, size_t ws_bytes, void* stream, int* fwd_rows, int* adj_rows, float* times_ms) {
+  efwi_status rc = efwi_validate(grid, 1, shot);
+  if (rc != EFWI_OK) return rc;
+  if (grid->ndim != 2) return fail(EFWI_E_UNSUPPORTED, "tile rows are tuned on 2D grids only");
+  if (!m || !src || !fwd_rows || !adj_rows || steps < 1) return fail(EFWI_E_INVAL, "NULL argument or steps < 1");
+  efwi_grid gt;
+  efwi_shot sh;
+  tune_case(*grid, *shot, steps, gt, sh);
+  rc = check_ws(ws, ws_bytes, tune_bytes(gt, sh));
+  if (rc != EFWI_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  hipEvent_t ev[3];
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  float best_f = 1e30f, best_a = 1e30f;
+  int rf = g_fwd_rows.load(), ra = g_adj_rows.load();
+  rc = EFWI_OK;
+  for (int ci = 0; ci < 3; ++ci) {
+    const int r = TILE_ROWS[ci];
+    std::vector<Plan2D> plans{plan2d(gt, sh, EFWI_WS_GRADIENT, r, r)};
+    const size_t wb = wave_bytes(plans, 0, 1);
+    ShotIO io;
+    io.m = m;
+    io.mplane = (long)grid->nz * grid->nx;
+    io.src = src;
+    io.d = reinterpret_cast<float*>(w + wb);
+    float mf = 1e30f, ma = 1e30f;
+    for (int rep = 0; rep < 3 && rc == EFWI_OK; ++rep) {  // the first run warms up; best of the others
+      Wave wv;
+      rc = setup_wave(gt, &sh, plans, 0, 1, {io}, EFWI_WS_GRADIENT, w, wv, st);
+      if (rc != EFWI_OK) break;
+      const Plan2D& p = wv.plans[0];
+      unsigned char* region = w + wv.regions[0];
+      if (hipEventRecord(ev[0], st) != hipSuccess || (rc = run_forward(wv, w, true, st)) != EFWI_OK) break;
+      // zero adjoint source: the sweep is timed, its result discarded
+      if (hipMemsetAsync(region + p.off_ebar, 0, (size_t)std::max(1, p.nch) * p.nt * sizeof(float), st) !=
+              hipSuccess ||
+          hipEventRecord(ev[1], st) != hipSuccess || (rc = run_reverse(wv, w, st)) != EFWI_OK ||
+          hipEventRecord(ev[2], st) != hipSuccess || hipEventSynchronize(ev[2]) != hipSuccess) {
+        if (rc == EFWI_OK) rc = fail(EFWI_E_HIP, "autotune: HIP event or memset failed");
+        break;
+      }
+      float tf = 0.f, ta = 0.f;
+      hipEventElapsedTime(&tf, ev[0], ev[1]);
+      hipEventElapsedTime(&ta, ev[1], ev[2]);
+      if (rep > 0) {
+        mf = std::min(mf, tf);
+        ma = std::min(ma, ta);
+      }
+    }
+    if (rc != EFWI_OK) break;
+    if (mf < best_f) best_f = mf, rf = r;
+    if (ma < best_a) best_a = ma, ra = r;
+    if (times_ms) {
+      times_ms[2 * ci] = mf;
+      times_ms[2 * ci + 1] = ma;
+    }
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  if (rc != EFWI_OK) return rc;
+  g_fwd_rows.store(rf);
+  g_adj_rows.store(ra);
+  *fwd_rows = rf;
+  *adj_rows = ra;
+  return EFWI_OK;
 }
 
 int efwi_plan_interval(const efwi_grid* grid, const efwi_shot* shot, size_t budget_bytes) {

@@ -106,14 +106,21 @@ struct Batch2D {
   const int* tile_first;
   Sched fwd;
   int ns, ntiles;
-  const int* step_tile_shot; // TSTEP-row tiles of the fused forward and transposed steps
+  // tiles of the fused forward step (fwd_rows rows) and of the fused transposed step
+  // (adj_rows rows), 64 columns wide
+  const int* step_tile_shot;
   const int* step_tile_first;
+  const int* adj_tile_shot;
+  const int* adj_tile_first;
   Sched step, adj_step;
-  int nstep_tiles;
+  int fwd_rows, adj_rows;
 };
 
-// Rows of a fused forward-step tile (64 columns wide).
-constexpr int TSTEP = 8;
+// Rows of a fused-step tile (64 columns wide): the kernels are built for these heights and
+// the autotuner picks one for each of the two fused steps.
+constexpr int TILE_ROWS[3] = {8, 12, 16};
+constexpr int DEFAULT_TILE_ROWS = 8;
+inline bool valid_tile_rows(int r) { return r == 8 || r == 12 || r == 16; }
 
 // Number of XCDs the hardware deals workgroups to, round robin.
 constexpr int NUM_XCD = 8;

@@ -1094,25 +1094,49 @@ hipError_t launch_stage2d(const Batch2D& b, hipStream_t st) {
 }
 
 #define STEP_ARGS b.shots, b.step_tile_shot, b.step_tile_first, b.step.sched
-#define ADJSTEP_ARGS b.shots, b.step_tile_shot, b.step_tile_first, b.adj_step.sched
+#define ADJSTEP_ARGS b.shots, b.adj_tile_shot, b.adj_tile_first, b.adj_step.sched
 
-hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
+namespace {
+
+template <int TZ>
+void fwd_step_launch(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
   const dim3 g = grid_of(b.step);
   if (kstore >= 0) {
-    if (record) k_fwd_step<TSTEP, true, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
-    else k_fwd_step<TSTEP, true, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
+    if (record) k_fwd_step<TZ, true, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
+    else k_fwd_step<TZ, true, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
   } else {
-    if (record) k_fwd_step<TSTEP, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
-    else k_fwd_step<TSTEP, false, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
+    if (record) k_fwd_step<TZ, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
+    else k_fwd_step<TZ, false, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
+  }
+}
+
+template <int TZ>
+void adj_step_launch(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
+  const dim3 g = grid_of(b.adj_step);
+  if (grad) k_adj_step<TZ, true, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, k, first);
+  else if (srcadj) k_adj_step<TZ, false, true><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
+  else k_adj_step<TZ, false, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
+}
+
+}  // namespace
+
+hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
+  switch (b.fwd_rows) {
+    case 8: fwd_step_launch<8>(b, n, kstore, record, st); break;
+    case 12: fwd_step_launch<12>(b, n, kstore, record, st); break;
+    case 16: fwd_step_launch<16>(b, n, kstore, record, st); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_adj_step(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
-  const dim3 g = grid_of(b.adj_step);
-  if (grad) k_adj_step<TSTEP, true, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, k, first);
-  else if (srcadj) k_adj_step<TSTEP, false, true><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
-  else k_adj_step<TSTEP, false, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
+  switch (b.adj_rows) {
+    case 8: adj_step_launch<8>(b, n, k, grad, first, srcadj, st); break;
+    case 12: adj_step_launch<12>(b, n, k, grad, first, srcadj, st); break;
+    case 16: adj_step_launch<16>(b, n, k, grad, first, srcadj, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

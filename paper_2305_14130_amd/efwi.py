@@ -30,7 +30,8 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_shot_gradient", "efwi_shot_jt", "efwi_batch_gradient", "efwi_extension_regularizer",
             "efwi_status_string", "efwi_last_error", "efwi_version", "efwi_timing_enable",
             "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name",
-            "efwi_plan_interval"]
+            "efwi_plan_interval", "efwi_set_tile_rows", "efwi_get_tile_rows", "efwi_autotune_workspace_size",
+            "efwi_autotune"]
 
 
 class Grid(ctypes.Structure):
@@ -102,6 +103,16 @@ def n_components(grid: Grid) -> int:
 _vp = ctypes.c_void_p
 _lib.efwi_workspace_size.restype = ctypes.c_size_t
 _lib.efwi_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC)]
+_lib.efwi_set_tile_rows.restype = ctypes.c_int
+_lib.efwi_set_tile_rows.argtypes = [ctypes.c_int, ctypes.c_int]
+_lib.efwi_get_tile_rows.restype = ctypes.c_int
+_lib.efwi_get_tile_rows.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.efwi_autotune_workspace_size.restype = ctypes.c_size_t
+_lib.efwi_autotune_workspace_size.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), ctypes.c_int]
+_lib.efwi_autotune.restype = ctypes.c_int
+_lib.efwi_autotune.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, ctypes.c_int, _vp,
+                               ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                               ctypes.POINTER(ctypes.c_float)]
 _lib.efwi_plan_interval.restype = ctypes.c_int
 _lib.efwi_plan_interval.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), ctypes.c_size_t]
 _lib.efwi_validate.restype = ctypes.c_int
@@ -218,6 +229,38 @@ def plan_interval(grid: Grid, shot: Shot, budget_bytes: int) -> int:
     L = _lib.efwi_plan_interval(ctypes.byref(grid), ctypes.byref(sc), int(budget_bytes))
     _check(min(L, 0))
     return int(L)
+
+
+def set_tile_rows(fwd_rows: int = 0, adj_rows: int = 0) -> None:
+    """Rows of the fused forward / transposed step tiles (8, 12 or 16; 0 keeps a value)."""
+    _check(_lib.efwi_set_tile_rows(int(fwd_rows), int(adj_rows)))
+
+
+def get_tile_rows():
+    f, a = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.efwi_get_tile_rows(ctypes.byref(f), ctypes.byref(a)))
+    return f.value, a.value
+
+
+def autotune(grid: Grid, shot: Shot, m, src, steps: int = 16, stream=None, times=None):
+    """Time the shot's forward and transposed sweeps over `steps` steps for each tile height,
+    keep the fastest for each (process-wide) and return (fwd_rows, adj_rows). With a dict
+    `times`, also fill {rows: (forward ms, transposed ms)}."""
+    _f32(m, "m"), _f32(src, "src")
+    sc = shot.c_struct()
+    need = _lib.efwi_autotune_workspace_size(ctypes.byref(grid), ctypes.byref(sc), int(steps))
+    if need == 0:
+        _check(_lib.efwi_validate(ctypes.byref(grid), 1, ctypes.byref(sc)))
+        raise EfwiError(E_UNSUPPORTED, "autotune needs a 2D grid and steps >= 1")
+    ws = workspace(need, m.device)
+    f, a = ctypes.c_int(), ctypes.c_int()
+    tm = (ctypes.c_float * 6)()
+    _check(_lib.efwi_autotune(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), int(steps), _ptr(ws),
+                              ws.numel(), _stream(stream), ctypes.byref(f), ctypes.byref(a), tm))
+    if times is not None:
+        for k, rows in enumerate((8, 12, 16)):
+            times[rows] = (tm[2 * k], tm[2 * k + 1])
+    return f.value, a.value
 
 
 def recompute_fraction(grid: Grid, interval: int) -> float:

@@ -100,3 +100,28 @@ def test_plan_interval_fits_the_budget(efwi):
     assert ei.value.status == efwi.E_WORKSPACE
     assert efwi.recompute_fraction(grid, nt) == 0.0
     assert efwi.recompute_fraction(grid, 10) == (5 - 1) * 10 / nt
+
+
+def test_tile_rows_setting(efwi):
+    f0, a0 = efwi.get_tile_rows()
+    try:
+        efwi.set_tile_rows(16, 12)
+        assert efwi.get_tile_rows() == (16, 12)
+        efwi.set_tile_rows(0, 8)            # 0 keeps the forward value
+        assert efwi.get_tile_rows() == (16, 8)
+        for bad in ((7, 0), (0, 32), (-8, 8)):
+            with pytest.raises(efwi.EfwiError) as ei:
+                efwi.set_tile_rows(*bad)
+            assert ei.value.status == efwi.E_INVAL
+        assert efwi.get_tile_rows() == (16, 8)
+    finally:
+        efwi.set_tile_rows(f0, a0)
+
+
+def test_autotune_workspace_size(efwi):
+    grid, shot = _ok_case(efwi)
+    sc = shot.c_struct()
+    assert efwi._lib.efwi_autotune_workspace_size(grid, sc, 16) > 0
+    assert efwi._lib.efwi_autotune_workspace_size(grid, sc, 0) == 0
+    grid.ndim = 3
+    assert efwi._lib.efwi_autotune_workspace_size(grid, sc, 16) == 0
