@@ -52,6 +52,12 @@ HBM_PEAK_GBS = 8000.0
 # (u_bar = b v_bar and t_bar = C sigma_bar are the scaled adjoint variables; the imaging
 # sums are gathered at the normal node.)
 KERNEL_BYTES = {"fwd_step": (52, 72), "adj_step": (96, 96)}
+# HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, KiB,
+# scaled by a 256 MiB copy) on one 1000 x 3000 shot; see
+# profiles/plain2d_1000x3000_hbm_counters.md. Valid for these kernels on this grid only.
+MEASURED_TRAFFIC = {"adj_step": {"cells": 3_000_000, "bytes": (104097.3 * 2.0 + 99192.4 * 1.0) * 1024},
+                    "fwd_step": {"cells": 3_000_000, "bytes": (53328.6 * 2.0 + 122576.0 * 1.0) * 1024}}
+
 
 def path_bytes_per_cell_step(recompute_fraction):
     """Whole-path algorithmic bytes per cell-step: every step runs forward once with storing
@@ -333,6 +339,8 @@ def main():  # noqa: C901
     dominant = max((n for n in kern if n in KERNEL_BYTES), key=lambda n: kern[n]["share"])
     bytes_launch = kernel_bytes_per_launch(dominant, nz * nx, nt, L)
     achieved = bytes_launch / (kern[dominant]["mean_us"] * 1e-6) / 1e9
+    mt = MEASURED_TRAFFIC.get(dominant)
+    traffic = int(mt["bytes"]) if mt and mt["cells"] == nz * nx and rf == 0.0 else None
     pb = path_bytes_per_cell_step(rf)
     out = {
         "metric": "Gcell-updates/s fwd+adj+grad (and % HBM roofline); shots/s batched vs plain",
@@ -355,7 +363,7 @@ def main():  # noqa: C901
                    "tile_rows": {"forward": tiles[0], "transposed": tiles[1],
                                  "autotune_ms": {str(k): [round(x, 3) for x in v] for k, v in tune_ms.items()}}},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": int(bytes_launch), "mean_launch_us": kern[dominant]["mean_us"]},
         "path": {"bytes_per_cell_step": round(pb, 1),
                  "achieved_GBs": round(pb * cell_steps / elapsed / 1e9, 1),

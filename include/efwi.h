@@ -190,10 +190,12 @@ efwi_status efwi_autotune(const efwi_grid* grid, const efwi_shot* shot, const fl
                           float* times_ms);
 
 /* Kernel timing sampler (profiling aid, off by default). With sample_every = k > 0, every
- * k-th launch of each kernel kind is bracketed by two HIP events recorded on the launch's
- * stream; 0 turns sampling off. efwi_timing_query() waits for the pending events of one kind
- * and returns the number of launches, of timed launches and their summed duration in ms.
- * Kinds are 0 .. efwi_kernel_count() - 1, named by efwi_kernel_name(). */
+ * k-th launch of each kernel kind (at least every 8th) opens a window of up to 8
+ * consecutive launches of that kind, bracketed by two HIP events recorded on the launches'
+ * stream; another kind's launch closes the window early; 0 turns sampling off.
+ * efwi_timing_query() waits for the pending events of one kind and returns the number of
+ * launches, of timed launches and their summed duration in ms. Kinds are
+ * 0 .. efwi_kernel_count() - 1, named by efwi_kernel_name(). */
 efwi_status efwi_timing_enable(int sample_every);
 efwi_status efwi_timing_reset(void);
 efwi_status efwi_timing_query(int kind, long* launches, long* timed, double* total_ms);

@@ -96,9 +96,11 @@ Staging& staging() {
 }
 
 // ----------------------------------------------------------------------------------------
-// Kernel timing sampler: when enabled, every `every`-th launch of each kernel kind is
-// bracketed by two HIP events recorded on the launch stream; durations are collected when
-// queried. Off by default (no events in the hot loop).
+// Kernel timing sampler: when enabled, every `every`-th launch of each kernel kind opens a
+// window of up to WINDOW consecutive launches of that kind, bracketed by two HIP events
+// recorded on the launch stream (one event pair per window, so the event overhead is
+// spread over its launches); another kind's launch closes the window early. Durations are
+// collected when queried. Off by default (no events in the hot loop).
 // ----------------------------------------------------------------------------------------
 // fwd_vel, fwd_str, adj_vel and adj_str are the 3D half steps; fwd_step and adj_step are the
 // fused 2D forward and transposed steps.
@@ -110,6 +112,7 @@ const char* const kKernelNames[KK_COUNT] = {"fwd_vel", "fwd_str",     "adj_vel",
 
 class Sampler {
  public:
+  static constexpr int WINDOW = 8;
   void enable(int every) {
     std::lock_guard<std::mutex> lock(mu_);
     every_ = every;
@@ -118,35 +121,53 @@ class Sampler {
   hipError_t run(int kind, hipStream_t st, F&& launch) {
     if (every_ <= 0) return launch();
     std::unique_lock<std::mutex> lock(mu_);
-    const bool take = (launched_[kind]++ % every_) == 0;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (take) {
-      hipError_t e = get_event(&a);
-      if (e == hipSuccess) e = get_event(&b);
-      if (e != hipSuccess) return e;
-      e = hipEventRecord(a, st);
-      if (e != hipSuccess) return e;
+    for (int k = 0; k < KK_COUNT; ++k) {  // another kind's launch closes an open window
+      Window& o = open_[k];
+      if (k != kind && o.active) {
+        hipError_t e = hipEventRecord(o.b, o.st);
+        if (e != hipSuccess) return e;
+        pending_[k].push_back(o);
+        o.active = false;
+      }
     }
+    Window& w = open_[kind];
+    if (!w.active && (launched_[kind] % std::max(every_, WINDOW)) == 0) {
+      hipError_t e = get_event(&w.a);
+      if (e == hipSuccess) e = get_event(&w.b);
+      if (e == hipSuccess) e = hipEventRecord(w.a, st);
+      if (e != hipSuccess) return e;
+      w.active = true;
+      w.valid = true;
+      w.count = 0;
+      w.st = st;
+    }
+    ++launched_[kind];
     lock.unlock();
     hipError_t e = launch();
-    if (e != hipSuccess || !take) return e;
-    e = hipEventRecord(b, st);
+    if (e != hipSuccess) return e;
     lock.lock();
-    pending_[kind].push_back({a, b});
+    if (w.active && w.st != st) w.valid = false;   // a window times one stream
+    if (w.active && ++w.count == WINDOW) {
+      e = hipEventRecord(w.b, st);
+      pending_[kind].push_back(w);
+      w.active = false;
+    }
     return e;
   }
   hipError_t query(int kind, long* launched, long* timed, double* total_ms) {
     std::lock_guard<std::mutex> lock(mu_);
-    for (auto& pr : pending_[kind]) {
-      hipError_t e = hipEventSynchronize(pr.second);
+    for (auto& w : pending_[kind]) {
+      hipError_t e = hipEventSynchronize(w.b);
       if (e != hipSuccess) return e;
-      float ms = 0.f;
-      e = hipEventElapsedTime(&ms, pr.first, pr.second);
-      if (e != hipSuccess) return e;
-      total_ms_[kind] += ms;
-      ++timed_[kind];
-      free_.push_back(pr.first);
-      free_.push_back(pr.second);
+      if (w.valid) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, w.a, w.b);
+        if (e != hipSuccess) return e;
+        total_ms_[kind] += ms;
+        timed_[kind] += w.count;
+      }
+      free_.push_back(w.a);
+      free_.push_back(w.b);
     }
     pending_[kind].clear();
     *launched = launched_[kind];
@@ -157,13 +178,14 @@ class Sampler {
   hipError_t reset() {
     std::lock_guard<std::mutex> lock(mu_);
     for (int k = 0; k < KK_COUNT; ++k) {
-      for (auto& pr : pending_[k]) {
-        hipError_t e = hipEventSynchronize(pr.second);
+      for (auto& w : pending_[k]) {
+        hipError_t e = hipEventSynchronize(w.b);
         if (e != hipSuccess) return e;
-        free_.push_back(pr.first);
-        free_.push_back(pr.second);
+        free_.push_back(w.a);
+        free_.push_back(w.b);
       }
       pending_[k].clear();
+      if (open_[k].active) open_[k].valid = false;
       launched_[k] = timed_[k] = 0;
       total_ms_[k] = 0.0;
     }
@@ -171,6 +193,12 @@ class Sampler {
   }
 
  private:
+  struct Window {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st = nullptr;
+    int count = 0;
+    bool active = false, valid = false;
+  };
   hipError_t get_event(hipEvent_t* ev) {
     if (!free_.empty()) {
       *ev = free_.back();
@@ -184,7 +212,8 @@ class Sampler {
   long launched_[KK_COUNT] = {};
   long timed_[KK_COUNT] = {};
   double total_ms_[KK_COUNT] = {};
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_[KK_COUNT];
+  Window open_[KK_COUNT];
+  std::vector<Window> pending_[KK_COUNT];
   std::vector<hipEvent_t> free_;
 };
 
