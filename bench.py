@@ -331,12 +331,13 @@ def main():  # noqa: C901
     kern = {}
     for name, (launches, timed, ms) in timing.items():
         if launches:
-            kern[name] = {"launches": launches, "timed": timed, "mean_us": round(ms * 1e3, 2),
-                          "share": None}
-    total_ms = sum(k["launches"] * k["mean_us"] / 1e3 for k in kern.values())
+            kern[name] = {"launches": launches, "timed": timed,
+                          "mean_us": round(ms * 1e3, 2) if timed else None, "share": None}
+    total_ms = sum(k["launches"] * k["mean_us"] / 1e3 for k in kern.values() if k["mean_us"])
     for k in kern.values():
-        k["share"] = round(k["launches"] * k["mean_us"] / 1e3 / total_ms, 4)
-    dominant = max((n for n in kern if n in KERNEL_BYTES), key=lambda n: kern[n]["share"])
+        if k["mean_us"]:
+            k["share"] = round(k["launches"] * k["mean_us"] / 1e3 / total_ms, 4)
+    dominant = max((n for n in kern if n in KERNEL_BYTES and kern[n]["share"]), key=lambda n: kern[n]["share"])
     bytes_launch = kernel_bytes_per_launch(dominant, nz * nx, nt, L)
     achieved = bytes_launch / (kern[dominant]["mean_us"] * 1e-6) / 1e9
     mt = MEASURED_TRAFFIC.get(dominant)

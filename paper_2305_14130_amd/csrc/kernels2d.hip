@@ -439,9 +439,6 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
 #pragma unroll
   for (int k = 0; k < NV; ++k) L[k] = vel_loads<PML>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
   const VelLoads H = vel_loads<PML>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
-  StrLoads SL[NSR];
-#pragma unroll
-  for (int k = 0; k < NSR; ++k) SL[k] = str_loads<PML>(p, s, i0 + tyu + k * BZ, j0 + tx);
   const float f_xx = s.src[n], f_zz = s.src[s.nt + n], f_xz = s.src[2 * s.nt + n];
 
   // ---- 1. staged sigma to LDS ----
@@ -487,7 +484,11 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
   if ((tid >> 2) < VR) vel(hv, hcol, H, false);
   __syncthreads();
 
-  // ---- 3. stresses of the tile ----
+  // ---- 3. stresses of the tile (their parameter loads issued here, after the velocity
+  //         phase, to bound the live registers) ----
+  StrLoads SL[NSR];
+#pragma unroll
+  for (int k = 0; k < NSR; ++k) SL[k] = str_loads<PML>(p, s, i0 + tyu + k * BZ, j0 + tx);
 #pragma unroll
   for (int k = 0; k < NSR; ++k) {
     const int i = i0 + tyu + k * BZ, j = j0 + tx;
@@ -580,7 +581,11 @@ struct AdjTile {
   static constexpr int SR = TZ + 8, SC = BX + 8;  // p_bar: rows i0-4 .. i0+TZ+3, columns j0-4 .. j0+67
   static constexpr int VR = TZ + 4, VC = BX + 4;  // u_bar, q_bar: rows i0-2 .. i0+TZ+1, columns j0-2 .. j0+65
   static constexpr int NP = SR * SC, NU = VR * VC;
-  static constexpr int LDS_FLOATS = 4 * NP + 6 * NU;
+  // interior tiles: 3 p_bar arrays, then u_bar (2); CPML tiles: 4 p_bar arrays, then (after a
+  // barrier) u_bar and the 4 q_bar operands over the same space
+  static constexpr int LDS_INT = 3 * NP + 2 * NU;
+  static constexpr int LDS_PML = (4 * NP > 6 * NU) ? 4 * NP : 6 * NU;
+  static constexpr int LDS_FLOATS = LDS_INT > LDS_PML ? LDS_INT : LDS_PML;
 };
 
 struct AdjPtrs {
@@ -744,7 +749,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   float* OZ1 = lds + NP;
   float* OX1 = lds + 2 * NP;
   float* OZ0 = PML ? lds + 3 * NP : OX1;
-  float* UX = lds + 4 * NP;
+  float* UX = PML ? lds : lds + 3 * NP;   // CPML tiles overwrite the staged operands
   float* UZ = UX + NU;
   float* QXA = UZ + NU;      // q_bar operands (CPML tiles): x-differentiated from u_x, u_z,
   float* QZA = QXA + NU;     // z-differentiated from u_x, u_z
@@ -836,7 +841,10 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   __syncthreads();
 
   // ---- 2. u_bar on the tile and a 2-node halo ----
-  auto ubar = [&](int vr, int lcol, const UbLoads& L, bool owned) {
+  struct UbOut {
+    float ux, uz, qxa, qza, qxb, qzb;
+  };
+  auto ubar = [&](int vr, int lcol, const UbLoads& L, bool owned) -> UbOut {
     const int gi = i0 - 2 + vr, gj = j0 - 2 + lcol;
     const int sr = vr + 2, sc = lcol + 2;   // LDS p_bar coordinates of the node
     const float ux_d = K1 * (OX0[sr * SC + sc + 1] - OX0[sr * SC + sc]) +
@@ -860,8 +868,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
     const float bx = 2.0f * rcpf(L.r0 + L.rx), bz = 2.0f * rcpf(L.r0 + L.rz);
     const float m = in ? 1.0f : 0.0f;
     const float uxn = m * (L.ux + bx * gx), uzn = m * (L.uz + bz * gz);
-    UX[vr * VC + lcol] = uxn;
-    UZ[vr * VC + lcol] = uzn;
+    UbOut out{uxn, uzn, 0.0f, 0.0f, 0.0f, 0.0f};
     int sx = -1, sz = -1;
     if (PML) {  // corrected q_bar operands: dt u (+ a (psi_bar + dt u) inside the strips)
       const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
@@ -869,10 +876,10 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       sz = strip_index(ic, p.nz, s.P);
       const float mx = sx >= 0 ? 1.0f : 0.0f, mz = sz >= 0 ? 1.0f : 0.0f;
       const float dux = dt * uxn, duz = dt * uzn;
-      QXA[vr * VC + lcol] = m * (dux + (mx * G(p.axh, (unsigned)jc)) * (L.q1 + dux));
-      QZA[vr * VC + lcol] = m * (duz + (mx * G(p.axi, (unsigned)jc)) * (L.q2 + duz));
-      QXB[vr * VC + lcol] = m * (dux + (mz * G(p.azi, (unsigned)ic)) * (L.q3 + dux));
-      QZB[vr * VC + lcol] = m * (duz + (mz * G(p.azh, (unsigned)ic)) * (L.q4 + duz));
+      out.qxa = m * (dux + (mx * G(p.axh, (unsigned)jc)) * (L.q1 + dux));
+      out.qza = m * (duz + (mx * G(p.axi, (unsigned)jc)) * (L.q2 + duz));
+      out.qxb = m * (dux + (mz * G(p.azi, (unsigned)ic)) * (L.q3 + dux));
+      out.qzb = m * (duz + (mz * G(p.azh, (unsigned)ic)) * (L.q4 + duz));
     }
     if (owned) {
       const unsigned o = pofs(p, gi, gj);
@@ -891,13 +898,31 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
         }
       }
     }
+    return out;
   };
+  auto put = [&](int vr, int lcol, const UbOut& o) {
+    UX[vr * VC + lcol] = o.ux;
+    UZ[vr * VC + lcol] = o.uz;
+    if (PML) {
+      QXA[vr * VC + lcol] = o.qxa;
+      QZA[vr * VC + lcol] = o.qza;
+      QXB[vr * VC + lcol] = o.qxb;
+      QZB[vr * VC + lcol] = o.qzb;
+    }
+  };
+  UbOut uo[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int vr = ty + k * BZ, gi = i0 - 2 + vr;
-    ubar(vr, tx + 2, UL[k], gi >= i0 && gi < i0 + TZ && gi < p.nz && j0 + tx < p.nx);
+    uo[k] = ubar(vr, tx + 2, UL[k], gi >= i0 && gi < i0 + TZ && gi < p.nz && j0 + tx < p.nx);
   }
-  if ((tid >> 2) < VR) ubar(hv, hcol, UH, false);
+  const bool has_halo = (tid >> 2) < VR;
+  UbOut ho{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (has_halo) ho = ubar(hv, hcol, UH, false);
+  if (PML) __syncthreads();   // every thread is done reading the staged operands
+#pragma unroll
+  for (int k = 0; k < NV; ++k) put(ty + k * BZ, tx + 2, uo[k]);
+  if (has_halo) put(hv, hcol, ho);
   __syncthreads();
 
   // ---- 3. t_bar, memory variables and imaging at the tile's normal nodes (their loads
