@@ -672,7 +672,9 @@ __device__ __forceinline__ UbLoads ub_loads(const AdjPtrs& p, const Shot2D& s, i
 struct TbLoads {
   float txx, tzz, txz, lam, mu, mu_x, mu_z, mu_xz;
   float r1, r2, r3, r4;      // stress-side adjoint memory variables of step n + 1 (CPML)
-  float h0, h1, e_nb, h3m, h3, h4m, h4, a0, a1, a2;   // imaging inputs
+  float h0, h1, h3m, h3, h4m, h4, a0, a1, a2;   // imaging inputs
+  float h2[4], c2[4], tq[4];  // around the node's four shear nodes: stored h2, how often the
+                              // node's mu is used, t_bar_xz (CPML tiles; else from LDS)
 };
 
 // `edges`: the node may sit on the grid's first or clamped last row or column (tiles that
@@ -700,22 +702,21 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
     L.r3 = G(p.rpz[Z_ZZ], qz);
     L.r4 = G(p.rpz[Z_XZ], qz);
   }
-  L.h0 = L.h1 = L.e_nb = L.h3m = L.h3 = L.h4m = L.h4 = L.a0 = L.a1 = L.a2 = 0.0f;
+  L.h0 = L.h1 = L.h3m = L.h3 = L.h4m = L.h4 = L.a0 = L.a1 = L.a2 = 0.0f;
   if (GRAD) {
     const unsigned cc = (unsigned)(ic * s.cp + jc), cells = (unsigned)s.cells;
     L.h0 = G(p.seg, cc);
     L.h1 = G(p.seg, cells + cc);
-    // shear nodes (a, b), a in {i-1, i}, b in {j-1, j}: t_bar_xz (step n + 1) times the
-    // stored (pzx + pxz) mu_xz / 4, weighted by how often mu_xz(a, b) uses mu(i, j)
-    float e = 0.0f;
-    for (int a = ic - 1; a <= ic; ++a) {
-      for (int b = jc - 1; b <= jc; ++b) {
-        const float c = edges ? (float)corner_count(a, b, ic, jc, p.nz, p.nx) : 1.0f;
-        const int aa = edges ? max(a, 0) : a, bb = edges ? max(b, 0) : b;
-        e += c * G(p.txz, pofs(p, aa, bb)) * G(p.seg, 2 * cells + (unsigned)(aa * s.cp + bb));
-      }
+    // shear nodes (a, b), a in {i-1, i}, b in {j-1, j} (k = 2 (a - i + 1) + b - j + 1): the
+    // stored (pzx + pxz) mu_xz / 4 and how often mu_xz(a, b) uses mu(i, j); t_bar_xz of
+    // step n + 1 there is read here in CPML tiles, from the staged operands otherwise
+    for (int k = 0; k < 4; ++k) {
+      const int a = ic - 1 + (k >> 1), b = jc - 1 + (k & 1);
+      L.c2[k] = edges ? (float)corner_count(a, b, ic, jc, p.nz, p.nx) : 1.0f;
+      const int aa = edges ? max(a, 0) : a, bb = edges ? max(b, 0) : b;
+      L.h2[k] = G(p.seg, 2 * cells + (unsigned)(aa * s.cp + bb));
+      L.tq[k] = PML ? G(p.txz, pofs(p, aa, bb)) : 0.0f;
     }
-    L.e_nb = e;
     const int jm = max(jc - 1, 0), im = max(ic - 1, 0);
     L.h3m = G(p.seg, 3 * cells + (unsigned)(ic * s.cp + jm));
     L.h3 = G(p.seg, 3 * cells + cc);
@@ -758,11 +759,6 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   const int hv = min(tid >> 2, VR - 1), hc = tid & 3;
   const int hcol = hc < 2 ? hc : VC - 4 + hc;     // LDS u column 0, 1, 66, 67
 
-  // ---- loads of the velocity and stress nodes, issued first ----
-  UbLoads UL[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) UL[k] = ub_loads<PML>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
-  const UbLoads UH = ub_loads<PML>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
 
   // ---- 1. stage p_bar ----
   if (!PML) {
@@ -838,6 +834,12 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       }
     }
   }
+  // loads of the velocity nodes, issued before the barrier (after the staging loads, whose
+  // registers are free by now)
+  UbLoads UL[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) UL[k] = ub_loads<PML>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
+  const UbLoads UH = ub_loads<PML>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
   __syncthreads();
 
   // ---- 2. u_bar on the tile and a 2-node halo ----
@@ -971,7 +973,15 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
     G(p.wtxz, o) = L.txz + mxz * dsxz;
     if (GRAD) {
       const unsigned cc = (unsigned)(i * s.cp + j), cells = (unsigned)s.cells;
-      const float e = (L.txx - L.tzz) * L.h1 + L.e_nb;
+      float e = (L.txx - L.tzz) * L.h1;
+      const int so = (vr + 2) * SC + tx + 4;   // LDS p_bar coordinates of the node
+      const float rdt = 1.0f / dt;
+      for (int q = 0; q < 4; ++q) {
+        // the same arithmetic either way (the staged operand is dt t_bar_xz), so the result
+        // does not depend on which tiles take the CPML path
+        const float txz = rdt * (PML ? dt * L.tq[q] : OX1[so + ((q >> 1) - 1) * SC + (q & 1) - 1]);
+        e += L.c2[q] * txz * L.h2[q];
+      }
       // vx nodes (i, j-1/2), (i, j+1/2) and vz nodes (i-1/2, j), (i+1/2, j) around rho(i, j)
       const float c0 = edges ? (float)pair_count(j - 1, j, p.nx) : 1.0f;
       const float c1 = edges ? (float)pair_count(j, j, p.nx) : 1.0f;
