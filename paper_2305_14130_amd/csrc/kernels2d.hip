@@ -205,16 +205,19 @@ struct VelLoads {
   float p1, p2, p3, p4;        // velocity-side memory variables (CPML tiles)
 };
 
-template <bool PML>
+// EDGE: the tile may reach the grid's edges (clamp indices, mask outside nodes); tiles away
+// from every edge skip both. Neighbours at a fixed offset are addressed through a shifted
+// uniform base, so the lane offset is shared by all of a node's loads.
+template <bool PML, bool EDGE>
 __device__ __forceinline__ VelLoads vel_loads(const StepPtrs& p, const Shot2D& s, int gi, int gj) {
   VelLoads L;
-  const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
+  const int ic = EDGE ? min(max(gi, 0), p.nz - 1) : gi, jc = EDGE ? min(max(gj, 0), p.nx - 1) : gj;
   const unsigned o = pofs(p, ic, jc);
   L.vx = G(p.vx, o);
   L.vz = G(p.vz, o);
   L.r0 = G(p.rho, o);
-  L.rx = G(p.rho, o + 1);
-  L.rz = G(p.rho, o + p.ld);
+  L.rx = G(p.rho + 1, o);
+  L.rz = G(p.rho + p.ld, o);
   L.p1 = L.p2 = L.p3 = L.p4 = 0.0f;
   if (PML) {
     const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
@@ -230,11 +233,11 @@ __device__ __forceinline__ VelLoads vel_loads(const StepPtrs& p, const Shot2D& s
 // Velocity node (gi, gj): the four stress differences d1 = D+x sxx, d2 = D-z sxz (vx) and
 // d3 = D-x sxz, d4 = D+z szz (vz) come from LDS. Returns v^{n+1/2} (0 outside the grid);
 // with `owned`, writes v, the memory variables and the stored divergences.
-template <bool STORE, bool PML>
+template <bool STORE, bool PML, bool EDGE>
 __device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int gi, int gj, bool owned,
                                          const VelLoads& L, float d1, float d2, float d3, float d4, float& vxn,
                                          float& vzn) {
-  const bool in = gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx;
+  const bool in = !EDGE || (gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx);
   int sx = -1, sz = -1;
   float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f, p4 = 0.0f;
   if (PML) {
@@ -256,9 +259,14 @@ __device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int
   }
   const float qx = d1 + d2, qz = d3 + d4;
   const float bx = 2.0f * rcpf(L.r0 + L.rx), bz = 2.0f * rcpf(L.r0 + L.rz);
-  const float m = in ? 1.0f : 0.0f;
-  vxn = m * (L.vx + s.dt * bx * qx);
-  vzn = m * (L.vz + s.dt * bz * qz);
+  if (EDGE) {
+    const float m = in ? 1.0f : 0.0f;
+    vxn = m * (L.vx + s.dt * bx * qx);
+    vzn = m * (L.vz + s.dt * bz * qz);
+  } else {
+    vxn = L.vx + s.dt * bx * qx;
+    vzn = L.vz + s.dt * bz * qz;
+  }
   if (owned) {
     const unsigned o = pofs(p, gi, gj);
     G(p.wvx, o) = vxn;
@@ -290,16 +298,16 @@ struct StrLoads {
   float p1, p2, p3, p4;        // stress-side memory variables (CPML tiles)
 };
 
-template <bool PML>
+template <bool PML, bool EDGE>
 __device__ __forceinline__ StrLoads str_loads(const StepPtrs& p, const Shot2D& s, int gi, int gj) {
   StrLoads L;
-  const int ic = min(gi, p.nz - 1), jc = min(gj, p.nx - 1);
+  const int ic = EDGE ? min(gi, p.nz - 1) : gi, jc = EDGE ? min(gj, p.nx - 1) : gj;
   const unsigned o = pofs(p, ic, jc);
   L.lam = G(p.lam, o);
   L.mu = G(p.mu, o);
-  L.mu_x = G(p.mu, o + 1);
-  L.mu_z = G(p.mu, o + p.ld);
-  L.mu_xz = G(p.mu, o + p.ld + 1);
+  L.mu_x = G(p.mu + 1, o);
+  L.mu_z = G(p.mu + p.ld, o);
+  L.mu_xz = G(p.mu + p.ld + 1, o);
   L.p1 = L.p2 = L.p3 = L.p4 = 0.0f;
   if (PML) {
     const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
@@ -380,7 +388,7 @@ __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int
   }
 }
 
-template <int TZ, bool STORE, bool RECORD, bool PML>
+template <int TZ, bool STORE, bool RECORD, bool PML, bool EDGE>
 __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, int n, gfloat* seg, float* lds) {
   using T = StepTile<TZ>;
   constexpr int SR = T::SR, SC = T::SC, VR = T::VR, VC = T::VC, NS = T::NS;
@@ -430,15 +438,15 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int f = min(sf[k], 2);   // past the last field only when e >= NQ: load a valid float4
-    const int ic = min(max(i0 - 4 + sr_[k], 0), p.nz - 1);
+    const int ic = EDGE ? min(max(i0 - 4 + sr_[k], 0), p.nz - 1) : i0 - 4 + sr_[k];
     const gfloat* src = f == 0 ? p.sxx : f == 1 ? p.szz : p.sxz;
     typedef const __attribute__((address_space(1))) char gchar;
     sv[k] = *(const __attribute__((address_space(1))) f4*)((gchar*)src + pofs(p, ic, j0 - 4 + 4 * sc4[k]) * 4u);
   }
   VelLoads L[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) L[k] = vel_loads<PML>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
-  const VelLoads H = vel_loads<PML>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
+  for (int k = 0; k < NV; ++k) L[k] = vel_loads<PML, EDGE>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
+  const VelLoads H = vel_loads<PML, EDGE>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
   const float f_xx = s.src[n], f_zz = s.src[s.nt + n], f_xz = s.src[2 * s.nt + n];
 
   // ---- 1. staged sigma to LDS ----
@@ -447,12 +455,14 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
     if (sf[k] < 3) {
       const int f = sf[k], r = sr_[k], c4 = sc4[k];
       const int gi = i0 - 4 + r, gj = j0 - 4 + 4 * c4;
-      const bool row_in = gi >= 0 && gi < p.nz;
-      f4 v;
-      v.x = (row_in && gj + 0 >= 0 && gj + 0 < p.nx) ? sv[k].x : 0.0f;
-      v.y = (row_in && gj + 1 >= 0 && gj + 1 < p.nx) ? sv[k].y : 0.0f;
-      v.z = (row_in && gj + 2 >= 0 && gj + 2 < p.nx) ? sv[k].z : 0.0f;
-      v.w = (row_in && gj + 3 >= 0 && gj + 3 < p.nx) ? sv[k].w : 0.0f;
+      f4 v = sv[k];
+      if (EDGE) {
+        const bool row_in = gi >= 0 && gi < p.nz;
+        v.x = (row_in && gj + 0 >= 0 && gj + 0 < p.nx) ? v.x : 0.0f;
+        v.y = (row_in && gj + 1 >= 0 && gj + 1 < p.nx) ? v.y : 0.0f;
+        v.z = (row_in && gj + 2 >= 0 && gj + 2 < p.nx) ? v.z : 0.0f;
+        v.w = (row_in && gj + 3 >= 0 && gj + 3 < p.nx) ? v.w : 0.0f;
+      }
       *(f4*)(lds + f * SR * SC + r * SC + 4 * c4) = v;
     }
   }
@@ -472,14 +482,14 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
     const float d4 = (K1 * (SZZ[(sr + 1) * SC + sc] - SZZ[sr * SC + sc]) +
                       K2 * (SZZ[(sr + 2) * SC + sc] - SZZ[(sr - 1) * SC + sc])) * s.rdz;
     float vxn, vzn;
-    vel_node<STORE, PML>(p, s, gi, gj, owned, LL, d1, d2, d3, d4, vxn, vzn);
+    vel_node<STORE, PML, EDGE>(p, s, gi, gj, owned, LL, d1, d2, d3, d4, vxn, vzn);
     VXL[vr * VC + lcol] = vxn;
     VZL[vr * VC + lcol] = vzn;
   };
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int vr = ty + k * BZ, gi = i0 - 2 + vr;
-    vel(vr, tx + 2, L[k], gi >= i0 && gi < i0 + TZ && gi < p.nz && j0 + tx < p.nx);
+    vel(vr, tx + 2, L[k], gi >= i0 && gi < i0 + TZ && (!EDGE || (gi < p.nz && j0 + tx < p.nx)));
   }
   if ((tid >> 2) < VR) vel(hv, hcol, H, false);
   __syncthreads();
@@ -488,11 +498,11 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
   //         phase, to bound the live registers) ----
   StrLoads SL[NSR];
 #pragma unroll
-  for (int k = 0; k < NSR; ++k) SL[k] = str_loads<PML>(p, s, i0 + tyu + k * BZ, j0 + tx);
+  for (int k = 0; k < NSR; ++k) SL[k] = str_loads<PML, EDGE>(p, s, i0 + tyu + k * BZ, j0 + tx);
 #pragma unroll
   for (int k = 0; k < NSR; ++k) {
     const int i = i0 + tyu + k * BZ, j = j0 + tx;
-    if (i >= p.nz || j >= p.nx) continue;
+    if (EDGE && (i >= p.nz || j >= p.nx)) continue;
     const int vr = tyu + k * BZ + 2, vc = tx + 2;   // LDS velocity coordinates of the node
     const float* X = VXL + vr * VC + vc;
     const float* Z = VZL + vr * VC + vc;
@@ -515,8 +525,11 @@ __global__ __launch_bounds__(BX * BZ) void k_fwd_step(STEP_PARAMS, int n, int ks
   const Shot2D& s = shots[sh_];
   gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG_FIELDS * s.cells : nullptr;
   // block-uniform branch: every thread reaches the barriers
-  if (block_in_pml(s, j0, i0, TZ, 2)) fwd_step_tile<TZ, STORE, RECORD, true>(s, i0, j0, n, seg, lds);
-  else fwd_step_tile<TZ, STORE, RECORD, false>(s, i0, j0, n, seg, lds);
+  // Tiles clear of the strips are at least P >= 2 nodes from every edge, so with CPML
+  // their staged halo lies inside the grid.
+  if (block_in_pml(s, j0, i0, TZ, 2)) fwd_step_tile<TZ, STORE, RECORD, true, true>(s, i0, j0, n, seg, lds);
+  else if (s.P < 2) fwd_step_tile<TZ, STORE, RECORD, false, true>(s, i0, j0, n, seg, lds);
+  else fwd_step_tile<TZ, STORE, RECORD, false, false>(s, i0, j0, n, seg, lds);
 }
 
 // ------------------------------------------------------------------------------------
@@ -643,19 +656,19 @@ struct UbLoads {
   float q1, q2, q3, q4;      // velocity-side adjoint memory variables of step n + 1 (CPML)
 };
 
-template <bool PML>
+template <bool PML, bool EDGE>
 __device__ __forceinline__ UbLoads ub_loads(const AdjPtrs& p, const Shot2D& s, int gi, int gj) {
   UbLoads L;
-  const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
+  const int ic = EDGE ? min(max(gi, 0), p.nz - 1) : gi, jc = EDGE ? min(max(gj, 0), p.nx - 1) : gj;
   const unsigned o = pofs(p, ic, jc);
-  const bool in = gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx;
+  const bool in = !EDGE || (gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx);
   const int slot = s.row_slot[ic];
   L.slot = in ? slot : -1;
   L.ux = G(p.ux, o);
   L.uz = G(p.uz, o);
   L.r0 = G(p.rho, o);
-  L.rx = G(p.rho, o + 1);
-  L.rz = G(p.rho, o + p.ld);
+  L.rx = G(p.rho + 1, o);
+  L.rz = G(p.rho + p.ld, o);
   L.q1 = L.q2 = L.q3 = L.q4 = 0.0f;
   if (PML) {
     const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
@@ -677,22 +690,21 @@ struct TbLoads {
                               // node's mu is used, t_bar_xz (CPML tiles; else from LDS)
 };
 
-// `edges`: the node may sit on the grid's first or clamped last row or column (tiles that
+// EDGE: the node may sit on the grid's first or clamped last row or column (tiles that
 // touch a CPML strip, or any tile without CPML); elsewhere every count below is 1.
-template <bool GRAD, bool PML>
-__device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, int gi, int gj, bool first,
-                                            bool edges) {
+template <bool GRAD, bool PML, bool EDGE>
+__device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, int gi, int gj, bool first) {
   TbLoads L;
-  const int ic = min(gi, p.nz - 1), jc = min(gj, p.nx - 1);
+  const int ic = EDGE ? min(gi, p.nz - 1) : gi, jc = EDGE ? min(gj, p.nx - 1) : gj;
   const unsigned o = pofs(p, ic, jc);
   L.txx = G(p.txx, o);
   L.tzz = G(p.tzz, o);
   L.txz = G(p.txz, o);
   L.lam = G(p.lam, o);
   L.mu = G(p.mu, o);
-  L.mu_x = G(p.mu, o + 1);
-  L.mu_z = G(p.mu, o + p.ld);
-  L.mu_xz = G(p.mu, o + p.ld + 1);
+  L.mu_x = G(p.mu + 1, o);
+  L.mu_z = G(p.mu + p.ld, o);
+  L.mu_xz = G(p.mu + p.ld + 1, o);
   L.r1 = L.r2 = L.r3 = L.r4 = 0.0f;
   if (PML) {
     const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
@@ -712,15 +724,26 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
     // step n + 1 there is read here in CPML tiles, from the staged operands otherwise
     for (int k = 0; k < 4; ++k) {
       const int a = ic - 1 + (k >> 1), b = jc - 1 + (k & 1);
-      L.c2[k] = edges ? (float)corner_count(a, b, ic, jc, p.nz, p.nx) : 1.0f;
-      const int aa = edges ? max(a, 0) : a, bb = edges ? max(b, 0) : b;
-      L.h2[k] = G(p.seg, 2 * cells + (unsigned)(aa * s.cp + bb));
-      L.tq[k] = PML ? G(p.txz, pofs(p, aa, bb)) : 0.0f;
+      if (EDGE) {
+        L.c2[k] = (float)corner_count(a, b, ic, jc, p.nz, p.nx);
+        const int aa = max(a, 0), bb = max(b, 0);
+        L.h2[k] = G(p.seg, 2 * cells + (unsigned)(aa * s.cp + bb));
+        L.tq[k] = PML ? G(p.txz, pofs(p, aa, bb)) : 0.0f;
+      } else {  // a shifted uniform base: the lane offset cc serves all four
+        L.c2[k] = 1.0f;
+        L.h2[k] = G(p.seg + 2 * s.cells + ((k >> 1) - 1) * s.cp + (k & 1) - 1, cc);
+        L.tq[k] = 0.0f;
+      }
     }
-    const int jm = max(jc - 1, 0), im = max(ic - 1, 0);
-    L.h3m = G(p.seg, 3 * cells + (unsigned)(ic * s.cp + jm));
+    if (EDGE) {
+      const int jm = max(jc - 1, 0), im = max(ic - 1, 0);
+      L.h3m = G(p.seg, 3 * cells + (unsigned)(ic * s.cp + jm));
+      L.h4m = G(p.seg, 4 * cells + (unsigned)(im * s.cp + jc));
+    } else {
+      L.h3m = G(p.seg + 3 * s.cells - 1, cc);
+      L.h4m = G(p.seg + 4 * s.cells - s.cp, cc);
+    }
     L.h3 = G(p.seg, 3 * cells + cc);
-    L.h4m = G(p.seg, 4 * cells + (unsigned)(im * s.cp + jc));
     L.h4 = G(p.seg, 4 * cells + cc);
     if (!first) {
       L.a0 = G(p.acc, cc);
@@ -731,7 +754,7 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
   return L;
 }
 
-template <int TZ, bool GRAD, bool SRCADJ, bool PML>
+template <int TZ, bool GRAD, bool SRCADJ, bool PML, bool EDGE>
 __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, int n, int kseg, bool first,
                                               float* lds) {
   using T = AdjTile<TZ>;
@@ -782,7 +805,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int f = min(sf[k], 2);
-      const int ic = min(max(i0 - 4 + sr_[k], 0), p.nz - 1);
+      const int ic = EDGE ? min(max(i0 - 4 + sr_[k], 0), p.nz - 1) : i0 - 4 + sr_[k];
       const gfloat* src = f == 0 ? p.txx : f == 1 ? p.tzz : p.txz;
       sv[k] = *(const __attribute__((address_space(1))) f4*)((gchar*)src + pofs(p, ic, j0 - 4 + 4 * sc4[k]) * 4u);
     }
@@ -791,12 +814,14 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       if (sf[k] < 3) {
         const int f = sf[k], r = sr_[k], c4 = sc4[k];
         const int gi = i0 - 4 + r, gj = j0 - 4 + 4 * c4;
-        const bool row_in = gi >= 0 && gi < p.nz;
-        f4 v;
-        v.x = (row_in && gj + 0 >= 0 && gj + 0 < p.nx) ? dt * sv[k].x : 0.0f;
-        v.y = (row_in && gj + 1 >= 0 && gj + 1 < p.nx) ? dt * sv[k].y : 0.0f;
-        v.z = (row_in && gj + 2 >= 0 && gj + 2 < p.nx) ? dt * sv[k].z : 0.0f;
-        v.w = (row_in && gj + 3 >= 0 && gj + 3 < p.nx) ? dt * sv[k].w : 0.0f;
+        f4 v = dt * sv[k];
+        if (EDGE) {
+          const bool row_in = gi >= 0 && gi < p.nz;
+          v.x = (row_in && gj + 0 >= 0 && gj + 0 < p.nx) ? v.x : 0.0f;
+          v.y = (row_in && gj + 1 >= 0 && gj + 1 < p.nx) ? v.y : 0.0f;
+          v.z = (row_in && gj + 2 >= 0 && gj + 2 < p.nx) ? v.z : 0.0f;
+          v.w = (row_in && gj + 3 >= 0 && gj + 3 < p.nx) ? v.w : 0.0f;
+        }
         *(f4*)(lds + f * NP + r * SC + 4 * c4) = v;
       }
     }
@@ -838,8 +863,8 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   // registers are free by now)
   UbLoads UL[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) UL[k] = ub_loads<PML>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
-  const UbLoads UH = ub_loads<PML>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
+  for (int k = 0; k < NV; ++k) UL[k] = ub_loads<PML, EDGE>(p, s, i0 - 2 + ty + k * BZ, j0 + tx);
+  const UbLoads UH = ub_loads<PML, EDGE>(p, s, i0 - 2 + hv, j0 - 2 + hcol);
   __syncthreads();
 
   // ---- 2. u_bar on the tile and a 2-node halo ----
@@ -857,7 +882,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
                        K2 * (OZ1[(sr + 2) * SC + sc] - OZ1[(sr - 1) * SC + sc]);
     const float wx_d = K1 * (OX1[sr * SC + sc] - OX1[sr * SC + sc - 1]) +
                        K2 * (OX1[sr * SC + sc + 1] - OX1[sr * SC + sc - 2]);
-    const bool in = gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx;
+    const bool in = !EDGE || (gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx);
     // DAS transpose: the channel at normal node jc feeds vx nodes jc (c1), jc-1 (-c1),
     // jc+1 (c2) and jc-2 (-c2) of its row
     float inj = 0.0f;
@@ -916,7 +941,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int vr = ty + k * BZ, gi = i0 - 2 + vr;
-    uo[k] = ubar(vr, tx + 2, UL[k], gi >= i0 && gi < i0 + TZ && gi < p.nz && j0 + tx < p.nx);
+    uo[k] = ubar(vr, tx + 2, UL[k], gi >= i0 && gi < i0 + TZ && (!EDGE || (gi < p.nz && j0 + tx < p.nx)));
   }
   const bool has_halo = (tid >> 2) < VR;
   UbOut ho{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
@@ -930,13 +955,12 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   // ---- 3. t_bar, memory variables and imaging at the tile's normal nodes (their loads
   //         issued here, after the velocity phase, to bound the live registers) ----
   TbLoads TL[NSR];
-  const bool edges = PML || s.P == 0;
 #pragma unroll
-  for (int k = 0; k < NSR; ++k) TL[k] = tb_loads<GRAD, PML>(p, s, i0 + tyu + k * BZ, j0 + tx, first, edges);
+  for (int k = 0; k < NSR; ++k) TL[k] = tb_loads<GRAD, PML, EDGE>(p, s, i0 + tyu + k * BZ, j0 + tx, first);
 #pragma unroll
   for (int k = 0; k < NSR; ++k) {
     const int i = i0 + tyu + k * BZ, j = j0 + tx;
-    if (i >= p.nz || j >= p.nx) continue;
+    if (EDGE && (i >= p.nz || j >= p.nx)) continue;
     const TbLoads& L = TL[k];
     const int vr = tyu + k * BZ + 2, vc = tx + 2;   // LDS u coordinates of the node
     const int u0 = vr * VC + vc;
@@ -983,10 +1007,10 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
         e += L.c2[q] * txz * L.h2[q];
       }
       // vx nodes (i, j-1/2), (i, j+1/2) and vz nodes (i-1/2, j), (i+1/2, j) around rho(i, j)
-      const float c0 = edges ? (float)pair_count(j - 1, j, p.nx) : 1.0f;
-      const float c1 = edges ? (float)pair_count(j, j, p.nx) : 1.0f;
-      const float c2 = edges ? (float)pair_count(i - 1, i, p.nz) : 1.0f;
-      const float c3 = edges ? (float)pair_count(i, i, p.nz) : 1.0f;
+      const float c0 = EDGE ? (float)pair_count(j - 1, j, p.nx) : 1.0f;
+      const float c1 = EDGE ? (float)pair_count(j, j, p.nx) : 1.0f;
+      const float c2 = EDGE ? (float)pair_count(i - 1, i, p.nz) : 1.0f;
+      const float c3 = EDGE ? (float)pair_count(i, i, p.nz) : 1.0f;
       float r = c0 * UX[u0 - 1] * L.h3m;
       r += c1 * UX[u0] * L.h3;
       r += c2 * UZ[u0 - VC] * L.h4m;
@@ -1023,9 +1047,12 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_step(STEP_PARAMS, int n, int ks
   if (!batch_tile<TZ>(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;
   const Shot2D& s = shots[sh_];
   // block-uniform branch: every thread reaches the barriers. The staged p_bar operands
-  // reach 4 nodes beyond the tile, so tiles within 4 nodes of a strip take the CPML path.
-  if (block_in_pml(s, j0, i0, TZ, 4)) adj_step_tile<TZ, GRAD, SRCADJ, true>(s, i0, j0, n, kseg, first != 0, lds);
-  else adj_step_tile<TZ, GRAD, SRCADJ, false>(s, i0, j0, n, kseg, first != 0, lds);
+  // reach 4 nodes beyond the tile, so tiles within 4 nodes of a strip take the CPML path;
+  // with strips at all four edges every other tile and its 4-node halo lie inside the
+  // grid and skip the edge handling (only a grid without strips needs it there).
+  if (block_in_pml(s, j0, i0, TZ, 4)) adj_step_tile<TZ, GRAD, SRCADJ, true, true>(s, i0, j0, n, kseg, first != 0, lds);
+  else if (s.P < 1) adj_step_tile<TZ, GRAD, SRCADJ, false, true>(s, i0, j0, n, kseg, first != 0, lds);
+  else adj_step_tile<TZ, GRAD, SRCADJ, false, false>(s, i0, j0, n, kseg, first != 0, lds);
 }
 
 // ------------------------------------------------------------------------------------
