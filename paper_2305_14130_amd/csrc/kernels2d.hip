@@ -598,7 +598,10 @@ struct AdjTile {
   // barrier) u_bar and the 4 q_bar operands over the same space
   static constexpr int LDS_INT = 3 * NP + 2 * NU;
   static constexpr int LDS_PML = (4 * NP > 6 * NU) ? 4 * NP : 6 * NU;
-  static constexpr int LDS_FLOATS = LDS_INT > LDS_PML ? LDS_INT : LDS_PML;
+  static constexpr int LDS_MAIN = LDS_INT > LDS_PML ? LDS_INT : LDS_PML;
+  // then t_bar_xx, t_bar_zz, t_bar_xz of the tile's own nodes, copied while staging: the
+  // transposed stress update reads them from here rather than from HBM a second time
+  static constexpr int LDS_FLOATS = LDS_MAIN + 3 * TZ * BX;
 };
 
 struct AdjPtrs {
@@ -683,7 +686,7 @@ __device__ __forceinline__ UbLoads ub_loads(const AdjPtrs& p, const Shot2D& s, i
 
 // Inputs of one t_bar node (loads only).
 struct TbLoads {
-  float txx, tzz, txz, lam, mu, mu_x, mu_z, mu_xz;
+  float lam, mu, mu_x, mu_z, mu_xz;
   float r1, r2, r3, r4;      // stress-side adjoint memory variables of step n + 1 (CPML)
   float h0, h1, h3m, h3, h4m, h4, a0, a1, a2;   // imaging inputs
   float h2[4], c2[4], tq[4];  // around the node's four shear nodes: stored h2, how often the
@@ -697,9 +700,6 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
   TbLoads L;
   const int ic = EDGE ? min(gi, p.nz - 1) : gi, jc = EDGE ? min(gj, p.nx - 1) : gj;
   const unsigned o = pofs(p, ic, jc);
-  L.txx = G(p.txx, o);
-  L.tzz = G(p.tzz, o);
-  L.txz = G(p.txz, o);
   L.lam = G(p.lam, o);
   L.mu = G(p.mu, o);
   L.mu_x = G(p.mu + 1, o);
@@ -779,6 +779,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   float* QZA = QXA + NU;     // z-differentiated from u_x, u_z
   float* QXB = QZA + NU;
   float* QZB = QXB + NU;
+  float* TO = lds + T::LDS_MAIN;   // own t_bar_xx, t_bar_zz, t_bar_xz (TZ x 64 each)
   const int hv = min(tid >> 2, VR - 1), hc = tid & 3;
   const int hcol = hc < 2 ? hc : VC - 4 + hc;     // LDS u column 0, 1, 66, 67
 
@@ -823,6 +824,8 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
           v.w = (row_in && gj + 3 >= 0 && gj + 3 < p.nx) ? v.w : 0.0f;
         }
         *(f4*)(lds + f * NP + r * SC + 4 * c4) = v;
+        if (r >= 4 && r < 4 + TZ && c4 >= 1 && c4 <= BX / 4)
+          *(f4*)(TO + f * TZ * BX + (r - 4) * BX + 4 * (c4 - 1)) = sv[k];
       }
     }
   } else {
@@ -836,7 +839,8 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       const gfloat* prof = op == 0 ? p.axi : op == 1 ? p.axh : op == 2 ? p.azh : p.azi;
       const gfloat* psi = op == 0 ? p.rpx[X_XX] : op == 1 ? p.rpx[X_XZ] : op == 2 ? p.rpz[Z_XZ] : p.rpz[Z_ZZ];
       float* dst = op == 0 ? OX0 : op == 1 ? OX1 : op == 2 ? OZ0 : OZ1;
-      float v[PER];
+      float* own = TO + (op == 0 ? 0 : op == 3 ? 1 : 2) * TZ * BX;
+      float v[PER], raw[PER];
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         const int e = min(tid + k * NT, NP - 1);
@@ -846,7 +850,8 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
         const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
         const int sidx = xaxis ? strip_index(jc, p.nx, s.P) : strip_index(ic, p.nz, s.P);
         const int sc = max(sidx, 0);
-        const float val = dt * G(f, pofs(p, ic, jc));
+        raw[k] = G(f, pofs(p, ic, jc));
+        const float val = dt * raw[k];
         const float ps = G(psi, xaxis ? (unsigned)(ic * p.P2 + sc) : (unsigned)(sc * p.nx + jc));
         const float ac = G(prof, (unsigned)(xaxis ? jc : ic));
         const float m_in = in ? 1.0f : 0.0f, m_strip = sidx >= 0 ? 1.0f : 0.0f;
@@ -855,7 +860,11 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         const int e = tid + k * NT;
-        if (e < NP) dst[e] = v[k];
+        if (e < NP) {
+          dst[e] = v[k];
+          const int r = e / SC, c = e - r * SC;
+          if (op != 2 && r >= 4 && r < 4 + TZ && c >= 4 && c < 4 + BX) own[(r - 4) * BX + c - 4] = raw[k];
+        }
       }
     }
   }
@@ -962,6 +971,8 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
     const int i = i0 + tyu + k * BZ, j = j0 + tx;
     if (EDGE && (i >= p.nz || j >= p.nx)) continue;
     const TbLoads& L = TL[k];
+    const int ow = (tyu + k * BZ) * BX + tx;
+    const float txx = TO[ow], tzz = TO[TZ * BX + ow], txz = TO[2 * TZ * BX + ow];
     const int vr = tyu + k * BZ + 2, vc = tx + 2;   // LDS u coordinates of the node
     const int u0 = vr * VC + vc;
     // q operands: interior tiles read dt u_bar directly
@@ -983,21 +994,21 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       const int sx = strip_index(j, p.nx, s.P), sz = strip_index(i, p.nz, s.P);
       if (sx >= 0) {
         const unsigned q = (unsigned)(i * p.P2 + sx);
-        G(p.wpx[X_XX], q) = G(p.bxi, (unsigned)j) * (L.r1 + dt * L.txx);
-        G(p.wpx[X_XZ], q) = G(p.bxh, (unsigned)j) * (L.r2 + dt * L.txz);
+        G(p.wpx[X_XX], q) = G(p.bxi, (unsigned)j) * (L.r1 + dt * txx);
+        G(p.wpx[X_XZ], q) = G(p.bxh, (unsigned)j) * (L.r2 + dt * txz);
       }
       if (sz >= 0) {
         const unsigned q = (unsigned)(sz * p.nx + j);
-        G(p.wpz[Z_ZZ], q) = G(p.bzi, (unsigned)i) * (L.r3 + dt * L.tzz);
-        G(p.wpz[Z_XZ], q) = G(p.bzh, (unsigned)i) * (L.r4 + dt * L.txz);
+        G(p.wpz[Z_ZZ], q) = G(p.bzi, (unsigned)i) * (L.r3 + dt * tzz);
+        G(p.wpz[Z_XZ], q) = G(p.bzh, (unsigned)i) * (L.r4 + dt * txz);
       }
     }
-    G(p.wtxx, o) = L.txx + (l2m * dsxx + lam * dszz);
-    G(p.wtzz, o) = L.tzz + (lam * dsxx + l2m * dszz);
-    G(p.wtxz, o) = L.txz + mxz * dsxz;
+    G(p.wtxx, o) = txx + (l2m * dsxx + lam * dszz);
+    G(p.wtzz, o) = tzz + (lam * dsxx + l2m * dszz);
+    G(p.wtxz, o) = txz + mxz * dsxz;
     if (GRAD) {
       const unsigned cc = (unsigned)(i * s.cp + j), cells = (unsigned)s.cells;
-      float e = (L.txx - L.tzz) * L.h1;
+      float e = (txx - tzz) * L.h1;
       const int so = (vr + 2) * SC + tx + 4;   // LDS p_bar coordinates of the node
       const float rdt = 1.0f / dt;
       for (int q = 0; q < 4; ++q) {
@@ -1015,7 +1026,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       r += c1 * UX[u0] * L.h3;
       r += c2 * UZ[u0 - VC] * L.h4m;
       r += c3 * UZ[u0] * L.h4;
-      G(p.acc, cc) = L.a0 + dt * (L.txx + L.tzz) * L.h0;
+      G(p.acc, cc) = L.a0 + dt * (txx + tzz) * L.h0;
       G(p.acc, cells + cc) = L.a1 + dt * e;
       G(p.acc, 2 * cells + cc) = L.a2 - dt * r;
     }
@@ -1023,7 +1034,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       // sigma_bar at the source from t_bar of step n + 1: invert the 2x2 normal block and
       // the shear moduli of the four shear nodes around the source
       const float det = (l2m - lam) * (l2m + lam);
-      const float sb0 = (l2m * L.txx - lam * L.tzz) / det, sb1 = (l2m * L.tzz - lam * L.txx) / det;
+      const float sb0 = (l2m * txx - lam * tzz) / det, sb1 = (l2m * tzz - lam * txx) / det;
       float sb2 = 0.0f;
       for (int a = i - 1; a <= i; ++a) {
         for (int b = j - 1; b <= j; ++b) {
