@@ -202,7 +202,6 @@ __device__ __forceinline__ const auto& G(const P* base, unsigned e) {
 // Inputs of one velocity node (loads only).
 struct VelLoads {
   float vx, vz, r0, rx, rz;
-  float p1, p2, p3, p4;        // velocity-side memory variables (CPML tiles)
 };
 
 // EDGE: the tile may reach the grid's edges (clamp indices, mask outside nodes); tiles away
@@ -218,15 +217,6 @@ __device__ __forceinline__ VelLoads vel_loads(const StepPtrs& p, const Shot2D& s
   L.r0 = G(p.rho, o);
   L.rx = G(p.rho + 1, o);
   L.rz = G(p.rho + p.ld, o);
-  L.p1 = L.p2 = L.p3 = L.p4 = 0.0f;
-  if (PML) {
-    const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
-    const unsigned qx = (unsigned)(ic * p.P2 + sx), qz = (unsigned)(sz * p.nx + jc);
-    L.p1 = G(p.rpx[X_VXX], qx);
-    L.p3 = G(p.rpx[X_VZX], qx);
-    L.p2 = G(p.rpz[Z_VXZ], qz);
-    L.p4 = G(p.rpz[Z_VZZ], qz);
-  }
   return L;
 }
 
@@ -244,10 +234,13 @@ __device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int
     const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
     sx = strip_index(jc, p.nx, s.P);
     sz = strip_index(ic, p.nz, s.P);
-    p1 = G(p.bxh, jc) * L.p1 + G(p.axh, jc) * d1;
-    p3 = G(p.bxi, jc) * L.p3 + G(p.axi, jc) * d3;
-    p2 = G(p.bzi, ic) * L.p2 + G(p.azi, ic) * d2;
-    p4 = G(p.bzh, ic) * L.p4 + G(p.azh, ic) * d4;
+    // the velocity-side memory variables are loaded here, not with the node's other
+    // inputs: CPML tiles keep fewer values live, so every tile kernel fits more waves
+    const unsigned qx = (unsigned)(ic * p.P2 + max(sx, 0)), qz = (unsigned)(max(sz, 0) * p.nx + jc);
+    p1 = G(p.bxh, jc) * G(p.rpx[X_VXX], qx) + G(p.axh, jc) * d1;
+    p3 = G(p.bxi, jc) * G(p.rpx[X_VZX], qx) + G(p.axi, jc) * d3;
+    p2 = G(p.bzi, ic) * G(p.rpz[Z_VXZ], qz) + G(p.azi, ic) * d2;
+    p4 = G(p.bzh, ic) * G(p.rpz[Z_VZZ], qz) + G(p.azh, ic) * d4;
     if (sx >= 0) {
       d1 += p1;
       d3 += p3;
@@ -295,7 +288,6 @@ __device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int
 // looked up in str_node).
 struct StrLoads {
   float lam, mu, mu_x, mu_z, mu_xz;
-  float p1, p2, p3, p4;        // stress-side memory variables (CPML tiles)
 };
 
 template <bool PML, bool EDGE>
@@ -308,15 +300,6 @@ __device__ __forceinline__ StrLoads str_loads(const StepPtrs& p, const Shot2D& s
   L.mu_x = G(p.mu + 1, o);
   L.mu_z = G(p.mu + p.ld, o);
   L.mu_xz = G(p.mu + p.ld + 1, o);
-  L.p1 = L.p2 = L.p3 = L.p4 = 0.0f;
-  if (PML) {
-    const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
-    const unsigned qx = (unsigned)(ic * p.P2 + sx), qz = (unsigned)(sz * p.nx + jc);
-    L.p1 = G(p.rpx[X_XX], qx);
-    L.p2 = G(p.rpx[X_XZ], qx);
-    L.p3 = G(p.rpz[Z_ZZ], qz);
-    L.p4 = G(p.rpz[Z_XZ], qz);
-  }
   return L;
 }
 
@@ -334,10 +317,12 @@ __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int
   if (PML) {
     sx = strip_index(j, p.nx, s.P);
     sz = strip_index(i, p.nz, s.P);
-    p1 = G(p.bxi, j) * L.p1 + G(p.axi, j) * pxx;
-    p2 = G(p.bxh, j) * L.p2 + G(p.axh, j) * pxz;
-    p3 = G(p.bzi, i) * L.p3 + G(p.azi, i) * pzz;
-    p4 = G(p.bzh, i) * L.p4 + G(p.azh, i) * pzx;
+    // memory variables loaded here rather than with the node's inputs (fewer live values)
+    const unsigned qx = (unsigned)(i * p.P2 + max(sx, 0)), qz = (unsigned)(max(sz, 0) * p.nx + j);
+    p1 = G(p.bxi, j) * G(p.rpx[X_XX], qx) + G(p.axi, j) * pxx;
+    p2 = G(p.bxh, j) * G(p.rpx[X_XZ], qx) + G(p.axh, j) * pxz;
+    p3 = G(p.bzi, i) * G(p.rpz[Z_ZZ], qz) + G(p.azi, i) * pzz;
+    p4 = G(p.bzh, i) * G(p.rpz[Z_XZ], qz) + G(p.azh, i) * pzx;
     if (sx >= 0) {
       pxx += p1;
       pxz += p2;
@@ -656,7 +641,6 @@ __device__ __forceinline__ unsigned pofs(const AdjPtrs& p, int i, int j) {
 struct UbLoads {
   int slot;                  // DAS slot of the node's row (-1: none or outside the grid)
   float ux, uz, r0, rx, rz;
-  float q1, q2, q3, q4;      // velocity-side adjoint memory variables of step n + 1 (CPML)
 };
 
 template <bool PML, bool EDGE>
@@ -672,25 +656,15 @@ __device__ __forceinline__ UbLoads ub_loads(const AdjPtrs& p, const Shot2D& s, i
   L.r0 = G(p.rho, o);
   L.rx = G(p.rho + 1, o);
   L.rz = G(p.rho + p.ld, o);
-  L.q1 = L.q2 = L.q3 = L.q4 = 0.0f;
-  if (PML) {
-    const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
-    const unsigned qx = (unsigned)(ic * p.P2 + sx), qz = (unsigned)(sz * p.nx + jc);
-    L.q1 = G(p.rpx[X_VXX], qx);
-    L.q2 = G(p.rpx[X_VZX], qx);
-    L.q3 = G(p.rpz[Z_VXZ], qz);
-    L.q4 = G(p.rpz[Z_VZZ], qz);
-  }
   return L;
 }
 
 // Inputs of one t_bar node (loads only).
 struct TbLoads {
   float lam, mu, mu_x, mu_z, mu_xz;
-  float r1, r2, r3, r4;      // stress-side adjoint memory variables of step n + 1 (CPML)
   float h0, h1, h3m, h3, h4m, h4, a0, a1, a2;   // imaging inputs
-  float h2[4], c2[4], tq[4];  // around the node's four shear nodes: stored h2, how often the
-                              // node's mu is used, t_bar_xz (CPML tiles; else from LDS)
+  float h2[4], c2[4];         // around the node's four shear nodes: stored h2 and how often
+                              // the node's mu is used
 };
 
 // EDGE: the node may sit on the grid's first or clamped last row or column (tiles that
@@ -705,15 +679,6 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
   L.mu_x = G(p.mu + 1, o);
   L.mu_z = G(p.mu + p.ld, o);
   L.mu_xz = G(p.mu + p.ld + 1, o);
-  L.r1 = L.r2 = L.r3 = L.r4 = 0.0f;
-  if (PML) {
-    const int sx = max(strip_index(jc, p.nx, s.P), 0), sz = max(strip_index(ic, p.nz, s.P), 0);
-    const unsigned qx = (unsigned)(ic * p.P2 + sx), qz = (unsigned)(sz * p.nx + jc);
-    L.r1 = G(p.rpx[X_XX], qx);
-    L.r2 = G(p.rpx[X_XZ], qx);
-    L.r3 = G(p.rpz[Z_ZZ], qz);
-    L.r4 = G(p.rpz[Z_XZ], qz);
-  }
   L.h0 = L.h1 = L.h3m = L.h3 = L.h4m = L.h4 = L.a0 = L.a1 = L.a2 = 0.0f;
   if (GRAD) {
     const unsigned cc = (unsigned)(ic * s.cp + jc), cells = (unsigned)s.cells;
@@ -728,11 +693,9 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
         L.c2[k] = (float)corner_count(a, b, ic, jc, p.nz, p.nx);
         const int aa = max(a, 0), bb = max(b, 0);
         L.h2[k] = G(p.seg, 2 * cells + (unsigned)(aa * s.cp + bb));
-        L.tq[k] = PML ? G(p.txz, pofs(p, aa, bb)) : 0.0f;
       } else {  // a shifted uniform base: the lane offset cc serves all four
         L.c2[k] = 1.0f;
         L.h2[k] = G(p.seg + 2 * s.cells + ((k >> 1) - 1) * s.cp + (k & 1) - 1, cc);
-        L.tq[k] = 0.0f;
       }
     }
     if (EDGE) {
@@ -906,16 +869,24 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
     const float uxn = m * (L.ux + bx * gx), uzn = m * (L.uz + bz * gz);
     UbOut out{uxn, uzn, 0.0f, 0.0f, 0.0f, 0.0f};
     int sx = -1, sz = -1;
+    float q1 = 0.0f, q2 = 0.0f, q3 = 0.0f, q4 = 0.0f;
     if (PML) {  // corrected q_bar operands: dt u (+ a (psi_bar + dt u) inside the strips)
       const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
       sx = strip_index(jc, p.nx, s.P);
       sz = strip_index(ic, p.nz, s.P);
+      // velocity-side adjoint memory variables of step n + 1, loaded here rather than with
+      // the node's other inputs (fewer live values in CPML tiles)
+      const unsigned qx = (unsigned)(ic * p.P2 + max(sx, 0)), qz = (unsigned)(max(sz, 0) * p.nx + jc);
+      q1 = G(p.rpx[X_VXX], qx);
+      q2 = G(p.rpx[X_VZX], qx);
+      q3 = G(p.rpz[Z_VXZ], qz);
+      q4 = G(p.rpz[Z_VZZ], qz);
       const float mx = sx >= 0 ? 1.0f : 0.0f, mz = sz >= 0 ? 1.0f : 0.0f;
       const float dux = dt * uxn, duz = dt * uzn;
-      out.qxa = m * (dux + (mx * G(p.axh, (unsigned)jc)) * (L.q1 + dux));
-      out.qza = m * (duz + (mx * G(p.axi, (unsigned)jc)) * (L.q2 + duz));
-      out.qxb = m * (dux + (mz * G(p.azi, (unsigned)ic)) * (L.q3 + dux));
-      out.qzb = m * (duz + (mz * G(p.azh, (unsigned)ic)) * (L.q4 + duz));
+      out.qxa = m * (dux + (mx * G(p.axh, (unsigned)jc)) * (q1 + dux));
+      out.qza = m * (duz + (mx * G(p.axi, (unsigned)jc)) * (q2 + duz));
+      out.qxb = m * (dux + (mz * G(p.azi, (unsigned)ic)) * (q3 + dux));
+      out.qzb = m * (duz + (mz * G(p.azh, (unsigned)ic)) * (q4 + duz));
     }
     if (owned) {
       const unsigned o = pofs(p, gi, gj);
@@ -924,13 +895,13 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       if (PML) {  // owned velocity-side adjoint memory variables
         if (sx >= 0) {
           const unsigned q = (unsigned)(gi * p.P2 + sx);
-          G(p.wpx[X_VXX], q) = G(p.bxh, (unsigned)gj) * (L.q1 + dt * uxn);
-          G(p.wpx[X_VZX], q) = G(p.bxi, (unsigned)gj) * (L.q2 + dt * uzn);
+          G(p.wpx[X_VXX], q) = G(p.bxh, (unsigned)gj) * (q1 + dt * uxn);
+          G(p.wpx[X_VZX], q) = G(p.bxi, (unsigned)gj) * (q2 + dt * uzn);
         }
         if (sz >= 0) {
           const unsigned q = (unsigned)(sz * p.nx + gj);
-          G(p.wpz[Z_VXZ], q) = G(p.bzi, (unsigned)gi) * (L.q3 + dt * uxn);
-          G(p.wpz[Z_VZZ], q) = G(p.bzh, (unsigned)gi) * (L.q4 + dt * uzn);
+          G(p.wpz[Z_VXZ], q) = G(p.bzi, (unsigned)gi) * (q3 + dt * uxn);
+          G(p.wpz[Z_VZZ], q) = G(p.bzh, (unsigned)gi) * (q4 + dt * uzn);
         }
       }
     }
@@ -994,13 +965,15 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       const int sx = strip_index(j, p.nx, s.P), sz = strip_index(i, p.nz, s.P);
       if (sx >= 0) {
         const unsigned q = (unsigned)(i * p.P2 + sx);
-        G(p.wpx[X_XX], q) = G(p.bxi, (unsigned)j) * (L.r1 + dt * txx);
-        G(p.wpx[X_XZ], q) = G(p.bxh, (unsigned)j) * (L.r2 + dt * txz);
+        const float r1 = G(p.rpx[X_XX], q), r2 = G(p.rpx[X_XZ], q);
+        G(p.wpx[X_XX], q) = G(p.bxi, (unsigned)j) * (r1 + dt * txx);
+        G(p.wpx[X_XZ], q) = G(p.bxh, (unsigned)j) * (r2 + dt * txz);
       }
       if (sz >= 0) {
         const unsigned q = (unsigned)(sz * p.nx + j);
-        G(p.wpz[Z_ZZ], q) = G(p.bzi, (unsigned)i) * (L.r3 + dt * tzz);
-        G(p.wpz[Z_XZ], q) = G(p.bzh, (unsigned)i) * (L.r4 + dt * txz);
+        const float r3 = G(p.rpz[Z_ZZ], q), r4 = G(p.rpz[Z_XZ], q);
+        G(p.wpz[Z_ZZ], q) = G(p.bzi, (unsigned)i) * (r3 + dt * tzz);
+        G(p.wpz[Z_XZ], q) = G(p.bzh, (unsigned)i) * (r4 + dt * txz);
       }
     }
     G(p.wtxx, o) = txx + (l2m * dsxx + lam * dszz);
@@ -1014,7 +987,8 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       for (int q = 0; q < 4; ++q) {
         // the same arithmetic either way (the staged operand is dt t_bar_xz), so the result
         // does not depend on which tiles take the CPML path
-        const float txz = rdt * (PML ? dt * L.tq[q] : OX1[so + ((q >> 1) - 1) * SC + (q & 1) - 1]);
+        const int a = max(i - 1 + (q >> 1), 0), b = max(j - 1 + (q & 1), 0);
+        const float txz = rdt * (PML ? dt * G(p.txz, pofs(p, a, b)) : OX1[so + ((q >> 1) - 1) * SC + (q & 1) - 1]);
         e += L.c2[q] * txz * L.h2[q];
       }
       // vx nodes (i, j-1/2), (i, j+1/2) and vz nodes (i-1/2, j), (i+1/2, j) around rho(i, j)
