@@ -144,11 +144,12 @@ struct StepPtrs {
   const gfloat *sxx, *szz, *sxz, *vx, *vz;   // buffer n & 1, padded plane origins
   gfloat *wsxx, *wszz, *wsxz, *wvx, *wvz;    // buffer (n + 1) & 1
   const gfloat *lam, *mu, *rho;              // staged parameters, padded plane origins
-  const gfloat *rpx[4], *rpz[4];             // memory variables of buffer n & 1
-  gfloat *wpx[4], *wpz[4];                   // and of buffer (n + 1) & 1
-  const gfloat *axi, *bxi, *axh, *bxh, *azi, *bzi, *azh, *bzh;
+  const gfloat* rps;                         // memory variables of buffer n & 1 (see xv, zv)
+  gfloat* wps;                               // and of buffer (n + 1) & 1
+  const gfloat* prof;                        // CPML profiles (see xp, zp)
   gfloat* seg;                               // this step's slot of the history (STORE)
   int ld, nx, nz, P2;                        // row pitch, window, strip width 2P
+  unsigned xs, zs;                           // elements of one x-strip and one z-strip array
 };
 
 __device__ __forceinline__ StepPtrs step_ptrs(const Shot2D& s, int n, gfloat* seg) {
@@ -168,16 +169,12 @@ __device__ __forceinline__ StepPtrs step_ptrs(const Shot2D& s, int n, gfloat* se
   p.lam = s.lam - org;
   p.mu = s.mu - org;
   p.rho = s.rho - org;
-  for (int k = 0; k < 4; ++k) {
-    p.rpx[k] = s.psx[k] + rd;
-    p.rpz[k] = s.psz[k] + rd;
-    p.wpx[k] = s.psx[k] + wr;
-    p.wpz[k] = s.psz[k] + wr;
-  }
-  p.axi = axi(s), p.bxi = bxi(s), p.axh = axh(s), p.bxh = bxh(s);
-  p.azi = azi(s), p.bzi = bzi(s), p.azh = azh(s), p.bzh = bzh(s);
+  p.rps = s.psx[0] + rd;
+  p.wps = s.psx[0] + wr;
+  p.prof = s.prof;
   p.seg = seg;
   p.ld = s.ld, p.nx = s.nx, p.nz = s.nz, p.P2 = 2 * s.P;
+  p.xs = (unsigned)(s.nz * 2 * s.P), p.zs = (unsigned)(2 * s.P * s.nx);
   return p;
 }
 
@@ -198,6 +195,20 @@ __device__ __forceinline__ const auto& G(const P* base, unsigned e) {
   typedef const __attribute__((address_space(1))) char gchar;
   return *(const P*)((gchar*)base + e * 4u);
 }
+
+// Element offsets inside the strip block of one buffer (x-strip arrays [nz][2P] of the
+// variables X_*, then z-strip arrays [2P][nx] of the variables Z_*) and inside the profile
+// table (a_x, b_x at integer then half nodes [nx], then the same along z [nz]; k = 0 a at
+// integer nodes, 1 b at integer nodes, 2 a at half nodes, 3 b at half nodes). One base
+// pointer plus 32-bit offsets keeps the CPML paths' scalar registers few.
+template <class P>
+__device__ __forceinline__ unsigned xv(const P& p, int k) { return (unsigned)k * p.xs; }
+template <class P>
+__device__ __forceinline__ unsigned zv(const P& p, int k) { return 4u * p.xs + (unsigned)k * p.zs; }
+template <class P>
+__device__ __forceinline__ unsigned xp(const P& p, int k) { return (unsigned)(k * p.nx); }
+template <class P>
+__device__ __forceinline__ unsigned zp(const P& p, int k) { return (unsigned)(4 * p.nx + k * p.nz); }
 
 // Inputs of one velocity node (loads only).
 struct VelLoads {
@@ -237,10 +248,10 @@ __device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int
     // the velocity-side memory variables are loaded here, not with the node's other
     // inputs: CPML tiles keep fewer values live, so every tile kernel fits more waves
     const unsigned qx = (unsigned)(ic * p.P2 + max(sx, 0)), qz = (unsigned)(max(sz, 0) * p.nx + jc);
-    p1 = G(p.bxh, jc) * G(p.rpx[X_VXX], qx) + G(p.axh, jc) * d1;
-    p3 = G(p.bxi, jc) * G(p.rpx[X_VZX], qx) + G(p.axi, jc) * d3;
-    p2 = G(p.bzi, ic) * G(p.rpz[Z_VXZ], qz) + G(p.azi, ic) * d2;
-    p4 = G(p.bzh, ic) * G(p.rpz[Z_VZZ], qz) + G(p.azh, ic) * d4;
+    p1 = G(p.prof, xp(p, 3) + jc) * G(p.rps, xv(p, X_VXX) + qx) + G(p.prof, xp(p, 2) + jc) * d1;
+    p3 = G(p.prof, xp(p, 1) + jc) * G(p.rps, xv(p, X_VZX) + qx) + G(p.prof, xp(p, 0) + jc) * d3;
+    p2 = G(p.prof, zp(p, 1) + ic) * G(p.rps, zv(p, Z_VXZ) + qz) + G(p.prof, zp(p, 0) + ic) * d2;
+    p4 = G(p.prof, zp(p, 3) + ic) * G(p.rps, zv(p, Z_VZZ) + qz) + G(p.prof, zp(p, 2) + ic) * d4;
     if (sx >= 0) {
       d1 += p1;
       d3 += p3;
@@ -267,13 +278,13 @@ __device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int
     if (PML) {
       if (sx >= 0) {
         const unsigned q = (unsigned)(gi * p.P2 + sx);
-        G(p.wpx[X_VXX], q) = p1;
-        G(p.wpx[X_VZX], q) = p3;
+        G(p.wps, xv(p, X_VXX) + q) = p1;
+        G(p.wps, xv(p, X_VZX) + q) = p3;
       }
       if (sz >= 0) {
         const unsigned q = (unsigned)(sz * p.nx + gj);
-        G(p.wpz[Z_VXZ], q) = p2;
-        G(p.wpz[Z_VZZ], q) = p4;
+        G(p.wps, zv(p, Z_VXZ) + q) = p2;
+        G(p.wps, zv(p, Z_VZZ) + q) = p4;
       }
     }
     if (STORE) {  // divergences times b/2: the rho imaging terms (d b / d rho = -b^2/2)
@@ -319,10 +330,10 @@ __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int
     sz = strip_index(i, p.nz, s.P);
     // memory variables loaded here rather than with the node's inputs (fewer live values)
     const unsigned qx = (unsigned)(i * p.P2 + max(sx, 0)), qz = (unsigned)(max(sz, 0) * p.nx + j);
-    p1 = G(p.bxi, j) * G(p.rpx[X_XX], qx) + G(p.axi, j) * pxx;
-    p2 = G(p.bxh, j) * G(p.rpx[X_XZ], qx) + G(p.axh, j) * pxz;
-    p3 = G(p.bzi, i) * G(p.rpz[Z_ZZ], qz) + G(p.azi, i) * pzz;
-    p4 = G(p.bzh, i) * G(p.rpz[Z_XZ], qz) + G(p.azh, i) * pzx;
+    p1 = G(p.prof, xp(p, 1) + j) * G(p.rps, xv(p, X_XX) + qx) + G(p.prof, xp(p, 0) + j) * pxx;
+    p2 = G(p.prof, xp(p, 3) + j) * G(p.rps, xv(p, X_XZ) + qx) + G(p.prof, xp(p, 2) + j) * pxz;
+    p3 = G(p.prof, zp(p, 1) + i) * G(p.rps, zv(p, Z_ZZ) + qz) + G(p.prof, zp(p, 0) + i) * pzz;
+    p4 = G(p.prof, zp(p, 3) + i) * G(p.rps, zv(p, Z_XZ) + qz) + G(p.prof, zp(p, 2) + i) * pzx;
     if (sx >= 0) {
       pxx += p1;
       pxz += p2;
@@ -344,13 +355,13 @@ __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int
   if (PML) {
     if (sx >= 0) {
       const unsigned q = (unsigned)(i * p.P2 + sx);
-      G(p.wpx[X_XX], q) = p1;
-      G(p.wpx[X_XZ], q) = p2;
+      G(p.wps, xv(p, X_XX) + q) = p1;
+      G(p.wps, xv(p, X_XZ) + q) = p2;
     }
     if (sz >= 0) {
       const unsigned q = (unsigned)(sz * p.nx + j);
-      G(p.wpz[Z_ZZ], q) = p3;
-      G(p.wpz[Z_XZ], q) = p4;
+      G(p.wps, zv(p, Z_ZZ) + q) = p3;
+      G(p.wps, zv(p, Z_XZ) + q) = p4;
     }
   }
   const unsigned o = pofs(p, i, j);
@@ -593,12 +604,13 @@ struct AdjPtrs {
   const gfloat *txx, *tzz, *txz, *ux, *uz;   // adjoint buffer (n + 1) & 1, padded plane origins
   gfloat *wtxx, *wtzz, *wtxz, *wux, *wuz;    // buffer n & 1
   const gfloat *lam, *mu, *rho;              // staged parameters, padded plane origins
-  const gfloat *rpx[4], *rpz[4];             // adjoint memory variables of step n + 1
-  gfloat *wpx[4], *wpz[4];                   // and of step n
-  const gfloat *axi, *bxi, *axh, *bxh, *azi, *bzi, *azh, *bzh;
+  const gfloat* rps;                         // adjoint memory variables of step n + 1 (see xv, zv)
+  gfloat* wps;                               // and of step n
+  const gfloat* prof;                        // CPML profiles (see xp, zp)
   const gfloat* seg;                         // history slot of step n (imaging)
   gfloat* acc;
   int ld, nx, nz, P2;
+  unsigned xs, zs;
 };
 
 __device__ __forceinline__ AdjPtrs adj_ptrs(const Shot2D& s, int n, int kseg) {
@@ -619,17 +631,13 @@ __device__ __forceinline__ AdjPtrs adj_ptrs(const Shot2D& s, int n, int kseg) {
   p.lam = s.lam - org;
   p.mu = s.mu - org;
   p.rho = s.rho - org;
-  for (int k = 0; k < 4; ++k) {
-    p.rpx[k] = s.pbx[prd][k];
-    p.rpz[k] = s.pbz[prd][k];
-    p.wpx[k] = s.pbx[pwr][k];
-    p.wpz[k] = s.pbz[pwr][k];
-  }
-  p.axi = axi(s), p.bxi = bxi(s), p.axh = axh(s), p.bxh = bxh(s);
-  p.azi = azi(s), p.bzi = bzi(s), p.azh = azh(s), p.bzh = bzh(s);
+  p.rps = s.pbx[prd][0];
+  p.wps = s.pbx[pwr][0];
+  p.prof = s.prof;
   p.seg = s.seg ? s.seg + (size_t)kseg * NSEG_FIELDS * s.cells : nullptr;
   p.acc = s.acc;
   p.ld = s.ld, p.nx = s.nx, p.nz = s.nz, p.P2 = 2 * s.P;
+  p.xs = (unsigned)(s.nz * 2 * s.P), p.zs = (unsigned)(2 * s.P * s.nx);
   return p;
 }
 
@@ -799,8 +807,8 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
     for (int op = 0; op < 4; ++op) {
       const gfloat* f = op == 0 ? p.txx : op == 3 ? p.tzz : p.txz;
       const bool xaxis = op < 2;
-      const gfloat* prof = op == 0 ? p.axi : op == 1 ? p.axh : op == 2 ? p.azh : p.azi;
-      const gfloat* psi = op == 0 ? p.rpx[X_XX] : op == 1 ? p.rpx[X_XZ] : op == 2 ? p.rpz[Z_XZ] : p.rpz[Z_ZZ];
+      const unsigned prof = op == 0 ? xp(p, 0) : op == 1 ? xp(p, 2) : op == 2 ? zp(p, 2) : zp(p, 0);
+      const unsigned psi = op == 0 ? xv(p, X_XX) : op == 1 ? xv(p, X_XZ) : op == 2 ? zv(p, Z_XZ) : zv(p, Z_ZZ);
       float* dst = op == 0 ? OX0 : op == 1 ? OX1 : op == 2 ? OZ0 : OZ1;
       float* own = TO + (op == 0 ? 0 : op == 3 ? 1 : 2) * TZ * BX;
       float v[PER], raw[PER];
@@ -815,8 +823,8 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
         const int sc = max(sidx, 0);
         raw[k] = G(f, pofs(p, ic, jc));
         const float val = dt * raw[k];
-        const float ps = G(psi, xaxis ? (unsigned)(ic * p.P2 + sc) : (unsigned)(sc * p.nx + jc));
-        const float ac = G(prof, (unsigned)(xaxis ? jc : ic));
+        const float ps = G(p.rps, psi + (xaxis ? (unsigned)(ic * p.P2 + sc) : (unsigned)(sc * p.nx + jc)));
+        const float ac = G(p.prof, prof + (unsigned)(xaxis ? jc : ic));
         const float m_in = in ? 1.0f : 0.0f, m_strip = sidx >= 0 ? 1.0f : 0.0f;
         v[k] = m_in * (val + (m_strip * ac) * (ps + val));
       }
@@ -877,16 +885,16 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       // velocity-side adjoint memory variables of step n + 1, loaded here rather than with
       // the node's other inputs (fewer live values in CPML tiles)
       const unsigned qx = (unsigned)(ic * p.P2 + max(sx, 0)), qz = (unsigned)(max(sz, 0) * p.nx + jc);
-      q1 = G(p.rpx[X_VXX], qx);
-      q2 = G(p.rpx[X_VZX], qx);
-      q3 = G(p.rpz[Z_VXZ], qz);
-      q4 = G(p.rpz[Z_VZZ], qz);
+      q1 = G(p.rps, xv(p, X_VXX) + qx);
+      q2 = G(p.rps, xv(p, X_VZX) + qx);
+      q3 = G(p.rps, zv(p, Z_VXZ) + qz);
+      q4 = G(p.rps, zv(p, Z_VZZ) + qz);
       const float mx = sx >= 0 ? 1.0f : 0.0f, mz = sz >= 0 ? 1.0f : 0.0f;
       const float dux = dt * uxn, duz = dt * uzn;
-      out.qxa = m * (dux + (mx * G(p.axh, (unsigned)jc)) * (q1 + dux));
-      out.qza = m * (duz + (mx * G(p.axi, (unsigned)jc)) * (q2 + duz));
-      out.qxb = m * (dux + (mz * G(p.azi, (unsigned)ic)) * (q3 + dux));
-      out.qzb = m * (duz + (mz * G(p.azh, (unsigned)ic)) * (q4 + duz));
+      out.qxa = m * (dux + (mx * G(p.prof, xp(p, 2) + (unsigned)jc)) * (q1 + dux));
+      out.qza = m * (duz + (mx * G(p.prof, xp(p, 0) + (unsigned)jc)) * (q2 + duz));
+      out.qxb = m * (dux + (mz * G(p.prof, zp(p, 0) + (unsigned)ic)) * (q3 + dux));
+      out.qzb = m * (duz + (mz * G(p.prof, zp(p, 2) + (unsigned)ic)) * (q4 + duz));
     }
     if (owned) {
       const unsigned o = pofs(p, gi, gj);
@@ -895,13 +903,13 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       if (PML) {  // owned velocity-side adjoint memory variables
         if (sx >= 0) {
           const unsigned q = (unsigned)(gi * p.P2 + sx);
-          G(p.wpx[X_VXX], q) = G(p.bxh, (unsigned)gj) * (q1 + dt * uxn);
-          G(p.wpx[X_VZX], q) = G(p.bxi, (unsigned)gj) * (q2 + dt * uzn);
+          G(p.wps, xv(p, X_VXX) + q) = G(p.prof, xp(p, 3) + (unsigned)gj) * (q1 + dt * uxn);
+          G(p.wps, xv(p, X_VZX) + q) = G(p.prof, xp(p, 1) + (unsigned)gj) * (q2 + dt * uzn);
         }
         if (sz >= 0) {
           const unsigned q = (unsigned)(sz * p.nx + gj);
-          G(p.wpz[Z_VXZ], q) = G(p.bzi, (unsigned)gi) * (q3 + dt * uxn);
-          G(p.wpz[Z_VZZ], q) = G(p.bzh, (unsigned)gi) * (q4 + dt * uzn);
+          G(p.wps, zv(p, Z_VXZ) + q) = G(p.prof, zp(p, 1) + (unsigned)gi) * (q3 + dt * uxn);
+          G(p.wps, zv(p, Z_VZZ) + q) = G(p.prof, zp(p, 3) + (unsigned)gi) * (q4 + dt * uzn);
         }
       }
     }
@@ -965,15 +973,15 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       const int sx = strip_index(j, p.nx, s.P), sz = strip_index(i, p.nz, s.P);
       if (sx >= 0) {
         const unsigned q = (unsigned)(i * p.P2 + sx);
-        const float r1 = G(p.rpx[X_XX], q), r2 = G(p.rpx[X_XZ], q);
-        G(p.wpx[X_XX], q) = G(p.bxi, (unsigned)j) * (r1 + dt * txx);
-        G(p.wpx[X_XZ], q) = G(p.bxh, (unsigned)j) * (r2 + dt * txz);
+        const float r1 = G(p.rps, xv(p, X_XX) + q), r2 = G(p.rps, xv(p, X_XZ) + q);
+        G(p.wps, xv(p, X_XX) + q) = G(p.prof, xp(p, 1) + (unsigned)j) * (r1 + dt * txx);
+        G(p.wps, xv(p, X_XZ) + q) = G(p.prof, xp(p, 3) + (unsigned)j) * (r2 + dt * txz);
       }
       if (sz >= 0) {
         const unsigned q = (unsigned)(sz * p.nx + j);
-        const float r3 = G(p.rpz[Z_ZZ], q), r4 = G(p.rpz[Z_XZ], q);
-        G(p.wpz[Z_ZZ], q) = G(p.bzi, (unsigned)i) * (r3 + dt * tzz);
-        G(p.wpz[Z_XZ], q) = G(p.bzh, (unsigned)i) * (r4 + dt * txz);
+        const float r3 = G(p.rps, zv(p, Z_ZZ) + q), r4 = G(p.rps, zv(p, Z_XZ) + q);
+        G(p.wps, zv(p, Z_ZZ) + q) = G(p.prof, zp(p, 1) + (unsigned)i) * (r3 + dt * tzz);
+        G(p.wps, zv(p, Z_XZ) + q) = G(p.prof, zp(p, 3) + (unsigned)i) * (r4 + dt * txz);
       }
     }
     G(p.wtxx, o) = txx + (l2m * dsxx + lam * dszz);
