@@ -570,7 +570,8 @@ size_t wave_bytes(const std::vector<Plan2D>& plans, int first, int count) {
   return t;
 }
 
-// Cut `weight` into NUM_XCD contiguous runs of equal total and write the schedule.
+// Cut `weight` into NUM_XCD contiguous runs of equal total and write the schedule: slot
+// m * NUM_XCD + k holds the m-th tile of XCD k's run (workgroups go to the XCDs round robin).
 efwi_status build_sched(const std::vector<int>& weight, int* sched, int& nsched) {
   const int ntiles = (int)weight.size();
   long wtot = 0;
@@ -585,8 +586,15 @@ efwi_status build_sched(const std::vector<int>& weight, int* sched, int& nsched)
   int maxrun = 0;
   for (int k = 0; k < NUM_XCD; ++k) maxrun = std::max(maxrun, cut[k + 1] - cut[k]);
   if ((size_t)maxrun * NUM_XCD > sched_capacity(ntiles)) return fail(EFWI_E_INVAL, "tile schedule overflow");
+  // inside a run the costlier tiles go first (the rest in list order), so that an XCD does
+  // not end its share of the launch on a few slow tiles near a strip
+  std::vector<int> order(ntiles);
+  for (int q = 0; q < ntiles; ++q) order[q] = q;
+  for (int k = 0; k < NUM_XCD; ++k)
+    std::stable_sort(order.begin() + cut[k], order.begin() + cut[k + 1],
+                     [&](int a, int b) { return weight[a] > weight[b]; });
   for (int m = 0; m < maxrun; ++m)
-    for (int k = 0; k < NUM_XCD; ++k) sched[m * NUM_XCD + k] = (cut[k] + m < cut[k + 1]) ? cut[k] + m : -1;
+    for (int k = 0; k < NUM_XCD; ++k) sched[m * NUM_XCD + k] = (cut[k] + m < cut[k + 1]) ? order[cut[k] + m] : -1;
   nsched = maxrun * NUM_XCD;
   return EFWI_OK;
 }
