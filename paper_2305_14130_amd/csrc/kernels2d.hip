@@ -196,6 +196,19 @@ __device__ __forceinline__ const auto& G(const P* base, unsigned e) {
   return *(const P*)((gchar*)base + e * 4u);
 }
 
+// Streaming (non-temporal) accesses of the history: written once per forward step, read
+// once in the reverse sweep.
+template <class P>
+__device__ __forceinline__ void GS(P* base, unsigned e, float v) {
+  typedef __attribute__((address_space(1))) char gchar;
+  __builtin_nontemporal_store(v, (P*)((gchar*)base + e * 4u));
+}
+template <class P>
+__device__ __forceinline__ float GL(const P* base, unsigned e) {
+  typedef const __attribute__((address_space(1))) char gchar;
+  return __builtin_nontemporal_load((const P*)((gchar*)base + e * 4u));
+}
+
 // Element offsets inside the strip block of one buffer (x-strip arrays [nz][2P] of the
 // variables X_*, then z-strip arrays [2P][nx] of the variables Z_*) and inside the profile
 // table (a_x, b_x at integer then half nodes [nx], then the same along z [nz]; k = 0 a at
@@ -289,8 +302,8 @@ __device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int
     }
     if (STORE) {  // divergences times b/2: the rho imaging terms (d b / d rho = -b^2/2)
       const unsigned c = (unsigned)(gi * s.cp + gj);
-      G(p.seg, 3 * s.cells + c) = 0.5f * qx * bx;
-      G(p.seg, 4 * s.cells + c) = 0.5f * qz * bz;
+      GS(p.seg, 3 * s.cells + c, 0.5f * qx * bx);
+      GS(p.seg, 4 * s.cells + c, 0.5f * qz * bz);
     }
   }
 }
@@ -378,9 +391,9 @@ __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int
   }
   if (STORE) {  // strain rates times the factors of the lambda and mu imaging terms
     const unsigned c = (unsigned)(i * s.cp + j);
-    G(p.seg, c) = (pxx + pzz) / (l2m + lam);
-    G(p.seg, s.cells + c) = 0.5f * (pxx - pzz) * mu;
-    G(p.seg, 2 * s.cells + c) = 0.25f * ps * mxz;
+    GS(p.seg, c, (pxx + pzz) / (l2m + lam));
+    GS(p.seg, s.cells + c, 0.5f * (pxx - pzz) * mu);
+    GS(p.seg, 2 * s.cells + c, 0.25f * ps * mxz);
   }
 }
 
@@ -690,8 +703,8 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
   L.h0 = L.h1 = L.h3m = L.h3 = L.h4m = L.h4 = L.a0 = L.a1 = L.a2 = 0.0f;
   if (GRAD) {
     const unsigned cc = (unsigned)(ic * s.cp + jc), cells = (unsigned)s.cells;
-    L.h0 = G(p.seg, cc);
-    L.h1 = G(p.seg, cells + cc);
+    L.h0 = GL(p.seg, cc);
+    L.h1 = GL(p.seg, cells + cc);
     // shear nodes (a, b), a in {i-1, i}, b in {j-1, j} (k = 2 (a - i + 1) + b - j + 1): the
     // stored (pzx + pxz) mu_xz / 4 and how often mu_xz(a, b) uses mu(i, j); t_bar_xz of
     // step n + 1 there is read here in CPML tiles, from the staged operands otherwise
@@ -700,22 +713,22 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
       if (EDGE) {
         L.c2[k] = (float)corner_count(a, b, ic, jc, p.nz, p.nx);
         const int aa = max(a, 0), bb = max(b, 0);
-        L.h2[k] = G(p.seg, 2 * cells + (unsigned)(aa * s.cp + bb));
+        L.h2[k] = GL(p.seg, 2 * cells + (unsigned)(aa * s.cp + bb));
       } else {  // a shifted uniform base: the lane offset cc serves all four
         L.c2[k] = 1.0f;
-        L.h2[k] = G(p.seg + 2 * s.cells + ((k >> 1) - 1) * s.cp + (k & 1) - 1, cc);
+        L.h2[k] = GL(p.seg + 2 * s.cells + ((k >> 1) - 1) * s.cp + (k & 1) - 1, cc);
       }
     }
     if (EDGE) {
       const int jm = max(jc - 1, 0), im = max(ic - 1, 0);
-      L.h3m = G(p.seg, 3 * cells + (unsigned)(ic * s.cp + jm));
-      L.h4m = G(p.seg, 4 * cells + (unsigned)(im * s.cp + jc));
+      L.h3m = GL(p.seg, 3 * cells + (unsigned)(ic * s.cp + jm));
+      L.h4m = GL(p.seg, 4 * cells + (unsigned)(im * s.cp + jc));
     } else {
-      L.h3m = G(p.seg + 3 * s.cells - 1, cc);
-      L.h4m = G(p.seg + 4 * s.cells - s.cp, cc);
+      L.h3m = GL(p.seg + 3 * s.cells - 1, cc);
+      L.h4m = GL(p.seg + 4 * s.cells - s.cp, cc);
     }
-    L.h3 = G(p.seg, 3 * cells + cc);
-    L.h4 = G(p.seg, 4 * cells + cc);
+    L.h3 = GL(p.seg, 3 * cells + cc);
+    L.h4 = GL(p.seg, 4 * cells + cc);
     if (!first) {
       L.a0 = G(p.acc, cc);
       L.a1 = G(p.acc, cells + cc);
@@ -1084,13 +1097,22 @@ __global__ __launch_bounds__(BX * BZ) void k_chain_flush(BATCH_PARAMS) {
   if (i >= s.nz || j >= s.nx) return;
   const long cc = (long)i * s.cp + j;
   const long mo = (long)i * s.mld + j;
-  const double vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
+  // the model and the FP64 sums are touched once per flush: streaming accesses keep them
+  // from displacing the time-step state in the caches
+  const double vp = __builtin_nontemporal_load(s.mvp + mo), vs = __builtin_nontemporal_load(s.mvs + mo);
+  const double rho = __builtin_nontemporal_load(s.mrho + mo);
   const double mu = rho * vs * vs;
   const double gl = s.acc[cc];
   const double gmu = gl + (mu > 0.0 ? (double)s.acc[s.cells + cc] / (mu * mu) : 0.0);
-  s.G[cc] += 2.0 * rho * vp * gl;
-  s.G[s.cells + cc] += 2.0 * rho * vs * (gmu - 2.0 * gl);
-  s.G[2 * s.cells + cc] += (vp * vp - 2.0 * vs * vs) * gl + vs * vs * gmu + (double)s.acc[2 * s.cells + cc];
+  gdouble* G0 = s.G + cc;
+  gdouble* G1 = s.G + s.cells + cc;
+  gdouble* G2 = s.G + 2 * s.cells + cc;
+  const double g0 = __builtin_nontemporal_load(G0), g1 = __builtin_nontemporal_load(G1);
+  const double g2 = __builtin_nontemporal_load(G2);
+  __builtin_nontemporal_store(g0 + 2.0 * rho * vp * gl, G0);
+  __builtin_nontemporal_store(g1 + 2.0 * rho * vs * (gmu - 2.0 * gl), G1);
+  __builtin_nontemporal_store(g2 + ((vp * vp - 2.0 * vs * vs) * gl + vs * vs * gmu + (double)s.acc[2 * s.cells + cc]),
+                              G2);
 }
 
 __global__ __launch_bounds__(BX * BZ) void k_write_gradient(BATCH_PARAMS) {
