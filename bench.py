@@ -18,7 +18,9 @@ each with their gradient's relative L2 distance from the FP32 one, and the batch
 Metric: Gcell-updates/s = shots * nz * nx * nt / wall time (fwd + adj + grad), inputs
 resident in HBM before the timed region. The JSON line also carries:
 * roofline: the dominant kernel's algorithmic bytes per launch over its mean launch time
-  (HIP events around sampled launches on the library's stream), against 8 TB/s;
+  (HIP events around sampled launches on the library's stream), against 8 TB/s, and the
+  HBM traffic per launch that rocprofv3's counters measured for that kernel and tile shape
+  on this grid (null when no such measurement applies);
 * cpu_baseline: the FP64 NumPy oracle on a bounded sample (one shot, full grid, a few
   time steps), in the same unit;
 * path: the whole step's algorithmic bytes (168 B per cell-step plus 52 B per recomputed
@@ -52,11 +54,26 @@ HBM_PEAK_GBS = 8000.0
 # (u_bar = b v_bar and t_bar = C sigma_bar are the scaled adjoint variables; the imaging
 # sums are gathered at the normal node.)
 KERNEL_BYTES = {"fwd_step": (52, 72), "adj_step": (96, 96)}
-# HBM bytes per launch measured with rocprofv3 (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, KiB,
-# scaled by a 256 MiB copy) on one 1000 x 3000 shot; see
-# profiles/plain2d_1000x3000_hbm_counters.md. Valid for these kernels on this grid only.
-MEASURED_TRAFFIC = {"adj_step": {"cells": 3_000_000, "bytes": (104097.3 * 2.0 + 99192.4 * 1.0) * 1024},
-                    "fwd_step": {"cells": 3_000_000, "bytes": (53328.6 * 2.0 + 122576.0 * 1.0) * 1024}}
+# HBM traffic per launch measured with rocprofv3 on one 1000 x 3000 shot, per tile shape
+# (rows): FETCH_SIZE and WRITE_SIZE in KiB, scaled by 2.00 and 1.00 (the factors a 256 MiB
+# device copy needs); see profiles/plain2d_1000x3000_hbm_counters.md. Valid for these
+# kernels on this grid only.
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+MEASURED_TRAFFIC = {
+    "adj_step": {"cells": 3_000_000, "kib": {8: (107768.2, 99034.3), 12: (109251.8, 99020.8),
+                                             16: (110167.2, 98978.3)}},
+    "fwd_step": {"cells": 3_000_000, "kib": {8: (54131.3, 122444.0), 12: (55712.0, 122437.7),
+                                             16: (56491.8, 122447.6)}},
+}
+
+
+def measured_traffic(name, cells, rows):
+    """Measured HBM bytes per launch of kernel `name` at `rows` tile rows, or None."""
+    mt = MEASURED_TRAFFIC.get(name)
+    if not mt or mt["cells"] != cells or rows not in mt["kib"]:
+        return None
+    fetch, write = mt["kib"][rows]
+    return int((fetch * FETCH_SCALE + write * WRITE_SCALE) * 1024)
 
 
 def path_bytes_per_cell_step(recompute_fraction):
@@ -340,8 +357,8 @@ def main():  # noqa: C901
     dominant = max((n for n in kern if n in KERNEL_BYTES and kern[n]["share"]), key=lambda n: kern[n]["share"])
     bytes_launch = kernel_bytes_per_launch(dominant, nz * nx, nt, L)
     achieved = bytes_launch / (kern[dominant]["mean_us"] * 1e-6) / 1e9
-    mt = MEASURED_TRAFFIC.get(dominant)
-    traffic = int(mt["bytes"]) if mt and mt["cells"] == nz * nx and rf == 0.0 else None
+    rows = tiles[1] if dominant == "adj_step" else tiles[0]
+    traffic = measured_traffic(dominant, nz * nx, rows) if rf == 0.0 else None
     pb = path_bytes_per_cell_step(rf)
     out = {
         "metric": "Gcell-updates/s fwd+adj+grad (and % HBM roofline); shots/s batched vs plain",
