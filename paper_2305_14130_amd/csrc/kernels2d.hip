@@ -861,10 +861,10 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   __syncthreads();
 
   // ---- 2. u_bar on the tile and a 2-node halo ----
-  struct UbOut {
-    float ux, uz, qxa, qza, qxb, qzb;
+  struct Ub {
+    float ux, uz;
   };
-  auto ubar = [&](int vr, int lcol, const UbLoads& L, bool owned) -> UbOut {
+  auto ubar = [&](int vr, int lcol, const UbLoads& L, bool owned) -> Ub {
     const int gi = i0 - 2 + vr, gj = j0 - 2 + lcol;
     const int sr = vr + 2, sc = lcol + 2;   // LDS p_bar coordinates of the node
     const float ux_d = K1 * (OX0[sr * SC + sc + 1] - OX0[sr * SC + sc]) +
@@ -887,70 +887,68 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
     const float gz = -(wz_d * s.rdz + wx_d * s.rdx);
     const float bx = 2.0f * rcpf(L.r0 + L.rx), bz = 2.0f * rcpf(L.r0 + L.rz);
     const float m = in ? 1.0f : 0.0f;
-    const float uxn = m * (L.ux + bx * gx), uzn = m * (L.uz + bz * gz);
-    UbOut out{uxn, uzn, 0.0f, 0.0f, 0.0f, 0.0f};
-    int sx = -1, sz = -1;
-    float q1 = 0.0f, q2 = 0.0f, q3 = 0.0f, q4 = 0.0f;
-    if (PML) {  // corrected q_bar operands: dt u (+ a (psi_bar + dt u) inside the strips)
-      const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
-      sx = strip_index(jc, p.nx, s.P);
-      sz = strip_index(ic, p.nz, s.P);
-      // velocity-side adjoint memory variables of step n + 1, loaded here rather than with
-      // the node's other inputs (fewer live values in CPML tiles)
-      const unsigned qx = (unsigned)(ic * p.P2 + max(sx, 0)), qz = (unsigned)(max(sz, 0) * p.nx + jc);
-      q1 = G(p.rps, xv(p, X_VXX) + qx);
-      q2 = G(p.rps, xv(p, X_VZX) + qx);
-      q3 = G(p.rps, zv(p, Z_VXZ) + qz);
-      q4 = G(p.rps, zv(p, Z_VZZ) + qz);
-      const float mx = sx >= 0 ? 1.0f : 0.0f, mz = sz >= 0 ? 1.0f : 0.0f;
-      const float dux = dt * uxn, duz = dt * uzn;
-      out.qxa = m * (dux + (mx * G(p.prof, xp(p, 2) + (unsigned)jc)) * (q1 + dux));
-      out.qza = m * (duz + (mx * G(p.prof, xp(p, 0) + (unsigned)jc)) * (q2 + duz));
-      out.qxb = m * (dux + (mz * G(p.prof, zp(p, 0) + (unsigned)ic)) * (q3 + dux));
-      out.qzb = m * (duz + (mz * G(p.prof, zp(p, 2) + (unsigned)ic)) * (q4 + duz));
-    }
+    const Ub u{m * (L.ux + bx * gx), m * (L.uz + bz * gz)};
     if (owned) {
       const unsigned o = pofs(p, gi, gj);
-      G(p.wux, o) = uxn;
-      G(p.wuz, o) = uzn;
-      if (PML) {  // owned velocity-side adjoint memory variables
+      G(p.wux, o) = u.ux;
+      G(p.wuz, o) = u.uz;
+    }
+    return u;
+  };
+  // u_bar of a node into LDS; CPML tiles also the corrected q_bar operands, dt u (+ a
+  // (psi_bar + dt u) inside the strips), and the owned velocity-side adjoint memory
+  // variables. In CPML tiles this runs after the barrier that ends the reads of the staged
+  // operands (the LDS space is reused), so only u_bar is held across it.
+  auto put = [&](int vr, int lcol, const Ub& u, bool owned) {
+    UX[vr * VC + lcol] = u.ux;
+    UZ[vr * VC + lcol] = u.uz;
+    if (PML) {
+      const int gi = i0 - 2 + vr, gj = j0 - 2 + lcol;
+      const bool in = gi >= 0 && gi < p.nz && gj >= 0 && gj < p.nx;
+      const float m = in ? 1.0f : 0.0f;
+      const int ic = min(max(gi, 0), p.nz - 1), jc = min(max(gj, 0), p.nx - 1);
+      const int sx = strip_index(jc, p.nx, s.P), sz = strip_index(ic, p.nz, s.P);
+      // velocity-side adjoint memory variables of step n + 1
+      const unsigned qx = (unsigned)(ic * p.P2 + max(sx, 0)), qz = (unsigned)(max(sz, 0) * p.nx + jc);
+      const float q1 = G(p.rps, xv(p, X_VXX) + qx);
+      const float q2 = G(p.rps, xv(p, X_VZX) + qx);
+      const float q3 = G(p.rps, zv(p, Z_VXZ) + qz);
+      const float q4 = G(p.rps, zv(p, Z_VZZ) + qz);
+      const float mx = sx >= 0 ? 1.0f : 0.0f, mz = sz >= 0 ? 1.0f : 0.0f;
+      const float dux = dt * u.ux, duz = dt * u.uz;
+      QXA[vr * VC + lcol] = m * (dux + (mx * G(p.prof, xp(p, 2) + (unsigned)jc)) * (q1 + dux));
+      QZA[vr * VC + lcol] = m * (duz + (mx * G(p.prof, xp(p, 0) + (unsigned)jc)) * (q2 + duz));
+      QXB[vr * VC + lcol] = m * (dux + (mz * G(p.prof, zp(p, 0) + (unsigned)ic)) * (q3 + dux));
+      QZB[vr * VC + lcol] = m * (duz + (mz * G(p.prof, zp(p, 2) + (unsigned)ic)) * (q4 + duz));
+      if (owned) {
         if (sx >= 0) {
           const unsigned q = (unsigned)(gi * p.P2 + sx);
-          G(p.wps, xv(p, X_VXX) + q) = G(p.prof, xp(p, 3) + (unsigned)gj) * (q1 + dt * uxn);
-          G(p.wps, xv(p, X_VZX) + q) = G(p.prof, xp(p, 1) + (unsigned)gj) * (q2 + dt * uzn);
+          G(p.wps, xv(p, X_VXX) + q) = G(p.prof, xp(p, 3) + (unsigned)gj) * (q1 + dt * u.ux);
+          G(p.wps, xv(p, X_VZX) + q) = G(p.prof, xp(p, 1) + (unsigned)gj) * (q2 + dt * u.uz);
         }
         if (sz >= 0) {
           const unsigned q = (unsigned)(sz * p.nx + gj);
-          G(p.wps, zv(p, Z_VXZ) + q) = G(p.prof, zp(p, 1) + (unsigned)gi) * (q3 + dt * uxn);
-          G(p.wps, zv(p, Z_VZZ) + q) = G(p.prof, zp(p, 3) + (unsigned)gi) * (q4 + dt * uzn);
+          G(p.wps, zv(p, Z_VXZ) + q) = G(p.prof, zp(p, 1) + (unsigned)gi) * (q3 + dt * u.ux);
+          G(p.wps, zv(p, Z_VZZ) + q) = G(p.prof, zp(p, 3) + (unsigned)gi) * (q4 + dt * u.uz);
         }
       }
     }
-    return out;
   };
-  auto put = [&](int vr, int lcol, const UbOut& o) {
-    UX[vr * VC + lcol] = o.ux;
-    UZ[vr * VC + lcol] = o.uz;
-    if (PML) {
-      QXA[vr * VC + lcol] = o.qxa;
-      QZA[vr * VC + lcol] = o.qza;
-      QXB[vr * VC + lcol] = o.qxb;
-      QZB[vr * VC + lcol] = o.qzb;
-    }
-  };
-  UbOut uo[NV];
+  Ub uo[NV];
+  bool own[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int vr = ty + k * BZ, gi = i0 - 2 + vr;
-    uo[k] = ubar(vr, tx + 2, UL[k], gi >= i0 && gi < i0 + TZ && (!EDGE || (gi < p.nz && j0 + tx < p.nx)));
+    own[k] = gi >= i0 && gi < i0 + TZ && (!EDGE || (gi < p.nz && j0 + tx < p.nx));
+    uo[k] = ubar(vr, tx + 2, UL[k], own[k]);
   }
   const bool has_halo = (tid >> 2) < VR;
-  UbOut ho{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  Ub ho{0.0f, 0.0f};
   if (has_halo) ho = ubar(hv, hcol, UH, false);
   if (PML) __syncthreads();   // every thread is done reading the staged operands
 #pragma unroll
-  for (int k = 0; k < NV; ++k) put(ty + k * BZ, tx + 2, uo[k]);
-  if (has_halo) put(hv, hcol, ho);
+  for (int k = 0; k < NV; ++k) put(ty + k * BZ, tx + 2, uo[k], own[k]);
+  if (has_halo) put(hv, hcol, ho, false);
   __syncthreads();
 
   // ---- 3. t_bar, memory variables and imaging at the tile's normal nodes (their loads
