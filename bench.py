@@ -10,8 +10,9 @@ the extended model), then the consistency-regularizer value and gradient over th
 The forward history for the imaging condition is kept with the largest checkpoint interval
 whose workspace fits in the free HBM (one shot's whole history, 224 GiB, fits in the 288 GB
 of an MI355X, so nothing is recomputed); the sqrt(nt)-checkpoint form (recomputing all but
-the last segment) and the batched form (all shots advanced together) are timed once each
-and must give the identical gradient; the FP16- and BF16-checkpoint forms are timed once
+the last segment) and the batched form (shots advanced together, one launch per half step
+over a wave's tiles, in waves whose per-step state fits the Infinity Cache) are timed once
+each and must give the identical gradient; the FP16- and BF16-checkpoint forms are timed once
 each with their gradient's relative L2 distance from the FP32 one, and the batched form on
 64 uneven windows (nz_s ~ U[400,1000], nx_s ~ U[800,3000]) is timed once.
 
@@ -24,7 +25,7 @@ resident in HBM before the timed region. The JSON line also carries:
 * cpu_baseline: the FP64 NumPy oracle on a bounded sample (one shot, full grid, a few
   time steps), in the same unit;
 * path: the whole step's algorithmic bytes (168 B per cell-step plus 52 B per recomputed
-  cell-step) over the step time.
+  cell-step) over the step time; each checkpointed form carries the same as path_frac.
 """
 from __future__ import annotations
 
@@ -156,8 +157,10 @@ def uneven_batched_form(efwi, inputs, torch, dev, grid, nt, log):
     dt = time.perf_counter() - t0
     assert bool(torch.isfinite(phi).all()) and bool(torch.isfinite(phi_reg))
     cells = sum(s.wz * s.wx for s in shots)
-    out = {"shots_per_s": round(ns / dt, 4), "gcell_per_s": round(cells * nt / dt / 1e9, 4),
-           "ms_per_step": round(dt * 1e3, 2), "waves": -(-need // bws.numel()), "shots": ns,
+    gcell = cells * nt / dt / 1e9
+    out = {"shots_per_s": round(ns / dt, 4), "gcell_per_s": round(gcell, 4),
+           "path_frac": round(path_bytes_per_cell_step(efwi.recompute_fraction(grid, 0)) * gcell / HBM_PEAK_GBS, 4),
+           "ms_per_step": round(dt * 1e3, 2), "waves": len(efwi.batch_waves(grid, shots, bws.numel())), "shots": ns,
            "mean_cells_per_shot": int(cells / ns)}
     log(f"uneven batched form done: {out}")
     del bws, m_ext, g_ext, b, sink, d_obs, src, m_start
@@ -274,14 +277,20 @@ def main():  # noqa: C901
 
     forms = {}
 
+    rf_sqrt = efwi.recompute_fraction(grid, 0)
+
     def timed_once(fn):
+        """One timed step of a checkpointed form; path_frac: its algorithmic bytes per
+        cell-step (recomputed steps included) over the step time, against 8 TB/s."""
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         fn()
         torch.cuda.synchronize()
         dt_ = time.perf_counter() - t1
-        return {"shots_per_s": round(ns / dt_, 4), "gcell_per_s": round(ns * nz * nx * nt / dt_ / 1e9, 4),
-                "ms_per_step": round(dt_ * 1e3, 2), "identical_to_plain": bool(torch.equal(g_plain, g_ext))}
+        gcell = ns * nz * nx * nt / dt_ / 1e9
+        return {"shots_per_s": round(ns / dt_, 4), "gcell_per_s": round(gcell, 4),
+                "ms_per_step": round(dt_ * 1e3, 2), "identical_to_plain": bool(torch.equal(g_plain, g_ext)),
+                "path_frac": round(path_bytes_per_cell_step(rf_sqrt) * gcell / HBM_PEAK_GBS, 4)}
 
     if not args.no_sqrt:
         # sqrt(nt)-checkpoint form: every segment but the last recomputed in the reverse sweep.
@@ -334,7 +343,7 @@ def main():  # noqa: C901
             efwi.extension_regularizer(grid, m_ext, b, sink, 1.0, g_ext, phi=phi_reg, ws=rws)
 
         forms["batched"] = timed_once(batched_step)
-        forms["batched"]["waves"] = -(-need // bws.numel())
+        forms["batched"]["waves"] = len(efwi.batch_waves(grid, bshots, bws.numel()))
         log(f"batched form done: {forms['batched']}")
         del bws
         torch.cuda.empty_cache()

@@ -152,6 +152,18 @@ efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* 
                                 const float* m_ext, const float* src, const float* d_obs,
                                 float* g_ext, double* phi, void* ws, size_t ws_bytes, void* stream);
 
+/* batch_waves: how efwi_batch_gradient groups the ns shots into waves (shots advanced
+ * together, one launch per half step) for a workspace of ws_bytes. A 2D wave holds as many
+ * shots as the workspace fits while their per-step state (both state buffers, imaging sums
+ * and parameters) stays within 192 MiB, three quarters of the MI355X's 256 MB Infinity
+ * Cache, so that each step finds the previous step's state cached; a wave holds at least one
+ * shot. 3D waves are limited by the workspace only.
+ *   nwaves     HOST int output: number of waves;
+ *   wave_first HOST int [ns] output (may be NULL): first shot of each wave, in order.
+ * EFWI_E_WORKSPACE if one shot alone does not fit. */
+efwi_status efwi_batch_waves(const efwi_grid* grid, int ns, const efwi_shot* shots, size_t ws_bytes,
+                             int* nwaves, int* wave_first);
+
 /* extension_regularizer: value and gradient of 1/2 eta^2 ||(I - S^T S_w) W m~||^2 (eq.(8)
  * second term), with W from eq.(11) (sinkhole samples of m_s replaced by the b-weighted mix
  * of the other components; a row whose other weights sum to 0 is the identity), S_w from

@@ -124,6 +124,9 @@ inline bool valid_tile_rows(int r) { return r == 8 || r == 12 || r == 16; }
 
 // Number of XCDs the hardware deals workgroups to, round robin.
 constexpr int NUM_XCD = 8;
+// Per-step bytes of the shots advanced together in one wave of a batch (3/4 of the
+// 256 MB Infinity Cache of an MI355X).
+constexpr size_t WAVE_CACHE_BYTES = (size_t)192 << 20;
 // Relative cost of an interior tile and of a tile that touches a CPML strip, as integer
 // weights (measured on MI355X with the 2D kernels: CPML tiles cost ~1.5x in the forward
 // kernels and ~2x in the adjoint kernels, which also update the adjoint memory variables

@@ -31,7 +31,7 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_status_string", "efwi_last_error", "efwi_version", "efwi_timing_enable",
             "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name",
             "efwi_plan_interval", "efwi_set_tile_rows", "efwi_get_tile_rows", "efwi_autotune_workspace_size",
-            "efwi_autotune"]
+            "efwi_autotune", "efwi_batch_waves"]
 
 
 class Grid(ctypes.Structure):
@@ -113,6 +113,9 @@ _lib.efwi_autotune.restype = ctypes.c_int
 _lib.efwi_autotune.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, ctypes.c_int, _vp,
                                ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                ctypes.POINTER(ctypes.c_float)]
+_lib.efwi_batch_waves.restype = ctypes.c_int
+_lib.efwi_batch_waves.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), ctypes.c_size_t,
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.efwi_plan_interval.restype = ctypes.c_int
 _lib.efwi_plan_interval.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), ctypes.c_size_t]
 _lib.efwi_validate.restype = ctypes.c_int
@@ -346,6 +349,18 @@ def batch_gradient(grid: Grid, shots, m_ext, src, d_obs, g_ext=None, phi=None, w
     _check(_lib.efwi_batch_gradient(ctypes.byref(grid), len(shots), arr, _ptr(m_ext), _ptr(src), _ptr(d_obs),
                                     _ptr(g_ext), _ptr(phi), _ptr(ws), ws.numel(), _stream(stream)))
     return g_ext, phi
+
+
+def batch_waves(grid: Grid, shots, ws_bytes: int):
+    """First shot of each wave that batch_gradient advances together for a workspace of
+    ws_bytes (see efwi_batch_waves)."""
+    shots = list(shots)
+    arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
+    n = ctypes.c_int()
+    first = (ctypes.c_int * max(1, len(shots)))()
+    _check(_lib.efwi_batch_waves(ctypes.byref(grid), len(shots), arr, ctypes.c_size_t(ws_bytes), ctypes.byref(n),
+                                 first))
+    return list(first[:n.value])
 
 
 def extension_regularizer(grid: Grid, m_ext, b, sink, eta, g_ext, phi=None, ws=None, stream=None):

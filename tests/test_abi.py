@@ -125,3 +125,24 @@ def test_autotune_workspace_size(efwi):
     assert efwi._lib.efwi_autotune_workspace_size(grid, sc, 0) == 0
     grid.ndim = 3
     assert efwi._lib.efwi_autotune_workspace_size(grid, sc, 16) == 0
+
+
+def test_batch_waves_follow_the_cache_budget(efwi):
+    """Small windows share a wave; 1000 x 3000 shots, whose per-step state alone fills most
+    of the 256 MB Infinity Cache, get one wave each; a small workspace splits waves too."""
+    small = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+    shots = [efwi.Shot(50, 40 + 10 * k, np.full(3, 50, np.int32), np.array([60, 63, 66], np.int32))
+             for k in range(6)]
+    big_ws = efwi.workspace_size(efwi.WS_BATCH, small, shots)
+    assert efwi.batch_waves(small, shots, big_ws) == [0]
+    one = efwi.workspace_size(efwi.WS_BATCH, small, shots[:1])
+    firsts = efwi.batch_waves(small, shots, one)
+    assert firsts == list(range(6))
+    with pytest.raises(efwi.EfwiError) as ei:
+        efwi.batch_waves(small, shots, one // 2)
+    assert ei.value.status == efwi.E_WORKSPACE
+    large = efwi.make_grid(1000, 3000, 2.5, 2.5, 0.25e-3, 40, 40, 1e-3, 60.0, 3990.0)
+    bshots = [efwi.Shot(500, 1000 + 100 * k, np.full(4, 500, np.int32), np.array([600, 610, 620, 630], np.int32))
+              for k in range(3)]
+    ws = efwi.workspace_size(efwi.WS_BATCH, large, bshots)
+    assert efwi.batch_waves(large, bshots, ws) == [0, 1, 2]
