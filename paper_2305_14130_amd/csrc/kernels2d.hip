@@ -11,11 +11,13 @@
 // zero (zero halo of the padded arrays), time stepping is leapfrog, the absorbing
 // boundary is an unsplit CPML with kappa = 1 whose memory variables live only in strips.
 //
-// The stencils are bandwidth bound (well under 1 flop/byte), so there is no MFMA: each
-// thread owns one cell (one node of every type), a wavefront covers 64 consecutive x, and
-// neighbour reads are served by L1/L2. The adjoint kernels are the exact transposes of the
-// forward sub-steps: material parameters sit inside the transposed differences, so they
-// are separate kernels rather than the forward run backwards.
+// The stencils are bandwidth bound (well under 1 flop/byte), so there is no MFMA. One
+// launch per time step fuses both half steps on tiles of 8, 12 or 16 rows x 64 columns
+// (a wavefront covers 64 consecutive x): the tile's halo of the first half step's input is
+// staged in LDS and the second half step's input is recomputed on a 2-node halo instead of
+// being exchanged between tiles. The transposed step is the exact transpose of the forward
+// step in scaled adjoint variables (material parameters applied at the owned node), not
+// the forward scheme run backwards; it also gathers the imaging sums.
 #include "efwi_internal.h"
 
 // Contract a * b + c into one fused multiply-add only inside a single expression, never
