@@ -561,7 +561,8 @@ size_t header_bytes(const std::vector<Plan2D>& plans, int first, int count) {
     return align_up((size_t)count * sizeof(int)) + align_up(n * sizeof(int)) +
            align_up(sched_capacity(n) * sizeof(int));
   };
-  return align_up((size_t)count * sizeof(Shot2D)) + list(tiles) + list(ftiles) + list(atiles) + tabs;
+  auto step_list = [&](size_t n) { return align_up(sched_capacity(n) * sizeof(StepSlot)); };
+  return align_up((size_t)count * sizeof(Shot2D)) + list(tiles) + step_list(ftiles) + step_list(atiles) + tabs;
 }
 
 size_t wave_bytes(const std::vector<Plan2D>& plans, int first, int count) {
@@ -620,9 +621,9 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     nftiles += p.nfwd_tiles;
     natiles += p.nadj_tiles;
   }
-  // header layout: descriptors, then three tile lists (tile_first [count], tile_shot
-  // [tiles], XCD schedule) for the 4-row tiles, the forward-step and the transposed-step
-  // tiles, then the per-shot tables
+  // header layout: descriptors, the 4-row tile list (tile_first [count], tile_shot
+  // [tiles], XCD schedule), the forward-step and transposed-step schedules (StepSlot per
+  // slot), then the per-shot tables
   const size_t off_desc = 0;
   size_t off = off_desc + align_up((size_t)count * sizeof(Shot2D));
   struct ListAt {
@@ -636,13 +637,17 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     off = l.sched + align_up(sched_capacity(n) * sizeof(int));
     return l;
   };
-  const ListAt l4 = list_at(ntiles), lf = list_at(nftiles), la = list_at(natiles);
+  const ListAt l4 = list_at(ntiles);
+  const size_t off_fs = off;   // the fused steps' schedules
+  off += align_up(sched_capacity(nftiles) * sizeof(StepSlot));
+  const size_t off_as = off;
+  off += align_up(sched_capacity(natiles) * sizeof(StepSlot));
   size_t off_tab = off;
   const size_t hdr = header_bytes(plans, first, count);
   std::vector<unsigned char> blob(hdr, 0);
   auto ints = [&](size_t o) { return reinterpret_cast<int*>(blob.data() + o); };
   size_t region = hdr;
-  int t4 = 0, tf = 0, ta = 0;
+  int t4 = 0;
   wv.descs.clear();
   wv.regions.clear();
   for (int k = 0; k < count; ++k) {
@@ -650,10 +655,6 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     const efwi_shot& s = shots[first + k];
     ints(l4.first)[k] = t4;
     for (int q = 0; q < p.ntiles; ++q) ints(l4.shot)[t4++] = k;
-    ints(lf.first)[k] = tf;
-    for (int q = 0; q < p.nfwd_tiles; ++q) ints(lf.shot)[tf++] = k;
-    ints(la.first)[k] = ta;
-    for (int q = 0; q < p.nadj_tiles; ++q) ints(la.shot)[ta++] = k;
     build_tables(g, s, p, blob.data() + off_tab);
     const float* tab_dev = reinterpret_cast<const float*>(ws + off_tab);
     wv.descs.push_back(make_desc(g, s, p, ws + region, tab_dev, io[first + k]));
@@ -665,10 +666,14 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   // XCD schedules: cut each tile list into NUM_XCD contiguous runs of equal weighted cost.
   // Tiles near a CPML strip cost more: the 4-row tiles (pointwise kernels) that contain
   // strip nodes, forward-step tiles within two nodes of a strip (velocity halo) and
-  // transposed-step tiles within four (staged operands).
-  auto weights = [&](int rows, int pad, int w_pml, int w_int, size_t n) {
+  // transposed-step tiles within four (staged operands). The fused steps' schedules hold
+  // each slot's tile itself (shot, origin, code path) rather than its index.
+  std::vector<StepSlot> info;
+  auto weights = [&](int rows, int pad, int edge_below, int w_pml, int w_int, size_t n) {
     std::vector<int> w(n);
+    info.assign(n, StepSlot{-1, 0, 0, 0});
     size_t q = 0;
+    int sh = 0;
     for (const Plan2D& p : wv.plans) {
       const int ntx = (p.nx + BX - 1) / BX, nty = (p.nz + rows - 1) / rows;
       for (int l = 0; l < ntx * nty; ++l, ++q) {
@@ -676,28 +681,39 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
         const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + BX - 1 + pad >= p.nx - p.P) || (i0 - pad < p.P) ||
                                      (i0 + rows - 1 + pad >= p.nz - p.P));
         w[q] = pml ? w_pml : w_int;
+        info[q] = StepSlot{sh, i0, j0, pml ? PATH_PML : p.P < edge_below ? PATH_EDGE : PATH_INTERIOR};
       }
+      ++sh;
     }
     return w;
   };
+  auto step_slots = [&](const int* order, int nslots, size_t off_slots) {
+    StepSlot* out = reinterpret_cast<StepSlot*>(blob.data() + off_slots);
+    for (int q = 0; q < nslots; ++q) out[q] = order[q] < 0 ? StepSlot{-1, 0, 0, 0} : info[order[q]];
+  };
   const int frows = wv.plans[0].fwd_rows, arows = wv.plans[0].adj_rows;
   int nsched[3];
-  efwi_status rc = build_sched(weights(BZ, 0, FWD_W_PML, FWD_W_INT, ntiles), ints(l4.sched), nsched[0]);
+  efwi_status rc = build_sched(weights(BZ, 0, 0, FWD_W_PML, FWD_W_INT, ntiles), ints(l4.sched), nsched[0]);
   if (rc != EFWI_OK) return rc;
-  rc = build_sched(weights(frows, 2, FWD_W_PML, FWD_W_INT, nftiles), ints(lf.sched), nsched[1]);
-  if (rc != EFWI_OK) return rc;
-  rc = build_sched(weights(arows, 4, ADJ_W_PML, ADJ_W_INT, natiles), ints(la.sched), nsched[2]);
-  if (rc != EFWI_OK) return rc;
+  {
+    // the halo of the forward step's staged stresses reaches 2 nodes beyond the velocity
+    // halo, so without strips of at least 2 nodes a tile may read outside the grid; the
+    // transposed step's reaches 4 nodes, inside the grid whenever there are strips
+    std::vector<int> order(sched_capacity(nftiles));
+    rc = build_sched(weights(frows, 2, 2, FWD_W_PML, FWD_W_INT, nftiles), order.data(), nsched[1]);
+    if (rc != EFWI_OK) return rc;
+    step_slots(order.data(), nsched[1], off_fs);
+    order.assign(sched_capacity(natiles), -1);
+    rc = build_sched(weights(arows, 4, 1, ADJ_W_PML, ADJ_W_INT, natiles), order.data(), nsched[2]);
+    if (rc != EFWI_OK) return rc;
+    step_slots(order.data(), nsched[2], off_as);
+  }
   auto dev = [&](size_t o) { return reinterpret_cast<const int*>(ws + o); };
   wv.batch.tile_first = dev(l4.first);
   wv.batch.tile_shot = dev(l4.shot);
   wv.batch.fwd = Sched{dev(l4.sched), nsched[0]};
-  wv.batch.step_tile_first = dev(lf.first);
-  wv.batch.step_tile_shot = dev(lf.shot);
-  wv.batch.step = Sched{dev(lf.sched), nsched[1]};
-  wv.batch.adj_tile_first = dev(la.first);
-  wv.batch.adj_tile_shot = dev(la.shot);
-  wv.batch.adj_step = Sched{dev(la.sched), nsched[2]};
+  wv.batch.step = StepSched{reinterpret_cast<const StepSlot*>(ws + off_fs), nsched[1]};
+  wv.batch.adj_step = StepSched{reinterpret_cast<const StepSlot*>(ws + off_as), nsched[2]};
   wv.batch.fwd_rows = frows;
   wv.batch.adj_rows = arows;
   wv.batch.shots = reinterpret_cast<const Shot2D*>(ws + off_desc);

@@ -100,19 +100,27 @@ struct Sched {
   const int* sched;
   int n;
 };
+// A slot of a fused-step schedule as the kernel reads it (one scalar load per workgroup):
+// the tile's shot (-1: empty slot), first row, first column and code path.
+constexpr int PATH_INTERIOR = 0;   // no CPML, halo inside the grid
+constexpr int PATH_EDGE = 1;       // halo may leave the grid (a grid without CPML)
+constexpr int PATH_PML = 2;        // the tile or its halo touches a CPML strip
+struct StepSlot {
+  int shot, i0, j0, path;
+};
+struct StepSched {
+  const StepSlot* slot;
+  int n;
+};
 struct Batch2D {
   const Shot2D* shots;
   const int* tile_shot;      // 4-row tiles (pointwise kernels)
   const int* tile_first;
   Sched fwd;
   int ns, ntiles;
-  // tiles of the fused forward step (fwd_rows rows) and of the fused transposed step
-  // (adj_rows rows), 64 columns wide
-  const int* step_tile_shot;
-  const int* step_tile_first;
-  const int* adj_tile_shot;
-  const int* adj_tile_first;
-  Sched step, adj_step;
+  // schedules of the fused forward step (tiles of fwd_rows rows) and of the fused
+  // transposed step (adj_rows rows), 64 columns wide
+  StepSched step, adj_step;
   int fwd_rows, adj_rows;
 };
 

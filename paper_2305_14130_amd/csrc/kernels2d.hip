@@ -98,18 +98,11 @@ __device__ __forceinline__ bool batch_tile(const int* __restrict__ sched, const 
 #define BATCH_PARAMS                                                                           \
   const Shot2D* __restrict__ shots, const int* __restrict__ tile_shot, const int* __restrict__ tile_first, \
       const int* __restrict__ sched
-#define STEP_PARAMS BATCH_PARAMS
+#define STEP_PARAMS const Shot2D* __restrict__ shots, const StepSlot* __restrict__ slots
 #define BATCH_TILE()                                                                           \
   int sh_, i0, j0;                                                                              \
   if (!batch_tile<BZ>(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;               \
   const Shot2D& s = shots[sh_]
-
-// Does the tile of `rows` rows touch a CPML strip (with `pad` extra cells of neighbourhood)?
-__device__ __forceinline__ bool block_in_pml(const Shot2D& s, int j0, int i0, int rows, int pad) {
-  if (s.P <= 0) return false;
-  const int j1 = j0 + BX - 1 + pad, i1 = i0 + rows - 1 + pad;
-  return (j0 - pad < s.P) || (j1 >= s.nx - s.P) || (i0 - pad < s.P) || (i1 >= s.nz - s.P);
-}
 
 // Every cell function below issues all of its loads before its first store: the
 // compiler cannot prove that the shot's arrays do not alias, so a store placed before a
@@ -528,18 +521,22 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
 }
 
 // Tile shape of the fused forward step: TSTEP rows x 64 columns.
+// Workgroup w takes schedule slot w: its tile and code path come in one scalar load (the
+// host classified the tile), so a workgroup starts its tile's loads after two dependent
+// scalar round trips (the slot, then the shot's descriptor).
 template <int TZ, bool STORE, bool RECORD>
 __global__ __launch_bounds__(BX * BZ) void k_fwd_step(STEP_PARAMS, int n, int kstore) {
   __shared__ float lds[StepTile<TZ>::LDS_FLOATS];
-  int sh_, i0, j0;
-  if (!batch_tile<TZ>(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;
-  const Shot2D& s = shots[sh_];
+  const StepSlot slot = slots[blockIdx.x];
+  if (slot.shot < 0) return;
+  const Shot2D& s = shots[slot.shot];
+  const int i0 = slot.i0, j0 = slot.j0;
   gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG_FIELDS * s.cells : nullptr;
-  // block-uniform branch: every thread reaches the barriers
-  // Tiles clear of the strips are at least P >= 2 nodes from every edge, so with CPML
-  // their staged halo lies inside the grid.
-  if (block_in_pml(s, j0, i0, TZ, 2)) fwd_step_tile<TZ, STORE, RECORD, true, true>(s, i0, j0, n, seg, lds);
-  else if (s.P < 2) fwd_step_tile<TZ, STORE, RECORD, false, true>(s, i0, j0, n, seg, lds);
+  // block-uniform branch: every thread reaches the barriers. CPML tiles: within 2 nodes of
+  // a strip (velocity halo); edge tiles (grids whose strips are under 2 nodes wide): the
+  // staged halo may leave the grid; every other tile's staged halo lies inside it.
+  if (slot.path == PATH_PML) fwd_step_tile<TZ, STORE, RECORD, true, true>(s, i0, j0, n, seg, lds);
+  else if (slot.path == PATH_EDGE) fwd_step_tile<TZ, STORE, RECORD, false, true>(s, i0, j0, n, seg, lds);
   else fwd_step_tile<TZ, STORE, RECORD, false, false>(s, i0, j0, n, seg, lds);
 }
 
@@ -1049,15 +1046,16 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
 template <int TZ, bool GRAD, bool SRCADJ>
 __global__ __launch_bounds__(BX * BZ) void k_adj_step(STEP_PARAMS, int n, int kseg, int first) {
   __shared__ float lds[AdjTile<TZ>::LDS_FLOATS];
-  int sh_, i0, j0;
-  if (!batch_tile<TZ>(sched, tile_shot, tile_first, shots, sh_, i0, j0)) return;
-  const Shot2D& s = shots[sh_];
+  const StepSlot slot = slots[blockIdx.x];
+  if (slot.shot < 0) return;
+  const Shot2D& s = shots[slot.shot];
+  const int i0 = slot.i0, j0 = slot.j0;
   // block-uniform branch: every thread reaches the barriers. The staged p_bar operands
   // reach 4 nodes beyond the tile, so tiles within 4 nodes of a strip take the CPML path;
   // with strips at all four edges every other tile and its 4-node halo lie inside the
   // grid and skip the edge handling (only a grid without strips needs it there).
-  if (block_in_pml(s, j0, i0, TZ, 4)) adj_step_tile<TZ, GRAD, SRCADJ, true, true>(s, i0, j0, n, kseg, first != 0, lds);
-  else if (s.P < 1) adj_step_tile<TZ, GRAD, SRCADJ, false, true>(s, i0, j0, n, kseg, first != 0, lds);
+  if (slot.path == PATH_PML) adj_step_tile<TZ, GRAD, SRCADJ, true, true>(s, i0, j0, n, kseg, first != 0, lds);
+  else if (slot.path == PATH_EDGE) adj_step_tile<TZ, GRAD, SRCADJ, false, true>(s, i0, j0, n, kseg, first != 0, lds);
   else adj_step_tile<TZ, GRAD, SRCADJ, false, false>(s, i0, j0, n, kseg, first != 0, lds);
 }
 
@@ -1170,14 +1168,14 @@ hipError_t launch_stage2d(const Batch2D& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-#define STEP_ARGS b.shots, b.step_tile_shot, b.step_tile_first, b.step.sched
-#define ADJSTEP_ARGS b.shots, b.adj_tile_shot, b.adj_tile_first, b.adj_step.sched
+#define STEP_ARGS b.shots, b.step.slot
+#define ADJSTEP_ARGS b.shots, b.adj_step.slot
 
 namespace {
 
 template <int TZ>
 void fwd_step_launch(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
-  const dim3 g = grid_of(b.step);
+  const dim3 g(b.step.n);
   if (kstore >= 0) {
     if (record) k_fwd_step<TZ, true, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
     else k_fwd_step<TZ, true, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
@@ -1189,7 +1187,7 @@ void fwd_step_launch(const Batch2D& b, int n, int kstore, bool record, hipStream
 
 template <int TZ>
 void adj_step_launch(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
-  const dim3 g = grid_of(b.adj_step);
+  const dim3 g(b.adj_step.n);
   if (grad) k_adj_step<TZ, true, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, k, first);
   else if (srcadj) k_adj_step<TZ, false, true><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
   else k_adj_step<TZ, false, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
