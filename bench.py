@@ -61,10 +61,10 @@ KERNEL_BYTES = {"fwd_step": (52, 72), "adj_step": (96, 96)}
 # kernels on this grid only.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "adj_step": {"cells": 3_000_000, "kib": {8: (107768.2, 99034.3), 12: (109251.8, 99020.8),
-                                             16: (110167.2, 98978.3)}},
-    "fwd_step": {"cells": 3_000_000, "kib": {8: (54131.3, 122444.0), 12: (55712.0, 122437.7),
-                                             16: (56491.8, 122447.6)}},
+    "adj_step": {"cells": 3_000_000, "kib": {8: (108323.2, 99081.7), 12: (109470.3, 99023.7),
+                                             16: (110520.7, 98996.5)}},
+    "fwd_step": {"cells": 3_000_000, "kib": {8: (54580.6, 122429.6), 12: (55684.7, 122444.2),
+                                             16: (56573.6, 122453.1)}},
 }
 
 
