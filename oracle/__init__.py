@@ -13,6 +13,7 @@ Modules
 ``regularizer`` eq.(8) regularization term with the operators W (eq.(11)), S_w (eq.(12))
                 and S^T, written as dense per-point matrices.
 ``checkpoint``  the 16-bit checkpoint encodings (per-snapshot max-abs scaling).
+``zoi``         the sources' zones of influence, eq.(10): weights b_s and sinkhole flags.
 
 Every function is FP64 and unblocked; arrays are NumPy. Where the paper is silent
 (discretization, absorbing boundary, source injection, DAS sampling details) the reading
