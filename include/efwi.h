@@ -178,6 +178,43 @@ efwi_status efwi_extension_regularizer(const efwi_grid* grid, int ns, const floa
                                        float* g_ext, double* phi, void* ws, size_t ws_bytes,
                                        void* stream);
 
+/* One source's zone of influence (Source zone of influence, eq.(10)). Node (i, k, j) of
+ * the grid sits at (i dz, k dy, j dx) metres; the y entries are ignored in 2D. */
+typedef struct {
+  float src[3];   /* z, y, x of the sinkhole centre (normally the source), metres           */
+  float icov[6];  /* zz, yy, xx, zy, zx, yx of the sinkhole's inverse covariance C^-1,
+                     1/m^2, symmetric positive definite: the sinkhole is the ellipse
+                     (ellipsoid) dp^T C^-1 dp < 1, dp = node - src                          */
+  float box[6];   /* z0, z1, y0, y1, x0, x1: the zone's active part (b = 1 there outside
+                     the sinkhole), metres                                                  */
+  float taper;    /* width of the outer transition beyond the box, metres (0: a step)      */
+} efwi_zoi;
+
+/* zoi_weights: the ZOI weights b_s of eq.(10) and the sinkhole flags of ns sources on the
+ * full grid: b = (cos^n(pi r / 2) - ln nu) / (1 - ln nu), r the larger of the outer
+ * transition's (Euclidean distance to the box over the taper, capped at 1) and the
+ * sinkhole's (1 - d inside the sinkhole, d the Mahalanobis distance to src), so b is 1 in
+ * the active part and (-ln nu) / (1 - ln nu) at the source; sink = (d < 1), decided in
+ * FP64 with a fixed summation order. The outputs feed efwi_extension_regularizer and
+ * efwi_final_model.
+ *   zones HOST [ns]; n > 0 sets the transition's stiffness, 0 < nu < 1 its height;
+ *   b     DEVICE [ns][nz][nx] (3D [ns][nz][ny][nx]) FP32 output;
+ *   sink  DEVICE unsigned char, same shape, output.
+ * FP64 arithmetic, one launch per source on `stream`. EFWI_E_INVAL for a box with an upper
+ * bound below its lower bound, a negative taper, an inverse covariance that is not positive
+ * definite, non-finite values, or n, nu out of range. */
+efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zones, float n, float nu,
+                             float* b, unsigned char* sink, void* stream);
+
+/* final_model: the physical model m = S_w W m~ of eq.(9) from an extended model, with W
+ * (eq.(11)) and S_w (eq.(12)) as in efwi_extension_regularizer; 0 where the weights b'
+ * sum to 0 (no source is useful there).
+ *   m_ext DEVICE [ns][3][nz][nx]; b, sink as in efwi_extension_regularizer;
+ *   m_out DEVICE [3][nz][nx] output (3D: [3][nz][ny][nx]).
+ * FP64 arithmetic, one launch on `stream`. */
+efwi_status efwi_final_model(const efwi_grid* grid, int ns, const float* m_ext, const float* b,
+                             const unsigned char* sink, float* m_out, void* stream);
+
 /* Tile shape of the fused 2D forward and transposed time-step kernels: tiles of 8, 12 or
  * 16 rows by 64 columns (the stencil halo is recomputed per tile, so taller tiles recompute
  * less but hold more LDS and registers). Results do not depend on the choice (every node

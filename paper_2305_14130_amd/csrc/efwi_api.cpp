@@ -105,10 +105,12 @@ Staging& staging() {
 // fwd_vel, fwd_str, adj_vel and adj_str are the 3D half steps; fwd_step and adj_step are the
 // fused 2D forward and transposed steps.
 enum KernelKind {
-  KK_FWD_VEL = 0, KK_FWD_STR, KK_ADJ_VEL, KK_ADJ_STR, KK_CHAIN, KK_MISFIT, KK_REG, KK_FWD_STEP, KK_ADJ_STEP, KK_COUNT
+  KK_FWD_VEL = 0, KK_FWD_STR, KK_ADJ_VEL, KK_ADJ_STR, KK_CHAIN, KK_MISFIT, KK_REG, KK_FWD_STEP, KK_ADJ_STEP,
+  KK_ZOI, KK_FINAL, KK_COUNT
 };
 const char* const kKernelNames[KK_COUNT] = {"fwd_vel", "fwd_str",     "adj_vel",  "adj_str", "chain_flush",
-                                            "misfit",  "regularizer", "fwd_step", "adj_step"};
+                                            "misfit",  "regularizer", "fwd_step", "adj_step",
+                                            "zoi",     "final_model"};
 
 class Sampler {
  public:
@@ -1643,6 +1645,68 @@ efwi_status efwi_extension_regularizer(const efwi_grid* grid, int ns, const floa
   HIP_TRY(TIMED(KK_REG, st,
                 launch_regularizer(ns, npts, npts, m_ext, b, sink, eta, g_ext, static_cast<double*>(ws), nb, phi,
                                    st)));
+  return EFWI_OK;
+}
+
+efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zones, float n, float nu, float* b,
+                             unsigned char* sink, void* stream) {
+  g_last_error.clear();
+  efwi_status rc = validate_grid(grid);
+  if (rc != EFWI_OK) return rc;
+  if (ns < 1) return fail(EFWI_E_INVAL, "ns must be >= 1");
+  if (!zones || !b || !sink) return fail(EFWI_E_INVAL, "NULL argument");
+  if (!(std::isfinite(n) && n > 0.0f)) return fail(EFWI_E_INVAL, "n must be finite and > 0 (got %g)", n);
+  if (!(nu > 0.0f && nu < 1.0f)) return fail(EFWI_E_INVAL, "nu must lie in (0, 1) (got %g)", nu);
+  const bool three = grid->ndim == 3;
+  for (int s = 0; s < ns; ++s) {
+    const efwi_zoi& z = zones[s];
+    bool finite = std::isfinite(z.taper);
+    for (float v : z.src) finite = finite && std::isfinite(v);
+    for (float v : z.icov) finite = finite && std::isfinite(v);
+    for (float v : z.box) finite = finite && std::isfinite(v);
+    if (!finite) return fail(EFWI_E_INVAL, "zone %d has a non-finite entry", s);
+    if (z.taper < 0.0f) return fail(EFWI_E_INVAL, "zone %d: negative taper", s);
+    if (z.box[1] < z.box[0] || z.box[5] < z.box[4] || (three && z.box[3] < z.box[2]))
+      return fail(EFWI_E_INVAL, "zone %d: box upper bound below lower bound", s);
+    // positive definite: leading principal minors of [[zz, zy, zx], [zy, yy, yx], [zx, yx, xx]]
+    // (2D: of [[zz, zx], [zx, xx]])
+    const double zz = z.icov[0], yy = z.icov[1], xx = z.icov[2], zy = z.icov[3], zx = z.icov[4], yx = z.icov[5];
+    bool pd;
+    if (three) {
+      const double m2 = zz * yy - zy * zy;
+      const double m3 = zz * (yy * xx - yx * yx) - zy * (zy * xx - yx * zx) + zx * (zy * yx - yy * zx);
+      pd = zz > 0.0 && m2 > 0.0 && m3 > 0.0;
+    } else {
+      pd = zz > 0.0 && zz * xx - zx * zx > 0.0;
+    }
+    if (!pd) return fail(EFWI_E_INVAL, "zone %d: inverse covariance is not positive definite", s);
+  }
+  const int ny = three ? grid->ny : 1;
+  const long npts = (long)grid->nz * ny * grid->nx;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int s = 0; s < ns; ++s) {
+    const efwi_zoi& z = zones[s];
+    ZoiArgs a;
+    for (int k = 0; k < 3; ++k) a.src[k] = z.src[k];
+    for (int k = 0; k < 6; ++k) a.icov[k] = z.icov[k], a.box[k] = z.box[k];
+    a.taper = z.taper, a.n = n, a.nu = nu;
+    HIP_TRY(TIMED(KK_ZOI, st,
+                  launch_zoi(three ? 1 : 0, npts, ny, grid->nx, grid->dz, three ? grid->dy : 0.0, grid->dx, a,
+                             b + (size_t)s * npts, sink + (size_t)s * npts, st)));
+  }
+  return EFWI_OK;
+}
+
+efwi_status efwi_final_model(const efwi_grid* grid, int ns, const float* m_ext, const float* b,
+                             const unsigned char* sink, float* m_out, void* stream) {
+  g_last_error.clear();
+  efwi_status rc = validate_grid(grid);
+  if (rc != EFWI_OK) return rc;
+  if (ns < 1) return fail(EFWI_E_INVAL, "ns must be >= 1");
+  if (!m_ext || !b || !sink || !m_out) return fail(EFWI_E_INVAL, "NULL array argument");
+  const long npts = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(TIMED(KK_FINAL, st, launch_final_model(ns, npts, m_ext, b, sink, m_out, st)));
   return EFWI_OK;
 }
 

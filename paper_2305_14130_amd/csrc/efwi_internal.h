@@ -195,6 +195,14 @@ hipError_t launch_regularizer(int ns, long npts, long plane, const float* m_ext,
                               const unsigned char* sink, float eta, float* g_ext, double* partial,
                               int nblocks, double* phi, hipStream_t st);
 int regularizer_blocks(long npts);
+// One source's zone of influence for k_zoi (efwi_zoi in FP64).
+struct ZoiArgs {
+  double src[3], icov[6], box[6], taper, n, nu;
+};
+hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy, double dx, const ZoiArgs& a,
+                      float* b, unsigned char* sink, hipStream_t st);
+hipError_t launch_final_model(int ns, long npts, const float* m_ext, const float* b, const unsigned char* sink,
+                              float* m_out, hipStream_t st);
 
 // ---------------------------------------------------------------------------------------
 // 3D. Arrays are [nz][ny][nx]; padded arrays have the same zero halo in z and y as in 2D

@@ -100,7 +100,101 @@ __global__ void k_sum_partials(const double* partial, int n, double scale, doubl
   if (threadIdx.x == 0) *out = scale * sh[0];
 }
 
+// ---------------------------------------------------------------------------------------
+// Zone of influence of one source (Source zone of influence, eq.(10)), pointwise:
+//   b = (cos^n(pi r / 2) - ln nu) / (1 - ln nu),  r = max(r_out, r_sink) in [0, 1]
+//   r_out  = (Euclidean distance to the active box) / taper, capped at 1 (a step if taper 0)
+//   r_sink = 1 - d inside the sinkhole d < 1, d = sqrt(dp^T C^-1 dp) (Mahalanobis distance
+//            to the source), 0 outside; sink = (d^2 < 1)
+// FP64, with the squared distance summed in a fixed order and no contraction, so that the
+// sinkhole flag (an integer decided by floating point) is reproducible.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(RB) void k_zoi(long npts, int ny, int nx, double dz, double dy, double dx, int three,
+                                            ZoiArgs a, float* __restrict__ b, unsigned char* __restrict__ sink) {
+#pragma clang fp contract(off)
+  const double ln = log(a.nu), den = 1.0 - ln;
+  for (long p = blockIdx.x * (long)RB + threadIdx.x; p < npts; p += (long)gridDim.x * RB) {
+    const long row = p / nx;
+    const int j = (int)(p - row * nx);
+    const int i = (int)(row / ny), k = (int)(row - (long)i * ny);
+    const double z = (double)i * dz, y = (double)k * dy, x = (double)j * dx;
+    const double ez = fmax(fmax(a.box[0] - z, z - a.box[1]), 0.0);
+    const double ex = fmax(fmax(a.box[4] - x, x - a.box[5]), 0.0);
+    double e2 = ez * ez + ex * ex;
+    if (three) {
+      const double ey = fmax(fmax(a.box[2] - y, y - a.box[3]), 0.0);
+      e2 = e2 + ey * ey;
+    }
+    const double e = sqrt(e2);
+    const double r_out = a.taper > 0.0 ? fmin(e / a.taper, 1.0) : (e > 0.0 ? 1.0 : 0.0);
+    const double pz = z - a.src[0], px = x - a.src[2];
+    // icov = (zz, yy, xx, zy, zx, yx)
+    double d2 = (a.icov[0] * pz) * pz;
+    d2 = d2 + (a.icov[2] * px) * px;
+    d2 = d2 + ((2.0 * a.icov[4]) * pz) * px;
+    if (three) {
+      const double py = y - a.src[1];
+      d2 = d2 + (a.icov[1] * py) * py;
+      d2 = d2 + ((2.0 * a.icov[3]) * pz) * py;
+      d2 = d2 + ((2.0 * a.icov[5]) * py) * px;
+    }
+    const bool in = d2 < 1.0;
+    const double r_sink = in ? 1.0 - sqrt(d2) : 0.0;
+    const double r = fmax(r_out, r_sink);
+    b[p] = (float)((pow(cos(0.5 * M_PI * r), a.n) - ln) / den);
+    sink[p] = in ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Final physical model m = S_w W m~ (eq.(9)), pointwise, with W and S_w as in k_regularizer
+// (0 where sum b' = 0: no source is useful there).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(RB) void k_final_model(int ns, long npts, long plane, const float* __restrict__ m,
+                                                    const float* __restrict__ b,
+                                                    const unsigned char* __restrict__ sink,
+                                                    float* __restrict__ out) {
+  for (long p = blockIdx.x * (long)RB + threadIdx.x; p < npts; p += (long)gridDim.x * RB) {
+    double bsum = 0.0, bpsum = 0.0;
+    for (int s = 0; s < ns; ++s) {
+      const double bs = b[(long)s * npts + p];
+      bsum += bs;
+      bpsum += sink[(long)s * npts + p] ? 1.0 : bs;
+    }
+    for (int k = 0; k < 3; ++k) {
+      if (!(bpsum > 0.0)) {
+        out[(long)k * plane + p] = 0.0f;
+        continue;
+      }
+      double A = 0.0;
+      for (int s = 0; s < ns; ++s) A += (double)b[(long)s * npts + p] * (double)m[((long)s * 3 + k) * plane + p];
+      double num = 0.0;
+      for (int s = 0; s < ns; ++s) {
+        const double bs = b[(long)s * npts + p];
+        const double Bs = bsum - bs;
+        const double ms = m[((long)s * 3 + k) * plane + p];
+        const bool in = sink[(long)s * npts + p] != 0;
+        const double wm = (in && Bs > 0.0) ? bs * ms + (1.0 - bs) * (A - bs * ms) / Bs : ms;
+        num += (in ? 1.0 : bs) * wm;
+      }
+      out[(long)k * plane + p] = (float)(num / bpsum);
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy, double dx, const ZoiArgs& a,
+                      float* b, unsigned char* sink, hipStream_t st) {
+  k_zoi<<<regularizer_blocks(npts), RB, 0, st>>>(npts, ny, nx, dz, dy, dx, three, a, b, sink);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_model(int ns, long npts, const float* m_ext, const float* b, const unsigned char* sink,
+                              float* m_out, hipStream_t st) {
+  k_final_model<<<regularizer_blocks(npts), RB, 0, st>>>(ns, npts, npts, m_ext, b, sink, m_out);
+  return hipGetLastError();
+}
 
 int regularizer_blocks(long npts) {
   long nb = (npts + RB - 1) / RB;

@@ -31,7 +31,7 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_status_string", "efwi_last_error", "efwi_version", "efwi_timing_enable",
             "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name",
             "efwi_plan_interval", "efwi_set_tile_rows", "efwi_get_tile_rows", "efwi_autotune_workspace_size",
-            "efwi_autotune", "efwi_batch_waves"]
+            "efwi_autotune", "efwi_batch_waves", "efwi_zoi_weights", "efwi_final_model"]
 
 
 class Grid(ctypes.Structure):
@@ -113,6 +113,8 @@ _lib.efwi_autotune.restype = ctypes.c_int
 _lib.efwi_autotune.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, ctypes.c_int, _vp,
                                ctypes.c_size_t, _vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                ctypes.POINTER(ctypes.c_float)]
+_lib.efwi_zoi_weights.restype = ctypes.c_int
+_lib.efwi_final_model.restype = ctypes.c_int
 _lib.efwi_batch_waves.restype = ctypes.c_int
 _lib.efwi_batch_waves.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), ctypes.c_size_t,
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -377,6 +379,54 @@ def extension_regularizer(grid: Grid, m_ext, b, sink, eta, g_ext, phi=None, ws=N
                                            float(eta), _ptr(g_ext), _ptr(phi), _ptr(ws), ws.numel(),
                                            _stream(stream)))
     return phi
+
+
+class Zone(ctypes.Structure):
+    """One source's zone of influence (efwi_zoi): sinkhole centre (z, y, x) and inverse
+    covariance (zz, yy, xx, zy, zx, yx) in metres, active box (z0, z1, y0, y1, x0, x1), outer
+    taper width."""
+    _fields_ = [("src", ctypes.c_float * 3), ("icov", ctypes.c_float * 6), ("box", ctypes.c_float * 6),
+                ("taper", ctypes.c_float)]
+
+
+_lib.efwi_zoi_weights.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(Zone), ctypes.c_float,
+                                  ctypes.c_float, _vp, _vp, _vp]
+_lib.efwi_final_model.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+
+
+def make_zone(src, icov, box, taper) -> Zone:
+    return Zone((ctypes.c_float * 3)(*src), (ctypes.c_float * 6)(*icov), (ctypes.c_float * 6)(*box), float(taper))
+
+
+def zoi_weights(grid: Grid, zones, n, nu, b=None, sink=None, device=None, stream=None):
+    """ZOI weights b [Ns][...] (FP32) and sinkhole flags (uint8) of eq.(10) on the full grid."""
+    zones = list(zones)
+    shape = (grid.nz, grid.ny, grid.nx) if grid.ndim == 3 else (grid.nz, grid.nx)
+    dev = device if device is not None else torch.device("cuda")
+    if b is None:
+        b = torch.empty((len(zones),) + shape, dtype=torch.float32, device=dev)
+    if sink is None:
+        sink = torch.empty((len(zones),) + shape, dtype=torch.uint8, device=b.device)
+    _f32(b, "b")
+    if sink.dtype != torch.uint8:
+        raise TypeError("sink must be uint8")
+    arr = (Zone * len(zones))(*zones)
+    _check(_lib.efwi_zoi_weights(ctypes.byref(grid), len(zones), arr, float(n), float(nu), _ptr(b), _ptr(sink),
+                                 _stream(stream)))
+    return b, sink
+
+
+def final_model(grid: Grid, m_ext, b, sink, m_out=None, stream=None):
+    """Physical model S_w W m~ of eq.(9), [3][...] FP32."""
+    _f32(m_ext, "m_ext"), _f32(b, "b")
+    if sink.dtype != torch.uint8:
+        raise TypeError("sink must be uint8")
+    if m_out is None:
+        m_out = torch.empty(m_ext.shape[1:], dtype=torch.float32, device=m_ext.device)
+    _f32(m_out, "m_out")
+    _check(_lib.efwi_final_model(ctypes.byref(grid), m_ext.shape[0], _ptr(m_ext), _ptr(b), _ptr(sink), _ptr(m_out),
+                                 _stream(stream)))
+    return m_out
 
 
 def source_components(M, stf) -> np.ndarray:

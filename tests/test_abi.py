@@ -146,3 +146,31 @@ def test_batch_waves_follow_the_cache_budget(efwi):
               for k in range(3)]
     ws = efwi.workspace_size(efwi.WS_BATCH, large, bshots)
     assert efwi.batch_waves(large, bshots, ws) == [0, 1, 2]
+
+
+@pytest.mark.parametrize("change", [
+    dict(nu=1.0), dict(nu=0.0), dict(n=0.0), dict(n=float("nan")),
+    dict(taper=-1.0), dict(box=(10.0, 5.0, 0, 0, 0, 100.0)),
+    dict(icov=(1e-3, 0.0, 1e-3, 0.0, 2e-3, 0.0)),          # |zx| > sqrt(zz xx): indefinite
+    dict(icov=(-1e-3, 0.0, 1e-3, 0.0, 0.0, 0.0)),
+    dict(src=(float("inf"), 0.0, 0.0)),
+])
+def test_zoi_argument_errors(efwi, change):
+    """efwi_zoi_weights validates every zone on the host before any launch (the device
+    pointers below are never used)."""
+    grid = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+    z = dict(src=(250.0, 0.0, 500.0), icov=(1e-3, 0.0, 1e-3, 0.0, 0.0, 0.0), box=(100.0, 400.0, 0, 0, 100.0, 900.0),
+             taper=50.0, n=2.0, nu=0.9)
+    z.update(change)
+    zone = efwi.make_zone(z["src"], z["icov"], z["box"], z["taper"])
+    fake = ctypes.c_void_p(256)
+    rc = efwi._lib.efwi_zoi_weights(ctypes.byref(grid), 1, ctypes.byref(zone), z["n"], z["nu"], fake, fake, None)
+    assert rc == efwi.E_INVAL
+    assert efwi._lib.efwi_last_error()
+
+
+def test_final_model_argument_errors(efwi):
+    grid = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+    fake = ctypes.c_void_p(256)
+    assert efwi._lib.efwi_final_model(ctypes.byref(grid), 0, fake, fake, fake, fake, None) == efwi.E_INVAL
+    assert efwi._lib.efwi_final_model(ctypes.byref(grid), 2, fake, None, fake, fake, None) == efwi.E_INVAL
