@@ -26,6 +26,9 @@ resident in HBM before the timed region. The JSON line also carries:
   time steps), in the same unit;
 * path: the whole step's algorithmic bytes (168 B per cell-step plus 52 B per recomputed
   cell-step) over the step time; each checkpointed form carries the same as path_frac.
+* extension_ops: the zones of influence (eq.(10)) of the 20 sources and the final model
+  S_w W m~ (eq.(9)) on the full grid (once per inversion, not part of the step), each with
+  its time and compulsory-bytes rate.
 """
 from __future__ import annotations
 
@@ -168,6 +171,45 @@ def uneven_batched_form(efwi, inputs, torch, dev, grid, nt, log):
     return out
 
 
+def extension_ops(efwi, torch, grid, w, m_ext, dev):
+    """The sources' zones of influence (eq.(10)) and the final model S_w W m~ (eq.(9)) on the
+    full grid for the bench's shots, each timed with events on the current stream (median of
+    5 calls), with their compulsory bytes (zones: write b and the sinkhole flag, 5 B per
+    point and source; final model: read m~, b and the flags of every source, write m)."""
+    ns, nz, nx = m_ext.shape[0], w.nz, w.nx
+    zones = []
+    for s in w.shots:
+        xs = [s.src_ix] + list(s.ch_ix)
+        zones.append(efwi.make_zone((s.src_iz * w.dz, 0.0, s.src_ix * w.dx),
+                                    (1.0 / (20.0 ** 2), 0.0, 1.0 / (75.0 ** 2), 0.0, 0.0, 0.0),
+                                    (0.0, (nz - 1) * w.dz, 0.0, 0.0, min(xs) * w.dx, max(xs) * w.dx), 200.0))
+    b = torch.empty((ns, nz, nx), dtype=torch.float32, device=dev)
+    sink = torch.empty((ns, nz, nx), dtype=torch.uint8, device=dev)
+    m_out = torch.empty((3, nz, nx), dtype=torch.float32, device=dev)
+
+    def med_ms(fn):
+        times = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return sorted(times)[2]
+
+    zms = med_ms(lambda: efwi.zoi_weights(grid, zones, 2.0, 0.9, b=b, sink=sink))
+    fms = med_ms(lambda: efwi.final_model(grid, m_ext, b, sink, m_out=m_out))
+    zbytes, fbytes = 5 * nz * nx * ns, (17 * ns + 12) * nz * nx
+    out = {"zoi_weights": {"sources": ns, "ms": round(zms, 3), "bytes": zbytes,
+                           "GBs": round(zbytes / zms / 1e6, 1), "frac": round(zbytes / zms / 1e6 / HBM_PEAK_GBS, 4),
+                           "sink_points": int(sink.sum().item())},
+           "final_model": {"components": ns, "ms": round(fms, 3), "bytes": fbytes,
+                           "GBs": round(fbytes / fms / 1e6, 1), "frac": round(fbytes / fms / 1e6 / HBM_PEAK_GBS, 4)}}
+    del b, sink, m_out
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -186,6 +228,7 @@ def main():  # noqa: C901
     ap.add_argument("--no-compressed", action="store_true", help="skip the FP16/BF16-checkpoint forms")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 64-shot uneven-window batched form")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape")
+    ap.add_argument("--no-extension-ops", action="store_true", help="skip timing the ZOI and final-model kernels")
     ap.add_argument("--interval", type=int, default=-1,
                     help="checkpoint interval of the plain form (-1: largest that fits, 0: sqrt(nt))")
     ap.add_argument("--mem-fraction", type=float, default=0.92,
@@ -348,6 +391,11 @@ def main():  # noqa: C901
         del bws
         torch.cuda.empty_cache()
 
+    ext_ops = None
+    if not args.no_extension_ops:
+        ext_ops = extension_ops(efwi, torch, grid, w, m_ext, dev)
+        log(f"extension operators done: {ext_ops}")
+
     if not args.no_uneven:
         forms["batched_uneven_64"] = uneven_batched_form(efwi, inputs, torch, dev, grid, nt, log)
 
@@ -398,6 +446,7 @@ def main():  # noqa: C901
         "shots_per_s": {"plain": round(ns * args.steps / elapsed, 4),
                         **{k: v["shots_per_s"] for k, v in forms.items()}},
         "forms": forms,
+        "extension_ops": ext_ops,
         "kernels": kern,
     }
     if not args.no_cpu_baseline:

@@ -141,7 +141,8 @@ __global__ __launch_bounds__(RB) void k_zoi(long npts, int ny, int nx, double dz
     const bool in = d2 < 1.0;
     const double r_sink = in ? 1.0 - sqrt(d2) : 0.0;
     const double r = fmax(r_out, r_sink);
-    b[p] = (float)((pow(cos(0.5 * M_PI * r), a.n) - ln) / den);
+    // r = 0 (the active part) gives exactly 1: skip the transcendental functions there
+    b[p] = r > 0.0 ? (float)((pow(cos(0.5 * M_PI * r), a.n) - ln) / den) : 1.0f;
     sink[p] = in ? 1 : 0;
   }
 }
