@@ -172,6 +172,71 @@ def batched_2d(nshots=64, nt=4000, nz=1000, nx=3000, seed=64, M0=1.0e16, zrange=
     return base
 
 
+# ---------------------------------------------------------------------------------------
+# Guided-wave synthetic of the paper's inversion tests (Synthetic examples): three layers
+# with the starting-model parameters of Table 1 (top 4.5 / 2.3 km/s / 2.3 g/cc, middle
+# waveguide 3.0 / 1.7 / 2.0, bottom 5.5 / 2.7 / 2.5) and smooth transitions, Gaussian Vp and
+# Vs perturbations inside the waveguide, three sources in it with the same diagonal moment
+# tensor (M_zz / M_xx = 0.75) and a 10 Hz Ricker time function. The paper's receivers are
+# two-component geophones; here a horizontal DAS fiber along the waveguide records e_xx.
+# The geometry (sizes, layer depths, anomaly positions) is this recipe's own.
+# ---------------------------------------------------------------------------------------
+def guided_wave_synthetic(nz=100, nx=400, h=5.0, dt=0.5e-3, nt=1600, npml=20, M0=1.0e16, mute_m=100.0,
+                          source_errors=False):
+    from scipy.ndimage import gaussian_filter
+    z = np.arange(nz) * h
+    layer = np.zeros(nz, int)
+    top, bot = 230.0, 270.0                     # 40 m waveguide
+    layer[z >= top] = 1
+    layer[z >= bot] = 2
+    params = np.array([[4500.0, 2300.0, 2300.0], [3000.0, 1700.0, 2000.0], [5500.0, 2700.0, 2500.0]])
+    m_start = np.empty((3, nz, nx))
+    for k in range(3):
+        col = gaussian_filter(params[layer, k], sigma=1.0, mode="nearest")
+        m_start[k] = col[:, None]
+    zc = int(round(0.5 * (top + bot) / h))
+    m_true = m_start.copy()
+    # Vp: one faster and one slower blob; Vs: one faster blob between them (relative)
+    for k, cx, amp in ((0, 130, 0.06), (0, 270, -0.05), (1, 200, 0.06)):
+        m_true[k] *= 1.0 + gaussian_blob((nz, nx), zc, cx, 6.0, amp)
+    src_ix = [100, 200, 300]
+    all_ch = np.arange(30, nx - 30, 2).astype(np.int32)
+    M = np.array([M0, 0.75 * M0, 0.0])              # (Mxx, Mzz, Mxz)
+    stf = ricker(nt, dt, 10.0)
+    shots = []
+    for sx in src_ix:
+        # channels closer than mute_m to the source are left out (near-field strain)
+        ch_ix = all_ch[np.abs(all_ch - sx) * h >= mute_m]
+        shots.append(Shot2D(src_iz=zc, src_ix=sx, M=M.copy(), ch_iz=np.full(len(ch_ix), zc, np.int32), ch_ix=ch_ix))
+    w = Workload2D(name="guided-wave-synthetic", nz=nz, nx=nx, dz=h, dx=h, dt=dt, nt=nt, npml=npml, f0=10.0,
+                   vp_max=5500.0, stf=stf, m_start=m_start, m_true=m_true, shots=shots)
+    if source_errors:
+        w = with_source_errors(w)
+    return w
+
+
+def with_source_errors(w, shift_cells=1, mt_ratio=0.964, stf_error=0.165, seed=21):
+    """The inverting side's wrong source parameters (inversion with source-related errors):
+    every source one node to the left (the paper shifts 1 m on a finer grid), M_zz / M_xx set
+    to mt_ratio at the same Frobenius norm, and the time function perturbed by a smooth
+    random series of relative L2 size stf_error, smoothed over a quarter of the central
+    period so that the error lies in the wavelet's band."""
+    rng = np.random.default_rng(seed)
+    shots = []
+    for s in w.shots:
+        fro = math.sqrt(s.M[0] ** 2 + s.M[1] ** 2 + 2.0 * s.M[2] ** 2)
+        mxx = fro / math.sqrt(1.0 + mt_ratio ** 2)
+        M = np.array([mxx, mt_ratio * mxx, 0.0])
+        shots.append(Shot2D(src_iz=s.src_iz, src_ix=s.src_ix - shift_cells, M=M, ch_iz=s.ch_iz, ch_ix=s.ch_ix))
+    from scipy.ndimage import gaussian_filter1d
+    noise = gaussian_filter1d(rng.standard_normal(len(w.stf)), 0.25 / (w.f0 * w.dt))
+    noise *= np.exp(-0.5 * ((np.arange(len(w.stf)) * w.dt - 1.5 / w.f0) / (1.0 / w.f0)) ** 2)
+    noise *= stf_error * np.linalg.norm(w.stf) / np.linalg.norm(noise)
+    return Workload2D(name=w.name + "-source-errors", nz=w.nz, nx=w.nx, dz=w.dz, dx=w.dx, dt=w.dt, nt=w.nt,
+                      npml=w.npml, f0=w.f0, vp_max=w.vp_max, stf=w.stf + noise, m_start=w.m_start, m_true=w.m_true,
+                      shots=shots, pml_R=w.pml_R)
+
+
 def hard_sinkholes(nshots, nz, nx, src_iz, src_ix, a_z=8, a_x=40):
     """Hard source masks (uint8 [Ns][nz][nx]): 1 inside the ellipse |dz/a_z|^2 + |dx/a_x|^2 < 1
     around each source, and the matching ZOI weights b (0 inside, 1 elsewhere)."""
