@@ -26,6 +26,8 @@ resident in HBM before the timed region. The JSON line also carries:
   time steps), in the same unit;
 * path: the whole step's algorithmic bytes (168 B per cell-step plus 52 B per recomputed
   cell-step) over the step time; each checkpointed form carries the same as path_frac.
+* forms.precision_3d_sample: one shot of the 3D precision workload (300 x 400 x 400) for
+  200 of its 3000 steps with sqrt(nt) FP16 checkpoints, timed once.
 * extension_ops: the zones of influence (eq.(10)) of the 20 sources and the final model
   S_w W m~ (eq.(9)) on the full grid (once per inversion, not part of the step), each with
   its time and compulsory-bytes rate.
@@ -210,6 +212,34 @@ def extension_ops(efwi, torch, grid, w, m_ext, dev):
     return out
 
 
+def precision_3d_sample(efwi, inputs, torch, dev, nt=200):
+    """One shot of the 3D precision workload on its full 300 x 400 x 400 grid (5 m, CPML 20,
+    2000 DAS channels on two wells, six-component moment tensor), nt steps of the 3000 with
+    sqrt(nt) FP16 checkpoints, d_obs = 0; timed once after one untimed call."""
+    w = inputs.precision_3d(nt=nt, nshots=1, anomalies=False)
+    s = w.shots[0]
+    grid = efwi.make_grid3d(w.nz, w.ny, w.nx, w.h, w.h, w.h, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)
+    shot = efwi.Shot(s.src_iz, s.src_ix, s.ch_iz, s.ch_ix, src_iy=s.src_iy, ch_iy=s.ch_iy, ckpt_mode=efwi.CKPT_FP16)
+    m = torch.tensor(np.asarray(w.m_start, np.float32), device=dev)
+    src = torch.tensor(np.asarray(np.outer(s.M, w.stf), np.float32), device=dev)
+    d_obs = torch.zeros((len(s.ch_ix), nt), dtype=torch.float32, device=dev)
+    ws = efwi.workspace(efwi.workspace_size(efwi.WS_GRADIENT, grid, [shot]), dev)
+    efwi.shot_gradient(grid, shot, m, src, d_obs, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, _ = efwi.shot_gradient(grid, shot, m, src, d_obs, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cells = w.nz * w.ny * w.nx
+    out = {"grid": [w.nz, w.ny, w.nx], "nt": nt, "checkpoints": "sqrt(nt), FP16",
+           "recompute_fraction": round(efwi.recompute_fraction(grid, 0), 4),
+           "ms": round(dt * 1e3, 1), "gcell_per_s": round(cells * nt / dt / 1e9, 3),
+           "finite": bool(torch.isfinite(g).all())}
+    del ws, m, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -229,6 +259,7 @@ def main():  # noqa: C901
     ap.add_argument("--no-uneven", action="store_true", help="skip the 64-shot uneven-window batched form")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--no-extension-ops", action="store_true", help="skip timing the ZOI and final-model kernels")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D precision-workload sample")
     ap.add_argument("--interval", type=int, default=-1,
                     help="checkpoint interval of the plain form (-1: largest that fits, 0: sqrt(nt))")
     ap.add_argument("--mem-fraction", type=float, default=0.92,
@@ -399,6 +430,10 @@ def main():  # noqa: C901
     if not args.no_uneven:
         forms["batched_uneven_64"] = uneven_batched_form(efwi, inputs, torch, dev, grid, nt, log)
 
+    if not args.no_3d:
+        forms["precision_3d_sample"] = precision_3d_sample(efwi, inputs, torch, dev)
+        log(f"3D sample done: {forms['precision_3d_sample']}")
+
     cell_steps = ns * nz * nx * nt * args.steps
     value = cell_steps / elapsed / 1e9
     rf = efwi.recompute_fraction(grid, L)
@@ -444,7 +479,7 @@ def main():  # noqa: C901
                  "achieved_GBs": round(pb * cell_steps / elapsed / 1e9, 1),
                  "frac": round(pb * cell_steps / elapsed / 1e9 / HBM_PEAK_GBS, 4)},
         "shots_per_s": {"plain": round(ns * args.steps / elapsed, 4),
-                        **{k: v["shots_per_s"] for k, v in forms.items()}},
+                        **{k: v["shots_per_s"] for k, v in forms.items() if "shots_per_s" in v}},
         "forms": forms,
         "extension_ops": ext_ops,
         "kernels": kern,

@@ -86,10 +86,21 @@ __device__ __forceinline__ bool tile3(const int* __restrict__ sched, const int* 
   const Shot3D& s = shots[sh_];                                                                        \
   const int j = j0 + threadIdx.x, k = k0 + threadIdx.y
 
-// CPML update psi <- b psi + a D at an owned node; returns D + psi.
-__device__ __forceinline__ float cpml(gfloat* psi, long q, const gfloat* a, const gfloat* b, int c, float d) {
-  const float p = b[c] * psi[q] + a[c] * d;
-  psi[q] = p;
+// Streaming (non-temporal) accesses of the history: written once per forward step, read
+// once in the reverse sweep, so they should not displace the wavefields in the caches.
+__device__ __forceinline__ void hist_put(gfloat* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ float hist_get(const gfloat* p) { return __builtin_nontemporal_load(p); }
+
+// Every cell function below reads all it needs before its first store: the compiler cannot
+// prove that the arrays do not alias, so a load placed after a store would cost another
+// memory round trip per wavefront.
+
+// CPML memory variable at an owned node: psi <- b psi + a D computed from the old value
+// (read with the cell's other inputs, before any store) into p; returns D + psi. The caller
+// stores p after the cell's field updates.
+__device__ __forceinline__ float cpml_new(const gfloat* psi, long q, const gfloat* a, const gfloat* b, int c, float d,
+                                          float& p) {
+  p = b[c] * psi[q] + a[c] * d;
   return d + p;
 }
 
@@ -103,36 +114,45 @@ __device__ __forceinline__ void fwd_vel3(const Shot3D& s, int i, int k, int j, g
   float a1 = dplus(s.sxx, o, 1, s.rdx), a2 = dminus(s.sxy, o, ld, s.rdy), a3 = dminus(s.sxz, o, pz, s.rdz);
   float b1 = dminus(s.sxy, o, 1, s.rdx), b2 = dplus(s.syy, o, ld, s.rdy), b3 = dminus(s.syz, o, pz, s.rdz);
   float c1 = dminus(s.sxz, o, 1, s.rdx), c2 = dminus(s.syz, o, ld, s.rdy), c3 = dplus(s.szz, o, pz, s.rdz);
+  const float vx = s.vx[o], vy = s.vy[o], vz = s.vz[o], bx = s.bx[o], by = s.by[o], bz = s.bz[o];
+  int sx = -1, sy = -1, sz = -1;
+  long qxs = 0, qys = 0, qzs = 0;
+  float p[9];
   if (PML) {
-    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+    sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
-      const long q = xq(s, i, k, sx);
-      a1 = cpml(s.psx[XS_VX], q, px_(s, 2), px_(s, 3), j, a1);
-      b1 = cpml(s.psx[XS_VY], q, px_(s, 0), px_(s, 1), j, b1);
-      c1 = cpml(s.psx[XS_VZ], q, px_(s, 0), px_(s, 1), j, c1);
+      qxs = xq(s, i, k, sx);
+      a1 = cpml_new(s.psx[XS_VX], qxs, px_(s, 2), px_(s, 3), j, a1, p[0]);
+      b1 = cpml_new(s.psx[XS_VY], qxs, px_(s, 0), px_(s, 1), j, b1, p[1]);
+      c1 = cpml_new(s.psx[XS_VZ], qxs, px_(s, 0), px_(s, 1), j, c1, p[2]);
     }
     if (sy >= 0) {
-      const long q = yq(s, i, sy, j);
-      a2 = cpml(s.psy[YS_VX], q, py_(s, 0), py_(s, 1), k, a2);
-      b2 = cpml(s.psy[YS_VY], q, py_(s, 2), py_(s, 3), k, b2);
-      c2 = cpml(s.psy[YS_VZ], q, py_(s, 0), py_(s, 1), k, c2);
+      qys = yq(s, i, sy, j);
+      a2 = cpml_new(s.psy[YS_VX], qys, py_(s, 0), py_(s, 1), k, a2, p[3]);
+      b2 = cpml_new(s.psy[YS_VY], qys, py_(s, 2), py_(s, 3), k, b2, p[4]);
+      c2 = cpml_new(s.psy[YS_VZ], qys, py_(s, 0), py_(s, 1), k, c2, p[5]);
     }
     if (sz >= 0) {
-      const long q = zq(s, sz, k, j);
-      a3 = cpml(s.psz[ZS_VX], q, pz_(s, 0), pz_(s, 1), i, a3);
-      b3 = cpml(s.psz[ZS_VY], q, pz_(s, 0), pz_(s, 1), i, b3);
-      c3 = cpml(s.psz[ZS_VZ], q, pz_(s, 2), pz_(s, 3), i, c3);
+      qzs = zq(s, sz, k, j);
+      a3 = cpml_new(s.psz[ZS_VX], qzs, pz_(s, 0), pz_(s, 1), i, a3, p[6]);
+      b3 = cpml_new(s.psz[ZS_VY], qzs, pz_(s, 0), pz_(s, 1), i, b3, p[7]);
+      c3 = cpml_new(s.psz[ZS_VZ], qzs, pz_(s, 2), pz_(s, 3), i, c3, p[8]);
     }
   }
   const float qx = a1 + a2 + a3, qy = b1 + b2 + b3, qz = c1 + c2 + c3;
-  s.vx[o] += s.dt * s.bx[o] * qx;
-  s.vy[o] += s.dt * s.by[o] * qy;
-  s.vz[o] += s.dt * s.bz[o] * qz;
+  s.vx[o] = vx + s.dt * bx * qx;
+  s.vy[o] = vy + s.dt * by * qy;
+  s.vz[o] = vz + s.dt * bz * qz;
+  if (PML) {
+    if (sx >= 0) s.psx[XS_VX][qxs] = p[0], s.psx[XS_VY][qxs] = p[1], s.psx[XS_VZ][qxs] = p[2];
+    if (sy >= 0) s.psy[YS_VX][qys] = p[3], s.psy[YS_VY][qys] = p[4], s.psy[YS_VZ][qys] = p[5];
+    if (sz >= 0) s.psz[ZS_VX][qzs] = p[6], s.psz[ZS_VY][qzs] = p[7], s.psz[ZS_VZ][qzs] = p[8];
+  }
   if (STORE) {
     const long c = ((long)i * s.ny + k) * s.cp + j;
-    seg[6 * s.cells + c] = qx / s.bx[o];
-    seg[7 * s.cells + c] = qy / s.by[o];
-    seg[8 * s.cells + c] = qz / s.bz[o];
+    hist_put(seg + 6 * s.cells + c, qx / bx);
+    hist_put(seg + 7 * s.cells + c, qy / by);
+    hist_put(seg + 8 * s.cells + c, qz / bz);
   }
 }
 
@@ -157,36 +177,42 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
   float vx_z = dplus(s.vx, o, pz, s.rdz), vz_x = dplus(s.vz, o, 1, s.rdx);
   float vy_z = dplus(s.vy, o, pz, s.rdz), vz_y = dplus(s.vz, o, ld, s.rdy);
   const float raw_pxx = pxx;
+  const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
+  const float mxy = s.muxy[o], mxz = s.muxz[o], myz = s.muyz[o];
+  const float sxx0 = s.sxx[o], syy0 = s.syy[o], szz0 = s.szz[o], sxy0 = s.sxy[o], sxz0 = s.sxz[o], syz0 = s.syz[o];
+  const int slot = RECORD ? s.row_slot[(long)i * s.ny + k] : -1;
+  int sx = -1, sy = -1, sz = -1;
+  long qxs = 0, qys = 0, qzs = 0;
+  float p[9];
   if (PML) {
-    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+    sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
-      const long q = xq(s, i, k, sx);
-      pxx = cpml(s.psx[XS_PXX], q, px_(s, 0), px_(s, 1), j, pxx);
-      vy_x = cpml(s.psx[XS_SXY], q, px_(s, 2), px_(s, 3), j, vy_x);
-      vz_x = cpml(s.psx[XS_SXZ], q, px_(s, 2), px_(s, 3), j, vz_x);
+      qxs = xq(s, i, k, sx);
+      pxx = cpml_new(s.psx[XS_PXX], qxs, px_(s, 0), px_(s, 1), j, pxx, p[0]);
+      vy_x = cpml_new(s.psx[XS_SXY], qxs, px_(s, 2), px_(s, 3), j, vy_x, p[1]);
+      vz_x = cpml_new(s.psx[XS_SXZ], qxs, px_(s, 2), px_(s, 3), j, vz_x, p[2]);
     }
     if (sy >= 0) {
-      const long q = yq(s, i, sy, j);
-      pyy = cpml(s.psy[YS_PYY], q, py_(s, 0), py_(s, 1), k, pyy);
-      vx_y = cpml(s.psy[YS_SXY], q, py_(s, 2), py_(s, 3), k, vx_y);
-      vz_y = cpml(s.psy[YS_SYZ], q, py_(s, 2), py_(s, 3), k, vz_y);
+      qys = yq(s, i, sy, j);
+      pyy = cpml_new(s.psy[YS_PYY], qys, py_(s, 0), py_(s, 1), k, pyy, p[3]);
+      vx_y = cpml_new(s.psy[YS_SXY], qys, py_(s, 2), py_(s, 3), k, vx_y, p[4]);
+      vz_y = cpml_new(s.psy[YS_SYZ], qys, py_(s, 2), py_(s, 3), k, vz_y, p[5]);
     }
     if (sz >= 0) {
-      const long q = zq(s, sz, k, j);
-      pzz = cpml(s.psz[ZS_PZZ], q, pz_(s, 0), pz_(s, 1), i, pzz);
-      vx_z = cpml(s.psz[ZS_SXZ], q, pz_(s, 2), pz_(s, 3), i, vx_z);
-      vy_z = cpml(s.psz[ZS_SYZ], q, pz_(s, 2), pz_(s, 3), i, vy_z);
+      qzs = zq(s, sz, k, j);
+      pzz = cpml_new(s.psz[ZS_PZZ], qzs, pz_(s, 0), pz_(s, 1), i, pzz, p[6]);
+      vx_z = cpml_new(s.psz[ZS_SXZ], qzs, pz_(s, 2), pz_(s, 3), i, vx_z, p[7]);
+      vy_z = cpml_new(s.psz[ZS_SYZ], qzs, pz_(s, 2), pz_(s, 3), i, vy_z, p[8]);
     }
   }
-  const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
   const float tr = pxx + pyy + pzz;
   const float sxy_r = vx_y + vy_x, sxz_r = vx_z + vz_x, syz_r = vy_z + vz_y;
-  float sxx = s.sxx[o] + s.dt * (lam * tr + two_mu * pxx);
-  float syy = s.syy[o] + s.dt * (lam * tr + two_mu * pyy);
-  float szz = s.szz[o] + s.dt * (lam * tr + two_mu * pzz);
-  float sxy = s.sxy[o] + s.dt * s.muxy[o] * sxy_r;
-  float sxz = s.sxz[o] + s.dt * s.muxz[o] * sxz_r;
-  float syz = s.syz[o] + s.dt * s.muyz[o] * syz_r;
+  float sxx = sxx0 + s.dt * (lam * tr + two_mu * pxx);
+  float syy = syy0 + s.dt * (lam * tr + two_mu * pyy);
+  float szz = szz0 + s.dt * (lam * tr + two_mu * pzz);
+  float sxy = sxy0 + s.dt * mxy * sxy_r;
+  float sxz = sxz0 + s.dt * mxz * sxz_r;
+  float syz = syz0 + s.dt * myz * syz_r;
   const int nt = s.nt;
   if (i == s.si && k == s.sk && j == s.sj) {
     sxx -= s.w * s.src[n];
@@ -203,8 +229,12 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
   s.sxy[o] = sxy;
   s.sxz[o] = sxz;
   s.syz[o] = syz;
+  if (PML) {
+    if (sx >= 0) s.psx[XS_PXX][qxs] = p[0], s.psx[XS_SXY][qxs] = p[1], s.psx[XS_SXZ][qxs] = p[2];
+    if (sy >= 0) s.psy[YS_PYY][qys] = p[3], s.psy[YS_SXY][qys] = p[4], s.psy[YS_SYZ][qys] = p[5];
+    if (sz >= 0) s.psz[ZS_PZZ][qzs] = p[6], s.psz[ZS_SXZ][qzs] = p[7], s.psz[ZS_SYZ][qzs] = p[8];
+  }
   if (RECORD) {
-    const int slot = s.row_slot[(long)i * s.ny + k];
     if (slot >= 0) {
       const int c = s.rowch[(long)slot * s.nx + j];
       if (c >= 0) {
@@ -217,13 +247,12 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
   if (STORE) {
     const long c = ((long)i * s.ny + k) * s.cp + j;
     const float mu = 0.5f * two_mu, third = tr * (1.0f / 3.0f);
-    const float mxy = s.muxy[o], mxz = s.muxz[o], myz = s.muyz[o];
-    seg[c] = tr / (l2m + 2.0f * lam);
-    seg[s.cells + c] = (pxx - third) / mu;
-    seg[2 * s.cells + c] = (pyy - third) / mu;
-    seg[3 * s.cells + c] = mxy > 0.0f ? sxy_r / mxy : 0.0f;
-    seg[4 * s.cells + c] = mxz > 0.0f ? sxz_r / mxz : 0.0f;
-    seg[5 * s.cells + c] = myz > 0.0f ? syz_r / myz : 0.0f;
+    hist_put(seg + c, tr / (l2m + 2.0f * lam));
+    hist_put(seg + s.cells + c, (pxx - third) / mu);
+    hist_put(seg + 2 * s.cells + c, (pyy - third) / mu);
+    hist_put(seg + 3 * s.cells + c, mxy > 0.0f ? sxy_r / mxy : 0.0f);
+    hist_put(seg + 4 * s.cells + c, mxz > 0.0f ? sxz_r / mxz : 0.0f);
+    hist_put(seg + 5 * s.cells + c, myz > 0.0f ? syz_r / myz : 0.0f);
   }
 }
 
@@ -279,11 +308,6 @@ __device__ __forceinline__ float ebar3(const Shot3D& s, int slot, int jc, int n)
   return c >= 0 ? s.ebar[(long)n * s.nch + c] : 0.0f;
 }
 
-__device__ __forceinline__ void acc3(gfloat* acc, long idx, float v, bool first) {
-  if (first) acc[idx] = v;
-  else acc[idx] += v;
-}
-
 // Transposed stress sub-step: t_bar -> u_bar.
 template <bool GRAD, bool SRCADJ, bool PML>
 __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, int n, const gfloat* seg, bool first) {
@@ -325,9 +349,13 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
   }
   const float txx = s.txxb[o], tyy = s.tyyb[o], tzz = s.tzzb[o];
   const float txy = s.txyb[o], txz = s.txzb[o], tyz = s.tyzb[o];
-  if (PML) {
-    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+  const float ux = s.uxb[o], uy = s.uyb[o], uz = s.uzb[o], bx = s.bx[o], by = s.by[o], bz = s.bz[o];
+  s.uxb[o] = ux + bx * gx;
+  s.uyb[o] = uy + by * gy;
+  s.uzb[o] = uz + bz * gz;
+  if (PML) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
     const float dt = s.dt;
+    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
       const long q = xq(s, i, k, sx);
       s.pbx[wr][XS_PXX][q] = px_(s, 1)[j] * (s.pbx[rd][XS_PXX][q] + dt * txx);
@@ -347,19 +375,20 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
       s.pbz[wr][ZS_SYZ][q] = pz_(s, 3)[i] * (s.pbz[rd][ZS_SYZ][q] + dt * tyz);
     }
   }
-  s.uxb[o] += s.bx[o] * gx;
-  s.uyb[o] += s.by[o] * gy;
-  s.uzb[o] += s.bz[o] * gz;
   if (GRAD) {
     const long c = ((long)i * s.ny + k) * s.cp + j;
+    float h[6], a[5] = {0, 0, 0, 0, 0};
+    for (int f = 0; f < 6; ++f) h[f] = hist_get(seg + f * s.cells + c);
+    if (!first)
+      for (int f = 0; f < 5; ++f) a[f] = s.acc[f * s.cells + c];
     const float trt = txx + tyy + tzz;
     const float da = txx - trt * (1.0f / 3.0f), db = tyy - trt * (1.0f / 3.0f);
-    const float D1 = seg[s.cells + c], D2 = seg[2 * s.cells + c];
-    acc3(s.acc, c, s.dt * trt * seg[c], first);
-    acc3(s.acc, s.cells + c, s.dt * (da * D1 + db * D2 + (da + db) * (D1 + D2)), first);
-    acc3(s.acc, 2 * s.cells + c, s.dt * txy * seg[3 * s.cells + c], first);
-    acc3(s.acc, 3 * s.cells + c, s.dt * txz * seg[4 * s.cells + c], first);
-    acc3(s.acc, 4 * s.cells + c, s.dt * tyz * seg[5 * s.cells + c], first);
+    const float D1 = h[1], D2 = h[2];
+    s.acc[c] = a[0] + s.dt * trt * h[0];
+    s.acc[s.cells + c] = a[1] + s.dt * (da * D1 + db * D2 + (da + db) * (D1 + D2));
+    s.acc[2 * s.cells + c] = a[2] + s.dt * txy * h[3];
+    s.acc[3 * s.cells + c] = a[3] + s.dt * txz * h[4];
+    s.acc[4 * s.cells + c] = a[4] + s.dt * tyz * h[5];
   }
   if (SRCADJ && i == s.si && k == s.sk && j == s.sj) {
     // sigma_bar at the source: invert C on the normal block and the shear moduli
@@ -419,9 +448,19 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
   const float dyz = -((K1 * (Qyz(i + 1, k, j) - Qyz(i, k, j)) + K2 * (Qyz(i + 2, k, j) - Qyz(i - 1, k, j))) * s.rdz +
                       (K1 * (Qzy(i, k + 1, j) - Qzy(i, k, j)) + K2 * (Qzy(i, k + 2, j) - Qzy(i, k - 1, j))) * s.rdy);
   const float ux = s.uxb[o], uy = s.uyb[o], uz = s.uzb[o];
-  if (PML) {
-    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+  const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
+  const float mxy = s.muxy[o], mxz = s.muxz[o], myz = s.muyz[o];
+  const float txx = s.txxb[o], tyy = s.tyyb[o], tzz = s.tzzb[o], txy = s.txyb[o], txz = s.txzb[o], tyz = s.tyzb[o];
+  const float tr = dxx + dyy + dzz;
+  s.txxb[o] = txx + (lam * tr + two_mu * dxx);
+  s.tyyb[o] = tyy + (lam * tr + two_mu * dyy);
+  s.tzzb[o] = tzz + (lam * tr + two_mu * dzz);
+  s.txyb[o] = txy + mxy * dxy;
+  s.txzb[o] = txz + mxz * dxz;
+  s.tyzb[o] = tyz + myz * dyz;
+  if (PML) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
     const float dt = s.dt;
+    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
       const long q = xq(s, i, k, sx);
       s.pbx[wr][XS_VX][q] = px_(s, 3)[j] * (s.pbx[rd][XS_VX][q] + dt * ux);
@@ -441,19 +480,15 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
       s.pbz[wr][ZS_VZ][q] = pz_(s, 3)[i] * (s.pbz[rd][ZS_VZ][q] + dt * uz);
     }
   }
-  const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
-  const float tr = dxx + dyy + dzz;
-  s.txxb[o] += lam * tr + two_mu * dxx;
-  s.tyyb[o] += lam * tr + two_mu * dyy;
-  s.tzzb[o] += lam * tr + two_mu * dzz;
-  s.txyb[o] += s.muxy[o] * dxy;
-  s.txzb[o] += s.muxz[o] * dxz;
-  s.tyzb[o] += s.muyz[o] * dyz;
   if (GRAD) {
     const long c = ((long)i * s.ny + k) * s.cp + j;
-    acc3(s.acc, 5 * s.cells + c, s.dt * ux * seg[6 * s.cells + c], first);
-    acc3(s.acc, 6 * s.cells + c, s.dt * uy * seg[7 * s.cells + c], first);
-    acc3(s.acc, 7 * s.cells + c, s.dt * uz * seg[8 * s.cells + c], first);
+    float h[3], a[3] = {0, 0, 0};
+    for (int f = 0; f < 3; ++f) h[f] = hist_get(seg + (6 + f) * s.cells + c);
+    if (!first)
+      for (int f = 0; f < 3; ++f) a[f] = s.acc[(5 + f) * s.cells + c];
+    s.acc[5 * s.cells + c] = a[0] + s.dt * ux * h[0];
+    s.acc[6 * s.cells + c] = a[1] + s.dt * uy * h[1];
+    s.acc[7 * s.cells + c] = a[2] + s.dt * uz * h[2];
   }
 }
 

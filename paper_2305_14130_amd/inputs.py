@@ -290,7 +290,7 @@ class Workload3D:
 
 
 def precision_3d(nz=300, ny=400, nx=400, nt=3000, nshots=8, nch_per_well=1000, h=5.0, dt=0.4e-3, npml=20,
-                 f0=30.0, M0=1.0e16, seed=8):
+                 f0=30.0, M0=1.0e16, seed=8, anomalies=True):
     """The shale geology at 5 m in 3D: background Vp 3800, Vs/Vp 0.6, rho 2550 with a 15 m
     (3-cell) reservoir Vp 3400, Vs/Vp 0.55, rho 2450 at mid depth, +-5% Gaussian-correlated
     anomalies (50 m) in the true model, moment-tensor shots (six components, seed 8) in the
@@ -299,8 +299,9 @@ def precision_3d(nz=300, ny=400, nx=400, nt=3000, nshots=8, nch_per_well=1000, h
     m = _shale_model(nz, nx, h, res_top, res_top + 3, anomalies=False)[:, :, None, :]
     m_start = np.repeat(m, ny, axis=2).transpose(0, 1, 2, 3)            # [3][nz][ny][nx]
     m_true = m_start.copy()
-    for k in range(3):
-        m_true[k] *= 1.0 + smooth_random_field((nz, ny, nx), 50.0 / h, 14130 + k, 0.05)
+    if anomalies:   # (the timing sample of the full grid skips them: no observed data needed)
+        for k in range(3):
+            m_true[k] *= 1.0 + smooth_random_field((nz, ny, nx), 50.0 / h, 14130 + k, 0.05)
     iz = nz // 2
     wells = [int(ny * 3 // 8), int(ny * 5 // 8)]
     lo = npml + 2
