@@ -61,6 +61,27 @@ __device__ __forceinline__ bool tile_in_pml(const Shot3D& s, int i, int k0, int 
          (k0 + TY - 1 + pad >= s.ny - s.P) || (i - pad < s.P) || (i + pad >= s.nz - s.P);
 }
 
+// Which axes' CPML strips a tile's cells (widened by pad on every side) reach: bit 0 x,
+// bit 1 y, bit 2 z.
+__device__ __forceinline__ int pml_axes(const Shot3D& s, int i, int k0, int j0, int pad) {
+  if (s.P <= 0) return 0;
+  const bool x = (j0 - pad < s.P) || (j0 + TX - 1 + pad >= s.nx - s.P);
+  const bool y = (k0 - pad < s.P) || (k0 + TY - 1 + pad >= s.ny - s.P);
+  const bool z = (i - pad < s.P) || (i + pad >= s.nz - s.P);
+  return (x ? 1 : 0) | (y ? 2 : 0) | (z ? 4 : 0);
+}
+#define DISPATCH_AXES(m, CALL)          \
+  switch (m) {                          \
+    case 0: CALL(false, false, false); break; \
+    case 1: CALL(true, false, false); break;  \
+    case 2: CALL(false, true, false); break;  \
+    case 3: CALL(true, true, false); break;   \
+    case 4: CALL(false, false, true); break;  \
+    case 5: CALL(true, false, true); break;   \
+    case 6: CALL(false, true, true); break;   \
+    default: CALL(true, true, true); break;   \
+  }
+
 // Tile list per shot: z plane, y band, x block (x fastest). Schedule as in 2D.
 __device__ __forceinline__ bool tile3(const int* __restrict__ sched, const int* __restrict__ tile_shot,
                                       const int* __restrict__ tile_first, const Shot3D* __restrict__ shots, int& sh,
@@ -268,30 +289,30 @@ __global__ __launch_bounds__(TX * TY) void k3_fwd_str(PARAMS3, int n, int kstore
 // ------------------------------------------------------------------------------------
 // Adjoint. Corrected transposed operands at a neighbour node: v + a (psi_bar + v) inside
 // the CPML strip of the derivative's axis (psi_bar from the buffer of step n+1), v outside.
+// PX, PY, PZ: the tile's stencil reaches a strip on that axis (otherwise no correction on
+// it is possible). A neighbour differs from the owned node only along the derivative's
+// axis, so only that index needs a range check (strip_index is negative below 0).
 // ------------------------------------------------------------------------------------
-template <bool PML>
+template <bool PX, bool PY, bool PZ>
 struct Adj3 {
   const Shot3D& s;
   int rd;
-  __device__ __forceinline__ bool in(int i, int k, int j) const {
-    return i >= 0 && i < s.nz && k >= 0 && k < s.ny && j >= 0 && j < s.nx;
-  }
   __device__ __forceinline__ float cx(float v, int i, int k, int j, int slot, int prof) const {
-    if (PML && in(i, k, j)) {
+    if (PX && j < s.nx) {
       const int sx = strip_index(j, s.nx, s.P);
       if (sx >= 0) v += px_(s, prof)[j] * (s.pbx[rd][slot][xq(s, i, k, sx)] + v);
     }
     return v;
   }
   __device__ __forceinline__ float cy(float v, int i, int k, int j, int slot, int prof) const {
-    if (PML && in(i, k, j)) {
+    if (PY && k < s.ny) {
       const int sy = strip_index(k, s.ny, s.P);
       if (sy >= 0) v += py_(s, prof)[k] * (s.pby[rd][slot][yq(s, i, sy, j)] + v);
     }
     return v;
   }
   __device__ __forceinline__ float cz(float v, int i, int k, int j, int slot, int prof) const {
-    if (PML && in(i, k, j)) {
+    if (PZ && i < s.nz) {
       const int sz = strip_index(i, s.nz, s.P);
       if (sz >= 0) v += pz_(s, prof)[i] * (s.pbz[rd][slot][zq(s, sz, k, j)] + v);
     }
@@ -309,12 +330,12 @@ __device__ __forceinline__ float ebar3(const Shot3D& s, int slot, int jc, int n)
 }
 
 // Transposed stress sub-step: t_bar -> u_bar.
-template <bool GRAD, bool SRCADJ, bool PML>
+template <bool GRAD, bool SRCADJ, bool PX, bool PY, bool PZ>
 __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, int n, const gfloat* seg, bool first) {
   const long ld = s.ld, pz = s.pz;
   const long o = (long)i * pz + (long)k * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  const Adj3<PML> A{s, rd};
+  const Adj3<PX, PY, PZ> A{s, rd};
   // operands: normal (int profile on their own axis), shear (half profile on the axis of
   // the velocity derivative they came from)
   auto Pxx = [&](int a, int b, int c) { return A.cx(A.at(s.txxb, a, b, c), a, b, c, XS_PXX, 0); };
@@ -353,9 +374,10 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
   s.uxb[o] = ux + bx * gx;
   s.uyb[o] = uy + by * gy;
   s.uzb[o] = uz + bz * gz;
-  if (PML) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
+  if (PX || PY || PZ) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
     const float dt = s.dt;
-    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+    const int sx = PX ? strip_index(j, s.nx, s.P) : -1, sy = PY ? strip_index(k, s.ny, s.P) : -1,
+              sz = PZ ? strip_index(i, s.nz, s.P) : -1;
     if (sx >= 0) {
       const long q = xq(s, i, k, sx);
       s.pbx[wr][XS_PXX][q] = px_(s, 1)[j] * (s.pbx[rd][XS_PXX][q] + dt * txx);
@@ -417,17 +439,18 @@ __global__ __launch_bounds__(TX * TY) void k3_adj_vel(PARAMS3, int n, int kseg, 
   TILE3();
   if (k >= s.ny || j >= s.nx) return;
   const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
-  if (tile_in_pml(s, i, k0, j0, 2)) adj_vel3<GRAD, SRCADJ, true>(s, i, k, j, n, seg, first != 0);
-  else adj_vel3<GRAD, SRCADJ, false>(s, i, k, j, n, seg, first != 0);
+#define CALL(X, Y, Z) adj_vel3<GRAD, SRCADJ, X, Y, Z>(s, i, k, j, n, seg, first != 0)
+  DISPATCH_AXES(pml_axes(s, i, k0, j0, 2), CALL);
+#undef CALL
 }
 
 // Transposed velocity sub-step: u_bar -> t_bar.
-template <bool GRAD, bool PML>
+template <bool GRAD, bool PX, bool PY, bool PZ>
 __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, int n, const gfloat* seg, bool first) {
   const long ld = s.ld, pz = s.pz;
   const long o = (long)i * pz + (long)k * ld + j;
   const int rd = (n + 1) & 1, wr = n & 1;
-  const Adj3<PML> A{s, rd};
+  const Adj3<PX, PY, PZ> A{s, rd};
   auto Qxx = [&](int a, int b, int c) { return A.cx(A.at(s.uxb, a, b, c), a, b, c, XS_VX, 2); };  // vx: D+x sxx
   auto Qxy = [&](int a, int b, int c) { return A.cy(A.at(s.uxb, a, b, c), a, b, c, YS_VX, 0); };  // vx: D-y sxy
   auto Qxz = [&](int a, int b, int c) { return A.cz(A.at(s.uxb, a, b, c), a, b, c, ZS_VX, 0); };  // vx: D-z sxz
@@ -458,9 +481,10 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
   s.txyb[o] = txy + mxy * dxy;
   s.txzb[o] = txz + mxz * dxz;
   s.tyzb[o] = tyz + myz * dyz;
-  if (PML) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
+  if (PX || PY || PZ) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
     const float dt = s.dt;
-    const int sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
+    const int sx = PX ? strip_index(j, s.nx, s.P) : -1, sy = PY ? strip_index(k, s.ny, s.P) : -1,
+              sz = PZ ? strip_index(i, s.nz, s.P) : -1;
     if (sx >= 0) {
       const long q = xq(s, i, k, sx);
       s.pbx[wr][XS_VX][q] = px_(s, 3)[j] * (s.pbx[rd][XS_VX][q] + dt * ux);
@@ -497,8 +521,9 @@ __global__ __launch_bounds__(TX * TY) void k3_adj_str(PARAMS3, int n, int kseg, 
   TILE3();
   if (k >= s.ny || j >= s.nx) return;
   const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
-  if (tile_in_pml(s, i, k0, j0, 2)) adj_str3<GRAD, true>(s, i, k, j, n, seg, first != 0);
-  else adj_str3<GRAD, false>(s, i, k, j, n, seg, first != 0);
+#define CALL(X, Y, Z) adj_str3<GRAD, X, Y, Z>(s, i, k, j, n, seg, first != 0)
+  DISPATCH_AXES(pml_axes(s, i, k0, j0, 2), CALL);
+#undef CALL
 }
 
 // ------------------------------------------------------------------------------------
