@@ -14,6 +14,9 @@ Modules
                 and S^T, written as dense per-point matrices.
 ``checkpoint``  the 16-bit checkpoint encodings (per-snapshot max-abs scaling).
 ``zoi``         the sources' zones of influence, eq.(10): weights b_s and sinkhole flags.
+``precondition`` the comparison methods: approximate inverse pseudo-Hessian (velocity
+                autocorrelation summed over shots, clipped, scaled), near-offset mute; the
+                gradient preconditioning of eq.(15) is ``regularizer.final_model``.
 
 Every function is FP64 and unblocked; arrays are NumPy. Where the paper is silent
 (discretization, absorbing boundary, source injection, DAS sampling details) the reading
