@@ -215,6 +215,26 @@ efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zone
 efwi_status efwi_final_model(const efwi_grid* grid, int ns, const float* m_ext, const float* b,
                              const unsigned char* sink, float* m_out, void* stream);
 
+/* pseudo_hessian: the approximate inverse pseudo-Hessian that the paper gives l-BFGS as
+ * its initial inverse Hessian in the comparison with alternative methods (synthetic
+ * example): the zero-lag autocorrelation in time of the particle velocity, summed over
+ * shots, clipped and scaled. Each shot s runs the forward problem on its own component
+ * m_s and window (no data are recorded) and adds, at every normal node of its window,
+ * vx^2 + vz^2 of the velocities of every step (vx at (i, j+1/2), vz at (i+1/2, j)); then
+ *   h = sum over shots (0 outside every window), FP32 sums in time, shots added in order;
+ *   p = c max(h) / max(h, c max(h)), c = clip: 1 where h <= c max(h), smallest (c) where
+ *       h is largest; p = 1 everywhere if h is 0.
+ * 2D only. Shots advance in waves as in efwi_batch_gradient.
+ *   m_ext DEVICE [ns][3][nz][nx]; src DEVICE [ns][3][nt];
+ *   clip  in (0, 1];
+ *   h     DEVICE [nz][nx] output (raw sums); p DEVICE [nz][nx] output (the operator);
+ *   ws    at least efwi_workspace_size(EFWI_WS_GRADIENT, ...) of the largest shot.
+ * EFWI_E_INVAL for a 3D grid, a clip outside (0, 1] or NULL arrays; EFWI_E_WORKSPACE if
+ * one shot does not fit. */
+efwi_status efwi_pseudo_hessian(const efwi_grid* grid, int ns, const efwi_shot* shots, const float* m_ext,
+                                const float* src, float clip, float* h, float* p, void* ws, size_t ws_bytes,
+                                void* stream);
+
 /* Tile shape of the fused 2D forward and transposed time-step kernels: tiles of 8, 12 or
  * 16 rows by 64 columns (the stencil halo is recomputed per tile, so taller tiles recompute
  * less but hold more LDS and registers). Results do not depend on the choice (every node

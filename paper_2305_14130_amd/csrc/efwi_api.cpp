@@ -106,11 +106,11 @@ Staging& staging() {
 // fused 2D forward and transposed steps.
 enum KernelKind {
   KK_FWD_VEL = 0, KK_FWD_STR, KK_ADJ_VEL, KK_ADJ_STR, KK_CHAIN, KK_MISFIT, KK_REG, KK_FWD_STEP, KK_ADJ_STEP,
-  KK_ZOI, KK_FINAL, KK_COUNT
+  KK_ZOI, KK_FINAL, KK_ACORR, KK_COUNT
 };
 const char* const kKernelNames[KK_COUNT] = {"fwd_vel", "fwd_str",     "adj_vel",  "adj_str", "chain_flush",
                                             "misfit",  "regularizer", "fwd_step", "adj_step",
-                                            "zoi",     "final_model"};
+                                            "zoi",     "final_model", "fwd_acorr"};
 
 class Sampler {
  public:
@@ -1694,6 +1694,52 @@ efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zone
                   launch_zoi(three ? 1 : 0, npts, ny, grid->nx, grid->dz, three ? grid->dy : 0.0, grid->dx, a,
                              b + (size_t)s * npts, sink + (size_t)s * npts, st)));
   }
+  return EFWI_OK;
+}
+
+efwi_status efwi_pseudo_hessian(const efwi_grid* grid, int ns, const efwi_shot* shots, const float* m_ext,
+                                const float* src, float clip, float* h, float* p, void* ws, size_t ws_bytes,
+                                void* stream) {
+  efwi_status rc = efwi_validate(grid, ns, shots);
+  if (rc != EFWI_OK) return rc;
+  if (grid->ndim != 2) return fail(EFWI_E_INVAL, "pseudo_hessian is 2D only");
+  if (ns < 1) return fail(EFWI_E_INVAL, "ns must be >= 1");
+  if (!m_ext || !src || !h || !p) return fail(EFWI_E_INVAL, "NULL array argument");
+  if (!(clip > 0.0f && clip <= 1.0f)) return fail(EFWI_E_INVAL, "clip must be in (0, 1]");
+  const efwi_grid& g = *grid;
+  const long plane = (long)g.nz * g.nx;
+  std::vector<ShotIO> io(ns);
+  for (int s = 0; s < ns; ++s) {
+    io[s].m = m_ext + (size_t)s * 3 * plane;
+    io[s].mplane = plane;
+    io[s].src = src + (size_t)s * 3 * g.nt;
+  }
+  std::vector<Plan2D> plans;
+  for (int k = 0; k < ns; ++k) plans.push_back(plan2d(g, shots[k], EFWI_WS_GRADIENT));
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  rc = check_ws(w, ws_bytes, std::max(wave_bytes(plans, 0, 1),
+                                     align_up((size_t)inverse_diag_partials(plane) * sizeof(float))));
+  if (rc != EFWI_OK) return rc;
+  std::vector<std::pair<int, int>> waves;
+  rc = plan_waves(plans, ws_bytes, waves);
+  if (rc != EFWI_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemsetAsync(h, 0, (size_t)plane * sizeof(float), st));
+  for (auto [first, count] : waves) {
+    Wave wv;
+    rc = setup_wave(g, shots, plans, first, count, io, EFWI_WS_GRADIENT, w, wv, st);
+    if (rc != EFWI_OK) return rc;
+    for (int k = 0; k < count; ++k)
+      HIP_TRY(hipMemsetAsync(w + wv.regions[k] + wv.plans[k].off_acc, 0, (size_t)wv.plans[k].cells * sizeof(float),
+                             st));
+    for (int n = 0; n < g.nt; ++n) HIP_TRY(TIMED(KK_ACORR, st, launch_fwd_acorr(wv.batch, n, st)));
+    for (int k = 0; k < count; ++k) {  // one launch per shot: overlapping windows add in shot order
+      const Plan2D& pl = wv.plans[k];
+      HIP_TRY(launch_add_window(reinterpret_cast<const float*>(w + wv.regions[k] + pl.off_acc), pl.cp, pl.nz, pl.nx,
+                                h, g.nx, pl.w.z0, pl.w.x0, st));
+    }
+  }
+  HIP_TRY(launch_inverse_diag(h, plane, clip, p, reinterpret_cast<float*>(w), st));
   return EFWI_OK;
 }
 

@@ -203,6 +203,14 @@ hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy
                       float* b, unsigned char* sink, hipStream_t st);
 hipError_t launch_final_model(int ns, long npts, const float* m_ext, const float* b, const unsigned char* sink,
                               float* m_out, hipStream_t st);
+// Approximate inverse pseudo-Hessian (precondition.hip): the forward step with the velocity
+// autocorrelation into acc[0], the window sum into the full grid, the clipped inverse
+// (partial: inverse_diag_partials(n) floats of scratch).
+hipError_t launch_fwd_acorr(const Batch2D& b, int n, hipStream_t st);
+hipError_t launch_add_window(const float* acc, int cp, int nz, int nx, float* h, long mld, int z0, int x0,
+                             hipStream_t st);
+int inverse_diag_partials(long n);
+hipError_t launch_inverse_diag(const float* h, long n, float clip, float* p, float* partial, hipStream_t st);
 
 // ---------------------------------------------------------------------------------------
 // 3D. Arrays are [nz][ny][nx]; padded arrays have the same zero halo in z and y as in 2D

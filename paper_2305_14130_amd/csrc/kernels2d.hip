@@ -392,7 +392,9 @@ __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int
   }
 }
 
-template <int TZ, bool STORE, bool RECORD, bool PML, bool EDGE>
+// ACORR: also add vx^2 + vz^2 of the new velocities at the owned nodes into acc[0] (the
+// zero-lag autocorrelation of the particle velocity, for the approximate pseudo-Hessian).
+template <int TZ, bool STORE, bool RECORD, bool PML, bool EDGE, bool ACORR>
 __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, int n, gfloat* seg, float* lds) {
   using T = StepTile<TZ>;
   constexpr int SR = T::SR, SC = T::SC, VR = T::VR, VC = T::VC, NS = T::NS;
@@ -489,6 +491,10 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
     vel_node<STORE, PML, EDGE>(p, s, gi, gj, owned, LL, d1, d2, d3, d4, vxn, vzn);
     VXL[vr * VC + lcol] = vxn;
     VZL[vr * VC + lcol] = vzn;
+    if (ACORR && owned) {
+      const unsigned c = (unsigned)(gi * s.cp + gj);
+      s.acc[c] += vxn * vxn + vzn * vzn;
+    }
   };
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -524,7 +530,7 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
 // Workgroup w takes schedule slot w: its tile and code path come in one scalar load (the
 // host classified the tile), so a workgroup starts its tile's loads after two dependent
 // scalar round trips (the slot, then the shot's descriptor).
-template <int TZ, bool STORE, bool RECORD>
+template <int TZ, bool STORE, bool RECORD, bool ACORR = false>
 __global__ __launch_bounds__(BX * BZ) void k_fwd_step(STEP_PARAMS, int n, int kstore) {
   __shared__ float lds[StepTile<TZ>::LDS_FLOATS];
   const StepSlot slot = slots[blockIdx.x];
@@ -535,9 +541,9 @@ __global__ __launch_bounds__(BX * BZ) void k_fwd_step(STEP_PARAMS, int n, int ks
   // block-uniform branch: every thread reaches the barriers. CPML tiles: within 2 nodes of
   // a strip (velocity halo); edge tiles (grids whose strips are under 2 nodes wide): the
   // staged halo may leave the grid; every other tile's staged halo lies inside it.
-  if (slot.path == PATH_PML) fwd_step_tile<TZ, STORE, RECORD, true, true>(s, i0, j0, n, seg, lds);
-  else if (slot.path == PATH_EDGE) fwd_step_tile<TZ, STORE, RECORD, false, true>(s, i0, j0, n, seg, lds);
-  else fwd_step_tile<TZ, STORE, RECORD, false, false>(s, i0, j0, n, seg, lds);
+  if (slot.path == PATH_PML) fwd_step_tile<TZ, STORE, RECORD, true, true, ACORR>(s, i0, j0, n, seg, lds);
+  else if (slot.path == PATH_EDGE) fwd_step_tile<TZ, STORE, RECORD, false, true, ACORR>(s, i0, j0, n, seg, lds);
+  else fwd_step_tile<TZ, STORE, RECORD, false, false, ACORR>(s, i0, j0, n, seg, lds);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1200,6 +1206,17 @@ hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hip
     case 8: fwd_step_launch<8>(b, n, kstore, record, st); break;
     case 12: fwd_step_launch<12>(b, n, kstore, record, st); break;
     case 16: fwd_step_launch<16>(b, n, kstore, record, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_acorr(const Batch2D& b, int n, hipStream_t st) {
+  const dim3 g(b.step.n);
+  switch (b.fwd_rows) {
+    case 8: k_fwd_step<8, false, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
+    case 12: k_fwd_step<12, false, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
+    case 16: k_fwd_step<16, false, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

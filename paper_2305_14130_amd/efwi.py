@@ -31,7 +31,8 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_status_string", "efwi_last_error", "efwi_version", "efwi_timing_enable",
             "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name",
             "efwi_plan_interval", "efwi_set_tile_rows", "efwi_get_tile_rows", "efwi_autotune_workspace_size",
-            "efwi_autotune", "efwi_batch_waves", "efwi_zoi_weights", "efwi_final_model"]
+            "efwi_autotune", "efwi_batch_waves", "efwi_zoi_weights", "efwi_final_model",
+            "efwi_pseudo_hessian"]
 
 
 class Grid(ctypes.Structure):
@@ -392,6 +393,9 @@ class Zone(ctypes.Structure):
 _lib.efwi_zoi_weights.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(Zone), ctypes.c_float,
                                   ctypes.c_float, _vp, _vp, _vp]
 _lib.efwi_final_model.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+_lib.efwi_pseudo_hessian.restype = ctypes.c_int
+_lib.efwi_pseudo_hessian.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), _vp, _vp,
+                                     ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t, _vp]
 
 
 def make_zone(src, icov, box, taper) -> Zone:
@@ -427,6 +431,25 @@ def final_model(grid: Grid, m_ext, b, sink, m_out=None, stream=None):
     _check(_lib.efwi_final_model(ctypes.byref(grid), m_ext.shape[0], _ptr(m_ext), _ptr(b), _ptr(sink), _ptr(m_out),
                                  _stream(stream)))
     return m_out
+
+
+def pseudo_hessian(grid: Grid, shots, m_ext, src, clip, h=None, p=None, ws=None, stream=None):
+    """Approximate inverse pseudo-Hessian (efwi_pseudo_hessian): returns (h, p), the summed
+    velocity autocorrelation and the clipped, scaled inverse, [nz][nx] FP32 each."""
+    shots = list(shots)
+    _f32(m_ext, "m_ext"), _f32(src, "src")
+    shape = (grid.nz, grid.nx)
+    h = h if h is not None else torch.empty(shape, dtype=torch.float32, device=m_ext.device)
+    p = p if p is not None else torch.empty(shape, dtype=torch.float32, device=m_ext.device)
+    _f32(h, "h"), _f32(p, "p")
+    arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
+    need = _lib.efwi_workspace_size(WS_BATCH, ctypes.byref(grid), len(shots), arr)
+    if need == 0:
+        _check(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr))
+    ws = ws if ws is not None else workspace(need, m_ext.device)
+    _check(_lib.efwi_pseudo_hessian(ctypes.byref(grid), len(shots), arr, _ptr(m_ext), _ptr(src), float(clip), _ptr(h),
+                                    _ptr(p), _ptr(ws), ws.numel(), _stream(stream)))
+    return h, p
 
 
 def source_components(M, stf) -> np.ndarray:

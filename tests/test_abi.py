@@ -174,3 +174,24 @@ def test_final_model_argument_errors(efwi):
     fake = ctypes.c_void_p(256)
     assert efwi._lib.efwi_final_model(ctypes.byref(grid), 0, fake, fake, fake, fake, None) == efwi.E_INVAL
     assert efwi._lib.efwi_final_model(ctypes.byref(grid), 2, fake, None, fake, fake, None) == efwi.E_INVAL
+
+
+@pytest.mark.parametrize("case", ["3d", "ns0", "clip0", "clip_big", "clip_nan", "null", "small_ws"])
+def test_pseudo_hessian_argument_errors(efwi, case):
+    """efwi_pseudo_hessian rejects bad arguments on the host before any launch (the device
+    pointers below are never used)."""
+    if case == "3d":
+        grid = efwi.make_grid3d(40, 40, 40, 5.0, 5.0, 5.0, 0.5e-3, 50, 8, 1e-3, 30.0, 4500.0)
+        shot = efwi.Shot(20, 20, [21], [25], src_iy=20, ch_iy=[20])
+    else:
+        grid = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+        shot = efwi.Shot(50, 100, [51, 51], [80, 120])
+    arr = (efwi._ShotC * 1)(shot.c_struct())
+    fake = ctypes.c_void_p(256)
+    ns = 0 if case == "ns0" else 1
+    clip = {"clip0": 0.0, "clip_big": 1.5, "clip_nan": float("nan")}.get(case, 0.01)
+    h = None if case == "null" else fake
+    ws_bytes = 64 if case == "small_ws" else 1 << 40
+    rc = efwi._lib.efwi_pseudo_hessian(ctypes.byref(grid), ns, arr, fake, fake, clip, h, fake, fake, ws_bytes, None)
+    assert rc == (efwi.E_WORKSPACE if case == "small_ws" else efwi.E_INVAL)
+    assert efwi._lib.efwi_last_error()
