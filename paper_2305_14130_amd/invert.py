@@ -13,6 +13,10 @@
   as in the paper's synthetic), one copy per source in the extended case.
 * ``final_model``: the physical model S_w W m~ of eq.(9) (efwi.final_model).
 * ``cosine_similarity``: eq.(14).
+* The two alternatives the paper compares with: conventional FWI with a near-offset mute and
+  an approximate inverse pseudo-Hessian as l-BFGS's initial inverse Hessian
+  (``lbfgs(h0=...)``, efwi.pseudo_hessian), and conventional FWI whose per-shot gradients
+  are mapped by S_w W before the solver sees them, eq.(15) (``PreconditionedFWI``).
 
 Only the optimizer's vector algebra (dot products, axpy on flat device tensors) runs in
 PyTorch; every wave propagation, gradient, regularizer and extension operator is the HIP
@@ -113,10 +117,12 @@ def wolfe_search(fg, x, f0, g0, d, alpha, c1=1e-4, c2=0.9, max_evals=20, record=
     return None
 
 
-def lbfgs(fg, x0, max_iter=100, rate_tol=1e-3, memory=10, first_step=None, callback=None):
+def lbfgs(fg, x0, max_iter=100, rate_tol=1e-3, memory=10, first_step=None, callback=None, h0=None):
     """Minimize f with l-BFGS; fg(x) -> (f: float, g: tensor like x). first_step: the
     largest |change| of x the first line search starts from (the later ones start from the
-    unit quasi-Newton step). Returns (x, Record)."""
+    unit quasi-Newton step). h0: an optional positive diagonal D (tensor like x) for the
+    initial inverse Hessian, used as gamma_k D with gamma_k = s^T y / (y^T D y) of the latest
+    pair (D alone before the first pair); None is the identity. Returns (x, Record)."""
     rec = Record()
     x = x0.clone()
     f, g = fg(x)
@@ -131,7 +137,12 @@ def lbfgs(fg, x0, max_iter=100, rate_tol=1e-3, memory=10, first_step=None, callb
             a = r * _dot(s, q)
             alphas.append(a)
             q -= a * y
-        if S:
+        if h0 is not None:
+            if S:
+                q *= h0 * (_dot(S[-1], Y[-1]) / _dot(Y[-1], h0 * Y[-1]))
+            else:
+                q *= h0
+        elif S:
             q *= _dot(S[-1], Y[-1]) / _dot(Y[-1], Y[-1])
         for (s, y, r), a in zip(zip(S, Y, R), reversed(alphas)):
             b = r * _dot(y, q)
@@ -241,15 +252,46 @@ class ConventionalFWI(_Problem):
         return self.model(x)
 
 
+class PreconditionedFWI(ConventionalFWI):
+    """Conventional misfit, but the solver receives the heuristic gradient of eq.(15): the
+    per-shot gradients g_s (each shot on the common model) stacked as an extended vector and
+    mapped by S_w W (efwi.final_model with the zones' weights and sinkholes) instead of
+    summed. The objective is unchanged, so the direction need not descend."""
+
+    def __init__(self, w, d_obs, b, sink, device=None):
+        super().__init__(w, d_obs, device)
+        self.b, self.sink = b, sink
+
+    def __call__(self, x):
+        m = self.model(x)
+        g, phi = self._data(m.unsqueeze(0).repeat(self.ns, 1, 1, 1).contiguous())
+        self.data_phi = phi
+        gbar = efwi.final_model(self.grid, g, self.b, self.sink)
+        return phi, (gbar[:2] * self.m0[:2]).contiguous()
+
+
+def inverse_pseudo_hessian(prob, clip):
+    """The diagonal initial inverse Hessian of the mute + pseudo-Hessian method for a
+    conventional problem over x [2][nz][nx]: efwi.pseudo_hessian at the starting model with
+    the inverting side's sources, the same weight for Vp and Vs."""
+    m_ext = prob.m0.unsqueeze(0).repeat(prob.ns, 1, 1, 1).contiguous()
+    _, p = efwi.pseudo_hessian(prob.grid, prob.shots, m_ext, prob.src, clip, ws=prob.ws)
+    return p.unsqueeze(0).repeat(2, 1, 1).contiguous()
+
+
 def synthetic_comparison(source_errors=False, eta_rel=1.0, max_iter=60, rate_tol=1e-3, nt=1600, mute_m=100.0,
-                         device=None, log=None):
+                         device=None, log=None, methods=("conventional", "extended"), ph_mute_m=200.0,
+                         ph_clip=0.01):
     """Conventional and extended FWI on the guided-wave synthetic (inputs.guided_wave_synthetic):
     noise-free data from the true model and the true sources, inverted with the exact or the
     perturbed source parameters; returns the iterations, stop reasons and the cosine
     similarity (eq.(14)) of the inverted Vp and Vs perturbations with the true ones, over the
     model without its absorbing strips. eta^2 = eta_rel * Phi_data(start) / ||0.01 m_start||^2
     summed over the components (Vp, Vs), i.e. a uniform 1% inconsistency costs eta_rel times
-    the starting data misfit."""
+    the starting data misfit. ``methods`` may also name the paper's two alternatives:
+    "mute_pseudo_hessian" (channels within ph_mute_m of a source dropped, the approximate
+    inverse pseudo-Hessian with clip fraction ph_clip as the initial inverse Hessian) and
+    "gradient_preconditioning" (eq.(15) with the extended FWI's zones)."""
     from . import inputs
     dev = device if device is not None else torch.device("cuda")
     w_true = inputs.guided_wave_synthetic(nt=nt, mute_m=mute_m)
@@ -272,9 +314,21 @@ def synthetic_comparison(source_errors=False, eta_rel=1.0, max_iter=60, rate_tol
     phi0, _ = conv(conv.x0())
     m_sc = conv.m0[:2].double()
     eta = float(np.sqrt(eta_rel * phi0 / float(conv.ns * torch.sum((0.01 * m_sc) ** 2))))
-    ext = ExtendedFWI(w, d_obs, b, sink, eta, dev)
-    for name, prob in (("conventional", conv), ("extended", ext)):
-        x, rec = lbfgs(prob, prob.x0(), max_iter=max_iter, rate_tol=rate_tol, first_step=0.01)
+    problems = {"conventional": lambda: (conv, None), "extended": lambda: (ExtendedFWI(w, d_obs, b, sink, eta, dev), None),
+                "gradient_preconditioning": lambda: (PreconditionedFWI(w, d_obs, b, sink, dev), None)}
+
+    def muted():
+        wt = inputs.guided_wave_synthetic(nt=nt, mute_m=ph_mute_m)
+        wm = inputs.with_source_errors(wt) if source_errors else wt
+        dm = torch.cat([efwi.model_forward(grid, efwi.Shot(s.src_iz, s.src_ix, s.ch_iz, s.ch_ix), m_true,
+                                           T(np.outer(s.M, wt.stf))) for s in wt.shots])
+        prob = ConventionalFWI(wm, dm, dev)
+        return prob, inverse_pseudo_hessian(prob, ph_clip)
+
+    problems["mute_pseudo_hessian"] = muted
+    for name in methods:
+        prob, h0 = problems[name]()
+        x, rec = lbfgs(prob, prob.x0(), max_iter=max_iter, rate_tol=rate_tol, first_step=0.01, h0=h0)
         m = prob.final(x).cpu().numpy().astype(np.float64)
         pert = (m[:2] - w.m_start[:2]) / w.m_start[:2]
         out[name] = {"iterations": len(rec.rate), "evaluations": rec.evaluations, "stop": rec.stop,

@@ -54,3 +54,27 @@ def test_a_few_iterations_decrease_both(setup):
         assert rec.phi[-1] < 0.9 * rec.phi[0]
         m = prob.final(x)
         assert m.shape == (3, w.nz, w.nx) and bool(torch.isfinite(m).all())
+
+
+def test_alternative_methods_match_library(setup):
+    """eq.(15): the preconditioned problem keeps the conventional objective and hands the
+    solver S_w W of the per-shot gradients; the mute + pseudo-Hessian start is the library's
+    operator at the starting model."""
+    w, grid, d_obs, b, sink = setup
+    rng = np.random.default_rng(2)
+    x = torch.tensor(0.01 * rng.standard_normal((2, w.nz, w.nx)), dtype=torch.float32, device="cuda")
+    pre = invert.PreconditionedFWI(w, d_obs, b, sink)
+    phi, gx = pre(x)
+    conv = invert.ConventionalFWI(w, d_obs)
+    assert phi == conv(x)[0]
+    m = pre.model(x)
+    g, _ = efwi.batch_gradient(pre.grid, pre.shots, m.unsqueeze(0).repeat(pre.ns, 1, 1, 1).contiguous(), pre.src,
+                               d_obs)
+    assert torch.equal(gx, (efwi.final_model(pre.grid, g, b, sink)[:2] * pre.m0[:2]).contiguous())
+    h0 = invert.inverse_pseudo_hessian(conv, 0.01)
+    _, p = efwi.pseudo_hessian(conv.grid, conv.shots, conv.m0.unsqueeze(0).repeat(conv.ns, 1, 1, 1).contiguous(),
+                               conv.src, 0.01)
+    assert h0.shape == (2, w.nz, w.nx) and torch.equal(h0[0], p) and torch.equal(h0[1], p)
+    assert float(p.min()) == pytest.approx(0.01, rel=1e-6) and float(p.max()) == 1.0
+    x1, rec = invert.lbfgs(conv, conv.x0(), max_iter=3, rate_tol=0.0, first_step=0.01, h0=h0)
+    assert rec.phi[-1] < 0.95 * rec.phi[0]
