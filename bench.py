@@ -27,10 +27,11 @@ resident in HBM before the timed region. The JSON line also carries:
 * path: the whole step's algorithmic bytes (168 B per cell-step plus 52 B per recomputed
   cell-step) over the step time; each checkpointed form carries the same as path_frac.
 * forms.precision_3d_sample: one shot of the 3D precision workload (300 x 400 x 400) for
-  200 of its 3000 steps with sqrt(nt) FP16 checkpoints, timed once.
+  200 of its 3000 steps with sqrt(nt) FP16 checkpoints, timed once, with its path_frac.
 * extension_ops: the zones of influence (eq.(10)) of the 20 sources and the final model
-  S_w W m~ (eq.(9)) on the full grid (once per inversion, not part of the step), each with
-  its time and compulsory-bytes rate.
+  S_w W m~ (eq.(9)) on the full grid (once per inversion, not part of the step), and the
+  approximate inverse pseudo-Hessian of the comparison methods (one shot, 200 steps), each
+  with its time and compulsory-bytes rate.
 """
 from __future__ import annotations
 
@@ -173,11 +174,15 @@ def uneven_batched_form(efwi, inputs, torch, dev, grid, nt, log):
     return out
 
 
-def extension_ops(efwi, torch, grid, w, m_ext, dev):
+def extension_ops(efwi, torch, grid, w, m_ext, src, dev, ph_steps=200):
     """The sources' zones of influence (eq.(10)) and the final model S_w W m~ (eq.(9)) on the
     full grid for the bench's shots, each timed with events on the current stream (median of
     5 calls), with their compulsory bytes (zones: write b and the sinkhole flag, 5 B per
-    point and source; final model: read m~, b and the flags of every source, write m)."""
+    point and source; final model: read m~, b and the flags of every source, write m).
+    Also the approximate inverse pseudo-Hessian of the comparison methods for one shot over
+    ph_steps time steps (median of 3 calls): per step the forward state (read and write 5
+    fields), the 3 staged parameters and the autocorrelation sum (read and write) are
+    compulsory, 60 B per cell; the window sum and the inverse add 12 B per cell once."""
     ns, nz, nx = m_ext.shape[0], w.nz, w.nx
     zones = []
     for s in w.shots:
@@ -203,19 +208,42 @@ def extension_ops(efwi, torch, grid, w, m_ext, dev):
     zms = med_ms(lambda: efwi.zoi_weights(grid, zones, 2.0, 0.9, b=b, sink=sink))
     fms = med_ms(lambda: efwi.final_model(grid, m_ext, b, sink, m_out=m_out))
     zbytes, fbytes = 5 * nz * nx * ns, (17 * ns + 12) * nz * nx
+    ph_grid = efwi.make_grid(nz, nx, w.dz, w.dx, w.dt, ph_steps, w.npml, w.pml_R, w.f0, w.vp_max)
+    s0 = w.shots[0]
+    ph_shot = [efwi.Shot(s0.src_iz, s0.src_ix, s0.ch_iz, s0.ch_ix)]
+    ph_ws = efwi.workspace(efwi.workspace_size(efwi.WS_GRADIENT, ph_grid, ph_shot), dev)
+    h = torch.empty((nz, nx), dtype=torch.float32, device=dev)
+    pinv = torch.empty((nz, nx), dtype=torch.float32, device=dev)
+    ph_src = src[:1, :, :ph_steps].contiguous()
+    ph_times = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        efwi.pseudo_hessian(ph_grid, ph_shot, m_ext[:1], ph_src, 0.01, h=h, p=pinv, ws=ph_ws)
+        e1.record()
+        e1.synchronize()
+        ph_times.append(e0.elapsed_time(e1))
+    pms = sorted(ph_times)[1]
+    pbytes = (60 * ph_steps + 12) * nz * nx
     out = {"zoi_weights": {"sources": ns, "ms": round(zms, 3), "bytes": zbytes,
                            "GBs": round(zbytes / zms / 1e6, 1), "frac": round(zbytes / zms / 1e6 / HBM_PEAK_GBS, 4),
                            "sink_points": int(sink.sum().item())},
            "final_model": {"components": ns, "ms": round(fms, 3), "bytes": fbytes,
-                           "GBs": round(fbytes / fms / 1e6, 1), "frac": round(fbytes / fms / 1e6 / HBM_PEAK_GBS, 4)}}
-    del b, sink, m_out
+                           "GBs": round(fbytes / fms / 1e6, 1), "frac": round(fbytes / fms / 1e6 / HBM_PEAK_GBS, 4)},
+           "pseudo_hessian": {"shots": 1, "steps": ph_steps, "ms": round(pms, 3), "bytes": pbytes,
+                              "gcell_per_s": round(nz * nx * ph_steps / pms / 1e6, 2),
+                              "GBs": round(pbytes / pms / 1e6, 1), "frac": round(pbytes / pms / 1e6 / HBM_PEAK_GBS, 4)}}
+    del b, sink, m_out, h, pinv, ph_ws
     return out
 
 
 def precision_3d_sample(efwi, inputs, torch, dev, nt=200):
     """One shot of the 3D precision workload on its full 300 x 400 x 400 grid (5 m, CPML 20,
     2000 DAS channels on two wells, six-component moment tensor), nt steps of the 3000 with
-    sqrt(nt) FP16 checkpoints, d_obs = 0; timed once after one untimed call."""
+    sqrt(nt) FP16 checkpoints, d_obs = 0; timed once after one untimed call. path_frac: the
+    algorithmic bytes per cell-step without the CPML memory variables (forward 140 B:
+    velocity 60, stress 80; recomputed step with the history 176 B; transposed step with the
+    imaging sums 240 B: velocity 124, stress 116) over the time, against 8 TB/s."""
     w = inputs.precision_3d(nt=nt, nshots=1, anomalies=False)
     s = w.shots[0]
     grid = efwi.make_grid3d(w.nz, w.ny, w.nx, w.h, w.h, w.h, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)
@@ -231,10 +259,14 @@ def precision_3d_sample(efwi, inputs, torch, dev, nt=200):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     cells = w.nz * w.ny * w.nx
+    rf = efwi.recompute_fraction(grid, 0)
+    bpc = 140.0 + 176.0 * rf + 240.0
+    gbs = bpc * cells * nt / dt / 1e9
     out = {"grid": [w.nz, w.ny, w.nx], "nt": nt, "checkpoints": "sqrt(nt), FP16",
-           "recompute_fraction": round(efwi.recompute_fraction(grid, 0), 4),
+           "recompute_fraction": round(rf, 4),
            "ms": round(dt * 1e3, 1), "gcell_per_s": round(cells * nt / dt / 1e9, 3),
-           "finite": bool(torch.isfinite(g).all())}
+           "bytes_per_cell_step": round(bpc, 1), "path_GBs": round(gbs, 1),
+           "path_frac": round(gbs / HBM_PEAK_GBS, 4), "finite": bool(torch.isfinite(g).all())}
     del ws, m, g
     torch.cuda.empty_cache()
     return out
@@ -424,7 +456,7 @@ def main():  # noqa: C901
 
     ext_ops = None
     if not args.no_extension_ops:
-        ext_ops = extension_ops(efwi, torch, grid, w, m_ext, dev)
+        ext_ops = extension_ops(efwi, torch, grid, w, m_ext, src, dev)
         log(f"extension operators done: {ext_ops}")
 
     if not args.no_uneven:
