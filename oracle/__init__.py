@@ -14,6 +14,8 @@ Modules
                 and S^T, written as dense per-point matrices.
 ``checkpoint``  the 16-bit checkpoint encodings (per-snapshot max-abs scaling).
 ``zoi``         the sources' zones of influence, eq.(10): weights b_s and sinkhole flags.
+``receiver``    the field-like DAS sampling K_r of eq.(3): gauge-length mean, strain rate,
+                resampling, its transpose and the per-shot gradient through it.
 ``precondition`` the comparison methods: approximate inverse pseudo-Hessian (velocity
                 autocorrelation summed over shots, clipped, scaled), near-offset mute; the
                 gradient preconditioning of eq.(15) is ``regularizer.final_model``.
