@@ -77,6 +77,17 @@ typedef struct {
   int ckpt_interval;          /* time steps per checkpoint segment; 0 = ceil(sqrt(nt));
                                  >= nt = keep the whole forward history (no recompute)   */
   int ckpt_mode;              /* EFWI_CKPT_*                                             */
+  /* DAS sampling K_r of eq.(3). The kernels record the x-x strain e_c(t_{n+1}) at every
+   * channel's normal node; with the defaults (0 or 1, 1, 0) that point strain [nch][nt] is
+   * the shot's data. Otherwise the data are field-like, [nch - gauge + 1][nt / decim]:
+   * field channel f is the mean over the gauge of channels f .. f + gauge - 1 (consecutive
+   * in the list, i.e. along the fiber), as strain rate (e(t_{n+1}) - e(t_n)) / dt with
+   * e(t_0) = 0 when rate = 1, sampled at t_{n+1} = k decim dt, k = 1, 2, ... Every entry
+   * point then reads and writes data in that shape (d, d_obs, r, v, d_out) and the misfit
+   * and gradients are those of the field data.                                         */
+  int gauge;                  /* channels per gauge length (0 or 1: point strain)        */
+  int decim;                  /* resampling factor in time steps (0 or 1: every step)    */
+  int rate;                   /* 1: strain rate, 0: strain                               */
 } efwi_shot;
 
 /* Which entry point a workspace is sized for. */
@@ -214,6 +225,13 @@ efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zone
  * FP64 arithmetic, one launch on `stream`. */
 efwi_status efwi_final_model(const efwi_grid* grid, int ns, const float* m_ext, const float* b,
                              const unsigned char* sink, float* m_out, void* stream);
+
+/* das_field: the field data K e of a shot (see efwi_shot's DAS sampling) from recorded point
+ * strains, e.g. of a shot with the default sampling.
+ *   e   DEVICE [nch][nt] point strains (x-x strain at each channel at t_{n+1});
+ *   out DEVICE [nch - gauge + 1][nt / decim] output.
+ * FP64 arithmetic, one launch on `stream`. EFWI_E_INVAL for an invalid grid or shot. */
+efwi_status efwi_das_field(const efwi_grid* grid, const efwi_shot* shot, const float* e, float* out, void* stream);
 
 /* pseudo_hessian: the approximate inverse pseudo-Hessian that the paper gives l-BFGS as
  * its initial inverse Hessian in the comparison with alternative methods (synthetic

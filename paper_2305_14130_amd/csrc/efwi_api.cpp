@@ -266,6 +266,24 @@ efwi_status validate_grid(const efwi_grid* g) {
   return EFWI_OK;
 }
 
+// The shot's DAS sampling (0 in gauge or decim means 1).
+Receiver receiver_of(const efwi_grid& g, const efwi_shot& s) {
+  Receiver R{};
+  R.nch = s.nch;
+  R.nt = g.nt;
+  R.gauge = s.gauge > 0 ? s.gauge : 1;
+  R.decim = s.decim > 0 ? s.decim : 1;
+  R.rate = s.rate;
+  R.rdt = (float)(1.0 / (double)g.dt);
+  return R;
+}
+
+// Data rows and samples of a shot as the caller sees them (field shape).
+size_t data_floats(const efwi_grid& g, const efwi_shot& s) {
+  const Receiver R = receiver_of(g, s);
+  return s.nch > 0 ? (size_t)std::max(0, R.nf()) * R.ntf() : 0;
+}
+
 efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
   if (!s) return fail(EFWI_E_INVAL, "shot %d descriptor is NULL", index);
   const bool three = g.ndim == 3;
@@ -295,6 +313,11 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
   if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
     return fail(EFWI_E_INVAL, "shot %d: two channels share one grid node", index);
   if (s->ckpt_interval < 0) return fail(EFWI_E_INVAL, "shot %d: ckpt_interval < 0", index);
+  if (s->gauge < 0 || s->decim < 0 || (s->rate != 0 && s->rate != 1))
+    return fail(EFWI_E_INVAL, "shot %d: gauge and decim must be >= 0 and rate 0 or 1", index);
+  if (s->nch > 0 && s->gauge > s->nch)
+    return fail(EFWI_E_INVAL, "shot %d: gauge of %d channels exceeds its %d channels", index, s->gauge, s->nch);
+  if (s->decim > g.nt) return fail(EFWI_E_INVAL, "shot %d: decim %d exceeds nt", index, s->decim);
   if (s->ckpt_mode != EFWI_CKPT_FP32 && s->ckpt_mode != EFWI_CKPT_BF16 && s->ckpt_mode != EFWI_CKPT_FP16)
     return fail(EFWI_E_INVAL, "shot %d: unknown ckpt_mode %d", index, s->ckpt_mode);
   return EFWI_OK;
@@ -319,8 +342,10 @@ struct Plan2D {
   CkptFields fields;
   size_t tab_bytes;    // CPML profiles + channel maps (kept in the batch header)
   size_t off_state, off_e, off_adj, off_par, off_ebar, off_partial, off_dint, off_acc, off_G, off_seg, off_ckpt,
-      off_maxbits, total;
+      off_maxbits, off_rf, total;
   size_t adj_bytes, par_bytes;
+  Receiver R;
+  bool field;          // the DAS sampling is not the identity
 };
 
 size_t strips_floats(int nz, int nx, int P) { return (size_t)4 * nz * 2 * P + (size_t)4 * 2 * P * nx; }
@@ -400,7 +425,10 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind, int fwd
   p.off_adj = adj ? take(p.adj_bytes) : 0;
   p.off_ebar = adj ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
   p.off_partial = grad ? take((size_t)std::max(1, p.nch) * sizeof(double)) : 0;
-  p.off_dint = grad ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
+  p.R = receiver_of(g, s);
+  p.field = !p.R.identity();
+  p.off_dint = (grad || (fwd && p.field)) ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
+  p.off_rf = (grad && p.field) ? take(std::max<size_t>(1, data_floats(g, s)) * sizeof(float)) : 0;
   p.off_acc = grad ? take((size_t)NACC * p.cells * sizeof(float)) : 0;
   p.off_G = grad ? take((size_t)3 * p.cells * sizeof(double)) : 0;
   p.off_seg = grad ? take((size_t)p.L * NSEG_FIELDS * p.cells * sizeof(float)) : 0;
@@ -525,7 +553,9 @@ Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsign
   d.mld = mld;
   d.src = (const gfloat*)(io.src);
   d.src_bar = (gfloat*)(io.src_bar);
-  d.d = (gfloat*)(io.d ? io.d : reinterpret_cast<float*>(region + p.off_dint));
+  // with a field sampling the kernels record the point strains internally and the field
+  // data are formed from them afterwards
+  d.d = (gfloat*)((io.d && !p.field) ? io.d : reinterpret_cast<float*>(region + p.off_dint));
   d.gout = (gfloat*)(io.gout);
   d.mplane = io.mplane;
   d.z0 = p.w.z0;
@@ -834,6 +864,21 @@ efwi_status plan_waves(const std::vector<Plan2D>& plans, size_t ws_bytes, std::v
 efwi_status gradient_waves3(const efwi_grid& g, const efwi_shot* shots, int ns, const std::vector<ShotIO>& io,
                             unsigned char* ws, size_t ws_bytes, hipStream_t st);
 
+// Misfit stage of a shot with a field sampling: the field data out of the recorded point
+// strains when asked for, then e_bar from the given field-space vector (J^T v) or from the
+// field residual K d - d_obs (with the misfit).
+hipError_t field_misfit(const Receiver& R, unsigned char* region, size_t off_dint, size_t off_rf, size_t off_partial,
+                        const ShotIO& io, float* ebar, hipStream_t st) {
+  const float* e = reinterpret_cast<const float*>(region + off_dint);
+  if (io.d) {
+    const hipError_t rc = launch_field_data(R, e, io.d, st);
+    if (rc != hipSuccess) return rc;
+  }
+  if (io.r) return launch_field_cumsum(R, io.r, ebar, st);
+  return launch_field_misfit(R, e, io.dobs, reinterpret_cast<float*>(region + off_rf),
+                             reinterpret_cast<double*>(region + off_partial), io.phi, ebar, st);
+}
+
 efwi_status gradient_waves(const efwi_grid& g, const efwi_shot* shots, int ns, const std::vector<ShotIO>& io,
                            unsigned char* ws, size_t ws_bytes, hipStream_t st) {
   if (g.ndim == 3) return gradient_waves3(g, shots, ns, io, ws, ws_bytes, st);
@@ -855,12 +900,15 @@ efwi_status gradient_waves(const efwi_grid& g, const efwi_shot* shots, int ns, c
       unsigned char* r = ws + wv.regions[k];
       const Plan2D& p = wv.plans[k];
       float* ebar = reinterpret_cast<float*>(r + p.off_ebar);
-      if (io[first + k].r)  // J^T v: the data-space vector drives the adjoint directly
+      if (p.field) {
+        HIP_TRY(TIMED(KK_MISFIT, st, field_misfit(p.R, r, p.off_dint, p.off_rf, p.off_partial, io[first + k], ebar, st)));
+      } else if (io[first + k].r) {  // J^T v: the data-space vector drives the adjoint directly
         HIP_TRY(TIMED(KK_MISFIT, st, launch_residual_cumsum(d, io[first + k].r, ebar, st)));
-      else
+      } else {
         HIP_TRY(TIMED(KK_MISFIT, st,
                       launch_misfit(d, (const float*)(d.d), io[first + k].dobs,
                                     reinterpret_cast<double*>(r + p.off_partial), io[first + k].phi, ebar, st)));
+      }
     }
     rc = run_reverse(wv, ws, st);
     if (rc != EFWI_OK) return rc;
@@ -893,7 +941,9 @@ struct Plan3D {
   int ckpt_mode;
   CkptFields fields;
   size_t off_par, off_state, off_e, off_adj, off_ebar, off_partial, off_dint, off_acc, off_G, off_seg, off_ckpt,
-      off_maxbits, total;
+      off_maxbits, off_rf, total;
+  Receiver R;
+  bool field;
 };
 
 int count_rows3(const efwi_shot& s, const Window& w) {
@@ -960,7 +1010,10 @@ Plan3D plan3d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.off_adj = adj ? take(p.adj_bytes) : 0;
   p.off_ebar = adj ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
   p.off_partial = grad ? take((size_t)std::max(1, p.nch) * sizeof(double)) : 0;
-  p.off_dint = grad ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
+  p.R = receiver_of(g, s);
+  p.field = !p.R.identity();
+  p.off_dint = (grad || (fwd && p.field)) ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
+  p.off_rf = (grad && p.field) ? take(std::max<size_t>(1, data_floats(g, s)) * sizeof(float)) : 0;
   p.off_acc = grad ? take((size_t)NACC3 * p.cells * sizeof(float)) : 0;
   p.off_G = grad ? take((size_t)3 * p.cells * sizeof(double)) : 0;
   p.off_seg = grad ? take((size_t)p.L * NSEG3 * p.cells * sizeof(float)) : 0;
@@ -1046,7 +1099,9 @@ Shot3D make_desc3(const efwi_grid& g, const efwi_shot& s, const Plan3D& p, unsig
   }
   d.src = (const gfloat*)(io.src);
   d.src_bar = (gfloat*)(io.src_bar);
-  d.d = (gfloat*)(io.d ? io.d : reinterpret_cast<float*>(region + p.off_dint));
+  // with a field sampling the kernels record the point strains internally and the field
+  // data are formed from them afterwards
+  d.d = (gfloat*)((io.d && !p.field) ? io.d : reinterpret_cast<float*>(region + p.off_dint));
   d.gout = (gfloat*)(io.gout);
   d.mplane = io.mplane;
   d.z0 = p.w.z0, d.y0 = p.w.y0, d.x0 = p.w.x0;
@@ -1242,7 +1297,9 @@ efwi_status gradient_waves3(const efwi_grid& g, const efwi_shot* shots, int ns, 
       const Plan3D& p = wv.plans[k];
       unsigned char* r = ws + wv.regions[k];
       float* ebar = reinterpret_cast<float*>(r + p.off_ebar);
-      if (io[first + k].r)
+      if (p.field)
+        HIP_TRY(TIMED(KK_MISFIT, st, field_misfit(p.R, r, p.off_dint, p.off_rf, p.off_partial, io[first + k], ebar, st)));
+      else if (io[first + k].r)
         HIP_TRY(TIMED(KK_MISFIT, st, launch_residual_cumsum_raw(p.nch, p.nt, io[first + k].r, ebar, st)));
       else
         HIP_TRY(TIMED(KK_MISFIT, st,
@@ -1494,7 +1551,10 @@ efwi_status efwi_model_forward(const efwi_grid* grid, const efwi_shot* shot, con
     Wave3 wv;
     rc = setup_wave3(*grid, shot, plans, 0, 1, {io}, EFWI_WS_FORWARD, w, wv, st);
     if (rc != EFWI_OK) return rc;
-    return run_forward3(wv, w, false, st);
+    rc = run_forward3(wv, w, false, st);
+    if (rc != EFWI_OK || !plans[0].field) return rc;
+    HIP_TRY(launch_field_data(plans[0].R, reinterpret_cast<const float*>(w + wv.regions[0] + plans[0].off_dint), d, st));
+    return EFWI_OK;
   }
   std::vector<Plan2D> plans{plan2d(*grid, *shot, EFWI_WS_FORWARD)};
   rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
@@ -1502,7 +1562,10 @@ efwi_status efwi_model_forward(const efwi_grid* grid, const efwi_shot* shot, con
   Wave wv;
   rc = setup_wave(*grid, shot, plans, 0, 1, {io}, EFWI_WS_FORWARD, w, wv, st);
   if (rc != EFWI_OK) return rc;
-  return run_forward(wv, w, false, st);
+  rc = run_forward(wv, w, false, st);
+  if (rc != EFWI_OK || !plans[0].field) return rc;
+  HIP_TRY(launch_field_data(plans[0].R, reinterpret_cast<const float*>(w + wv.regions[0] + plans[0].off_dint), d, st));
+  return EFWI_OK;
 }
 
 efwi_status efwi_model_adjoint(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* r,
@@ -1524,7 +1587,9 @@ efwi_status efwi_model_adjoint(const efwi_grid* grid, const efwi_shot* shot, con
     rc = setup_wave3(*grid, shot, plans, 0, 1, {io}, EFWI_WS_ADJOINT, w, wv, st);
     if (rc != EFWI_OK) return rc;
     const Plan3D& p = wv.plans[0];
-    HIP_TRY(launch_residual_cumsum_raw(p.nch, p.nt, r, reinterpret_cast<float*>(w + wv.regions[0] + p.off_ebar), st));
+    float* ebar3 = reinterpret_cast<float*>(w + wv.regions[0] + p.off_ebar);
+    if (p.field) HIP_TRY(launch_field_cumsum(p.R, r, ebar3, st));
+    else HIP_TRY(launch_residual_cumsum_raw(p.nch, p.nt, r, ebar3, st));
     for (int n = p.nt - 1; n >= 0; --n) {
       HIP_TRY(TIMED(KK_ADJ_VEL, st, launch3_adj_vel(wv.batch, n, 0, false, false, true, st)));
       HIP_TRY(TIMED(KK_ADJ_STR, st, launch3_adj_str(wv.batch, n, 0, false, false, st)));
@@ -1538,7 +1603,9 @@ efwi_status efwi_model_adjoint(const efwi_grid* grid, const efwi_shot* shot, con
   rc = setup_wave(*grid, shot, plans, 0, 1, {io}, EFWI_WS_ADJOINT, w, wv, st);
   if (rc != EFWI_OK) return rc;
   const Plan2D& p = wv.plans[0];
-  HIP_TRY(launch_residual_cumsum(wv.descs[0], r, reinterpret_cast<float*>(w + wv.regions[0] + p.off_ebar), st));
+  float* ebar = reinterpret_cast<float*>(w + wv.regions[0] + p.off_ebar);
+  if (p.field) HIP_TRY(launch_field_cumsum(p.R, r, ebar, st));
+  else HIP_TRY(launch_residual_cumsum(wv.descs[0], r, ebar, st));
   for (int n = p.nt - 1; n >= 0; --n) {
     HIP_TRY(TIMED(KK_ADJ_STEP, st, launch_adj_step(wv.batch, n, 0, false, false, true, st)));
   }
@@ -1622,7 +1689,7 @@ efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* 
     io[s].dobs = d_obs ? d_obs + off_obs : nullptr;
     io[s].gout = g_ext + (size_t)s * 3 * plane;
     io[s].phi = phi + s;
-    off_obs += (size_t)shots[s].nch * grid->nt;
+    off_obs += data_floats(*grid, shots[s]);
   }
   return gradient_waves(*grid, shots, ns, io, static_cast<unsigned char*>(ws), ws_bytes,
                         reinterpret_cast<hipStream_t>(stream));
@@ -1694,6 +1761,14 @@ efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zone
                   launch_zoi(three ? 1 : 0, npts, ny, grid->nx, grid->dz, three ? grid->dy : 0.0, grid->dx, a,
                              b + (size_t)s * npts, sink + (size_t)s * npts, st)));
   }
+  return EFWI_OK;
+}
+
+efwi_status efwi_das_field(const efwi_grid* grid, const efwi_shot* shot, const float* e, float* out, void* stream) {
+  efwi_status rc = efwi_validate(grid, 1, shot);
+  if (rc != EFWI_OK) return rc;
+  if (shot->nch > 0 && (!e || !out)) return fail(EFWI_E_INVAL, "NULL array argument");
+  HIP_TRY(launch_field_data(receiver_of(*grid, *shot), e, out, reinterpret_cast<hipStream_t>(stream)));
   return EFWI_OK;
 }
 

@@ -203,6 +203,21 @@ hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy
                       float* b, unsigned char* sink, hipStream_t st);
 hipError_t launch_final_model(int ns, long npts, const float* m_ext, const float* b, const unsigned char* sink,
                               float* m_out, hipStream_t st);
+// Field-like DAS sampling of recorded point strains (receiver.hip): gauge mean of `gauge`
+// consecutive channels, strain rate when `rate`, every decim-th sample. Identity when
+// gauge = decim = 1 and rate = 0 (the library then keeps the plain misfit path).
+struct Receiver {
+  int nch, nt, gauge, decim, rate;
+  float rdt;  // 1 / dt
+  bool identity() const { return gauge == 1 && decim == 1 && rate == 0; }
+  int nf() const { return nch - gauge + 1; }
+  int ntf() const { return nt / decim; }
+};
+hipError_t launch_field_data(const Receiver& R, const float* e, float* out, hipStream_t st);
+hipError_t launch_field_misfit(const Receiver& R, const float* e, const float* dobs, float* rf, double* partial,
+                               double* phi, float* ebar, hipStream_t st);
+hipError_t launch_field_cumsum(const Receiver& R, const float* rf, float* ebar, hipStream_t st);
+
 // Approximate inverse pseudo-Hessian (precondition.hip): the forward step with the velocity
 // autocorrelation into acc[0], the window sum into the full grid, the clipped inverse
 // (partial: inverse_diag_partials(n) floats of scratch).

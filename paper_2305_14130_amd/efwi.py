@@ -32,7 +32,7 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name",
             "efwi_plan_interval", "efwi_set_tile_rows", "efwi_get_tile_rows", "efwi_autotune_workspace_size",
             "efwi_autotune", "efwi_batch_waves", "efwi_zoi_weights", "efwi_final_model",
-            "efwi_pseudo_hessian"]
+            "efwi_pseudo_hessian", "efwi_das_field"]
 
 
 class Grid(ctypes.Structure):
@@ -48,13 +48,15 @@ class _ShotC(ctypes.Structure):
                 ("ch_iy", ctypes.POINTER(ctypes.c_int)), ("ch_ix", ctypes.POINTER(ctypes.c_int)),
                 ("z0", ctypes.c_int), ("y0", ctypes.c_int), ("x0", ctypes.c_int),
                 ("wz", ctypes.c_int), ("wy", ctypes.c_int), ("wx", ctypes.c_int),
-                ("ckpt_interval", ctypes.c_int), ("ckpt_mode", ctypes.c_int)]
+                ("ckpt_interval", ctypes.c_int), ("ckpt_mode", ctypes.c_int),
+                ("gauge", ctypes.c_int), ("decim", ctypes.c_int), ("rate", ctypes.c_int)]
 
 
 @dataclass
 class Shot:
-    """One shot: source node, DAS channel nodes (full-model coordinates), window, checkpointing.
-    The y fields are used on 3D grids only."""
+    """One shot: source node, DAS channel nodes (full-model coordinates), window, checkpointing,
+    DAS sampling (gauge channels, resampling factor, strain rate: see efwi_shot). The y
+    fields are used on 3D grids only."""
     src_iz: int
     src_ix: int
     ch_iz: np.ndarray
@@ -69,11 +71,21 @@ class Shot:
     ch_iy: np.ndarray = None
     y0: int = 0
     wy: int = 0
+    gauge: int = 1
+    decim: int = 1
+    rate: bool = False
     _keep: list = field(default_factory=list, repr=False)
 
     @property
     def nch(self) -> int:
         return int(len(self.ch_iz))
+
+    def data_shape(self, nt: int):
+        """Shape of this shot's data for nt time steps: (nch, nt) for point strain, else
+        (nch - gauge + 1, nt // decim)."""
+        if self.nch == 0:
+            return (0, nt // max(1, self.decim))
+        return (self.nch - max(1, self.gauge) + 1, nt // max(1, self.decim))
 
     def c_struct(self) -> _ShotC:
         iz = np.ascontiguousarray(self.ch_iz, dtype=np.int32)
@@ -83,7 +95,8 @@ class Shot:
         ip = ctypes.POINTER(ctypes.c_int)
         return _ShotC(self.src_iz, self.src_iy, self.src_ix, len(iz), iz.ctypes.data_as(ip),
                       None if iy is None else iy.ctypes.data_as(ip), ix.ctypes.data_as(ip),
-                      self.z0, self.y0, self.x0, self.wz, self.wy, self.wx, self.ckpt_interval, self.ckpt_mode)
+                      self.z0, self.y0, self.x0, self.wz, self.wy, self.wx, self.ckpt_interval, self.ckpt_mode,
+                      int(self.gauge), int(self.decim), int(bool(self.rate)))
 
 
 def make_grid(nz, nx, dz, dx, dt, nt, npml=0, pml_R=1e-3, pml_f0=10.0, vp_max=0.0) -> Grid:
@@ -283,10 +296,11 @@ def workspace(nbytes: int, device=None) -> torch.Tensor:
 
 
 def model_forward(grid: Grid, shot: Shot, m, src, d=None, ws=None, stream=None):
-    """d = K u(m): DAS e_xx data [nch][nt] of one shot."""
+    """d = K u(m): DAS data of one shot, shot.data_shape(nt) (point strain [nch][nt] by
+    default)."""
     _f32(m, "m"), _f32(src, "src")
     if d is None:
-        d = torch.empty((shot.nch, grid.nt), dtype=torch.float32, device=m.device)
+        d = torch.empty(shot.data_shape(grid.nt), dtype=torch.float32, device=m.device)
     sc = shot.c_struct()
     need = _lib.efwi_workspace_size(WS_FORWARD, ctypes.byref(grid), 1, ctypes.byref(sc))
     ws = ws if ws is not None else workspace(need, m.device)
@@ -393,6 +407,8 @@ class Zone(ctypes.Structure):
 _lib.efwi_zoi_weights.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(Zone), ctypes.c_float,
                                   ctypes.c_float, _vp, _vp, _vp]
 _lib.efwi_final_model.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+_lib.efwi_das_field.restype = ctypes.c_int
+_lib.efwi_das_field.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp]
 _lib.efwi_pseudo_hessian.restype = ctypes.c_int
 _lib.efwi_pseudo_hessian.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), _vp, _vp,
                                      ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t, _vp]
@@ -431,6 +447,17 @@ def final_model(grid: Grid, m_ext, b, sink, m_out=None, stream=None):
     _check(_lib.efwi_final_model(ctypes.byref(grid), m_ext.shape[0], _ptr(m_ext), _ptr(b), _ptr(sink), _ptr(m_out),
                                  _stream(stream)))
     return m_out
+
+
+def das_field(grid: Grid, shot: Shot, e, out=None, stream=None):
+    """Field data K e of the shot's DAS sampling from point strains e [nch][nt]."""
+    _f32(e, "e")
+    if out is None:
+        out = torch.empty(shot.data_shape(grid.nt), dtype=torch.float32, device=e.device)
+    _f32(out, "out")
+    sc = shot.c_struct()
+    _check(_lib.efwi_das_field(ctypes.byref(grid), ctypes.byref(sc), _ptr(e), _ptr(out), _stream(stream)))
+    return out
 
 
 def pseudo_hessian(grid: Grid, shots, m_ext, src, clip, h=None, p=None, ws=None, stream=None):

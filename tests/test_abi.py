@@ -195,3 +195,29 @@ def test_pseudo_hessian_argument_errors(efwi, case):
     rc = efwi._lib.efwi_pseudo_hessian(ctypes.byref(grid), ns, arr, fake, fake, clip, h, fake, fake, ws_bytes, None)
     assert rc == (efwi.E_WORKSPACE if case == "small_ws" else efwi.E_INVAL)
     assert efwi._lib.efwi_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(gauge=-1), dict(decim=-2), dict(gauge=5), dict(decim=60), dict(rate=2)])
+def test_das_sampling_validation(efwi, kw):
+    """The shot's DAS sampling is checked on the host: gauge and decim >= 0, a gauge no
+    longer than the channel list, decim <= nt, rate 0 or 1."""
+    grid = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+    shot = efwi.Shot(50, 100, [51, 51, 51, 51], [80, 81, 82, 83])
+    sc = shot.c_struct()
+    for k, v in kw.items():
+        setattr(sc, k, v)
+    arr = (efwi._ShotC * 1)(sc)
+    assert efwi._lib.efwi_validate(ctypes.byref(grid), 1, arr) == efwi.E_INVAL
+    assert efwi._lib.efwi_last_error()
+
+
+def test_das_sampling_sizes(efwi):
+    """Field sampling needs the recorded strains and the field residual in the workspace;
+    the default sampling keeps the sizes of the point-strain path."""
+    grid = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+    point = efwi.Shot(50, 100, [51] * 8, list(range(80, 88)))
+    field = efwi.Shot(50, 100, [51] * 8, list(range(80, 88)), gauge=3, decim=4, rate=True)
+    assert field.data_shape(50) == (6, 12) and point.data_shape(50) == (8, 50)
+    for kind in (efwi.WS_FORWARD, efwi.WS_GRADIENT):
+        assert efwi.workspace_size(kind, grid, [field]) > efwi.workspace_size(kind, grid, [point])
+    assert efwi.workspace_size(efwi.WS_ADJOINT, grid, [field]) == efwi.workspace_size(efwi.WS_ADJOINT, grid, [point])
