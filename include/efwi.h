@@ -163,6 +163,19 @@ efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* 
                                 const float* m_ext, const float* src, const float* d_obs,
                                 float* g_ext, double* phi, void* ws, size_t ws_bytes, void* stream);
 
+/* batch_gradient_grouped: the data term of eq.(8) with the model extended along groups of
+ * sources instead of single ones (the paper's suggestion for surveys with many shots):
+ * shot s runs on component group[s] of an extended model with ng components, and each
+ * component's gradient is the sum of its shots' gradients (each shot's FP64 sums rounded
+ * to FP32, then added in shot order, so the result does not depend on the waves).
+ *   group HOST int [ns], 0 <= group[s] < ng;
+ *   m_ext DEVICE [ng][3][nz][nx]; src DEVICE [ns][3][nt]; d_obs as in efwi_batch_gradient;
+ *   g_ext DEVICE [ng][3][nz][nx] output, overwritten; phi DEVICE double [ns] output.
+ * The regularizer, zones and final model then take ng components. */
+efwi_status efwi_batch_gradient_grouped(const efwi_grid* grid, int ns, const efwi_shot* shots, const int* group,
+                                        int ng, const float* m_ext, const float* src, const float* d_obs,
+                                        float* g_ext, double* phi, void* ws, size_t ws_bytes, void* stream);
+
 /* batch_waves: how efwi_batch_gradient groups the ns shots into waves (shots advanced
  * together, one launch per half step) for a workspace of ws_bytes. A 2D wave holds as many
  * shots as the workspace fits while their per-step state (both state buffers, imaging sums

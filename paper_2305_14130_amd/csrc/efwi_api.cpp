@@ -492,6 +492,7 @@ struct ShotIO {
   float* gout = nullptr;
   double* phi = nullptr;
   float* src_bar = nullptr;
+  bool accumulate = false;     // add the gradient into gout (shots sharing a component)
 };
 
 Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsigned char* region,
@@ -912,6 +913,15 @@ efwi_status gradient_waves(const efwi_grid& g, const efwi_shot* shots, int ns, c
     }
     rc = run_reverse(wv, ws, st);
     if (rc != EFWI_OK) return rc;
+    if (io[first].accumulate) {  // one launch per shot, in shot order: shots of a group add deterministically
+      for (int k = 0; k < count; ++k) {
+        const Plan2D& p = wv.plans[k];
+        HIP_TRY(launch_add_gradient(reinterpret_cast<const double*>(ws + wv.regions[k] + p.off_G), p.cells, p.cp, p.nz,
+                                    1, p.nx, io[first + k].gout, io[first + k].mplane, g.nx, g.nx, p.w.z0, 0, p.w.x0,
+                                    st));
+      }
+      continue;
+    }
     for (int k = 0; k < count; ++k) {
       const Plan2D& p = wv.plans[k];
       const bool full = p.w.z0 == 0 && p.w.x0 == 0 && p.nz == g.nz && p.nx == g.nx;
@@ -1308,6 +1318,15 @@ efwi_status gradient_waves3(const efwi_grid& g, const efwi_shot* shots, int ns, 
     }
     rc = run_reverse3(wv, ws, st);
     if (rc != EFWI_OK) return rc;
+    if (io[first].accumulate) {
+      for (int k = 0; k < count; ++k) {
+        const Plan3D& p = wv.plans[k];
+        HIP_TRY(launch_add_gradient(reinterpret_cast<const double*>(ws + wv.regions[k] + p.off_G), p.cells, p.cp, p.nz,
+                                    p.ny, p.nx, io[first + k].gout, io[first + k].mplane, g.nx, (long)g.ny * g.nx,
+                                    p.w.z0, p.w.y0, p.w.x0, st));
+      }
+      continue;
+    }
     for (int k = 0; k < count; ++k) {
       const Plan3D& p = wv.plans[k];
       const bool full = p.w.z0 == 0 && p.w.y0 == 0 && p.w.x0 == 0 && p.nz == g.nz && p.ny == g.ny && p.nx == g.nx;
@@ -1693,6 +1712,40 @@ efwi_status efwi_batch_gradient(const efwi_grid* grid, int ns, const efwi_shot* 
   }
   return gradient_waves(*grid, shots, ns, io, static_cast<unsigned char*>(ws), ws_bytes,
                         reinterpret_cast<hipStream_t>(stream));
+}
+
+efwi_status efwi_batch_gradient_grouped(const efwi_grid* grid, int ns, const efwi_shot* shots, const int* group,
+                                        int ng, const float* m_ext, const float* src, const float* d_obs,
+                                        float* g_ext, double* phi, void* ws, size_t ws_bytes, void* stream) {
+  efwi_status rc = efwi_validate(grid, ns, shots);
+  if (rc != EFWI_OK) return rc;
+  if (ns < 1 || ng < 1) return fail(EFWI_E_INVAL, "ns and ng must be >= 1");
+  if (!group || !m_ext || !src || !g_ext || !phi) return fail(EFWI_E_INVAL, "NULL array argument");
+  for (int s = 0; s < ns; ++s)
+    if (group[s] < 0 || group[s] >= ng) return fail(EFWI_E_INVAL, "shot %d: group %d outside [0, %d)", s, group[s], ng);
+  rc = check_same_schedule(*grid, ns, shots);
+  if (rc != EFWI_OK) return rc;
+  const long plane = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
+  const int ncomp = grid->ndim == 3 ? 6 : 3;
+  std::vector<ShotIO> io(ns);
+  size_t off_obs = 0;
+  for (int s = 0; s < ns; ++s) {
+    if (shots[s].nch > 0 && !d_obs) return fail(EFWI_E_INVAL, "d_obs is NULL");
+    io[s].m = m_ext + (size_t)group[s] * 3 * plane;
+    io[s].mplane = plane;
+    io[s].src = src + (size_t)s * ncomp * grid->nt;
+    io[s].dobs = d_obs ? d_obs + off_obs : nullptr;
+    io[s].gout = g_ext + (size_t)group[s] * 3 * plane;
+    io[s].phi = phi + s;
+    io[s].accumulate = true;
+    off_obs += data_floats(*grid, shots[s]);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // the first shot's workspace is checked before anything is written
+  rc = check_ws(ws, ws_bytes, efwi_workspace_size(EFWI_WS_GRADIENT, grid, 1, shots));
+  if (rc != EFWI_OK) return rc;
+  HIP_TRY(hipMemsetAsync(g_ext, 0, (size_t)ng * 3 * plane * sizeof(float), st));
+  return gradient_waves(*grid, shots, ns, io, static_cast<unsigned char*>(ws), ws_bytes, st);
 }
 
 efwi_status efwi_extension_regularizer(const efwi_grid* grid, int ns, const float* m_ext, const float* b,

@@ -203,6 +203,11 @@ hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy
                       float* b, unsigned char* sink, hipStream_t st);
 hipError_t launch_final_model(int ns, long npts, const float* m_ext, const float* b, const unsigned char* sink,
                               float* m_out, hipStream_t st);
+// Extension along groups of shots (regularizer.hip): one shot's FP64 gradient sums of its
+// window, rounded to FP32, added into its group's gradient component.
+hipError_t launch_add_gradient(const double* G, long cells, int cp, int nz, int ny, int nx, float* out, long mplane,
+                               long mrow, long mslab, int z0, int y0, int x0, hipStream_t st);
+
 // Field-like DAS sampling of recorded point strains (receiver.hip): gauge mean of `gauge`
 // consecutive channels, strain rate when `rate`, every decim-th sample. Identity when
 // gauge = decim = 1 and rate = 0 (the library then keeps the plain misfit path).

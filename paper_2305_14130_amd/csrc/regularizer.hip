@@ -183,6 +183,23 @@ __global__ __launch_bounds__(RB) void k_final_model(int ns, long npts, long plan
   }
 }
 
+// Extension along groups of shots: one shot's FP64 gradient sums G [3][nz][ny][cp] (its
+// window) rounded to FP32 and added into its group's component of the extended gradient,
+// out [3][...] with the full model's plane, row strides and the window origin.
+__global__ __launch_bounds__(RB) void k_add_gradient(const double* __restrict__ G, long cells, int cp, int nz, int ny,
+                                                     int nx, float* __restrict__ out, long mplane, long mrow,
+                                                     long mslab, int z0, int y0, int x0) {
+  const long n = (long)nz * ny * nx;
+  for (long q = blockIdx.x * (long)RB + threadIdx.x; q < n; q += (long)gridDim.x * RB) {
+    const int j = (int)(q % nx);
+    const long r = q / nx;
+    const int k = (int)(r % ny), i = (int)(r / ny);
+    const long c = ((long)i * ny + k) * cp + j;
+    const long o = (long)(z0 + i) * mslab + (long)(y0 + k) * mrow + (x0 + j);
+    for (int f = 0; f < 3; ++f) out[f * mplane + o] += (float)G[f * cells + c];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy, double dx, const ZoiArgs& a,
@@ -194,6 +211,14 @@ hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy
 hipError_t launch_final_model(int ns, long npts, const float* m_ext, const float* b, const unsigned char* sink,
                               float* m_out, hipStream_t st) {
   k_final_model<<<regularizer_blocks(npts), RB, 0, st>>>(ns, npts, npts, m_ext, b, sink, m_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_gradient(const double* G, long cells, int cp, int nz, int ny, int nx, float* out, long mplane,
+                               long mrow, long mslab, int z0, int y0, int x0, hipStream_t st) {
+  const long n = (long)nz * ny * nx;
+  if (n <= 0) return hipSuccess;
+  k_add_gradient<<<regularizer_blocks(n), RB, 0, st>>>(G, cells, cp, nz, ny, nx, out, mplane, mrow, mslab, z0, y0, x0);
   return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_timing_reset", "efwi_timing_query", "efwi_kernel_count", "efwi_kernel_name",
             "efwi_plan_interval", "efwi_set_tile_rows", "efwi_get_tile_rows", "efwi_autotune_workspace_size",
             "efwi_autotune", "efwi_batch_waves", "efwi_zoi_weights", "efwi_final_model",
-            "efwi_pseudo_hessian", "efwi_das_field"]
+            "efwi_pseudo_hessian", "efwi_das_field",
+            "efwi_batch_gradient_grouped"]
 
 
 class Grid(ctypes.Structure):
@@ -368,6 +369,31 @@ def batch_gradient(grid: Grid, shots, m_ext, src, d_obs, g_ext=None, phi=None, w
     return g_ext, phi
 
 
+def batch_gradient_grouped(grid: Grid, shots, groups, m_ext, src, d_obs, g_ext=None, phi=None, ws=None,
+                           stream=None):
+    """Data term with the model extended along groups of shots: shot s on m_ext[groups[s]],
+    g_ext[k] = sum of the gradients of the shots of group k (efwi_batch_gradient_grouped)."""
+    shots = list(shots)
+    grp = np.ascontiguousarray(groups, dtype=np.int32)
+    if grp.shape != (len(shots),):
+        raise ValueError("one group index per shot")
+    _f32(m_ext, "m_ext"), _f32(src, "src"), _f32(d_obs, "d_obs")
+    if g_ext is None:
+        g_ext = torch.empty_like(m_ext)
+    if phi is None:
+        phi = torch.empty((len(shots),), dtype=torch.float64, device=m_ext.device)
+    arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
+    need = _lib.efwi_workspace_size(WS_BATCH, ctypes.byref(grid), len(shots), arr)
+    if need == 0:
+        _check(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr))
+    ws = ws if ws is not None else workspace(need, m_ext.device)
+    _check(_lib.efwi_batch_gradient_grouped(ctypes.byref(grid), len(shots), arr,
+                                            grp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), m_ext.shape[0],
+                                            _ptr(m_ext), _ptr(src), _ptr(d_obs), _ptr(g_ext), _ptr(phi), _ptr(ws),
+                                            ws.numel(), _stream(stream)))
+    return g_ext, phi
+
+
 def batch_waves(grid: Grid, shots, ws_bytes: int):
     """First shot of each wave that batch_gradient advances together for a workspace of
     ws_bytes (see efwi_batch_waves)."""
@@ -407,6 +433,10 @@ class Zone(ctypes.Structure):
 _lib.efwi_zoi_weights.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(Zone), ctypes.c_float,
                                   ctypes.c_float, _vp, _vp, _vp]
 _lib.efwi_final_model.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+_lib.efwi_batch_gradient_grouped.restype = ctypes.c_int
+_lib.efwi_batch_gradient_grouped.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC),
+                                             ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
+                                             ctypes.c_size_t, _vp]
 _lib.efwi_das_field.restype = ctypes.c_int
 _lib.efwi_das_field.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp]
 _lib.efwi_pseudo_hessian.restype = ctypes.c_int

@@ -204,18 +204,29 @@ class _Problem:
 
 class ExtendedFWI(_Problem):
     """eq.(8): sum_s 1/2 ||d_s(m_s) - d_obs_s||^2 + 1/2 eta^2 ||(I - S^T S_w) W m~||^2 over
-    x [ns][2][nz][nx] (relative Vp, Vs perturbations of every component)."""
+    x [nc][2][nz][nx] (relative Vp, Vs perturbations of every component). With ``groups``
+    (one index per shot) the model is extended along groups of sources: shot s runs on
+    component groups[s], nc = max(groups) + 1, and b, sink hold one zone per group."""
 
-    def __init__(self, w, d_obs, b, sink, eta, device=None):
+    def __init__(self, w, d_obs, b, sink, eta, device=None, groups=None):
         super().__init__(w, d_obs, device)
         self.b, self.sink, self.eta = b, sink, eta
+        self.groups = None if groups is None else [int(k) for k in groups]
+        self.nc = self.ns if groups is None else max(self.groups) + 1
         self.rws = efwi.workspace(efwi.workspace_size(efwi.WS_REGULARIZER, self.grid, []), self.dev)
 
+    def _data(self, m_ext):
+        if self.groups is None:
+            return super()._data(m_ext)
+        g, phi = efwi.batch_gradient_grouped(self.grid, self.shots, self.groups, m_ext, self.src, self.d_obs,
+                                             ws=self.ws)
+        return g, float(phi.sum())
+
     def x0(self):
-        return torch.zeros((self.ns, 2, self.w.nz, self.w.nx), dtype=torch.float32, device=self.dev)
+        return torch.zeros((self.nc, 2, self.w.nz, self.w.nx), dtype=torch.float32, device=self.dev)
 
     def model(self, x):
-        m = self.m0.unsqueeze(0).repeat(self.ns, 1, 1, 1)
+        m = self.m0.unsqueeze(0).repeat(self.nc, 1, 1, 1)
         m[:, :2] *= 1.0 + x
         return m.contiguous()
 

@@ -221,3 +221,20 @@ def test_das_sampling_sizes(efwi):
     for kind in (efwi.WS_FORWARD, efwi.WS_GRADIENT):
         assert efwi.workspace_size(kind, grid, [field]) > efwi.workspace_size(kind, grid, [point])
     assert efwi.workspace_size(efwi.WS_ADJOINT, grid, [field]) == efwi.workspace_size(efwi.WS_ADJOINT, grid, [point])
+
+
+def test_grouped_gradient_argument_errors(efwi):
+    """Group indices outside [0, ng), ng < 1 and NULL arrays are rejected on the host."""
+    grid = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+    shots = [efwi.Shot(50, 100, [51], [120]), efwi.Shot(50, 110, [51], [130])]
+    arr = (efwi._ShotC * 2)(*[s.c_struct() for s in shots])
+    fake = ctypes.c_void_p(256)
+    ip = ctypes.POINTER(ctypes.c_int)
+    for grp, ng in (([0, 2], 2), ([0, -1], 2), ([0, 0], 0)):
+        g = np.asarray(grp, np.int32)
+        rc = efwi._lib.efwi_batch_gradient_grouped(ctypes.byref(grid), 2, arr, g.ctypes.data_as(ip), ng, fake, fake,
+                                                   fake, fake, fake, fake, 1 << 40, None)
+        assert rc == efwi.E_INVAL
+    rc = efwi._lib.efwi_batch_gradient_grouped(ctypes.byref(grid), 2, arr, None, 1, fake, fake, fake, fake, fake, fake,
+                                               1 << 40, None)
+    assert rc == efwi.E_INVAL
