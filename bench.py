@@ -182,7 +182,10 @@ def extension_ops(efwi, torch, grid, w, m_ext, src, dev, ph_steps=200):
     Also the approximate inverse pseudo-Hessian of the comparison methods for one shot over
     ph_steps time steps (median of 3 calls): per step the forward state (read and write 5
     fields), the 3 staged parameters and the autocorrelation sum (read and write) are
-    compulsory, 60 B per cell; the window sum and the inverse add 12 B per cell once."""
+    compulsory, 60 B per cell; the window sum and the inverse add 12 B per cell once. And the
+    field-like DAS sampling of the first shot's recorded strains (1500 channels x 4000 steps,
+    10-channel gauge, strain rate, every 4th sample; median of 5): reading the strains once
+    and writing the field data are compulsory."""
     ns, nz, nx = m_ext.shape[0], w.nz, w.nx
     zones = []
     for s in w.shots:
@@ -225,6 +228,11 @@ def extension_ops(efwi, torch, grid, w, m_ext, src, dev, ph_steps=200):
         ph_times.append(e0.elapsed_time(e1))
     pms = sorted(ph_times)[1]
     pbytes = (60 * ph_steps + 12) * nz * nx
+    fshot = efwi.Shot(s0.src_iz, s0.src_ix, s0.ch_iz, s0.ch_ix, gauge=10, decim=4, rate=True)
+    e = torch.randn((len(s0.ch_ix), w.nt), dtype=torch.float32, device=dev)
+    fout = torch.empty(fshot.data_shape(w.nt), dtype=torch.float32, device=dev)
+    dms = med_ms(lambda: efwi.das_field(grid, fshot, e, out=fout))
+    dbytes = 4 * (e.numel() + fout.numel())
     out = {"zoi_weights": {"sources": ns, "ms": round(zms, 3), "bytes": zbytes,
                            "GBs": round(zbytes / zms / 1e6, 1), "frac": round(zbytes / zms / 1e6 / HBM_PEAK_GBS, 4),
                            "sink_points": int(sink.sum().item())},
@@ -232,8 +240,11 @@ def extension_ops(efwi, torch, grid, w, m_ext, src, dev, ph_steps=200):
                            "GBs": round(fbytes / fms / 1e6, 1), "frac": round(fbytes / fms / 1e6 / HBM_PEAK_GBS, 4)},
            "pseudo_hessian": {"shots": 1, "steps": ph_steps, "ms": round(pms, 3), "bytes": pbytes,
                               "gcell_per_s": round(nz * nx * ph_steps / pms / 1e6, 2),
-                              "GBs": round(pbytes / pms / 1e6, 1), "frac": round(pbytes / pms / 1e6 / HBM_PEAK_GBS, 4)}}
-    del b, sink, m_out, h, pinv, ph_ws
+                              "GBs": round(pbytes / pms / 1e6, 1), "frac": round(pbytes / pms / 1e6 / HBM_PEAK_GBS, 4)},
+           "das_field": {"channels": int(e.shape[0]), "steps": int(e.shape[1]), "gauge": 10, "decim": 4, "rate": True,
+                         "ms": round(dms, 3), "bytes": dbytes, "GBs": round(dbytes / dms / 1e6, 1),
+                         "frac": round(dbytes / dms / 1e6 / HBM_PEAK_GBS, 4)}}
+    del b, sink, m_out, h, pinv, ph_ws, e, fout
     return out
 
 

@@ -16,36 +16,45 @@ namespace {
 
 constexpr int RB_ = 128;
 
-// One thread per field channel f: y = K e at every resampled time; with dobs, the residual
-// y - dobs goes to out and its squares' FP64 sum to partial[f], else y goes to out.
+// Field sample (f, k) of K e, in FP64: the gauge's channels summed in order, then scaled.
+__device__ __forceinline__ double field_sample(const Receiver& R, const float* __restrict__ e, int f, int k) {
+  const int n = k * R.decim + R.decim - 1;
+  double s = 0.0;
+  for (int c = f; c < f + R.gauge; ++c) {
+    const float* row = e + (long)c * R.nt;
+    double x = row[n];
+    if (R.rate) x = (x - (n > 0 ? (double)row[n - 1] : 0.0)) * (double)R.rdt;
+    s += x;
+  }
+  return s * (1.0 / R.gauge);
+}
+
+// One thread per field sample (consecutive threads take consecutive times of a channel).
+__global__ __launch_bounds__(RB_) void k_field_data(Receiver R, const float* __restrict__ e, float* __restrict__ out,
+                                                    long total) {
+  const int ntf = R.nt / R.decim;
+  for (long q = blockIdx.x * (long)RB_ + threadIdx.x; q < total; q += (long)gridDim.x * RB_) {
+    const int f = (int)(q / ntf), k = (int)(q - (long)f * ntf);
+    out[q] = (float)field_sample(R, e, f, k);
+  }
+}
+
+// One thread per field channel f: the residual K e - dobs at every resampled time into rf
+// and the FP64 sum of its squares into partial[f].
 __global__ __launch_bounds__(RB_) void k_field_residual(Receiver R, const float* __restrict__ e,
-                                                        const float* __restrict__ dobs, float* __restrict__ out,
+                                                        const float* __restrict__ dobs, float* __restrict__ rf,
                                                         double* __restrict__ partial) {
   const int f = blockIdx.x * RB_ + threadIdx.x;
   const int nf = R.nch - R.gauge + 1, ntf = R.nt / R.decim;
   if (f >= nf) return;
-  const double inv_g = 1.0 / R.gauge;
   double sq = 0.0;
   for (int k = 0; k < ntf; ++k) {
-    const int n = k * R.decim + R.decim - 1;
-    double s = 0.0;
-    for (int c = f; c < f + R.gauge; ++c) {
-      const float* row = e + (long)c * R.nt;
-      double x = row[n];
-      if (R.rate) x = (x - (n > 0 ? (double)row[n - 1] : 0.0)) * (double)R.rdt;
-      s += x;
-    }
-    const double y = s * inv_g;
     const long o = (long)f * ntf + k;
-    if (dobs) {
-      const double r = y - (double)dobs[o];
-      sq += r * r;
-      out[o] = (float)r;
-    } else {
-      out[o] = (float)y;
-    }
+    const double r = field_sample(R, e, f, k) - (double)dobs[o];
+    sq += r * r;
+    rf[o] = (float)r;
   }
-  if (partial) partial[f] = sq;
+  partial[f] = sq;
 }
 
 __global__ __launch_bounds__(256) void k_field_phi(const double* __restrict__ partial, int n,
@@ -96,8 +105,11 @@ int field_rows(const Receiver& R) { return R.nch > 0 ? std::max(0, R.nch - R.gau
 }  // namespace
 
 hipError_t launch_field_data(const Receiver& R, const float* e, float* out, hipStream_t st) {
-  const int nf = field_rows(R);
-  if (nf > 0 && R.nt / R.decim > 0) k_field_residual<<<blocks(nf), RB_, 0, st>>>(R, e, nullptr, out, nullptr);
+  const long total = (long)field_rows(R) * (R.nt / R.decim);
+  if (total > 0) {
+    const long nb = std::min<long>((total + RB_ - 1) / RB_, 4096);
+    k_field_data<<<(int)nb, RB_, 0, st>>>(R, e, out, total);
+  }
   return hipGetLastError();
 }
 
