@@ -16,6 +16,7 @@ Modules
 ``zoi``         the sources' zones of influence, eq.(10): weights b_s and sinkhole flags.
 ``receiver``    the field-like DAS sampling K_r of eq.(3): gauge-length mean, strain rate,
                 resampling, its transpose and the per-shot gradient through it.
+``bspline``     the cubic B-spline model parameterization (expansion and its transpose).
 ``precondition`` the comparison methods: approximate inverse pseudo-Hessian (velocity
                 autocorrelation summed over shots, clipped, scaled), near-offset mute; the
                 gradient preconditioning of eq.(15) is ``regularizer.final_model``.
