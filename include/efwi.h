@@ -239,6 +239,25 @@ efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zone
 efwi_status efwi_final_model(const efwi_grid* grid, int ns, const float* m_ext, const float* b,
                              const unsigned char* sink, float* m_out, void* stream);
 
+/* Cubic B-spline model parameterization (the smoothing regularization of the field example,
+ * which describes the model by cubic B-spline coefficients on a node grid of 50 m in x and
+ * the grid spacing in z). Along an axis of n cells with node spacing D cells (D >= 1), node
+ * k = 0 .. N-1 sits at cell (k - 1) D and carries the uniform cubic B-spline
+ * B((i - (k - 1) D) / D): 2/3 - t^2 + |t|^3/2 for |t| < 1, (2 - |t|)^3 / 6 for 1 <= |t| < 2,
+ * 0 beyond; N = ceil((n - 1) / D) + 3 nodes, so the basis sums to one on the grid.
+ * efwi_bspline_nodes: N (0 for n < 1 or D < 1).
+ * efwi_bspline_expand: m = Bz c Bx^T for np planes; c DEVICE [np][Nz][Nx], m DEVICE
+ *   [np][nz][nx] output.
+ * efwi_bspline_adjoint: c_bar = Bz^T g Bx (the transpose: gradients with respect to the
+ *   coefficients); g DEVICE [np][nz][nx], c_bar DEVICE [np][Nz][Nx] output.
+ * FP64 weights and sums, one launch on `stream`; EFWI_E_INVAL for sizes or spacings below
+ * 1 or NULL arrays. */
+int efwi_bspline_nodes(int n, int spacing);
+efwi_status efwi_bspline_expand(int nz, int nx, int dz_nodes, int dx_nodes, int np, const float* c, float* m,
+                                void* stream);
+efwi_status efwi_bspline_adjoint(int nz, int nx, int dz_nodes, int dx_nodes, int np, const float* g, float* c_bar,
+                                 void* stream);
+
 /* das_field: the field data K e of a shot (see efwi_shot's DAS sampling) from recorded point
  * strains, e.g. of a shot with the default sampling.
  *   e   DEVICE [nch][nt] point strains (x-x strain at each channel at t_{n+1});

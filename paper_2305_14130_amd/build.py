@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libefwi.so")
 SOURCES = ["kernels2d.hip", "kernels3d.hip", "regularizer.hip", "checkpoint.hip", "precondition.hip",
-           "receiver.hip", "efwi_api.cpp"]
+           "receiver.hip", "bspline.hip", "efwi_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1817,6 +1817,33 @@ efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zone
   return EFWI_OK;
 }
 
+int efwi_bspline_nodes(int n, int spacing) { return (n >= 1 && spacing >= 1) ? bspline_nodes(n, spacing) : 0; }
+
+static efwi_status check_bspline(int nz, int nx, int dz_nodes, int dx_nodes, int np, const void* a, const void* b) {
+  if (nz < 1 || nx < 1 || np < 1) return fail(EFWI_E_INVAL, "nz, nx and np must be >= 1");
+  if (dz_nodes < 1 || dx_nodes < 1) return fail(EFWI_E_INVAL, "node spacings must be >= 1 cell");
+  if (!a || !b) return fail(EFWI_E_INVAL, "NULL array argument");
+  return EFWI_OK;
+}
+
+efwi_status efwi_bspline_expand(int nz, int nx, int dz_nodes, int dx_nodes, int np, const float* c, float* m,
+                                void* stream) {
+  g_last_error.clear();
+  const efwi_status rc = check_bspline(nz, nx, dz_nodes, dx_nodes, np, c, m);
+  if (rc != EFWI_OK) return rc;
+  HIP_TRY(launch_bspline_expand(np, nz, nx, dz_nodes, dx_nodes, c, m, reinterpret_cast<hipStream_t>(stream)));
+  return EFWI_OK;
+}
+
+efwi_status efwi_bspline_adjoint(int nz, int nx, int dz_nodes, int dx_nodes, int np, const float* g, float* c_bar,
+                                 void* stream) {
+  g_last_error.clear();
+  const efwi_status rc = check_bspline(nz, nx, dz_nodes, dx_nodes, np, g, c_bar);
+  if (rc != EFWI_OK) return rc;
+  HIP_TRY(launch_bspline_adjoint(np, nz, nx, dz_nodes, dx_nodes, g, c_bar, reinterpret_cast<hipStream_t>(stream)));
+  return EFWI_OK;
+}
+
 efwi_status efwi_das_field(const efwi_grid* grid, const efwi_shot* shot, const float* e, float* out, void* stream) {
   efwi_status rc = efwi_validate(grid, 1, shot);
   if (rc != EFWI_OK) return rc;

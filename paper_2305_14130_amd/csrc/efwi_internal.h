@@ -208,6 +208,12 @@ hipError_t launch_final_model(int ns, long npts, const float* m_ext, const float
 hipError_t launch_add_gradient(const double* G, long cells, int cp, int nz, int ny, int nx, float* out, long mplane,
                                long mrow, long mslab, int z0, int y0, int x0, hipStream_t st);
 
+// Cubic B-spline model parameterization (bspline.hip): node count of an axis of n cells with
+// node spacing D, expansion of coefficient planes and its transpose.
+int bspline_nodes(int n, int D);
+hipError_t launch_bspline_expand(int np, int nz, int nx, int Dz, int Dx, const float* c, float* m, hipStream_t st);
+hipError_t launch_bspline_adjoint(int np, int nz, int nx, int Dz, int Dx, const float* g, float* cb, hipStream_t st);
+
 // Field-like DAS sampling of recorded point strains (receiver.hip): gauge mean of `gauge`
 // consecutive channels, strain rate when `rate`, every decim-th sample. Identity when
 // gauge = decim = 1 and rate = 0 (the library then keeps the plain misfit path).

@@ -33,7 +33,8 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_plan_interval", "efwi_set_tile_rows", "efwi_get_tile_rows", "efwi_autotune_workspace_size",
             "efwi_autotune", "efwi_batch_waves", "efwi_zoi_weights", "efwi_final_model",
             "efwi_pseudo_hessian", "efwi_das_field",
-            "efwi_batch_gradient_grouped"]
+            "efwi_batch_gradient_grouped", "efwi_bspline_nodes", "efwi_bspline_expand",
+            "efwi_bspline_adjoint"]
 
 
 class Grid(ctypes.Structure):
@@ -437,6 +438,11 @@ _lib.efwi_batch_gradient_grouped.restype = ctypes.c_int
 _lib.efwi_batch_gradient_grouped.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC),
                                              ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp,
                                              ctypes.c_size_t, _vp]
+_lib.efwi_bspline_nodes.restype = ctypes.c_int
+_lib.efwi_bspline_nodes.argtypes = [ctypes.c_int, ctypes.c_int]
+for _name in ("efwi_bspline_expand", "efwi_bspline_adjoint"):
+    getattr(_lib, _name).restype = ctypes.c_int
+    getattr(_lib, _name).argtypes = [ctypes.c_int] * 5 + [_vp, _vp, _vp]
 _lib.efwi_das_field.restype = ctypes.c_int
 _lib.efwi_das_field.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp]
 _lib.efwi_pseudo_hessian.restype = ctypes.c_int
@@ -477,6 +483,38 @@ def final_model(grid: Grid, m_ext, b, sink, m_out=None, stream=None):
     _check(_lib.efwi_final_model(ctypes.byref(grid), m_ext.shape[0], _ptr(m_ext), _ptr(b), _ptr(sink), _ptr(m_out),
                                  _stream(stream)))
     return m_out
+
+
+def bspline_nodes(n: int, spacing: int) -> int:
+    """Cubic B-spline nodes along an axis of n cells with the given node spacing (cells)."""
+    return int(_lib.efwi_bspline_nodes(int(n), int(spacing)))
+
+
+def bspline_expand(c, nz: int, nx: int, dz_nodes: int, dx_nodes: int, out=None, stream=None):
+    """Model planes [..][nz][nx] from cubic B-spline coefficients c [..][Nz][Nx]."""
+    _f32(c, "c")
+    lead = c.shape[:-2]
+    if out is None:
+        out = torch.empty(lead + (nz, nx), dtype=torch.float32, device=c.device)
+    _f32(out, "out")
+    np_ = int(np.prod(lead)) if len(lead) else 1
+    if c.shape[-2:] != (bspline_nodes(nz, dz_nodes), bspline_nodes(nx, dx_nodes)):
+        raise ValueError("coefficient planes must be [Nz][Nx] for these spacings")
+    _check(_lib.efwi_bspline_expand(nz, nx, dz_nodes, dx_nodes, np_, _ptr(c), _ptr(out), _stream(stream)))
+    return out
+
+
+def bspline_adjoint(g, dz_nodes: int, dx_nodes: int, out=None, stream=None):
+    """Coefficient gradients [..][Nz][Nx] from model-plane gradients g [..][nz][nx]."""
+    _f32(g, "g")
+    lead, (nz, nx) = g.shape[:-2], g.shape[-2:]
+    shape = lead + (bspline_nodes(nz, dz_nodes), bspline_nodes(nx, dx_nodes))
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=g.device)
+    _f32(out, "out")
+    np_ = int(np.prod(lead)) if len(lead) else 1
+    _check(_lib.efwi_bspline_adjoint(nz, nx, dz_nodes, dx_nodes, np_, _ptr(g), _ptr(out), _stream(stream)))
+    return out
 
 
 def das_field(grid: Grid, shot: Shot, e, out=None, stream=None):

@@ -182,9 +182,13 @@ def lbfgs(fg, x0, max_iter=100, rate_tol=1e-3, memory=10, first_step=None, callb
 
 
 class _Problem:
-    """Shared set-up: grid, shots, sources, observed data and the starting model."""
+    """Shared set-up: grid, shots, sources, observed data and the starting model, and the
+    parameterization of the unknowns: relative Vp, Vs perturbations on the grid, or, with
+    ``bspline=(dz_nodes, dx_nodes)``, their cubic B-spline coefficients (efwi.bspline_*; the
+    field example's smoothing regularization); ``mask`` [nz][nx] multiplies the gradients on
+    the grid (the field example restricts the update to the reservoir layer)."""
 
-    def __init__(self, w, d_obs, device=None):
+    def __init__(self, w, d_obs, device=None, bspline=None, mask=None):
         self.dev = device if device is not None else torch.device("cuda")
         self.w = w
         self.grid = efwi.make_grid(w.nz, w.nx, w.dz, w.dx, w.dt, w.nt, w.npml, w.pml_R, w.f0, w.vp_max)
@@ -196,6 +200,28 @@ class _Problem:
         self.m0 = torch.tensor(w.m_start, dtype=torch.float32, device=self.dev)
         self.ws = efwi.workspace(efwi.workspace_size(efwi.WS_BATCH, self.grid, self.shots), self.dev)
         self.data_phi = None
+        self.bspline = None if bspline is None else (int(bspline[0]), int(bspline[1]))
+        self.mask = mask
+
+    def _xshape(self):
+        if self.bspline is None:
+            return (self.w.nz, self.w.nx)
+        return (efwi.bspline_nodes(self.w.nz, self.bspline[0]), efwi.bspline_nodes(self.w.nx, self.bspline[1]))
+
+    def _rel(self, x):
+        """Relative perturbations on the grid from the unknowns."""
+        if self.bspline is None:
+            return x
+        return efwi.bspline_expand(x.contiguous(), self.w.nz, self.w.nx, *self.bspline)
+
+    def _grad_x(self, g_rel):
+        """Gradient with respect to the unknowns from the one on the grid's relative
+        perturbations: mask, then the B-spline transpose."""
+        if self.mask is not None:
+            g_rel = g_rel * self.mask
+        if self.bspline is None:
+            return g_rel.contiguous()
+        return efwi.bspline_adjoint(g_rel.contiguous(), *self.bspline)
 
     def _data(self, m_ext):
         g, phi = efwi.batch_gradient(self.grid, self.shots, m_ext, self.src, self.d_obs, ws=self.ws)
@@ -208,8 +234,8 @@ class ExtendedFWI(_Problem):
     (one index per shot) the model is extended along groups of sources: shot s runs on
     component groups[s], nc = max(groups) + 1, and b, sink hold one zone per group."""
 
-    def __init__(self, w, d_obs, b, sink, eta, device=None, groups=None):
-        super().__init__(w, d_obs, device)
+    def __init__(self, w, d_obs, b, sink, eta, device=None, groups=None, bspline=None, mask=None):
+        super().__init__(w, d_obs, device, bspline, mask)
         self.b, self.sink, self.eta = b, sink, eta
         self.groups = None if groups is None else [int(k) for k in groups]
         self.nc = self.ns if groups is None else max(self.groups) + 1
@@ -223,11 +249,11 @@ class ExtendedFWI(_Problem):
         return g, float(phi.sum())
 
     def x0(self):
-        return torch.zeros((self.nc, 2, self.w.nz, self.w.nx), dtype=torch.float32, device=self.dev)
+        return torch.zeros((self.nc, 2) + self._xshape(), dtype=torch.float32, device=self.dev)
 
     def model(self, x):
         m = self.m0.unsqueeze(0).repeat(self.nc, 1, 1, 1)
-        m[:, :2] *= 1.0 + x
+        m[:, :2] *= 1.0 + self._rel(x)
         return m.contiguous()
 
     def __call__(self, x):
@@ -235,7 +261,7 @@ class ExtendedFWI(_Problem):
         g, phi_d = self._data(m)
         phi_r = efwi.extension_regularizer(self.grid, m, self.b, self.sink, self.eta, g, ws=self.rws)
         self.data_phi = phi_d
-        return phi_d + float(phi_r), (g[:, :2] * self.m0[:2]).contiguous()
+        return phi_d + float(phi_r), self._grad_x(g[:, :2] * self.m0[:2])
 
     def final(self, x):
         """eq.(9): the physical model S_w W m~."""
@@ -243,21 +269,22 @@ class ExtendedFWI(_Problem):
 
 
 class ConventionalFWI(_Problem):
-    """Conventional misfit: every shot on the one model m, x [2][nz][nx]."""
+    """Conventional misfit: every shot on the one model m, x [2][...] (grid or B-spline
+    coefficients)."""
 
     def x0(self):
-        return torch.zeros((2, self.w.nz, self.w.nx), dtype=torch.float32, device=self.dev)
+        return torch.zeros((2,) + self._xshape(), dtype=torch.float32, device=self.dev)
 
     def model(self, x):
         m = self.m0.clone()
-        m[:2] *= 1.0 + x
+        m[:2] *= 1.0 + self._rel(x)
         return m
 
     def __call__(self, x):
         m = self.model(x)
         g, phi = self._data(m.unsqueeze(0).repeat(self.ns, 1, 1, 1).contiguous())
         self.data_phi = phi
-        return phi, (g.sum(0)[:2] * self.m0[:2]).contiguous()
+        return phi, self._grad_x(g.sum(0)[:2] * self.m0[:2])
 
     def final(self, x):
         return self.model(x)
@@ -269,8 +296,8 @@ class PreconditionedFWI(ConventionalFWI):
     mapped by S_w W (efwi.final_model with the zones' weights and sinkholes) instead of
     summed. The objective is unchanged, so the direction need not descend."""
 
-    def __init__(self, w, d_obs, b, sink, device=None):
-        super().__init__(w, d_obs, device)
+    def __init__(self, w, d_obs, b, sink, device=None, bspline=None, mask=None):
+        super().__init__(w, d_obs, device, bspline, mask)
         self.b, self.sink = b, sink
 
     def __call__(self, x):
@@ -278,7 +305,7 @@ class PreconditionedFWI(ConventionalFWI):
         g, phi = self._data(m.unsqueeze(0).repeat(self.ns, 1, 1, 1).contiguous())
         self.data_phi = phi
         gbar = efwi.final_model(self.grid, g, self.b, self.sink)
-        return phi, (gbar[:2] * self.m0[:2]).contiguous()
+        return phi, self._grad_x(gbar[:2] * self.m0[:2])
 
 
 def inverse_pseudo_hessian(prob, clip):

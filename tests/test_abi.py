@@ -238,3 +238,16 @@ def test_grouped_gradient_argument_errors(efwi):
     rc = efwi._lib.efwi_batch_gradient_grouped(ctypes.byref(grid), 2, arr, None, 1, fake, fake, fake, fake, fake, fake,
                                                1 << 40, None)
     assert rc == efwi.E_INVAL
+
+
+def test_bspline_arguments(efwi):
+    """Node counts follow ceil((n - 1) / D) + 3; bad sizes, spacings and NULL arrays are
+    rejected before any launch."""
+    assert efwi._lib.efwi_bspline_nodes(100, 10) == 13 and efwi._lib.efwi_bspline_nodes(101, 10) == 13
+    assert efwi._lib.efwi_bspline_nodes(102, 10) == 14 and efwi._lib.efwi_bspline_nodes(1, 1) == 3
+    assert efwi._lib.efwi_bspline_nodes(0, 1) == 0 and efwi._lib.efwi_bspline_nodes(10, 0) == 0
+    fake = ctypes.c_void_p(256)
+    for args in ((0, 10, 1, 1, 1), (10, 10, 0, 1, 1), (10, 10, 1, 1, 0)):
+        assert efwi._lib.efwi_bspline_expand(*args, fake, fake, None) == efwi.E_INVAL
+        assert efwi._lib.efwi_bspline_adjoint(*args, fake, fake, None) == efwi.E_INVAL
+    assert efwi._lib.efwi_bspline_expand(10, 10, 1, 1, 1, None, fake, None) == efwi.E_INVAL
