@@ -10,6 +10,8 @@ Modules
 ``elastic2d``   eq.(1)-(4), (6), (8) data term: 2D isotropic elastic velocity-stress
                 propagation (forward, exact discrete transpose, per-shot gradient).
 ``elastic3d``   the same for 3D (9 fields).
+``vti2d``       the 2D propagation, transpose and gradient in a VTI medium (Thomsen eps,
+                delta = eps / 2) at fixed eps and density, as in the field example.
 ``regularizer`` eq.(8) regularization term with the operators W (eq.(11)), S_w (eq.(12))
                 and S^T, written as dense per-point matrices.
 ``checkpoint``  the 16-bit checkpoint encodings (per-snapshot max-abs scaling).
