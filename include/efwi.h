@@ -60,6 +60,13 @@ typedef struct {
   float pml_R;     /* CPML target reflection coefficient (e.g. 1e-3)                 */
   float pml_f0;    /* CPML frequency-shift parameter alpha_max = pi * pml_f0         */
   float vp_max;    /* caller's bound on Vp: CFL check and CPML damping d0            */
+  /* VTI medium (the field example's starting model: vertical symmetry axis, Thomsen eps,
+   * delta = eps / 2): DEVICE [nz][nx] eps of the full model, or NULL for an isotropic
+   * medium. The model's (Vp, Vs, rho) are then (Vp0, Vs0, rho): c33 = rho Vp0^2,
+   * c55 = rho Vs0^2, c11 = c33 (1 + 2 eps), c13 = sqrt((c33 - c55)(c33 (1 + eps) - c55))
+   * - c55; gradients are with respect to (Vp0, Vs0, rho) at fixed eps. vp_max must bound
+   * the horizontal P speed Vp0 sqrt(1 + 2 eps). 2D only (EFWI_E_UNSUPPORTED in 3D). */
+  const float* eps;
 } efwi_grid;
 
 /* Checkpoint storage modes for the reverse sweep (wavefield recomputation). */

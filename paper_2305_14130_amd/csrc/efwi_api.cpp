@@ -256,6 +256,7 @@ efwi_status validate_grid(const efwi_grid* g) {
     return fail(EFWI_E_INVAL, "grid spacings and dt must be positive");
   if (g->nt < 1) return fail(EFWI_E_INVAL, "nt must be >= 1 (got %d)", g->nt);
   if (g->npml < 0) return fail(EFWI_E_INVAL, "npml must be >= 0");
+  if (g->eps && three) return fail(EFWI_E_UNSUPPORTED, "VTI media are 2D only");
   if (!(g->vp_max > 0.f)) return fail(EFWI_E_INVAL, "vp_max must be positive");
   if (g->npml > 0 && !(g->pml_R > 0.f && g->pml_R < 1.f)) return fail(EFWI_E_INVAL, "pml_R must be in (0, 1)");
   if (g->npml > 0 && !(g->pml_f0 >= 0.f)) return fail(EFWI_E_INVAL, "pml_f0 must be >= 0");
@@ -407,7 +408,8 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind, int fwd
   // adjoint fields double-buffered by step parity (10 planes), then the two buffers of the
   // adjoint memory variables
   p.adj_bytes = align_up(((size_t)10 * p.plane + 2 * strips) * sizeof(float));
-  p.par_bytes = align_up((size_t)3 * p.plane * sizeof(float));
+  // staged lambda, mu, rho (+ c11, c13 in a VTI medium)
+  p.par_bytes = align_up((size_t)(g.eps ? 5 : 3) * p.plane * sizeof(float));
   p.tab_bytes = align_up((size_t)(4 * p.nx + 4 * p.nz) * sizeof(float) + (size_t)p.nz * sizeof(int) +
                          (size_t)p.nslots * p.nx * sizeof(int));
   const bool fwd = kind != EFWI_WS_ADJOINT;
@@ -429,7 +431,7 @@ Plan2D plan2d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind, int fwd
   p.field = !p.R.identity();
   p.off_dint = (grad || (fwd && p.field)) ? take((size_t)std::max(1, p.nch) * p.nt * sizeof(float)) : 0;
   p.off_rf = (grad && p.field) ? take(std::max<size_t>(1, data_floats(g, s)) * sizeof(float)) : 0;
-  p.off_acc = grad ? take((size_t)NACC * p.cells * sizeof(float)) : 0;
+  p.off_acc = grad ? take((size_t)(g.eps ? NACC_VTI : NACC) * p.cells * sizeof(float)) : 0;
   p.off_G = grad ? take((size_t)3 * p.cells * sizeof(double)) : 0;
   p.off_seg = grad ? take((size_t)p.L * NSEG_FIELDS * p.cells * sizeof(float)) : 0;
   p.off_ckpt = grad ? take((size_t)std::max(0, p.nseg - 2) * p.slot_bytes) : 0;
@@ -536,6 +538,9 @@ Shot2D make_desc(const efwi_grid& g, const efwi_shot& s, const Plan2D& p, unsign
   strips_at(st + strips, d.pbx[1], d.pbz[1]);
   fields(p.off_par, f);
   d.lam = f[0], d.mu = f[1], d.rho = f[2];
+  d.c11 = g.eps ? f[3] : nullptr;
+  d.c13 = g.eps ? f[4] : nullptr;
+  d.meps = g.eps ? (const gfloat*)(g.eps + (long)p.w.z0 * g.nx + p.w.x0) : nullptr;
   d.prof = (const gfloat*)(tab);
   d.row_slot = (const gint*)(tab + 4 * p.nx + 4 * p.nz);
   d.rowch = d.row_slot + p.nz;
@@ -749,6 +754,7 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   wv.batch.adj_step = StepSched{reinterpret_cast<const StepSlot*>(ws + off_as), nsched[2]};
   wv.batch.fwd_rows = frows;
   wv.batch.adj_rows = arows;
+  wv.batch.vti = g.eps != nullptr;
   wv.batch.shots = reinterpret_cast<const Shot2D*>(ws + off_desc);
   wv.batch.ns = count;
   wv.batch.ntiles = ntiles;

@@ -31,6 +31,7 @@ constexpr int NSEG_FIELDS = 5;
 // (the normal-node mu term plus the four surrounding mu_xz terms); rho through the
 // buoyancies of the four surrounding velocity nodes.
 constexpr int NACC = 3;
+constexpr int NACC_VTI = 5;   // VTI: the c11, c33 and c13 sums replace the lambda sum
 // Time steps summed in FP32 before the imaging sums are chained into the FP64 gradient.
 constexpr int FLUSH_STEPS = 32;
 
@@ -67,6 +68,11 @@ struct Shot2D {
   gfloat* pbz[2][4];             // double-buffered z-strip adjoint memory variables
   // staged parameters at the normal nodes (padded; the halo repeats the last row and column)
   gfloat *lam, *mu, *rho;
+  // VTI (Thomsen eps, delta = eps / 2): staged c11 and c13 at the normal nodes (c33 is
+  // lambda + 2 mu), and the window of the eps model (unpadded, full-model pitch); NULL in
+  // an isotropic medium
+  gfloat *c11, *c13;
+  const gfloat* meps;
   // CPML profiles: axi bxi axh bxh [nx] then azi bzi azh bzh [nz]
   const gfloat* prof;
   // source
@@ -122,6 +128,7 @@ struct Batch2D {
   // transposed step (adj_rows rows), 64 columns wide
   StepSched step, adj_step;
   int fwd_rows, adj_rows;
+  int vti;                   // the shots' medium is VTI (the fused steps' VTI instances)
 };
 
 // Rows of a fused-step tile (64 columns wide): the kernels are built for these heights and

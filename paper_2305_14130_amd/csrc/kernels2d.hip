@@ -139,6 +139,7 @@ struct StepPtrs {
   const gfloat *sxx, *szz, *sxz, *vx, *vz;   // buffer n & 1, padded plane origins
   gfloat *wsxx, *wszz, *wsxz, *wvx, *wvz;    // buffer (n + 1) & 1
   const gfloat *lam, *mu, *rho;              // staged parameters, padded plane origins
+  const gfloat *c11, *c13;                   // VTI staged parameters (NULL: isotropic)
   const gfloat* rps;                         // memory variables of buffer n & 1 (see xv, zv)
   gfloat* wps;                               // and of buffer (n + 1) & 1
   const gfloat* prof;                        // CPML profiles (see xp, zp)
@@ -164,6 +165,8 @@ __device__ __forceinline__ StepPtrs step_ptrs(const Shot2D& s, int n, gfloat* se
   p.lam = s.lam - org;
   p.mu = s.mu - org;
   p.rho = s.rho - org;
+  p.c11 = s.c11 ? s.c11 - org : nullptr;
+  p.c13 = s.c13 ? s.c13 - org : nullptr;
   p.rps = s.psx[0] + rd;
   p.wps = s.psx[0] + wr;
   p.prof = s.prof;
@@ -306,14 +309,16 @@ __device__ __forceinline__ void vel_node(const StepPtrs& p, const Shot2D& s, int
 // Inputs of one stress node (loads only; the DAS channel, in the rare channel rows, is
 // looked up in str_node).
 struct StrLoads {
-  float lam, mu, mu_x, mu_z, mu_xz;
+  float lam, mu, mu_x, mu_z, mu_xz, c11, c13;
 };
 
-template <bool PML, bool EDGE>
+template <bool PML, bool EDGE, bool VTI>
 __device__ __forceinline__ StrLoads str_loads(const StepPtrs& p, const Shot2D& s, int gi, int gj) {
   StrLoads L;
   const int ic = EDGE ? min(gi, p.nz - 1) : gi, jc = EDGE ? min(gj, p.nx - 1) : gj;
   const unsigned o = pofs(p, ic, jc);
+  L.c11 = VTI ? G(p.c11, o) : 0.0f;
+  L.c13 = VTI ? G(p.c13, o) : 0.0f;
   L.lam = G(p.lam, o);
   L.mu = G(p.mu, o);
   L.mu_x = G(p.mu + 1, o);
@@ -324,7 +329,9 @@ __device__ __forceinline__ StrLoads str_loads(const StepPtrs& p, const Shot2D& s
 
 // Stress node (i, j) from the LDS strain rates pxx = D-x vx, pzz = D-z vz, pzx = D+z vx,
 // pxz = D+x vz and the LDS sigma^n.
-template <bool STORE, bool RECORD, bool PML>
+// VTI: sigma_xx += dt (c11 p_xx + c13 p_zz), sigma_zz += dt (c13 p_xx + c33 p_zz), and the
+// stored normal-block quantities are p_xx / det and p_zz / det, det = c11 c33 - c13^2.
+template <bool STORE, bool RECORD, bool PML, bool VTI>
 __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int i, int j, int n, const StrLoads& L,
                                          int slot, float pxx, float pzz, float pzx, float pxz, float sxx, float szz,
                                          float sxz, float f_xx, float f_zz, float f_xz) {
@@ -352,8 +359,9 @@ __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int
     }
   }
   const float ps = pzx + pxz;
-  sxx += s.dt * (l2m * pxx + lam * pzz);
-  szz += s.dt * (lam * pxx + l2m * pzz);
+  const float c11 = VTI ? L.c11 : l2m, c13 = VTI ? L.c13 : lam;
+  sxx += s.dt * (c11 * pxx + c13 * pzz);
+  szz += s.dt * (c13 * pxx + l2m * pzz);
   sxz += s.dt * mxz * ps;
   if (i == s.si && j == s.sj) {
     sxx -= s.w * f_xx;
@@ -386,15 +394,21 @@ __device__ __forceinline__ void str_node(const StepPtrs& p, const Shot2D& s, int
   }
   if (STORE) {  // strain rates times the factors of the lambda and mu imaging terms
     const unsigned c = (unsigned)(i * s.cp + j);
-    GS(p.seg, c, (pxx + pzz) / (l2m + lam));
-    GS(p.seg, s.cells + c, 0.5f * (pxx - pzz) * mu);
+    if (VTI) {
+      const float det = c11 * l2m - c13 * c13;
+      GS(p.seg, c, pxx / det);
+      GS(p.seg, s.cells + c, pzz / det);
+    } else {
+      GS(p.seg, c, (pxx + pzz) / (l2m + lam));
+      GS(p.seg, s.cells + c, 0.5f * (pxx - pzz) * mu);
+    }
     GS(p.seg, 2 * s.cells + c, 0.25f * ps * mxz);
   }
 }
 
 // ACORR: also add vx^2 + vz^2 of the new velocities at the owned nodes into acc[0] (the
 // zero-lag autocorrelation of the particle velocity, for the approximate pseudo-Hessian).
-template <int TZ, bool STORE, bool RECORD, bool PML, bool EDGE, bool ACORR>
+template <int TZ, bool STORE, bool RECORD, bool PML, bool EDGE, bool ACORR, bool VTI>
 __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, int n, gfloat* seg, float* lds) {
   using T = StepTile<TZ>;
   constexpr int SR = T::SR, SC = T::SC, VR = T::VR, VC = T::VC, NS = T::NS;
@@ -508,7 +522,7 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
   //         phase, to bound the live registers) ----
   StrLoads SL[NSR];
 #pragma unroll
-  for (int k = 0; k < NSR; ++k) SL[k] = str_loads<PML, EDGE>(p, s, i0 + tyu + k * BZ, j0 + tx);
+  for (int k = 0; k < NSR; ++k) SL[k] = str_loads<PML, EDGE, VTI>(p, s, i0 + tyu + k * BZ, j0 + tx);
 #pragma unroll
   for (int k = 0; k < NSR; ++k) {
     const int i = i0 + tyu + k * BZ, j = j0 + tx;
@@ -521,7 +535,7 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
     const float pzx = (K1 * (X[VC] - X[0]) + K2 * (X[2 * VC] - X[-VC])) * s.rdz;
     const float pxz = (K1 * (Z[1] - Z[0]) + K2 * (Z[2] - Z[-1])) * s.rdx;
     const int so = (vr + 2) * SC + tx + 4;           // LDS sigma of the node
-    str_node<STORE, RECORD, PML>(p, s, i, j, n, SL[k], slot[k], pxx, pzz, pzx, pxz, SXX[so], SZZ[so], SXZ[so],
+    str_node<STORE, RECORD, PML, VTI>(p, s, i, j, n, SL[k], slot[k], pxx, pzz, pzx, pxz, SXX[so], SZZ[so], SXZ[so],
                                  f_xx, f_zz, f_xz);
   }
 }
@@ -530,7 +544,7 @@ __device__ __forceinline__ void fwd_step_tile(const Shot2D& s, int i0, int j0, i
 // Workgroup w takes schedule slot w: its tile and code path come in one scalar load (the
 // host classified the tile), so a workgroup starts its tile's loads after two dependent
 // scalar round trips (the slot, then the shot's descriptor).
-template <int TZ, bool STORE, bool RECORD, bool ACORR = false>
+template <int TZ, bool STORE, bool RECORD, bool ACORR, bool VTI>
 __global__ __launch_bounds__(BX * BZ) void k_fwd_step(STEP_PARAMS, int n, int kstore) {
   __shared__ float lds[StepTile<TZ>::LDS_FLOATS];
   const StepSlot slot = slots[blockIdx.x];
@@ -541,9 +555,9 @@ __global__ __launch_bounds__(BX * BZ) void k_fwd_step(STEP_PARAMS, int n, int ks
   // block-uniform branch: every thread reaches the barriers. CPML tiles: within 2 nodes of
   // a strip (velocity halo); edge tiles (grids whose strips are under 2 nodes wide): the
   // staged halo may leave the grid; every other tile's staged halo lies inside it.
-  if (slot.path == PATH_PML) fwd_step_tile<TZ, STORE, RECORD, true, true, ACORR>(s, i0, j0, n, seg, lds);
-  else if (slot.path == PATH_EDGE) fwd_step_tile<TZ, STORE, RECORD, false, true, ACORR>(s, i0, j0, n, seg, lds);
-  else fwd_step_tile<TZ, STORE, RECORD, false, false, ACORR>(s, i0, j0, n, seg, lds);
+  if (slot.path == PATH_PML) fwd_step_tile<TZ, STORE, RECORD, true, true, ACORR, VTI>(s, i0, j0, n, seg, lds);
+  else if (slot.path == PATH_EDGE) fwd_step_tile<TZ, STORE, RECORD, false, true, ACORR, VTI>(s, i0, j0, n, seg, lds);
+  else fwd_step_tile<TZ, STORE, RECORD, false, false, ACORR, VTI>(s, i0, j0, n, seg, lds);
 }
 
 // ------------------------------------------------------------------------------------
@@ -622,6 +636,7 @@ struct AdjPtrs {
   const gfloat *txx, *tzz, *txz, *ux, *uz;   // adjoint buffer (n + 1) & 1, padded plane origins
   gfloat *wtxx, *wtzz, *wtxz, *wux, *wuz;    // buffer n & 1
   const gfloat *lam, *mu, *rho;              // staged parameters, padded plane origins
+  const gfloat *c11, *c13;                   // VTI staged parameters (NULL: isotropic)
   const gfloat* rps;                         // adjoint memory variables of step n + 1 (see xv, zv)
   gfloat* wps;                               // and of step n
   const gfloat* prof;                        // CPML profiles (see xp, zp)
@@ -649,6 +664,8 @@ __device__ __forceinline__ AdjPtrs adj_ptrs(const Shot2D& s, int n, int kseg) {
   p.lam = s.lam - org;
   p.mu = s.mu - org;
   p.rho = s.rho - org;
+  p.c11 = s.c11 ? s.c11 - org : nullptr;
+  p.c13 = s.c13 ? s.c13 - org : nullptr;
   p.rps = s.pbx[prd][0];
   p.wps = s.pbx[pwr][0];
   p.prof = s.prof;
@@ -687,25 +704,27 @@ __device__ __forceinline__ UbLoads ub_loads(const AdjPtrs& p, const Shot2D& s, i
 
 // Inputs of one t_bar node (loads only).
 struct TbLoads {
-  float lam, mu, mu_x, mu_z, mu_xz;
-  float h0, h1, h3m, h3, h4m, h4, a0, a1, a2;   // imaging inputs
+  float lam, mu, mu_x, mu_z, mu_xz, c11, c13;
+  float h0, h1, h3m, h3, h4m, h4, a0, a1, a2, a3, a4;   // imaging inputs (a3, a4: VTI)
   float h2[4], c2[4];         // around the node's four shear nodes: stored h2 and how often
                               // the node's mu is used
 };
 
 // EDGE: the node may sit on the grid's first or clamped last row or column (tiles that
 // touch a CPML strip, or any tile without CPML); elsewhere every count below is 1.
-template <bool GRAD, bool PML, bool EDGE>
+template <bool GRAD, bool PML, bool EDGE, bool VTI>
 __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, int gi, int gj, bool first) {
   TbLoads L;
   const int ic = EDGE ? min(gi, p.nz - 1) : gi, jc = EDGE ? min(gj, p.nx - 1) : gj;
   const unsigned o = pofs(p, ic, jc);
+  L.c11 = VTI ? G(p.c11, o) : 0.0f;
+  L.c13 = VTI ? G(p.c13, o) : 0.0f;
   L.lam = G(p.lam, o);
   L.mu = G(p.mu, o);
   L.mu_x = G(p.mu + 1, o);
   L.mu_z = G(p.mu + p.ld, o);
   L.mu_xz = G(p.mu + p.ld + 1, o);
-  L.h0 = L.h1 = L.h3m = L.h3 = L.h4m = L.h4 = L.a0 = L.a1 = L.a2 = 0.0f;
+  L.h0 = L.h1 = L.h3m = L.h3 = L.h4m = L.h4 = L.a0 = L.a1 = L.a2 = L.a3 = L.a4 = 0.0f;
   if (GRAD) {
     const unsigned cc = (unsigned)(ic * s.cp + jc), cells = (unsigned)s.cells;
     L.h0 = GL(p.seg, cc);
@@ -738,12 +757,16 @@ __device__ __forceinline__ TbLoads tb_loads(const AdjPtrs& p, const Shot2D& s, i
       L.a0 = G(p.acc, cc);
       L.a1 = G(p.acc, cells + cc);
       L.a2 = G(p.acc, 2 * cells + cc);
+      if (VTI) {
+        L.a3 = G(p.acc, 3 * cells + cc);
+        L.a4 = G(p.acc, 4 * cells + cc);
+      }
     }
   }
   return L;
 }
 
-template <int TZ, bool GRAD, bool SRCADJ, bool PML, bool EDGE>
+template <int TZ, bool GRAD, bool SRCADJ, bool PML, bool EDGE, bool VTI>
 __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, int n, int kseg, bool first,
                                               float* lds) {
   using T = AdjTile<TZ>;
@@ -960,7 +983,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   //         issued here, after the velocity phase, to bound the live registers) ----
   TbLoads TL[NSR];
 #pragma unroll
-  for (int k = 0; k < NSR; ++k) TL[k] = tb_loads<GRAD, PML, EDGE>(p, s, i0 + tyu + k * BZ, j0 + tx, first);
+  for (int k = 0; k < NSR; ++k) TL[k] = tb_loads<GRAD, PML, EDGE, VTI>(p, s, i0 + tyu + k * BZ, j0 + tx, first);
 #pragma unroll
   for (int k = 0; k < NSR; ++k) {
     const int i = i0 + tyu + k * BZ, j = j0 + tx;
@@ -1000,12 +1023,13 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
         G(p.wps, zv(p, Z_XZ) + q) = G(p.prof, zp(p, 3) + (unsigned)i) * (r4 + dt * txz);
       }
     }
-    G(p.wtxx, o) = txx + (l2m * dsxx + lam * dszz);
-    G(p.wtzz, o) = tzz + (lam * dsxx + l2m * dszz);
+    const float c11 = VTI ? L.c11 : l2m, c13 = VTI ? L.c13 : lam;
+    G(p.wtxx, o) = txx + (c11 * dsxx + c13 * dszz);
+    G(p.wtzz, o) = tzz + (c13 * dsxx + l2m * dszz);
     G(p.wtxz, o) = txz + mxz * dsxz;
     if (GRAD) {
       const unsigned cc = (unsigned)(i * s.cp + j), cells = (unsigned)s.cells;
-      float e = (txx - tzz) * L.h1;
+      float e = VTI ? 0.0f : (txx - tzz) * L.h1;
       const int so = (vr + 2) * SC + tx + 4;   // LDS p_bar coordinates of the node
       const float rdt = 1.0f / dt;
       for (int q = 0; q < 4; ++q) {
@@ -1024,15 +1048,22 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
       r += c1 * UX[u0] * L.h3;
       r += c2 * UZ[u0 - VC] * L.h4m;
       r += c3 * UZ[u0] * L.h4;
-      G(p.acc, cc) = L.a0 + dt * (txx + tzz) * L.h0;
+      if (VTI) {  // sigma_bar = C^-1 t_bar on the normal block: (u, v) / det, det in h0, h1
+        const float u = l2m * txx - c13 * tzz, v = c11 * tzz - c13 * txx;
+        G(p.acc, cc) = L.a0 + dt * u * L.h0;                         // c11
+        G(p.acc, 3 * cells + cc) = L.a3 + dt * v * L.h1;             // c33
+        G(p.acc, 4 * cells + cc) = L.a4 + dt * (u * L.h1 + v * L.h0);  // c13
+      } else {
+        G(p.acc, cc) = L.a0 + dt * (txx + tzz) * L.h0;
+      }
       G(p.acc, cells + cc) = L.a1 + dt * e;
       G(p.acc, 2 * cells + cc) = L.a2 - dt * r;
     }
     if (SRCADJ && i == s.si && j == s.sj) {
       // sigma_bar at the source from t_bar of step n + 1: invert the 2x2 normal block and
       // the shear moduli of the four shear nodes around the source
-      const float det = (l2m - lam) * (l2m + lam);
-      const float sb0 = (l2m * txx - lam * tzz) / det, sb1 = (l2m * tzz - lam * txx) / det;
+      const float det = VTI ? c11 * l2m - c13 * c13 : (l2m - lam) * (l2m + lam);
+      const float sb0 = (l2m * txx - c13 * tzz) / det, sb1 = (c11 * tzz - c13 * txx) / det;
       float sb2 = 0.0f;
       for (int a = i - 1; a <= i; ++a) {
         for (int b = j - 1; b <= j; ++b) {
@@ -1049,7 +1080,7 @@ __device__ __forceinline__ void adj_step_tile(const Shot2D& s, int i0, int j0, i
   }
 }
 
-template <int TZ, bool GRAD, bool SRCADJ>
+template <int TZ, bool GRAD, bool SRCADJ, bool VTI>
 __global__ __launch_bounds__(BX * BZ) void k_adj_step(STEP_PARAMS, int n, int kseg, int first) {
   __shared__ float lds[AdjTile<TZ>::LDS_FLOATS];
   const StepSlot slot = slots[blockIdx.x];
@@ -1060,9 +1091,10 @@ __global__ __launch_bounds__(BX * BZ) void k_adj_step(STEP_PARAMS, int n, int ks
   // reach 4 nodes beyond the tile, so tiles within 4 nodes of a strip take the CPML path;
   // with strips at all four edges every other tile and its 4-node halo lie inside the
   // grid and skip the edge handling (only a grid without strips needs it there).
-  if (slot.path == PATH_PML) adj_step_tile<TZ, GRAD, SRCADJ, true, true>(s, i0, j0, n, kseg, first != 0, lds);
-  else if (slot.path == PATH_EDGE) adj_step_tile<TZ, GRAD, SRCADJ, false, true>(s, i0, j0, n, kseg, first != 0, lds);
-  else adj_step_tile<TZ, GRAD, SRCADJ, false, false>(s, i0, j0, n, kseg, first != 0, lds);
+  if (slot.path == PATH_PML) adj_step_tile<TZ, GRAD, SRCADJ, true, true, VTI>(s, i0, j0, n, kseg, first != 0, lds);
+  else if (slot.path == PATH_EDGE)
+    adj_step_tile<TZ, GRAD, SRCADJ, false, true, VTI>(s, i0, j0, n, kseg, first != 0, lds);
+  else adj_step_tile<TZ, GRAD, SRCADJ, false, false, VTI>(s, i0, j0, n, kseg, first != 0, lds);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1078,6 +1110,14 @@ __global__ __launch_bounds__(BX * BZ) void k_stage(BATCH_PARAMS) {
   const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
   const float mu = rho * vs * vs;
   const float lam = rho * vp * vp - 2.0f * mu;
+  // VTI (Thomsen eps, delta = eps / 2): c11 = c33 (1 + 2 eps),
+  // c13 = sqrt((c33 - mu)(c33 (1 + 2 delta) - mu)) - mu, from the FP32 c33 and mu in FP64
+  float c11 = 0.0f, c13 = 0.0f;
+  if (s.meps) {
+    const double c33 = (double)lam + 2.0 * (double)mu, eps = s.meps[mo], m = mu;
+    c11 = (float)(c33 * (1.0 + 2.0 * eps));
+    c13 = (float)(sqrt(fmax((c33 - m) * (c33 * (1.0 + eps) - m), 0.0)) - m);
+  }
   const long o = (long)i * s.ld + j;
   const bool xe = j == s.nx - 1, ze = i == s.nz - 1;
   for (int c = 0; c < 4; ++c) {
@@ -1087,6 +1127,10 @@ __global__ __launch_bounds__(BX * BZ) void k_stage(BATCH_PARAMS) {
     s.lam[oc] = lam;
     s.mu[oc] = mu;
     s.rho[oc] = rho;
+    if (s.meps) {
+      s.c11[oc] = c11;
+      s.c13[oc] = c13;
+    }
   }
 }
 
@@ -1106,13 +1150,29 @@ __global__ __launch_bounds__(BX * BZ) void k_chain_flush(BATCH_PARAMS) {
   const double vp = __builtin_nontemporal_load(s.mvp + mo), vs = __builtin_nontemporal_load(s.mvs + mo);
   const double rho = __builtin_nontemporal_load(s.mrho + mo);
   const double mu = rho * vs * vs;
-  const double gl = s.acc[cc];
-  const double gmu = gl + (mu > 0.0 ? (double)s.acc[s.cells + cc] / (mu * mu) : 0.0);
   gdouble* G0 = s.G + cc;
   gdouble* G1 = s.G + s.cells + cc;
   gdouble* G2 = s.G + 2 * s.cells + cc;
   const double g0 = __builtin_nontemporal_load(G0), g1 = __builtin_nontemporal_load(G1);
   const double g2 = __builtin_nontemporal_load(G2);
+  if (s.meps) {
+    // VTI at fixed eps: sums of c11, c33, c13 at the node; c13 = R - mu with
+    // R^2 = (c33 - mu)(c33 (1 + eps) - mu) moves with c33 and mu; the shear sum E / mu^2
+    // and the buoyancy sum as in the isotropic case
+    const double eps = __builtin_nontemporal_load(s.meps + mo);
+    const double c33 = rho * vp * vp, A = c33 - mu, B = c33 * (1.0 + eps) - mu, R = sqrt(fmax(A * B, 0.0));
+    const double d33 = R > 0.0 ? (B + A * (1.0 + eps)) / (2.0 * R) : 0.0;
+    const double dmu = (R > 0.0 ? -(A + B) / (2.0 * R) : 0.0) - 1.0;
+    const double a11 = s.acc[cc], a33 = s.acc[3 * s.cells + cc], a13 = s.acc[4 * s.cells + cc];
+    const double g33 = a33 + (1.0 + 2.0 * eps) * a11 + d33 * a13;
+    const double gm = (mu > 0.0 ? (double)s.acc[s.cells + cc] / (mu * mu) : 0.0) + dmu * a13;
+    __builtin_nontemporal_store(g0 + 2.0 * rho * vp * g33, G0);
+    __builtin_nontemporal_store(g1 + 2.0 * rho * vs * gm, G1);
+    __builtin_nontemporal_store(g2 + (vp * vp * g33 + vs * vs * gm + (double)s.acc[2 * s.cells + cc]), G2);
+    return;
+  }
+  const double gl = s.acc[cc];
+  const double gmu = gl + (mu > 0.0 ? (double)s.acc[s.cells + cc] / (mu * mu) : 0.0);
   __builtin_nontemporal_store(g0 + 2.0 * rho * vp * gl, G0);
   __builtin_nontemporal_store(g1 + 2.0 * rho * vs * (gmu - 2.0 * gl), G1);
   __builtin_nontemporal_store(g2 + ((vp * vp - 2.0 * vs * vs) * gl + vs * vs * gmu + (double)s.acc[2 * s.cells + cc]),
@@ -1179,54 +1239,69 @@ hipError_t launch_stage2d(const Batch2D& b, hipStream_t st) {
 
 namespace {
 
-template <int TZ>
+template <int TZ, bool VTI>
 void fwd_step_launch(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
   const dim3 g(b.step.n);
   if (kstore >= 0) {
-    if (record) k_fwd_step<TZ, true, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
-    else k_fwd_step<TZ, true, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
+    if (record) k_fwd_step<TZ, true, true, false, VTI><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
+    else k_fwd_step<TZ, true, false, false, VTI><<<g, block2d(), 0, st>>>(STEP_ARGS, n, kstore);
   } else {
-    if (record) k_fwd_step<TZ, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
-    else k_fwd_step<TZ, false, false><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
+    if (record) k_fwd_step<TZ, false, true, false, VTI><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
+    else k_fwd_step<TZ, false, false, false, VTI><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0);
   }
 }
 
-template <int TZ>
+template <int TZ, bool VTI>
 void adj_step_launch(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
   const dim3 g(b.adj_step.n);
-  if (grad) k_adj_step<TZ, true, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, k, first);
-  else if (srcadj) k_adj_step<TZ, false, true><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
-  else k_adj_step<TZ, false, false><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
+  if (grad) k_adj_step<TZ, true, false, VTI><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, k, first);
+  else if (srcadj) k_adj_step<TZ, false, true, VTI><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
+  else k_adj_step<TZ, false, false, VTI><<<g, block2d(), 0, st>>>(ADJSTEP_ARGS, n, 0, 0);
+}
+
+template <bool VTI>
+void fwd_acorr_launch(const Batch2D& b, int n, hipStream_t st) {
+  const dim3 g(b.step.n);
+  switch (b.fwd_rows) {
+    case 8: k_fwd_step<8, false, false, true, VTI><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
+    case 12: k_fwd_step<12, false, false, true, VTI><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
+    default: k_fwd_step<16, false, false, true, VTI><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
+  }
 }
 
 }  // namespace
 
 hipError_t launch_fwd_step(const Batch2D& b, int n, int kstore, bool record, hipStream_t st) {
   switch (b.fwd_rows) {
-    case 8: fwd_step_launch<8>(b, n, kstore, record, st); break;
-    case 12: fwd_step_launch<12>(b, n, kstore, record, st); break;
-    case 16: fwd_step_launch<16>(b, n, kstore, record, st); break;
+    case 8: b.vti ? fwd_step_launch<8, true>(b, n, kstore, record, st) : fwd_step_launch<8, false>(b, n, kstore, record, st); break;
+    case 12: b.vti ? fwd_step_launch<12, true>(b, n, kstore, record, st) : fwd_step_launch<12, false>(b, n, kstore, record, st); break;
+    case 16: b.vti ? fwd_step_launch<16, true>(b, n, kstore, record, st) : fwd_step_launch<16, false>(b, n, kstore, record, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_fwd_acorr(const Batch2D& b, int n, hipStream_t st) {
-  const dim3 g(b.step.n);
-  switch (b.fwd_rows) {
-    case 8: k_fwd_step<8, false, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
-    case 12: k_fwd_step<12, false, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
-    case 16: k_fwd_step<16, false, false, true><<<g, block2d(), 0, st>>>(STEP_ARGS, n, 0); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (b.fwd_rows != 8 && b.fwd_rows != 12 && b.fwd_rows != 16) return hipErrorInvalidValue;
+  if (b.vti) fwd_acorr_launch<true>(b, n, st);
+  else fwd_acorr_launch<false>(b, n, st);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_step(const Batch2D& b, int n, int k, bool grad, bool first, bool srcadj, hipStream_t st) {
   switch (b.adj_rows) {
-    case 8: adj_step_launch<8>(b, n, k, grad, first, srcadj, st); break;
-    case 12: adj_step_launch<12>(b, n, k, grad, first, srcadj, st); break;
-    case 16: adj_step_launch<16>(b, n, k, grad, first, srcadj, st); break;
+    case 8:
+      b.vti ? adj_step_launch<8, true>(b, n, k, grad, first, srcadj, st)
+            : adj_step_launch<8, false>(b, n, k, grad, first, srcadj, st);
+      break;
+    case 12:
+      b.vti ? adj_step_launch<12, true>(b, n, k, grad, first, srcadj, st)
+            : adj_step_launch<12, false>(b, n, k, grad, first, srcadj, st);
+      break;
+    case 16:
+      b.vti ? adj_step_launch<16, true>(b, n, k, grad, first, srcadj, st)
+            : adj_step_launch<16, false>(b, n, k, grad, first, srcadj, st);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -41,7 +41,7 @@ class Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("nz", ctypes.c_int), ("ny", ctypes.c_int), ("nx", ctypes.c_int),
                 ("dz", ctypes.c_float), ("dy", ctypes.c_float), ("dx", ctypes.c_float), ("dt", ctypes.c_float),
                 ("nt", ctypes.c_int), ("npml", ctypes.c_int), ("pml_R", ctypes.c_float),
-                ("pml_f0", ctypes.c_float), ("vp_max", ctypes.c_float)]
+                ("pml_f0", ctypes.c_float), ("vp_max", ctypes.c_float), ("eps", ctypes.c_void_p)]
 
 
 class _ShotC(ctypes.Structure):
@@ -101,14 +101,23 @@ class Shot:
                       int(self.gauge), int(self.decim), int(bool(self.rate)))
 
 
-def make_grid(nz, nx, dz, dx, dt, nt, npml=0, pml_R=1e-3, pml_f0=10.0, vp_max=0.0) -> Grid:
-    return Grid(2, int(nz), 1, int(nx), float(dz), 1.0, float(dx), float(dt), int(nt), int(npml),
-                float(pml_R), float(pml_f0), float(vp_max))
+def make_grid(nz, nx, dz, dx, dt, nt, npml=0, pml_R=1e-3, pml_f0=10.0, vp_max=0.0, eps=None) -> Grid:
+    """2D grid; eps: an FP32 device tensor [nz][nx] of Thomsen epsilon for a VTI medium
+    (delta = eps / 2), kept alive by the grid, or None (isotropic)."""
+    g = Grid(2, int(nz), 1, int(nx), float(dz), 1.0, float(dx), float(dt), int(nt), int(npml),
+             float(pml_R), float(pml_f0), float(vp_max), None)
+    if eps is not None:
+        _f32(eps, "eps")
+        if tuple(eps.shape) != (int(nz), int(nx)) or not eps.is_contiguous():
+            raise ValueError("eps must be a contiguous [nz][nx] tensor")
+        g.eps = eps.data_ptr()
+        g._eps_ref = eps
+    return g
 
 
 def make_grid3d(nz, ny, nx, dz, dy, dx, dt, nt, npml=0, pml_R=1e-3, pml_f0=10.0, vp_max=0.0) -> Grid:
     return Grid(3, int(nz), int(ny), int(nx), float(dz), float(dy), float(dx), float(dt), int(nt), int(npml),
-                float(pml_R), float(pml_f0), float(vp_max))
+                float(pml_R), float(pml_f0), float(vp_max), None)
 
 
 def n_components(grid: Grid) -> int:

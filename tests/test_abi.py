@@ -251,3 +251,18 @@ def test_bspline_arguments(efwi):
         assert efwi._lib.efwi_bspline_expand(*args, fake, fake, None) == efwi.E_INVAL
         assert efwi._lib.efwi_bspline_adjoint(*args, fake, fake, None) == efwi.E_INVAL
     assert efwi._lib.efwi_bspline_expand(10, 10, 1, 1, 1, None, fake, None) == efwi.E_INVAL
+
+
+def test_vti_is_2d_only(efwi):
+    """A VTI medium (grid.eps set) is refused on a 3D grid before any device access."""
+    g3 = efwi.make_grid3d(40, 40, 40, 5.0, 5.0, 5.0, 0.5e-3, 50, 8, 1e-3, 30.0, 4500.0)
+    g3.eps = 256
+    shot = efwi.Shot(20, 20, [21], [25], src_iy=20, ch_iy=[20])
+    arr = (efwi._ShotC * 1)(shot.c_struct())
+    assert efwi._lib.efwi_validate(ctypes.byref(g3), 1, arr) == efwi.E_UNSUPPORTED
+    g2 = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+    sh2 = efwi.Shot(50, 100, [51], [120])
+    a2 = (efwi._ShotC * 1)(sh2.c_struct())
+    iso = efwi._lib.efwi_workspace_size(efwi.WS_GRADIENT, ctypes.byref(g2), 1, a2)
+    g2.eps = 256
+    assert efwi._lib.efwi_workspace_size(efwi.WS_GRADIENT, ctypes.byref(g2), 1, a2) > iso
