@@ -26,6 +26,8 @@ resident in HBM before the timed region. The JSON line also carries:
   time steps), in the same unit;
 * path: the whole step's algorithmic bytes (168 B per cell-step plus 52 B per recomputed
   cell-step) over the step time; each checkpointed form carries the same as path_frac.
+* forms.vti_1shot: one shot of the workload in a VTI medium (Thomsen eps, delta = eps / 2),
+  whole history, timed once, with its path_frac.
 * forms.precision_3d_sample: one shot of the 3D precision workload (300 x 400 x 400) for
   200 of its 3000 steps with sqrt(nt) FP16 checkpoints, timed once, with its path_frac.
 * extension_ops: the zones of influence (eq.(10)) of the 20 sources and the final model
@@ -248,6 +250,35 @@ def extension_ops(efwi, torch, grid, w, m_ext, src, dev, ph_steps=200):
     return out
 
 
+def vti_shot_form(efwi, inputs, torch, dev, w, m_start, src, d_obs_0):
+    """One shot of the plain workload (1000 x 3000, nt = 4000, whole history) in a VTI medium
+    (Thomsen eps 0.1 above the reservoir, 0.6 in it and 0.3 below, smoothed; delta = eps / 2),
+    observed data those of the isotropic medium, timed once after one untimed call.
+    path_frac: 200 B per cell-step (the isotropic 168 plus c11, c13 read in both steps and two
+    more imaging sums read and written) over the time, against 8 TB/s."""
+    from scipy.ndimage import gaussian_filter
+    nz, nx = w.nz, w.nx
+    i = np.arange(nz)
+    col = np.where(i < nz // 2 - 3, 0.1, np.where(i < nz // 2 + 3, 0.6, 0.3))
+    eps = torch.tensor(np.repeat(gaussian_filter(col, 2.0)[:, None], nx, axis=1).astype(np.float32), device=dev)
+    vmax = 1.01 * float((m_start[0] * torch.sqrt(1.0 + 2.0 * eps)).max())   # horizontal P speed bound
+    grid = efwi.make_grid(nz, nx, w.dz, w.dx, w.dt, w.nt, w.npml, w.pml_R, w.f0, vmax, eps=eps)
+    s = w.shots[0]
+    shot = efwi.Shot(s.src_iz, s.src_ix, s.ch_iz, s.ch_ix, ckpt_interval=w.nt)
+    ws = efwi.workspace(efwi.workspace_size(efwi.WS_GRADIENT, grid, [shot]), dev)
+    efwi.shot_gradient(grid, shot, m_start, src[0], d_obs_0, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, _ = efwi.shot_gradient(grid, shot, m_start, src[0], d_obs_0, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gcell = nz * nx * w.nt / dt / 1e9
+    out = {"shots": 1, "ms": round(dt * 1e3, 1), "gcell_per_s": round(gcell, 3), "bytes_per_cell_step": 200,
+           "path_frac": round(200.0 * gcell / HBM_PEAK_GBS, 4), "finite": bool(torch.isfinite(g).all())}
+    del ws, g
+    return out
+
+
 def precision_3d_sample(efwi, inputs, torch, dev, nt=200):
     """One shot of the 3D precision workload on its full 300 x 400 x 400 grid (5 m, CPML 20,
     2000 DAS channels on two wells, six-component moment tensor), nt steps of the 3000 with
@@ -300,6 +331,7 @@ def main():  # noqa: C901
     ap.add_argument("--no-sqrt", action="store_true", help="skip the sqrt(nt)-checkpoint form")
     ap.add_argument("--no-compressed", action="store_true", help="skip the FP16/BF16-checkpoint forms")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 64-shot uneven-window batched form")
+    ap.add_argument("--no-vti", action="store_true", help="skip the one-shot VTI form")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--no-extension-ops", action="store_true", help="skip timing the ZOI and final-model kernels")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D precision-workload sample")
@@ -472,6 +504,11 @@ def main():  # noqa: C901
 
     if not args.no_uneven:
         forms["batched_uneven_64"] = uneven_batched_form(efwi, inputs, torch, dev, grid, nt, log)
+
+    if not args.no_vti:
+        nch0 = len(w.shots[0].ch_ix)
+        forms["vti_1shot"] = vti_shot_form(efwi, inputs, torch, dev, w, m_start, src, d_obs[:nch0 * nt].reshape(nch0, nt))
+        log(f"VTI form done: {forms['vti_1shot']}")
 
     if not args.no_3d:
         forms["precision_3d_sample"] = precision_3d_sample(efwi, inputs, torch, dev)
