@@ -69,10 +69,10 @@ KERNEL_BYTES = {"fwd_step": (52, 72), "adj_step": (96, 96)}
 # kernels on this grid only.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 MEASURED_TRAFFIC = {
-    "adj_step": {"cells": 3_000_000, "kib": {8: (108323.2, 99081.7), 12: (109470.3, 99023.7),
-                                             16: (110520.7, 98996.5)}},
-    "fwd_step": {"cells": 3_000_000, "kib": {8: (54580.6, 122429.6), 12: (55684.7, 122444.2),
-                                             16: (56573.6, 122453.1)}},
+    "adj_step": {"cells": 3_000_000, "kib": {8: (108335.4, 99086.1), 12: (109512.9, 99026.9),
+                                             16: (110407.7, 98984.8)}},
+    "fwd_step": {"cells": 3_000_000, "kib": {8: (54604.5, 122430.2), 12: (55683.2, 122443.6),
+                                             16: (56538.1, 122455.1)}},
 }
 
 
