@@ -507,7 +507,7 @@ def main():  # noqa: C901
 
     if not args.no_vti:
         nch0 = len(w.shots[0].ch_ix)
-        forms["vti_1shot"] = vti_shot_form(efwi, inputs, torch, dev, w, m_start, src, d_obs[:nch0 * nt].reshape(nch0, nt))
+        forms["vti_1shot"] = vti_shot_form(efwi, inputs, torch, dev, w, m_start, src, d_obs[:nch0].contiguous())
         log(f"VTI form done: {forms['vti_1shot']}")
 
     if not args.no_3d:
