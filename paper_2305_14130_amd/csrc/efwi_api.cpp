@@ -985,7 +985,7 @@ Plan3D plan3d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.nt = g.nt;
   p.nch = s.nch;
   p.nslots = count_rows3(s, p.w);
-  p.ntiles = p.nz * ((p.ny + 3) / 4) * ((p.nx + 63) / 64);
+  p.ntiles = tiles3(p.nz, p.ny, p.nx);
   p.L = interval_of(g, s);
   p.nseg = (g.nt + p.L - 1) / p.L;
   const long xs = (long)p.nz * p.ny * 2 * p.P, ys = (long)p.nz * 2 * p.P * p.nx, zs = (long)2 * p.P * p.ny * p.nx;
@@ -1175,12 +1175,14 @@ efwi_status setup_wave3(const efwi_grid& g, const efwi_shot* shots, const std::v
     const Plan3D& p = wv.plans[k];
     const efwi_shot& s = shots[first + k];
     tfirst[k] = t;
-    const int ntx = (p.nx + 63) / 64, nty = (p.ny + 3) / 4;
     for (int q = 0; q < p.ntiles; ++q) {
       tshot[t++] = k;
-      const int i = q / (ntx * nty), rem = q % (ntx * nty), k0 = (rem / ntx) * 4, j0 = (rem % ntx) * 64, pad = 2;
-      const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + 63 + pad >= p.nx - p.P) || (k0 - pad < p.P) ||
-                                   (k0 + 3 + pad >= p.ny - p.P) || (i - pad < p.P) || (i + pad >= p.nz - p.P));
+      int i, k0, j0;
+      tile3_coords(q, p.nz, p.nx, i, k0, j0);
+      const int pad = 2;
+      const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + TILE3_X - 1 + pad >= p.nx - p.P) || (k0 - pad < p.P) ||
+                                   (k0 + TILE3_Y - 1 + pad >= p.ny - p.P) || (i - pad < p.P) ||
+                                   (i + pad >= p.nz - p.P));
       weight.push_back(pml ? ADJ3_W_PML : ADJ3_W_INT);
     }
     build_tables3(g, s, p, blob.data() + off_tab);

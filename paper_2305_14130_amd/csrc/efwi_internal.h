@@ -139,6 +139,22 @@ inline bool valid_tile_rows(int r) { return r == 8 || r == 12 || r == 16; }
 
 // Number of XCDs the hardware deals workgroups to, round robin.
 constexpr int NUM_XCD = 8;
+
+// 3D tiles: TILE3_X columns (x) by TILE3_Y rows (y) of one z plane, covered by a workgroup
+// of TILE3_X x TILE3_TY threads (each thread takes every TILE3_TY-th row). A shot's tiles
+// are listed by y band (slowest), then z plane, then x block, so consecutive tiles march
+// down z through one band and the z neighbours of a tile were touched a few tiles earlier.
+constexpr int TILE3_X = 64, TILE3_Y = 16, TILE3_TY = 4;
+__host__ __device__ inline int tiles3(int nz, int ny, int nx) {
+  return nz * ((ny + TILE3_Y - 1) / TILE3_Y) * ((nx + TILE3_X - 1) / TILE3_X);
+}
+__host__ __device__ inline void tile3_coords(int local, int nz, int nx, int& i, int& k0, int& j0) {
+  const int ntx = (nx + TILE3_X - 1) / TILE3_X, per_band = nz * ntx;
+  const int band = local / per_band, rem = local - band * per_band;
+  i = rem / ntx;
+  j0 = (rem - i * ntx) * TILE3_X;
+  k0 = band * TILE3_Y;
+}
 // Per-step bytes of the shots advanced together in one wave of a batch (3/4 of the
 // 256 MB Infinity Cache of an MI355X).
 constexpr size_t WAVE_CACHE_BYTES = (size_t)192 << 20;

@@ -29,7 +29,7 @@ namespace {
 
 constexpr float K1 = 1.125f;
 constexpr float K2 = -0.041666666666666664f;
-constexpr int TX = 64, TY = 4;
+constexpr int TX = TILE3_X, TY = TILE3_TY;
 
 // Strip slots. x-strips: vx(D+x sxx) vy(D-x sxy) vz(D-x sxz) pxx(D-x vx) sxy(D+x vy) sxz(D+x vz)
 enum { XS_VX = 0, XS_VY, XS_VZ, XS_PXX, XS_SXY, XS_SXZ };
@@ -58,7 +58,7 @@ __device__ __forceinline__ long zq(const Shot3D& s, int sz, int k, int j) { retu
 __device__ __forceinline__ bool tile_in_pml(const Shot3D& s, int i, int k0, int j0, int pad) {
   if (s.P <= 0) return false;
   return (j0 - pad < s.P) || (j0 + TX - 1 + pad >= s.nx - s.P) || (k0 - pad < s.P) ||
-         (k0 + TY - 1 + pad >= s.ny - s.P) || (i - pad < s.P) || (i + pad >= s.nz - s.P);
+         (k0 + TILE3_Y - 1 + pad >= s.ny - s.P) || (i - pad < s.P) || (i + pad >= s.nz - s.P);
 }
 
 // Which axes' CPML strips a tile's cells (widened by pad on every side) reach: bit 0 x,
@@ -66,7 +66,7 @@ __device__ __forceinline__ bool tile_in_pml(const Shot3D& s, int i, int k0, int 
 __device__ __forceinline__ int pml_axes(const Shot3D& s, int i, int k0, int j0, int pad) {
   if (s.P <= 0) return 0;
   const bool x = (j0 - pad < s.P) || (j0 + TX - 1 + pad >= s.nx - s.P);
-  const bool y = (k0 - pad < s.P) || (k0 + TY - 1 + pad >= s.ny - s.P);
+  const bool y = (k0 - pad < s.P) || (k0 + TILE3_Y - 1 + pad >= s.ny - s.P);
   const bool z = (i - pad < s.P) || (i + pad >= s.nz - s.P);
   return (x ? 1 : 0) | (y ? 2 : 0) | (z ? 4 : 0);
 }
@@ -82,30 +82,28 @@ __device__ __forceinline__ int pml_axes(const Shot3D& s, int i, int k0, int j0, 
     default: CALL(true, true, true); break;   \
   }
 
-// Tile list per shot: z plane, y band, x block (x fastest). Schedule as in 2D.
+// Tile of schedule slot blockIdx.x (tile order: tile3_coords). Schedule as in 2D.
 __device__ __forceinline__ bool tile3(const int* __restrict__ sched, const int* __restrict__ tile_shot,
                                       const int* __restrict__ tile_first, const Shot3D* __restrict__ shots, int& sh,
                                       int& i, int& k0, int& j0) {
   const int t = sched[blockIdx.x];
   if (t < 0) return false;
   sh = tile_shot[t];
-  const int local = t - tile_first[sh];
-  const int ntx = (shots[sh].nx + TX - 1) / TX, nty = (shots[sh].ny + TY - 1) / TY;
-  i = local / (ntx * nty);
-  const int rem = local % (ntx * nty);
-  k0 = (rem / ntx) * TY;
-  j0 = (rem % ntx) * TX;
+  tile3_coords(t - tile_first[sh], shots[sh].nz, shots[sh].nx, i, k0, j0);
   return true;
 }
 
 #define PARAMS3                                                                                      \
   const Shot3D* __restrict__ shots, const int* __restrict__ tile_shot, const int* __restrict__ tile_first, \
       const int* __restrict__ sched
+// The tile, then a loop over the thread's rows k of it: the kernel body that follows is the
+// loop's body (a row beyond the grid ends the thread, as every later row is beyond it too).
 #define TILE3()                                                                                       \
   int sh_, i, k0, j0;                                                                                  \
   if (!tile3(sched, tile_shot, tile_first, shots, sh_, i, k0, j0)) return;                            \
   const Shot3D& s = shots[sh_];                                                                        \
-  const int j = j0 + threadIdx.x, k = k0 + threadIdx.y
+  const int j = j0 + threadIdx.x;                                                                      \
+  _Pragma("unroll 1") for (int k = k0 + (int)threadIdx.y; k < k0 + TILE3_Y; k += TILE3_TY)
 
 // Streaming (non-temporal) accesses of the history: written once per forward step, read
 // once in the reverse sweep, so they should not displace the wavefields in the caches.
@@ -179,11 +177,12 @@ __device__ __forceinline__ void fwd_vel3(const Shot3D& s, int i, int k, int j, g
 
 template <bool STORE>
 __global__ __launch_bounds__(TX * TY) void k3_fwd_vel(PARAMS3, int kstore) {
-  TILE3();
-  if (k >= s.ny || j >= s.nx) return;
-  gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG3 * s.cells : nullptr;
-  if (tile_in_pml(s, i, k0, j0, 0)) fwd_vel3<STORE, true>(s, i, k, j, seg);
-  else fwd_vel3<STORE, false>(s, i, k, j, seg);
+  TILE3() {
+    if (k >= s.ny || j >= s.nx) return;
+    gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG3 * s.cells : nullptr;
+    if (tile_in_pml(s, i, k0, j0, 0)) fwd_vel3<STORE, true>(s, i, k, j, seg);
+    else fwd_vel3<STORE, false>(s, i, k, j, seg);
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -279,11 +278,12 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
 
 template <bool STORE, bool RECORD>
 __global__ __launch_bounds__(TX * TY) void k3_fwd_str(PARAMS3, int n, int kstore) {
-  TILE3();
-  if (k >= s.ny || j >= s.nx) return;
-  gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG3 * s.cells : nullptr;
-  if (tile_in_pml(s, i, k0, j0, 0)) fwd_str3<STORE, RECORD, true>(s, i, k, j, n, seg);
-  else fwd_str3<STORE, RECORD, false>(s, i, k, j, n, seg);
+  TILE3() {
+    if (k >= s.ny || j >= s.nx) return;
+    gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG3 * s.cells : nullptr;
+    if (tile_in_pml(s, i, k0, j0, 0)) fwd_str3<STORE, RECORD, true>(s, i, k, j, n, seg);
+    else fwd_str3<STORE, RECORD, false>(s, i, k, j, n, seg);
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -436,12 +436,13 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
 
 template <bool GRAD, bool SRCADJ>
 __global__ __launch_bounds__(TX * TY) void k3_adj_vel(PARAMS3, int n, int kseg, int first) {
-  TILE3();
-  if (k >= s.ny || j >= s.nx) return;
-  const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
+  TILE3() {
+    if (k >= s.ny || j >= s.nx) return;
+    const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
 #define CALL(X, Y, Z) adj_vel3<GRAD, SRCADJ, X, Y, Z>(s, i, k, j, n, seg, first != 0)
-  DISPATCH_AXES(pml_axes(s, i, k0, j0, 2), CALL);
+    DISPATCH_AXES(pml_axes(s, i, k0, j0, 2), CALL);
 #undef CALL
+  }
 }
 
 // Transposed velocity sub-step: u_bar -> t_bar.
@@ -518,111 +519,115 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
 
 template <bool GRAD>
 __global__ __launch_bounds__(TX * TY) void k3_adj_str(PARAMS3, int n, int kseg, int first) {
-  TILE3();
-  if (k >= s.ny || j >= s.nx) return;
-  const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
+  TILE3() {
+    if (k >= s.ny || j >= s.nx) return;
+    const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
 #define CALL(X, Y, Z) adj_str3<GRAD, X, Y, Z>(s, i, k, j, n, seg, first != 0)
-  DISPATCH_AXES(pml_axes(s, i, k0, j0, 2), CALL);
+    DISPATCH_AXES(pml_axes(s, i, k0, j0, 2), CALL);
 #undef CALL
+  }
 }
 
 // ------------------------------------------------------------------------------------
 // Staging: (Vp, Vs, rho) -> lambda + 2 mu, lambda, harmonic shear moduli, buoyancies.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(TX * TY) void k3_stage(PARAMS3) {
-  TILE3();
-  if (k >= s.ny || j >= s.nx) return;
-  const int ip = min(i + 1, s.nz - 1), kp = min(k + 1, s.ny - 1), jp = min(j + 1, s.nx - 1);
-  auto at = [&](const gfloat* f, int a, int b, int c) { return f[(long)a * s.mplanestride + (long)b * s.mld + c]; };
-  auto mu_at = [&](int a, int b, int c) {
-    const float v = at(s.mvs, a, b, c);
-    return at(s.mrho, a, b, c) * v * v;
-  };
-  auto harm = [](float a, float b, float c, float d) {
-    return (a > 0.f && b > 0.f && c > 0.f && d > 0.f) ? 4.0f / (1.0f / a + 1.0f / b + 1.0f / c + 1.0f / d) : 0.0f;
-  };
-  const float vp = at(s.mvp, i, k, j), rho = at(s.mrho, i, k, j);
-  const float mu = mu_at(i, k, j);
-  const long o = (long)i * s.pz + (long)k * s.ld + j;
-  const float l2m = rho * vp * vp;
-  s.l2m[o] = l2m;
-  s.lam[o] = l2m - 2.0f * mu;
-  s.muxy[o] = harm(mu, mu_at(i, kp, j), mu_at(i, k, jp), mu_at(i, kp, jp));
-  s.muxz[o] = harm(mu, mu_at(ip, k, j), mu_at(i, k, jp), mu_at(ip, k, jp));
-  s.muyz[o] = harm(mu, mu_at(ip, k, j), mu_at(i, kp, j), mu_at(ip, kp, j));
-  s.bx[o] = 2.0f / (rho + at(s.mrho, i, k, jp));
-  s.by[o] = 2.0f / (rho + at(s.mrho, i, kp, j));
-  s.bz[o] = 2.0f / (rho + at(s.mrho, ip, k, j));
+  TILE3() {
+    if (k >= s.ny || j >= s.nx) return;
+    const int ip = min(i + 1, s.nz - 1), kp = min(k + 1, s.ny - 1), jp = min(j + 1, s.nx - 1);
+    auto at = [&](const gfloat* f, int a, int b, int c) { return f[(long)a * s.mplanestride + (long)b * s.mld + c]; };
+    auto mu_at = [&](int a, int b, int c) {
+      const float v = at(s.mvs, a, b, c);
+      return at(s.mrho, a, b, c) * v * v;
+    };
+    auto harm = [](float a, float b, float c, float d) {
+      return (a > 0.f && b > 0.f && c > 0.f && d > 0.f) ? 4.0f / (1.0f / a + 1.0f / b + 1.0f / c + 1.0f / d) : 0.0f;
+    };
+    const float vp = at(s.mvp, i, k, j), rho = at(s.mrho, i, k, j);
+    const float mu = mu_at(i, k, j);
+    const long o = (long)i * s.pz + (long)k * s.ld + j;
+    const float l2m = rho * vp * vp;
+    s.l2m[o] = l2m;
+    s.lam[o] = l2m - 2.0f * mu;
+    s.muxy[o] = harm(mu, mu_at(i, kp, j), mu_at(i, k, jp), mu_at(i, kp, jp));
+    s.muxz[o] = harm(mu, mu_at(ip, k, j), mu_at(i, k, jp), mu_at(ip, k, jp));
+    s.muyz[o] = harm(mu, mu_at(ip, k, j), mu_at(i, kp, j), mu_at(ip, kp, j));
+    s.bx[o] = 2.0f / (rho + at(s.mrho, i, k, jp));
+    s.by[o] = 2.0f / (rho + at(s.mrho, i, kp, j));
+    s.bz[o] = 2.0f / (rho + at(s.mrho, ip, k, j));
+  }
 }
 
 // ------------------------------------------------------------------------------------
 // Chain rule of one block of FP32 imaging sums into the FP64 (Vp, Vs, rho) gradient.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(TX * TY) void k3_chain_flush(PARAMS3) {
-  TILE3();
-  if (k >= s.ny || j >= s.nx) return;
-  const long cs = s.cells;
-  auto ci = [&](int a, int b, int c) { return ((long)a * s.ny + b) * s.cp + c; };
-  auto pi = [&](int a, int b, int c) { return (long)a * s.pz + (long)b * s.ld + c; };
-  const long cc = ci(i, k, j);
-  const long mo = (long)i * s.mplanestride + (long)k * s.mld + j;
-  const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
-  const double mu = (double)(rho * vs * vs);
-  const double gl = s.acc[cc];
-  double gmu = 2.0 / 3.0 * gl + (double)s.acc[cs + cc];
-  const int NZ = s.nz - 1, NY = s.ny - 1, NX = s.nx - 1;
-  // shear node (a, b, c) of each type and its four clamped corners
-  for (int t = 0; t < 3; ++t) {
-    const gfloat* mod = t == 0 ? s.muxy : (t == 1 ? s.muxz : s.muyz);
-    const gfloat* g = s.acc + (2 + t) * cs;
-    for (int q = 0; q < 4; ++q) {
-      const int d1 = q & 1, d2 = q >> 1;
-      int a = i, b = k, c = j;
-      if (t == 0) { b -= d1; c -= d2; }       // xy: (i, k-1..k, j-1..j)
-      else if (t == 1) { a -= d1; c -= d2; }  // xz: (i-1..i, k, j-1..j)
-      else { a -= d1; b -= d2; }              // yz: (i-1..i, k-1..k, j)
-      if (a < 0 || b < 0 || c < 0) continue;
-      int mult = 0;
-      for (int e = 0; e < 4; ++e) {
-        const int e1 = e & 1, e2 = e >> 1;
-        int aa = a, bb = b, cc2 = c;
-        if (t == 0) { bb = min(b + e1, NY); cc2 = min(c + e2, NX); }
-        else if (t == 1) { aa = min(a + e1, NZ); cc2 = min(c + e2, NX); }
-        else { aa = min(a + e1, NZ); bb = min(b + e2, NY); }
-        mult += (aa == i && bb == k && cc2 == j);
+  TILE3() {
+    if (k >= s.ny || j >= s.nx) return;
+    const long cs = s.cells;
+    auto ci = [&](int a, int b, int c) { return ((long)a * s.ny + b) * s.cp + c; };
+    auto pi = [&](int a, int b, int c) { return (long)a * s.pz + (long)b * s.ld + c; };
+    const long cc = ci(i, k, j);
+    const long mo = (long)i * s.mplanestride + (long)k * s.mld + j;
+    const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
+    const double mu = (double)(rho * vs * vs);
+    const double gl = s.acc[cc];
+    double gmu = 2.0 / 3.0 * gl + (double)s.acc[cs + cc];
+    const int NZ = s.nz - 1, NY = s.ny - 1, NX = s.nx - 1;
+    // shear node (a, b, c) of each type and its four clamped corners
+    for (int t = 0; t < 3; ++t) {
+      const gfloat* mod = t == 0 ? s.muxy : (t == 1 ? s.muxz : s.muyz);
+      const gfloat* g = s.acc + (2 + t) * cs;
+      for (int q = 0; q < 4; ++q) {
+        const int d1 = q & 1, d2 = q >> 1;
+        int a = i, b = k, c = j;
+        if (t == 0) { b -= d1; c -= d2; }       // xy: (i, k-1..k, j-1..j)
+        else if (t == 1) { a -= d1; c -= d2; }  // xz: (i-1..i, k, j-1..j)
+        else { a -= d1; b -= d2; }              // yz: (i-1..i, k-1..k, j)
+        if (a < 0 || b < 0 || c < 0) continue;
+        int mult = 0;
+        for (int e = 0; e < 4; ++e) {
+          const int e1 = e & 1, e2 = e >> 1;
+          int aa = a, bb = b, cc2 = c;
+          if (t == 0) { bb = min(b + e1, NY); cc2 = min(c + e2, NX); }
+          else if (t == 1) { aa = min(a + e1, NZ); cc2 = min(c + e2, NX); }
+          else { aa = min(a + e1, NZ); bb = min(b + e2, NY); }
+          mult += (aa == i && bb == k && cc2 == j);
+        }
+        if (mult == 0) continue;
+        const float m = mod[pi(a, b, c)];
+        if (m > 0.0f) gmu += (double)mult * g[ci(a, b, c)] * ((double)m * m / (4.0 * mu * mu));
       }
-      if (mult == 0) continue;
-      const float m = mod[pi(a, b, c)];
-      if (m > 0.0f) gmu += (double)mult * g[ci(a, b, c)] * ((double)m * m / (4.0 * mu * mu));
     }
-  }
-  double grho = 0.0;
-  for (int t = 0; t < 3; ++t) {
-    const gfloat* bb = t == 0 ? s.bx : (t == 1 ? s.by : s.bz);
-    const gfloat* g = s.acc + (5 + t) * cs;
-    for (int d = -1; d <= 0; ++d) {
-      int a = i, b = k, c = j;
-      int mult;
-      if (t == 0) { c += d; if (c < 0) continue; mult = (c == j) + (min(c + 1, NX) == j); }
-      else if (t == 1) { b += d; if (b < 0) continue; mult = (b == k) + (min(b + 1, NY) == k); }
-      else { a += d; if (a < 0) continue; mult = (a == i) + (min(a + 1, NZ) == i); }
-      if (mult == 0) continue;
-      const double bv = bb[pi(a, b, c)];
-      grho -= 0.5 * mult * g[ci(a, b, c)] * bv * bv;
+    double grho = 0.0;
+    for (int t = 0; t < 3; ++t) {
+      const gfloat* bb = t == 0 ? s.bx : (t == 1 ? s.by : s.bz);
+      const gfloat* g = s.acc + (5 + t) * cs;
+      for (int d = -1; d <= 0; ++d) {
+        int a = i, b = k, c = j;
+        int mult;
+        if (t == 0) { c += d; if (c < 0) continue; mult = (c == j) + (min(c + 1, NX) == j); }
+        else if (t == 1) { b += d; if (b < 0) continue; mult = (b == k) + (min(b + 1, NY) == k); }
+        else { a += d; if (a < 0) continue; mult = (a == i) + (min(a + 1, NZ) == i); }
+        if (mult == 0) continue;
+        const double bv = bb[pi(a, b, c)];
+        grho -= 0.5 * mult * g[ci(a, b, c)] * bv * bv;
+      }
     }
+    const double dvp = vp, dvs = vs, drho = rho;
+    s.G[cc] += 2.0 * drho * dvp * gl;
+    s.G[cs + cc] += 2.0 * drho * dvs * (gmu - 2.0 * gl);
+    s.G[2 * cs + cc] += (dvp * dvp - 2.0 * dvs * dvs) * gl + dvs * dvs * gmu + grho;
   }
-  const double dvp = vp, dvs = vs, drho = rho;
-  s.G[cc] += 2.0 * drho * dvp * gl;
-  s.G[cs + cc] += 2.0 * drho * dvs * (gmu - 2.0 * gl);
-  s.G[2 * cs + cc] += (dvp * dvp - 2.0 * dvs * dvs) * gl + dvs * dvs * gmu + grho;
 }
 
 __global__ __launch_bounds__(TX * TY) void k3_write_gradient(PARAMS3) {
-  TILE3();
-  if (k >= s.ny || j >= s.nx) return;
-  const long cc = ((long)i * s.ny + k) * s.cp + j;
-  const long go = (long)(s.z0 + i) * s.mplanestride + (long)(s.y0 + k) * s.mld + (s.x0 + j);
-  for (int q = 0; q < 3; ++q) s.gout[q * s.mplane + go] = (float)s.G[q * s.cells + cc];
+  TILE3() {
+    if (k >= s.ny || j >= s.nx) return;
+    const long cc = ((long)i * s.ny + k) * s.cp + j;
+    const long go = (long)(s.z0 + i) * s.mplanestride + (long)(s.y0 + k) * s.mld + (s.x0 + j);
+    for (int q = 0; q < 3; ++q) s.gout[q * s.mplane + go] = (float)s.G[q * s.cells + cc];
+  }
 }
 
 inline dim3 grid3(const Sched& q) { return dim3(q.n); }
