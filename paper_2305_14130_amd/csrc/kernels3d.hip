@@ -8,7 +8,7 @@
 // i = z, k = y, j = x. 4th-order differences, zero outside the grid (zero halo), leapfrog,
 // unsplit CPML (kappa = 1) with memory variables in strips on every face.
 //
-// Tiles are 64 (x) by 4 (y) cells of one z plane; one thread owns one cell. The adjoint
+// Tiles are 64 (x) by 16 (y) cells of one z plane, four rows per thread. The adjoint
 // carries u_bar = b v_bar and t_bar = C sigma_bar (C: lambda 1 1^T + 2 mu I on the normal
 // block, the shear moduli on the shear components), so its transposed differences read one
 // array per neighbour, and the imaging condition uses forward quantities stored

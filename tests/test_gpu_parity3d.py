@@ -2,7 +2,7 @@
 
 A crop of the 3D precision workload (shale with a 3-cell reservoir, six-component
 moment-tensor shots in the layer, two horizontal DAS wells): 36 x 40 x 72 cells at 5 m with
-an 8-cell CPML, so the 64 x 4 tiles are ragged in x and several tiles touch the strips.
+an 8-cell CPML, so the 64 x 16 tiles are ragged in x and y and several tiles touch the strips.
 Same bars as 2D: data 1e-5, gradient and misfit 1e-5 * max(1, kappa).
 """
 import numpy as np
