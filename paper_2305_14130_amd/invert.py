@@ -311,7 +311,10 @@ class PreconditionedFWI(ConventionalFWI):
 def inverse_pseudo_hessian(prob, clip):
     """The diagonal initial inverse Hessian of the mute + pseudo-Hessian method for a
     conventional problem over x [2][nz][nx]: efwi.pseudo_hessian at the starting model with
-    the inverting side's sources, the same weight for Vp and Vs."""
+    the inverting side's sources, the same weight for Vp and Vs. The unknowns must be on the
+    grid (no B-spline parameterization)."""
+    if prob.bspline is not None:
+        raise ValueError("the diagonal pseudo-Hessian acts on grid unknowns, not on B-spline coefficients")
     m_ext = prob.m0.unsqueeze(0).repeat(prob.ns, 1, 1, 1).contiguous()
     _, p = efwi.pseudo_hessian(prob.grid, prob.shots, m_ext, prob.src, clip, ws=prob.ws)
     return p.unsqueeze(0).repeat(2, 1, 1).contiguous()
