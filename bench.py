@@ -187,7 +187,11 @@ def extension_ops(efwi, torch, grid, w, m_ext, src, dev, ph_steps=200):
     compulsory, 60 B per cell; the window sum and the inverse add 12 B per cell once. And the
     field-like DAS sampling of the first shot's recorded strains (1500 channels x 4000 steps,
     10-channel gauge, strain rate, every 4th sample; median of 5): reading the strains once
-    and writing the field data are compulsory."""
+    and writing the field data are compulsory. And the cubic B-spline parameterization of the
+    extended model's Vp and Vs planes (2 x shots planes, nodes every 50 m in x and every cell
+    in z, as in the field example; median of 5 each): the model planes written by the
+    expansion and read by the transpose are compulsory (the coefficients are 20 times
+    fewer)."""
     ns, nz, nx = m_ext.shape[0], w.nz, w.nx
     zones = []
     for s in w.shots:
@@ -235,6 +239,14 @@ def extension_ops(efwi, torch, grid, w, m_ext, src, dev, ph_steps=200):
     fout = torch.empty(fshot.data_shape(w.nt), dtype=torch.float32, device=dev)
     dms = med_ms(lambda: efwi.das_field(grid, fshot, e, out=fout))
     dbytes = 4 * (e.numel() + fout.numel())
+    dzn, dxn = 1, max(1, int(round(50.0 / w.dx)))
+    coef = torch.randn((ns, 2, efwi.bspline_nodes(nz, dzn), efwi.bspline_nodes(nx, dxn)), dtype=torch.float32,
+                       device=dev)
+    planes = torch.empty((ns, 2, nz, nx), dtype=torch.float32, device=dev)
+    cbar = torch.empty_like(coef)
+    ems = med_ms(lambda: efwi.bspline_expand(coef, nz, nx, dzn, dxn, out=planes))
+    ams = med_ms(lambda: efwi.bspline_adjoint(planes, dzn, dxn, out=cbar))
+    bbytes = 4 * (planes.numel() + coef.numel())
     out = {"zoi_weights": {"sources": ns, "ms": round(zms, 3), "bytes": zbytes,
                            "GBs": round(zbytes / zms / 1e6, 1), "frac": round(zbytes / zms / 1e6 / HBM_PEAK_GBS, 4),
                            "sink_points": int(sink.sum().item())},
@@ -245,8 +257,13 @@ def extension_ops(efwi, torch, grid, w, m_ext, src, dev, ph_steps=200):
                               "GBs": round(pbytes / pms / 1e6, 1), "frac": round(pbytes / pms / 1e6 / HBM_PEAK_GBS, 4)},
            "das_field": {"channels": int(e.shape[0]), "steps": int(e.shape[1]), "gauge": 10, "decim": 4, "rate": True,
                          "ms": round(dms, 3), "bytes": dbytes, "GBs": round(dbytes / dms / 1e6, 1),
-                         "frac": round(dbytes / dms / 1e6 / HBM_PEAK_GBS, 4)}}
-    del b, sink, m_out, h, pinv, ph_ws, e, fout
+                         "frac": round(dbytes / dms / 1e6 / HBM_PEAK_GBS, 4)},
+           "bspline_expand": {"planes": 2 * ns, "nodes": [int(coef.shape[2]), int(coef.shape[3])],
+                              "ms": round(ems, 3), "bytes": bbytes, "GBs": round(bbytes / ems / 1e6, 1),
+                              "frac": round(bbytes / ems / 1e6 / HBM_PEAK_GBS, 4)},
+           "bspline_adjoint": {"planes": 2 * ns, "ms": round(ams, 3), "bytes": bbytes,
+                               "GBs": round(bbytes / ams / 1e6, 1), "frac": round(bbytes / ams / 1e6 / HBM_PEAK_GBS, 4)}}
+    del b, sink, m_out, h, pinv, ph_ws, e, fout, coef, planes, cbar
     return out
 
 

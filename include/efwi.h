@@ -258,7 +258,8 @@ efwi_status efwi_final_model(const efwi_grid* grid, int ns, const float* m_ext, 
  * efwi_bspline_adjoint: c_bar = Bz^T g Bx (the transpose: gradients with respect to the
  *   coefficients); g DEVICE [np][nz][nx], c_bar DEVICE [np][Nz][Nx] output.
  * FP64 weights and sums, one launch on `stream`; EFWI_E_INVAL for sizes or spacings below
- * 1 or NULL arrays. */
+ * 1, spacings summing to more than 2000 cells (the weight tables live in LDS) or NULL
+ * arrays. */
 int efwi_bspline_nodes(int n, int spacing);
 efwi_status efwi_bspline_expand(int nz, int nx, int dz_nodes, int dx_nodes, int np, const float* c, float* m,
                                 void* stream);

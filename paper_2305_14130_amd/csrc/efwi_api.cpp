@@ -1830,6 +1830,7 @@ int efwi_bspline_nodes(int n, int spacing) { return (n >= 1 && spacing >= 1) ? b
 static efwi_status check_bspline(int nz, int nx, int dz_nodes, int dx_nodes, int np, const void* a, const void* b) {
   if (nz < 1 || nx < 1 || np < 1) return fail(EFWI_E_INVAL, "nz, nx and np must be >= 1");
   if (dz_nodes < 1 || dx_nodes < 1) return fail(EFWI_E_INVAL, "node spacings must be >= 1 cell");
+  if (dz_nodes + dx_nodes > 2000) return fail(EFWI_E_INVAL, "node spacings must sum to at most 2000 cells");
   if (!a || !b) return fail(EFWI_E_INVAL, "NULL array argument");
   return EFWI_OK;
 }

@@ -247,7 +247,7 @@ def test_bspline_arguments(efwi):
     assert efwi._lib.efwi_bspline_nodes(102, 10) == 14 and efwi._lib.efwi_bspline_nodes(1, 1) == 3
     assert efwi._lib.efwi_bspline_nodes(0, 1) == 0 and efwi._lib.efwi_bspline_nodes(10, 0) == 0
     fake = ctypes.c_void_p(256)
-    for args in ((0, 10, 1, 1, 1), (10, 10, 0, 1, 1), (10, 10, 1, 1, 0)):
+    for args in ((0, 10, 1, 1, 1), (10, 10, 0, 1, 1), (10, 10, 1, 1, 0), (10, 10, 1000, 1001, 1)):
         assert efwi._lib.efwi_bspline_expand(*args, fake, fake, None) == efwi.E_INVAL
         assert efwi._lib.efwi_bspline_adjoint(*args, fake, fake, None) == efwi.E_INVAL
     assert efwi._lib.efwi_bspline_expand(10, 10, 1, 1, 1, None, fake, None) == efwi.E_INVAL
