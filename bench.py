@@ -360,8 +360,8 @@ def main():  # noqa: C901
                     help="first run a plain device copy of this many MiB (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(shots shard across GPUs by design, see DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (on several GPUs the shots would be "
+                                   "sharded, one process per GPU; that path is not built)"}))
         sys.exit(2)
 
     import torch

@@ -45,7 +45,7 @@ typedef enum {
   EFWI_E_WORKSPACE = -4,    /* workspace smaller than efwi_workspace_size()            */
   EFWI_E_HIP = -5,          /* a HIP runtime call failed (message in efwi_last_error)  */
   EFWI_E_NONFINITE = -6,    /* reserved: non-finite value detected                      */
-  EFWI_E_UNSUPPORTED = -7   /* option not supported by this build                       */
+  EFWI_E_UNSUPPORTED = -7   /* option not supported (a VTI medium on a 3D grid, ...)    */
 } efwi_status;
 
 /* Simulation grid. In the batched call nz, nx are the extended model's full size and each
