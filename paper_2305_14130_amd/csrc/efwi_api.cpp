@@ -295,6 +295,14 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
     return fail(EFWI_E_RANGE, "shot %d: window outside the model", index);
   if (w.wz < 2 * P + 4 || w.wx < 2 * P + 4 || (three && w.wy < 2 * P + 4))
     return fail(EFWI_E_RANGE, "shot %d: window too small for %d CPML cells", index, g.npml);
+  if (three) {  // the 3D kernels address a shot's arrays with 32-bit byte offsets
+    const long ld = (XOFF + w.wx + HALO + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
+    const long cp = (w.wx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
+    const long padded = (long)(w.wz + 2 * HALO) * (w.wy + 2 * HALO) * ld, cells = (long)w.wz * w.wy * cp;
+    if (padded >= (1L << 30) || (long)NSEG3 * cells >= (1L << 30))
+      return fail(EFWI_E_RANGE, "shot %d: 3D window of %ld cells is beyond this library's 2^30-element arrays", index,
+                  cells);
+  }
   const int si = s->src_iz - w.z0, sj = s->src_ix - w.x0, sk = three ? s->src_iy - w.y0 : 0;
   if (si < P + 1 || si > w.wz - P - 1 || sj < P + 1 || sj > w.wx - P - 1 ||
       (three && (sk < P + 1 || sk > w.wy - P - 1)))

@@ -42,13 +42,35 @@ __device__ __forceinline__ const gfloat* px_(const Shot3D& s, int w) { return s.
 __device__ __forceinline__ const gfloat* py_(const Shot3D& s, int w) { return s.prof + 4 * s.nx + w * s.ny; }
 __device__ __forceinline__ const gfloat* pz_(const Shot3D& s, int w) { return s.prof + 4 * s.nx + 4 * s.ny + w * s.nz; }
 
+// Field accesses in the cell functions: a uniform base pointer at the padded plane's origin
+// (PF) plus a non-negative 32-bit element offset (cell_ofs), so that a load is a scalar base
+// and a 32-bit lane offset rather than per-lane 64-bit address arithmetic. Offsets stay far
+// below 2^30 elements at the sizes the plans allow.
+__device__ __forceinline__ long org3(const Shot3D& s) { return (long)HALO * s.pz + (long)HALO * s.ld + XOFF; }
+#define PF(f) ((f) - org3(s))
+__device__ __forceinline__ unsigned cell_ofs(const Shot3D& s, int i, int k, int j) {
+  return (unsigned)(i + HALO) * (unsigned)s.pz + (unsigned)(k + HALO) * (unsigned)s.ld + (unsigned)(XOFF + j);
+}
+// Element e of a global array as a 32-bit byte offset from a uniform base (the form the
+// hardware's scalar-base global loads and stores take; e < 2^30, checked on the host).
 template <class P>
-__device__ __forceinline__ float dplus(P f, long o, long st, float r) {
-  return (K1 * (f[o + st] - f[o]) + K2 * (f[o + 2 * st] - f[o - st])) * r;
+__device__ __forceinline__ auto& G(P* base, unsigned e) {
+  typedef __attribute__((address_space(1))) char gchar;
+  return *(P*)((gchar*)base + e * 4u);
 }
 template <class P>
-__device__ __forceinline__ float dminus(P f, long o, long st, float r) {
-  return (K1 * (f[o] - f[o - st]) + K2 * (f[o + st] - f[o - 2 * st])) * r;
+__device__ __forceinline__ const auto& G(const P* base, unsigned e) {
+  typedef const __attribute__((address_space(1))) char gchar;
+  return *(const P*)((gchar*)base + e * 4u);
+}
+
+template <class P>
+__device__ __forceinline__ float dplus(P f, unsigned o, unsigned st, float r) {
+  return (K1 * (G(f, o + st) - G(f, o)) + K2 * (G(f, o + 2 * st) - G(f, o - st))) * r;
+}
+template <class P>
+__device__ __forceinline__ float dminus(P f, unsigned o, unsigned st, float r) {
+  return (K1 * (G(f, o) - G(f, o - st)) + K2 * (G(f, o + st) - G(f, o - 2 * st))) * r;
 }
 
 __device__ __forceinline__ long xq(const Shot3D& s, int i, int k, int sx) { return ((long)i * s.ny + k) * 2 * s.P + sx; }
@@ -107,8 +129,14 @@ __device__ __forceinline__ bool tile3(const int* __restrict__ sched, const int* 
 
 // Streaming (non-temporal) accesses of the history: written once per forward step, read
 // once in the reverse sweep, so they should not displace the wavefields in the caches.
-__device__ __forceinline__ void hist_put(gfloat* p, float v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ float hist_get(const gfloat* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void hist_put(gfloat* base, unsigned e, float v) {
+  typedef __attribute__((address_space(1))) char gchar;
+  __builtin_nontemporal_store(v, (gfloat*)((gchar*)base + e * 4u));
+}
+__device__ __forceinline__ float hist_get(const gfloat* base, unsigned e) {
+  typedef const __attribute__((address_space(1))) char gchar;
+  return __builtin_nontemporal_load((const gfloat*)((gchar*)base + e * 4u));
+}
 
 // Every cell function below reads all it needs before its first store: the compiler cannot
 // prove that the arrays do not alias, so a load placed after a store would cost another
@@ -117,9 +145,9 @@ __device__ __forceinline__ float hist_get(const gfloat* p) { return __builtin_no
 // CPML memory variable at an owned node: psi <- b psi + a D computed from the old value
 // (read with the cell's other inputs, before any store) into p; returns D + psi. The caller
 // stores p after the cell's field updates.
-__device__ __forceinline__ float cpml_new(const gfloat* psi, long q, const gfloat* a, const gfloat* b, int c, float d,
-                                          float& p) {
-  p = b[c] * psi[q] + a[c] * d;
+__device__ __forceinline__ float cpml_new(const gfloat* psi, unsigned q, const gfloat* a, const gfloat* b, int c,
+                                          float d, float& p) {
+  p = b[c] * G(psi, q) + a[c] * d;
   return d + p;
 }
 
@@ -128,50 +156,50 @@ __device__ __forceinline__ float cpml_new(const gfloat* psi, long q, const gfloa
 // ------------------------------------------------------------------------------------
 template <bool STORE, bool PML>
 __device__ __forceinline__ void fwd_vel3(const Shot3D& s, int i, int k, int j, gfloat* seg) {
-  const long ld = s.ld, pz = s.pz;
-  const long o = (long)i * pz + (long)k * ld + j;
-  float a1 = dplus(s.sxx, o, 1, s.rdx), a2 = dminus(s.sxy, o, ld, s.rdy), a3 = dminus(s.sxz, o, pz, s.rdz);
-  float b1 = dminus(s.sxy, o, 1, s.rdx), b2 = dplus(s.syy, o, ld, s.rdy), b3 = dminus(s.syz, o, pz, s.rdz);
-  float c1 = dminus(s.sxz, o, 1, s.rdx), c2 = dminus(s.syz, o, ld, s.rdy), c3 = dplus(s.szz, o, pz, s.rdz);
-  const float vx = s.vx[o], vy = s.vy[o], vz = s.vz[o], bx = s.bx[o], by = s.by[o], bz = s.bz[o];
+  const unsigned ld = (unsigned)s.ld, pz = (unsigned)s.pz;
+  const unsigned o = cell_ofs(s, i, k, j);
+  float a1 = dplus(PF(s.sxx), o, 1u, s.rdx), a2 = dminus(PF(s.sxy), o, ld, s.rdy), a3 = dminus(PF(s.sxz), o, pz, s.rdz);
+  float b1 = dminus(PF(s.sxy), o, 1u, s.rdx), b2 = dplus(PF(s.syy), o, ld, s.rdy), b3 = dminus(PF(s.syz), o, pz, s.rdz);
+  float c1 = dminus(PF(s.sxz), o, 1u, s.rdx), c2 = dminus(PF(s.syz), o, ld, s.rdy), c3 = dplus(PF(s.szz), o, pz, s.rdz);
+  const float vx = G(PF(s.vx), o), vy = G(PF(s.vy), o), vz = G(PF(s.vz), o), bx = G(PF(s.bx), o), by = G(PF(s.by), o), bz = G(PF(s.bz), o);
   int sx = -1, sy = -1, sz = -1;
-  long qxs = 0, qys = 0, qzs = 0;
+  unsigned qxs = 0, qys = 0, qzs = 0;
   float p[9];
   if (PML) {
     sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
-      qxs = xq(s, i, k, sx);
+      qxs = (unsigned)xq(s, i, k, sx);
       a1 = cpml_new(s.psx[XS_VX], qxs, px_(s, 2), px_(s, 3), j, a1, p[0]);
       b1 = cpml_new(s.psx[XS_VY], qxs, px_(s, 0), px_(s, 1), j, b1, p[1]);
       c1 = cpml_new(s.psx[XS_VZ], qxs, px_(s, 0), px_(s, 1), j, c1, p[2]);
     }
     if (sy >= 0) {
-      qys = yq(s, i, sy, j);
+      qys = (unsigned)yq(s, i, sy, j);
       a2 = cpml_new(s.psy[YS_VX], qys, py_(s, 0), py_(s, 1), k, a2, p[3]);
       b2 = cpml_new(s.psy[YS_VY], qys, py_(s, 2), py_(s, 3), k, b2, p[4]);
       c2 = cpml_new(s.psy[YS_VZ], qys, py_(s, 0), py_(s, 1), k, c2, p[5]);
     }
     if (sz >= 0) {
-      qzs = zq(s, sz, k, j);
+      qzs = (unsigned)zq(s, sz, k, j);
       a3 = cpml_new(s.psz[ZS_VX], qzs, pz_(s, 0), pz_(s, 1), i, a3, p[6]);
       b3 = cpml_new(s.psz[ZS_VY], qzs, pz_(s, 0), pz_(s, 1), i, b3, p[7]);
       c3 = cpml_new(s.psz[ZS_VZ], qzs, pz_(s, 2), pz_(s, 3), i, c3, p[8]);
     }
   }
   const float qx = a1 + a2 + a3, qy = b1 + b2 + b3, qz = c1 + c2 + c3;
-  s.vx[o] = vx + s.dt * bx * qx;
-  s.vy[o] = vy + s.dt * by * qy;
-  s.vz[o] = vz + s.dt * bz * qz;
+  G(PF(s.vx), o) = vx + s.dt * bx * qx;
+  G(PF(s.vy), o) = vy + s.dt * by * qy;
+  G(PF(s.vz), o) = vz + s.dt * bz * qz;
   if (PML) {
-    if (sx >= 0) s.psx[XS_VX][qxs] = p[0], s.psx[XS_VY][qxs] = p[1], s.psx[XS_VZ][qxs] = p[2];
-    if (sy >= 0) s.psy[YS_VX][qys] = p[3], s.psy[YS_VY][qys] = p[4], s.psy[YS_VZ][qys] = p[5];
-    if (sz >= 0) s.psz[ZS_VX][qzs] = p[6], s.psz[ZS_VY][qzs] = p[7], s.psz[ZS_VZ][qzs] = p[8];
+    if (sx >= 0) G(s.psx[XS_VX], qxs) = p[0], G(s.psx[XS_VY], qxs) = p[1], G(s.psx[XS_VZ], qxs) = p[2];
+    if (sy >= 0) G(s.psy[YS_VX], qys) = p[3], G(s.psy[YS_VY], qys) = p[4], G(s.psy[YS_VZ], qys) = p[5];
+    if (sz >= 0) G(s.psz[ZS_VX], qzs) = p[6], G(s.psz[ZS_VY], qzs) = p[7], G(s.psz[ZS_VZ], qzs) = p[8];
   }
   if (STORE) {
-    const long c = ((long)i * s.ny + k) * s.cp + j;
-    hist_put(seg + 6 * s.cells + c, qx / bx);
-    hist_put(seg + 7 * s.cells + c, qy / by);
-    hist_put(seg + 8 * s.cells + c, qz / bz);
+    const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
+    hist_put(seg, 6 * cells + c, qx / bx);
+    hist_put(seg, 7 * cells + c, qy / by);
+    hist_put(seg, 8 * cells + c, qz / bz);
   }
 }
 
@@ -190,36 +218,36 @@ __global__ __launch_bounds__(TX * TY) void k3_fwd_vel(PARAMS3, int kstore) {
 // ------------------------------------------------------------------------------------
 template <bool STORE, bool RECORD, bool PML>
 __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, int n, gfloat* seg) {
-  const long ld = s.ld, pz = s.pz;
-  const long o = (long)i * pz + (long)k * ld + j;
-  float pxx = dminus(s.vx, o, 1, s.rdx), pyy = dminus(s.vy, o, ld, s.rdy), pzz = dminus(s.vz, o, pz, s.rdz);
-  float vx_y = dplus(s.vx, o, ld, s.rdy), vy_x = dplus(s.vy, o, 1, s.rdx);
-  float vx_z = dplus(s.vx, o, pz, s.rdz), vz_x = dplus(s.vz, o, 1, s.rdx);
-  float vy_z = dplus(s.vy, o, pz, s.rdz), vz_y = dplus(s.vz, o, ld, s.rdy);
+  const unsigned ld = (unsigned)s.ld, pz = (unsigned)s.pz;
+  const unsigned o = cell_ofs(s, i, k, j);
+  float pxx = dminus(PF(s.vx), o, 1u, s.rdx), pyy = dminus(PF(s.vy), o, ld, s.rdy), pzz = dminus(PF(s.vz), o, pz, s.rdz);
+  float vx_y = dplus(PF(s.vx), o, ld, s.rdy), vy_x = dplus(PF(s.vy), o, 1u, s.rdx);
+  float vx_z = dplus(PF(s.vx), o, pz, s.rdz), vz_x = dplus(PF(s.vz), o, 1u, s.rdx);
+  float vy_z = dplus(PF(s.vy), o, pz, s.rdz), vz_y = dplus(PF(s.vz), o, ld, s.rdy);
   const float raw_pxx = pxx;
-  const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
-  const float mxy = s.muxy[o], mxz = s.muxz[o], myz = s.muyz[o];
-  const float sxx0 = s.sxx[o], syy0 = s.syy[o], szz0 = s.szz[o], sxy0 = s.sxy[o], sxz0 = s.sxz[o], syz0 = s.syz[o];
+  const float l2m = G(PF(s.l2m), o), lam = G(PF(s.lam), o), two_mu = l2m - lam;
+  const float mxy = G(PF(s.muxy), o), mxz = G(PF(s.muxz), o), myz = G(PF(s.muyz), o);
+  const float sxx0 = G(PF(s.sxx), o), syy0 = G(PF(s.syy), o), szz0 = G(PF(s.szz), o), sxy0 = G(PF(s.sxy), o), sxz0 = G(PF(s.sxz), o), syz0 = G(PF(s.syz), o);
   const int slot = RECORD ? s.row_slot[(long)i * s.ny + k] : -1;
   int sx = -1, sy = -1, sz = -1;
-  long qxs = 0, qys = 0, qzs = 0;
+  unsigned qxs = 0, qys = 0, qzs = 0;
   float p[9];
   if (PML) {
     sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
     if (sx >= 0) {
-      qxs = xq(s, i, k, sx);
+      qxs = (unsigned)xq(s, i, k, sx);
       pxx = cpml_new(s.psx[XS_PXX], qxs, px_(s, 0), px_(s, 1), j, pxx, p[0]);
       vy_x = cpml_new(s.psx[XS_SXY], qxs, px_(s, 2), px_(s, 3), j, vy_x, p[1]);
       vz_x = cpml_new(s.psx[XS_SXZ], qxs, px_(s, 2), px_(s, 3), j, vz_x, p[2]);
     }
     if (sy >= 0) {
-      qys = yq(s, i, sy, j);
+      qys = (unsigned)yq(s, i, sy, j);
       pyy = cpml_new(s.psy[YS_PYY], qys, py_(s, 0), py_(s, 1), k, pyy, p[3]);
       vx_y = cpml_new(s.psy[YS_SXY], qys, py_(s, 2), py_(s, 3), k, vx_y, p[4]);
       vz_y = cpml_new(s.psy[YS_SYZ], qys, py_(s, 2), py_(s, 3), k, vz_y, p[5]);
     }
     if (sz >= 0) {
-      qzs = zq(s, sz, k, j);
+      qzs = (unsigned)zq(s, sz, k, j);
       pzz = cpml_new(s.psz[ZS_PZZ], qzs, pz_(s, 0), pz_(s, 1), i, pzz, p[6]);
       vx_z = cpml_new(s.psz[ZS_SXZ], qzs, pz_(s, 2), pz_(s, 3), i, vx_z, p[7]);
       vy_z = cpml_new(s.psz[ZS_SYZ], qzs, pz_(s, 2), pz_(s, 3), i, vy_z, p[8]);
@@ -243,16 +271,16 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
   if (i == s.si && kk && jj) sxy -= 0.25f * s.w * s.src[3 * nt + n];
   if (ii && k == s.sk && jj) sxz -= 0.25f * s.w * s.src[4 * nt + n];
   if (ii && kk && j == s.sj) syz -= 0.25f * s.w * s.src[5 * nt + n];
-  s.sxx[o] = sxx;
-  s.syy[o] = syy;
-  s.szz[o] = szz;
-  s.sxy[o] = sxy;
-  s.sxz[o] = sxz;
-  s.syz[o] = syz;
+  G(PF(s.sxx), o) = sxx;
+  G(PF(s.syy), o) = syy;
+  G(PF(s.szz), o) = szz;
+  G(PF(s.sxy), o) = sxy;
+  G(PF(s.sxz), o) = sxz;
+  G(PF(s.syz), o) = syz;
   if (PML) {
-    if (sx >= 0) s.psx[XS_PXX][qxs] = p[0], s.psx[XS_SXY][qxs] = p[1], s.psx[XS_SXZ][qxs] = p[2];
-    if (sy >= 0) s.psy[YS_PYY][qys] = p[3], s.psy[YS_SXY][qys] = p[4], s.psy[YS_SYZ][qys] = p[5];
-    if (sz >= 0) s.psz[ZS_PZZ][qzs] = p[6], s.psz[ZS_SXZ][qzs] = p[7], s.psz[ZS_SYZ][qzs] = p[8];
+    if (sx >= 0) G(s.psx[XS_PXX], qxs) = p[0], G(s.psx[XS_SXY], qxs) = p[1], G(s.psx[XS_SXZ], qxs) = p[2];
+    if (sy >= 0) G(s.psy[YS_PYY], qys) = p[3], G(s.psy[YS_SXY], qys) = p[4], G(s.psy[YS_SYZ], qys) = p[5];
+    if (sz >= 0) G(s.psz[ZS_PZZ], qzs) = p[6], G(s.psz[ZS_SXZ], qzs) = p[7], G(s.psz[ZS_SYZ], qzs) = p[8];
   }
   if (RECORD) {
     if (slot >= 0) {
@@ -265,14 +293,14 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
     }
   }
   if (STORE) {
-    const long c = ((long)i * s.ny + k) * s.cp + j;
+    const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
     const float mu = 0.5f * two_mu, third = tr * (1.0f / 3.0f);
-    hist_put(seg + c, tr / (l2m + 2.0f * lam));
-    hist_put(seg + s.cells + c, (pxx - third) / mu);
-    hist_put(seg + 2 * s.cells + c, (pyy - third) / mu);
-    hist_put(seg + 3 * s.cells + c, mxy > 0.0f ? sxy_r / mxy : 0.0f);
-    hist_put(seg + 4 * s.cells + c, mxz > 0.0f ? sxz_r / mxz : 0.0f);
-    hist_put(seg + 5 * s.cells + c, myz > 0.0f ? syz_r / myz : 0.0f);
+    hist_put(seg, c, tr / (l2m + 2.0f * lam));
+    hist_put(seg, cells + c, (pxx - third) / mu);
+    hist_put(seg, 2 * cells + c, (pyy - third) / mu);
+    hist_put(seg, 3 * cells + c, mxy > 0.0f ? sxy_r / mxy : 0.0f);
+    hist_put(seg, 4 * cells + c, mxz > 0.0f ? sxz_r / mxz : 0.0f);
+    hist_put(seg, 5 * cells + c, myz > 0.0f ? syz_r / myz : 0.0f);
   }
 }
 
@@ -300,26 +328,26 @@ struct Adj3 {
   __device__ __forceinline__ float cx(float v, int i, int k, int j, int slot, int prof) const {
     if (PX && j < s.nx) {
       const int sx = strip_index(j, s.nx, s.P);
-      if (sx >= 0) v += px_(s, prof)[j] * (s.pbx[rd][slot][xq(s, i, k, sx)] + v);
+      if (sx >= 0) v += px_(s, prof)[j] * (G(s.pbx[rd][slot], (unsigned)xq(s, i, k, sx)) + v);
     }
     return v;
   }
   __device__ __forceinline__ float cy(float v, int i, int k, int j, int slot, int prof) const {
     if (PY && k < s.ny) {
       const int sy = strip_index(k, s.ny, s.P);
-      if (sy >= 0) v += py_(s, prof)[k] * (s.pby[rd][slot][yq(s, i, sy, j)] + v);
+      if (sy >= 0) v += py_(s, prof)[k] * (G(s.pby[rd][slot], (unsigned)yq(s, i, sy, j)) + v);
     }
     return v;
   }
   __device__ __forceinline__ float cz(float v, int i, int k, int j, int slot, int prof) const {
     if (PZ && i < s.nz) {
       const int sz = strip_index(i, s.nz, s.P);
-      if (sz >= 0) v += pz_(s, prof)[i] * (s.pbz[rd][slot][zq(s, sz, k, j)] + v);
+      if (sz >= 0) v += pz_(s, prof)[i] * (G(s.pbz[rd][slot], (unsigned)zq(s, sz, k, j)) + v);
     }
     return v;
   }
   __device__ __forceinline__ float at(const gfloat* f, int i, int k, int j) const {
-    return s.dt * f[(long)i * s.pz + (long)k * s.ld + j];
+    return s.dt * G(PF(f), cell_ofs(s, i, k, j));
   }
 };
 
@@ -332,8 +360,8 @@ __device__ __forceinline__ float ebar3(const Shot3D& s, int slot, int jc, int n)
 // Transposed stress sub-step: t_bar -> u_bar.
 template <bool GRAD, bool SRCADJ, bool PX, bool PY, bool PZ>
 __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, int n, const gfloat* seg, bool first) {
-  const long ld = s.ld, pz = s.pz;
-  const long o = (long)i * pz + (long)k * ld + j;
+  const unsigned ld = (unsigned)s.ld, pz = (unsigned)s.pz;
+  const unsigned o = cell_ofs(s, i, k, j);
   const int rd = (n + 1) & 1, wr = n & 1;
   const Adj3<PX, PY, PZ> A{s, rd};
   // operands: normal (int profile on their own axis), shear (half profile on the axis of
@@ -368,59 +396,61 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
                       K2 * (ebar3(s, slot, j - 1, n) - ebar3(s, slot, j + 2, n));
     gx += s.dt * s.rdx * inj;
   }
-  const float txx = s.txxb[o], tyy = s.tyyb[o], tzz = s.tzzb[o];
-  const float txy = s.txyb[o], txz = s.txzb[o], tyz = s.tyzb[o];
-  const float ux = s.uxb[o], uy = s.uyb[o], uz = s.uzb[o], bx = s.bx[o], by = s.by[o], bz = s.bz[o];
-  s.uxb[o] = ux + bx * gx;
-  s.uyb[o] = uy + by * gy;
-  s.uzb[o] = uz + bz * gz;
+  const float txx = G(PF(s.txxb), o), tyy = G(PF(s.tyyb), o), tzz = G(PF(s.tzzb), o);
+  const float txy = G(PF(s.txyb), o), txz = G(PF(s.txzb), o), tyz = G(PF(s.tyzb), o);
+  const float ux = G(PF(s.uxb), o), uy = G(PF(s.uyb), o), uz = G(PF(s.uzb), o), bx = G(PF(s.bx), o), by = G(PF(s.by), o), bz = G(PF(s.bz), o);
+  G(PF(s.uxb), o) = ux + bx * gx;
+  G(PF(s.uyb), o) = uy + by * gy;
+  G(PF(s.uzb), o) = uz + bz * gz;
   if (PX || PY || PZ) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
     const float dt = s.dt;
     const int sx = PX ? strip_index(j, s.nx, s.P) : -1, sy = PY ? strip_index(k, s.ny, s.P) : -1,
               sz = PZ ? strip_index(i, s.nz, s.P) : -1;
     if (sx >= 0) {
-      const long q = xq(s, i, k, sx);
-      s.pbx[wr][XS_PXX][q] = px_(s, 1)[j] * (s.pbx[rd][XS_PXX][q] + dt * txx);
-      s.pbx[wr][XS_SXY][q] = px_(s, 3)[j] * (s.pbx[rd][XS_SXY][q] + dt * txy);
-      s.pbx[wr][XS_SXZ][q] = px_(s, 3)[j] * (s.pbx[rd][XS_SXZ][q] + dt * txz);
+      const unsigned q = (unsigned)xq(s, i, k, sx);
+      G(s.pbx[wr][XS_PXX], q) = px_(s, 1)[j] * (G(s.pbx[rd][XS_PXX], q) + dt * txx);
+      G(s.pbx[wr][XS_SXY], q) = px_(s, 3)[j] * (G(s.pbx[rd][XS_SXY], q) + dt * txy);
+      G(s.pbx[wr][XS_SXZ], q) = px_(s, 3)[j] * (G(s.pbx[rd][XS_SXZ], q) + dt * txz);
     }
     if (sy >= 0) {
-      const long q = yq(s, i, sy, j);
-      s.pby[wr][YS_PYY][q] = py_(s, 1)[k] * (s.pby[rd][YS_PYY][q] + dt * tyy);
-      s.pby[wr][YS_SXY][q] = py_(s, 3)[k] * (s.pby[rd][YS_SXY][q] + dt * txy);
-      s.pby[wr][YS_SYZ][q] = py_(s, 3)[k] * (s.pby[rd][YS_SYZ][q] + dt * tyz);
+      const unsigned q = (unsigned)yq(s, i, sy, j);
+      G(s.pby[wr][YS_PYY], q) = py_(s, 1)[k] * (G(s.pby[rd][YS_PYY], q) + dt * tyy);
+      G(s.pby[wr][YS_SXY], q) = py_(s, 3)[k] * (G(s.pby[rd][YS_SXY], q) + dt * txy);
+      G(s.pby[wr][YS_SYZ], q) = py_(s, 3)[k] * (G(s.pby[rd][YS_SYZ], q) + dt * tyz);
     }
     if (sz >= 0) {
-      const long q = zq(s, sz, k, j);
-      s.pbz[wr][ZS_PZZ][q] = pz_(s, 1)[i] * (s.pbz[rd][ZS_PZZ][q] + dt * tzz);
-      s.pbz[wr][ZS_SXZ][q] = pz_(s, 3)[i] * (s.pbz[rd][ZS_SXZ][q] + dt * txz);
-      s.pbz[wr][ZS_SYZ][q] = pz_(s, 3)[i] * (s.pbz[rd][ZS_SYZ][q] + dt * tyz);
+      const unsigned q = (unsigned)zq(s, sz, k, j);
+      G(s.pbz[wr][ZS_PZZ], q) = pz_(s, 1)[i] * (G(s.pbz[rd][ZS_PZZ], q) + dt * tzz);
+      G(s.pbz[wr][ZS_SXZ], q) = pz_(s, 3)[i] * (G(s.pbz[rd][ZS_SXZ], q) + dt * txz);
+      G(s.pbz[wr][ZS_SYZ], q) = pz_(s, 3)[i] * (G(s.pbz[rd][ZS_SYZ], q) + dt * tyz);
     }
   }
   if (GRAD) {
-    const long c = ((long)i * s.ny + k) * s.cp + j;
+    const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
     float h[6], a[5] = {0, 0, 0, 0, 0};
-    for (int f = 0; f < 6; ++f) h[f] = hist_get(seg + f * s.cells + c);
+    for (int f = 0; f < 6; ++f) h[f] = hist_get(seg, f * cells + c);
     if (!first)
-      for (int f = 0; f < 5; ++f) a[f] = s.acc[f * s.cells + c];
+      for (int f = 0; f < 5; ++f) a[f] = G(s.acc, f * cells + c);
     const float trt = txx + tyy + tzz;
     const float da = txx - trt * (1.0f / 3.0f), db = tyy - trt * (1.0f / 3.0f);
     const float D1 = h[1], D2 = h[2];
-    s.acc[c] = a[0] + s.dt * trt * h[0];
-    s.acc[s.cells + c] = a[1] + s.dt * (da * D1 + db * D2 + (da + db) * (D1 + D2));
-    s.acc[2 * s.cells + c] = a[2] + s.dt * txy * h[3];
-    s.acc[3 * s.cells + c] = a[3] + s.dt * txz * h[4];
-    s.acc[4 * s.cells + c] = a[4] + s.dt * tyz * h[5];
+    G(s.acc, c) = a[0] + s.dt * trt * h[0];
+    G(s.acc, cells + c) = a[1] + s.dt * (da * D1 + db * D2 + (da + db) * (D1 + D2));
+    G(s.acc, 2 * cells + c) = a[2] + s.dt * txy * h[3];
+    G(s.acc, 3 * cells + c) = a[3] + s.dt * txz * h[4];
+    G(s.acc, 4 * cells + c) = a[4] + s.dt * tyz * h[5];
   }
   if (SRCADJ && i == s.si && k == s.sk && j == s.sj) {
     // sigma_bar at the source: invert C on the normal block and the shear moduli
-    const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
+    const float l2m = G(PF(s.l2m), o), lam = G(PF(s.lam), o), two_mu = l2m - lam;
     const float trs = (txx + tyy + tzz) / (l2m + 2.0f * lam);
     const int nt = s.nt;
     s.src_bar[n] = -s.w * (txx - lam * trs) / two_mu;
     s.src_bar[nt + n] = -s.w * (tyy - lam * trs) / two_mu;
     s.src_bar[2 * nt + n] = -s.w * (tzz - lam * trs) / two_mu;
-    auto sh = [&](const gfloat* t, const gfloat* mu, long oo) { return mu[oo] > 0.0f ? t[oo] / mu[oo] : 0.0f; };
+    auto sh = [&](const gfloat* t, const gfloat* mu, unsigned oo) {
+      return G(PF(mu), oo) > 0.0f ? G(PF(t), oo) / G(PF(mu), oo) : 0.0f;
+    };
     float a = 0.f, b = 0.f, c = 0.f;
     for (int q = 0; q < 4; ++q) {
       const int d1 = q & 1, d2 = q >> 1;
@@ -448,8 +478,8 @@ __global__ __launch_bounds__(TX * TY) void k3_adj_vel(PARAMS3, int n, int kseg, 
 // Transposed velocity sub-step: u_bar -> t_bar.
 template <bool GRAD, bool PX, bool PY, bool PZ>
 __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, int n, const gfloat* seg, bool first) {
-  const long ld = s.ld, pz = s.pz;
-  const long o = (long)i * pz + (long)k * ld + j;
+  const unsigned ld = (unsigned)s.ld, pz = (unsigned)s.pz;
+  const unsigned o = cell_ofs(s, i, k, j);
   const int rd = (n + 1) & 1, wr = n & 1;
   const Adj3<PX, PY, PZ> A{s, rd};
   auto Qxx = [&](int a, int b, int c) { return A.cx(A.at(s.uxb, a, b, c), a, b, c, XS_VX, 2); };  // vx: D+x sxx
@@ -471,49 +501,49 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
                       (K1 * (Qzx(i, k, j + 1) - Qzx(i, k, j)) + K2 * (Qzx(i, k, j + 2) - Qzx(i, k, j - 1))) * s.rdx);
   const float dyz = -((K1 * (Qyz(i + 1, k, j) - Qyz(i, k, j)) + K2 * (Qyz(i + 2, k, j) - Qyz(i - 1, k, j))) * s.rdz +
                       (K1 * (Qzy(i, k + 1, j) - Qzy(i, k, j)) + K2 * (Qzy(i, k + 2, j) - Qzy(i, k - 1, j))) * s.rdy);
-  const float ux = s.uxb[o], uy = s.uyb[o], uz = s.uzb[o];
-  const float l2m = s.l2m[o], lam = s.lam[o], two_mu = l2m - lam;
-  const float mxy = s.muxy[o], mxz = s.muxz[o], myz = s.muyz[o];
-  const float txx = s.txxb[o], tyy = s.tyyb[o], tzz = s.tzzb[o], txy = s.txyb[o], txz = s.txzb[o], tyz = s.tyzb[o];
+  const float ux = G(PF(s.uxb), o), uy = G(PF(s.uyb), o), uz = G(PF(s.uzb), o);
+  const float l2m = G(PF(s.l2m), o), lam = G(PF(s.lam), o), two_mu = l2m - lam;
+  const float mxy = G(PF(s.muxy), o), mxz = G(PF(s.muxz), o), myz = G(PF(s.muyz), o);
+  const float txx = G(PF(s.txxb), o), tyy = G(PF(s.tyyb), o), tzz = G(PF(s.tzzb), o), txy = G(PF(s.txyb), o), txz = G(PF(s.txzb), o), tyz = G(PF(s.tyzb), o);
   const float tr = dxx + dyy + dzz;
-  s.txxb[o] = txx + (lam * tr + two_mu * dxx);
-  s.tyyb[o] = tyy + (lam * tr + two_mu * dyy);
-  s.tzzb[o] = tzz + (lam * tr + two_mu * dzz);
-  s.txyb[o] = txy + mxy * dxy;
-  s.txzb[o] = txz + mxz * dxz;
-  s.tyzb[o] = tyz + myz * dyz;
+  G(PF(s.txxb), o) = txx + (lam * tr + two_mu * dxx);
+  G(PF(s.tyyb), o) = tyy + (lam * tr + two_mu * dyy);
+  G(PF(s.tzzb), o) = tzz + (lam * tr + two_mu * dzz);
+  G(PF(s.txyb), o) = txy + mxy * dxy;
+  G(PF(s.txzb), o) = txz + mxz * dxz;
+  G(PF(s.tyzb), o) = tyz + myz * dyz;
   if (PX || PY || PZ) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
     const float dt = s.dt;
     const int sx = PX ? strip_index(j, s.nx, s.P) : -1, sy = PY ? strip_index(k, s.ny, s.P) : -1,
               sz = PZ ? strip_index(i, s.nz, s.P) : -1;
     if (sx >= 0) {
-      const long q = xq(s, i, k, sx);
-      s.pbx[wr][XS_VX][q] = px_(s, 3)[j] * (s.pbx[rd][XS_VX][q] + dt * ux);
-      s.pbx[wr][XS_VY][q] = px_(s, 1)[j] * (s.pbx[rd][XS_VY][q] + dt * uy);
-      s.pbx[wr][XS_VZ][q] = px_(s, 1)[j] * (s.pbx[rd][XS_VZ][q] + dt * uz);
+      const unsigned q = (unsigned)xq(s, i, k, sx);
+      G(s.pbx[wr][XS_VX], q) = px_(s, 3)[j] * (G(s.pbx[rd][XS_VX], q) + dt * ux);
+      G(s.pbx[wr][XS_VY], q) = px_(s, 1)[j] * (G(s.pbx[rd][XS_VY], q) + dt * uy);
+      G(s.pbx[wr][XS_VZ], q) = px_(s, 1)[j] * (G(s.pbx[rd][XS_VZ], q) + dt * uz);
     }
     if (sy >= 0) {
-      const long q = yq(s, i, sy, j);
-      s.pby[wr][YS_VX][q] = py_(s, 1)[k] * (s.pby[rd][YS_VX][q] + dt * ux);
-      s.pby[wr][YS_VY][q] = py_(s, 3)[k] * (s.pby[rd][YS_VY][q] + dt * uy);
-      s.pby[wr][YS_VZ][q] = py_(s, 1)[k] * (s.pby[rd][YS_VZ][q] + dt * uz);
+      const unsigned q = (unsigned)yq(s, i, sy, j);
+      G(s.pby[wr][YS_VX], q) = py_(s, 1)[k] * (G(s.pby[rd][YS_VX], q) + dt * ux);
+      G(s.pby[wr][YS_VY], q) = py_(s, 3)[k] * (G(s.pby[rd][YS_VY], q) + dt * uy);
+      G(s.pby[wr][YS_VZ], q) = py_(s, 1)[k] * (G(s.pby[rd][YS_VZ], q) + dt * uz);
     }
     if (sz >= 0) {
-      const long q = zq(s, sz, k, j);
-      s.pbz[wr][ZS_VX][q] = pz_(s, 1)[i] * (s.pbz[rd][ZS_VX][q] + dt * ux);
-      s.pbz[wr][ZS_VY][q] = pz_(s, 1)[i] * (s.pbz[rd][ZS_VY][q] + dt * uy);
-      s.pbz[wr][ZS_VZ][q] = pz_(s, 3)[i] * (s.pbz[rd][ZS_VZ][q] + dt * uz);
+      const unsigned q = (unsigned)zq(s, sz, k, j);
+      G(s.pbz[wr][ZS_VX], q) = pz_(s, 1)[i] * (G(s.pbz[rd][ZS_VX], q) + dt * ux);
+      G(s.pbz[wr][ZS_VY], q) = pz_(s, 1)[i] * (G(s.pbz[rd][ZS_VY], q) + dt * uy);
+      G(s.pbz[wr][ZS_VZ], q) = pz_(s, 3)[i] * (G(s.pbz[rd][ZS_VZ], q) + dt * uz);
     }
   }
   if (GRAD) {
-    const long c = ((long)i * s.ny + k) * s.cp + j;
+    const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
     float h[3], a[3] = {0, 0, 0};
-    for (int f = 0; f < 3; ++f) h[f] = hist_get(seg + (6 + f) * s.cells + c);
+    for (int f = 0; f < 3; ++f) h[f] = hist_get(seg, (6 + f) * cells + c);
     if (!first)
-      for (int f = 0; f < 3; ++f) a[f] = s.acc[(5 + f) * s.cells + c];
-    s.acc[5 * s.cells + c] = a[0] + s.dt * ux * h[0];
-    s.acc[6 * s.cells + c] = a[1] + s.dt * uy * h[1];
-    s.acc[7 * s.cells + c] = a[2] + s.dt * uz * h[2];
+      for (int f = 0; f < 3; ++f) a[f] = G(s.acc, (5 + f) * cells + c);
+    G(s.acc, 5 * cells + c) = a[0] + s.dt * ux * h[0];
+    G(s.acc, 6 * cells + c) = a[1] + s.dt * uy * h[1];
+    G(s.acc, 7 * cells + c) = a[2] + s.dt * uz * h[2];
   }
 }
 
@@ -545,16 +575,16 @@ __global__ __launch_bounds__(TX * TY) void k3_stage(PARAMS3) {
     };
     const float vp = at(s.mvp, i, k, j), rho = at(s.mrho, i, k, j);
     const float mu = mu_at(i, k, j);
-    const long o = (long)i * s.pz + (long)k * s.ld + j;
+    const unsigned o = cell_ofs(s, i, k, j);
     const float l2m = rho * vp * vp;
-    s.l2m[o] = l2m;
-    s.lam[o] = l2m - 2.0f * mu;
-    s.muxy[o] = harm(mu, mu_at(i, kp, j), mu_at(i, k, jp), mu_at(i, kp, jp));
-    s.muxz[o] = harm(mu, mu_at(ip, k, j), mu_at(i, k, jp), mu_at(ip, k, jp));
-    s.muyz[o] = harm(mu, mu_at(ip, k, j), mu_at(i, kp, j), mu_at(ip, kp, j));
-    s.bx[o] = 2.0f / (rho + at(s.mrho, i, k, jp));
-    s.by[o] = 2.0f / (rho + at(s.mrho, i, kp, j));
-    s.bz[o] = 2.0f / (rho + at(s.mrho, ip, k, j));
+    G(PF(s.l2m), o) = l2m;
+    G(PF(s.lam), o) = l2m - 2.0f * mu;
+    G(PF(s.muxy), o) = harm(mu, mu_at(i, kp, j), mu_at(i, k, jp), mu_at(i, kp, jp));
+    G(PF(s.muxz), o) = harm(mu, mu_at(ip, k, j), mu_at(i, k, jp), mu_at(ip, k, jp));
+    G(PF(s.muyz), o) = harm(mu, mu_at(ip, k, j), mu_at(i, kp, j), mu_at(ip, kp, j));
+    G(PF(s.bx), o) = 2.0f / (rho + at(s.mrho, i, k, jp));
+    G(PF(s.by), o) = 2.0f / (rho + at(s.mrho, i, kp, j));
+    G(PF(s.bz), o) = 2.0f / (rho + at(s.mrho, ip, k, j));
   }
 }
 
