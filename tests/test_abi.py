@@ -266,3 +266,15 @@ def test_vti_is_2d_only(efwi):
     iso = efwi._lib.efwi_workspace_size(efwi.WS_GRADIENT, ctypes.byref(g2), 1, a2)
     g2.eps = 256
     assert efwi._lib.efwi_workspace_size(efwi.WS_GRADIENT, ctypes.byref(g2), 1, a2) > iso
+
+
+def test_3d_window_size_limit(efwi):
+    """3D kernels address a shot's arrays with 32-bit byte offsets: a window whose padded
+    arrays reach 2^30 elements is refused on the host."""
+    g = efwi.make_grid3d(1100, 1100, 1000, 5.0, 5.0, 5.0, 0.4e-3, 10, 8, 1e-3, 30.0, 4500.0)
+    shot = efwi.Shot(500, 500, [501], [520], src_iy=500, ch_iy=[500])
+    arr = (efwi._ShotC * 1)(shot.c_struct())
+    assert efwi._lib.efwi_validate(ctypes.byref(g), 1, arr) == efwi.E_RANGE
+    small = efwi.Shot(500, 500, [501], [520], src_iy=500, ch_iy=[500], z0=300, y0=300, x0=300, wz=400, wy=400, wx=400)
+    arr = (efwi._ShotC * 1)(small.c_struct())
+    assert efwi._lib.efwi_validate(ctypes.byref(g), 1, arr) == efwi.OK
