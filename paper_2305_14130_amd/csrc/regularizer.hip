@@ -29,50 +29,67 @@ __global__ __launch_bounds__(RB) void k_regularizer(int ns, long npts, long plan
   __shared__ double sh[RB];
   double phi = 0.0;
   for (long p = blockIdx.x * (long)RB + threadIdx.x; p < npts; p += (long)gridDim.x * RB) {
-    double bsum = 0.0;
-    for (int s = 0; s < ns; ++s) bsum += b[(long)s * npts + p];
-    double bpsum = 0.0;
-    for (int s = 0; s < ns; ++s) bpsum += sink[(long)s * npts + p] ? 1.0 : (double)b[(long)s * npts + p];
+    // Passes over the sources with the three parameters together; per source the sinkhole
+    // mix (in s's sinkhole and other weights present) and 1 / B_s are formed once a pass.
+    // (W m)_s,k = mix ? b_s m_s,k + (1 - b_s)(A_k - b_s m_s,k) / B_s : m_s,k
+    auto mv = [&](int s, int k) { return (double)m[((long)s * 3 + k) * plane + p]; };
+    double bsum = 0.0, bpsum = 0.0, A[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < ns; ++s) {
+      const double bs = b[(long)s * npts + p];
+      bsum += bs;
+      bpsum += sink[(long)s * npts + p] ? 1.0 : bs;
+      for (int k = 0; k < 3; ++k) A[k] += bs * mv(s, k);
+    }
     if (!(bpsum > 0.0)) continue;
-    for (int k = 0; k < 3; ++k) {
-      auto mv = [&](int s) { return (double)m[((long)s * 3 + k) * plane + p]; };
-      double A = 0.0;
-      for (int s = 0; s < ns; ++s) A += (double)b[(long)s * npts + p] * mv(s);
-      auto wm = [&](int s) {
-        const double bs = b[(long)s * npts + p];
-        const double Bs = bsum - bs;
-        const double ms = mv(s);
-        if (sink[(long)s * npts + p] && Bs > 0.0) return bs * ms + (1.0 - bs) * (A - bs * ms) / Bs;
-        return ms;
-      };
-      double num = 0.0;
-      for (int s = 0; s < ns; ++s) {
-        const double bp = sink[(long)s * npts + p] ? 1.0 : (double)b[(long)s * npts + p];
-        num += bp * wm(s);
-      }
-      const double mbar = num / bpsum;
-      double Y = 0.0;
-      for (int s = 0; s < ns; ++s) {
-        const double y = wm(s) - mbar;
-        Y += y;
+    struct Src {
+      double bs, bp, inv;
+      bool mix;
+    };
+    auto src = [&](int s) {
+      Src r;
+      r.bs = b[(long)s * npts + p];
+      const double Bs = bsum - r.bs;
+      const bool in = sink[(long)s * npts + p] != 0;
+      r.mix = in && Bs > 0.0;
+      r.bp = in ? 1.0 : r.bs;
+      r.inv = r.mix ? 1.0 / Bs : 0.0;
+      return r;
+    };
+    auto wm = [&](const Src& q, int s, int k) {
+      const double ms = mv(s, k);
+      return q.mix ? q.bs * ms + (1.0 - q.bs) * (A[k] - q.bs * ms) * q.inv : ms;
+    };
+    // mean over the useful components: mbar_k = sum_s b'_s (W m)_s,k / sum b'
+    double mbar[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < ns; ++s) {
+      const Src q = src(s);
+      for (int k = 0; k < 3; ++k) mbar[k] += q.bp * wm(q, s, k);
+    }
+    for (int k = 0; k < 3; ++k) mbar[k] /= bpsum;
+    // y = W m - mbar: its sum over sources and the penalty
+    double Y[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < ns; ++s) {
+      const Src q = src(s);
+      for (int k = 0; k < 3; ++k) {
+        const double y = wm(q, s, k) - mbar[k];
+        Y[k] += y;
         phi += y * y;
       }
-      auto zf = [&](int s) {
-        const double bp = sink[(long)s * npts + p] ? 1.0 : (double)b[(long)s * npts + p];
-        return (wm(s) - mbar) - bp / bpsum * Y;
-      };
-      double T = 0.0;
-      for (int s = 0; s < ns; ++s) {
-        const double bs = b[(long)s * npts + p];
-        const double Bs = bsum - bs;
-        if (sink[(long)s * npts + p] && Bs > 0.0) T += (1.0 - bs) * zf(s) / Bs;
-      }
-      for (int s = 0; s < ns; ++s) {
-        const double bs = b[(long)s * npts + p];
-        const double Bs = bsum - bs;
-        const double z = zf(s);
-        const bool in = sink[(long)s * npts + p] && Bs > 0.0;
-        const double wz = (in ? bs : 1.0) * z + bs * (T - (in ? (1.0 - bs) * z / Bs : 0.0));
+    }
+    // z_s = y_s - b'_s / sum b' * sum y; T_k = sum over mixing sources of (1 - b_s) z_s / B_s
+    auto zf = [&](const Src& q, int s, int k) { return (wm(q, s, k) - mbar[k]) - q.bp / bpsum * Y[k]; };
+    double T[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < ns; ++s) {
+      const Src q = src(s);
+      if (!q.mix) continue;
+      for (int k = 0; k < 3; ++k) T[k] += (1.0 - q.bs) * zf(q, s, k) * q.inv;
+    }
+    // g_s += eta^2 W^T z
+    for (int s = 0; s < ns; ++s) {
+      const Src q = src(s);
+      for (int k = 0; k < 3; ++k) {
+        const double z = zf(q, s, k);
+        const double wz = (q.mix ? q.bs : 1.0) * z + q.bs * (T[k] - (q.mix ? (1.0 - q.bs) * z * q.inv : 0.0));
         float* gp = g + ((long)s * 3 + k) * plane + p;
         *gp = (float)((double)*gp + eta2 * wz);
       }
@@ -156,30 +173,33 @@ __global__ __launch_bounds__(RB) void k_final_model(int ns, long npts, long plan
                                                     const unsigned char* __restrict__ sink,
                                                     float* __restrict__ out) {
   for (long p = blockIdx.x * (long)RB + threadIdx.x; p < npts; p += (long)gridDim.x * RB) {
-    double bsum = 0.0, bpsum = 0.0;
+    // first pass: sum b, sum b' and A_k = sum_s b_s m_s,k for the three parameters
+    double bsum = 0.0, bpsum = 0.0, A[3] = {0.0, 0.0, 0.0};
     for (int s = 0; s < ns; ++s) {
       const double bs = b[(long)s * npts + p];
       bsum += bs;
       bpsum += sink[(long)s * npts + p] ? 1.0 : bs;
+      for (int k = 0; k < 3; ++k) A[k] += bs * (double)m[((long)s * 3 + k) * plane + p];
     }
-    for (int k = 0; k < 3; ++k) {
-      if (!(bpsum > 0.0)) {
-        out[(long)k * plane + p] = 0.0f;
-        continue;
-      }
-      double A = 0.0;
-      for (int s = 0; s < ns; ++s) A += (double)b[(long)s * npts + p] * (double)m[((long)s * 3 + k) * plane + p];
-      double num = 0.0;
-      for (int s = 0; s < ns; ++s) {
-        const double bs = b[(long)s * npts + p];
-        const double Bs = bsum - bs;
+    if (!(bpsum > 0.0)) {
+      for (int k = 0; k < 3; ++k) out[(long)k * plane + p] = 0.0f;
+      continue;
+    }
+    // second pass: (W m)_s (one division per source) weighted by b'_s
+    double num[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < ns; ++s) {
+      const double bs = b[(long)s * npts + p];
+      const double Bs = bsum - bs;
+      const bool in = sink[(long)s * npts + p] != 0;
+      const bool mix = in && Bs > 0.0;
+      const double inv = mix ? 1.0 / Bs : 0.0, wp = in ? 1.0 : bs;
+      for (int k = 0; k < 3; ++k) {
         const double ms = m[((long)s * 3 + k) * plane + p];
-        const bool in = sink[(long)s * npts + p] != 0;
-        const double wm = (in && Bs > 0.0) ? bs * ms + (1.0 - bs) * (A - bs * ms) / Bs : ms;
-        num += (in ? 1.0 : bs) * wm;
+        const double wm = mix ? bs * ms + (1.0 - bs) * (A[k] - bs * ms) * inv : ms;
+        num[k] += wp * wm;
       }
-      out[(long)k * plane + p] = (float)(num / bpsum);
     }
+    for (int k = 0; k < 3; ++k) out[(long)k * plane + p] = (float)(num[k] / bpsum);
   }
 }
 
