@@ -144,6 +144,26 @@ def plain_2d(nz=1000, nx=3000, nt=4000, nshots=20, nch=1500, M0=1.0e16, anomalie
                       m_start=m_start, m_true=m_true, shots=shots)
 
 
+def differentiation_2d(nz=1200, nx=4000, nt=8000, nshots=32, nch=2000, M0=1.0e16, anomalies=True):
+    """The shale geology resampled to 2 m: grid 1200 x 4000, nt = 8000 at 0.2 ms, 40-cell
+    CPML, Ricker 60 Hz, a reservoir of 8 cells (16 m) at mid depth, 32 moment-tensor sources
+    along the well in the layer and 2000 DAS e_xx channels one cell apart (iz = nz / 2)."""
+    h, dt = 2.0, 0.2e-3
+    res_top, res_bot = nz // 2 - 4, nz // 2 + 4
+    m_true = _shale_model(nz, nx, h, res_top, res_bot, anomalies=anomalies)
+    m_start = _shale_model(nz, nx, h, res_top, res_bot, anomalies=False)
+    rng = np.random.default_rng(2305)
+    iz = nz // 2
+    ch_ix = (nx // 4 + np.arange(nch)).astype(np.int32)
+    ch_iz = np.full(nch, iz, np.int32)
+    span = max(1, nch // max(1, nshots))
+    shots = [Shot2D(src_iz=iz, src_ix=int(nx // 4 + span // 2 + span * k), M=_mt_components(rng, M0),
+                    ch_iz=ch_iz, ch_ix=ch_ix) for k in range(nshots)]
+    return Workload2D(name=f"differentiation-2d-{nz}x{nx}", nz=nz, nx=nx, dz=h, dx=h, dt=dt, nt=nt, npml=40,
+                      f0=60.0, vp_max=3800.0 * 1.05, stf=ricker(nt, dt, f0=60.0), m_start=m_start,
+                      m_true=m_true, shots=shots)
+
+
 def batched_2d(nshots=64, nt=4000, nz=1000, nx=3000, seed=64, M0=1.0e16, zrange=(400, 1000),
                xrange_=(800, 3000), npml=40):
     """64 shots on uneven subdomains (nz_s ~ U[400,1000], nx_s ~ U[800,3000]) cut around

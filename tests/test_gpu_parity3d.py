@@ -121,3 +121,58 @@ def test_batch_3d_equals_per_shot(gpu_lib, case):
     for k in range(2):
         g1, p1 = efwi.shot_gradient(grid, shots[k], m_ext[k], src[k], obs[k])
         assert torch.equal(g1, g2[k]) and p1.item() == p2[k].item()
+
+
+def test_full_size_sampled_3d(gpu_lib):
+    """The 3D precision workload at full size (300 x 400 x 400 at 5 m, 20-cell CPML, both DAS
+    wells, one six-component shot) for nt = 30 steps, with sqrt(nt) FP32 checkpoints and with
+    the FP16 checkpoints the timed sample uses. The wavefield travels about 10 cells, so the
+    oracle on an 80^3 crop centred on the source (its own CPML 20 cells from the source)
+    reproduces the data at the channels clear of the crop's CPML and the gradient in the
+    crop's interior; channels outside the crop carry zero data."""
+    efwi = gpu_lib
+    nt, c = 30, 80
+    w = inputs.precision_3d(nt=nt, nshots=1, anomalies=False)
+    sh = w.shots[0]
+    z0, y0, x0 = sh.src_iz - c // 2, sh.src_iy - c // 2, sh.src_ix - c // 2
+    assert min(z0, y0, x0) >= w.npml and max(z0 - w.nz, y0 - w.ny, x0 - w.nx) + c <= -w.npml
+    g_o = E3.Grid3D(nz=c, ny=c, nx=c, dz=r32(w.h), dy=r32(w.h), dx=r32(w.h), dt=r32(w.dt), nt=nt, npml=w.npml,
+                    pml_R=r32(w.pml_R), pml_f0=r32(w.f0), vp_max=r32(w.vp_max))
+    crop = (slice(None), slice(z0, z0 + c), slice(y0, y0 + c), slice(x0, x0 + c))
+    m_full = np.asarray(w.m_start, np.float32)
+    m = f32(m_full[crop])
+    scale = np.array([1.1, 1.05, 1.0])[:, None, None, None]
+    src = f32(np.outer(sh.M, w.stf))
+    def within(lo, hi):
+        return ((sh.ch_ix >= x0 + lo) & (sh.ch_ix < x0 + hi) & (sh.ch_iy >= y0 + lo) & (sh.ch_iy < y0 + hi)
+                & (sh.ch_iz >= z0 + lo) & (sh.ch_iz < z0 + hi))
+
+    # compared: channels clear of the crop's CPML; zero on both sides: channels outside the crop
+    inside, outside = within(w.npml + 2, c - w.npml - 2), ~within(0, c)
+    assert inside.sum() > 0 and outside.sum() > 0
+    pos = (sh.src_iz - z0, sh.src_iy - y0, sh.src_ix - x0)
+    ch = (sh.ch_iz[inside] - z0, sh.ch_iy[inside] - y0, sh.ch_ix[inside] - x0)
+    d_obs_c = f32(E3.model_forward(g_o, f32(m * scale), pos, src, ch))
+    g_ref, phi_o, d_o = E3.shot_gradient(g_o, m, pos, src, ch, d_obs_c)
+    d_obs = np.zeros((len(sh.ch_ix), nt))
+    d_obs[inside] = d_obs_c
+    kap = max(1.0, float(np.linalg.norm(d_o) / np.linalg.norm(d_o - d_obs_c)))
+    grid = efwi.make_grid3d(w.nz, w.ny, w.nx, w.h, w.h, w.h, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)
+    core = (slice(None), slice(z0 + 25, z0 + c - 25), slice(y0 + 25, y0 + c - 25), slice(x0 + 25, x0 + c - 25))
+    ccore = (slice(None), slice(25, c - 25), slice(25, c - 25), slice(25, c - 25))
+    mg, sg, og = T(m_full), T(src), T(d_obs)
+    del m_full
+    for mode, bar in ((efwi.CKPT_FP32, TOL * kap), (efwi.CKPT_FP16, 1e-3)):
+        shot = _shot(efwi, sh, ckpt_mode=mode)
+        d_out = torch.empty((len(sh.ch_ix), nt), dtype=torch.float32, device="cuda")
+        g, phi = efwi.shot_gradient(grid, shot, mg, sg, og, d_out=d_out)
+        torch.cuda.synchronize()
+        d = d_out.cpu().numpy()
+        assert rel(d[inside], d_o) <= TOL, mode
+        assert np.max(np.abs(d[outside])) <= 1e-6 * np.max(np.abs(d_o)), mode
+        gc = g[core].cpu().numpy()
+        for k in range(3):
+            e = rel(gc[k], g_ref[ccore][k])
+            assert e <= bar, (mode, k, e, kap)
+        assert abs(phi.item() - phi_o) / phi_o <= 2 * bar, mode
+        del g
