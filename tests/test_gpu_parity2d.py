@@ -322,3 +322,48 @@ def test_full_size_sampled(gpu_lib):
     for q in range(3):
         assert rel(g[core][q], g_o[ccore][q]) <= TOL * k, q
     assert abs(phi.item() - phi_o) / phi_o <= 2 * TOL * k
+
+
+def test_full_size_batched_64(gpu_lib):
+    """The 64-window batched workload at full size (windows nz ~ U[400,1000], nx ~
+    U[800,3000] of the 1000 x 3000 model, sqrt(nt) checkpoints, the bench's workspace rule)
+    for nt = 160: the batched gradients and misfits equal 64 per-shot calls bit for bit, and
+    the regularizer over the 64 components (hard sinkholes, eta = 1), which acts point by
+    point, matches the oracle at 3000 sampled points, a third of them inside sinkholes."""
+    efwi = gpu_lib
+    nt = 160
+    w = inputs.batched_2d(nshots=64, nt=nt)
+    grid = efwi.make_grid(w.nz, w.nx, w.dz, w.dx, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)
+    shots = [efwi.Shot(s.src_iz, s.src_ix, s.ch_iz, s.ch_ix, z0=s.z0, x0=s.x0, wz=s.wz, wx=s.wx) for s in w.shots]
+    ns, nz, nx = len(shots), w.nz, w.nx
+    m_start = T(w.m_start)
+    src = T(np.stack([np.outer(s.M, w.stf) for s in w.shots]))
+    d_obs = torch.cat([efwi.model_forward(grid, shots[k], T(w.m_true), src[k]) for k in range(ns)])
+    noise = T(np.stack([inputs.smooth_random_field((nz, nx), 20.0, 177 + k, 0.01) for k in range(3)]))
+    m_ext = torch.stack([m_start * (1.0 + torch.roll(noise, shifts=(0, 41 * k), dims=(1, 2))) for k in range(ns)])
+    del noise
+    need = efwi.workspace_size(efwi.WS_BATCH, grid, shots)
+    ws = efwi.workspace(min(need, int(torch.cuda.mem_get_info()[0] * 0.9)))
+    g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, d_obs, ws=ws)
+    del ws
+    g1 = torch.empty((3, nz, nx), dtype=torch.float32, device="cuda")
+    p1 = torch.empty((), dtype=torch.float64, device="cuda")
+    off = 0
+    for k in range(ns):
+        nch = len(w.shots[k].ch_ix)
+        efwi.shot_gradient(grid, shots[k], m_ext[k], src[k], d_obs[off:off + nch], g=g1, phi=p1)
+        off += nch
+        assert torch.equal(g1, g2[k]) and p1.item() == p2[k].item(), k
+    del g1, g2
+    b_np, sink_np = inputs.hard_sinkholes(ns, nz, nx, [s.src_iz for s in w.shots], [s.src_ix for s in w.shots])
+    g_reg = torch.zeros_like(m_ext)
+    efwi.extension_regularizer(grid, m_ext, T(b_np), torch.tensor(sink_np, device="cuda"), 1.0, g_reg)
+    rng = np.random.default_rng(64)
+    in_sink = np.flatnonzero(sink_np.any(0).ravel())
+    pts = np.concatenate([rng.choice(nz * nx, 2000, replace=False), rng.choice(in_sink, 1000, replace=False)])
+    idx = torch.tensor(pts, device="cuda")
+    m_s = m_ext.reshape(ns, 3, -1)[:, :, idx].cpu().numpy().astype(np.float64)
+    g_s = g_reg.reshape(ns, 3, -1)[:, :, idx].cpu().numpy().astype(np.float64)
+    b_s, k_s = b_np.reshape(ns, -1)[:, pts], sink_np.reshape(ns, -1)[:, pts]
+    _, g_o = R.regularizer(m_s, b_s, k_s, eta=1.0)
+    assert rel(g_s, g_o) <= TOL
