@@ -548,7 +548,7 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
 }
 
 template <bool GRAD>
-__global__ __launch_bounds__(TX * TY) void k3_adj_str(PARAMS3, int n, int kseg, int first) {
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(8, 8))) void k3_adj_str(PARAMS3, int n, int kseg, int first) {
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
     const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
