@@ -298,7 +298,8 @@ def vti_shot_form(efwi, inputs, torch, dev, w, m_start, src, d_obs_0):
 
 def precision_3d_sample(efwi, inputs, torch, dev, nt=200):
     """One shot of the 3D precision workload on its full 300 x 400 x 400 grid (5 m, CPML 20,
-    2000 DAS channels on two wells, six-component moment tensor), nt steps of the 3000 with
+    two DAS wells along x with a channel at every interior node, 356 each and 712 in all,
+    six-component moment tensor), nt steps of the 3000 with
     sqrt(nt) FP16 checkpoints, d_obs = 0; timed once after one untimed call. path_frac: the
     algorithmic bytes per cell-step without the CPML memory variables (forward 140 B:
     velocity 60, stress 80; recomputed step with the history 176 B; transposed step with the

@@ -295,13 +295,18 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
     return fail(EFWI_E_RANGE, "shot %d: window outside the model", index);
   if (w.wz < 2 * P + 4 || w.wx < 2 * P + 4 || (three && w.wy < 2 * P + 4))
     return fail(EFWI_E_RANGE, "shot %d: window too small for %d CPML cells", index, g.npml);
-  if (three) {  // the 3D kernels address a shot's arrays with 32-bit byte offsets
+  {  // the kernels address a shot's arrays with 32-bit byte offsets from uniform bases
     const long ld = (XOFF + w.wx + HALO + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
     const long cp = (w.wx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN;
-    const long padded = (long)(w.wz + 2 * HALO) * (w.wy + 2 * HALO) * ld, cells = (long)w.wz * w.wy * cp;
-    if (padded >= (1L << 30) || (long)NSEG3 * cells >= (1L << 30))
-      return fail(EFWI_E_RANGE, "shot %d: 3D window of %ld cells is beyond this library's 2^30-element arrays", index,
-                  cells);
+    const long padded = (long)(w.wz + 2 * HALO) * (three ? w.wy + 2 * HALO : 1) * ld;
+    const long cells = (long)w.wz * w.wy * cp;
+    // per-cell arrays addressed from one base: the history slots of a step and the imaging
+    // sums (2D: NSEG_FIELDS and up to NACC_VTI; 3D: NSEG3 and NACC3), and the CPML strips
+    const long per_cell = three ? std::max(NSEG3, NACC3) : std::max(NSEG_FIELDS, NACC_VTI);
+    const long strips = three ? 0 : 4L * ((long)w.wz * 2 * P + (long)2 * P * w.wx);
+    if (padded >= (1L << 30) || per_cell * cells >= (1L << 30) || strips >= (1L << 30))
+      return fail(EFWI_E_RANGE, "shot %d: window of %ld cells is beyond this library's 2^30-element arrays", index,
+                  (long)w.wz * w.wy * w.wx);
   }
   const int si = s->src_iz - w.z0, sj = s->src_ix - w.x0, sk = three ? s->src_iy - w.y0 : 0;
   if (si < P + 1 || si > w.wz - P - 1 || sj < P + 1 || sj > w.wx - P - 1 ||

@@ -238,6 +238,72 @@ def _f32(t, name):
     return t
 
 
+# The C ABI takes raw pointers: every tensor is checked here, before its pointer is passed,
+# for dtype, exact shape (or element count) and contiguity, and then all of a call's tensors
+# for being device tensors on one device, so that a wrongly shaped or placed tensor raises
+# instead of becoming an out-of-bounds device access. (Shapes are checked first so that the
+# checks can be exercised without a GPU.)
+def _arg(t, name, shape, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype:
+        raise TypeError(f"{name} must be a {dtype} tensor")
+    want = tuple(int(x) for x in shape)
+    if tuple(t.shape) != want:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {want}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _opt(t, name, shape, dtype=torch.float32):
+    return None if t is None else _arg(t, name, shape, dtype)
+
+
+def _flat(t, name, numel, dtype=torch.float32):
+    """A tensor of any shape holding exactly numel contiguous elements (concatenated data)."""
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype:
+        raise TypeError(f"{name} must be a {dtype} tensor")
+    if t.numel() != int(numel):
+        raise ValueError(f"{name} holds {t.numel()} elements, expected {int(numel)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ws(ws):
+    if not isinstance(ws, torch.Tensor) or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise TypeError("ws must be a contiguous uint8 tensor (see workspace())")
+    return ws
+
+
+def _device(**tensors):
+    """The one device of a call's tensors (None entries are skipped)."""
+    dev = None
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{name} is on {t.device}, the call's other tensors on {dev}")
+    return dev
+
+
+def space(grid: Grid):
+    """Grid points of one model parameter: (nz, nx), or (nz, ny, nx) in 3D."""
+    return (grid.nz, grid.ny, grid.nx) if grid.ndim == 3 else (grid.nz, grid.nx)
+
+
+def model_shape(grid: Grid):
+    """(3, nz, nx) or (3, nz, ny, nx): a model (Vp, Vs, rho) or its gradient."""
+    return (3,) + space(grid)
+
+
+def _data_shape(grid: Grid, shot) -> tuple:
+    return tuple(shot.data_shape(grid.nt))
+
+
 def validate(grid: Grid, shots) -> None:
     arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
     _check(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr))
@@ -276,7 +342,9 @@ def autotune(grid: Grid, shot: Shot, m, src, steps: int = 16, stream=None, times
     """Time the shot's forward and transposed sweeps over `steps` steps for each tile height,
     keep the fastest for each (process-wide) and return (fwd_rows, adj_rows). With a dict
     `times`, also fill {rows: (forward ms, transposed ms)}."""
-    _f32(m, "m"), _f32(src, "src")
+    _arg(m, "m", model_shape(grid))
+    _arg(src, "src", (n_components(grid), grid.nt))
+    _device(m=m, src=src)
     sc = shot.c_struct()
     need = _lib.efwi_autotune_workspace_size(ctypes.byref(grid), ctypes.byref(sc), int(steps))
     if need == 0:
@@ -309,12 +377,16 @@ def workspace(nbytes: int, device=None) -> torch.Tensor:
 def model_forward(grid: Grid, shot: Shot, m, src, d=None, ws=None, stream=None):
     """d = K u(m): DAS data of one shot, shot.data_shape(nt) (point strain [nch][nt] by
     default)."""
-    _f32(m, "m"), _f32(src, "src")
+    _arg(m, "m", model_shape(grid))
+    dev = m.device
+    _arg(src, "src", (n_components(grid), grid.nt))
     if d is None:
-        d = torch.empty(shot.data_shape(grid.nt), dtype=torch.float32, device=m.device)
+        d = torch.empty(shot.data_shape(grid.nt), dtype=torch.float32, device=dev)
+    _arg(d, "d", _data_shape(grid, shot))
+    _device(m=m, src=src, d=d, ws=ws)
     sc = shot.c_struct()
     need = _lib.efwi_workspace_size(WS_FORWARD, ctypes.byref(grid), 1, ctypes.byref(sc))
-    ws = ws if ws is not None else workspace(need, m.device)
+    ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_model_forward(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(d), _ptr(ws),
                                    ws.numel(), _stream(stream)))
     return d
@@ -322,12 +394,16 @@ def model_forward(grid: Grid, shot: Shot, m, src, d=None, ws=None, stream=None):
 
 def model_adjoint(grid: Grid, shot: Shot, m, r, src_bar=None, ws=None, stream=None):
     """L^T r with respect to the [3][nt] source components."""
-    _f32(m, "m"), _f32(r, "r")
+    _arg(m, "m", model_shape(grid))
+    dev = m.device
+    _arg(r, "r", _data_shape(grid, shot))
     if src_bar is None:
-        src_bar = torch.empty((n_components(grid), grid.nt), dtype=torch.float32, device=m.device)
+        src_bar = torch.empty((n_components(grid), grid.nt), dtype=torch.float32, device=dev)
+    _arg(src_bar, "src_bar", (n_components(grid), grid.nt))
+    _device(m=m, r=r, src_bar=src_bar, ws=ws)
     sc = shot.c_struct()
     need = _lib.efwi_workspace_size(WS_ADJOINT, ctypes.byref(grid), 1, ctypes.byref(sc))
-    ws = ws if ws is not None else workspace(need, m.device)
+    ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_model_adjoint(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(r), _ptr(src_bar),
                                    _ptr(ws), ws.numel(), _stream(stream)))
     return src_bar
@@ -335,14 +411,21 @@ def model_adjoint(grid: Grid, shot: Shot, m, r, src_bar=None, ws=None, stream=No
 
 def shot_gradient(grid: Grid, shot: Shot, m, src, d_obs, g=None, phi=None, d_out=None, ws=None, stream=None):
     """Misfit phi_s (device double) and gradient g_s [3][nz][nx] w.r.t. (Vp, Vs, rho)."""
-    _f32(m, "m"), _f32(src, "src"), _f32(d_obs, "d_obs")
+    _arg(m, "m", model_shape(grid))
+    dev = m.device
+    _arg(src, "src", (n_components(grid), grid.nt))
+    _arg(d_obs, "d_obs", _data_shape(grid, shot))
     if g is None:
         g = torch.empty_like(m)
     if phi is None:
-        phi = torch.empty((), dtype=torch.float64, device=m.device)
+        phi = torch.empty((), dtype=torch.float64, device=dev)
+    _arg(g, "g", model_shape(grid))
+    _flat(phi, "phi", 1, torch.float64)
+    _opt(d_out, "d_out", _data_shape(grid, shot))
+    _device(m=m, src=src, d_obs=d_obs, g=g, phi=phi, d_out=d_out, ws=ws)
     sc = shot.c_struct()
     need = _lib.efwi_workspace_size(WS_GRADIENT, ctypes.byref(grid), 1, ctypes.byref(sc))
-    ws = ws if ws is not None else workspace(need, m.device)
+    ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_shot_gradient(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(d_obs), _ptr(g),
                                    _ptr(phi), _ptr(d_out), _ptr(ws), ws.numel(), _stream(stream)))
     return g, phi
@@ -350,12 +433,18 @@ def shot_gradient(grid: Grid, shot: Shot, m, src, d_obs, g=None, phi=None, d_out
 
 def shot_jt(grid: Grid, shot: Shot, m, src, v, g=None, d_out=None, ws=None, stream=None):
     """g = J_s^T v for a data-space vector v [nch][nt] (backward of m -> d)."""
-    _f32(m, "m"), _f32(src, "src"), _f32(v, "v")
+    _arg(m, "m", model_shape(grid))
+    dev = m.device
+    _arg(src, "src", (n_components(grid), grid.nt))
+    _arg(v, "v", _data_shape(grid, shot))
     if g is None:
         g = torch.empty_like(m)
+    _arg(g, "g", model_shape(grid))
+    _opt(d_out, "d_out", _data_shape(grid, shot))
+    _device(m=m, src=src, v=v, g=g, d_out=d_out, ws=ws)
     sc = shot.c_struct()
     need = _lib.efwi_workspace_size(WS_GRADIENT, ctypes.byref(grid), 1, ctypes.byref(sc))
-    ws = ws if ws is not None else workspace(need, m.device)
+    ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_shot_jt(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(v), _ptr(g),
                              _ptr(d_out), _ptr(ws), ws.numel(), _stream(stream)))
     return g
@@ -364,16 +453,23 @@ def shot_jt(grid: Grid, shot: Shot, m, src, v, g=None, d_out=None, ws=None, stre
 def batch_gradient(grid: Grid, shots, m_ext, src, d_obs, g_ext=None, phi=None, ws=None, stream=None):
     """Data term of the extended misfit for all shots: g_ext[s] = J_s^T r_s on m_ext[s]."""
     shots = list(shots)
-    _f32(m_ext, "m_ext"), _f32(src, "src"), _f32(d_obs, "d_obs")
+    ns = len(shots)
+    _arg(m_ext, "m_ext", (ns,) + model_shape(grid))
+    dev = m_ext.device
+    _arg(src, "src", (ns, n_components(grid), grid.nt))
+    _flat(d_obs, "d_obs", sum(int(np.prod(_data_shape(grid, s))) for s in shots))
     if g_ext is None:
         g_ext = torch.empty_like(m_ext)
     if phi is None:
-        phi = torch.empty((len(shots),), dtype=torch.float64, device=m_ext.device)
+        phi = torch.empty((ns,), dtype=torch.float64, device=dev)
+    _arg(g_ext, "g_ext", (ns,) + model_shape(grid))
+    _flat(phi, "phi", ns, torch.float64)
+    _device(m_ext=m_ext, src=src, d_obs=d_obs, g_ext=g_ext, phi=phi, ws=ws)
     arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
     need = _lib.efwi_workspace_size(WS_BATCH, ctypes.byref(grid), len(shots), arr)
     if need == 0:
         _check(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr))
-    ws = ws if ws is not None else workspace(need, m_ext.device)
+    ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_batch_gradient(ctypes.byref(grid), len(shots), arr, _ptr(m_ext), _ptr(src), _ptr(d_obs),
                                     _ptr(g_ext), _ptr(phi), _ptr(ws), ws.numel(), _stream(stream)))
     return g_ext, phi
@@ -387,16 +483,28 @@ def batch_gradient_grouped(grid: Grid, shots, groups, m_ext, src, d_obs, g_ext=N
     grp = np.ascontiguousarray(groups, dtype=np.int32)
     if grp.shape != (len(shots),):
         raise ValueError("one group index per shot")
-    _f32(m_ext, "m_ext"), _f32(src, "src"), _f32(d_obs, "d_obs")
+    ns = len(shots)
+    if not isinstance(m_ext, torch.Tensor) or m_ext.dim() < 1:
+        raise TypeError("m_ext must be a [ng][3][...] tensor")
+    ng = int(m_ext.shape[0])
+    _arg(m_ext, "m_ext", (ng,) + model_shape(grid))
+    dev = m_ext.device
+    if ns and (grp.min() < 0 or grp.max() >= ng):
+        raise ValueError(f"group indices must lie in [0, {ng})")
+    _arg(src, "src", (ns, n_components(grid), grid.nt))
+    _flat(d_obs, "d_obs", sum(int(np.prod(_data_shape(grid, s))) for s in shots))
     if g_ext is None:
         g_ext = torch.empty_like(m_ext)
     if phi is None:
-        phi = torch.empty((len(shots),), dtype=torch.float64, device=m_ext.device)
+        phi = torch.empty((ns,), dtype=torch.float64, device=dev)
+    _arg(g_ext, "g_ext", (ng,) + model_shape(grid))
+    _flat(phi, "phi", ns, torch.float64)
+    _device(m_ext=m_ext, src=src, d_obs=d_obs, g_ext=g_ext, phi=phi, ws=ws)
     arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
     need = _lib.efwi_workspace_size(WS_BATCH, ctypes.byref(grid), len(shots), arr)
     if need == 0:
         _check(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr))
-    ws = ws if ws is not None else workspace(need, m_ext.device)
+    ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_batch_gradient_grouped(ctypes.byref(grid), len(shots), arr,
                                             grp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), m_ext.shape[0],
                                             _ptr(m_ext), _ptr(src), _ptr(d_obs), _ptr(g_ext), _ptr(phi), _ptr(ws),
@@ -418,14 +526,20 @@ def batch_waves(grid: Grid, shots, ws_bytes: int):
 
 def extension_regularizer(grid: Grid, m_ext, b, sink, eta, g_ext, phi=None, ws=None, stream=None):
     """phi_reg (device double) and g_ext += gradient of 1/2 eta^2 ||(I - S^T S_w) W m~||^2."""
-    _f32(m_ext, "m_ext"), _f32(b, "b"), _f32(g_ext, "g_ext")
-    if sink.dtype != torch.uint8:
-        raise TypeError("sink must be uint8")
-    ns = m_ext.shape[0]
+    if not isinstance(m_ext, torch.Tensor) or m_ext.dim() < 1:
+        raise TypeError("m_ext must be a [ns][3][...] tensor")
+    ns = int(m_ext.shape[0])
+    _arg(m_ext, "m_ext", (ns,) + model_shape(grid))
+    dev = m_ext.device
+    _arg(b, "b", (ns,) + space(grid))
+    _arg(sink, "sink", (ns,) + space(grid), torch.uint8)
+    _arg(g_ext, "g_ext", (ns,) + model_shape(grid))
     if phi is None:
-        phi = torch.empty((), dtype=torch.float64, device=m_ext.device)
+        phi = torch.empty((), dtype=torch.float64, device=dev)
+    _flat(phi, "phi", 1, torch.float64)
+    _device(m_ext=m_ext, b=b, sink=sink, g_ext=g_ext, phi=phi, ws=ws)
     need = _lib.efwi_workspace_size(WS_REGULARIZER, ctypes.byref(grid), 0, None)
-    ws = ws if ws is not None else workspace(need, m_ext.device)
+    ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_extension_regularizer(ctypes.byref(grid), ns, _ptr(m_ext), _ptr(b), _ptr(sink),
                                            float(eta), _ptr(g_ext), _ptr(phi), _ptr(ws), ws.numel(),
                                            _stream(stream)))
@@ -472,9 +586,9 @@ def zoi_weights(grid: Grid, zones, n, nu, b=None, sink=None, device=None, stream
         b = torch.empty((len(zones),) + shape, dtype=torch.float32, device=dev)
     if sink is None:
         sink = torch.empty((len(zones),) + shape, dtype=torch.uint8, device=b.device)
-    _f32(b, "b")
-    if sink.dtype != torch.uint8:
-        raise TypeError("sink must be uint8")
+    _arg(b, "b", (len(zones),) + shape)
+    _arg(sink, "sink", (len(zones),) + shape, torch.uint8)
+    _device(b=b, sink=sink)
     arr = (Zone * len(zones))(*zones)
     _check(_lib.efwi_zoi_weights(ctypes.byref(grid), len(zones), arr, float(n), float(nu), _ptr(b), _ptr(sink),
                                  _stream(stream)))
@@ -483,12 +597,17 @@ def zoi_weights(grid: Grid, zones, n, nu, b=None, sink=None, device=None, stream
 
 def final_model(grid: Grid, m_ext, b, sink, m_out=None, stream=None):
     """Physical model S_w W m~ of eq.(9), [3][...] FP32."""
-    _f32(m_ext, "m_ext"), _f32(b, "b")
-    if sink.dtype != torch.uint8:
-        raise TypeError("sink must be uint8")
+    if not isinstance(m_ext, torch.Tensor) or m_ext.dim() < 1:
+        raise TypeError("m_ext must be a [ns][3][...] tensor")
+    ns = int(m_ext.shape[0])
+    _arg(m_ext, "m_ext", (ns,) + model_shape(grid))
+    dev = m_ext.device
+    _arg(b, "b", (ns,) + space(grid))
+    _arg(sink, "sink", (ns,) + space(grid), torch.uint8)
     if m_out is None:
-        m_out = torch.empty(m_ext.shape[1:], dtype=torch.float32, device=m_ext.device)
-    _f32(m_out, "m_out")
+        m_out = torch.empty(model_shape(grid), dtype=torch.float32, device=dev)
+    _arg(m_out, "m_out", model_shape(grid))
+    _device(m_ext=m_ext, b=b, sink=sink, m_out=m_out)
     _check(_lib.efwi_final_model(ctypes.byref(grid), m_ext.shape[0], _ptr(m_ext), _ptr(b), _ptr(sink), _ptr(m_out),
                                  _stream(stream)))
     return m_out
@@ -501,26 +620,30 @@ def bspline_nodes(n: int, spacing: int) -> int:
 
 def bspline_expand(c, nz: int, nx: int, dz_nodes: int, dx_nodes: int, out=None, stream=None):
     """Model planes [..][nz][nx] from cubic B-spline coefficients c [..][Nz][Nx]."""
-    _f32(c, "c")
-    lead = c.shape[:-2]
+    if not isinstance(c, torch.Tensor) or c.dim() < 2:
+        raise TypeError("c must be a [..][Nz][Nx] tensor")
+    lead = tuple(c.shape[:-2])
+    _arg(c, "c", lead + (bspline_nodes(nz, dz_nodes), bspline_nodes(nx, dx_nodes)))
     if out is None:
         out = torch.empty(lead + (nz, nx), dtype=torch.float32, device=c.device)
-    _f32(out, "out")
+    _arg(out, "out", lead + (nz, nx))
+    _device(c=c, out=out)
     np_ = int(np.prod(lead)) if len(lead) else 1
-    if c.shape[-2:] != (bspline_nodes(nz, dz_nodes), bspline_nodes(nx, dx_nodes)):
-        raise ValueError("coefficient planes must be [Nz][Nx] for these spacings")
     _check(_lib.efwi_bspline_expand(nz, nx, dz_nodes, dx_nodes, np_, _ptr(c), _ptr(out), _stream(stream)))
     return out
 
 
 def bspline_adjoint(g, dz_nodes: int, dx_nodes: int, out=None, stream=None):
     """Coefficient gradients [..][Nz][Nx] from model-plane gradients g [..][nz][nx]."""
-    _f32(g, "g")
-    lead, (nz, nx) = g.shape[:-2], g.shape[-2:]
+    if not isinstance(g, torch.Tensor) or g.dim() < 2:
+        raise TypeError("g must be a [..][nz][nx] tensor")
+    lead, (nz, nx) = tuple(g.shape[:-2]), tuple(g.shape[-2:])
+    _arg(g, "g", lead + (nz, nx))
     shape = lead + (bspline_nodes(nz, dz_nodes), bspline_nodes(nx, dx_nodes))
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=g.device)
-    _f32(out, "out")
+    _arg(out, "out", shape)
+    _device(g=g, out=out)
     np_ = int(np.prod(lead)) if len(lead) else 1
     _check(_lib.efwi_bspline_adjoint(nz, nx, dz_nodes, dx_nodes, np_, _ptr(g), _ptr(out), _stream(stream)))
     return out
@@ -528,10 +651,11 @@ def bspline_adjoint(g, dz_nodes: int, dx_nodes: int, out=None, stream=None):
 
 def das_field(grid: Grid, shot: Shot, e, out=None, stream=None):
     """Field data K e of the shot's DAS sampling from point strains e [nch][nt]."""
-    _f32(e, "e")
+    _arg(e, "e", (shot.nch, grid.nt))
     if out is None:
         out = torch.empty(shot.data_shape(grid.nt), dtype=torch.float32, device=e.device)
-    _f32(out, "out")
+    _arg(out, "out", _data_shape(grid, shot))
+    _device(e=e, out=out)
     sc = shot.c_struct()
     _check(_lib.efwi_das_field(ctypes.byref(grid), ctypes.byref(sc), _ptr(e), _ptr(out), _stream(stream)))
     return out
@@ -541,23 +665,21 @@ def pseudo_hessian(grid: Grid, shots, m_ext, src, clip, h=None, p=None, ws=None,
     """Approximate inverse pseudo-Hessian (efwi_pseudo_hessian): returns (h, p), the summed
     velocity autocorrelation and the clipped, scaled inverse, [nz][nx] FP32 each."""
     shots = list(shots)
-    _f32(m_ext, "m_ext"), _f32(src, "src")
-    shape = (grid.nz, grid.nx)
-    h = h if h is not None else torch.empty(shape, dtype=torch.float32, device=m_ext.device)
-    p = p if p is not None else torch.empty(shape, dtype=torch.float32, device=m_ext.device)
-    _f32(h, "h"), _f32(p, "p")
+    ns = len(shots)
+    _arg(m_ext, "m_ext", (ns,) + model_shape(grid))
+    dev = m_ext.device
+    _arg(src, "src", (ns, n_components(grid), grid.nt))
+    shape = space(grid)
+    h = h if h is not None else torch.empty(shape, dtype=torch.float32, device=dev)
+    p = p if p is not None else torch.empty(shape, dtype=torch.float32, device=dev)
+    _arg(h, "h", shape), _arg(p, "p", shape)
+    _device(m_ext=m_ext, src=src, h=h, p=p, ws=ws)
     arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
     need = _lib.efwi_workspace_size(WS_BATCH, ctypes.byref(grid), len(shots), arr)
     if need == 0:
         _check(_lib.efwi_validate(ctypes.byref(grid), len(shots), arr))
-    ws = ws if ws is not None else workspace(need, m_ext.device)
+    ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_pseudo_hessian(ctypes.byref(grid), len(shots), arr, _ptr(m_ext), _ptr(src), float(clip), _ptr(h),
                                     _ptr(p), _ptr(ws), ws.numel(), _stream(stream)))
     return h, p
 
-
-def source_components(M, stf) -> np.ndarray:
-    """Source components x moment-rate samples: [3][nt] for (M_xx, M_zz, M_xz) in 2D,
-    [6][nt] for (M_xx, M_yy, M_zz, M_xy, M_xz, M_yz) in 3D."""
-    M = np.asarray(M, np.float64)
-    return np.outer(M, np.asarray(stf, np.float64)).astype(np.float32)

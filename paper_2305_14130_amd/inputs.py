@@ -314,7 +314,9 @@ def precision_3d(nz=300, ny=400, nx=400, nt=3000, nshots=8, nch_per_well=1000, h
     """The shale geology at 5 m in 3D: background Vp 3800, Vs/Vp 0.6, rho 2550 with a 15 m
     (3-cell) reservoir Vp 3400, Vs/Vp 0.55, rho 2450 at mid depth, +-5% Gaussian-correlated
     anomalies (50 m) in the true model, moment-tensor shots (six components, seed 8) in the
-    layer and two horizontal DAS wells along x at y = 3/8 and 5/8 of the width."""
+    layer and two horizontal DAS wells along x at y = 3/8 and 5/8 of the width. A well holds
+    at most one channel per interior node along x: on the 400-node axis that is 356 per well
+    (712 in all), fewer than the nch_per_well = 1000 asked for, which is then capped."""
     res_top = nz // 2 - 1
     m = _shale_model(nz, nx, h, res_top, res_top + 3, anomalies=False)[:, :, None, :]
     m_start = np.repeat(m, ny, axis=2).transpose(0, 1, 2, 3)            # [3][nz][ny][nx]

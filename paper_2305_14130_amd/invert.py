@@ -372,6 +372,7 @@ def synthetic_comparison(source_errors=False, eta_rel=1.0, max_iter=60, rate_tol
         x, rec = lbfgs(prob, prob.x0(), max_iter=max_iter, rate_tol=rate_tol, first_step=0.01, h0=h0)
         m = prob.final(x).cpu().numpy().astype(np.float64)
         pert = (m[:2] - w.m_start[:2]) / w.m_start[:2]
+        prob(x)   # the data misfit of the accepted iterate (the last evaluation may be a rejected trial)
         out[name] = {"iterations": len(rec.rate), "evaluations": rec.evaluations, "stop": rec.stop,
                      "phi": [rec.phi[0], rec.phi[-1]], "data_phi_final": prob.data_phi,
                      "cs_vp": cosine_similarity(pert[0][interior[1:]], true_pert[0][interior[1:]]),

@@ -278,3 +278,18 @@ def test_3d_window_size_limit(efwi):
     small = efwi.Shot(500, 500, [501], [520], src_iy=500, ch_iy=[500], z0=300, y0=300, x0=300, wz=400, wy=400, wx=400)
     arr = (efwi._ShotC * 1)(small.c_struct())
     assert efwi._lib.efwi_validate(ctypes.byref(g), 1, arr) == efwi.OK
+
+
+def test_2d_window_size_limit(efwi):
+    """The 2D kernels address a shot's history slots and imaging sums with 32-bit byte
+    offsets from one base: a window whose 5 * cells reaches 2^30 elements (about 2.1e8 cells)
+    is refused on the host, before any launch; the largest workloads here pass."""
+    g = efwi.make_grid(12000, 20000, 5.0, 5.0, 0.5e-3, 10, 20, 1e-3, 30.0, 4500.0)
+    shot = efwi.Shot(6000, 10000, [6001], [10020])
+    arr = (efwi._ShotC * 1)(shot.c_struct())
+    assert efwi._lib.efwi_validate(ctypes.byref(g), 1, arr) == efwi.E_RANGE
+    assert b"2^30" in efwi._lib.efwi_last_error()
+    for wz, wx in ((1200, 4000), (6000, 6000)):   # 4.8e6 and 3.6e7 cells: accepted
+        ok = efwi.Shot(6000, 10000, [6001], [10020], z0=6000 - wz // 2, x0=10000 - wx // 2, wz=wz, wx=wx)
+        arr = (efwi._ShotC * 1)(ok.c_struct())
+        assert efwi._lib.efwi_validate(ctypes.byref(g), 1, arr) == efwi.OK

@@ -114,3 +114,30 @@ def test_degenerate_points():
     phi, g = R.regularizer(np.ones((2, 3, 1)) * np.array([1.0, 2.0])[:, None, None],
                            np.zeros((2, 1)), np.zeros((2, 1), bool), 1.0)
     assert phi == 0.0 and np.all(g == 0.0)
+
+
+def test_soft_weight_sinkhole_by_hand():
+    """A point worked by hand from eqs.(9), (11) and (12) with soft weights inside a
+    sinkhole: Ns = 3, b = (0.2, 0.5, 1.0), source 0's sinkhole covers the point, m = (1, 2, 4).
+
+    eq.(11): (W m)_0 = 0.2 * 1 + 0.8 * (0.5 * 2 + 1.0 * 4) / 1.5 = 43/15; rows 1, 2 unchanged.
+    eq.(12): b' = (1, 0.5, 1.0) (b'_0 = 1 inside source 0's sinkhole), sum 5/2, so
+    S_w W m = (43/15 + 1 + 4) / (5/2) = 236/75 (b'_0 = b_0 would give 3.2784...).
+    y = W m - S^T S_w W m = (-21, -86, 64) / 75; phi = 1/2 |y|^2 = 11933/11250 (eta = 1).
+    z = y - (b'/sum b') sum(y) = (-19, -387, 406) / 375 and g = W^T z =
+    (-19/1875, -5881/5625, 5938/5625)."""
+    b = np.array([0.2, 0.5, 1.0])[:, None]
+    sink = np.array([True, False, False])[:, None]
+    m = np.array([1.0, 2.0, 4.0])
+    scale = np.array([1.0, -3.0, 0.5])                      # Vp, Vs, rho: same weights
+    m_ext = (m[:, None] * scale[None, :])[:, :, None]        # [3 shots][3 params][1 point]
+    assert np.allclose(R.w_matrix(b[:, 0], sink[:, 0]) @ m, [43 / 15, 2.0, 4.0], rtol=0, atol=1e-14)
+    assert np.allclose(R.sw_row(b[:, 0], sink[:, 0]), [0.4, 0.2, 0.4], rtol=0, atol=1e-15)
+    assert np.allclose(R.final_model(m_ext, b, sink)[:, 0], 236 / 75 * scale, rtol=1e-14)
+    phi, g = R.regularizer(m_ext, b, sink, eta=1.0)
+    assert np.isclose(phi, 11933 / 11250 * float(np.sum(scale ** 2)), rtol=1e-13)
+    g_hand = np.array([-19 / 1875, -5881 / 5625, 5938 / 5625])
+    assert np.allclose(g[:, :, 0], g_hand[:, None] * scale[None, :], rtol=1e-13, atol=1e-15)
+    # eta scales the value by eta^2 and the gradient by eta^2
+    phi2, g2 = R.regularizer(m_ext, b, sink, eta=3.0)
+    assert np.isclose(phi2, 9.0 * phi, rtol=1e-13) and np.allclose(g2, 9.0 * g, rtol=1e-13)
