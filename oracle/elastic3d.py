@@ -309,3 +309,85 @@ def shot_gradient(grid, m, src_pos, src, ch, d_obs):
     phi, r = misfit(d, d_obs)
     _, grads = adjoint(grid, m, src_pos, ch, r, hist=hist)
     return chain_rule(m, grads), phi, d
+
+
+# ---------------------------------------------------------------------------------------
+# Checkpointed gradient: the wavefield-recomputation schedule, optionally with 16-bit
+# snapshots, so that the compressed-checkpoint modes can be compared with this function at
+# FP32 parity (and with ``shot_gradient`` for the error the compression itself causes).
+# ---------------------------------------------------------------------------------------
+def _snapshot(P, codec):
+    from .checkpoint import roundtrip
+    snap = {f: roundtrip(getattr(P, f), codec) for f in FIELDS}
+    snap["psi"] = {k: roundtrip(v, codec) for k, v in P.psi.items()}
+    return snap
+
+
+def _restore(P, snap):
+    for f in FIELDS:
+        setattr(P, f, snap[f].copy())
+    P.psi = {k: v.copy() for k, v in snap["psi"].items()}
+
+
+class _RecomputedHistory:
+    """The forward quantities of step n, as ``adjoint`` asks for them (n descending): the
+    last segment's from the first sweep, every other segment's recomputed from its (decoded)
+    snapshot when its first step is asked for; segment 0 starts from the exact zero state."""
+
+    def __init__(self, grid, m, src_pos, src, L, snaps, last0, last_hist):
+        self.grid, self.m, self.src_pos, self.src, self.L = grid, m, src_pos, src, L
+        self.snaps, self.last0, self.last_hist = snaps, last0, last_hist
+        self.k, self.seg = None, None
+
+    def __bool__(self):
+        return True
+
+    def __getitem__(self, n):
+        if n >= self.last0:
+            return self.last_hist[n - self.last0]
+        k = n // self.L
+        if k != self.k:
+            Q = Propagator3D(self.grid, *self.m)
+            if k > 0:
+                _restore(Q, self.snaps[k])
+            self.seg = []
+            for j in range(k * self.L, min(self.grid.nt, (k + 1) * self.L)):
+                qs = Q.velocity_half_step()
+                p, ps = Q.stress_half_step()
+                Q.inject(*self.src_pos, self.src[:, j])
+                self.seg.append((p, ps, qs))
+            self.k = k
+        return self.seg[n - k * self.L]
+
+
+def shot_gradient_checkpointed(grid, m, src_pos, src, ch, d_obs, interval, codec=None):
+    """``shot_gradient`` with the forward state (nine fields and the CPML memory variables)
+    snapshotted at the start of every segment of `interval` steps but the first and the last,
+    each field encoded by ``checkpoint.roundtrip(., codec)``; the last segment's forward
+    quantities are kept from the first sweep and the others recomputed from their snapshots
+    during the transposed sweep. With codec None this equals ``shot_gradient`` to round-off.
+
+    Returns (g[3][nz][ny][nx], phi, d)."""
+    g = grid
+    L = max(1, min(int(interval), g.nt))
+    nseg = (g.nt + L - 1) // L
+    last0 = (nseg - 1) * L
+    P = Propagator3D(g, m[0], m[1], m[2])
+    ch = tuple(np.asarray(c) for c in ch)
+    d = np.zeros((len(ch[0]), g.nt))
+    e = np.zeros(len(ch[0]))
+    snaps, last_hist = {}, []
+    for n in range(g.nt):
+        if n % L == 0 and 0 < n < last0:
+            snaps[n // L] = _snapshot(P, codec)
+        qs = P.velocity_half_step()
+        p, ps = P.stress_half_step()
+        P.inject(*src_pos, src[:, n])
+        e = e + g.dt * P.strain_rate_xx(ch)
+        d[:, n] = e
+        if n >= last0:
+            last_hist.append((p, ps, qs))
+    phi, r = misfit(d, d_obs)
+    hist = _RecomputedHistory(g, m, src_pos, src, L, snaps, last0, last_hist)
+    _, grads = adjoint(g, m, src_pos, ch, r, hist=hist)
+    return chain_rule(m, grads), phi, d

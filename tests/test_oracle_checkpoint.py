@@ -66,3 +66,37 @@ def test_compressed_snapshots_perturb_gradient_slightly(codec, lo, hi):
     for k in range(3):
         e = np.linalg.norm(g1[k] - g0[k]) / np.linalg.norm(g0[k])
         assert lo < e < hi, (codec, k, e)
+
+
+def _case3d(nt=48):
+    from oracle import elastic3d as E3
+    from paper_2305_14130_amd.inputs import ricker
+    rng = np.random.default_rng(5)
+    shape = (18, 20, 22)
+    vp = 3000.0 * (1 + 0.05 * rng.standard_normal(shape))
+    m = np.stack([vp, vp / 1.7, 2300.0 * (1 + 0.04 * rng.standard_normal(shape))])
+    g = E3.Grid3D(*shape, 5.0, 5.0, 5.0, 0.4e-3, nt, npml=4, pml_f0=40.0, vp_max=3600.0)
+    src = E3.moment_tensor_series([1.0, -0.4, 0.7, 0.3, -0.2, 0.5], ricker(nt, g.dt, 60.0) * 1e9)
+    pos = (9, 10, 8)
+    ch = (np.full(6, 9), np.full(6, 11), np.arange(7, 13))
+    d_obs = E3.model_forward(g, m * np.array([1.05, 1.02, 1.0])[:, None, None, None], pos, src, ch)
+    return E3, g, m, pos, src, ch, d_obs
+
+
+def test_checkpointed_schedule_equals_full_history_3d():
+    E3, g, m, pos, src, ch, d_obs = _case3d()
+    g0, phi0, d0 = E3.shot_gradient(g, m, pos, src, ch, d_obs)
+    for L in (7, 16, 48):
+        g1, phi1, d1 = E3.shot_gradient_checkpointed(g, m, pos, src, ch, d_obs, L)
+        assert np.array_equal(d0, d1) and phi0 == phi1
+        assert np.max(np.abs(g1 - g0)) <= 1e-12 * np.max(np.abs(g0)), L
+
+
+@pytest.mark.parametrize("codec,lo,hi", [("fp16", 1e-9, 1e-3), ("bf16", 1e-7, 3e-2)])
+def test_compressed_snapshots_perturb_gradient_slightly_3d(codec, lo, hi):
+    E3, g, m, pos, src, ch, d_obs = _case3d()
+    g0, _, _ = E3.shot_gradient(g, m, pos, src, ch, d_obs)
+    g1, _, d1 = E3.shot_gradient_checkpointed(g, m, pos, src, ch, d_obs, 7, codec)
+    for k in range(3):
+        e = np.linalg.norm(g1[k] - g0[k]) / np.linalg.norm(g0[k])
+        assert lo < e < hi, (codec, k, e)
