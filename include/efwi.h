@@ -15,7 +15,8 @@
  *   the moment-rate wavelet, sampled at t_{n+1/2} (Forward problem, eq.(2), MT case).
  * - The library allocates no device memory. Scratch comes from a caller-provided
  *   workspace of at least efwi_workspace_size() bytes (256-byte aligned). Workspaces
- *   must not be shared by calls that may overlap in time.
+ *   must not be shared by calls that may overlap in time. (The one exception is
+ *   efwi_shot_gradient_noalloc, whose scratch is a fixed array the library holds per GPU.)
  * - Every call is asynchronous on the given HIP stream (hipStream_t passed as void*);
  *   scalar results (misfits) are written to DEVICE doubles.
  * - All arguments are validated on the host before anything is enqueued; on error the
@@ -158,6 +159,28 @@ efwi_status efwi_shot_gradient(const efwi_grid* grid, const efwi_shot* shot, con
  *   d_out DEVICE [nch][nt] predicted data, or NULL. */
 efwi_status efwi_shot_jt(const efwi_grid* grid, const efwi_shot* shot, const float* m, const float* src,
                          const float* v, float* g, float* d_out, void* ws, size_t ws_bytes, void* stream);
+
+/* shot_gradient_noalloc: efwi_shot_gradient for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same arguments without a workspace, the same results bit for bit. Its scratch is one
+ * library-owned device array per GPU of EFWI_NOALLOC_SCRATCH_BYTES (64 MiB), held from the
+ * first call on that GPU until the process ends; the call allocates no device or pinned
+ * memory and creates no events (the kernel timing sampler skips it). Every call on a GPU
+ * shares that GPU's array, so calls that may overlap in time on one GPU (several streams or
+ * host threads) race and must not be made; sequential calls on one stream are safe (each
+ * clears what must start at zero). Its small per-call tables are copied from host memory and
+ * the call waits for that copy (and so for the stream's earlier work) before enqueueing the
+ * time steps.
+ * Errors: as efwi_shot_gradient; EFWI_E_WORKSPACE when the shot's gradient workspace
+ * (efwi_workspace_size(EFWI_WS_GRADIENT, ...) with its ckpt_interval and ckpt_mode) exceeds
+ * the scratch: choose a smaller ckpt_interval (efwi_plan_interval with this budget) or use
+ * efwi_shot_gradient with a workspace. */
+#define EFWI_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+efwi_status efwi_shot_gradient_noalloc(const efwi_grid* grid, const efwi_shot* shot, const float* m,
+                                       const float* src, const float* d_obs, float* g, double* phi, float* d_out,
+                                       void* stream);
+/* The scratch size of efwi_shot_gradient_noalloc in bytes (EFWI_NOALLOC_SCRATCH_BYTES). */
+size_t efwi_noalloc_scratch_bytes(void);
 
 /* batch_gradient: the data term of eq.(8) for ns shots at once, each shot s on its own
  * component m_s of the extended model and its own window, advanced together (one launch

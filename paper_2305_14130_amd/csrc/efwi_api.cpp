@@ -95,6 +95,21 @@ Staging& staging() {
   return *s;
 }
 
+// Calls that must not allocate (efwi_shot_gradient_noalloc) upload their header with a plain
+// copy from the planning code's host buffer instead of the staging ring (whose pinned slots
+// are allocated on first use), and wait for it, since that buffer is freed on return.
+thread_local bool t_no_alloc = false;
+struct NoAllocScope {
+  NoAllocScope() { t_no_alloc = true; }
+  ~NoAllocScope() { t_no_alloc = false; }
+};
+
+hipError_t upload_header(void* dst, const std::vector<unsigned char>& blob, hipStream_t st) {
+  if (!t_no_alloc) return staging().upload(dst, blob.data(), blob.size(), st);
+  hipError_t e = hipMemcpyAsync(dst, blob.data(), blob.size(), hipMemcpyHostToDevice, st);
+  return e != hipSuccess ? e : hipStreamSynchronize(st);
+}
+
 // ----------------------------------------------------------------------------------------
 // Kernel timing sampler: when enabled, every `every`-th launch of each kernel kind opens a
 // window of up to WINDOW consecutive launches of that kind, bracketed by two HIP events
@@ -121,7 +136,7 @@ class Sampler {
   }
   template <class F>
   hipError_t run(int kind, hipStream_t st, F&& launch) {
-    if (every_ <= 0) return launch();
+    if (every_ <= 0 || t_no_alloc) return launch();   // allocation-free calls create no events
     std::unique_lock<std::mutex> lock(mu_);
     for (int k = 0; k < KK_COUNT; ++k) {  // another kind's launch closes an open window
       Window& o = open_[k];
@@ -786,7 +801,7 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
     if (adj) HIP_TRY(hipMemsetAsync(r + p.off_adj, 0, p.adj_bytes, st));
     if (grad) HIP_TRY(hipMemsetAsync(r + p.off_G, 0, (size_t)3 * p.cells * sizeof(double), st));
   }
-  HIP_TRY(staging().upload(ws, blob.data(), blob.size(), st));
+  HIP_TRY(upload_header(ws, blob, st));
   HIP_TRY(launch_stage2d(wv.batch, st));
   return EFWI_OK;
 }
@@ -1232,7 +1247,7 @@ efwi_status setup_wave3(const efwi_grid& g, const efwi_shot* shots, const std::v
     if (adj) HIP_TRY(hipMemsetAsync(r + p.off_adj, 0, p.adj_bytes, st));
     if (grad) HIP_TRY(hipMemsetAsync(r + p.off_G, 0, (size_t)3 * p.cells * sizeof(double), st));
   }
-  HIP_TRY(staging().upload(ws, blob.data(), blob.size(), st));
+  HIP_TRY(upload_header(ws, blob, st));
   HIP_TRY(launch3_stage(wv.batch, st));
   return EFWI_OK;
 }
@@ -1364,6 +1379,37 @@ size_t workspace3(efwi_ws_kind kind, const efwi_grid& g, int n, const efwi_shot*
   return wave_bytes3(plans, 0, n);
 }
 
+}  // namespace
+
+// ========================================================================================
+// Scratch of the allocation-free entry point: one array per GPU, held until the process
+// ends. Host code never passes the array's name (a host-side stand-in) to a kernel or copy:
+// it uses the device address hipGetSymbolAddress returns for the current device.
+// ========================================================================================
+namespace {
+static __device__ __align__(256) unsigned char scratch[EFWI_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::once_flag g_scratch_once[MAX_DEVICES];
+void* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+
+// The current device's scratch address (looked up once per device, with that device current).
+efwi_status scratch_of_current_device(unsigned char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(EFWI_E_UNSUPPORTED, "device %d beyond %d devices", dev, MAX_DEVICES);
+  std::call_once(g_scratch_once[dev], [dev]() {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+  });
+  if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+    return fail(EFWI_E_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                hipGetErrorString(g_scratch_err[dev]));
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return EFWI_OK;
+}
 }  // namespace
 
 // ========================================================================================
@@ -1684,6 +1730,35 @@ efwi_status efwi_shot_jt(const efwi_grid* grid, const efwi_shot* shot, const flo
   io.gout = g;
   return gradient_waves(*grid, shot, 1, {io}, static_cast<unsigned char*>(ws), ws_bytes,
                         reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t efwi_noalloc_scratch_bytes(void) { return EFWI_NOALLOC_SCRATCH_BYTES; }
+
+efwi_status efwi_shot_gradient_noalloc(const efwi_grid* grid, const efwi_shot* shot, const float* m,
+                                       const float* src, const float* d_obs, float* g, double* phi, float* d_out,
+                                       void* stream) {
+  efwi_status rc = efwi_validate(grid, 1, shot);
+  if (rc != EFWI_OK) return rc;
+  if (!m || !src || !g || !phi || (shot->nch > 0 && !d_obs)) return fail(EFWI_E_INVAL, "NULL array argument");
+  const size_t need = efwi_workspace_size(EFWI_WS_GRADIENT, grid, 1, shot);
+  if (need > EFWI_NOALLOC_SCRATCH_BYTES)
+    return fail(EFWI_E_WORKSPACE,
+                "the shot needs %zu bytes of scratch; the allocation-free entry point has %zu (use a smaller "
+                "ckpt_interval or efwi_shot_gradient with a workspace)",
+                need, (size_t)EFWI_NOALLOC_SCRATCH_BYTES);
+  unsigned char* ws = nullptr;
+  rc = scratch_of_current_device(&ws);
+  if (rc != EFWI_OK) return rc;
+  ShotIO io;
+  io.m = m;
+  io.mplane = (long)grid->nz * grid->nx * (grid->ndim == 3 ? grid->ny : 1);
+  io.src = src;
+  io.dobs = d_obs;
+  io.d = d_out;
+  io.gout = g;
+  io.phi = phi;
+  NoAllocScope scope;
+  return gradient_waves(*grid, shot, 1, {io}, ws, EFWI_NOALLOC_SCRATCH_BYTES, reinterpret_cast<hipStream_t>(stream));
 }
 
 efwi_status efwi_batch_waves(const efwi_grid* grid, int ns, const efwi_shot* shots, size_t ws_bytes, int* nwaves,

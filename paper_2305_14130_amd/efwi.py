@@ -34,7 +34,7 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_autotune", "efwi_batch_waves", "efwi_zoi_weights", "efwi_final_model",
             "efwi_pseudo_hessian", "efwi_das_field",
             "efwi_batch_gradient_grouped", "efwi_bspline_nodes", "efwi_bspline_expand",
-            "efwi_bspline_adjoint"]
+            "efwi_bspline_adjoint", "efwi_shot_gradient_noalloc", "efwi_noalloc_scratch_bytes"]
 
 
 class Grid(ctypes.Structure):
@@ -159,6 +159,11 @@ _lib.efwi_shot_gradient.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC)
 _lib.efwi_shot_jt.restype = ctypes.c_int
 _lib.efwi_shot_jt.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp, _vp, _vp, _vp,
                               ctypes.c_size_t, _vp]
+_lib.efwi_shot_gradient_noalloc.restype = ctypes.c_int
+_lib.efwi_shot_gradient_noalloc.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), _vp, _vp, _vp, _vp, _vp,
+                                            _vp, _vp]
+_lib.efwi_noalloc_scratch_bytes.restype = ctypes.c_size_t
+_lib.efwi_noalloc_scratch_bytes.argtypes = []
 _lib.efwi_batch_gradient.restype = ctypes.c_int
 _lib.efwi_batch_gradient.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), _vp, _vp, _vp,
                                      _vp, _vp, _vp, ctypes.c_size_t, _vp]
@@ -428,6 +433,28 @@ def shot_gradient(grid: Grid, shot: Shot, m, src, d_obs, g=None, phi=None, d_out
     ws = _ws(ws if ws is not None else workspace(need, dev))
     _check(_lib.efwi_shot_gradient(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(d_obs), _ptr(g),
                                    _ptr(phi), _ptr(d_out), _ptr(ws), ws.numel(), _stream(stream)))
+    return g, phi
+
+
+def noalloc_scratch_bytes() -> int:
+    """Scratch bytes of shot_gradient_noalloc (one library-owned array per GPU)."""
+    return int(_lib.efwi_noalloc_scratch_bytes())
+
+
+def shot_gradient_noalloc(grid: Grid, shot: Shot, m, src, d_obs, g, phi, d_out=None, stream=None):
+    """shot_gradient for callers that cannot allocate: no workspace, the outputs g [3][...]
+    and phi (float64, one element) passed in; the library's per-GPU scratch array instead
+    (efwi_shot_gradient_noalloc). Allocates nothing."""
+    _arg(m, "m", model_shape(grid))
+    _arg(src, "src", (n_components(grid), grid.nt))
+    _arg(d_obs, "d_obs", _data_shape(grid, shot))
+    _arg(g, "g", model_shape(grid))
+    _flat(phi, "phi", 1, torch.float64)
+    _opt(d_out, "d_out", _data_shape(grid, shot))
+    _device(m=m, src=src, d_obs=d_obs, g=g, phi=phi, d_out=d_out)
+    sc = shot.c_struct()
+    _check(_lib.efwi_shot_gradient_noalloc(ctypes.byref(grid), ctypes.byref(sc), _ptr(m), _ptr(src), _ptr(d_obs),
+                                           _ptr(g), _ptr(phi), _ptr(d_out), _stream(stream)))
     return g, phi
 
 

@@ -293,3 +293,18 @@ def test_2d_window_size_limit(efwi):
         ok = efwi.Shot(6000, 10000, [6001], [10020], z0=6000 - wz // 2, x0=10000 - wx // 2, wz=wz, wx=wx)
         arr = (efwi._ShotC * 1)(ok.c_struct())
         assert efwi._lib.efwi_validate(ctypes.byref(g), 1, arr) == efwi.OK
+
+
+def test_noalloc_scratch_limit_checked_on_host(efwi):
+    """efwi_shot_gradient_noalloc refuses a shot whose gradient workspace exceeds its fixed
+    scratch before any HIP call (the pointers are never dereferenced)."""
+    grid, shot = _ok_case(efwi)
+    grid.nt = 1000
+    shot.ckpt_interval = 10**6                       # whole history: beyond 64 MiB
+    assert efwi.noalloc_scratch_bytes() == 64 << 20
+    sc = shot.c_struct()
+    fake = ctypes.c_void_p(256)
+    rc = efwi._lib.efwi_shot_gradient_noalloc(ctypes.byref(grid), ctypes.byref(sc), fake, fake, fake, fake, fake,
+                                              None, None)
+    assert rc == efwi.E_WORKSPACE
+    assert b"scratch" in efwi._lib.efwi_last_error()
