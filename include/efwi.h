@@ -209,14 +209,23 @@ efwi_status efwi_batch_gradient_grouped(const efwi_grid* grid, int ns, const efw
 /* batch_waves: how efwi_batch_gradient groups the ns shots into waves (shots advanced
  * together, one launch per half step) for a workspace of ws_bytes. A 2D wave holds as many
  * shots as the workspace fits while their per-step state (both state buffers, imaging sums
- * and parameters) stays within 192 MiB, three quarters of the MI355X's 256 MB Infinity
- * Cache, so that each step finds the previous step's state cached; a wave holds at least one
- * shot. 3D waves are limited by the workspace only.
+ * and parameters) stays within 256 MiB, about the MI355X's 256 MB Infinity Cache, so that
+ * each step finds most of the previous step's state cached (efwi_set_wave_cache_bytes); a
+ * wave holds at least one shot. 3D waves are limited by the workspace only.
  *   nwaves     HOST int output: number of waves;
  *   wave_first HOST int [ns] output (may be NULL): first shot of each wave, in order.
  * EFWI_E_WORKSPACE if one shot alone does not fit. */
 efwi_status efwi_batch_waves(const efwi_grid* grid, int ns, const efwi_shot* shots, size_t ws_bytes,
                              int* nwaves, int* wave_first);
+
+/* Per-step state bound of a 2D wave (efwi_batch_waves, efwi_batch_gradient, and the calls
+ * that advance shots in waves): a wave takes shots while their per-step state stays within
+ * `bytes`; the default, 256 MiB, is about the MI355X's 256 MB Infinity Cache.
+ * (size_t)-1 sizes waves by the workspace alone; 0 restores the default. Process-wide,
+ * applies to calls planned after it; results do not depend on it (each shot's arithmetic is
+ * the same in any wave). Always EFWI_OK. */
+efwi_status efwi_set_wave_cache_bytes(size_t bytes);
+size_t efwi_get_wave_cache_bytes(void);
 
 /* extension_regularizer: value and gradient of 1/2 eta^2 ||(I - S^T S_w) W m~||^2 (eq.(8)
  * second term), with W from eq.(11) (sinkhole samples of m_s replaced by the b-weighted mix

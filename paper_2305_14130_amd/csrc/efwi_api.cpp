@@ -358,6 +358,8 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
 // Rows of the fused forward-step and transposed-step tiles for the plans made from now on
 // (set by efwi_set_tile_rows or efwi_autotune; process-wide).
 std::atomic<int> g_fwd_rows{DEFAULT_TILE_ROWS}, g_adj_rows{DEFAULT_TILE_ROWS};
+// Per-step state bound of a 2D wave (efwi_set_wave_cache_bytes; process-wide).
+std::atomic<size_t> g_wave_cache_bytes{WAVE_CACHE_BYTES};
 
 struct Plan2D {
   Window w;
@@ -871,7 +873,7 @@ size_t step_bytes(const Plan2D& p) {
 }
 
 // Split shots [0, ns) into waves that fit ws_bytes. A wave also keeps its shots' step
-// bytes within WAVE_CACHE_BYTES (at least one shot per wave): while they fit in the
+// bytes within the wave bound (WAVE_CACHE_BYTES unless set; at least one shot per wave): while they fit in the
 // 256 MB Infinity Cache, each step finds the previous step's state there, and one launch
 // over more shots than fit is slower per cell than a launch per wave (measured on the
 // 1000 x 3000 shots: a 2-shot launch took 1.5x (forward) and 1.1x (transposed) the time
@@ -883,7 +885,7 @@ efwi_status plan_waves(const std::vector<Plan2D>& plans, size_t ws_bytes, std::v
     int count = 0;
     size_t cached = 0;
     while (first + count < ns && wave_bytes(plans, first, count + 1) <= ws_bytes &&
-           (count == 0 || cached + step_bytes(plans[first + count]) <= WAVE_CACHE_BYTES)) {
+           (count == 0 || cached + step_bytes(plans[first + count]) <= g_wave_cache_bytes.load())) {
       cached += step_bytes(plans[first + count]);
       ++count;
     }
@@ -1491,6 +1493,13 @@ efwi_status efwi_set_tile_rows(int fwd_rows, int adj_rows) {
   if (adj_rows) g_adj_rows.store(adj_rows);
   return EFWI_OK;
 }
+
+efwi_status efwi_set_wave_cache_bytes(size_t bytes) {
+  g_wave_cache_bytes.store(bytes == 0 ? WAVE_CACHE_BYTES : bytes);
+  return EFWI_OK;
+}
+
+size_t efwi_get_wave_cache_bytes(void) { return g_wave_cache_bytes.load(); }
 
 efwi_status efwi_get_tile_rows(int* fwd_rows, int* adj_rows) {
   if (!fwd_rows || !adj_rows) return fail(EFWI_E_INVAL, "NULL output pointer");

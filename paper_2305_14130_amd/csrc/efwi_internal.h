@@ -155,9 +155,11 @@ __host__ __device__ inline void tile3_coords(int local, int nz, int nx, int& i, 
   j0 = (rem - i * ntx) * TILE3_X;
   k0 = band * TILE3_Y;
 }
-// Per-step bytes of the shots advanced together in one wave of a batch (3/4 of the
-// 256 MB Infinity Cache of an MI355X).
-constexpr size_t WAVE_CACHE_BYTES = (size_t)192 << 20;
+// Per-step bytes of the shots advanced together in one wave of a batch: 256 MiB, about the
+// MI355X's 256 MB Infinity Cache (a sweep of 96-384 MiB on 64 uneven windows measured
+// 96 and 128 MiB 8% slower and 192 MiB 0.8% slower than 256 MiB; 384 MiB gave the same
+// waves as 256 MiB there).
+constexpr size_t WAVE_CACHE_BYTES = (size_t)256 << 20;
 // Relative cost of an interior tile and of a tile that touches a CPML strip, as integer
 // weights (measured on MI355X with the 2D kernels: CPML tiles cost ~1.5x in the forward
 // kernels and ~2x in the adjoint kernels, which also update the adjoint memory variables

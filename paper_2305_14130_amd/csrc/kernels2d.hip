@@ -1193,21 +1193,47 @@ __global__ __launch_bounds__(BX * BZ) void k_write_gradient(BATCH_PARAMS) {
 
 // ------------------------------------------------------------------------------------
 // Misfit (FP64) and the reverse cumulative residual that drives the DAS transpose:
-// e_bar[n][c] = sum_{k >= n} r[c][k], r = d - d_obs. One thread per channel; the per-channel
-// FP64 partial sums are reduced in a fixed order by a single block.
+// e_bar[n][c] = sum_{k >= n} r[c][k], r = d - d_obs. A block takes RES_T channels and walks
+// the time axis from the end in tiles of RES_T samples: the tile is read along time
+// (coalesced; d and e_bar are [nch][nt] and [nt][nch]), its residuals transposed through
+// LDS in FP64, summed by one thread per channel in the order of a serial reverse sum (so the
+// sums do not depend on the tiling), and written along the channels. The per-channel FP64
+// partial sums of r^2 are reduced in a fixed order by a single block.
 // ------------------------------------------------------------------------------------
-__global__ void k_residual(const float* d, const float* dobs, int nch, int nt, double* partial, float* ebar) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nch) return;
-  double acc = 0.0, sq = 0.0;
-  for (int n = nt - 1; n >= 0; --n) {
-    const long k = (long)c * nt + n;
-    const double r = dobs ? (double)d[k] - (double)dobs[k] : (double)d[k];
-    sq += r * r;
-    acc += r;
-    ebar[(long)n * nch + c] = (float)acc;
+constexpr int RES_T = 64;
+__global__ __launch_bounds__(256) void k_residual(const float* d, const float* dobs, int nch, int nt,
+                                                  double* partial, float* ebar) {
+  __shared__ double tile[RES_T][RES_T + 1];
+  const int c0 = blockIdx.x * RES_T, tid = threadIdx.x;
+  constexpr int ROWS = 256 / RES_T;   // channels (loads) or samples (stores) per pass of the block
+  double acc = 0.0, sq = 0.0;         // of channel c0 + tid, in threads tid < RES_T
+  for (int t0 = (nt - 1) / RES_T * RES_T; t0 >= 0; t0 -= RES_T) {
+    for (int k = 0; k < RES_T / ROWS; ++k) {
+      const int ch = tid / RES_T + ROWS * k, sm = tid % RES_T, c = c0 + ch, t = t0 + sm;
+      double r = 0.0;
+      if (c < nch && t < nt) {
+        const long e = (long)c * nt + t;
+        r = dobs ? (double)d[e] - (double)dobs[e] : (double)d[e];
+      }
+      tile[ch][sm] = r;
+    }
+    __syncthreads();
+    if (tid < RES_T) {
+      for (int sm = RES_T - 1; sm >= 0; --sm) {   // samples past nt hold r = 0 and change nothing
+        const double r = tile[tid][sm];
+        sq += r * r;
+        acc += r;
+        tile[tid][sm] = acc;
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < RES_T / ROWS; ++k) {
+      const int sm = tid / RES_T + ROWS * k, ch = tid % RES_T, c = c0 + ch, t = t0 + sm;
+      if (c < nch && t < nt) ebar[(long)t * nch + c] = (float)tile[ch][sm];
+    }
+    __syncthreads();
   }
-  if (partial) partial[c] = sq;
+  if (partial && tid < RES_T && c0 + tid < nch) partial[c0 + tid] = sq;
 }
 
 __global__ void k_reduce_phi(const double* partial, int n, double* phi) {
@@ -1319,13 +1345,13 @@ hipError_t launch_write_gradient(const Batch2D& b, hipStream_t st) {
 
 hipError_t launch_misfit_raw(int nch, int nt, const float* d, const float* dobs, double* partial, double* phi,
                              float* ebar, hipStream_t st) {
-  if (nch > 0) k_residual<<<(nch + 127) / 128, 128, 0, st>>>(d, dobs, nch, nt, partial, ebar);
+  if (nch > 0) k_residual<<<(nch + RES_T - 1) / RES_T, 256, 0, st>>>(d, dobs, nch, nt, partial, ebar);
   k_reduce_phi<<<1, 256, 0, st>>>(partial, nch > 0 ? nch : 0, phi);
   return hipGetLastError();
 }
 
 hipError_t launch_residual_cumsum_raw(int nch, int nt, const float* r, float* ebar, hipStream_t st) {
-  if (nch > 0) k_residual<<<(nch + 127) / 128, 128, 0, st>>>(r, nullptr, nch, nt, nullptr, ebar);
+  if (nch > 0) k_residual<<<(nch + RES_T - 1) / RES_T, 256, 0, st>>>(r, nullptr, nch, nt, nullptr, ebar);
   return hipGetLastError();
 }
 

@@ -34,7 +34,8 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_autotune", "efwi_batch_waves", "efwi_zoi_weights", "efwi_final_model",
             "efwi_pseudo_hessian", "efwi_das_field",
             "efwi_batch_gradient_grouped", "efwi_bspline_nodes", "efwi_bspline_expand",
-            "efwi_bspline_adjoint", "efwi_shot_gradient_noalloc", "efwi_noalloc_scratch_bytes"]
+            "efwi_bspline_adjoint", "efwi_shot_gradient_noalloc", "efwi_noalloc_scratch_bytes",
+            "efwi_set_wave_cache_bytes", "efwi_get_wave_cache_bytes"]
 
 
 class Grid(ctypes.Structure):
@@ -132,6 +133,10 @@ _lib.efwi_set_tile_rows.restype = ctypes.c_int
 _lib.efwi_set_tile_rows.argtypes = [ctypes.c_int, ctypes.c_int]
 _lib.efwi_get_tile_rows.restype = ctypes.c_int
 _lib.efwi_get_tile_rows.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+_lib.efwi_set_wave_cache_bytes.restype = ctypes.c_int
+_lib.efwi_set_wave_cache_bytes.argtypes = [ctypes.c_size_t]
+_lib.efwi_get_wave_cache_bytes.restype = ctypes.c_size_t
+_lib.efwi_get_wave_cache_bytes.argtypes = []
 _lib.efwi_autotune_workspace_size.restype = ctypes.c_size_t
 _lib.efwi_autotune_workspace_size.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), ctypes.c_int]
 _lib.efwi_autotune.restype = ctypes.c_int
@@ -335,6 +340,15 @@ def plan_interval(grid: Grid, shot: Shot, budget_bytes: int) -> int:
 def set_tile_rows(fwd_rows: int = 0, adj_rows: int = 0) -> None:
     """Rows of the fused forward / transposed step tiles (8, 12 or 16; 0 keeps a value)."""
     _check(_lib.efwi_set_tile_rows(int(fwd_rows), int(adj_rows)))
+
+
+def set_wave_cache_bytes(nbytes: int) -> None:
+    """Per-step state bound of a 2D wave (0: the default 256 MiB; -1: the workspace alone)."""
+    _check(_lib.efwi_set_wave_cache_bytes(ctypes.c_size_t(nbytes if nbytes >= 0 else 2**64 - 1)))
+
+
+def get_wave_cache_bytes() -> int:
+    return int(_lib.efwi_get_wave_cache_bytes())
 
 
 def get_tile_rows():

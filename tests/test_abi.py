@@ -146,6 +146,16 @@ def test_batch_waves_follow_the_cache_budget(efwi):
               for k in range(3)]
     ws = efwi.workspace_size(efwi.WS_BATCH, large, bshots)
     assert efwi.batch_waves(large, bshots, ws) == [0, 1, 2]
+    # the per-step bound can be lifted (waves sized by the workspace alone) and restored
+    assert efwi.get_wave_cache_bytes() == 256 << 20
+    try:
+        efwi.set_wave_cache_bytes(-1)
+        assert efwi.batch_waves(large, bshots, ws) == [0]
+        efwi.set_wave_cache_bytes(1)                      # below one shot: still one shot per wave
+        assert efwi.batch_waves(small, shots, big_ws) == list(range(6))
+    finally:
+        efwi.set_wave_cache_bytes(0)
+    assert efwi.get_wave_cache_bytes() == 256 << 20
 
 
 @pytest.mark.parametrize("change", [
