@@ -32,8 +32,9 @@ constexpr int NSEG_FIELDS = 5;
 // buoyancies of the four surrounding velocity nodes.
 constexpr int NACC = 3;
 constexpr int NACC_VTI = 5;   // VTI: the c11, c33 and c13 sums replace the lambda sum
-// Time steps summed in FP32 before the imaging sums are chained into the FP64 gradient.
-constexpr int FLUSH_STEPS = 32;
+// Time steps summed in FP32 before the imaging sums are chained into the FP64 gradient
+// (each flush reads and writes the FP64 sums: 64 steps keep it near 0.5% of a reverse sweep).
+constexpr int FLUSH_STEPS = 64;
 
 // Device pointers in the global address space. Kernels read each shot's descriptor from a
 // device array; typing its pointer members as global keeps every access a global_load /
