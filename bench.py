@@ -433,8 +433,10 @@ class Batched:
     true model's), the 64-component extended model (start model times 1% smooth noise per
     shot), hard sinkholes for the regularizer."""
 
-    def __init__(self, efwi, inputs, torch, dev, nt, nshots=64):
+    def __init__(self, efwi, inputs, torch, dev, nt, nshots=64, windows=None):
         w = inputs.batched_2d(nshots=nshots, nt=nt)
+        if windows:   # the first `windows` of the 64 (profiling runs): the full run's first waves
+            w.shots = w.shots[:windows]
         self.w, self.nt, self.dev = w, nt, dev
         T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
         self.grid = efwi.make_grid(w.nz, w.nx, w.dz, w.dx, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)
@@ -483,6 +485,12 @@ def main():  # noqa: C901
     ap.add_argument("--no-forms", action="store_true", help="time the headline only (profiling runs)")
     for f in ("sequential", "sqrt", "compressed", "plain", "autograd", "vti", "3d", "extension-ops", "autotune"):
         ap.add_argument(f"--no-{f}", action="store_true")
+    ap.add_argument("--tile-rows", default="",
+                    help="FWD,ADJ: fix the step kernels' tile rows instead of autotuning them (counter runs, "
+                         "whose serialised launches would distort the autotuner's timings)")
+    ap.add_argument("--windows", type=int, default=0,
+                    help="time the headline over the first K of its 64 windows only (counter runs: the launches "
+                         "of the full run's first waves, without its hundreds of thousands of other launches)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (scales HBM byte counters)")
     ap.add_argument("--cpu-worker", type=int, default=0, help=argparse.SUPPRESS)
@@ -517,13 +525,15 @@ def main():  # noqa: C901
     nt = args.nt
     if args.wave_cache_mib:
         efwi.set_wave_cache_bytes(args.wave_cache_mib << 20 if args.wave_cache_mib > 0 else -1)
-    B = Batched(efwi, inputs, torch, dev, nt)
+    B = Batched(efwi, inputs, torch, dev, nt, windows=args.windows)
     grid, ns = B.grid, B.ns
     torch.cuda.synchronize()
     log(f"set-up done: {ns} windows, {sum(B.cells) / 1e6:.2f} M cells")
     tune_ms = {}
     big = B.largest
-    tiles = efwi.get_tile_rows() if args.no_autotune else \
+    if args.tile_rows:
+        efwi.set_tile_rows(*(int(x) for x in args.tile_rows.split(",")))
+    tiles = efwi.get_tile_rows() if args.no_autotune or args.tile_rows else \
         efwi.autotune(grid, B.shots[big], B.m_ext[big], B.src[big], steps=64, times=tune_ms)
     log(f"tile rows (forward, transposed): {tiles}; sweep ms by rows: {tune_ms}")
     budget = int(args.mem_fraction * torch.cuda.mem_get_info(dev)[0])
