@@ -130,7 +130,7 @@ def _host_info():
     return {"nproc": os.cpu_count(), "model": model}
 
 
-def cpu_baseline(steps=48, workers=None):
+def cpu_baseline(steps=240, workers=None):
     """One oracle process alone, then `workers` independent processes at once (shots are
     independent, one per core); NumPy single-threaded in each (its elementwise ops are)."""
     host = _host_info()
