@@ -481,6 +481,7 @@ def main():  # noqa: C901
                     help="share of the free device memory the headline's workspace may take")
     ap.add_argument("--wave-cache-mib", type=int, default=0,
                     help="per-step state bound of a wave in MiB (0: the library's default, -1: the workspace alone)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes of the batched calls (0: the library's default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="time the headline only (profiling runs)")
     for f in ("sequential", "sqrt", "compressed", "plain", "autograd", "vti", "3d", "extension-ops", "autotune"):
@@ -523,6 +524,8 @@ def main():  # noqa: C901
         torch.cuda.synchronize()
         del x, y
     nt = args.nt
+    if args.lanes:
+        efwi.set_wave_lanes(args.lanes)
     if args.wave_cache_mib:
         efwi.set_wave_cache_bytes(args.wave_cache_mib << 20 if args.wave_cache_mib > 0 else -1)
     B = Batched(efwi, inputs, torch, dev, nt, windows=args.windows)

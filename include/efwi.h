@@ -207,16 +207,21 @@ efwi_status efwi_batch_gradient_grouped(const efwi_grid* grid, int ns, const efw
                                         float* g_ext, double* phi, void* ws, size_t ws_bytes, void* stream);
 
 /* batch_waves: how efwi_batch_gradient groups the ns shots into waves (shots advanced
- * together, one launch per half step) for a workspace of ws_bytes. A 2D wave holds as many
- * shots as the workspace fits while their per-step state (both state buffers, imaging sums
- * and parameters) stays within 256 MiB, about the MI355X's 256 MB Infinity Cache, so that
- * each step finds most of the previous step's state cached (efwi_set_wave_cache_bytes); a
- * wave holds at least one shot. 3D waves are limited by the workspace only.
+ * together, one launch per half step) for a workspace of ws_bytes. 2D: the shots are packed
+ * first fit, largest first (by workspace bytes), into as few waves as the workspace holds
+ * while each wave's per-step state (both state buffers, imaging sums and parameters) stays
+ * within 256 MiB, about the MI355X's 256 MB Infinity Cache, so that each step finds most of
+ * the previous step's state cached (efwi_set_wave_cache_bytes); a wave holds at least one
+ * shot. With two lanes (efwi_set_wave_lanes) the plan is that of each lane's half, waves
+ * 2m and 2m+1 running side by side. 3D waves take the shots in order, limited by the
+ * workspace only. (efwi_batch_gradient_grouped keeps the shot order and one lane.)
  *   nwaves     HOST int output: number of waves;
- *   wave_first HOST int [ns] output (may be NULL): first shot of each wave, in order.
+ *   wave_first HOST int [ns] output (may be NULL): start of each wave in `order`;
+ *   order      HOST int [ns] output (may be NULL): the shots in the order the waves take them,
+ *              wave w being order[wave_first[w]] .. order[wave_first[w+1] - 1], ascending.
  * EFWI_E_WORKSPACE if one shot alone does not fit. */
 efwi_status efwi_batch_waves(const efwi_grid* grid, int ns, const efwi_shot* shots, size_t ws_bytes,
-                             int* nwaves, int* wave_first);
+                             int* nwaves, int* wave_first, int* order);
 
 /* Per-step state bound of a 2D wave (efwi_batch_waves, efwi_batch_gradient, and the calls
  * that advance shots in waves): a wave takes shots while their per-step state stays within
@@ -226,6 +231,21 @@ efwi_status efwi_batch_waves(const efwi_grid* grid, int ns, const efwi_shot* sho
  * the same in any wave). Always EFWI_OK. */
 efwi_status efwi_set_wave_cache_bytes(size_t bytes);
 size_t efwi_get_wave_cache_bytes(void);
+
+/* Lanes of a 2D batch (efwi_batch_gradient, efwi_batch_waves): with 2, the workspace is split
+ * into two halves and consecutive waves alternate between them, one half advanced on the
+ * caller's stream and the other on a second stream the library creates on the current
+ * device (default priority, once per device); every time step is enqueued for both waves in
+ * turn, so one wave's launches fill the end of the other's. Each lane's waves keep half of
+ * the per-step state bound (efwi_set_wave_cache_bytes). A batch uses two lanes when one lane
+ * would take several waves, every shot fits half the workspace and the halves' plan has at
+ * most about twice as many waves, else one; shots whose
+ * gradients add into a shared component (efwi_batch_gradient_grouped) always use one. The
+ * caller's stream waits for the second one before the call returns its work; results are
+ * bitwise those of one lane. lanes: 1 or 2, 0 restores the default (2). Process-wide,
+ * applies to calls planned after it. EFWI_E_INVAL for other values. */
+efwi_status efwi_set_wave_lanes(int lanes);
+int efwi_get_wave_lanes(void);
 
 /* extension_regularizer: value and gradient of 1/2 eta^2 ||(I - S^T S_w) W m~||^2 (eq.(8)
  * second term), with W from eq.(11) (sinkhole samples of m_s replaced by the b-weighted mix

@@ -112,10 +112,12 @@ hipError_t upload_header(void* dst, const std::vector<unsigned char>& blob, hipS
 
 // ----------------------------------------------------------------------------------------
 // Kernel timing sampler: when enabled, every `every`-th launch of each kernel kind opens a
-// window of up to WINDOW consecutive launches of that kind, bracketed by two HIP events
-// recorded on the launch stream (one event pair per window, so the event overhead is
-// spread over its launches); another kind's launch closes the window early. Durations are
-// collected when queried. Off by default (no events in the hot loop).
+// window of up to WINDOW consecutive launches of that kind on one stream, bracketed by two
+// HIP events recorded on that stream (one event pair per window, so the event overhead is
+// spread over its launches); a launch of another kind on the same stream closes the window
+// early. Windows are kept per stream, so the two lanes of a batch are timed separately (a
+// window's launches then share the GPU with the other lane's). Durations are collected when
+// queried. Off by default (no events in the hot loop).
 // ----------------------------------------------------------------------------------------
 // fwd_vel, fwd_str, adj_vel and adj_str are the 3D half steps; fwd_step and adj_step are the
 // fused 2D forward and transposed steps.
@@ -138,16 +140,16 @@ class Sampler {
   hipError_t run(int kind, hipStream_t st, F&& launch) {
     if (every_ <= 0 || t_no_alloc) return launch();   // allocation-free calls create no events
     std::unique_lock<std::mutex> lock(mu_);
-    for (int k = 0; k < KK_COUNT; ++k) {  // another kind's launch closes an open window
-      Window& o = open_[k];
-      if (k != kind && o.active) {
-        hipError_t e = hipEventRecord(o.b, o.st);
+    for (int k = 0; k < KK_COUNT; ++k) {  // another kind's launch on this stream closes its open window
+      Window* o = find(k, st);
+      if (k != kind && o && o->active) {
+        hipError_t e = hipEventRecord(o->b, o->st);
         if (e != hipSuccess) return e;
-        pending_[k].push_back(o);
-        o.active = false;
+        pending_[k].push_back(*o);
+        o->active = false;
       }
     }
-    Window& w = open_[kind];
+    Window& w = window(kind, st);
     if (!w.active && (launched_[kind] % std::max(every_, WINDOW)) == 0) {
       hipError_t e = get_event(&w.a);
       if (e == hipSuccess) e = get_event(&w.b);
@@ -156,18 +158,17 @@ class Sampler {
       w.active = true;
       w.valid = true;
       w.count = 0;
-      w.st = st;
     }
     ++launched_[kind];
     lock.unlock();
     hipError_t e = launch();
     if (e != hipSuccess) return e;
     lock.lock();
-    if (w.active && w.st != st) w.valid = false;   // a window times one stream
-    if (w.active && ++w.count == WINDOW) {
-      e = hipEventRecord(w.b, st);
-      pending_[kind].push_back(w);
-      w.active = false;
+    Window& v = window(kind, st);
+    if (v.active && ++v.count == WINDOW) {
+      e = hipEventRecord(v.b, st);
+      pending_[kind].push_back(v);
+      v.active = false;
     }
     return e;
   }
@@ -202,7 +203,8 @@ class Sampler {
         free_.push_back(w.b);
       }
       pending_[k].clear();
-      if (open_[k].active) open_[k].valid = false;
+      for (Window& o : open_[k])
+        if (o.active) o.valid = false;   // closes later; its events are then recycled
       launched_[k] = timed_[k] = 0;
       total_ms_[k] = 0.0;
     }
@@ -216,6 +218,18 @@ class Sampler {
     int count = 0;
     bool active = false, valid = false;
   };
+  // the open window of a kind on a stream (created inactive on first use)
+  Window* find(int kind, hipStream_t st) {
+    for (Window& w : open_[kind])
+      if (w.st == st) return &w;
+    return nullptr;
+  }
+  Window& window(int kind, hipStream_t st) {
+    if (Window* w = find(kind, st)) return *w;
+    open_[kind].push_back(Window{});
+    open_[kind].back().st = st;
+    return open_[kind].back();
+  }
   hipError_t get_event(hipEvent_t* ev) {
     if (!free_.empty()) {
       *ev = free_.back();
@@ -229,7 +243,7 @@ class Sampler {
   long launched_[KK_COUNT] = {};
   long timed_[KK_COUNT] = {};
   double total_ms_[KK_COUNT] = {};
-  Window open_[KK_COUNT];
+  std::vector<Window> open_[KK_COUNT];
   std::vector<Window> pending_[KK_COUNT];
   std::vector<hipEvent_t> free_;
 };
@@ -360,6 +374,8 @@ efwi_status validate_shot(const efwi_grid& g, const efwi_shot* s, int index) {
 std::atomic<int> g_fwd_rows{DEFAULT_TILE_ROWS}, g_adj_rows{DEFAULT_TILE_ROWS};
 // Per-step state bound of a 2D wave (efwi_set_wave_cache_bytes; process-wide).
 std::atomic<size_t> g_wave_cache_bytes{WAVE_CACHE_BYTES};
+// Lanes of a 2D batch (efwi_set_wave_lanes; process-wide): 1 or 2.
+std::atomic<int> g_wave_lanes{DEFAULT_WAVE_LANES};
 
 struct Plan2D {
   Window w;
@@ -808,61 +824,98 @@ efwi_status setup_wave(const efwi_grid& g, const efwi_shot* shots, const std::ve
   return EFWI_OK;
 }
 
-// Forward sweep of a wave. With `checkpoints`, the state block of every shot is copied at
-// the start of segments 1 .. nseg-2 (segment 0 starts from zero) and the last segment's
-// imaging quantities are kept from this sweep, so the reverse sweep need not recompute it.
-efwi_status run_forward(Wave& wv, unsigned char* ws, bool checkpoints, hipStream_t st) {
-  const int last0 = (wv.nseg - 1) * wv.L;
-  for (int n = 0; n < wv.nt; ++n) {
-    if (checkpoints && n % wv.L == 0 && n > 0 && n < last0) {
-      const int k = n / wv.L;
-      for (size_t q = 0; q < wv.plans.size(); ++q) {
-        const Plan2D& p = wv.plans[q];
-        unsigned char* r = ws + wv.regions[q];
-        unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
-        unsigned char* state = r + p.off_state + (size_t)(n & 1) * p.state_bytes;  // state of step n
-        if (p.ckpt_mode == EFWI_CKPT_FP32)
-          HIP_TRY(hipMemcpyAsync(slot, state, p.state_bytes, hipMemcpyDeviceToDevice, st));
-        else
-          HIP_TRY(launch_ckpt_encode(reinterpret_cast<const float*>(state), p.fields,
-                                     reinterpret_cast<unsigned int*>(r + p.off_maxbits), slot, p.ckpt_mode, st));
+// A wave being advanced: its plan and descriptors, the workspace it was set up in and the
+// stream its work goes to. The sweeps below advance one or more waves of the same schedule
+// (nt, checkpoint interval) together, enqueuing each time step for every wave in turn, so
+// that waves on different streams run their launches side by side.
+struct Lane {
+  Wave wv;
+  unsigned char* ws = nullptr;
+  hipStream_t st = nullptr;
+};
+
+// Forward sweep. With `checkpoints`, the state block of every shot is copied at the start of
+// segments 1 .. nseg-2 (segment 0 starts from zero) and the last segment's imaging
+// quantities are kept from this sweep, so the reverse sweep need not recompute it.
+efwi_status run_forward(std::vector<Lane>& lanes, bool checkpoints) {
+  const Wave& w0 = lanes[0].wv;
+  const int last0 = (w0.nseg - 1) * w0.L;
+  for (int n = 0; n < w0.nt; ++n) {
+    for (Lane& l : lanes) {
+      Wave& wv = l.wv;
+      hipStream_t st = l.st;
+      if (checkpoints && n % wv.L == 0 && n > 0 && n < last0) {
+        const int k = n / wv.L;
+        for (size_t q = 0; q < wv.plans.size(); ++q) {
+          const Plan2D& p = wv.plans[q];
+          unsigned char* r = l.ws + wv.regions[q];
+          unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
+          unsigned char* state = r + p.off_state + (size_t)(n & 1) * p.state_bytes;  // state of step n
+          if (p.ckpt_mode == EFWI_CKPT_FP32)
+            HIP_TRY(hipMemcpyAsync(slot, state, p.state_bytes, hipMemcpyDeviceToDevice, st));
+          else
+            HIP_TRY(launch_ckpt_encode(reinterpret_cast<const float*>(state), p.fields,
+                                       reinterpret_cast<unsigned int*>(r + p.off_maxbits), slot, p.ckpt_mode, st));
+        }
       }
+      const int kstore = (checkpoints && n >= last0) ? n - last0 : -1;
+      HIP_TRY(TIMED(KK_FWD_STEP, st, launch_fwd_step(wv.batch, n, kstore, true, st)));
     }
-    const int kstore = (checkpoints && n >= last0) ? n - last0 : -1;
-    HIP_TRY(TIMED(KK_FWD_STEP, st, launch_fwd_step(wv.batch, n, kstore, true, st)));
   }
   return EFWI_OK;
 }
 
-// Reverse sweep of a wave: segments last to first; each segment (but the last) is
-// recomputed from its checkpoint while storing the imaging quantities, then stepped back.
-efwi_status run_reverse(Wave& wv, unsigned char* ws, hipStream_t st) {
-  for (int k = wv.nseg - 1; k >= 0; --k) {
-    const int n0 = k * wv.L, n1 = std::min(wv.nt, n0 + wv.L);
-    if (k < wv.nseg - 1) {
-      for (size_t q = 0; q < wv.plans.size(); ++q) {
-        const Plan2D& p = wv.plans[q];
-        unsigned char* r = ws + wv.regions[q];
-        const unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
-        unsigned char* state = r + p.off_state + (size_t)(n0 & 1) * p.state_bytes;  // state of step n0
-        if (k == 0) HIP_TRY(hipMemsetAsync(state, 0, p.state_bytes, st));
-        else if (p.ckpt_mode == EFWI_CKPT_FP32)
-          HIP_TRY(hipMemcpyAsync(state, slot, p.state_bytes, hipMemcpyDeviceToDevice, st));
-        else
-          HIP_TRY(launch_ckpt_decode(reinterpret_cast<float*>(state), p.fields, slot, p.ckpt_mode, st));
+efwi_status run_forward(Wave& wv, unsigned char* ws, bool checkpoints, hipStream_t st) {
+  std::vector<Lane> one(1);
+  one[0].wv = wv;
+  one[0].ws = ws;
+  one[0].st = st;
+  return run_forward(one, checkpoints);
+}
+
+// Reverse sweep: segments last to first; each segment (but the last) is recomputed from its
+// checkpoint while storing the imaging quantities, then stepped back.
+efwi_status run_reverse(std::vector<Lane>& lanes) {
+  const Wave& w0 = lanes[0].wv;
+  for (int k = w0.nseg - 1; k >= 0; --k) {
+    const int n0 = k * w0.L, n1 = std::min(w0.nt, n0 + w0.L);
+    if (k < w0.nseg - 1) {
+      for (Lane& l : lanes) {
+        for (size_t q = 0; q < l.wv.plans.size(); ++q) {
+          const Plan2D& p = l.wv.plans[q];
+          unsigned char* r = l.ws + l.wv.regions[q];
+          const unsigned char* slot = r + p.off_ckpt + (size_t)(k - 1) * p.slot_bytes;
+          unsigned char* state = r + p.off_state + (size_t)(n0 & 1) * p.state_bytes;  // state of step n0
+          if (k == 0) HIP_TRY(hipMemsetAsync(state, 0, p.state_bytes, l.st));
+          else if (p.ckpt_mode == EFWI_CKPT_FP32)
+            HIP_TRY(hipMemcpyAsync(state, slot, p.state_bytes, hipMemcpyDeviceToDevice, l.st));
+          else
+            HIP_TRY(launch_ckpt_decode(reinterpret_cast<float*>(state), p.fields, slot, p.ckpt_mode, l.st));
+        }
       }
-      for (int n = n0; n < n1; ++n) HIP_TRY(TIMED(KK_FWD_STEP, st, launch_fwd_step(wv.batch, n, n - n0, false, st)));
+      for (int n = n0; n < n1; ++n)
+        for (Lane& l : lanes) HIP_TRY(TIMED(KK_FWD_STEP, l.st, launch_fwd_step(l.wv.batch, n, n - n0, false, l.st)));
     }
     // Imaging sums run in FP32 over blocks of FLUSH_STEPS steps aligned on absolute step
     // numbers and are then added into the FP64 gradient, so the result does not depend on
     // the checkpoint interval.
     for (int n = n1 - 1; n >= n0; --n) {
-      const bool first = (n == wv.nt - 1) || ((n + 1) % FLUSH_STEPS == 0);
-      HIP_TRY(TIMED(KK_ADJ_STEP, st, launch_adj_step(wv.batch, n, n - n0, true, first, false, st)));
-      if (n % FLUSH_STEPS == 0) HIP_TRY(TIMED(KK_CHAIN, st, launch_chain_flush(wv.batch, st)));
+      const bool first = (n == w0.nt - 1) || ((n + 1) % FLUSH_STEPS == 0);
+      for (Lane& l : lanes) {
+        HIP_TRY(TIMED(KK_ADJ_STEP, l.st, launch_adj_step(l.wv.batch, n, n - n0, true, first, false, l.st)));
+        if (n % FLUSH_STEPS == 0) HIP_TRY(TIMED(KK_CHAIN, l.st, launch_chain_flush(l.wv.batch, l.st)));
+      }
     }
   }
   return EFWI_OK;
+}
+
+efwi_status run_reverse(Wave& wv, unsigned char* ws, hipStream_t st) {
+  std::vector<Lane> one(1);
+  one[0].wv = wv;
+  one[0].ws = ws;
+  one[0].st = st;
+  return run_reverse(one);
 }
 
 // Bytes that one time step of a shot reads and writes again at the next step: both
@@ -878,14 +931,16 @@ size_t step_bytes(const Plan2D& p) {
 // over more shots than fit is slower per cell than a launch per wave (measured on the
 // 1000 x 3000 shots: a 2-shot launch took 1.5x (forward) and 1.1x (transposed) the time
 // per cell of a 1-shot launch). Small windows are still advanced many at a time.
-efwi_status plan_waves(const std::vector<Plan2D>& plans, size_t ws_bytes, std::vector<std::pair<int, int>>& waves) {
+efwi_status plan_waves(const std::vector<Plan2D>& plans, size_t ws_bytes, std::vector<std::pair<int, int>>& waves,
+                       size_t cache_bytes = 0) {
   const int ns = (int)plans.size();
+  if (cache_bytes == 0) cache_bytes = g_wave_cache_bytes.load();
   int first = 0;
   while (first < ns) {
     int count = 0;
     size_t cached = 0;
     while (first + count < ns && wave_bytes(plans, first, count + 1) <= ws_bytes &&
-           (count == 0 || cached + step_bytes(plans[first + count]) <= g_wave_cache_bytes.load())) {
+           (count == 0 || cached + step_bytes(plans[first + count]) <= cache_bytes)) {
       cached += step_bytes(plans[first + count]);
       ++count;
     }
@@ -896,6 +951,134 @@ efwi_status plan_waves(const std::vector<Plan2D>& plans, size_t ws_bytes, std::v
     first += count;
   }
   return EFWI_OK;
+}
+
+// First-fit-decreasing packing of a batch into waves, for calls whose shots do not depend on
+// one another's order: the shots taken largest first (by workspace bytes), each into the
+// first wave that still fits it in the workspace and, beyond its first shot, in the per-step
+// state bound. Fewer, fuller waves than taking the shots in order (the batched workload's 64
+// windows: 29 waves of 3.14 M cells against 39 of 2.34 M), so longer launches. `order` lists
+// the shots wave by wave (ascending inside a wave); wave w is order[first, first + count).
+efwi_status pack_waves(const std::vector<Plan2D>& plans, size_t ws_bytes, size_t cache_bytes, std::vector<int>& order,
+                       std::vector<std::pair<int, int>>& waves) {
+  const int ns = (int)plans.size();
+  std::vector<int> idx(ns);
+  for (int k = 0; k < ns; ++k) idx[k] = k;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return plans[a].total > plans[b].total; });
+  struct Bin {
+    std::vector<int> shots;
+    size_t tiles = 0, ftiles = 0, atiles = 0, tabs = 0, total = 0, step = 0;
+  };
+  auto bytes_with = [&](const Bin& b, const Plan2D& p) {   // wave_bytes of the bin plus shot p
+    const size_t count = b.shots.size() + 1, tiles = b.tiles + p.ntiles, ftiles = b.ftiles + p.nfwd_tiles,
+                 atiles = b.atiles + p.nadj_tiles;
+    auto list = [&](size_t n) {
+      return align_up(count * sizeof(int)) + align_up(n * sizeof(int)) + align_up(sched_capacity(n) * sizeof(int));
+    };
+    auto step_list = [&](size_t n) { return align_up(sched_capacity(n) * sizeof(StepSlot)); };
+    return align_up(count * sizeof(Shot2D)) + list(tiles) + step_list(ftiles) + step_list(atiles) + b.tabs + p.tab_bytes +
+           b.total + p.total;
+  };
+  std::vector<Bin> bins;
+  for (int k : idx) {
+    const Plan2D& p = plans[k];
+    Bin* into = nullptr;
+    for (Bin& b : bins)
+      if (b.step + step_bytes(p) <= cache_bytes && bytes_with(b, p) <= ws_bytes) {
+        into = &b;
+        break;
+      }
+    if (!into) {
+      if (bytes_with(Bin{}, p) > ws_bytes)
+        return fail(EFWI_E_WORKSPACE, "workspace has %zu bytes; shot %d alone needs %zu", ws_bytes, k,
+                    bytes_with(Bin{}, p));
+      bins.emplace_back();
+      into = &bins.back();
+    }
+    into->shots.push_back(k);
+    into->tiles += p.ntiles;
+    into->ftiles += p.nfwd_tiles;
+    into->atiles += p.nadj_tiles;
+    into->tabs += p.tab_bytes;
+    into->total += p.total;
+    into->step += step_bytes(p);
+  }
+  order.clear();
+  waves.clear();
+  for (Bin& b : bins) {
+    std::sort(b.shots.begin(), b.shots.end());
+    waves.push_back({(int)order.size(), (int)b.shots.size()});
+    order.insert(order.end(), b.shots.begin(), b.shots.end());
+  }
+  return EFWI_OK;
+}
+
+// The lane plan of a 2D batch: the waves (packed when `reorder`, else in shot order) and the
+// lanes that advance them. With two lanes (efwi_set_wave_lanes) each lane takes half of the
+// workspace and half of the per-step state bound (so that the two waves running side by side
+// keep their state within the Infinity Cache together), and consecutive waves alternate
+// between the lanes. Two lanes are used when `lanes2` holds, one lane would take more than
+// one wave, every shot fits a lane's half and the two lanes' plan has at most about twice
+// the waves of one lane's; otherwise one lane takes everything.
+efwi_status plan_lanes(const std::vector<Plan2D>& plans, size_t ws_bytes, bool lanes2, bool reorder,
+                       std::vector<int>& order, std::vector<std::pair<int, int>>& waves, int& nlanes,
+                       size_t& lane_bytes) {
+  const size_t cache = g_wave_cache_bytes.load();
+  auto plan = [&](size_t ws, size_t cache_bytes) {
+    if (reorder) return pack_waves(plans, ws, cache_bytes, order, waves);
+    order.resize(plans.size());
+    for (size_t k = 0; k < plans.size(); ++k) order[k] = (int)k;
+    waves.clear();
+    return plan_waves(plans, ws, waves, cache_bytes);
+  };
+  nlanes = 1;
+  lane_bytes = ws_bytes;
+  efwi_status rc = plan(ws_bytes, cache);
+  if (rc != EFWI_OK || !lanes2 || g_wave_lanes.load() < 2 || waves.size() < 2) return rc;
+  const size_t one_lane = waves.size();
+  const size_t half = ws_bytes / 2 / ALIGN * ALIGN;
+  for (size_t k = 0; k < plans.size(); ++k)
+    if (wave_bytes(plans, (int)k, 1) > half) return EFWI_OK;
+  const std::vector<int> order1 = order;
+  const std::vector<std::pair<int, int>> waves1 = waves;
+  // two lanes when each lane's waves are not finer than half of one lane's
+  if (plan(half, std::max<size_t>(cache / 2, 1)) == EFWI_OK && waves.size() >= 2 && waves.size() <= 2 * one_lane + 1) {
+    nlanes = 2;
+    lane_bytes = half;
+    return EFWI_OK;
+  }
+  order = order1;
+  waves = waves1;
+  return EFWI_OK;
+}
+
+// The second lane's stream on the current device, created on first use (default priority,
+// not synchronizing with the null stream: the calls order it with events).
+hipError_t lane_stream(hipStream_t* out) {
+  static std::mutex mu;
+  static std::vector<hipStream_t>* streams = new std::vector<hipStream_t>();  // lives for the process
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)streams->size() <= dev) streams->resize(dev + 1, nullptr);
+  if (!(*streams)[dev]) {
+    e = hipStreamCreateWithFlags(&(*streams)[dev], hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  *out = (*streams)[dev];
+  return hipSuccess;
+}
+
+// Event-ordered hand-over between two streams: `to` waits for what `from` has enqueued so far.
+hipError_t join_streams(hipStream_t from, hipStream_t to) {
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev, from);
+  if (e == hipSuccess) e = hipStreamWaitEvent(to, ev, 0);
+  const hipError_t d = hipEventDestroy(ev);
+  return e != hipSuccess ? e : d;
 }
 
 efwi_status gradient_waves3(const efwi_grid& g, const efwi_shot* shots, int ns, const std::vector<ShotIO>& io,
@@ -916,6 +1099,71 @@ hipError_t field_misfit(const Receiver& R, unsigned char* region, size_t off_din
                              reinterpret_cast<double*>(region + off_partial), io.phi, ebar, st);
 }
 
+// The data term over a batch of 2D shots: waves set up in turn in the workspace (or in its
+// two halves, one per lane), each swept forward, its misfit taken, swept back and its
+// gradient written. Shots whose gradients add into a shared component (io.accumulate) use
+// one lane, so that the additions keep the shot order.
+efwi_status gradient_lanes(const efwi_grid& g, const efwi_shot* shots, const std::vector<ShotIO>& io,
+                           const std::vector<Plan2D>& plans, const std::vector<std::pair<int, int>>& waves,
+                           int nlanes, size_t lane_bytes, unsigned char* ws, hipStream_t st, hipStream_t st1) {
+  efwi_status rc = EFWI_OK;
+  for (size_t w = 0; w < waves.size(); w += nlanes) {
+    std::vector<Lane> lanes(std::min<size_t>(nlanes, waves.size() - w));
+    for (size_t l = 0; l < lanes.size(); ++l) {
+      lanes[l].ws = ws + l * lane_bytes;
+      lanes[l].st = l == 0 ? st : st1;
+      rc = setup_wave(g, shots, plans, waves[w + l].first, waves[w + l].second, io, EFWI_WS_GRADIENT, lanes[l].ws,
+                      lanes[l].wv, lanes[l].st);
+      if (rc != EFWI_OK) return rc;
+    }
+    rc = run_forward(lanes, true);
+    if (rc != EFWI_OK) return rc;
+    for (size_t l = 0; l < lanes.size(); ++l) {
+      const Wave& wv = lanes[l].wv;
+      const int first = waves[w + l].first;
+      hipStream_t ls = lanes[l].st;
+      for (int k = 0; k < waves[w + l].second; ++k) {
+        const Shot2D& d = wv.descs[k];
+        unsigned char* r = lanes[l].ws + wv.regions[k];
+        const Plan2D& p = wv.plans[k];
+        float* ebar = reinterpret_cast<float*>(r + p.off_ebar);
+        if (p.field) {
+          HIP_TRY(TIMED(KK_MISFIT, ls, field_misfit(p.R, r, p.off_dint, p.off_rf, p.off_partial, io[first + k], ebar, ls)));
+        } else if (io[first + k].r) {  // J^T v: the data-space vector drives the adjoint directly
+          HIP_TRY(TIMED(KK_MISFIT, ls, launch_residual_cumsum(d, io[first + k].r, ebar, ls)));
+        } else {
+          HIP_TRY(TIMED(KK_MISFIT, ls,
+                        launch_misfit(d, (const float*)(d.d), io[first + k].dobs,
+                                      reinterpret_cast<double*>(r + p.off_partial), io[first + k].phi, ebar, ls)));
+        }
+      }
+    }
+    rc = run_reverse(lanes);
+    if (rc != EFWI_OK) return rc;
+    for (size_t l = 0; l < lanes.size(); ++l) {
+      const Wave& wv = lanes[l].wv;
+      const int first = waves[w + l].first, count = waves[w + l].second;
+      hipStream_t ls = lanes[l].st;
+      if (io[first].accumulate) {  // one launch per shot, in shot order: shots of a group add deterministically
+        for (int k = 0; k < count; ++k) {
+          const Plan2D& p = wv.plans[k];
+          HIP_TRY(launch_add_gradient(reinterpret_cast<const double*>(lanes[l].ws + wv.regions[k] + p.off_G), p.cells,
+                                      p.cp, p.nz, 1, p.nx, io[first + k].gout, io[first + k].mplane, g.nx, g.nx,
+                                      p.w.z0, 0, p.w.x0, ls));
+        }
+        continue;
+      }
+      for (int k = 0; k < count; ++k) {
+        const Plan2D& p = wv.plans[k];
+        const bool full = p.w.z0 == 0 && p.w.x0 == 0 && p.nz == g.nz && p.nx == g.nx;
+        if (!full) HIP_TRY(hipMemsetAsync(io[first + k].gout, 0, (size_t)3 * io[first + k].mplane * sizeof(float), ls));
+      }
+      HIP_TRY(launch_write_gradient(wv.batch, ls));
+    }
+  }
+  return EFWI_OK;
+}
+
 efwi_status gradient_waves(const efwi_grid& g, const efwi_shot* shots, int ns, const std::vector<ShotIO>& io,
                            unsigned char* ws, size_t ws_bytes, hipStream_t st) {
   if (g.ndim == 3) return gradient_waves3(g, shots, ns, io, ws, ws_bytes, st);
@@ -924,47 +1172,31 @@ efwi_status gradient_waves(const efwi_grid& g, const efwi_shot* shots, int ns, c
   efwi_status rc = check_ws(ws, ws_bytes, wave_bytes(plans, 0, 1));
   if (rc != EFWI_OK) return rc;
   std::vector<std::pair<int, int>> waves;
-  rc = plan_waves(plans, ws_bytes, waves);
+  std::vector<int> order;
+  int nlanes = 1;
+  size_t lane_bytes = ws_bytes;
+  const bool independent = !io[0].accumulate;   // grouped shots add into shared components in shot order
+  rc = plan_lanes(plans, ws_bytes, independent && !t_no_alloc, independent, order, waves, nlanes, lane_bytes);
   if (rc != EFWI_OK) return rc;
-  for (auto [first, count] : waves) {
-    Wave wv;
-    rc = setup_wave(g, shots, plans, first, count, io, EFWI_WS_GRADIENT, ws, wv, st);
-    if (rc != EFWI_OK) return rc;
-    rc = run_forward(wv, ws, true, st);
-    if (rc != EFWI_OK) return rc;
-    for (int k = 0; k < count; ++k) {
-      const Shot2D& d = wv.descs[k];
-      unsigned char* r = ws + wv.regions[k];
-      const Plan2D& p = wv.plans[k];
-      float* ebar = reinterpret_cast<float*>(r + p.off_ebar);
-      if (p.field) {
-        HIP_TRY(TIMED(KK_MISFIT, st, field_misfit(p.R, r, p.off_dint, p.off_rf, p.off_partial, io[first + k], ebar, st)));
-      } else if (io[first + k].r) {  // J^T v: the data-space vector drives the adjoint directly
-        HIP_TRY(TIMED(KK_MISFIT, st, launch_residual_cumsum(d, io[first + k].r, ebar, st)));
-      } else {
-        HIP_TRY(TIMED(KK_MISFIT, st,
-                      launch_misfit(d, (const float*)(d.d), io[first + k].dobs,
-                                    reinterpret_cast<double*>(r + p.off_partial), io[first + k].phi, ebar, st)));
-      }
-    }
-    rc = run_reverse(wv, ws, st);
-    if (rc != EFWI_OK) return rc;
-    if (io[first].accumulate) {  // one launch per shot, in shot order: shots of a group add deterministically
-      for (int k = 0; k < count; ++k) {
-        const Plan2D& p = wv.plans[k];
-        HIP_TRY(launch_add_gradient(reinterpret_cast<const double*>(ws + wv.regions[k] + p.off_G), p.cells, p.cp, p.nz,
-                                    1, p.nx, io[first + k].gout, io[first + k].mplane, g.nx, g.nx, p.w.z0, 0, p.w.x0,
-                                    st));
-      }
-      continue;
-    }
-    for (int k = 0; k < count; ++k) {
-      const Plan2D& p = wv.plans[k];
-      const bool full = p.w.z0 == 0 && p.w.x0 == 0 && p.nz == g.nz && p.nx == g.nx;
-      if (!full) HIP_TRY(hipMemsetAsync(io[first + k].gout, 0, (size_t)3 * io[first + k].mplane * sizeof(float), st));
-    }
-    HIP_TRY(launch_write_gradient(wv.batch, st));
+  // the shots, their plans and outputs in the order the waves take them
+  std::vector<efwi_shot> sp(ns);
+  std::vector<ShotIO> iop(ns);
+  std::vector<Plan2D> pp(ns);
+  for (int q = 0; q < ns; ++q) {
+    sp[q] = shots[order[q]];
+    iop[q] = io[order[q]];
+    pp[q] = plans[order[q]];
   }
+  if (nlanes == 1) return gradient_lanes(g, sp.data(), iop, pp, waves, 1, lane_bytes, ws, st, nullptr);
+  hipStream_t st1 = nullptr;
+  HIP_TRY(lane_stream(&st1));
+  HIP_TRY(join_streams(st, st1));   // the second lane starts after the caller's earlier work
+  rc = gradient_lanes(g, sp.data(), iop, pp, waves, nlanes, lane_bytes, ws, st, st1);
+  // the caller's stream then waits for the second lane, also after an error, so that no
+  // work on the workspace is left behind the caller's stream
+  const hipError_t e = join_streams(st1, st);
+  if (rc != EFWI_OK) return rc;
+  if (e != hipSuccess) return fail(EFWI_E_HIP, "joining the lanes failed: %s", hipGetErrorString(e));
   return EFWI_OK;
 }
 
@@ -1501,6 +1733,14 @@ efwi_status efwi_set_wave_cache_bytes(size_t bytes) {
 
 size_t efwi_get_wave_cache_bytes(void) { return g_wave_cache_bytes.load(); }
 
+efwi_status efwi_set_wave_lanes(int lanes) {
+  if (lanes < 0 || lanes > 2) return fail(EFWI_E_INVAL, "lanes must be 1 or 2 (0 restores the default)");
+  g_wave_lanes.store(lanes == 0 ? DEFAULT_WAVE_LANES : lanes);
+  return EFWI_OK;
+}
+
+int efwi_get_wave_lanes(void) { return g_wave_lanes.load(); }
+
 efwi_status efwi_get_tile_rows(int* fwd_rows, int* adj_rows) {
   if (!fwd_rows || !adj_rows) return fail(EFWI_E_INVAL, "NULL output pointer");
   *fwd_rows = g_fwd_rows.load();
@@ -1771,11 +2011,13 @@ efwi_status efwi_shot_gradient_noalloc(const efwi_grid* grid, const efwi_shot* s
 }
 
 efwi_status efwi_batch_waves(const efwi_grid* grid, int ns, const efwi_shot* shots, size_t ws_bytes, int* nwaves,
-                             int* wave_first) {
+                             int* wave_first, int* order) {
   efwi_status rc = efwi_validate(grid, ns, shots);
   if (rc != EFWI_OK) return rc;
   if (ns < 1 || !nwaves) return fail(EFWI_E_INVAL, "ns must be >= 1 and nwaves not NULL");
   std::vector<std::pair<int, int>> waves;
+  std::vector<int> ord(ns);
+  for (int k = 0; k < ns; ++k) ord[k] = k;
   if (grid->ndim == 3) {
     std::vector<Plan3D> plans;
     for (int k = 0; k < ns; ++k) plans.push_back(plan3d(*grid, shots[k], EFWI_WS_GRADIENT));
@@ -1783,12 +2025,16 @@ efwi_status efwi_batch_waves(const efwi_grid* grid, int ns, const efwi_shot* sho
   } else {
     std::vector<Plan2D> plans;
     for (int k = 0; k < ns; ++k) plans.push_back(plan2d(*grid, shots[k], EFWI_WS_GRADIENT));
-    rc = plan_waves(plans, ws_bytes, waves);
+    int nlanes = 1;
+    size_t lane_bytes = ws_bytes;
+    rc = plan_lanes(plans, ws_bytes, true, true, ord, waves, nlanes, lane_bytes);
   }
   if (rc != EFWI_OK) return rc;
   *nwaves = (int)waves.size();
   if (wave_first)
     for (size_t i = 0; i < waves.size(); ++i) wave_first[i] = waves[i].first;
+  if (order)
+    for (int k = 0; k < ns; ++k) order[k] = ord[k];
   return EFWI_OK;
 }
 

@@ -161,6 +161,9 @@ __host__ __device__ inline void tile3_coords(int local, int nz, int nx, int& i, 
 // 96 and 128 MiB 8% slower and 192 MiB 0.8% slower than 256 MiB; 384 MiB gave the same
 // waves as 256 MiB there).
 constexpr size_t WAVE_CACHE_BYTES = (size_t)256 << 20;
+// Lanes of a 2D batch by default (efwi_set_wave_lanes): two lanes ran the 64 uneven windows
+// with sqrt(nt) checkpoints 4% faster than one (MI355X).
+constexpr int DEFAULT_WAVE_LANES = 2;
 // Relative cost of an interior tile and of a tile that touches a CPML strip, as integer
 // weights (measured on MI355X with the 2D kernels: CPML tiles cost ~1.5x in the forward
 // kernels and ~2x in the adjoint kernels, which also update the adjoint memory variables

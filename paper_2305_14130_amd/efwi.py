@@ -35,7 +35,8 @@ EXPORTED = ["efwi_workspace_size", "efwi_validate", "efwi_model_forward", "efwi_
             "efwi_pseudo_hessian", "efwi_das_field",
             "efwi_batch_gradient_grouped", "efwi_bspline_nodes", "efwi_bspline_expand",
             "efwi_bspline_adjoint", "efwi_shot_gradient_noalloc", "efwi_noalloc_scratch_bytes",
-            "efwi_set_wave_cache_bytes", "efwi_get_wave_cache_bytes"]
+            "efwi_set_wave_cache_bytes", "efwi_get_wave_cache_bytes", "efwi_set_wave_lanes",
+            "efwi_get_wave_lanes"]
 
 
 class Grid(ctypes.Structure):
@@ -137,6 +138,10 @@ _lib.efwi_set_wave_cache_bytes.restype = ctypes.c_int
 _lib.efwi_set_wave_cache_bytes.argtypes = [ctypes.c_size_t]
 _lib.efwi_get_wave_cache_bytes.restype = ctypes.c_size_t
 _lib.efwi_get_wave_cache_bytes.argtypes = []
+_lib.efwi_set_wave_lanes.restype = ctypes.c_int
+_lib.efwi_set_wave_lanes.argtypes = [ctypes.c_int]
+_lib.efwi_get_wave_lanes.restype = ctypes.c_int
+_lib.efwi_get_wave_lanes.argtypes = []
 _lib.efwi_autotune_workspace_size.restype = ctypes.c_size_t
 _lib.efwi_autotune_workspace_size.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), ctypes.c_int]
 _lib.efwi_autotune.restype = ctypes.c_int
@@ -147,7 +152,8 @@ _lib.efwi_zoi_weights.restype = ctypes.c_int
 _lib.efwi_final_model.restype = ctypes.c_int
 _lib.efwi_batch_waves.restype = ctypes.c_int
 _lib.efwi_batch_waves.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), ctypes.c_size_t,
-                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int)]
 _lib.efwi_plan_interval.restype = ctypes.c_int
 _lib.efwi_plan_interval.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), ctypes.c_size_t]
 _lib.efwi_validate.restype = ctypes.c_int
@@ -349,6 +355,16 @@ def set_wave_cache_bytes(nbytes: int) -> None:
 
 def get_wave_cache_bytes() -> int:
     return int(_lib.efwi_get_wave_cache_bytes())
+
+
+def set_wave_lanes(lanes: int) -> None:
+    """Lanes of a 2D batch: 1, or 2 (waves alternate between two streams, each in half of
+    the workspace); 0 restores the default."""
+    _check(_lib.efwi_set_wave_lanes(int(lanes)))
+
+
+def get_wave_lanes() -> int:
+    return int(_lib.efwi_get_wave_lanes())
 
 
 def get_tile_rows():
@@ -554,15 +570,17 @@ def batch_gradient_grouped(grid: Grid, shots, groups, m_ext, src, d_obs, g_ext=N
 
 
 def batch_waves(grid: Grid, shots, ws_bytes: int):
-    """First shot of each wave that batch_gradient advances together for a workspace of
-    ws_bytes (see efwi_batch_waves)."""
+    """The waves that batch_gradient advances for a workspace of ws_bytes, in order, each as
+    the list of its shots' indices (see efwi_batch_waves)."""
     shots = list(shots)
     arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
     n = ctypes.c_int()
     first = (ctypes.c_int * max(1, len(shots)))()
+    order = (ctypes.c_int * max(1, len(shots)))()
     _check(_lib.efwi_batch_waves(ctypes.byref(grid), len(shots), arr, ctypes.c_size_t(ws_bytes), ctypes.byref(n),
-                                 first))
-    return list(first[:n.value])
+                                 first, order))
+    starts = list(first[:n.value]) + [len(shots)]
+    return [list(order[starts[w]:starts[w + 1]]) for w in range(n.value)]
 
 
 def extension_regularizer(grid: Grid, m_ext, b, sink, eta, g_ext, phi=None, ws=None, stream=None):

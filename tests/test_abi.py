@@ -134,10 +134,9 @@ def test_batch_waves_follow_the_cache_budget(efwi):
     shots = [efwi.Shot(50, 40 + 10 * k, np.full(3, 50, np.int32), np.array([60, 63, 66], np.int32))
              for k in range(6)]
     big_ws = efwi.workspace_size(efwi.WS_BATCH, small, shots)
-    assert efwi.batch_waves(small, shots, big_ws) == [0]
+    assert efwi.batch_waves(small, shots, big_ws) == [list(range(6))]
     one = efwi.workspace_size(efwi.WS_BATCH, small, shots[:1])
-    firsts = efwi.batch_waves(small, shots, one)
-    assert firsts == list(range(6))
+    assert efwi.batch_waves(small, shots, one) == [[k] for k in range(6)]
     with pytest.raises(efwi.EfwiError) as ei:
         efwi.batch_waves(small, shots, one // 2)
     assert ei.value.status == efwi.E_WORKSPACE
@@ -145,17 +144,56 @@ def test_batch_waves_follow_the_cache_budget(efwi):
     bshots = [efwi.Shot(500, 1000 + 100 * k, np.full(4, 500, np.int32), np.array([600, 610, 620, 630], np.int32))
               for k in range(3)]
     ws = efwi.workspace_size(efwi.WS_BATCH, large, bshots)
-    assert efwi.batch_waves(large, bshots, ws) == [0, 1, 2]
+    assert efwi.batch_waves(large, bshots, ws) == [[0], [1], [2]]
     # the per-step bound can be lifted (waves sized by the workspace alone) and restored
     assert efwi.get_wave_cache_bytes() == 256 << 20
     try:
         efwi.set_wave_cache_bytes(-1)
-        assert efwi.batch_waves(large, bshots, ws) == [0]
+        assert efwi.batch_waves(large, bshots, ws) == [[0, 1, 2]]
         efwi.set_wave_cache_bytes(1)                      # below one shot: still one shot per wave
-        assert efwi.batch_waves(small, shots, big_ws) == list(range(6))
+        assert efwi.batch_waves(small, shots, big_ws) == [[k] for k in range(6)]
     finally:
         efwi.set_wave_cache_bytes(0)
     assert efwi.get_wave_cache_bytes() == 256 << 20
+
+
+def test_batch_waves_pack_largest_first(efwi):
+    """Uneven windows are packed first fit, largest first: windows of 600, 500, 400 and 500
+    columns in a workspace that holds 600 + 400 or 500 + 500 but not 600 + 500 go into two
+    waves (in order they would take three); each wave lists its shots ascending. Two lanes
+    (the default) plan each half of the workspace when one lane would take several waves and
+    every shot fits a half; other lane counts are refused."""
+    grid = efwi.make_grid(120, 700, 5.0, 5.0, 0.5e-3, 200, 10, 1e-3, 30.0, 4500.0)
+
+    def shot(wx, x0):
+        return efwi.Shot(60, x0 + wx // 2, np.full(3, 60, np.int32), np.array([x0 + 20, x0 + 23, x0 + 26], np.int32),
+                         z0=0, x0=x0, wz=120, wx=wx)
+
+    sh = [shot(600, 0), shot(500, 100), shot(400, 200), shot(500, 50)]
+    pair = lambda a, b: efwi.workspace_size(efwi.WS_BATCH, grid, [sh[a], sh[b]])
+    ws = max(pair(0, 2), pair(1, 3))
+    assert pair(0, 1) > ws and pair(1, 2) + efwi.workspace_size(efwi.WS_GRADIENT, grid, [sh[3]]) > ws
+    assert efwi.get_wave_lanes() == 2                                    # the default
+    assert efwi.batch_waves(grid, sh, ws) == [[0, 2], [1, 3]]            # a shot exceeds half: one lane
+    try:
+        efwi.set_wave_lanes(1)
+        assert efwi.get_wave_lanes() == 1
+        assert efwi.batch_waves(grid, sh, ws) == [[0, 2], [1, 3]]
+        assert efwi.batch_waves(grid, sh, 2 * ws) == [[0, 1, 2, 3]]
+        efwi.set_wave_lanes(2)
+        assert efwi.get_wave_lanes() == 2
+        assert efwi.batch_waves(grid, sh, 2 * ws) == [[0, 1, 2, 3]]     # one wave holds all: one lane
+        assert efwi.batch_waves(grid, sh[:1], 2 * ws) == [[0]]
+        efwi.set_wave_cache_bytes(1)                                       # one shot per wave, two lanes
+        assert efwi.batch_waves(grid, sh, 2 * ws) == [[0], [1], [3], [2]]
+        for bad in (-1, 3):
+            with pytest.raises(efwi.EfwiError) as ei:
+                efwi.set_wave_lanes(bad)
+            assert ei.value.status == efwi.E_INVAL
+    finally:
+        efwi.set_wave_lanes(0)
+        efwi.set_wave_cache_bytes(0)
+    assert efwi.get_wave_lanes() == 2
 
 
 @pytest.mark.parametrize("change", [

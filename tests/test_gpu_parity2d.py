@@ -273,6 +273,22 @@ def test_batch_uneven_windows_and_waves(gpu_lib):
         ws = efwi.workspace(nbytes)
         g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, torch.cat(d_obs), ws=ws)
         assert torch.equal(g1, g2) and torch.equal(p1, p2), nbytes
+    # two lanes: consecutive waves alternate between two streams, each in half of the
+    # workspace (with a workspace of 3 x full one wave holds every shot: one lane)
+    try:
+        efwi.set_wave_lanes(1)
+        g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, torch.cat(d_obs), ws=efwi.workspace(full))
+        assert torch.equal(g1, g2) and torch.equal(p1, p2)
+        efwi.set_wave_lanes(2)
+        for nbytes, cache in ((full, 1), (2 * one + (1 << 20), 0), (3 * full, 0)):
+            efwi.set_wave_cache_bytes(cache)    # 1: one shot per wave, so both lanes take waves
+            waves = efwi.batch_waves(grid, shots, nbytes)
+            assert sorted(sum(waves, [])) == list(range(len(wins)))
+            g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, torch.cat(d_obs), ws=efwi.workspace(nbytes))
+            assert torch.equal(g1, g2) and torch.equal(p1, p2), (nbytes, waves)
+    finally:
+        efwi.set_wave_lanes(0)
+        efwi.set_wave_cache_bytes(0)
     # outside each window the shot's gradient slot is zero
     for k, (z0, x0, wz, wx) in enumerate(wins):
         gk = g1[k].clone()
