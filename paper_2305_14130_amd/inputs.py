@@ -202,7 +202,7 @@ def batched_2d(nshots=64, nt=4000, nz=1000, nx=3000, seed=64, M0=1.0e16, zrange=
 # The geometry (sizes, layer depths, anomaly positions) is this recipe's own.
 # ---------------------------------------------------------------------------------------
 def guided_wave_synthetic(nz=100, nx=400, h=5.0, dt=0.5e-3, nt=1600, npml=20, M0=1.0e16, mute_m=100.0,
-                          source_errors=False):
+                          source_errors=False, anomalies=((0, 130, 0.06), (0, 270, -0.05), (1, 200, 0.06))):
     from scipy.ndimage import gaussian_filter
     z = np.arange(nz) * h
     layer = np.zeros(nz, int)
@@ -216,8 +216,9 @@ def guided_wave_synthetic(nz=100, nx=400, h=5.0, dt=0.5e-3, nt=1600, npml=20, M0
         m_start[k] = col[:, None]
     zc = int(round(0.5 * (top + bot) / h))
     m_true = m_start.copy()
-    # Vp: one faster and one slower blob; Vs: one faster blob between them (relative)
-    for k, cx, amp in ((0, 130, 0.06), (0, 270, -0.05), (1, 200, 0.06)):
+    # relative Gaussian blobs (parameter, column, amplitude); by default a faster and a slower
+    # Vp blob and a faster Vs blob between them
+    for k, cx, amp in anomalies:
         m_true[k] *= 1.0 + gaussian_blob((nz, nx), zc, cx, 6.0, amp)
     src_ix = [100, 200, 300]
     all_ch = np.arange(30, nx - 30, 2).astype(np.int32)

@@ -322,7 +322,7 @@ def inverse_pseudo_hessian(prob, clip):
 
 def synthetic_comparison(source_errors=False, eta_rel=1.0, max_iter=60, rate_tol=1e-3, nt=1600, mute_m=100.0,
                          device=None, log=None, methods=("conventional", "extended"), ph_mute_m=200.0,
-                         ph_clip=0.01):
+                         ph_clip=0.01, sink_m=(20.0, 100.0), anomalies=None, shift_cells=1):
     """Conventional and extended FWI on the guided-wave synthetic (inputs.guided_wave_synthetic):
     noise-free data from the true model and the true sources, inverted with the exact or the
     perturbed source parameters; returns the iterations, stop reasons and the cosine
@@ -332,11 +332,15 @@ def synthetic_comparison(source_errors=False, eta_rel=1.0, max_iter=60, rate_tol
     the starting data misfit. ``methods`` may also name the paper's two alternatives:
     "mute_pseudo_hessian" (channels within ph_mute_m of a source dropped, the approximate
     inverse pseudo-Hessian with clip fraction ph_clip as the initial inverse Hessian) and
-    "gradient_preconditioning" (eq.(15) with the extended FWI's zones)."""
+    "gradient_preconditioning" (eq.(15) with the extended FWI's zones). ``sink_m`` gives the
+    sinkholes' vertical and horizontal semi-axes in metres; ``anomalies`` the true model's
+    blobs (inputs.guided_wave_synthetic); ``shift_cells`` the assumed sources' shift to the
+    left in the source-error protocol."""
     from . import inputs
     dev = device if device is not None else torch.device("cuda")
-    w_true = inputs.guided_wave_synthetic(nt=nt, mute_m=mute_m)
-    w = inputs.with_source_errors(w_true) if source_errors else w_true
+    kw = {} if anomalies is None else {"anomalies": anomalies}
+    w_true = inputs.guided_wave_synthetic(nt=nt, mute_m=mute_m, **kw)
+    w = inputs.with_source_errors(w_true, shift_cells=shift_cells) if source_errors else w_true
     grid = efwi.make_grid(w.nz, w.nx, w.dz, w.dx, w.dt, w.nt, w.npml, w.pml_R, w.f0, w.vp_max)
     T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
     m_true = T(w_true.m_true)
@@ -344,10 +348,10 @@ def synthetic_comparison(source_errors=False, eta_rel=1.0, max_iter=60, rate_tol
                                           T(np.outer(s.M, w_true.stf))) for s in w_true.shots])
     # zones of influence around the assumed source positions: an elliptical sinkhole
     # (20 m vertical, 100 m horizontal semi-axes) in a zone covering the whole model
-    zones = [efwi.make_zone((s.src_iz * w.dz, 0.0, s.src_ix * w.dx), (1 / 20.0 ** 2, 0.0, 1 / 100.0 ** 2, 0.0, 0.0, 0.0),
+    zones = [efwi.make_zone((s.src_iz * w.dz, 0.0, s.src_ix * w.dx), (1 / sink_m[0] ** 2, 0.0, 1 / sink_m[1] ** 2, 0.0, 0.0, 0.0),
                             (0.0, (w.nz - 1) * w.dz, 0.0, 0.0, 0.0, (w.nx - 1) * w.dx), 0.0) for s in w.shots]
     b, sink = efwi.zoi_weights(grid, zones, 2.0, 0.9, device=dev)
-    out = {"source_errors": source_errors, "eta_rel": eta_rel, "mute_m": mute_m}
+    out = {"source_errors": source_errors, "eta_rel": eta_rel, "mute_m": mute_m, "sink_m": list(sink_m)}
     P = w.npml + 1
     interior = (slice(None), slice(P, w.nz - P), slice(P, w.nx - P))
     true_pert = (w_true.m_true[:2] - w.m_start[:2]) / w.m_start[:2]
@@ -359,8 +363,8 @@ def synthetic_comparison(source_errors=False, eta_rel=1.0, max_iter=60, rate_tol
                 "gradient_preconditioning": lambda: (PreconditionedFWI(w, d_obs, b, sink, dev), None)}
 
     def muted():
-        wt = inputs.guided_wave_synthetic(nt=nt, mute_m=ph_mute_m)
-        wm = inputs.with_source_errors(wt) if source_errors else wt
+        wt = inputs.guided_wave_synthetic(nt=nt, mute_m=ph_mute_m, **kw)
+        wm = inputs.with_source_errors(wt, shift_cells=shift_cells) if source_errors else wt
         dm = torch.cat([efwi.model_forward(grid, efwi.Shot(s.src_iz, s.src_ix, s.ch_iz, s.ch_ix), m_true,
                                            T(np.outer(s.M, wt.stf))) for s in wt.shots])
         prob = ConventionalFWI(wm, dm, dev)
