@@ -707,7 +707,8 @@ def main():  # noqa: C901
                                f"per-shot m_s gradients + extension regularizer (hard sinkholes), FP32, "
                                f"checkpoint interval {L}",
                    "shots": ns, "nt": nt, "cells": int(cells), "ckpt_interval": L,
-                   "recompute_fraction": round(rf, 4), "waves": len(waves), "form": "batched (efwi_batch_gradient)",
+                   "recompute_fraction": round(rf, 4), "waves": len(waves), "lanes_setting": efwi.get_wave_lanes(),
+                   "form": "batched (efwi_batch_gradient, shots packed into waves largest first)",
                    "wave_cache_MiB": efwi.get_wave_cache_bytes() / 2**20 if efwi.get_wave_cache_bytes() < 2**63 else None,
                    "tile_rows": {"forward": tiles[0], "transposed": tiles[1],
                                  "autotune_ms": {str(k): [round(x, 3) for x in v] for k, v in tune_ms.items()}}},
