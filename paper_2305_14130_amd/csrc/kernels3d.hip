@@ -73,14 +73,28 @@ __device__ __forceinline__ float dminus(P f, unsigned o, unsigned st, float r) {
   return (K1 * (G(f, o) - G(f, o - st)) + K2 * (G(f, o + st) - G(f, o - 2 * st))) * r;
 }
 
-__device__ __forceinline__ long xq(const Shot3D& s, int i, int k, int sx) { return ((long)i * s.ny + k) * 2 * s.P + sx; }
-__device__ __forceinline__ long yq(const Shot3D& s, int i, int sy, int j) { return ((long)i * 2 * s.P + sy) * s.nx + j; }
-__device__ __forceinline__ long zq(const Shot3D& s, int sz, int k, int j) { return ((long)sz * s.ny + k) * s.nx + j; }
-
-__device__ __forceinline__ bool tile_in_pml(const Shot3D& s, int i, int k0, int j0, int pad) {
-  if (s.P <= 0) return false;
-  return (j0 - pad < s.P) || (j0 + TX - 1 + pad >= s.nx - s.P) || (k0 - pad < s.P) ||
-         (k0 + TILE3_Y - 1 + pad >= s.ny - s.P) || (i - pad < s.P) || (i + pad >= s.nz - s.P);
+// Element offsets into the strip arrays (32-bit: a strip array holds far fewer than 2^30
+// elements at the sizes the plans allow).
+__device__ __forceinline__ unsigned xq(const Shot3D& s, int i, int k, int sx) {
+  return ((unsigned)i * (unsigned)s.ny + (unsigned)k) * (2u * (unsigned)s.P) + (unsigned)sx;
+}
+__device__ __forceinline__ unsigned yq(const Shot3D& s, int i, int sy, int j) {
+  return ((unsigned)i * (2u * (unsigned)s.P) + (unsigned)sy) * (unsigned)s.nx + (unsigned)j;
+}
+__device__ __forceinline__ unsigned zq(const Shot3D& s, int sz, int k, int j) {
+  return ((unsigned)sz * (unsigned)s.ny + (unsigned)k) * (unsigned)s.nx + (unsigned)j;
+}
+// Strip node of coordinate k on an axis of n nodes (strip_index), clamped into 0 .. 2P-1 so
+// that it always addresses the strip arrays; `in` tells whether k lies in a strip of the
+// grid. The CPML code reads the strip arrays at the clamped node unconditionally and keeps
+// the result only where `in` holds: no load sits in a (divergent) branch, so a cell's loads
+// are issued together instead of one memory round trip per branch. Only the CPML code paths
+// call it, which run only when the strips exist (P > 0, see pml_axes).
+__device__ __forceinline__ int strip_clamp(int k, int n, int P, bool& in) {
+  const bool lo = k < P, hi = k >= n - P;
+  in = (lo && k >= 0) || (hi && k < n);
+  const int sk = lo ? k : k - (n - 2 * P);
+  return min(max(sk, 0), 2 * P - 1);
 }
 
 // Which axes' CPML strips a tile's cells (widened by pad on every side) reach: bit 0 x,
@@ -154,7 +168,7 @@ __device__ __forceinline__ float cpml_new(const gfloat* psi, unsigned q, const g
 // ------------------------------------------------------------------------------------
 // Forward velocity half step.
 // ------------------------------------------------------------------------------------
-template <bool STORE, bool PML>
+template <bool STORE, bool PX, bool PY, bool PZ>
 __device__ __forceinline__ void fwd_vel3(const Shot3D& s, int i, int k, int j, gfloat* seg) {
   const unsigned ld = (unsigned)s.ld, pz = (unsigned)s.pz;
   const unsigned o = cell_ofs(s, i, k, j);
@@ -162,39 +176,37 @@ __device__ __forceinline__ void fwd_vel3(const Shot3D& s, int i, int k, int j, g
   float b1 = dminus(PF(s.sxy), o, 1u, s.rdx), b2 = dplus(PF(s.syy), o, ld, s.rdy), b3 = dminus(PF(s.syz), o, pz, s.rdz);
   float c1 = dminus(PF(s.sxz), o, 1u, s.rdx), c2 = dminus(PF(s.syz), o, ld, s.rdy), c3 = dplus(PF(s.szz), o, pz, s.rdz);
   const float vx = G(PF(s.vx), o), vy = G(PF(s.vy), o), vz = G(PF(s.vz), o), bx = G(PF(s.bx), o), by = G(PF(s.by), o), bz = G(PF(s.bz), o);
-  int sx = -1, sy = -1, sz = -1;
+  bool inx = false, iny = false, inz = false;
   unsigned qxs = 0, qys = 0, qzs = 0;
   float p[9];
-  if (PML) {
-    sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
-    if (sx >= 0) {
-      qxs = (unsigned)xq(s, i, k, sx);
-      a1 = cpml_new(s.psx[XS_VX], qxs, px_(s, 2), px_(s, 3), j, a1, p[0]);
-      b1 = cpml_new(s.psx[XS_VY], qxs, px_(s, 0), px_(s, 1), j, b1, p[1]);
-      c1 = cpml_new(s.psx[XS_VZ], qxs, px_(s, 0), px_(s, 1), j, c1, p[2]);
-    }
-    if (sy >= 0) {
-      qys = (unsigned)yq(s, i, sy, j);
-      a2 = cpml_new(s.psy[YS_VX], qys, py_(s, 0), py_(s, 1), k, a2, p[3]);
-      b2 = cpml_new(s.psy[YS_VY], qys, py_(s, 2), py_(s, 3), k, b2, p[4]);
-      c2 = cpml_new(s.psy[YS_VZ], qys, py_(s, 0), py_(s, 1), k, c2, p[5]);
-    }
-    if (sz >= 0) {
-      qzs = (unsigned)zq(s, sz, k, j);
-      a3 = cpml_new(s.psz[ZS_VX], qzs, pz_(s, 0), pz_(s, 1), i, a3, p[6]);
-      b3 = cpml_new(s.psz[ZS_VY], qzs, pz_(s, 0), pz_(s, 1), i, b3, p[7]);
-      c3 = cpml_new(s.psz[ZS_VZ], qzs, pz_(s, 2), pz_(s, 3), i, c3, p[8]);
-    }
+  if (PX) {
+    qxs = xq(s, i, k, strip_clamp(j, s.nx, s.P, inx));
+    const float ta = cpml_new(s.psx[XS_VX], qxs, px_(s, 2), px_(s, 3), j, a1, p[0]);
+    const float tb = cpml_new(s.psx[XS_VY], qxs, px_(s, 0), px_(s, 1), j, b1, p[1]);
+    const float tc = cpml_new(s.psx[XS_VZ], qxs, px_(s, 0), px_(s, 1), j, c1, p[2]);
+    a1 = inx ? ta : a1, b1 = inx ? tb : b1, c1 = inx ? tc : c1;
+  }
+  if (PY) {
+    qys = yq(s, i, strip_clamp(k, s.ny, s.P, iny), j);
+    const float ta = cpml_new(s.psy[YS_VX], qys, py_(s, 0), py_(s, 1), k, a2, p[3]);
+    const float tb = cpml_new(s.psy[YS_VY], qys, py_(s, 2), py_(s, 3), k, b2, p[4]);
+    const float tc = cpml_new(s.psy[YS_VZ], qys, py_(s, 0), py_(s, 1), k, c2, p[5]);
+    a2 = iny ? ta : a2, b2 = iny ? tb : b2, c2 = iny ? tc : c2;
+  }
+  if (PZ) {
+    qzs = zq(s, strip_clamp(i, s.nz, s.P, inz), k, j);
+    const float ta = cpml_new(s.psz[ZS_VX], qzs, pz_(s, 0), pz_(s, 1), i, a3, p[6]);
+    const float tb = cpml_new(s.psz[ZS_VY], qzs, pz_(s, 0), pz_(s, 1), i, b3, p[7]);
+    const float tc = cpml_new(s.psz[ZS_VZ], qzs, pz_(s, 2), pz_(s, 3), i, c3, p[8]);
+    a3 = inz ? ta : a3, b3 = inz ? tb : b3, c3 = inz ? tc : c3;
   }
   const float qx = a1 + a2 + a3, qy = b1 + b2 + b3, qz = c1 + c2 + c3;
   G(PF(s.vx), o) = vx + s.dt * bx * qx;
   G(PF(s.vy), o) = vy + s.dt * by * qy;
   G(PF(s.vz), o) = vz + s.dt * bz * qz;
-  if (PML) {
-    if (sx >= 0) G(s.psx[XS_VX], qxs) = p[0], G(s.psx[XS_VY], qxs) = p[1], G(s.psx[XS_VZ], qxs) = p[2];
-    if (sy >= 0) G(s.psy[YS_VX], qys) = p[3], G(s.psy[YS_VY], qys) = p[4], G(s.psy[YS_VZ], qys) = p[5];
-    if (sz >= 0) G(s.psz[ZS_VX], qzs) = p[6], G(s.psz[ZS_VY], qzs) = p[7], G(s.psz[ZS_VZ], qzs) = p[8];
-  }
+  if (PX && inx) G(s.psx[XS_VX], qxs) = p[0], G(s.psx[XS_VY], qxs) = p[1], G(s.psx[XS_VZ], qxs) = p[2];
+  if (PY && iny) G(s.psy[YS_VX], qys) = p[3], G(s.psy[YS_VY], qys) = p[4], G(s.psy[YS_VZ], qys) = p[5];
+  if (PZ && inz) G(s.psz[ZS_VX], qzs) = p[6], G(s.psz[ZS_VY], qzs) = p[7], G(s.psz[ZS_VZ], qzs) = p[8];
   if (STORE) {
     const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
     hist_put(seg, 6 * cells + c, qx / bx);
@@ -208,15 +220,16 @@ __global__ __launch_bounds__(TX * TY) void k3_fwd_vel(PARAMS3, int kstore) {
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
     gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG3 * s.cells : nullptr;
-    if (tile_in_pml(s, i, k0, j0, 0)) fwd_vel3<STORE, true>(s, i, k, j, seg);
-    else fwd_vel3<STORE, false>(s, i, k, j, seg);
+#define CALL(X, Y, Z) fwd_vel3<STORE, X, Y, Z>(s, i, k, j, seg)
+    DISPATCH_AXES(pml_axes(s, i, k0, j0, 0), CALL);
+#undef CALL
   }
 }
 
 // ------------------------------------------------------------------------------------
 // Forward stress half step + six-component moment-tensor injection + DAS e_xx record.
 // ------------------------------------------------------------------------------------
-template <bool STORE, bool RECORD, bool PML>
+template <bool STORE, bool RECORD, bool PX, bool PY, bool PZ>
 __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, int n, gfloat* seg) {
   const unsigned ld = (unsigned)s.ld, pz = (unsigned)s.pz;
   const unsigned o = cell_ofs(s, i, k, j);
@@ -229,29 +242,29 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
   const float mxy = G(PF(s.muxy), o), mxz = G(PF(s.muxz), o), myz = G(PF(s.muyz), o);
   const float sxx0 = G(PF(s.sxx), o), syy0 = G(PF(s.syy), o), szz0 = G(PF(s.szz), o), sxy0 = G(PF(s.sxy), o), sxz0 = G(PF(s.sxz), o), syz0 = G(PF(s.syz), o);
   const int slot = RECORD ? s.row_slot[(long)i * s.ny + k] : -1;
-  int sx = -1, sy = -1, sz = -1;
+  bool inx = false, iny = false, inz = false;
   unsigned qxs = 0, qys = 0, qzs = 0;
   float p[9];
-  if (PML) {
-    sx = strip_index(j, s.nx, s.P), sy = strip_index(k, s.ny, s.P), sz = strip_index(i, s.nz, s.P);
-    if (sx >= 0) {
-      qxs = (unsigned)xq(s, i, k, sx);
-      pxx = cpml_new(s.psx[XS_PXX], qxs, px_(s, 0), px_(s, 1), j, pxx, p[0]);
-      vy_x = cpml_new(s.psx[XS_SXY], qxs, px_(s, 2), px_(s, 3), j, vy_x, p[1]);
-      vz_x = cpml_new(s.psx[XS_SXZ], qxs, px_(s, 2), px_(s, 3), j, vz_x, p[2]);
-    }
-    if (sy >= 0) {
-      qys = (unsigned)yq(s, i, sy, j);
-      pyy = cpml_new(s.psy[YS_PYY], qys, py_(s, 0), py_(s, 1), k, pyy, p[3]);
-      vx_y = cpml_new(s.psy[YS_SXY], qys, py_(s, 2), py_(s, 3), k, vx_y, p[4]);
-      vz_y = cpml_new(s.psy[YS_SYZ], qys, py_(s, 2), py_(s, 3), k, vz_y, p[5]);
-    }
-    if (sz >= 0) {
-      qzs = (unsigned)zq(s, sz, k, j);
-      pzz = cpml_new(s.psz[ZS_PZZ], qzs, pz_(s, 0), pz_(s, 1), i, pzz, p[6]);
-      vx_z = cpml_new(s.psz[ZS_SXZ], qzs, pz_(s, 2), pz_(s, 3), i, vx_z, p[7]);
-      vy_z = cpml_new(s.psz[ZS_SYZ], qzs, pz_(s, 2), pz_(s, 3), i, vy_z, p[8]);
-    }
+  if (PX) {
+    qxs = xq(s, i, k, strip_clamp(j, s.nx, s.P, inx));
+    const float ta = cpml_new(s.psx[XS_PXX], qxs, px_(s, 0), px_(s, 1), j, pxx, p[0]);
+    const float tb = cpml_new(s.psx[XS_SXY], qxs, px_(s, 2), px_(s, 3), j, vy_x, p[1]);
+    const float tc = cpml_new(s.psx[XS_SXZ], qxs, px_(s, 2), px_(s, 3), j, vz_x, p[2]);
+    pxx = inx ? ta : pxx, vy_x = inx ? tb : vy_x, vz_x = inx ? tc : vz_x;
+  }
+  if (PY) {
+    qys = yq(s, i, strip_clamp(k, s.ny, s.P, iny), j);
+    const float ta = cpml_new(s.psy[YS_PYY], qys, py_(s, 0), py_(s, 1), k, pyy, p[3]);
+    const float tb = cpml_new(s.psy[YS_SXY], qys, py_(s, 2), py_(s, 3), k, vx_y, p[4]);
+    const float tc = cpml_new(s.psy[YS_SYZ], qys, py_(s, 2), py_(s, 3), k, vz_y, p[5]);
+    pyy = iny ? ta : pyy, vx_y = iny ? tb : vx_y, vz_y = iny ? tc : vz_y;
+  }
+  if (PZ) {
+    qzs = zq(s, strip_clamp(i, s.nz, s.P, inz), k, j);
+    const float ta = cpml_new(s.psz[ZS_PZZ], qzs, pz_(s, 0), pz_(s, 1), i, pzz, p[6]);
+    const float tb = cpml_new(s.psz[ZS_SXZ], qzs, pz_(s, 2), pz_(s, 3), i, vx_z, p[7]);
+    const float tc = cpml_new(s.psz[ZS_SYZ], qzs, pz_(s, 2), pz_(s, 3), i, vy_z, p[8]);
+    pzz = inz ? ta : pzz, vx_z = inz ? tb : vx_z, vy_z = inz ? tc : vy_z;
   }
   const float tr = pxx + pyy + pzz;
   const float sxy_r = vx_y + vy_x, sxz_r = vx_z + vz_x, syz_r = vy_z + vz_y;
@@ -277,11 +290,9 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
   G(PF(s.sxy), o) = sxy;
   G(PF(s.sxz), o) = sxz;
   G(PF(s.syz), o) = syz;
-  if (PML) {
-    if (sx >= 0) G(s.psx[XS_PXX], qxs) = p[0], G(s.psx[XS_SXY], qxs) = p[1], G(s.psx[XS_SXZ], qxs) = p[2];
-    if (sy >= 0) G(s.psy[YS_PYY], qys) = p[3], G(s.psy[YS_SXY], qys) = p[4], G(s.psy[YS_SYZ], qys) = p[5];
-    if (sz >= 0) G(s.psz[ZS_PZZ], qzs) = p[6], G(s.psz[ZS_SXZ], qzs) = p[7], G(s.psz[ZS_SYZ], qzs) = p[8];
-  }
+  if (PX && inx) G(s.psx[XS_PXX], qxs) = p[0], G(s.psx[XS_SXY], qxs) = p[1], G(s.psx[XS_SXZ], qxs) = p[2];
+  if (PY && iny) G(s.psy[YS_PYY], qys) = p[3], G(s.psy[YS_SXY], qys) = p[4], G(s.psy[YS_SYZ], qys) = p[5];
+  if (PZ && inz) G(s.psz[ZS_PZZ], qzs) = p[6], G(s.psz[ZS_SXZ], qzs) = p[7], G(s.psz[ZS_SYZ], qzs) = p[8];
   if (RECORD) {
     if (slot >= 0) {
       const int c = s.rowch[(long)slot * s.nx + j];
@@ -309,8 +320,9 @@ __global__ __launch_bounds__(TX * TY) void k3_fwd_str(PARAMS3, int n, int kstore
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
     gfloat* seg = STORE ? s.seg + (size_t)kstore * NSEG3 * s.cells : nullptr;
-    if (tile_in_pml(s, i, k0, j0, 0)) fwd_str3<STORE, RECORD, true>(s, i, k, j, n, seg);
-    else fwd_str3<STORE, RECORD, false>(s, i, k, j, n, seg);
+#define CALL(X, Y, Z) fwd_str3<STORE, RECORD, X, Y, Z>(s, i, k, j, n, seg)
+    DISPATCH_AXES(pml_axes(s, i, k0, j0, 0), CALL);
+#undef CALL
   }
 }
 
@@ -319,32 +331,35 @@ __global__ __launch_bounds__(TX * TY) void k3_fwd_str(PARAMS3, int n, int kstore
 // the CPML strip of the derivative's axis (psi_bar from the buffer of step n+1), v outside.
 // PX, PY, PZ: the tile's stencil reaches a strip on that axis (otherwise no correction on
 // it is possible). A neighbour differs from the owned node only along the derivative's
-// axis, so only that index needs a range check (strip_index is negative below 0).
+// axis, so only that index is range-checked (strip_clamp).
 // ------------------------------------------------------------------------------------
 template <bool PX, bool PY, bool PZ>
 struct Adj3 {
   const Shot3D& s;
   int rd;
   __device__ __forceinline__ float cx(float v, int i, int k, int j, int slot, int prof) const {
-    if (PX && j < s.nx) {
-      const int sx = strip_index(j, s.nx, s.P);
-      if (sx >= 0) v += px_(s, prof)[j] * (G(s.pbx[rd][slot], (unsigned)xq(s, i, k, sx)) + v);
-    }
-    return v;
+    if (!PX) return v;
+    bool in;
+    const unsigned q = xq(s, i, k, strip_clamp(j, s.nx, s.P, in));
+    float c = v;
+    c += px_(s, prof)[min(max(j, 0), s.nx - 1)] * (G(s.pbx[rd][slot], q) + c);
+    return in ? c : v;
   }
   __device__ __forceinline__ float cy(float v, int i, int k, int j, int slot, int prof) const {
-    if (PY && k < s.ny) {
-      const int sy = strip_index(k, s.ny, s.P);
-      if (sy >= 0) v += py_(s, prof)[k] * (G(s.pby[rd][slot], (unsigned)yq(s, i, sy, j)) + v);
-    }
-    return v;
+    if (!PY) return v;
+    bool in;
+    const unsigned q = yq(s, i, strip_clamp(k, s.ny, s.P, in), j);
+    float c = v;
+    c += py_(s, prof)[min(max(k, 0), s.ny - 1)] * (G(s.pby[rd][slot], q) + c);
+    return in ? c : v;
   }
   __device__ __forceinline__ float cz(float v, int i, int k, int j, int slot, int prof) const {
-    if (PZ && i < s.nz) {
-      const int sz = strip_index(i, s.nz, s.P);
-      if (sz >= 0) v += pz_(s, prof)[i] * (G(s.pbz[rd][slot], (unsigned)zq(s, sz, k, j)) + v);
-    }
-    return v;
+    if (!PZ) return v;
+    bool in;
+    const unsigned q = zq(s, strip_clamp(i, s.nz, s.P, in), k, j);
+    float c = v;
+    c += pz_(s, prof)[min(max(i, 0), s.nz - 1)] * (G(s.pbz[rd][slot], q) + c);
+    return in ? c : v;
   }
   __device__ __forceinline__ float at(const gfloat* f, int i, int k, int j) const {
     return s.dt * G(PF(f), cell_ofs(s, i, k, j));
@@ -404,25 +419,35 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
   G(PF(s.uzb), o) = uz + bz * gz;
   if (PX || PY || PZ) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
     const float dt = s.dt;
-    const int sx = PX ? strip_index(j, s.nx, s.P) : -1, sy = PY ? strip_index(k, s.ny, s.P) : -1,
-              sz = PZ ? strip_index(i, s.nz, s.P) : -1;
-    if (sx >= 0) {
-      const unsigned q = (unsigned)xq(s, i, k, sx);
-      G(s.pbx[wr][XS_PXX], q) = px_(s, 1)[j] * (G(s.pbx[rd][XS_PXX], q) + dt * txx);
-      G(s.pbx[wr][XS_SXY], q) = px_(s, 3)[j] * (G(s.pbx[rd][XS_SXY], q) + dt * txy);
-      G(s.pbx[wr][XS_SXZ], q) = px_(s, 3)[j] * (G(s.pbx[rd][XS_SXZ], q) + dt * txz);
+    if (PX) {
+      bool in;
+      const unsigned q = xq(s, i, k, strip_clamp(j, s.nx, s.P, in));
+      const float o0 = G(s.pbx[rd][XS_PXX], q), o1 = G(s.pbx[rd][XS_SXY], q), o2 = G(s.pbx[rd][XS_SXZ], q);
+      if (in) {
+        G(s.pbx[wr][XS_PXX], q) = px_(s, 1)[j] * (o0 + dt * txx);
+        G(s.pbx[wr][XS_SXY], q) = px_(s, 3)[j] * (o1 + dt * txy);
+        G(s.pbx[wr][XS_SXZ], q) = px_(s, 3)[j] * (o2 + dt * txz);
+      }
     }
-    if (sy >= 0) {
-      const unsigned q = (unsigned)yq(s, i, sy, j);
-      G(s.pby[wr][YS_PYY], q) = py_(s, 1)[k] * (G(s.pby[rd][YS_PYY], q) + dt * tyy);
-      G(s.pby[wr][YS_SXY], q) = py_(s, 3)[k] * (G(s.pby[rd][YS_SXY], q) + dt * txy);
-      G(s.pby[wr][YS_SYZ], q) = py_(s, 3)[k] * (G(s.pby[rd][YS_SYZ], q) + dt * tyz);
+    if (PY) {
+      bool in;
+      const unsigned q = yq(s, i, strip_clamp(k, s.ny, s.P, in), j);
+      const float o0 = G(s.pby[rd][YS_PYY], q), o1 = G(s.pby[rd][YS_SXY], q), o2 = G(s.pby[rd][YS_SYZ], q);
+      if (in) {
+        G(s.pby[wr][YS_PYY], q) = py_(s, 1)[k] * (o0 + dt * tyy);
+        G(s.pby[wr][YS_SXY], q) = py_(s, 3)[k] * (o1 + dt * txy);
+        G(s.pby[wr][YS_SYZ], q) = py_(s, 3)[k] * (o2 + dt * tyz);
+      }
     }
-    if (sz >= 0) {
-      const unsigned q = (unsigned)zq(s, sz, k, j);
-      G(s.pbz[wr][ZS_PZZ], q) = pz_(s, 1)[i] * (G(s.pbz[rd][ZS_PZZ], q) + dt * tzz);
-      G(s.pbz[wr][ZS_SXZ], q) = pz_(s, 3)[i] * (G(s.pbz[rd][ZS_SXZ], q) + dt * txz);
-      G(s.pbz[wr][ZS_SYZ], q) = pz_(s, 3)[i] * (G(s.pbz[rd][ZS_SYZ], q) + dt * tyz);
+    if (PZ) {
+      bool in;
+      const unsigned q = zq(s, strip_clamp(i, s.nz, s.P, in), k, j);
+      const float o0 = G(s.pbz[rd][ZS_PZZ], q), o1 = G(s.pbz[rd][ZS_SXZ], q), o2 = G(s.pbz[rd][ZS_SYZ], q);
+      if (in) {
+        G(s.pbz[wr][ZS_PZZ], q) = pz_(s, 1)[i] * (o0 + dt * tzz);
+        G(s.pbz[wr][ZS_SXZ], q) = pz_(s, 3)[i] * (o1 + dt * txz);
+        G(s.pbz[wr][ZS_SYZ], q) = pz_(s, 3)[i] * (o2 + dt * tyz);
+      }
     }
   }
   if (GRAD) {
@@ -465,7 +490,10 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
 }
 
 template <bool GRAD, bool SRCADJ>
-__global__ __launch_bounds__(TX * TY) void k3_adj_vel(PARAMS3, int n, int kseg, int first) {
+// At least 4 waves per SIMD (at most 128 VGPRs; the compiler takes 121 without spilling):
+// 1.59 ms per 300 x 400 x 400 launch against 1.73 ms with its own allocation (136 VGPRs, 3
+// waves) and 2.02 ms capped at 5 waves (spills).
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(4))) void k3_adj_vel(PARAMS3, int n, int kseg, int first) {
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
     const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
@@ -514,25 +542,35 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
   G(PF(s.tyzb), o) = tyz + myz * dyz;
   if (PX || PY || PZ) {  // adjoint memory variables: step n + 1 (read buffer) -> step n (write buffer)
     const float dt = s.dt;
-    const int sx = PX ? strip_index(j, s.nx, s.P) : -1, sy = PY ? strip_index(k, s.ny, s.P) : -1,
-              sz = PZ ? strip_index(i, s.nz, s.P) : -1;
-    if (sx >= 0) {
-      const unsigned q = (unsigned)xq(s, i, k, sx);
-      G(s.pbx[wr][XS_VX], q) = px_(s, 3)[j] * (G(s.pbx[rd][XS_VX], q) + dt * ux);
-      G(s.pbx[wr][XS_VY], q) = px_(s, 1)[j] * (G(s.pbx[rd][XS_VY], q) + dt * uy);
-      G(s.pbx[wr][XS_VZ], q) = px_(s, 1)[j] * (G(s.pbx[rd][XS_VZ], q) + dt * uz);
+    if (PX) {
+      bool in;
+      const unsigned q = xq(s, i, k, strip_clamp(j, s.nx, s.P, in));
+      const float o0 = G(s.pbx[rd][XS_VX], q), o1 = G(s.pbx[rd][XS_VY], q), o2 = G(s.pbx[rd][XS_VZ], q);
+      if (in) {
+        G(s.pbx[wr][XS_VX], q) = px_(s, 3)[j] * (o0 + dt * ux);
+        G(s.pbx[wr][XS_VY], q) = px_(s, 1)[j] * (o1 + dt * uy);
+        G(s.pbx[wr][XS_VZ], q) = px_(s, 1)[j] * (o2 + dt * uz);
+      }
     }
-    if (sy >= 0) {
-      const unsigned q = (unsigned)yq(s, i, sy, j);
-      G(s.pby[wr][YS_VX], q) = py_(s, 1)[k] * (G(s.pby[rd][YS_VX], q) + dt * ux);
-      G(s.pby[wr][YS_VY], q) = py_(s, 3)[k] * (G(s.pby[rd][YS_VY], q) + dt * uy);
-      G(s.pby[wr][YS_VZ], q) = py_(s, 1)[k] * (G(s.pby[rd][YS_VZ], q) + dt * uz);
+    if (PY) {
+      bool in;
+      const unsigned q = yq(s, i, strip_clamp(k, s.ny, s.P, in), j);
+      const float o0 = G(s.pby[rd][YS_VX], q), o1 = G(s.pby[rd][YS_VY], q), o2 = G(s.pby[rd][YS_VZ], q);
+      if (in) {
+        G(s.pby[wr][YS_VX], q) = py_(s, 1)[k] * (o0 + dt * ux);
+        G(s.pby[wr][YS_VY], q) = py_(s, 3)[k] * (o1 + dt * uy);
+        G(s.pby[wr][YS_VZ], q) = py_(s, 1)[k] * (o2 + dt * uz);
+      }
     }
-    if (sz >= 0) {
-      const unsigned q = (unsigned)zq(s, sz, k, j);
-      G(s.pbz[wr][ZS_VX], q) = pz_(s, 1)[i] * (G(s.pbz[rd][ZS_VX], q) + dt * ux);
-      G(s.pbz[wr][ZS_VY], q) = pz_(s, 1)[i] * (G(s.pbz[rd][ZS_VY], q) + dt * uy);
-      G(s.pbz[wr][ZS_VZ], q) = pz_(s, 3)[i] * (G(s.pbz[rd][ZS_VZ], q) + dt * uz);
+    if (PZ) {
+      bool in;
+      const unsigned q = zq(s, strip_clamp(i, s.nz, s.P, in), k, j);
+      const float o0 = G(s.pbz[rd][ZS_VX], q), o1 = G(s.pbz[rd][ZS_VY], q), o2 = G(s.pbz[rd][ZS_VZ], q);
+      if (in) {
+        G(s.pbz[wr][ZS_VX], q) = pz_(s, 1)[i] * (o0 + dt * ux);
+        G(s.pbz[wr][ZS_VY], q) = pz_(s, 1)[i] * (o1 + dt * uy);
+        G(s.pbz[wr][ZS_VZ], q) = pz_(s, 3)[i] * (o2 + dt * uz);
+      }
     }
   }
   if (GRAD) {
@@ -548,7 +586,9 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
 }
 
 template <bool GRAD>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(8, 8))) void k3_adj_str(PARAMS3, int n, int kseg, int first) {
+// The compiler's own allocation (102 VGPRs, 4 waves per SIMD): 1.64 ms per 300 x 400 x 400
+// launch against 1.88 ms capped at 8 waves (64 VGPRs, spills) and 2.00 ms at 7.
+__global__ __launch_bounds__(TX * TY) void k3_adj_str(PARAMS3, int n, int kseg, int first) {
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
     const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
