@@ -218,10 +218,11 @@ efwi_status efwi_batch_gradient_grouped(const efwi_grid* grid, int ns, const efw
  *   nwaves     HOST int output: number of waves;
  *   wave_first HOST int [ns] output (may be NULL): start of each wave in `order`;
  *   order      HOST int [ns] output (may be NULL): the shots in the order the waves take them,
- *              wave w being order[wave_first[w]] .. order[wave_first[w+1] - 1], ascending.
+ *              wave w being order[wave_first[w]] .. order[wave_first[w+1] - 1], ascending;
+ *   lanes      HOST int output (may be NULL): 1 or 2, the lanes that advance the waves.
  * EFWI_E_WORKSPACE if one shot alone does not fit. */
 efwi_status efwi_batch_waves(const efwi_grid* grid, int ns, const efwi_shot* shots, size_t ws_bytes,
-                             int* nwaves, int* wave_first, int* order);
+                             int* nwaves, int* wave_first, int* order, int* lanes);
 
 /* Per-step state bound of a 2D wave (efwi_batch_waves, efwi_batch_gradient, and the calls
  * that advance shots in waves): a wave takes shots while their per-step state stays within
@@ -239,7 +240,8 @@ size_t efwi_get_wave_cache_bytes(void);
  * turn, so one wave's launches fill the end of the other's. Each lane's waves keep half of
  * the per-step state bound (efwi_set_wave_cache_bytes). A batch uses two lanes when one lane
  * would take several waves, every shot fits half the workspace and the halves' plan has at
- * most about twice as many waves, else one; shots whose
+ * most about twice as many waves, none of them with more per-step state than the whole
+ * bound, else one; shots whose
  * gradients add into a shared component (efwi_batch_gradient_grouped) always use one. The
  * caller's stream waits for the second one before the call returns its work; results are
  * bitwise those of one lane. lanes: 1 or 2, 0 restores the default (2). Process-wide,

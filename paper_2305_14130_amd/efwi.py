@@ -153,7 +153,7 @@ _lib.efwi_final_model.restype = ctypes.c_int
 _lib.efwi_batch_waves.restype = ctypes.c_int
 _lib.efwi_batch_waves.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.POINTER(_ShotC), ctypes.c_size_t,
                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                  ctypes.POINTER(ctypes.c_int)]
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
 _lib.efwi_plan_interval.restype = ctypes.c_int
 _lib.efwi_plan_interval.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(_ShotC), ctypes.c_size_t]
 _lib.efwi_validate.restype = ctypes.c_int
@@ -569,18 +569,19 @@ def batch_gradient_grouped(grid: Grid, shots, groups, m_ext, src, d_obs, g_ext=N
     return g_ext, phi
 
 
-def batch_waves(grid: Grid, shots, ws_bytes: int):
+def batch_waves(grid: Grid, shots, ws_bytes: int, with_lanes: bool = False):
     """The waves that batch_gradient advances for a workspace of ws_bytes, in order, each as
-    the list of its shots' indices (see efwi_batch_waves)."""
+    the list of its shots' indices (see efwi_batch_waves); with_lanes: (waves, lanes)."""
     shots = list(shots)
     arr = (_ShotC * len(shots))(*[s.c_struct() for s in shots])
-    n = ctypes.c_int()
+    n, lanes = ctypes.c_int(), ctypes.c_int()
     first = (ctypes.c_int * max(1, len(shots)))()
     order = (ctypes.c_int * max(1, len(shots)))()
     _check(_lib.efwi_batch_waves(ctypes.byref(grid), len(shots), arr, ctypes.c_size_t(ws_bytes), ctypes.byref(n),
-                                 first, order))
+                                 first, order, ctypes.byref(lanes)))
     starts = list(first[:n.value]) + [len(shots)]
-    return [list(order[starts[w]:starts[w + 1]]) for w in range(n.value)]
+    waves = [list(order[starts[w]:starts[w + 1]]) for w in range(n.value)]
+    return (waves, lanes.value) if with_lanes else waves
 
 
 def extension_regularizer(grid: Grid, m_ext, b, sink, eta, g_ext, phi=None, ws=None, stream=None):

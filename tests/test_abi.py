@@ -184,8 +184,26 @@ def test_batch_waves_pack_largest_first(efwi):
         assert efwi.get_wave_lanes() == 2
         assert efwi.batch_waves(grid, sh, 2 * ws) == [[0, 1, 2, 3]]     # one wave holds all: one lane
         assert efwi.batch_waves(grid, sh[:1], 2 * ws) == [[0]]
-        efwi.set_wave_cache_bytes(1)                                       # one shot per wave, two lanes
-        assert efwi.batch_waves(grid, sh, 2 * ws) == [[0], [1], [3], [2]]
+        assert efwi.batch_waves(grid, sh, 2 * ws, with_lanes=True)[1] == 1
+        efwi.set_wave_cache_bytes(1)                # one shot per wave: the whole bound is exceeded, one lane
+        assert efwi.batch_waves(grid, sh, 2 * ws, with_lanes=True) == ([[0], [1], [3], [2]], 1)
+        # six equal shots with a bound of two shots' per-step state: one lane would take waves
+        # of two, each lane takes waves of one (half the bound), so two lanes advance them
+        small = efwi.make_grid(100, 200, 5.0, 5.0, 0.5e-3, 50, 20, 1e-3, 30.0, 4500.0)
+        six = [efwi.Shot(50, 40 + 10 * k, np.full(3, 50, np.int32), np.array([60, 63, 66], np.int32))
+               for k in range(6)]
+        big_ws = efwi.workspace_size(efwi.WS_BATCH, small, six)
+        efwi.set_wave_lanes(1)
+        lo, hi = 1, 1 << 34                         # the least bound that pairs two shots in a wave
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            efwi.set_wave_cache_bytes(mid)
+            lo, hi = (lo, mid) if len(efwi.batch_waves(small, six, big_ws)[0]) >= 2 else (mid, hi)
+        efwi.set_wave_cache_bytes(hi)
+        assert efwi.batch_waves(small, six, big_ws, with_lanes=True) == ([[0, 1], [2, 3], [4, 5]], 1)
+        efwi.set_wave_lanes(2)
+        assert efwi.batch_waves(small, six, big_ws, with_lanes=True) == ([[k] for k in range(6)], 2)
+        efwi.set_wave_cache_bytes(0)
         for bad in (-1, 3):
             with pytest.raises(efwi.EfwiError) as ei:
                 efwi.set_wave_lanes(bad)

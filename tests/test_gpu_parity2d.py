@@ -280,8 +280,13 @@ def test_batch_uneven_windows_and_waves(gpu_lib):
         g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, torch.cat(d_obs), ws=efwi.workspace(full))
         assert torch.equal(g1, g2) and torch.equal(p1, p2)
         efwi.set_wave_lanes(2)
-        for nbytes, cache in ((full, 1), (2 * one + (1 << 20), 0), (3 * full, 0)):
-            efwi.set_wave_cache_bytes(cache)    # 1: one shot per wave, so both lanes take waves
+        # a per-step bound under which the plan takes two lanes (some bound between one shot's
+        # state and all of them does)
+        two = [c for c in (1 << e for e in range(16, 32)) if (efwi.set_wave_cache_bytes(c) or True) and
+               efwi.batch_waves(grid, shots, full, with_lanes=True)[1] == 2]
+        assert two
+        for nbytes, cache in ((full, two[0]), (full, two[-1]), (2 * one + (1 << 20), 0), (3 * full, 0)):
+            efwi.set_wave_cache_bytes(cache)
             waves = efwi.batch_waves(grid, shots, nbytes)
             assert sorted(sum(waves, [])) == list(range(len(wins)))
             g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, torch.cat(d_obs), ws=efwi.workspace(nbytes))
