@@ -1451,7 +1451,7 @@ efwi_status setup_wave3(const efwi_grid& g, const efwi_shot* shots, const std::v
     for (int q = 0; q < p.ntiles; ++q) {
       tshot[t++] = k;
       int i, k0, j0;
-      tile3_coords(q, p.nz, p.nx, i, k0, j0);
+      tile3_coords(q, p.nz, p.ny, p.nx, i, k0, j0);
       const int pad = 2;
       const bool pml = p.P > 0 && ((j0 - pad < p.P) || (j0 + TILE3_X - 1 + pad >= p.nx - p.P) || (k0 - pad < p.P) ||
                                    (k0 + TILE3_Y - 1 + pad >= p.ny - p.P) || (i - pad < p.P) ||

@@ -125,7 +125,7 @@ __device__ __forceinline__ bool tile3(const int* __restrict__ sched, const int* 
   const int t = sched[blockIdx.x];
   if (t < 0) return false;
   sh = tile_shot[t];
-  tile3_coords(t - tile_first[sh], shots[sh].nz, shots[sh].nx, i, k0, j0);
+  tile3_coords(t - tile_first[sh], shots[sh].nz, shots[sh].ny, shots[sh].nx, i, k0, j0);
   return true;
 }
 
