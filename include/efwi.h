@@ -183,8 +183,11 @@ efwi_status efwi_shot_gradient_noalloc(const efwi_grid* grid, const efwi_shot* s
 size_t efwi_noalloc_scratch_bytes(void);
 
 /* batch_gradient: the data term of eq.(8) for ns shots at once, each shot s on its own
- * component m_s of the extended model and its own window, advanced together (one launch
- * per half step covers every shot's tiles).
+ * component m_s of the extended model and its own window, advanced in waves (one launch per
+ * half step covers every tile of a wave's shots; the waves and lanes efwi_batch_waves
+ * reports). Each shot's results are bitwise those of efwi_shot_gradient, whatever the waves.
+ * With two lanes the call also enqueues work on the library's second stream of the current
+ * device; the caller's stream waits for it before the call's work is complete there.
  *   m_ext DEVICE [ns][3][nz][nx]; src DEVICE [ns][3][nt];
  *   d_obs DEVICE concatenation of the shots' [nch_s][nt] blocks in shot order;
  *   g_ext DEVICE [ns][3][nz][nx] output, overwritten (slot s holds g_s);
