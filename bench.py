@@ -226,48 +226,62 @@ def plain_1000x3000_form(efwi, inputs, torch, dev, nt, nshots=20):
 
 def autograd_form(efwi, inputs, torch, dev, nt, subset=4, nshots=32):
     """The differentiation workload (1200 x 4000 at 2 m, nt = 8000, 32 shots along the well):
-    each shot's misfit through autograd.ShotMisfit with sqrt(nt) = 90-step checkpoints
-    (recomputation in the reverse sweep), backward to the model; `subset` of the 32 shots
-    timed once after one untimed shot, the 32-shot time extrapolated linearly (shots cost
-    the same: same grid and channels)."""
+    each shot's misfit through autograd.ShotMisfit, backward to the model, with sqrt(nt) = 90-step
+    checkpoints (recomputation in the reverse sweep) and, for comparison with storing the
+    forward history, with the largest checkpoint interval whose workspace fits 85% of the free
+    HBM (a shot's whole history, 5 x 4.8e6 x 8000 x 4 B = 768 GB, does not fit); `subset` of the
+    32 shots timed once per form after one untimed shot, the 32-shot time extrapolated linearly
+    (shots cost the same: same grid and channels). Both forms give the same gradient bit for
+    bit (the imaging sums are blocked on absolute step numbers)."""
     from paper_2305_14130_amd import autograd as AG
     w = inputs.differentiation_2d(nt=nt, nshots=nshots)
     nz, nx = w.nz, w.nx
     grid = efwi.make_grid(nz, nx, w.dz, w.dx, w.dt, nt, w.npml, w.pml_R, w.f0, w.vp_max)
     T = lambda a: torch.tensor(np.asarray(a, np.float32), device=dev)
     picks = [int(round(k * (nshots - 1) / max(1, subset - 1))) for k in range(subset)]
-    shots = [efwi.Shot(w.shots[k].src_iz, w.shots[k].src_ix, w.shots[k].ch_iz, w.shots[k].ch_ix, ckpt_interval=0)
-             for k in picks]
+    base = [efwi.Shot(w.shots[k].src_iz, w.shots[k].src_ix, w.shots[k].ch_iz, w.shots[k].ch_ix, ckpt_interval=0)
+            for k in picks]
     srcs = [T(np.outer(w.shots[k].M, w.stf)) for k in picks]
     m_true = T(w.m_true)
-    obs = [efwi.model_forward(grid, shots[q], m_true, srcs[q]) for q in range(subset)]
+    obs = [efwi.model_forward(grid, base[q], m_true, srcs[q]) for q in range(subset)]
     del m_true
     m = T(w.m_start).requires_grad_(True)
-
-    def one(q):
-        phi = AG.ShotMisfit.apply(m, srcs[q], obs[q], grid, shots[q])
-        phi.backward()
-        return phi
-
-    one(0)
     torch.cuda.synchronize()
-    m.grad = None
-    t0 = time.perf_counter()
-    for q in range(subset):
-        one(q)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert bool(torch.isfinite(m.grad).all())
-    rf = efwi.recompute_fraction(grid, 0)
-    cells = nz * nx
-    gcell = subset * cells * nt / dt / 1e9
-    alg = path_bytes_2d(cells, strip_cells_2d(nz, nx, w.npml), rf) / cells
-    out = {"grid": [nz, nx], "nt": nt, "shots_timed": subset, "shots_total": nshots, "shot_indices": picks,
-           "ckpt_interval": int(np.ceil(np.sqrt(nt))), "recompute_fraction": round(rf, 4),
-           "ms": round(dt * 1e3, 1), "gcell_per_s": round(gcell, 3),
-           "extrapolated_32_shots_s": round(dt * nshots / subset, 2),
-           "bytes_per_cell_step": round(alg, 1), "path_frac": round(alg * gcell / HBM_PEAK_GBS, 4)}
-    del m, obs, srcs
+    # the workspace for the largest interval is planned on the shot with the most channels
+    big = min(efwi.plan_interval(grid, s, int(0.85 * torch.cuda.mem_get_info(dev)[0])) for s in base)
+    out = {"grid": [nz, nx], "nt": nt, "shots_timed": subset, "shots_total": nshots, "shot_indices": picks}
+    grads = {}
+    for name, interval in (("sqrt_nt", 0), ("largest_interval", big)):
+        shots = [dataclasses.replace(s, ckpt_interval=interval, _keep=[]) for s in base]
+        ws = efwi.workspace(max(efwi.workspace_size(efwi.WS_GRADIENT, grid, [s]) for s in shots), dev)
+
+        def one(q):
+            phi = AG.ShotMisfit.apply(m, srcs[q], obs[q], grid, shots[q], ws)
+            phi.backward()
+
+        one(0)
+        torch.cuda.synchronize()
+        m.grad = None
+        t0 = time.perf_counter()
+        for q in range(subset):
+            one(q)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert bool(torch.isfinite(m.grad).all())
+        grads[name] = m.grad.clone()
+        m.grad = None
+        rf = efwi.recompute_fraction(grid, interval)
+        cells = nz * nx
+        gcell = subset * cells * nt / dt / 1e9
+        alg = path_bytes_2d(cells, strip_cells_2d(nz, nx, w.npml), rf) / cells
+        out[name] = {"ckpt_interval": int(np.ceil(np.sqrt(nt))) if interval == 0 else interval,
+                     "recompute_fraction": round(rf, 4), "ms": round(dt * 1e3, 1), "gcell_per_s": round(gcell, 3),
+                     "extrapolated_32_shots_s": round(dt * nshots / subset, 2),
+                     "bytes_per_cell_step": round(alg, 1), "path_frac": round(alg * gcell / HBM_PEAK_GBS, 4)}
+        del ws
+        torch.cuda.empty_cache()
+    out["identical_gradients"] = bool(torch.equal(grads["sqrt_nt"], grads["largest_interval"]))
+    del m, obs, srcs, grads
     torch.cuda.empty_cache()
     return out
 

@@ -53,18 +53,19 @@ class ShotData(torch.autograd.Function):
 
 
 class ShotMisfit(torch.autograd.Function):
-    """phi_s(m) = 1/2 ||d_s(m) - d_obs||^2 (FP64 scalar)."""
+    """phi_s(m) = 1/2 ||d_s(m) - d_obs||^2 (FP64 scalar); ``ws`` an optional workspace (one
+    is allocated per call otherwise)."""
 
     @staticmethod
-    def forward(ctx, m, src, d_obs, grid, shot):
-        g, phi = efwi.shot_gradient(grid, shot, m.contiguous(), src, d_obs)
+    def forward(ctx, m, src, d_obs, grid, shot, ws=None):
+        g, phi = efwi.shot_gradient(grid, shot, m.contiguous(), src, d_obs, ws=ws)
         ctx.save_for_backward(g)
         return phi
 
     @staticmethod
     def backward(ctx, gphi):
         (g,) = ctx.saved_tensors
-        return gphi.to(g.dtype) * g, None, None, None, None
+        return gphi.to(g.dtype) * g, None, None, None, None, None
 
 
 class BatchMisfit(torch.autograd.Function):
