@@ -502,6 +502,7 @@ def main():  # noqa: C901
     ap.add_argument("--wave-cache-mib", type=int, default=0,
                     help="per-step state bound of a wave in MiB (0: the library's default, -1: the workspace alone)")
     ap.add_argument("--lanes", type=int, default=0, help="lanes of the batched calls (0: the library's default)")
+    ap.add_argument("--nt3d", type=int, default=3000, help="time steps of the 3D shot (profiling runs use fewer)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="time the headline only (profiling runs)")
     for f in ("sequential", "sqrt", "compressed", "plain", "autograd", "vti", "3d", "extension-ops", "autotune"):
@@ -677,7 +678,7 @@ def main():  # noqa: C901
         forms["vti_1shot"] = vti_shot_form(efwi, inputs, torch, dev, nt)
         log(f"VTI form done: {forms['vti_1shot']}")
     if run_forms and not args.no_3d:
-        forms["precision_3d_shot"] = precision_3d_shot(efwi, inputs, torch, dev)
+        forms["precision_3d_shot"] = precision_3d_shot(efwi, inputs, torch, dev, nt=args.nt3d)
         log(f"3D shot done: {forms['precision_3d_shot']}")
     ext_ops = None
     if run_forms and not args.no_extension_ops:
