@@ -129,10 +129,26 @@ def test_batch_with_field_sampling_equals_per_shot(gpu_lib, c2):
     m_ext = T(np.stack([c2.m * (1 + 0.01 * rng.standard_normal(c2.m.shape)) for _ in shots]))
     src = T(np.stack([c2.src * (k + 1) for k in range(len(shots))]))
     d_obs = [efwi.model_forward(grid, s, T(c2.m), src[k]) * 0.5 for k, s in enumerate(shots)]
-    g_ext, phi = efwi.batch_gradient(grid, shots, m_ext, src, torch.cat([d.reshape(-1) for d in d_obs]))
+    d_cat = torch.cat([d.reshape(-1) for d in d_obs])
+    g_ext, phi = efwi.batch_gradient(grid, shots, m_ext, src, d_cat)
     for k, s in enumerate(shots):
         g1, p1 = efwi.shot_gradient(grid, s, m_ext[k], src[k], d_obs[k])
         assert torch.equal(g_ext[k], g1) and phi[k].item() == p1.item()
+    # the same batch in several waves, packed largest first (shot 2 ahead of the others), on
+    # one lane and on two: the shots' data differ in length, so each shot's data, residual and
+    # misfit slots must follow it through the reordering
+    full = efwi.workspace_size(efwi.WS_BATCH, grid, shots)
+    try:
+        two = [c for c in (1 << e for e in range(12, 32)) if (efwi.set_wave_cache_bytes(c) or True) and
+               efwi.batch_waves(grid, shots, full, with_lanes=True)[1] == 2]
+        assert two
+        for cache in sorted({1 << 16, two[0], two[-1]}):
+            efwi.set_wave_cache_bytes(cache)
+            assert len(efwi.batch_waves(grid, shots, full)) > 1
+            g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, d_cat, ws=efwi.workspace(full))
+            assert torch.equal(g_ext, g2) and torch.equal(phi, p2), cache
+    finally:
+        efwi.set_wave_cache_bytes(0)
 
 
 def test_field_gradient_3d(gpu_lib):

@@ -136,6 +136,18 @@ def test_vti_batch_and_pseudo_hessian(gpu_lib, case):
         g1, p1 = efwi.shot_gradient(grid, shots[k], m_ext[k], src[k], d_obs[k * case.d_obs.size:(k + 1) * case.d_obs.size]
                                     .reshape(case.d_obs.shape))
         assert torch.equal(g_ext[k], g1) and phi[k].item() == p1.item()
+    # the same batch as two waves on two lanes (each lane's half of the workspace holds one
+    # shot, and a per-step bound holds one shot's state but not both)
+    nbytes = 2 * efwi.workspace_size(efwi.WS_GRADIENT, grid, shots[:1]) + (1 << 20)
+    try:
+        two = [c for c in (1 << e for e in range(12, 32)) if (efwi.set_wave_cache_bytes(c) or True) and
+               efwi.batch_waves(grid, shots, nbytes, with_lanes=True)[1] == 2]
+        assert two
+        efwi.set_wave_cache_bytes(two[0])
+        g2, p2 = efwi.batch_gradient(grid, shots, m_ext, src, d_obs, ws=efwi.workspace(nbytes))
+        assert torch.equal(g_ext, g2) and torch.equal(phi, p2)
+    finally:
+        efwi.set_wave_cache_bytes(0)
     # velocity autocorrelation of the VTI forward step against the VTI oracle (nt = 200)
     c2 = Case(nt=200)
     h, _ = efwi.pseudo_hessian(c2.grid(efwi), [c2.shot(efwi)], T(c2.m)[None].contiguous(), T(c2.src)[None].contiguous(),
