@@ -279,9 +279,11 @@ hipError_t launch_inverse_diag(const float* h, long n, float clip, float* p, flo
 // 3D. Arrays are [nz][ny][nx]; padded arrays have the same zero halo in z and y as in 2D
 // and the XOFF / ROW_ALIGN layout in x; element (i, k, j) is at p[i * pz + k * ld + j].
 // ---------------------------------------------------------------------------------------
-constexpr int NSEG3 = 9;   // stored per step: tr/(3l+2m), dev_xx/m, dev_yy/m (normal node),
-                           // three shear strain rates / shear moduli, qx/bx, qy/by, qz/bz
-constexpr int NACC3 = 8;   // imaging sums: lambda, deviatoric mu, mu_xy, mu_xz, mu_yz, bx, by, bz
+constexpr int NSEG3 = 9;   // stored per step: tr/(3l+2m), dev_xx m, dev_yy m (normal node),
+                           // the three shear strain rates x their modulus / 4 (shear nodes),
+                           // qx bx / 2, qy by / 2, qz bz / 2 (velocity nodes)
+constexpr int NACC3 = 3;   // imaging sums gathered at the normal node: lambda, mu^2 x (mu part
+                           // beyond 2/3 lambda's), rho
 
 struct Shot3D {
   int nz, ny, nx, ld, P;

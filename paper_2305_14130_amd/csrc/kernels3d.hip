@@ -11,12 +11,18 @@
 // Tiles are 64 (x) by 16 (y) cells of one z plane, four rows per thread. The adjoint
 // carries u_bar = b v_bar and t_bar = C sigma_bar (C: lambda 1 1^T + 2 mu I on the normal
 // block, the shear moduli on the shear components), so its transposed differences read one
-// array per neighbour, and the imaging condition uses forward quantities stored
-// pre-divided by the moduli:
-//   g_lambda       += dt tr(t) tr(p) / (3l + 2m)          = dt tr(sigma_bar) tr(p)
-//   g_mu (normal)   = 2/3 g_lambda + dt dev(t) : dev(p) / m = 2 dt sum_c sigma_bar_cc p_cc
-//   g_mu_xy        += dt t_xy (D+y vx + D+x vy) / mu_xy    (and xz, yz)
-//   g_b_x          += dt u_x q_x / b_x                     (and y, z)
+// array per neighbour. The imaging condition gathers three sums at each normal node from
+// forward quantities stored with the factors of the chain rule already applied, so that
+// the transposed kernels read and write three sums per cell and step instead of one per
+// modulus and buoyancy:
+//   A += dt tr(t) tr(p) / (3l + 2m)                           g_lambda = A
+//   E += dt dev(t) : (m dev(p)) + dt sum_s c_s t_xy(s) (mu_xy(s) / 4) (D+y vx + D+x vy)(s)
+//        (and xz, yz)                                          g_mu = 2/3 A + E / m^2
+//   R += dt sum_v c_v u_x(v) (b_x(v) / 2) q_x(v)  (and y, z)   g_rho = -R
+// over the four shear nodes s of each type and the two velocity nodes v of each component
+// whose harmonic modulus or buoyancy uses the node's mu or rho, c counting how often (twice
+// at the last plane, row or column, where the neighbour is clamped): d mu_xy / d mu =
+// mu_xy^2 / (4 mu^2) per corner and d b / d rho = -b^2 / 2.
 #include "efwi_internal.h"
 
 // Contract a * b + c into one fused multiply-add only inside a single expression, never
@@ -236,9 +242,9 @@ __device__ __forceinline__ void fwd_vel3(const Shot3D& s, int i, int k, int j, g
   if (PZ && inz) G(s.psz[ZS_VX], qzs) = p[6], G(s.psz[ZS_VY], qzs) = p[7], G(s.psz[ZS_VZ], qzs) = p[8];
   if (STORE) {
     const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
-    hist_put(seg, 6 * cells + c, qx / bx);
-    hist_put(seg, 7 * cells + c, qy / by);
-    hist_put(seg, 8 * cells + c, qz / bz);
+    hist_put(seg, 6 * cells + c, 0.5f * qx * bx);
+    hist_put(seg, 7 * cells + c, 0.5f * qy * by);
+    hist_put(seg, 8 * cells + c, 0.5f * qz * bz);
   }
 }
 
@@ -335,11 +341,11 @@ __device__ __forceinline__ void fwd_str3(const Shot3D& s, int i, int k, int j, i
     const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
     const float mu = 0.5f * two_mu, third = tr * (1.0f / 3.0f);
     hist_put(seg, c, tr / (l2m + 2.0f * lam));
-    hist_put(seg, cells + c, (pxx - third) / mu);
-    hist_put(seg, 2 * cells + c, (pyy - third) / mu);
-    hist_put(seg, 3 * cells + c, mxy > 0.0f ? sxy_r / mxy : 0.0f);
-    hist_put(seg, 4 * cells + c, mxz > 0.0f ? sxz_r / mxz : 0.0f);
-    hist_put(seg, 5 * cells + c, myz > 0.0f ? syz_r / myz : 0.0f);
+    hist_put(seg, cells + c, (pxx - third) * mu);
+    hist_put(seg, 2 * cells + c, (pyy - third) * mu);
+    hist_put(seg, 3 * cells + c, 0.25f * mxy * sxy_r);
+    hist_put(seg, 4 * cells + c, 0.25f * mxz * sxz_r);
+    hist_put(seg, 5 * cells + c, 0.25f * myz * syz_r);
   }
 }
 
@@ -418,18 +424,25 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
   auto Pxz_vz = [&](int a, int b, int c) { return A.cx(A.at(s.txzb, a, b, c), a, b, c, XS_SXZ, 2); };
   auto Pyz_vy = [&](int a, int b, int c) { return A.cz(A.at(s.tyzb, a, b, c), a, b, c, ZS_SYZ, 2); };
   auto Pyz_vz = [&](int a, int b, int c) { return A.cy(A.at(s.tyzb, a, b, c), a, b, c, YS_SYZ, 2); };
+  // t_bar one back along either axis of each shear type: operands of the differences and,
+  // with the imaging, terms of its gather below (loaded once for both; without the imaging
+  // the differences load them as the other operands, which keeps that instance's registers
+  // below the cap)
+  const float txy_km = GRAD ? G(PF(s.txyb), o - ld) : 0.0f, txy_jm = GRAD ? G(PF(s.txyb), o - 1u) : 0.0f;
+  const float txz_im = GRAD ? G(PF(s.txzb), o - pz) : 0.0f, txz_jm = GRAD ? G(PF(s.txzb), o - 1u) : 0.0f;
+  const float tyz_im = GRAD ? G(PF(s.tyzb), o - pz) : 0.0f, tyz_km = GRAD ? G(PF(s.tyzb), o - ld) : 0.0f;
   // v_bar_x += -(D+x Pxx + D-y Pxy_vx + D-z Pxz_vx)
   const float x1 = K1 * (Pxx(i, k, j + 1) - Pxx(i, k, j)) + K2 * (Pxx(i, k, j + 2) - Pxx(i, k, j - 1));
-  const float x2 = K1 * (Pxy_vx(i, k, j) - Pxy_vx(i, k - 1, j)) + K2 * (Pxy_vx(i, k + 1, j) - Pxy_vx(i, k - 2, j));
-  const float x3 = K1 * (Pxz_vx(i, k, j) - Pxz_vx(i - 1, k, j)) + K2 * (Pxz_vx(i + 1, k, j) - Pxz_vx(i - 2, k, j));
+  const float x2 = K1 * (Pxy_vx(i, k, j) - (GRAD ? A.cy(s.dt * txy_km, i, k - 1, j, YS_SXY, 2) : Pxy_vx(i, k - 1, j))) + K2 * (Pxy_vx(i, k + 1, j) - Pxy_vx(i, k - 2, j));
+  const float x3 = K1 * (Pxz_vx(i, k, j) - (GRAD ? A.cz(s.dt * txz_im, i - 1, k, j, ZS_SXZ, 2) : Pxz_vx(i - 1, k, j))) + K2 * (Pxz_vx(i + 1, k, j) - Pxz_vx(i - 2, k, j));
   // v_bar_y += -(D+y Pyy + D-x Pxy_vy + D-z Pyz_vy)
   const float y1 = K1 * (Pyy(i, k + 1, j) - Pyy(i, k, j)) + K2 * (Pyy(i, k + 2, j) - Pyy(i, k - 1, j));
-  const float y2 = K1 * (Pxy_vy(i, k, j) - Pxy_vy(i, k, j - 1)) + K2 * (Pxy_vy(i, k, j + 1) - Pxy_vy(i, k, j - 2));
-  const float y3 = K1 * (Pyz_vy(i, k, j) - Pyz_vy(i - 1, k, j)) + K2 * (Pyz_vy(i + 1, k, j) - Pyz_vy(i - 2, k, j));
+  const float y2 = K1 * (Pxy_vy(i, k, j) - (GRAD ? A.cx(s.dt * txy_jm, i, k, j - 1, XS_SXY, 2) : Pxy_vy(i, k, j - 1))) + K2 * (Pxy_vy(i, k, j + 1) - Pxy_vy(i, k, j - 2));
+  const float y3 = K1 * (Pyz_vy(i, k, j) - (GRAD ? A.cz(s.dt * tyz_im, i - 1, k, j, ZS_SYZ, 2) : Pyz_vy(i - 1, k, j))) + K2 * (Pyz_vy(i + 1, k, j) - Pyz_vy(i - 2, k, j));
   // v_bar_z += -(D+z Pzz + D-x Pxz_vz + D-y Pyz_vz)
   const float z1 = K1 * (Pzz(i + 1, k, j) - Pzz(i, k, j)) + K2 * (Pzz(i + 2, k, j) - Pzz(i - 1, k, j));
-  const float z2 = K1 * (Pxz_vz(i, k, j) - Pxz_vz(i, k, j - 1)) + K2 * (Pxz_vz(i, k, j + 1) - Pxz_vz(i, k, j - 2));
-  const float z3 = K1 * (Pyz_vz(i, k, j) - Pyz_vz(i, k - 1, j)) + K2 * (Pyz_vz(i, k + 1, j) - Pyz_vz(i, k - 2, j));
+  const float z2 = K1 * (Pxz_vz(i, k, j) - (GRAD ? A.cx(s.dt * txz_jm, i, k, j - 1, XS_SXZ, 2) : Pxz_vz(i, k, j - 1))) + K2 * (Pxz_vz(i, k, j + 1) - Pxz_vz(i, k, j - 2));
+  const float z3 = K1 * (Pyz_vz(i, k, j) - (GRAD ? A.cy(s.dt * tyz_km, i, k - 1, j, YS_SYZ, 2) : Pyz_vz(i, k - 1, j))) + K2 * (Pyz_vz(i, k + 1, j) - Pyz_vz(i, k - 2, j));
   float gx = -(x1 * s.rdx + x2 * s.rdy + x3 * s.rdz);
   const float gy = -(y1 * s.rdy + y2 * s.rdx + y3 * s.rdz);
   const float gz = -(z1 * s.rdz + z2 * s.rdx + z3 * s.rdy);
@@ -441,6 +454,31 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
   }
   const float txx = G(PF(s.txxb), o), tyy = G(PF(s.tyyb), o), tzz = G(PF(s.tzzb), o);
   const float txy = G(PF(s.txyb), o), txz = G(PF(s.txzb), o), tyz = G(PF(s.tyzb), o);
+  // Imaging terms of this normal node, formed before the stores below so that the t_bar
+  // neighbours the differences above loaded are not loaded again. The four shear nodes of
+  // a type (this node's and those one back along either or both of the type's axes a, b)
+  // are weighted by how often their clamped corners use this node: twice at the last
+  // plane, row or column (wa, wb), else once. Before the first one t_bar is the zero halo
+  // and the stored quantity is read at this node instead, so the term is zero. The stored
+  // shear quantities are read through the caches: four normal nodes gather each.
+  float img_a = 0.0f, img_e = 0.0f;
+  if (GRAD) {
+    const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
+    const float h0 = hist_get(seg, c), D1 = hist_get(seg, cells + c), D2 = hist_get(seg, 2 * cells + c);
+    const float trt = txx + tyy + tzz;
+    const float da = txx - trt * (1.0f / 3.0f), db = tyy - trt * (1.0f / 3.0f);
+    const unsigned hx = j > 0 ? 1u : 0u, hy = k > 0 ? (unsigned)s.cp : 0u, hz = i > 0 ? (unsigned)(s.ny * s.cp) : 0u;
+    const float wx = j == s.nx - 1 ? 2.0f : 1.0f, wy = k == s.ny - 1 ? 2.0f : 1.0f, wz = i == s.nz - 1 ? 2.0f : 1.0f;
+    const gfloat *hxy = seg + 3 * cells, *hxz = seg + 4 * cells, *hyz = seg + 5 * cells;
+    const float sxy = wy * (wx * (txy * G(hxy, c)) + txy_jm * G(hxy, c - hx)) +
+                      (wx * (txy_km * G(hxy, c - hy)) + G(PF(s.txyb), o - ld - 1u) * G(hxy, c - hy - hx));
+    const float sxz = wz * (wx * (txz * G(hxz, c)) + txz_jm * G(hxz, c - hx)) +
+                      (wx * (txz_im * G(hxz, c - hz)) + G(PF(s.txzb), o - pz - 1u) * G(hxz, c - hz - hx));
+    const float syz = wz * (wy * (tyz * G(hyz, c)) + tyz_km * G(hyz, c - hy)) +
+                      (wy * (tyz_im * G(hyz, c - hz)) + G(PF(s.tyzb), o - pz - ld) * G(hyz, c - hz - hy));
+    img_a = trt * h0;
+    img_e = (da * D1 + db * D2 + (da + db) * (D1 + D2)) + (sxy + sxz + syz);
+  }
   const float ux = G(PF(s.uxb), o), uy = G(PF(s.uyb), o), uz = G(PF(s.uzb), o);
   float bx, by, bz;
   buoyancies(s, o, bx, by, bz);
@@ -482,18 +520,9 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
   }
   if (GRAD) {
     const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
-    float h[6], a[5] = {0, 0, 0, 0, 0};
-    for (int f = 0; f < 6; ++f) h[f] = hist_get(seg, f * cells + c);
-    if (!first)
-      for (int f = 0; f < 5; ++f) a[f] = G(s.acc, f * cells + c);
-    const float trt = txx + tyy + tzz;
-    const float da = txx - trt * (1.0f / 3.0f), db = tyy - trt * (1.0f / 3.0f);
-    const float D1 = h[1], D2 = h[2];
-    G(s.acc, c) = a[0] + s.dt * trt * h[0];
-    G(s.acc, cells + c) = a[1] + s.dt * (da * D1 + db * D2 + (da + db) * (D1 + D2));
-    G(s.acc, 2 * cells + c) = a[2] + s.dt * txy * h[3];
-    G(s.acc, 3 * cells + c) = a[3] + s.dt * txz * h[4];
-    G(s.acc, 4 * cells + c) = a[4] + s.dt * tyz * h[5];
+    const float a0 = first ? 0.0f : G(s.acc, c), a1 = first ? 0.0f : G(s.acc, cells + c);
+    G(s.acc, c) = a0 + s.dt * img_a;
+    G(s.acc, cells + c) = a1 + s.dt * img_e;
   }
   if (SRCADJ && i == s.si && k == s.sk && j == s.sj) {
     // sigma_bar at the source: invert C on the normal block and the shear moduli
@@ -520,9 +549,10 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
 }
 
 template <bool GRAD, bool SRCADJ>
-// At least 4 waves per SIMD (at most 128 VGPRs; the compiler takes 121 without spilling):
-// 1.59 ms per 300 x 400 x 400 launch against 1.73 ms with its own allocation (136 VGPRs, 3
-// waves) and 2.02 ms capped at 5 waves (spills).
+// At least 4 waves per SIMD (at most 128 VGPRs; the compiler takes 125 with the imaging
+// gather, without spilling): 1.54 ms per 300 x 400 x 400 launch. Before the gather, 1.59 ms
+// at this cap against 1.73 ms with the compiler's own allocation (136 VGPRs, 3 waves) and
+// 2.02 ms capped at 5 waves (spills).
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(4))) void k3_adj_vel(PARAMS3, int n, int kseg, int first) {
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
@@ -606,20 +636,27 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
     }
   }
   if (GRAD) {
+    // The two velocity nodes of each component whose buoyancy uses this node's density
+    // (this node's and the one back along the component's axis), weighted as the shear
+    // nodes of the transposed stress sub-step.
     const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
-    float h[3], a[3] = {0, 0, 0};
-    for (int f = 0; f < 3; ++f) h[f] = hist_get(seg, (6 + f) * cells + c);
-    if (!first)
-      for (int f = 0; f < 3; ++f) a[f] = G(s.acc, (5 + f) * cells + c);
-    G(s.acc, 5 * cells + c) = a[0] + s.dt * ux * h[0];
-    G(s.acc, 6 * cells + c) = a[1] + s.dt * uy * h[1];
-    G(s.acc, 7 * cells + c) = a[2] + s.dt * uz * h[2];
+    const unsigned hx = j > 0 ? 1u : 0u, hy = k > 0 ? (unsigned)s.cp : 0u, hz = i > 0 ? (unsigned)(s.ny * s.cp) : 0u;
+    const float wx = j == s.nx - 1 ? 2.0f : 1.0f, wy = k == s.ny - 1 ? 2.0f : 1.0f, wz = i == s.nz - 1 ? 2.0f : 1.0f;
+    auto pair = [&](const gfloat* u, float u0, unsigned f, unsigned oa, unsigned ha, float wa) {
+      const gfloat* h = seg + f * cells;
+      return wa * (u0 * G(h, c)) + G(PF(u), o - oa) * G(h, c - ha);
+    };
+    const float a0 = first ? 0.0f : G(s.acc, 2 * cells + c);
+    const float rx = pair(s.uxb, ux, 6u, 1u, hx, wx), ry = pair(s.uyb, uy, 7u, ld, hy, wy);
+    const float rz = pair(s.uzb, uz, 8u, pz, hz, wz);
+    G(s.acc, 2 * cells + c) = a0 + s.dt * (rx + ry + rz);
   }
 }
 
 template <bool GRAD>
-// The compiler's own allocation (102 VGPRs, 4 waves per SIMD): 1.64 ms per 300 x 400 x 400
-// launch against 1.88 ms capped at 8 waves (64 VGPRs, spills) and 2.00 ms at 7.
+// The compiler's own allocation (95 VGPRs with the imaging gather, 5 waves per SIMD): 1.46
+// ms per 300 x 400 x 400 launch. Before the gather (102 VGPRs, 4 waves), 1.64 ms against 1.88
+// ms capped at 8 waves (64 VGPRs, spills) and 2.00 ms at 7.
 __global__ __launch_bounds__(TX * TY) void k3_adj_str(PARAMS3, int n, int kseg, int first) {
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
@@ -680,54 +717,13 @@ __global__ __launch_bounds__(TX * TY) void k3_chain_flush(PARAMS3) {
     if (k >= s.ny || j >= s.nx) return;
     const long cs = s.cells;
     auto ci = [&](int a, int b, int c) { return ((long)a * s.ny + b) * s.cp + c; };
-    auto pi = [&](int a, int b, int c) { return (long)a * s.pz + (long)b * s.ld + c; };
     const long cc = ci(i, k, j);
     const long mo = (long)i * s.mplanestride + (long)k * s.mld + j;
     const float vp = s.mvp[mo], vs = s.mvs[mo], rho = s.mrho[mo];
     const double mu = (double)(rho * vs * vs);
     const double gl = s.acc[cc];
-    double gmu = 2.0 / 3.0 * gl + (double)s.acc[cs + cc];
-    const int NZ = s.nz - 1, NY = s.ny - 1, NX = s.nx - 1;
-    // shear node (a, b, c) of each type and its four clamped corners
-    for (int t = 0; t < 3; ++t) {
-      const gfloat* mod = t == 0 ? s.muxy : (t == 1 ? s.muxz : s.muyz);
-      const gfloat* g = s.acc + (2 + t) * cs;
-      for (int q = 0; q < 4; ++q) {
-        const int d1 = q & 1, d2 = q >> 1;
-        int a = i, b = k, c = j;
-        if (t == 0) { b -= d1; c -= d2; }       // xy: (i, k-1..k, j-1..j)
-        else if (t == 1) { a -= d1; c -= d2; }  // xz: (i-1..i, k, j-1..j)
-        else { a -= d1; b -= d2; }              // yz: (i-1..i, k-1..k, j)
-        if (a < 0 || b < 0 || c < 0) continue;
-        int mult = 0;
-        for (int e = 0; e < 4; ++e) {
-          const int e1 = e & 1, e2 = e >> 1;
-          int aa = a, bb = b, cc2 = c;
-          if (t == 0) { bb = min(b + e1, NY); cc2 = min(c + e2, NX); }
-          else if (t == 1) { aa = min(a + e1, NZ); cc2 = min(c + e2, NX); }
-          else { aa = min(a + e1, NZ); bb = min(b + e2, NY); }
-          mult += (aa == i && bb == k && cc2 == j);
-        }
-        if (mult == 0) continue;
-        const float m = mod[pi(a, b, c)];
-        if (m > 0.0f) gmu += (double)mult * g[ci(a, b, c)] * ((double)m * m / (4.0 * mu * mu));
-      }
-    }
-    double grho = 0.0;
-    for (int t = 0; t < 3; ++t) {
-      const gfloat* bb = t == 0 ? s.bx : (t == 1 ? s.by : s.bz);
-      const gfloat* g = s.acc + (5 + t) * cs;
-      for (int d = -1; d <= 0; ++d) {
-        int a = i, b = k, c = j;
-        int mult;
-        if (t == 0) { c += d; if (c < 0) continue; mult = (c == j) + (min(c + 1, NX) == j); }
-        else if (t == 1) { b += d; if (b < 0) continue; mult = (b == k) + (min(b + 1, NY) == k); }
-        else { a += d; if (a < 0) continue; mult = (a == i) + (min(a + 1, NZ) == i); }
-        if (mult == 0) continue;
-        const double bv = bb[pi(a, b, c)];
-        grho -= 0.5 * mult * g[ci(a, b, c)] * bv * bv;
-      }
-    }
+    const double gmu = 2.0 / 3.0 * gl + (mu > 0.0 ? (double)s.acc[cs + cc] / (mu * mu) : 0.0);
+    const double grho = -(double)s.acc[2 * cs + cc];
     const double dvp = vp, dvs = vs, drho = rho;
     s.G[cc] += 2.0 * drho * dvp * gl;
     s.G[cs + cc] += 2.0 * drho * dvs * (gmu - 2.0 * gl);
