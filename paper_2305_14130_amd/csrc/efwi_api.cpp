@@ -1266,7 +1266,7 @@ Plan3D plan3d(const efwi_grid& g, const efwi_shot& s, efwi_ws_kind kind) {
   p.state_elems = (size_t)9 * p.plane + p.strips;
   p.state_bytes = align_up(p.state_elems * sizeof(float));
   p.adj_bytes = align_up(((size_t)9 * p.plane + 2 * p.strips) * sizeof(float));
-  p.par_bytes = align_up((size_t)10 * p.plane * sizeof(float));
+  p.par_bytes = align_up((size_t)7 * p.plane * sizeof(float));
   p.tab_bytes = align_up((size_t)(4 * p.nx + 4 * p.ny + 4 * p.nz) * sizeof(float) +
                          (size_t)p.nz * p.ny * sizeof(int) + (size_t)p.nslots * p.nx * sizeof(int));
   p.ckpt_mode = s.ckpt_mode;
@@ -1368,10 +1368,9 @@ Shot3D make_desc3(const efwi_grid& g, const efwi_shot& s, const Plan3D& p, unsig
   d.txzb = f[7], d.tyzb = f[8];
   strips_at(st, d.pbx[0], d.pby[0], d.pbz[0]);
   strips_at(st + p.strips, d.pbx[1], d.pby[1], d.pbz[1]);
-  gfloat* pf[10];
-  fields(p.off_par, pf, 10);
-  d.l2m = pf[0], d.lam = pf[1], d.muxy = pf[2], d.muxz = pf[3], d.muyz = pf[4], d.bx = pf[5], d.by = pf[6],
-  d.bz = pf[7], d.rho = pf[8], d.mu = pf[9];
+  gfloat* pf[7];
+  fields(p.off_par, pf, 7);
+  d.l2m = pf[0], d.lam = pf[1], d.muxy = pf[2], d.muxz = pf[3], d.muyz = pf[4], d.rho = pf[5], d.mu = pf[6];
   d.prof = (const gfloat*)(tab);
   d.row_slot = (const gint*)(tab + 4 * p.nx + 4 * p.ny + 4 * p.nz);
   d.rowch = d.row_slot + (long)p.nz * p.ny;

@@ -301,10 +301,11 @@ struct Shot3D {
   gfloat* pbx[2][6];
   gfloat* pby[2][6];
   gfloat* pbz[2][6];
-  gfloat *l2m, *lam, *muxy, *muxz, *muyz, *bx, *by, *bz;
+  gfloat *l2m, *lam, *muxy, *muxz, *muyz;
   // density and mu at the normal nodes, padded, with the last plane, row and column repeated
   // one node beyond the grid: the step kernels derive the buoyancies and harmonic shear
-  // moduli from them (the same values as the staged ones, which the chain rule reads)
+  // moduli from them (the moduli bitwise the staged ones, which the transposed stress
+  // kernel and the source adjoint read)
   gfloat *rho, *mu;
   const gfloat* prof;           // x: a_int b_int a_half b_half [nx] each, then y [ny], then z [nz]
   const gfloat* src;            // [6][nt]

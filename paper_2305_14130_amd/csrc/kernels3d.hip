@@ -159,9 +159,9 @@ __device__ __forceinline__ float hist_get(const gfloat* base, unsigned e) {
 }
 
 // Harmonic mean of the four shear moduli around a shear node (0 if any is 0), and the
-// buoyancy between two normal nodes: the staging kernel and the step kernels evaluate the
-// same expressions on the same FP32 values, so the derived parameters are bitwise the staged
-// ones.
+// buoyancy between two normal nodes. The staging kernel and the step kernels evaluate the
+// shear moduli by the same expressions on the same FP32 values, so the derived moduli are
+// bitwise the staged ones that the transposed stress kernel reads.
 __device__ __forceinline__ float harm4(float a, float b, float c, float d) {
   return (a > 0.f && b > 0.f && c > 0.f && d > 0.f) ? 4.0f / (1.0f / a + 1.0f / b + 1.0f / c + 1.0f / d) : 0.0f;
 }
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(TX * TY) void k3_adj_str(PARAMS3, int n, int kseg, 
 }
 
 // ------------------------------------------------------------------------------------
-// Staging: (Vp, Vs, rho) -> lambda + 2 mu, lambda, harmonic shear moduli, buoyancies.
+// Staging: (Vp, Vs, rho) -> lambda + 2 mu, lambda, harmonic shear moduli, padded rho and mu.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(TX * TY) void k3_stage(PARAMS3) {
   TILE3() {
@@ -688,9 +688,6 @@ __global__ __launch_bounds__(TX * TY) void k3_stage(PARAMS3) {
     G(PF(s.muxy), o) = harm4(mu, mu_at(i, kp, j), mu_at(i, k, jp), mu_at(i, kp, jp));
     G(PF(s.muxz), o) = harm4(mu, mu_at(ip, k, j), mu_at(i, k, jp), mu_at(ip, k, jp));
     G(PF(s.muyz), o) = harm4(mu, mu_at(ip, k, j), mu_at(i, kp, j), mu_at(ip, kp, j));
-    G(PF(s.bx), o) = buoy(rho, at(s.mrho, i, k, jp));
-    G(PF(s.by), o) = buoy(rho, at(s.mrho, i, kp, j));
-    G(PF(s.bz), o) = buoy(rho, at(s.mrho, ip, k, j));
     // rho and mu, repeated one node beyond the last plane, row and column (the clamped
     // neighbours of the derivations above)
     const unsigned ld = (unsigned)s.ld, pz = (unsigned)s.pz;
