@@ -32,8 +32,8 @@ The JSON line also carries:
 * roofline: the dominant kernel's algorithmic bytes per launch (adj_step: 92 B per cell plus
   32 B per strip cell, averaged over the launches of the waves) over its mean launch time
   (HIP events around sampled launches on the library's stream), against 8 TB/s; `traffic`
-  is the HBM bytes per launch rocprofv3's counters measured for it on this workload, when
-  such a measurement of the current kernels is recorded below (else null);
+  is the HBM bytes per launch from rocprofv3's read and write counters, measured per cell on
+  the first windows of this workload and recorded below for the current kernel (else null);
 * path: the whole step's algorithmic bytes (with CPML) over the step time;
 * forms: the same 64 windows as 64 sequential shot_gradient calls (shots/s plain vs
   batched), the batched form with sqrt(nt) FP32, FP16 and BF16 checkpoints (accuracy of the
@@ -70,11 +70,14 @@ ALG3 = {"fwd": 84, "store": 12, "adj": 84, "img": 24, "acc": 24, "psi": 48}
 # quantities), fused transposed step 96 (state, 3 staged parameters, 5 stored quantities,
 # 3 imaging sums read and written)
 DESIGN2 = {"fwd": 52, "fwd_store": 72, "adj": 96}
-# HBM traffic per launch of the dominant kernel measured with rocprofv3 on this workload
-# (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors of a 256 MiB device copy), keyed by
-# (kernel, tile rows); filled in from profiles/ when a measurement of the current kernels
-# exists.
-MEASURED_TRAFFIC = {}
+# HBM bytes per cell of one launch of the dominant kernel, measured with rocprofv3's read
+# and write counters (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 KiB, the factors of a 256 MiB
+# device copy) on the first 3 windows of this workload at 400 steps (whole history, one wave
+# each: 1.45 M cells per launch, 14.7% of them CPML strip cells against the full workload's
+# 15.1%), keyed by (kernel, tile rows); profiles/batched2d_64windows_adj_step_counters.md.
+# `traffic` is that figure times the cells of a launch of this run. A kernel changed since
+# its measurement is removed from here.
+MEASURED_TRAFFIC_PER_CELL = {("adj_step", 12): 109.71}
 
 
 def strip_cells_2d(wz, wx, npml):
@@ -708,7 +711,8 @@ def main():  # noqa: C901
     bytes_launch = per_step * nt / launches_per_step
     achieved = bytes_launch / (kern[dominant]["mean_us"] * 1e-6) / 1e9
     rows = tiles[1] if dominant == "adj_step" else tiles[0]
-    traffic = MEASURED_TRAFFIC.get((dominant, rows)) if rf == 0.0 and nt == 4000 else None
+    per_cell = MEASURED_TRAFFIC_PER_CELL.get((dominant, rows)) if rf == 0.0 else None
+    traffic = int(per_cell * cells / len(waves)) if per_cell and dominant == "adj_step" else None
     out = {
         "metric": "Gcell-updates/s fwd+adj+grad (and % HBM roofline); shots/s batched vs plain",
         "value": round(value, 4),
@@ -735,6 +739,9 @@ def main():  # noqa: C901
                                  "autotune_ms": {str(k): [round(x, 3) for x in v] for k, v in tune_ms.items()}}},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_basis": ("HBM bytes per launch: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE (KiB, "
+                                       "copy-calibrated) per cell of this kernel on the first 3 windows, "
+                                       f"{per_cell} B, times the cells of a launch here") if traffic else None,
                      "bytes_per_launch": int(bytes_launch), "mean_launch_us": kern[dominant]["mean_us"],
                      "bytes_model": "92 B per cell (adjoint step 52, imaging 16, accumulators 24) + 32 B per CPML "
                                     "strip cell, averaged over the launches of the waves"},
