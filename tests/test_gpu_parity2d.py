@@ -112,6 +112,15 @@ def _check_gradient(efwi, c, interval, label):
     for k, name in enumerate(["Vp", "Vs", "rho"]):
         e = rel(g[k], c.g_o[k])
         assert e <= bar, f"{label} g{name} rel L2 {e:.3e} > {bar:.2e} (kappa {c.kappa:.1f})"
+        # the first and last row and column on their own: there the staggered averages clamp
+        # and the imaging gather weights a neighbour twice, and the CPML leaves too little of
+        # the gradient's norm there for the whole-grid comparison to see a mistake; a wrongly
+        # weighted node errs by tens of percent, FP32 rounding on a face with little of the
+        # norm by more than the whole grid's bar, so the faces take 10 times the bar
+        for face, sl in (("top", np.s_[0, :]), ("bottom", np.s_[-1, :]), ("left", np.s_[:, 0]),
+                         ("right", np.s_[:, -1])):
+            e = rel(g[k][sl], c.g_o[k][sl])
+            assert e <= 10 * bar, f"{label} g{name} {face} rel L2 {e:.3e} > {10 * bar:.2e}"
 
 
 @pytest.mark.parametrize("interval,label", [(0, "sqrt-nt"), (37, "ragged"), (10**6, "full-storage")])
@@ -173,6 +182,10 @@ def test_rigid_boundaries_parity(gpu_lib):
     bar = TOL * kappa(d_o, d_o - d_obs)
     for k in range(3):
         assert rel(g[k], g_o[k]) <= bar
+        # the reflected waves put much of the gradient on the edges, where the staggered
+        # averages clamp (each edge at 10 times the bar, as in the CPML cases)
+        for sl in (np.s_[0, :], np.s_[-1, :], np.s_[:, 0], np.s_[:, -1]):
+            assert rel(g[k][sl], g_o[k][sl]) <= 10 * bar
 
 
 def test_windowed_shot_matches_oracle_on_crop(gpu_lib):
