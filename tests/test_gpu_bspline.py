@@ -20,7 +20,7 @@ def close32(out, ref):
 # the last two: rows longer than a workgroup's column segment and node group (every column
 # a node), and a spacing whose weight table leaves room for only a few hundred staged cells
 @pytest.mark.parametrize("nz,nx,Dz,Dx", [(37, 150, 1, 10), (64, 65, 4, 7), (5, 3, 2, 9), (100, 400, 1, 10),
-                                         (70, 4500, 3, 1), (40, 5000, 1, 1990)])
+                                         (30, 1100, 3, 1), (40, 5000, 1, 1990)])
 def test_expand_and_adjoint_parity(gpu_lib, nz, nx, Dz, Dx):
     efwi = gpu_lib
     rng = np.random.default_rng(nz + nx)

@@ -99,6 +99,14 @@ def test_forward_data_parity(gpu_lib, case):
     assert rel(d.cpu().numpy(), case.d_o) <= TOL
 
 
+def face_err(g, ref, sl):
+    """Error on one edge of the grid: relative to the edge's own norm, or to 1e-4 of the
+    whole gradient's where the edge carries less (the waves may not reach it at all)."""
+    ref = np.asarray(ref, np.float64)
+    scale = max(float(np.linalg.norm(ref[sl])), 1e-4 * float(np.linalg.norm(ref)))
+    return float(np.linalg.norm(np.asarray(g, np.float64)[sl] - ref[sl])) / scale
+
+
 def _check_gradient(efwi, c, interval, label):
     d_out = torch.empty((c.sh.ch_iz.size, c.grid_o.nt), dtype=torch.float32, device="cuda")
     g, phi = efwi.shot_gradient(c.grid_g(efwi), c.shot_g(efwi, ckpt_interval=interval), T(c.m),
@@ -119,7 +127,7 @@ def _check_gradient(efwi, c, interval, label):
         # norm by more than the whole grid's bar, so the faces take 10 times the bar
         for face, sl in (("top", np.s_[0, :]), ("bottom", np.s_[-1, :]), ("left", np.s_[:, 0]),
                          ("right", np.s_[:, -1])):
-            e = rel(g[k][sl], c.g_o[k][sl])
+            e = face_err(g[k], c.g_o[k], sl)
             assert e <= 10 * bar, f"{label} g{name} {face} rel L2 {e:.3e} > {10 * bar:.2e}"
 
 
@@ -185,7 +193,7 @@ def test_rigid_boundaries_parity(gpu_lib):
         # the reflected waves put much of the gradient on the edges, where the staggered
         # averages clamp (each edge at 10 times the bar, as in the CPML cases)
         for sl in (np.s_[0, :], np.s_[-1, :], np.s_[:, 0], np.s_[:, -1]):
-            assert rel(g[k][sl], g_o[k][sl]) <= 10 * bar
+            assert face_err(g[k], g_o[k], sl) <= 10 * bar
 
 
 def test_windowed_shot_matches_oracle_on_crop(gpu_lib):

@@ -27,6 +27,14 @@ FACES = (("z0", np.s_[0]), ("z1", np.s_[-1]), ("y0", np.s_[:, 0]), ("y1", np.s_[
 FACE_FACTOR = 10.0
 
 
+def face_err(g, ref, sl):
+    """Error on one face: relative to the face's own norm, or to 1e-4 of the whole
+    gradient's where the face carries less (the waves may not reach it at all)."""
+    ref = np.asarray(ref, np.float64)
+    scale = max(float(np.linalg.norm(ref[sl])), 1e-4 * float(np.linalg.norm(ref)))
+    return float(np.linalg.norm(np.asarray(g, np.float64)[sl] - ref[sl])) / scale
+
+
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
@@ -89,7 +97,7 @@ def test_gradient_3d(gpu_lib, case, interval):
         e = rel(g[k], case.g_ref[k])
         assert e <= bar, (interval, k, e, case.kappa)
         for face, sl in FACES:
-            e = rel(g[k][sl], case.g_ref[k][sl])
+            e = face_err(g[k], case.g_ref[k], sl)
             assert e <= FACE_FACTOR * bar, (interval, k, face, e)
     assert abs(phi.item() - case.phi_o) / case.phi_o <= 2 * bar
 
@@ -116,7 +124,7 @@ def test_rigid_boundaries_3d(gpu_lib):
     for k in range(3):
         assert rel(g[k], g_ref[k]) <= bar, (k, rel(g[k], g_ref[k]))
         for face, sl in FACES:
-            e = rel(g[k][sl], g_ref[k][sl])
+            e = face_err(g[k], g_ref[k], sl)
             assert e <= FACE_FACTOR * bar, (k, face, e)
 
 
