@@ -2168,15 +2168,19 @@ efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zone
   const int ny = three ? grid->ny : 1;
   const long npts = (long)grid->nz * ny * grid->nx;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  for (int s = 0; s < ns; ++s) {
-    const efwi_zoi& z = zones[s];
-    ZoiArgs a;
-    for (int k = 0; k < 3; ++k) a.src[k] = z.src[k];
-    for (int k = 0; k < 6; ++k) a.icov[k] = z.icov[k], a.box[k] = z.box[k];
-    a.taper = z.taper, a.n = n, a.nu = nu;
+  for (int s0 = 0; s0 < ns; s0 += ZOI_BATCH) {   // up to ZOI_BATCH zones per launch
+    const int count = std::min(ZOI_BATCH, ns - s0);
+    ZoiBatch zb{};
+    for (int q = 0; q < count; ++q) {
+      const efwi_zoi& z = zones[s0 + q];
+      ZoiArgs& a = zb.z[q];
+      for (int k = 0; k < 3; ++k) a.src[k] = z.src[k];
+      for (int k = 0; k < 6; ++k) a.icov[k] = z.icov[k], a.box[k] = z.box[k];
+      a.taper = z.taper, a.n = n, a.nu = nu;
+    }
     HIP_TRY(TIMED(KK_ZOI, st,
-                  launch_zoi(three ? 1 : 0, npts, ny, grid->nx, grid->dz, three ? grid->dy : 0.0, grid->dx, a,
-                             b + (size_t)s * npts, sink + (size_t)s * npts, st)));
+                  launch_zoi(three ? 1 : 0, count, npts, grid->nz, ny, grid->nx, grid->dz, three ? grid->dy : 0.0,
+                             grid->dx, zb, b + (size_t)s0 * npts, sink + (size_t)s0 * npts, st)));
   }
   return EFWI_OK;
 }

@@ -236,8 +236,14 @@ int regularizer_blocks(long npts);
 struct ZoiArgs {
   double src[3], icov[6], box[6], taper, n, nu;
 };
-hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy, double dx, const ZoiArgs& a,
-                      float* b, unsigned char* sink, hipStream_t st);
+// Up to ZOI_BATCH zones per launch, passed by value (the launch's arguments stay below 4 KB).
+constexpr int ZOI_BATCH = 16;
+struct ZoiBatch {
+  ZoiArgs z[ZOI_BATCH];
+};
+// Zones zb.z[0 .. count) into b[s][npts], sink[s][npts] (s counted from the batch's first).
+hipError_t launch_zoi(int three, int count, long npts, int nz, int ny, int nx, double dz, double dy, double dx,
+                      const ZoiBatch& zb, float* b, unsigned char* sink, hipStream_t st);
 hipError_t launch_final_model(int ns, long npts, const float* m_ext, const float* b, const unsigned char* sink,
                               float* m_out, hipStream_t st);
 // Extension along groups of shots (regularizer.hip): one shot's FP64 gradient sums of its

@@ -126,14 +126,16 @@ __global__ void k_sum_partials(const double* partial, int n, double scale, doubl
 // FP64, with the squared distance summed in a fixed order and no contraction, so that the
 // sinkhole flag (an integer decided by floating point) is reproducible.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(RB) void k_zoi(long npts, int ny, int nx, double dz, double dy, double dx, int three,
-                                            ZoiArgs a, float* __restrict__ b, unsigned char* __restrict__ sink) {
+__global__ __launch_bounds__(RB) void k_zoi(long npts, int ny, int nx, int xblocks, double dz, double dy, double dx,
+                                            int three, ZoiBatch zb, float* __restrict__ b,
+                                            unsigned char* __restrict__ sink) {
 #pragma clang fp contract(off)
-  const double ln = log(a.nu), den = 1.0 - ln;
-  for (long p = blockIdx.x * (long)RB + threadIdx.x; p < npts; p += (long)gridDim.x * RB) {
-    const long row = p / nx;
-    const int j = (int)(p - row * nx);
-    const int i = (int)(row / ny), k = (int)(row - (long)i * ny);
+  // one zone per blockIdx.y; blockIdx.x = row (i, k) x block of RB columns
+  const ZoiArgs& a = zb.z[blockIdx.y];
+  const int row = (int)(blockIdx.x / (unsigned)xblocks), j = (int)(blockIdx.x - (unsigned)row * xblocks) * RB + threadIdx.x;
+  if (j < nx) {
+    const int i = row / ny, k = row - i * ny;
+    const long p = (long)row * nx + j;
     const double z = (double)i * dz, y = (double)k * dy, x = (double)j * dx;
     const double ez = fmax(fmax(a.box[0] - z, z - a.box[1]), 0.0);
     const double ex = fmax(fmax(a.box[4] - x, x - a.box[5]), 0.0);
@@ -159,8 +161,14 @@ __global__ __launch_bounds__(RB) void k_zoi(long npts, int ny, int nx, double dz
     const double r_sink = in ? 1.0 - sqrt(d2) : 0.0;
     const double r = fmax(r_out, r_sink);
     // r = 0 (the active part) gives exactly 1: skip the transcendental functions there
-    b[p] = r > 0.0 ? (float)((pow(cos(0.5 * M_PI * r), a.n) - ln) / den) : 1.0f;
-    sink[p] = in ? 1 : 0;
+    const long q = (long)blockIdx.y * npts + p;
+    float w = 1.0f;
+    if (r > 0.0) {
+      const double ln = log(a.nu), den = 1.0 - ln;
+      w = (float)((pow(cos(0.5 * M_PI * r), a.n) - ln) / den);
+    }
+    b[q] = w;
+    sink[q] = in ? 1 : 0;
   }
 }
 
@@ -222,9 +230,13 @@ __global__ __launch_bounds__(RB) void k_add_gradient(const double* __restrict__ 
 
 }  // namespace
 
-hipError_t launch_zoi(int three, long npts, int ny, int nx, double dz, double dy, double dx, const ZoiArgs& a,
-                      float* b, unsigned char* sink, hipStream_t st) {
-  k_zoi<<<regularizer_blocks(npts), RB, 0, st>>>(npts, ny, nx, dz, dy, dx, three, a, b, sink);
+hipError_t launch_zoi(int three, int count, long npts, int nz, int ny, int nx, double dz, double dy, double dx,
+                      const ZoiBatch& zb, float* b, unsigned char* sink, hipStream_t st) {
+  if (count < 1 || count > ZOI_BATCH || npts <= 0) return count == 0 ? hipSuccess : hipErrorInvalidValue;
+  const int xblocks = (nx + RB - 1) / RB;
+  if ((long)nz * ny * xblocks > 0x7fffffffL) return hipErrorInvalidValue;
+  k_zoi<<<dim3((unsigned)((long)nz * ny * xblocks), (unsigned)count), RB, 0, st>>>(npts, ny, nx, xblocks, dz, dy, dx,
+                                                                                   three, zb, b, sink);
   return hipGetLastError();
 }
 
