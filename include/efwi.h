@@ -288,7 +288,7 @@ typedef struct {
  *   zones HOST [ns]; n > 0 sets the transition's stiffness, 0 < nu < 1 its height;
  *   b     DEVICE [ns][nz][nx] (3D [ns][nz][ny][nx]) FP32 output;
  *   sink  DEVICE unsigned char, same shape, output.
- * FP64 arithmetic, one launch per source on `stream`. EFWI_E_INVAL for a box with an upper
+ * FP64 arithmetic, one launch per 16 sources on `stream`. EFWI_E_INVAL for a box with an upper
  * bound below its lower bound, a negative taper, an inverse covariance that is not positive
  * definite, non-finite values, or n, nu out of range. */
 efwi_status efwi_zoi_weights(const efwi_grid* grid, int ns, const efwi_zoi* zones, float n, float nu,
