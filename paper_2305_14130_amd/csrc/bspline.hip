@@ -136,9 +136,11 @@ int bspline_nodes(int n, int D) { return (n - 1 + D - 1) / D + 3; }
 
 hipError_t launch_bspline_expand(int np, int nz, int nx, int Dz, int Dx, const float* c, float* m, hipStream_t st) {
   if ((long)np * nz <= 0 || nx <= 0) return hipSuccess;
+  if ((long)np * nz > 0x7fffffffL) return hipErrorInvalidValue;   // one workgroup row per output row
   const int cols = std::min(4096, 1024 * Dx);
   const size_t lds = (size_t)(4 * Dx - 1 + cols / Dx + 5) * sizeof(double);
   if (lds > 64 * 1024) return hipErrorInvalidValue;   // the entry points refuse such spacings
+  if ((nx + cols - 1) / cols > 65535) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((long)np * nz), (unsigned)((nx + cols - 1) / cols));
   k_bspline_expand<<<grid, BB, lds, st>>>(nz, nx, Dz, Dx, bspline_nodes(nz, Dz), bspline_nodes(nx, Dx), cols, c, m);
   return hipGetLastError();
@@ -147,6 +149,7 @@ hipError_t launch_bspline_expand(int np, int nz, int nx, int Dz, int Dx, const f
 hipError_t launch_bspline_adjoint(int np, int nz, int nx, int Dz, int Dx, const float* g, float* cb, hipStream_t st) {
   const int Nz = bspline_nodes(nz, Dz), Nx = bspline_nodes(nx, Dx);
   if ((long)np * Nz <= 0) return hipSuccess;
+  if ((long)np * Nz > 0x7fffffffL || (Nx + ADJ_NODES - 1) / ADJ_NODES > 65535) return hipErrorInvalidValue;
   const size_t table = (size_t)(4 * Dx - 1) * sizeof(double);
   if (table + sizeof(float) > 64 * 1024) return hipErrorInvalidValue;   // the entry points refuse such spacings
   // staged cells: what the 64 KB of LDS leave beside the table, at most 4096
