@@ -128,6 +128,41 @@ def test_rigid_boundaries_3d(gpu_lib):
             assert e <= FACE_FACTOR * bar, (k, face, e)
 
 
+def test_windowed_shot_3d_matches_oracle_on_crop(gpu_lib):
+    """A 3D shot on a window of a larger model (ragged against the 64 x 16 tiles, its own
+    6-cell CPML on the window's faces) equals the oracle on the cropped model, each face of
+    the window included; the gradient outside the window is zero (eq.(8))."""
+    efwi = gpu_lib
+    w = inputs.precision_3d(nz=36, ny=40, nx=72, nt=160, nshots=1, nch_per_well=20, npml=8)
+    z0, y0, x0, wz, wy, wx, npml = 3, 5, 9, 30, 32, 56, 6
+    siz, siy, six = z0 + 15, y0 + 16, x0 + 28
+    chx = np.arange(x0 + 12, x0 + 45, 2).astype(np.int32)
+    chz, chy = np.full(chx.size, siz + 1, np.int32), np.full(chx.size, siy, np.int32)
+    m = f32(w.m_start)
+    mc = m[:, z0:z0 + wz, y0:y0 + wy, x0:x0 + wx]
+    src = f32(np.outer(w.shots[0].M, w.stf))
+    g_o = E3.Grid3D(nz=wz, ny=wy, nx=wx, dz=r32(w.h), dy=r32(w.h), dx=r32(w.h), dt=r32(w.dt), nt=w.nt, npml=npml,
+                    pml_R=r32(w.pml_R), pml_f0=r32(w.f0), vp_max=r32(w.vp_max))
+    pos, ch = (siz - z0, siy - y0, six - x0), (chz - z0, chy - y0, chx - x0)
+    d_obs = f32(E3.model_forward(g_o, mc * np.array([1.1, 1.05, 1.0])[:, None, None, None], pos, src, ch))
+    g_ref, phi_o, d_o = E3.shot_gradient(g_o, mc, pos, src, ch, d_obs)
+    bar = TOL * max(1.0, float(np.linalg.norm(d_o) / np.linalg.norm(d_o - d_obs)))
+    grid = efwi.make_grid3d(w.nz, w.ny, w.nx, w.h, w.h, w.h, w.dt, w.nt, npml, w.pml_R, w.f0, w.vp_max)
+    shot = efwi.Shot(siz, six, chz, chx, src_iy=siy, ch_iy=chy, z0=z0, y0=y0, x0=x0, wz=wz, wy=wy, wx=wx,
+                     ckpt_interval=23)
+    g, phi = efwi.shot_gradient(grid, shot, T(m), T(src), T(d_obs))
+    g = g.cpu().numpy()
+    inside = g[:, z0:z0 + wz, y0:y0 + wy, x0:x0 + wx]
+    assert abs(phi.item() - phi_o) / phi_o <= 2 * bar
+    for k in range(3):
+        assert rel(inside[k], g_ref[k]) <= bar, (k, rel(inside[k], g_ref[k]))
+        for face, sl in FACES:
+            e = face_err(inside[k], g_ref[k], sl)
+            assert e <= FACE_FACTOR * bar, (k, face, e)
+    g[:, z0:z0 + wz, y0:y0 + wy, x0:x0 + wx] = 0.0
+    assert np.all(g == 0.0)
+
+
 def test_adjoint_and_dot_product_3d(gpu_lib, case):
     efwi = gpu_lib
     w = case.w
