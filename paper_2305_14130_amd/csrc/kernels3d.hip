@@ -458,9 +458,10 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
   // neighbours the differences above loaded are not loaded again. The four shear nodes of
   // a type (this node's and those one back along either or both of the type's axes a, b)
   // are weighted by how often their clamped corners use this node: twice at the last
-  // plane, row or column (wa, wb), else once. Before the first one t_bar is the zero halo
-  // and the stored quantity is read at this node instead, so the term is zero. The stored
-  // shear quantities are read through the caches: four normal nodes gather each.
+  // plane, row or column (wa, wb), else once. A neighbour before the first plane, row or
+  // column has its t_bar in the zero halo, and its stored quantity is read at this node
+  // instead (in bounds and finite), so its term is zero. The stored shear quantities are
+  // read through the caches: four normal nodes gather each.
   float img_a = 0.0f, img_e = 0.0f;
   if (GRAD) {
     const unsigned c = (unsigned)(((long)i * s.ny + k) * s.cp + j), cells = (unsigned)s.cells;
