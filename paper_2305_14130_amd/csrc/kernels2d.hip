@@ -1203,33 +1203,34 @@ __global__ __launch_bounds__(BX * BZ) void k_write_gradient(BATCH_PARAMS) {
 constexpr int RES_T = 64;
 __global__ __launch_bounds__(256) void k_residual(const float* d, const float* dobs, int nch, int nt,
                                                   double* partial, float* ebar) {
+  // sample-major ([sample][channel]): the sequential scan below, one channel per lane,
+  // then reads consecutive addresses across the wave (bank-conflict free)
   __shared__ double tile[RES_T][RES_T + 1];
   const int c0 = blockIdx.x * RES_T, tid = threadIdx.x;
   constexpr int ROWS = 256 / RES_T;   // channels (loads) or samples (stores) per pass of the block
   double acc = 0.0, sq = 0.0;         // of channel c0 + tid, in threads tid < RES_T
   for (int t0 = (nt - 1) / RES_T * RES_T; t0 >= 0; t0 -= RES_T) {
+    // every load in bounds (index clamped, the value then kept or zeroed), so that the
+    // loads of a pass issue together instead of one branch and round trip each
     for (int k = 0; k < RES_T / ROWS; ++k) {
       const int ch = tid / RES_T + ROWS * k, sm = tid % RES_T, c = c0 + ch, t = t0 + sm;
-      double r = 0.0;
-      if (c < nch && t < nt) {
-        const long e = (long)c * nt + t;
-        r = dobs ? (double)d[e] - (double)dobs[e] : (double)d[e];
-      }
-      tile[ch][sm] = r;
+      const long e = (long)min(c, nch - 1) * nt + min(t, nt - 1);
+      const double r = dobs ? (double)d[e] - (double)dobs[e] : (double)d[e];
+      tile[sm][ch] = (c < nch && t < nt) ? r : 0.0;
     }
     __syncthreads();
     if (tid < RES_T) {
       for (int sm = RES_T - 1; sm >= 0; --sm) {   // samples past nt hold r = 0 and change nothing
-        const double r = tile[tid][sm];
+        const double r = tile[sm][tid];
         sq += r * r;
         acc += r;
-        tile[tid][sm] = acc;
+        tile[sm][tid] = acc;
       }
     }
     __syncthreads();
     for (int k = 0; k < RES_T / ROWS; ++k) {
       const int sm = tid / RES_T + ROWS * k, ch = tid % RES_T, c = c0 + ch, t = t0 + sm;
-      if (c < nch && t < nt) ebar[(long)t * nch + c] = (float)tile[ch][sm];
+      if (c < nch && t < nt) ebar[(long)t * nch + c] = (float)tile[sm][ch];
     }
     __syncthreads();
   }
