@@ -72,6 +72,22 @@ def test_zoi_weights_2d(gpu_lib, n, nu):
     check_weights(b.cpu().numpy(), sink.cpu().numpy(), b_ref, s_ref)
 
 
+def test_zoi_weights_more_zones_than_a_launch(gpu_lib):
+    """21 zones (the kernel takes up to 16 per launch): each zone's weights and flags land
+    in its own slot, the second launch's too."""
+    efwi = gpu_lib
+    nz, nx, h = 60, 131, 5.0
+    grid = efwi.make_grid(nz, nx, h, h, 1e-4, 10, 0, 1e-3, 10.0, 4000.0)
+    zs = [{"src": (80.0 + 5.0 * (s % 7), 0.0, 30.0 * s), "icov": (1 / (400.0 + 50.0 * s), 0.0, 1 / 1600.0, 0.0, 0.0, 0.0),
+           "box": (40.0, 220.0, 0.0, 0.0, max(0.0, 30.0 * s - 100.0), 30.0 * s + 100.0), "taper": 20.0 + 5.0 * s}
+          for s in range(21)]
+    b, sink = efwi.zoi_weights(grid, [to_c(efwi, z) for z in zs], 2.5, 0.7)
+    torch.cuda.synchronize()
+    b_ref, s_ref = Z.zoi_weights((nz, nx), (h, h), [rounded(z) for z in zs], 2.5, float(np.float32(0.7)))
+    assert all(s_ref[s].any() for s in range(21))
+    check_weights(b.cpu().numpy(), sink.cpu().numpy(), b_ref, s_ref)
+
+
 def test_zoi_weights_3d(gpu_lib):
     efwi = gpu_lib
     nz, ny, nx, h = 20, 24, 28, 5.0
