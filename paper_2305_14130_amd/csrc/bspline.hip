@@ -77,28 +77,35 @@ __global__ __launch_bounds__(BB) void k_bspline_expand(int nz, int nx, int Dz, i
   }
 }
 
-// Transpose: one workgroup per group of ADJ_NODES nodes of one coefficient row (plane p,
-// node row a). The input rows in the row's support are staged in LDS one after the other,
-// in chunks of `chunk` cells (after the x weight table); each thread sums, for each of its
-// nodes, the staged cells in the node's support with the tabulated x weights (every lane
-// of a wave reads the same table entry), and adds the row's sum times its z weight.
-constexpr int ADJ_NPT = 4, ADJ_NODES = ADJ_NPT * BB;
+// Transpose: one workgroup per group of ADJ_NODES nodes of `rows` (at most ADJ_ROWS)
+// consecutive coefficient rows (plane p, node rows a0 ..). The input rows in the union of those rows' z supports are
+// staged in LDS one after the other, in chunks of `chunk` cells (after the x weight table);
+// each thread sums, for each of its nodes, the staged cells in the node's support with the
+// tabulated x weights (every lane of a wave reads the same table entry), once per input row,
+// and adds that sum times the row's z weight to each coefficient row whose support holds the
+// input row (each in ascending input-row order, as one row at a time would).
+constexpr int ADJ_NPT = 4, ADJ_NODES = ADJ_NPT * BB, ADJ_ROWS = 4;
 
 __global__ __launch_bounds__(BB) void k_bspline_adjoint(int nz, int nx, int Dz, int Dx, int Nz, int Nx, int chunk,
-                                                        const float* __restrict__ g, float* __restrict__ cb) {
+                                                        int rows, const float* __restrict__ g,
+                                                        float* __restrict__ cb) {
   extern __shared__ double wtab[];
   double* wxs = wtab;                                   // wxs[d + 2 Dx - 1] = B(d / Dx)
   float* gs = reinterpret_cast<float*>(wtab + 4 * Dx - 1);
   for (int u = threadIdx.x; u < 4 * Dx - 1; u += BB) wxs[u] = bsp((double)(u - 2 * Dx + 1) * (1.0 / Dx));
-  const int row = blockIdx.x, a = row % Nz, p = row / Nz;
+  const int rgroups = (Nz + rows - 1) / rows;
+  const int p = blockIdx.x / rgroups, a0 = (blockIdx.x - p * rgroups) * rows;
+  const int a1 = min(Nz, a0 + rows) - 1;
   const int bfirst = blockIdx.y * ADJ_NODES, blast = min(Nx, bfirst + ADJ_NODES) - 1;
-  // cells the group's nodes reach, and the rows in node row a's support: (k - 3) D < i < (k + 1) D
+  // cells the group's nodes reach; rows in node row a's support: (a - 3) D < i < (a + 1) D
   const int cfirst = max(0, (bfirst - 3) * Dx + 1), clast = min(nx - 1, (blast + 1) * Dx - 1);
-  const int i0 = max(0, (a - 3) * Dz + 1), i1 = min(nz - 1, (a + 1) * Dz - 1);
+  const int i0 = max(0, (a0 - 3) * Dz + 1), i1 = min(nz - 1, (a1 + 1) * Dz - 1);
   const float* gp = g + (size_t)p * nz * nx;
-  double acc[ADJ_NPT], h[ADJ_NPT];
+  double acc[ADJ_ROWS][ADJ_NPT], h[ADJ_NPT];
 #pragma unroll
-  for (int q = 0; q < ADJ_NPT; ++q) acc[q] = 0.0;
+  for (int r = 0; r < ADJ_ROWS; ++r)
+#pragma unroll
+    for (int q = 0; q < ADJ_NPT; ++q) acc[r][q] = 0.0;
   for (int i = i0; i <= i1; ++i) {
 #pragma unroll
     for (int q = 0; q < ADJ_NPT; ++q) h[q] = 0.0;
@@ -113,20 +120,29 @@ __global__ __launch_bounds__(BB) void k_bspline_adjoint(int nz, int nx, int Dz, 
         if (b > blast) continue;
         const int jl = max(max((b - 3) * Dx + 1, c0), 0), jh = min(min((b + 1) * Dx - 1, c1), nx - 1);
         const int ox = 2 * Dx - 1 - (b - 1) * Dx;   // wxs[j + ox]: node b, cell j
-        double r = 0.0;
-        for (int j = jl; j <= jh; ++j) r += (double)gs[j - c0] * wxs[j + ox];
-        h[q] += r;
+        double rs = 0.0;
+        for (int j = jl; j <= jh; ++j) rs += (double)gs[j - c0] * wxs[j + ox];
+        h[q] += rs;
       }
     }
-    const double wz = bsp((double)(i - (a - 1) * Dz) * (1.0 / Dz));
 #pragma unroll
-    for (int q = 0; q < ADJ_NPT; ++q) acc[q] += wz * h[q];
+    for (int r = 0; r < ADJ_ROWS; ++r) {
+      const int a = a0 + r;
+      if (a > a1 || i <= (a - 3) * Dz || i >= (a + 1) * Dz) continue;   // i outside row a's support
+      const double wz = bsp((double)(i - (a - 1) * Dz) * (1.0 / Dz));
+#pragma unroll
+      for (int q = 0; q < ADJ_NPT; ++q) acc[r][q] += wz * h[q];
+    }
   }
-  float* crow = cb + (size_t)row * Nx;
 #pragma unroll
-  for (int q = 0; q < ADJ_NPT; ++q) {
-    const int b = bfirst + (int)threadIdx.x + q * BB;
-    if (b <= blast) crow[b] = (float)acc[q];
+  for (int r = 0; r < ADJ_ROWS; ++r) {
+    if (a0 + r > a1) continue;
+    float* crow = cb + ((size_t)p * Nz + a0 + r) * Nx;
+#pragma unroll
+    for (int q = 0; q < ADJ_NPT; ++q) {
+      const int b = bfirst + (int)threadIdx.x + q * BB;
+      if (b <= blast) crow[b] = (float)acc[r][q];
+    }
   }
 }
 
@@ -149,14 +165,18 @@ hipError_t launch_bspline_expand(int np, int nz, int nx, int Dz, int Dx, const f
 hipError_t launch_bspline_adjoint(int np, int nz, int nx, int Dz, int Dx, const float* g, float* cb, hipStream_t st) {
   const int Nz = bspline_nodes(nz, Dz), Nx = bspline_nodes(nx, Dx);
   if ((long)np * Nz <= 0) return hipSuccess;
-  if ((long)np * Nz > 0x7fffffffL || (Nx + ADJ_NODES - 1) / ADJ_NODES > 65535) return hipErrorInvalidValue;
+  // coefficient rows per workgroup: four share each staged input row's x sums (an input row
+  // lies in four rows' z supports), one where that would leave the GPU too few workgroups
+  const int rows = (long)np * Nz >= 2048 ? ADJ_ROWS : 1;
+  const long rgroups = (Nz + rows - 1) / rows;
+  if ((long)np * rgroups > 0x7fffffffL || (Nx + ADJ_NODES - 1) / ADJ_NODES > 65535) return hipErrorInvalidValue;
   const size_t table = (size_t)(4 * Dx - 1) * sizeof(double);
   if (table + sizeof(float) > 64 * 1024) return hipErrorInvalidValue;   // the entry points refuse such spacings
   // staged cells: what the 64 KB of LDS leave beside the table, at most 4096
   const int chunk = (int)std::min<size_t>(4096, (64 * 1024 - table) / sizeof(float));
   const size_t lds = table + (size_t)chunk * sizeof(float);
-  const dim3 grid((unsigned)((long)np * Nz), (unsigned)((Nx + ADJ_NODES - 1) / ADJ_NODES));
-  k_bspline_adjoint<<<grid, BB, lds, st>>>(nz, nx, Dz, Dx, Nz, Nx, chunk, g, cb);
+  const dim3 grid((unsigned)(np * rgroups), (unsigned)((Nx + ADJ_NODES - 1) / ADJ_NODES));
+  k_bspline_adjoint<<<grid, BB, lds, st>>>(nz, nx, Dz, Dx, Nz, Nx, chunk, rows, g, cb);
   return hipGetLastError();
 }
 

@@ -17,10 +17,12 @@ def close32(out, ref):
     return bool(np.all(np.abs(out - ref32) <= 2 * np.spacing(np.abs(ref32)) + 1e-30))
 
 
-# the last two: rows longer than a workgroup's column segment and node group (every column
-# a node), and a spacing whose weight table leaves room for only a few hundred staged cells
+# (30, 1100, 3, 1): rows longer than a workgroup's column segment and node group (every
+# column a node); (40, 5000, 1, 1990): a spacing whose weight table leaves room for only a
+# few hundred staged cells; (700, 60, 1, 5): enough coefficient rows (3 x 702) for the
+# transpose to take four rows per workgroup
 @pytest.mark.parametrize("nz,nx,Dz,Dx", [(37, 150, 1, 10), (64, 65, 4, 7), (5, 3, 2, 9), (100, 400, 1, 10),
-                                         (30, 1100, 3, 1), (40, 5000, 1, 1990)])
+                                         (30, 1100, 3, 1), (40, 5000, 1, 1990), (700, 60, 1, 5)])
 def test_expand_and_adjoint_parity(gpu_lib, nz, nx, Dz, Dx):
     efwi = gpu_lib
     rng = np.random.default_rng(nz + nx)
