@@ -207,9 +207,9 @@ def test_batch_3d_equals_per_shot(gpu_lib, case):
 
 def test_full_size_sampled_3d(gpu_lib):
     """The 3D precision workload at full size (300 x 400 x 400 at 5 m, 20-cell CPML, both DAS
-    wells, one six-component shot) for nt = 30 steps, with sqrt(nt) FP32 checkpoints and with
-    the FP16 checkpoints the timed sample uses. The wavefield travels about 10 cells, so the
-    oracle on an 80^3 crop centred on the source (its own CPML 20 cells from the source)
+    wells, one six-component shot) for nt = 30 steps, with sqrt(nt) FP32 checkpoints, with the
+    FP16 checkpoints the timed shot uses and with BF16 ones. The wavefield travels about 10
+    cells, so the oracle on an 80^3 crop centred on the source (its own CPML 20 cells from the source)
     reproduces the data at the channels clear of the crop's CPML and the gradient in the
     crop's interior; channels outside the crop carry zero data."""
     efwi = gpu_lib
@@ -244,7 +244,8 @@ def test_full_size_sampled_3d(gpu_lib):
     ccore = (slice(None), slice(25, c - 25), slice(25, c - 25), slice(25, c - 25))
     mg, sg, og = T(m_full), T(src), T(d_obs)
     del m_full
-    for mode, bar in ((efwi.CKPT_FP32, TOL * kap), (efwi.CKPT_FP16, 1e-3)):
+    # FP32 checkpoints at the parity bar; the 16-bit ones at their stated bounds
+    for mode, bar in ((efwi.CKPT_FP32, TOL * kap), (efwi.CKPT_FP16, 1e-3), (efwi.CKPT_BF16, 1e-2)):
         shot = _shot(efwi, sh, ckpt_mode=mode)
         d_out = torch.empty((len(sh.ch_ix), nt), dtype=torch.float32, device="cuda")
         g, phi = efwi.shot_gradient(grid, shot, mg, sg, og, d_out=d_out)
