@@ -135,6 +135,11 @@ __device__ __forceinline__ bool tile3(const int* __restrict__ sched, const int* 
   return true;
 }
 
+// The transposed kernels pass the row k through readfirstlane: a wave is one row of a tile
+// (64 x 4 workgroups, four rows per thread), so k is the same in every lane, and saying so
+// lets the compiler keep the row's addresses and y-profile values in scalar registers
+// (transposed velocity 1.54 -> 1.47 ms, 125 -> 116 VGPRs; the forward kernels were 1-2%
+// slower with it).
 #define PARAMS3                                                                                      \
   const Shot3D* __restrict__ shots, const int* __restrict__ tile_shot, const int* __restrict__ tile_first, \
       const int* __restrict__ sched
@@ -550,15 +555,15 @@ __device__ __forceinline__ void adj_vel3(const Shot3D& s, int i, int k, int j, i
 }
 
 template <bool GRAD, bool SRCADJ>
-// At least 4 waves per SIMD (at most 128 VGPRs; the compiler takes 125 with the imaging
-// gather, without spilling): 1.54 ms per 300 x 400 x 400 launch. Before the gather, 1.59 ms
+// At least 4 waves per SIMD (at most 128 VGPRs; the compiler takes 116 with the imaging
+// gather and the wave-uniform row, without spilling): 1.47 ms per 300 x 400 x 400 launch. Before the gather, 1.59 ms
 // at this cap against 1.73 ms with the compiler's own allocation (136 VGPRs, 3 waves) and
 // 2.02 ms capped at 5 waves (spills).
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(4))) void k3_adj_vel(PARAMS3, int n, int kseg, int first) {
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
     const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
-#define CALL(X, Y, Z) adj_vel3<GRAD, SRCADJ, X, Y, Z>(s, i, k, j, n, seg, first != 0)
+#define CALL(X, Y, Z) adj_vel3<GRAD, SRCADJ, X, Y, Z>(s, i, __builtin_amdgcn_readfirstlane(k), j, n, seg, first != 0)
     DISPATCH_AXES(pml_axes(s, i, k0, j0, 2), CALL);
 #undef CALL
   }
@@ -655,14 +660,14 @@ __device__ __forceinline__ void adj_str3(const Shot3D& s, int i, int k, int j, i
 }
 
 template <bool GRAD>
-// The compiler's own allocation (95 VGPRs with the imaging gather, 5 waves per SIMD): 1.46
-// ms per 300 x 400 x 400 launch. Before the gather (102 VGPRs, 4 waves), 1.64 ms against 1.88
+// The compiler's own allocation (88 VGPRs with the imaging gather and the wave-uniform row, 5
+// waves per SIMD): 1.45 ms per 300 x 400 x 400 launch. Before the gather (102 VGPRs, 4 waves), 1.64 ms against 1.88
 // ms capped at 8 waves (64 VGPRs, spills) and 2.00 ms at 7.
 __global__ __launch_bounds__(TX * TY) void k3_adj_str(PARAMS3, int n, int kseg, int first) {
   TILE3() {
     if (k >= s.ny || j >= s.nx) return;
     const gfloat* seg = GRAD ? s.seg + (size_t)kseg * NSEG3 * s.cells : nullptr;
-#define CALL(X, Y, Z) adj_str3<GRAD, X, Y, Z>(s, i, k, j, n, seg, first != 0)
+#define CALL(X, Y, Z) adj_str3<GRAD, X, Y, Z>(s, i, __builtin_amdgcn_readfirstlane(k), j, n, seg, first != 0)
     DISPATCH_AXES(pml_axes(s, i, k0, j0, 2), CALL);
 #undef CALL
   }
